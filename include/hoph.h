@@ -1,0 +1,253 @@
+/*
+ * hoph.h -- C ABI of libhoph, the MI355X (gfx950) library for one-permutation
+ * hashing (OPH) and its grouped (GOPH) and hierarchical (HOPH) early-stop
+ * comparison, after Zhang, Lin, Zhu, Yuan, Long and Huang, "Hierarchical One
+ * Permutation Hashing: Efficient Multimedia Near Duplicate Detection"
+ * (arXiv 1805.11254).
+ *
+ * Conventions for every entry point:
+ *  - Every call returns hoph_status; nothing is thrown across the ABI and
+ *    nothing aborts.  hoph_last_error() holds a message for the calling thread.
+ *  - d_* arguments are device pointers (HIP device memory of the current
+ *    device); h_* and plain struct pointers are host memory.  The caller owns
+ *    every buffer it passes; the library owns hoph_index objects.
+ *  - hip_stream is a hipStream_t (NULL = the default stream).  Work is queued
+ *    on that stream in order.  Calls that must read a device count
+ *    (query_*, minwise_query, hoph_sync) synchronise that stream once.
+ *  - A set is a CSR segment: ids d_ids[d_offsets[i] .. d_offsets[i+1]), ids in
+ *    [0, universe).  Duplicate ids are allowed (the minimum is idempotent).
+ *  - A signature is k uint32 words.  Word b is the smallest permuted value that
+ *    fell in bin b minus the first value of bin b (Sec. 3.2, "smallest possible
+ *    representation"), or HOPH_EMPTY when no value fell in the bin.
+ *  - Limits: 1 <= k_group <= 64, k % k_group == 0, k / k_group <= 64.
+ */
+#ifndef HOPH_H
+#define HOPH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HOPH_OK = 0,
+    HOPH_E_INVAL = -1,       /* invalid argument, checked on the host before any launch      */
+    HOPH_E_RANGE = -2,       /* an id >= universe was seen by the device (reported at a sync) */
+    HOPH_E_CAPACITY = -3,    /* an output or the index is too small; see hoph_results.needed  */
+    HOPH_E_NOMEM = -4,       /* device or pinned host allocation failed                       */
+    HOPH_E_UNSUPPORTED = -5, /* exact 64-bit decision state would overflow for these params   */
+    HOPH_E_DEVICE = -6       /* a HIP runtime call failed                                     */
+} hoph_status;
+
+#define HOPH_EMPTY 0xFFFFFFFFu
+#define HOPH_MAX_KGROUP 64u
+#define HOPH_MAX_GROUPS 64u
+
+/* An exact rational num/den (den > 0).  T = 0.8 is {4, 5}; eps = 1e-4 is {1, 10000}. */
+typedef struct { uint32_t num, den; } hoph_ratio;
+
+/* The one shared permutation psi (Sec. 3.2). */
+enum {
+    HOPH_HASH_TABLE = 0,      /* psi(x) = d_perm[x]; d_perm is a bijection of [0, universe); R = universe   */
+    HOPH_HASH_MODP31 = 1,     /* psi(x) = (a x + b) mod (2^31 - 1); universe <= 2^31 - 1; R = 2^31 - 1       */
+    HOPH_HASH_MODP32P15 = 2   /* psi(x) = (a x + b) mod (2^32 + 15); universe <= 2^32; R = 2^32 + 15        */
+};
+
+/* How the permuted range [0, R) is cut into k bins. */
+enum {
+    HOPH_LAYOUT_OPH = 0,      /* Sec. 3.2: k equal contiguous bins, bin(v) = floor(v k / R); GOPH groups are
+                                 the contiguous runs of k_group bins                                     */
+    HOPH_LAYOUT_HIER = 1      /* Sec. 4.1: split a:b (floor), the first part is a group of k_group equal
+                                 bins, the second part is split again; L = k / k_group groups; every split
+                                 must leave both parts larger than k_group (the paper's stop rule)         */
+};
+
+/* Which bins count as "empty" in N_eb (Eqs. 2 and 4). */
+enum {
+    HOPH_EMPTY_JOINT = 0,     /* Eq. 4: empty in both signatures (default)                              */
+    HOPH_EMPTY_LITERAL = 1,   /* no correction: rate = matched / k_group (Alg. 1 and 2 as printed)      */
+    HOPH_EMPTY_EITHER = 2     /* empty in either signature (reproduces the worked examples' estimates)  */
+};
+
+typedef struct {
+    uint32_t layout;          /* HOPH_LAYOUT_*                                           */
+    uint32_t k;               /* bins per signature                                      */
+    uint32_t k_group;         /* k': bins per group                                      */
+    uint32_t ratio_a;         /* HIER: the a of a:b (>= 1); ignored for OPH              */
+    uint32_t ratio_b;         /* HIER: the b of a:b (>= 1)                               */
+    uint32_t hash;            /* HOPH_HASH_*                                             */
+    uint64_t universe;        /* D: every id must be < universe                          */
+    uint64_t hash_a;          /* MODP*: 1 <= a < p                                       */
+    uint64_t hash_b;          /* MODP*: 0 <= b < p                                       */
+    const uint32_t *d_perm;   /* TABLE: device array of universe entries, a bijection    */
+} hoph_sketch_params;
+
+typedef struct {
+    hoph_ratio T;             /* similarity threshold, 0 < T <= 1                        */
+    hoph_ratio eps;           /* error tolerance of the small-probability event, 0 <= eps < 1 */
+    uint32_t empty_policy;    /* HOPH_EMPTY_*                                            */
+    uint32_t coarse_depth;    /* 0 = let the library choose; else groups scanned for every
+                                 pair before survivors move to the per-pair pass (a tuning
+                                 knob: results do not depend on it)                      */
+} hoph_query_params;
+
+/* Accepted pairs as CSR: for query i, set ids d_set_ids[d_offsets[i] .. d_offsets[i+1]),
+   ascending.  needed is written on return: the total number of accepted pairs. */
+typedef struct {
+    uint64_t *d_offsets;      /* device, n_q + 1 entries                                 */
+    uint32_t *d_set_ids;      /* device, capacity entries                                */
+    uint64_t capacity;
+    uint64_t needed;          /* out                                                     */
+} hoph_results;
+
+typedef struct hoph_index hoph_index;   /* opaque, owned by the library */
+
+/*
+ * sketch_oph -- OPH / HOPH signatures of n_sets sets (Sec. 3.2, Sec. 4.1).
+ * d_sigs: n_sets * k uint32, row-major (set i at d_sigs + i * k).
+ * Asynchronous.  Ids >= universe are skipped and raise HOPH_E_RANGE at the next
+ * hoph_sync / query on the device; an empty set gets an all-EMPTY signature and
+ * raises HOPH_E_INVAL there (Jaccard similarity is undefined for it).
+ * Host errors: HOPH_E_INVAL (bad params, null pointers with n_sets > 0).
+ */
+hoph_status sketch_oph(const hoph_sketch_params *params, const uint32_t *d_ids,
+                       const uint64_t *d_offsets, uint64_t n_sets, uint32_t *d_sigs,
+                       void *hip_stream);
+
+/*
+ * build_index -- a resident index of signatures in group-major slabs (the
+ * per-group comparison order of Sec. 3.3 / Sec. 4.1).  capacity >= n_sets is the
+ * number of sets the index can hold (index_append grows it up to capacity).
+ * d_sigs: n_sets * k uint32 row-major, as written by sketch_oph.  Allocates device
+ * memory (the only allocation point besides first-use workspace growth).
+ * Asynchronous on hip_stream; *out is valid on return.
+ */
+hoph_status build_index(const hoph_sketch_params *params, const uint32_t *d_sigs,
+                        uint64_t n_sets, uint64_t capacity, hoph_index **out, void *hip_stream);
+
+/* index_append -- append n_new signatures (ids continue from the current size).
+   HOPH_E_CAPACITY if size + n_new > capacity.  Asynchronous. */
+hoph_status index_append(hoph_index *index, const uint32_t *d_sigs, uint64_t n_new,
+                         void *hip_stream);
+
+/* hoph_index_reset -- forget every stored set (size 0, capacity kept) so the
+   index can be refilled with index_append without a new allocation. */
+hoph_status hoph_index_reset(hoph_index *index);
+
+/* hoph_query_timing -- device time of the last query_* call on this index, in
+   milliseconds, measured with HIP events on the query's stream:
+   ms[0] coarse pass, ms[1] per-survivor pass, ms[2] sort and CSR output.
+   (query_oph_full reports its scan in ms[0].) */
+hoph_status hoph_query_timing(const hoph_index *index, float ms[3]);
+
+/* hoph_index_size -- number of sets in the index (0 for NULL). */
+uint64_t hoph_index_size(const hoph_index *index);
+
+/* hoph_index_free -- release the index and its device memory (NULL is a no-op). */
+void hoph_index_free(hoph_index *index);
+
+/*
+ * query_goph -- Alg. 1 (GOPH): for each of n_q query signatures (d_qsigs,
+ * n_q * k uint32 row-major, same params as the index), compare group by group
+ * against every indexed set, group weights 1/L, stop under the small-probability
+ * event (Def. 1) and accept iff the weighted estimate reaches T after the last
+ * group.  Requires an index built with HOPH_LAYOUT_OPH.
+ * Returns HOPH_E_CAPACITY (with results->needed) if capacity is too small;
+ * HOPH_E_UNSUPPORTED if the exact state does not fit 64 bits.
+ * Synchronises hip_stream once; the CSR output is complete on return.
+ */
+hoph_status query_goph(const hoph_index *index, const uint32_t *d_qsigs, uint32_t n_q,
+                       const hoph_query_params *qp, hoph_results *results, void *hip_stream);
+
+/* query_hoph -- Alg. 2 ((a:b) HOPH): as query_goph with group weights
+   a b^(j-1)/(a+b)^j (last group (b/(a+b))^(L-1)).  Requires HOPH_LAYOUT_HIER. */
+hoph_status query_hoph(const hoph_index *index, const uint32_t *d_qsigs, uint32_t n_q,
+                       const hoph_query_params *qp, hoph_results *results, void *hip_stream);
+
+/* query_oph_full -- plain OPH comparator (Eq. 6 over all k bins, no early stop):
+   accept iff N_mb / (k - N_eb) >= T under qp->empty_policy (eps ignored). Any layout. */
+hoph_status query_oph_full(const hoph_index *index, const uint32_t *d_qsigs, uint32_t n_q,
+                           const hoph_query_params *qp, hoph_results *results, void *hip_stream);
+
+/* MinWise comparator (Sec. 1-2): k independent hashes (a_i x + b_i) mod p. */
+typedef struct {
+    uint32_t k;               /* number of hash functions                                */
+    uint32_t hash;            /* HOPH_HASH_MODP31 or HOPH_HASH_MODP32P15                 */
+    uint64_t universe;
+    const uint64_t *d_hash_a; /* device, k entries, 1 <= a_i < p                         */
+    const uint64_t *d_hash_b; /* device, k entries, 0 <= b_i < p                         */
+} hoph_minwise_params;
+
+/* minwise_sketch -- d_sigs: n_sets * k uint64 row-major, each the minimum hash
+   (UINT64_MAX for an empty set).  Asynchronous; errors as sketch_oph. */
+hoph_status minwise_sketch(const hoph_minwise_params *params, const uint32_t *d_ids,
+                           const uint64_t *d_offsets, uint64_t n_sets, uint64_t *d_sigs,
+                           void *hip_stream);
+
+/* minwise_query -- accept iff (#equal minima) / k >= T.  Synchronises once. */
+hoph_status minwise_query(const hoph_minwise_params *params, const uint64_t *d_sigs,
+                          uint64_t n_sets, const uint64_t *d_qsigs, uint32_t n_q, hoph_ratio T,
+                          hoph_results *results, void *hip_stream);
+
+/* hoph_sync -- synchronise hip_stream and report (then clear) the device error
+   flags raised by earlier sketches on the current device. */
+hoph_status hoph_sync(void *hip_stream);
+
+const char *hoph_status_str(hoph_status status);
+const char *hoph_last_error(void);    /* thread-local; "" when none */
+
+/* ------------------------------------------------------------------------ */
+/* Host-only helpers (no GPU needed)                                         */
+/* ------------------------------------------------------------------------ */
+
+/* hoph_layout_starts -- the first permuted value of each bin, starts[0..k), and
+   starts[k] = R (Sec. 3.2 / Sec. 4.1).  starts: host array of k + 1 entries. */
+hoph_status hoph_layout_starts(const hoph_sketch_params *params, uint64_t *starts);
+
+/* hoph_tail_integers -- for X ~ Bin(n, T) (Eq. 10): *j_lo = max{j >= -1 : P(X <= j) <= eps},
+   *j_hi = min{j <= n + 1 : P(X >= j) <= eps}, computed exactly.  n <= 256. */
+hoph_status hoph_tail_integers(uint32_t n, hoph_ratio T, hoph_ratio eps, int32_t *j_lo,
+                               int32_t *j_hi);
+
+/* The exact decision tables the scan applies (Alg. 1/2 with Def. 1).  With
+   lcm = lcm(1..k_group) and the group weights as integers W_j over wsum, the state
+   after group l is S~_l = sum_{j<=l} W_j * rho_j, rho_j = lcm * rate_j; the pair is
+   accepted at step l iff S~_l >= acc[l-1] and rejected iff S~_l <= rej[l-1]. */
+typedef struct {
+    uint32_t L, k_group, empty_policy, goph;
+    int32_t j_lo, j_hi;
+    int64_t lcm;              /* lcm(1..k_group)                                         */
+    int64_t wsum;             /* sum of W                                                */
+    int64_t W[64];
+    int64_t acc[64];
+    int64_t rej[64];
+    int64_t dmul[65];         /* lcm / (k_group - e) for e < k_group; lcm at e = k_group */
+} hoph_decision_tables;
+
+/* hoph_build_decision_tables -- the tables for an index layout (params) and a
+   query (qp); goph = 1 for GOPH weights, 0 for HOPH weights. */
+hoph_status hoph_build_decision_tables(const hoph_sketch_params *params,
+                                       const hoph_query_params *qp, uint32_t goph,
+                                       hoph_decision_tables *out);
+
+/* hoph_selftest_bins -- runs the library's own hash-and-bin arithmetic (the code
+   the sketch kernel inlines) on the host for n ids: out_bin[i], out_off[i].  A
+   test hook for checking that arithmetic without a GPU. */
+hoph_status hoph_selftest_bins(const hoph_sketch_params *params, const uint32_t *h_perm,
+                               const uint32_t *h_ids, uint64_t n, uint32_t *out_bin,
+                               uint32_t *out_off);
+
+/* hoph_pair_counts -- per-group counts (m_j, e_j) under policy for n_pairs pairs
+   (d_pairs[2i] = query row < n_q, d_pairs[2i+1] = set id < index size) against the
+   index: d_m and d_e are n_pairs * L uint32, device; a pair out of range gets
+   0xFFFFFFFF in every group.  A test hook for the device counting.  Synchronises. */
+hoph_status hoph_pair_counts(const hoph_index *index, const uint32_t *d_qsigs, uint32_t n_q,
+                             const uint32_t *d_pairs, uint64_t n_pairs, uint32_t policy,
+                             uint32_t *d_m, uint32_t *d_e, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOPH_H */

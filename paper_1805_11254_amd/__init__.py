@@ -1,0 +1,377 @@
+"""Python binding of libhoph (include/hoph.h): one-permutation hashing (OPH),
+grouped OPH (GOPH) and (a:b) hierarchical OPH (HOPH) on MI355X.
+
+The binding only marshals arguments: tensors live in device memory (PyTorch is
+used for allocation and streams), every step runs in the library's HIP kernels.
+Importing works without a GPU; the device entry points raise if the library is
+not built or no GPU is present.  Signatures are uint32 words carried in int32
+tensors (same bits).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Tuple
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhoph.so")
+
+HOPH_OK, HOPH_E_INVAL, HOPH_E_RANGE, HOPH_E_CAPACITY = 0, -1, -2, -3
+HOPH_E_NOMEM, HOPH_E_UNSUPPORTED, HOPH_E_DEVICE = -4, -5, -6
+HASH_TABLE, HASH_MODP31, HASH_MODP32P15 = 0, 1, 2
+LAYOUT_OPH, LAYOUT_HIER = 0, 1
+EMPTY_JOINT, EMPTY_LITERAL, EMPTY_EITHER = 0, 1, 2
+EMPTY = 0xFFFFFFFF
+
+u32, u64, i32, i64, vp = C.c_uint32, C.c_uint64, C.c_int32, C.c_int64, C.c_void_p
+
+
+class Ratio(C.Structure):
+    _fields_ = [("num", u32), ("den", u32)]
+
+
+class SketchParamsC(C.Structure):
+    _fields_ = [("layout", u32), ("k", u32), ("k_group", u32), ("ratio_a", u32), ("ratio_b", u32),
+                ("hash", u32), ("universe", u64), ("hash_a", u64), ("hash_b", u64), ("d_perm", vp)]
+
+
+class QueryParamsC(C.Structure):
+    _fields_ = [("T", Ratio), ("eps", Ratio), ("empty_policy", u32), ("coarse_depth", u32)]
+
+
+class ResultsC(C.Structure):
+    _fields_ = [("d_offsets", vp), ("d_set_ids", vp), ("capacity", u64), ("needed", u64)]
+
+
+class MinwiseParamsC(C.Structure):
+    _fields_ = [("k", u32), ("hash", u32), ("universe", u64), ("d_hash_a", vp), ("d_hash_b", vp)]
+
+
+class DecisionTablesC(C.Structure):
+    _fields_ = [("L", u32), ("k_group", u32), ("empty_policy", u32), ("goph", u32), ("j_lo", i32), ("j_hi", i32),
+                ("lcm", i64), ("wsum", i64), ("W", i64 * 64), ("acc", i64 * 64), ("rej", i64 * 64),
+                ("dmul", i64 * 65)]
+
+
+# name -> (restype, argtypes); every symbol declared in include/hoph.h
+SIGNATURES = {
+    "sketch_oph": (C.c_int, [C.POINTER(SketchParamsC), vp, vp, u64, vp, vp]),
+    "build_index": (C.c_int, [C.POINTER(SketchParamsC), vp, u64, u64, C.POINTER(vp), vp]),
+    "index_append": (C.c_int, [vp, vp, u64, vp]),
+    "hoph_index_size": (u64, [vp]),
+    "hoph_index_reset": (C.c_int, [vp]),
+    "hoph_query_timing": (C.c_int, [vp, C.POINTER(C.c_float)]),
+    "hoph_index_free": (None, [vp]),
+    "query_goph": (C.c_int, [vp, vp, u32, C.POINTER(QueryParamsC), C.POINTER(ResultsC), vp]),
+    "query_hoph": (C.c_int, [vp, vp, u32, C.POINTER(QueryParamsC), C.POINTER(ResultsC), vp]),
+    "query_oph_full": (C.c_int, [vp, vp, u32, C.POINTER(QueryParamsC), C.POINTER(ResultsC), vp]),
+    "minwise_sketch": (C.c_int, [C.POINTER(MinwiseParamsC), vp, vp, u64, vp, vp]),
+    "minwise_query": (C.c_int, [C.POINTER(MinwiseParamsC), vp, u64, vp, u32, Ratio, C.POINTER(ResultsC), vp]),
+    "hoph_sync": (C.c_int, [vp]),
+    "hoph_status_str": (C.c_char_p, [C.c_int]),
+    "hoph_last_error": (C.c_char_p, []),
+    "hoph_layout_starts": (C.c_int, [C.POINTER(SketchParamsC), vp]),
+    "hoph_tail_integers": (C.c_int, [u32, Ratio, Ratio, C.POINTER(i32), C.POINTER(i32)]),
+    "hoph_build_decision_tables": (C.c_int, [C.POINTER(SketchParamsC), C.POINTER(QueryParamsC), u32,
+                                             C.POINTER(DecisionTablesC)]),
+    "hoph_selftest_bins": (C.c_int, [C.POINTER(SketchParamsC), vp, vp, u64, vp, vp]),
+    "hoph_pair_counts": (C.c_int, [vp, vp, u32, vp, u64, u32, vp, vp, vp]),
+}
+
+_lib = None
+
+
+class HophError(RuntimeError):
+    def __init__(self, status: int, message: str, needed: Optional[int] = None):
+        self.status = status
+        self.needed = needed
+        super().__init__(f"{lib().hoph_status_str(status).decode()}: {message}")
+
+
+def lib():
+    """The loaded library; raises ImportError when it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_1805_11254_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int, needed: Optional[int] = None):
+    if status != HOPH_OK:
+        raise HophError(status, lib().hoph_last_error().decode(), needed)
+
+
+def _ratio(r) -> Ratio:
+    from fractions import Fraction
+    if isinstance(r, Ratio):
+        return r
+    if isinstance(r, tuple):
+        return Ratio(int(r[0]), int(r[1]))
+    f = Fraction(str(r)) if isinstance(r, float) else Fraction(r)
+    return Ratio(f.numerator, f.denominator)
+
+
+# ---------------------------------------------------------------------------
+# Parameters
+# ---------------------------------------------------------------------------
+@dataclass
+class SketchParams:
+    """Sketch layout and permutation (Sec. 3.2 / Sec. 4.1)."""
+    layout: int
+    k: int
+    k_group: int
+    hash: int
+    universe: int
+    ratio_a: int = 1
+    ratio_b: int = 1
+    hash_a: int = 0
+    hash_b: int = 0
+    perm: object = None          # torch int32 cuda tensor (HASH_TABLE), or numpy for host helpers
+
+    def c(self, perm_ptr: Optional[int] = None) -> SketchParamsC:
+        if perm_ptr is None and self.perm is not None and hasattr(self.perm, "data_ptr"):
+            perm_ptr = self.perm.data_ptr()
+        return SketchParamsC(self.layout, self.k, self.k_group, self.ratio_a, self.ratio_b, self.hash,
+                             self.universe, self.hash_a, self.hash_b, perm_ptr)
+
+    @property
+    def groups(self) -> int:
+        return self.k // self.k_group
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _need_cuda(t, name, dtypes):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{name} must have dtype in {dtypes}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+# ---------------------------------------------------------------------------
+# Device entry points
+# ---------------------------------------------------------------------------
+def sketch_oph(params: SketchParams, ids, offsets, out=None, stream=None):
+    """OPH / HOPH signatures, int32 tensor (n_sets, k) holding uint32 words."""
+    import torch
+    _need_cuda(ids, "ids", (torch.int32,))
+    _need_cuda(offsets, "offsets", (torch.int64,))
+    n = offsets.numel() - 1
+    if out is None:
+        out = torch.empty((max(n, 0), params.k), dtype=torch.int32, device=ids.device)
+    else:
+        _need_cuda(out, "out", (torch.int32,))
+    pc = params.c()
+    _check(lib().sketch_oph(C.byref(pc), vp(ids.data_ptr()), vp(offsets.data_ptr()), max(n, 0),
+                            vp(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def sync(stream=None):
+    """Synchronise and report device-side sketch errors (ids out of range, empty sets)."""
+    _check(lib().hoph_sync(_stream(stream)))
+
+
+class Index:
+    """A resident signature index in HBM (library-owned)."""
+
+    def __init__(self, params: SketchParams, sigs, capacity: Optional[int] = None, stream=None):
+        import torch
+        _need_cuda(sigs, "sigs", (torch.int32,))
+        n = sigs.shape[0]
+        self.params = params
+        self._h = vp()
+        pc = params.c()
+        _check(lib().build_index(C.byref(pc), vp(sigs.data_ptr()), n, capacity if capacity is not None else n,
+                                 C.byref(self._h), _stream(stream)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def append(self, sigs, stream=None):
+        import torch
+        _need_cuda(sigs, "sigs", (torch.int32,))
+        _check(lib().index_append(self._h, vp(sigs.data_ptr()), sigs.shape[0], _stream(stream)))
+
+    def __len__(self):
+        return int(lib().hoph_index_size(self._h)) if self._h else 0
+
+    def reset(self):
+        """Size 0, capacity kept (refill with append)."""
+        _check(lib().hoph_index_reset(self._h))
+
+    def last_query_ms(self):
+        """(coarse, per-survivor, sort+output) device ms of the last query."""
+        ms = (C.c_float * 3)()
+        _check(lib().hoph_query_timing(self._h, ms))
+        return tuple(ms)
+
+    def free(self):
+        if self._h:
+            lib().hoph_index_free(self._h)
+            self._h = vp()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _run_query(fn, handle, qsigs, qp: QueryParamsC, capacity, stream, device):
+    import torch
+    n_q = qsigs.shape[0]
+    offsets = torch.empty(n_q + 1, dtype=torch.int64, device=device)
+    cap = capacity if capacity is not None else max(4096, 64 * n_q)
+    while True:
+        ids = torch.empty(max(cap, 1), dtype=torch.int32, device=device)
+        res = ResultsC(offsets.data_ptr(), ids.data_ptr(), cap, 0)
+        st = fn(handle, vp(qsigs.data_ptr()), n_q, C.byref(qp), C.byref(res), _stream(stream))
+        if st == HOPH_E_CAPACITY and capacity is None:
+            cap = int(res.needed)
+            continue
+        _check(st, int(res.needed))
+        return offsets, ids[:int(res.needed)]
+
+
+def _query(name, index: Index, qsigs, T, eps, policy, capacity, coarse_depth, stream):
+    import torch
+    _need_cuda(qsigs, "qsigs", (torch.int32,))
+    qp = QueryParamsC(_ratio(T), _ratio(eps), policy, coarse_depth)
+    return _run_query(getattr(lib(), name), index.handle, qsigs, qp, capacity, stream, qsigs.device)
+
+
+def query_goph(index: Index, qsigs, T=(4, 5), eps=(1, 10000), policy=EMPTY_JOINT, capacity=None,
+               coarse_depth=0, stream=None):
+    """Alg. 1 over the index: (offsets int64[n_q+1], set ids int32[...])."""
+    return _query("query_goph", index, qsigs, T, eps, policy, capacity, coarse_depth, stream)
+
+
+def query_hoph(index: Index, qsigs, T=(4, 5), eps=(1, 10000), policy=EMPTY_JOINT, capacity=None,
+               coarse_depth=0, stream=None):
+    """Alg. 2 over the index: (offsets int64[n_q+1], set ids int32[...])."""
+    return _query("query_hoph", index, qsigs, T, eps, policy, capacity, coarse_depth, stream)
+
+
+def query_oph_full(index: Index, qsigs, T=(4, 5), policy=EMPTY_JOINT, capacity=None, stream=None):
+    """Plain OPH over all k bins (comparator)."""
+    return _query("query_oph_full", index, qsigs, T, (0, 1), policy, capacity, 0, stream)
+
+
+@dataclass
+class MinwiseParams:
+    k: int
+    hash: int
+    universe: int
+    hash_a: object               # torch int64 cuda tensor, k entries
+    hash_b: object
+
+    def c(self) -> MinwiseParamsC:
+        return MinwiseParamsC(self.k, self.hash, self.universe, self.hash_a.data_ptr(), self.hash_b.data_ptr())
+
+
+def minwise_sketch(params: MinwiseParams, ids, offsets, out=None, stream=None):
+    """MinWise signatures, int64 tensor (n_sets, k) holding uint64 minima."""
+    import torch
+    _need_cuda(ids, "ids", (torch.int32,))
+    _need_cuda(offsets, "offsets", (torch.int64,))
+    n = offsets.numel() - 1
+    if out is None:
+        out = torch.empty((max(n, 0), params.k), dtype=torch.int64, device=ids.device)
+    pc = params.c()
+    _check(lib().minwise_sketch(C.byref(pc), vp(ids.data_ptr()), vp(offsets.data_ptr()), max(n, 0),
+                                vp(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def minwise_query(params: MinwiseParams, sigs, qsigs, T=(4, 5), capacity=None, stream=None):
+    import torch
+    _need_cuda(sigs, "sigs", (torch.int64,))
+    _need_cuda(qsigs, "qsigs", (torch.int64,))
+    pc = params.c()
+    n_q = qsigs.shape[0]
+    offsets = torch.empty(n_q + 1, dtype=torch.int64, device=qsigs.device)
+    cap = capacity if capacity is not None else max(4096, 64 * n_q)
+    while True:
+        ids = torch.empty(max(cap, 1), dtype=torch.int32, device=qsigs.device)
+        res = ResultsC(offsets.data_ptr(), ids.data_ptr(), cap, 0)
+        st = lib().minwise_query(C.byref(pc), vp(sigs.data_ptr()), sigs.shape[0], vp(qsigs.data_ptr()), n_q,
+                                 _ratio(T), C.byref(res), _stream(stream))
+        if st == HOPH_E_CAPACITY and capacity is None:
+            cap = int(res.needed)
+            continue
+        _check(st, int(res.needed))
+        return offsets, ids[:int(res.needed)]
+
+
+def pair_counts(index: Index, qsigs, pairs, policy=EMPTY_JOINT, stream=None):
+    """Per-group (m, e) for (query row, set id) pairs: two int32 tensors (n_pairs, L)."""
+    import torch
+    _need_cuda(qsigs, "qsigs", (torch.int32,))
+    _need_cuda(pairs, "pairs", (torch.int32,))
+    n = pairs.shape[0]
+    L = index.params.groups
+    m = torch.empty((n, L), dtype=torch.int32, device=pairs.device)
+    e = torch.empty((n, L), dtype=torch.int32, device=pairs.device)
+    _check(lib().hoph_pair_counts(index.handle, vp(qsigs.data_ptr()), qsigs.shape[0], vp(pairs.data_ptr()), n,
+                                  policy, vp(m.data_ptr()), vp(e.data_ptr()), _stream(stream)))
+    return m, e
+
+
+# ---------------------------------------------------------------------------
+# Host-only helpers (no GPU)
+# ---------------------------------------------------------------------------
+def layout_starts(params: SketchParams):
+    import numpy as np
+    out = np.zeros(params.k + 1, dtype=np.uint64)
+    pc = params.c(perm_ptr=0)
+    _check(lib().hoph_layout_starts(C.byref(pc), out.ctypes.data_as(vp)))
+    return out
+
+
+def tail_integers(n: int, T, eps) -> Tuple[int, int]:
+    lo, hi = i32(), i32()
+    _check(lib().hoph_tail_integers(n, _ratio(T), _ratio(eps), C.byref(lo), C.byref(hi)))
+    return lo.value, hi.value
+
+
+def decision_tables(params: SketchParams, T, eps, policy=EMPTY_JOINT, goph: Optional[bool] = None) -> dict:
+    if goph is None:
+        goph = params.layout == LAYOUT_OPH
+    pc = params.c(perm_ptr=0)
+    qp = QueryParamsC(_ratio(T), _ratio(eps), policy, 0)
+    t = DecisionTablesC()
+    _check(lib().hoph_build_decision_tables(C.byref(pc), C.byref(qp), 1 if goph else 0, C.byref(t)))
+    L, kp = t.L, t.k_group
+    return dict(L=L, k_group=kp, j_lo=t.j_lo, j_hi=t.j_hi, lcm=t.lcm, wsum=t.wsum, W=list(t.W[:L]),
+                acc=list(t.acc[:L]), rej=list(t.rej[:L]), dmul=list(t.dmul[:kp + 1]), policy=t.empty_policy)
+
+
+def selftest_bins(params: SketchParams, ids, perm=None):
+    """The library's own hash-and-bin arithmetic run on the host (test hook)."""
+    import numpy as np
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    pp = None if perm is None else np.ascontiguousarray(perm, dtype=np.uint32)
+    b = np.zeros(len(ids), dtype=np.uint32)
+    o = np.zeros(len(ids), dtype=np.uint32)
+    pc = params.c(perm_ptr=0)
+    _check(lib().hoph_selftest_bins(C.byref(pc), None if pp is None else pp.ctypes.data_as(vp),
+                                    ids.ctypes.data_as(vp), len(ids), b.ctypes.data_as(vp), o.ctypes.data_as(vp)))
+    return b, o

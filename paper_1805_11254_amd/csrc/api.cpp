@@ -1,0 +1,658 @@
+// The C ABI of libhoph (include/hoph.h): host validation, ownership of the
+// index and its workspace, and the order of kernel launches for each call.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "hoph_internal.h"
+
+namespace hoph {
+uint32_t max_depth_for_kpad(uint32_t kpad);
+uint64_t sort_capacity(uint64_t n);
+}  // namespace hoph
+
+using namespace hoph;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+hoph_status fail(hoph_status st, const std::string &msg) {
+    g_last_error = msg;
+    return st;
+}
+
+hoph_status hip_fail(hipError_t e, const char *what) {
+    return fail(HOPH_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HOPH_HIP(call, what)                      \
+    do {                                          \
+        hipError_t e_ = (call);                   \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// One 32-bit device error word per device, allocated on first use.
+constexpr int kMaxDevices = 64;
+std::mutex g_err_mu;
+uint32_t *g_err[kMaxDevices] = {};
+
+hoph_status device_err_word(uint32_t **out) {
+    int dev = 0;
+    HOPH_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(HOPH_E_DEVICE, "device ordinal out of range");
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    if (!g_err[dev]) {
+        uint32_t *p = nullptr;
+        HOPH_HIP(hipMalloc(&p, 256), "hipMalloc(error word)");
+        HOPH_HIP(hipMemset(p, 0, 256), "hipMemset(error word)");
+        g_err[dev] = p;
+    }
+    *out = g_err[dev];
+    return HOPH_OK;
+}
+
+// Device buffers for one query at a time: survivors, accepted keys, counters.
+struct Workspace {
+    Survivor *surv = nullptr;
+    uint64_t surv_cap = 0;
+    uint64_t *keys = nullptr;
+    uint64_t keys_cap = 0;        // a power of two >= 4096
+    uint64_t *counters = nullptr; // device [0] survivors, [1] accepted
+    uint64_t *qmasks = nullptr;   // per (query, group) empty-bin masks
+    uint64_t qmask_cap = 0;
+    uint64_t *h_counters = nullptr; // pinned host mirror
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    float last_ms[3] = {0, 0, 0};
+    void release() {
+        for (auto &e : ev)
+            if (e) { (void)hipEventDestroy(e); e = nullptr; }
+        if (surv) (void)hipFree(surv);
+        if (keys) (void)hipFree(keys);
+        if (counters) (void)hipFree(counters);
+        if (qmasks) (void)hipFree(qmasks);
+        if (h_counters) (void)hipHostFree(h_counters);
+        qmasks = nullptr;
+        qmask_cap = 0;
+        surv = nullptr;
+        keys = nullptr;
+        counters = nullptr;
+        h_counters = nullptr;
+        surv_cap = keys_cap = 0;
+    }
+    hoph_status init(uint64_t surv_records, uint64_t keys_records) {
+        HOPH_HIP(hipMalloc(&counters, 64), "hipMalloc(counters)");
+        HOPH_HIP(hipHostMalloc(&h_counters, 64, hipHostMallocDefault), "hipHostMalloc(counters)");
+        for (auto &e : ev) HOPH_HIP(hipEventCreate(&e), "hipEventCreate");
+        hoph_status st = grow_surv(surv_records);
+        if (st) return st;
+        return grow_keys(keys_records);
+    }
+    hoph_status grow_surv(uint64_t n) {
+        if (n <= surv_cap) return HOPH_OK;
+        if (surv) (void)hipFree(surv);
+        surv = nullptr;
+        surv_cap = 0;
+        if (hipMalloc(&surv, n * sizeof(Survivor)) != hipSuccess) return fail(HOPH_E_NOMEM, "survivor buffer");
+        surv_cap = n;
+        return HOPH_OK;
+    }
+    hoph_status grow_qmasks(uint64_t n) {
+        if (n <= qmask_cap) return HOPH_OK;
+        if (qmasks) (void)hipFree(qmasks);
+        qmasks = nullptr;
+        qmask_cap = 0;
+        uint64_t want = 4096;
+        while (want < n) want <<= 1;
+        if (hipMalloc(&qmasks, want * sizeof(uint64_t)) != hipSuccess) return fail(HOPH_E_NOMEM, "query mask buffer");
+        qmask_cap = want;
+        return HOPH_OK;
+    }
+    hoph_status grow_keys(uint64_t n) {
+        const uint64_t want = sort_capacity(n);
+        if (want <= keys_cap) return HOPH_OK;
+        if (keys) (void)hipFree(keys);
+        keys = nullptr;
+        keys_cap = 0;
+        if (hipMalloc(&keys, want * sizeof(uint64_t)) != hipSuccess) return fail(HOPH_E_NOMEM, "key buffer");
+        keys_cap = want;
+        return HOPH_OK;
+    }
+};
+
+uint32_t round4(uint32_t x) { return (x + 3u) & ~3u; }
+
+}  // namespace
+
+struct hoph_index {
+    int device = 0;
+    hoph_sketch_params params{};
+    LayoutInfo lay;
+    uint32_t kpad = 0;
+    uint64_t n = 0;
+    uint64_t capacity = 0;        // slab capacity in sets, a multiple of 64
+    uint64_t max_sets = 0;        // the capacity the caller asked for
+    uint32_t *slab = nullptr;
+    Workspace ws;
+    std::mutex mu;
+};
+
+namespace {
+
+bool valid_ratio_T(hoph_ratio T) { return T.den != 0 && T.num != 0 && T.num <= T.den; }
+bool valid_ratio_eps(hoph_ratio e) { return e.den != 0 && e.num < e.den; }
+
+hoph_status check_results(const hoph_results *r, uint32_t n_q) {
+    if (!r) return fail(HOPH_E_INVAL, "results is NULL");
+    if (!r->d_offsets) return fail(HOPH_E_INVAL, "results->d_offsets is NULL");
+    if (r->capacity && !r->d_set_ids) return fail(HOPH_E_INVAL, "results->d_set_ids is NULL");
+    (void)n_q;
+    return HOPH_OK;
+}
+
+enum class QueryKind { GOPH, HOPH, OPH_FULL };
+
+// Pick queries per wavefront so that the grid has enough wavefronts to fill
+// the device (about 32 per CU) without splitting the query batch further.
+uint32_t pick_q_per_wave(uint64_t n_sets, uint32_t n_q) {
+    const uint64_t ntiles = std::max<uint64_t>(1, (n_sets + 63) / 64);
+    uint64_t want_chunks = (8192 + ntiles - 1) / ntiles;
+    if (want_chunks > n_q) want_chunks = n_q;
+    if (want_chunks == 0) want_chunks = 1;
+    return (uint32_t)((n_q + want_chunks - 1) / want_chunks);
+}
+
+hoph_status copy_counters(Workspace &ws, hipStream_t st) {
+    HOPH_HIP(hipMemcpyAsync(ws.h_counters, ws.counters, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, st),
+             "hipMemcpyAsync(counters)");
+    HOPH_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    return HOPH_OK;
+}
+
+hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t n_q, const hoph_query_params *qp,
+                      hoph_results *res, void *stream, QueryKind kind) {
+    if (!cidx) return fail(HOPH_E_INVAL, "index is NULL");
+    if (!qp) return fail(HOPH_E_INVAL, "query params are NULL");
+    if (n_q && !d_qsigs) return fail(HOPH_E_INVAL, "d_qsigs is NULL");
+    if (!valid_ratio_T(qp->T)) return fail(HOPH_E_INVAL, "T must be an exact ratio in (0, 1]");
+    if (kind != QueryKind::OPH_FULL && !valid_ratio_eps(qp->eps)) return fail(HOPH_E_INVAL, "eps must be in [0, 1)");
+    if (qp->empty_policy > HOPH_EMPTY_EITHER) return fail(HOPH_E_INVAL, "unknown empty policy");
+    hoph_status st = check_results(res, n_q);
+    if (st) return st;
+    hoph_index *idx = const_cast<hoph_index *>(cidx);
+    if (kind == QueryKind::GOPH && idx->params.layout != HOPH_LAYOUT_OPH)
+        return fail(HOPH_E_INVAL, "query_goph needs an index built with HOPH_LAYOUT_OPH");
+    if (kind == QueryKind::HOPH && idx->params.layout != HOPH_LAYOUT_HIER)
+        return fail(HOPH_E_INVAL, "query_hoph needs an index built with HOPH_LAYOUT_HIER");
+    std::lock_guard<std::mutex> lk(idx->mu);
+    DeviceGuard dg(idx->device);
+    if (!dg.ok) return fail(HOPH_E_DEVICE, "cannot select the index device");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const LayoutInfo &lay = idx->lay;
+    Workspace &ws = idx->ws;
+
+    ScanTab tab{};
+    uint32_t depth = 0;
+    if (kind != QueryKind::OPH_FULL) {
+        hoph_decision_tables t;
+        std::string err;
+        st = build_tables(lay, *qp, kind == QueryKind::GOPH, t, err);
+        if (st) return fail(st, err);
+        to_scan_tab(t, tab);
+        // depth: the first step at which a pair with no matched bin is rejected
+        uint32_t g1 = lay.L;
+        for (uint32_t l = 0; l < lay.L; ++l)
+            if (t.rej[l] >= 0) { g1 = l + 1; break; }
+        const uint32_t maxd = std::min(max_depth_for_kpad(idx->kpad), lay.L);
+        depth = qp->coarse_depth ? qp->coarse_depth : g1;
+        depth = std::max<uint32_t>(1, std::min(depth, maxd));
+    }
+
+    ScanLaunch a{};
+    a.slab = idx->slab;
+    a.capacity = idx->capacity;
+    a.n_sets = idx->n;
+    a.kpad = idx->kpad;
+    a.kp = lay.kp;
+    a.L = lay.L;
+    a.k = lay.k;
+    a.qsigs = d_qsigs;
+    a.depth = depth;
+    a.counters = ws.counters;
+    if (kind != QueryKind::OPH_FULL && n_q && idx->n) {
+        st = ws.grow_qmasks((uint64_t)n_q * lay.L);
+        if (st) return st;
+        HOPH_HIP(launch_query_masks(d_qsigs, n_q, lay.k, lay.kp, lay.L, ws.qmasks, s), "query mask launch");
+    }
+    a.qmasks = ws.qmasks;
+
+    uint64_t accepted = 0;
+    float pass_ms[2] = {0, 0};
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        a.surv = ws.surv;
+        a.surv_cap = ws.surv_cap;
+        a.keys = ws.keys;
+        a.keys_cap = ws.keys_cap;
+        HOPH_HIP(launch_fill_u64(ws.counters, 2, 0, s), "fill counters");
+        if (n_q && idx->n) {
+            // one pass over the whole batch; on survivor overflow, redo in sub-batches
+            auto pass = [&](uint32_t q0, uint32_t q1) -> hoph_status {
+                a.q0 = q0;
+                a.q1 = q1;
+                a.q_per_wave = pick_q_per_wave(idx->n, q1 - q0);
+                HOPH_HIP(hipEventRecord(ws.ev[0], s), "hipEventRecord");
+                if (kind == QueryKind::OPH_FULL) {
+                    HOPH_HIP(launch_oph_full(a, qp->T, qp->empty_policy, s), "oph_full launch");
+                    HOPH_HIP(hipEventRecord(ws.ev[1], s), "hipEventRecord");
+                } else {
+                    HOPH_HIP(launch_scan_coarse(a, tab, s), "coarse scan launch");
+                    HOPH_HIP(hipEventRecord(ws.ev[1], s), "hipEventRecord");
+                    HOPH_HIP(launch_scan_fine(a, tab, s), "fine scan launch");
+                }
+                HOPH_HIP(hipEventRecord(ws.ev[2], s), "hipEventRecord");
+                return HOPH_OK;
+            };
+            st = pass(0, n_q);
+            if (st) return st;
+            st = copy_counters(ws, s);
+            if (st) return st;
+            (void)hipEventElapsedTime(&pass_ms[0], ws.ev[0], ws.ev[1]);
+            (void)hipEventElapsedTime(&pass_ms[1], ws.ev[1], ws.ev[2]);
+            if (ws.h_counters[0] > ws.surv_cap) {
+                const uint64_t seen = ws.h_counters[0];
+                HOPH_HIP(launch_fill_u64(ws.counters, 2, 0, s), "fill counters");
+                uint64_t acc_before = 0;
+                uint32_t sub = (uint32_t)std::max<uint64_t>(1, (uint64_t)n_q * ws.surv_cap / seen / 2);
+                uint32_t q = 0;
+                while (q < n_q) {
+                    const uint32_t q1 = (uint32_t)std::min<uint64_t>(n_q, (uint64_t)q + sub);
+                    HOPH_HIP(launch_fill_u64(ws.counters, 1, 0, s), "fill counters");
+                    st = pass(q, q1);
+                    if (st) return st;
+                    st = copy_counters(ws, s);
+                    if (st) return st;
+                    if (ws.h_counters[0] > ws.surv_cap) {
+                        if (sub == 1) return fail(HOPH_E_NOMEM, "survivor buffer smaller than the index");
+                        sub = std::max<uint32_t>(1, sub / 2);
+                        HOPH_HIP(launch_fill_u64(ws.counters + 1, 1, acc_before, s), "fill counters");
+                        continue;
+                    }
+                    acc_before = ws.h_counters[1];
+                    q = q1;
+                }
+            }
+        }
+        st = copy_counters(ws, s);
+        if (st) return st;
+        accepted = ws.h_counters[1];
+        if (accepted <= ws.keys_cap) break;
+        if (accepted > res->capacity) break;      // reported below; no need to keep every key
+        st = ws.grow_keys(accepted);
+        if (st) return st;
+    }
+    res->needed = accepted;
+    if (accepted > res->capacity) {
+        return fail(HOPH_E_CAPACITY, "results capacity " + std::to_string(res->capacity) + " < " +
+                                         std::to_string(accepted) + " accepted pairs");
+    }
+    const bool timed = n_q && idx->n;
+    if (timed) HOPH_HIP(hipEventRecord(ws.ev[2], s), "hipEventRecord");
+    HOPH_HIP(launch_sort_keys(ws.keys, accepted, sort_capacity(accepted), s), "sort launch");
+    HOPH_HIP(launch_results(ws.keys, accepted, n_q, res->d_offsets, res->d_set_ids, s), "results launch");
+    if (timed) HOPH_HIP(hipEventRecord(ws.ev[3], s), "hipEventRecord");
+    HOPH_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    ws.last_ms[0] = ws.last_ms[1] = ws.last_ms[2] = 0.f;
+    if (timed) {
+        ws.last_ms[0] = pass_ms[0];
+        ws.last_ms[1] = pass_ms[1];
+        (void)hipEventElapsedTime(&ws.last_ms[2], ws.ev[2], ws.ev[3]);
+    }
+    return HOPH_OK;
+}
+
+// Workspace for MinWise queries, one per device.
+std::mutex g_mw_mu;
+Workspace *g_mw_ws[kMaxDevices] = {};
+
+}  // namespace
+
+extern "C" {
+
+const char *hoph_status_str(hoph_status s) {
+    switch (s) {
+    case HOPH_OK: return "HOPH_OK";
+    case HOPH_E_INVAL: return "HOPH_E_INVAL";
+    case HOPH_E_RANGE: return "HOPH_E_RANGE";
+    case HOPH_E_CAPACITY: return "HOPH_E_CAPACITY";
+    case HOPH_E_NOMEM: return "HOPH_E_NOMEM";
+    case HOPH_E_UNSUPPORTED: return "HOPH_E_UNSUPPORTED";
+    case HOPH_E_DEVICE: return "HOPH_E_DEVICE";
+    }
+    return "HOPH_E_UNKNOWN";
+}
+
+const char *hoph_last_error(void) { return g_last_error.c_str(); }
+
+hoph_status sketch_oph(const hoph_sketch_params *params, const uint32_t *d_ids, const uint64_t *d_offsets,
+                       uint64_t n_sets, uint32_t *d_sigs, void *hip_stream) {
+    g_last_error.clear();
+    if (!params) return fail(HOPH_E_INVAL, "params is NULL");
+    LayoutInfo lay;
+    std::string err;
+    hoph_status st = build_layout(*params, lay, err);
+    if (st) return fail(st, err);
+    if (n_sets == 0) return HOPH_OK;
+    if (!d_offsets || !d_sigs) return fail(HOPH_E_INVAL, "d_offsets / d_sigs is NULL");
+    if (!d_ids) return fail(HOPH_E_INVAL, "d_ids is NULL");
+    uint32_t *errw = nullptr;
+    st = device_err_word(&errw);
+    if (st) return st;
+    SketchDesc d;
+    fill_sketch_desc(*params, lay, d);
+    HOPH_HIP(launch_sketch(d, d_ids, d_offsets, n_sets, d_sigs, errw, reinterpret_cast<hipStream_t>(hip_stream)),
+             "sketch launch");
+    return HOPH_OK;
+}
+
+hoph_status build_index(const hoph_sketch_params *params, const uint32_t *d_sigs, uint64_t n_sets, uint64_t capacity,
+                        hoph_index **out, void *hip_stream) {
+    g_last_error.clear();
+    if (!params || !out) return fail(HOPH_E_INVAL, "params / out is NULL");
+    *out = nullptr;
+    if (n_sets && !d_sigs) return fail(HOPH_E_INVAL, "d_sigs is NULL");
+    if (capacity < n_sets) return fail(HOPH_E_INVAL, "capacity < n_sets");
+    if (capacity > 0xFFFFFFFFull) return fail(HOPH_E_INVAL, "capacity exceeds 2^32 sets (set ids are uint32)");
+    std::unique_ptr<hoph_index> idx(new (std::nothrow) hoph_index());
+    if (!idx) return fail(HOPH_E_NOMEM, "host allocation");
+    std::string err;
+    hoph_status st = build_layout(*params, idx->lay, err);
+    if (st) return fail(st, err);
+    HOPH_HIP(hipGetDevice(&idx->device), "hipGetDevice");
+    idx->params = *params;
+    idx->kpad = round4(params->k_group);
+    idx->capacity = std::max<uint64_t>(64, (capacity + 63) / 64 * 64);
+    idx->max_sets = capacity;
+    const uint64_t words = idx->capacity * idx->kpad * idx->lay.L;
+    if (hipMalloc(&idx->slab, words * sizeof(uint32_t)) != hipSuccess) return fail(HOPH_E_NOMEM, "index slabs");
+    st = idx->ws.init(std::max<uint64_t>(idx->capacity, 1u << 20), 1u << 16);
+    if (st) {
+        (void)hipFree(idx->slab);
+        idx->ws.release();
+        return st;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    hipError_t e = launch_index_store(d_sigs, n_sets, 0, params->k, params->k_group, idx->lay.L, idx->kpad,
+                                      idx->capacity, idx->slab, s);
+    if (e != hipSuccess) {
+        (void)hipFree(idx->slab);
+        idx->ws.release();
+        return hip_fail(e, "index store launch");
+    }
+    idx->n = n_sets;
+    *out = idx.release();
+    return HOPH_OK;
+}
+
+hoph_status index_append(hoph_index *idx, const uint32_t *d_sigs, uint64_t n_new, void *hip_stream) {
+    g_last_error.clear();
+    if (!idx) return fail(HOPH_E_INVAL, "index is NULL");
+    if (n_new == 0) return HOPH_OK;
+    if (!d_sigs) return fail(HOPH_E_INVAL, "d_sigs is NULL");
+    std::lock_guard<std::mutex> lk(idx->mu);
+    if (idx->n + n_new > idx->max_sets)
+        return fail(HOPH_E_CAPACITY, "index capacity " + std::to_string(idx->max_sets) + " exceeded");
+    DeviceGuard dg(idx->device);
+    HOPH_HIP(launch_index_store(d_sigs, n_new, idx->n, idx->params.k, idx->params.k_group, idx->lay.L, idx->kpad,
+                                idx->capacity, idx->slab, reinterpret_cast<hipStream_t>(hip_stream)),
+             "index store launch");
+    idx->n += n_new;
+    return HOPH_OK;
+}
+
+uint64_t hoph_index_size(const hoph_index *idx) { return idx ? idx->n : 0; }
+
+hoph_status hoph_index_reset(hoph_index *idx) {
+    g_last_error.clear();
+    if (!idx) return fail(HOPH_E_INVAL, "index is NULL");
+    std::lock_guard<std::mutex> lk(idx->mu);
+    idx->n = 0;
+    return HOPH_OK;
+}
+
+hoph_status hoph_query_timing(const hoph_index *idx, float ms[3]) {
+    g_last_error.clear();
+    if (!idx || !ms) return fail(HOPH_E_INVAL, "NULL argument");
+    hoph_index *m = const_cast<hoph_index *>(idx);
+    std::lock_guard<std::mutex> lk(m->mu);
+    for (int i = 0; i < 3; ++i) ms[i] = m->ws.last_ms[i];
+    return HOPH_OK;
+}
+
+void hoph_index_free(hoph_index *idx) {
+    if (!idx) return;
+    {
+        DeviceGuard dg(idx->device);
+        (void)hipDeviceSynchronize();
+        if (idx->slab) (void)hipFree(idx->slab);
+        idx->ws.release();
+    }
+    delete idx;
+}
+
+hoph_status query_goph(const hoph_index *index, const uint32_t *d_qsigs, uint32_t n_q, const hoph_query_params *qp,
+                       hoph_results *results, void *hip_stream) {
+    g_last_error.clear();
+    return run_query(index, d_qsigs, n_q, qp, results, hip_stream, QueryKind::GOPH);
+}
+
+hoph_status query_hoph(const hoph_index *index, const uint32_t *d_qsigs, uint32_t n_q, const hoph_query_params *qp,
+                       hoph_results *results, void *hip_stream) {
+    g_last_error.clear();
+    return run_query(index, d_qsigs, n_q, qp, results, hip_stream, QueryKind::HOPH);
+}
+
+hoph_status query_oph_full(const hoph_index *index, const uint32_t *d_qsigs, uint32_t n_q,
+                           const hoph_query_params *qp, hoph_results *results, void *hip_stream) {
+    g_last_error.clear();
+    return run_query(index, d_qsigs, n_q, qp, results, hip_stream, QueryKind::OPH_FULL);
+}
+
+static hoph_status check_minwise(const hoph_minwise_params *p) {
+    if (!p) return fail(HOPH_E_INVAL, "params is NULL");
+    if (p->k == 0 || p->k > 4096) return fail(HOPH_E_INVAL, "k must be in [1, 4096]");
+    if (p->hash != HOPH_HASH_MODP31 && p->hash != HOPH_HASH_MODP32P15)
+        return fail(HOPH_E_INVAL, "MinWise needs HOPH_HASH_MODP31 or HOPH_HASH_MODP32P15");
+    if (p->universe == 0 || p->universe > (1ull << 32)) return fail(HOPH_E_INVAL, "universe must be in [1, 2^32]");
+    if (p->hash == HOPH_HASH_MODP31 && p->universe > kP31) return fail(HOPH_E_INVAL, "universe exceeds 2^31 - 1");
+    if (!p->d_hash_a || !p->d_hash_b) return fail(HOPH_E_INVAL, "hash coefficient arrays are NULL");
+    return HOPH_OK;
+}
+
+hoph_status minwise_sketch(const hoph_minwise_params *params, const uint32_t *d_ids, const uint64_t *d_offsets,
+                           uint64_t n_sets, uint64_t *d_sigs, void *hip_stream) {
+    g_last_error.clear();
+    hoph_status st = check_minwise(params);
+    if (st) return st;
+    if (n_sets == 0) return HOPH_OK;
+    if (!d_ids || !d_offsets || !d_sigs) return fail(HOPH_E_INVAL, "NULL device pointer");
+    uint32_t *errw = nullptr;
+    st = device_err_word(&errw);
+    if (st) return st;
+    HOPH_HIP(launch_minwise_sketch(params->k, params->hash, params->universe, params->d_hash_a, params->d_hash_b, d_ids,
+                                   d_offsets, n_sets, d_sigs, errw, reinterpret_cast<hipStream_t>(hip_stream)),
+             "minwise sketch launch");
+    return HOPH_OK;
+}
+
+hoph_status minwise_query(const hoph_minwise_params *params, const uint64_t *d_sigs, uint64_t n_sets,
+                          const uint64_t *d_qsigs, uint32_t n_q, hoph_ratio T, hoph_results *res, void *hip_stream) {
+    g_last_error.clear();
+    hoph_status st = check_minwise(params);
+    if (st) return st;
+    if (!valid_ratio_T(T)) return fail(HOPH_E_INVAL, "T must be an exact ratio in (0, 1]");
+    st = check_results(res, n_q);
+    if (st) return st;
+    if ((n_sets && !d_sigs) || (n_q && !d_qsigs)) return fail(HOPH_E_INVAL, "NULL device pointer");
+    if (n_sets > 0xFFFFFFFFull) return fail(HOPH_E_INVAL, "n_sets exceeds 2^32");
+    int dev = 0;
+    HOPH_HIP(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_mw_mu);
+    if (!g_mw_ws[dev]) {
+        Workspace *w = new (std::nothrow) Workspace();
+        if (!w) return fail(HOPH_E_NOMEM, "host allocation");
+        st = w->init(1, 1u << 16);
+        if (st) { w->release(); delete w; return st; }
+        g_mw_ws[dev] = w;
+    }
+    Workspace &ws = *g_mw_ws[dev];
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    uint64_t accepted = 0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        HOPH_HIP(launch_fill_u64(ws.counters, 2, 0, s), "fill counters");
+        HOPH_HIP(launch_minwise_scan(params->k, d_sigs, n_sets, d_qsigs, 0, n_q, T, ws.keys, ws.keys_cap, ws.counters, s),
+                 "minwise scan launch");
+        st = copy_counters(ws, s);
+        if (st) return st;
+        accepted = ws.h_counters[1];
+        if (accepted <= ws.keys_cap || accepted > res->capacity) break;
+        st = ws.grow_keys(accepted);
+        if (st) return st;
+    }
+    res->needed = accepted;
+    if (accepted > res->capacity) return fail(HOPH_E_CAPACITY, "results capacity too small");
+    HOPH_HIP(launch_sort_keys(ws.keys, accepted, sort_capacity(accepted), s), "sort launch");
+    HOPH_HIP(launch_results(ws.keys, accepted, n_q, res->d_offsets, res->d_set_ids, s), "results launch");
+    HOPH_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    return HOPH_OK;
+}
+
+hoph_status hoph_sync(void *hip_stream) {
+    g_last_error.clear();
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    HOPH_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    uint32_t *errw = nullptr;
+    hoph_status st = device_err_word(&errw);
+    if (st) return st;
+    uint32_t h = 0;
+    HOPH_HIP(hipMemcpy(&h, errw, sizeof(h), hipMemcpyDeviceToHost), "hipMemcpy(error word)");
+    if (h) {
+        HOPH_HIP(hipMemset(errw, 0, sizeof(uint32_t)), "hipMemset(error word)");
+        if (h & kErrRange) return fail(HOPH_E_RANGE, "an id >= universe (or a table value >= universe) was skipped");
+        return fail(HOPH_E_INVAL, "an empty set was sketched (its signature is all EMPTY)");
+    }
+    return HOPH_OK;
+}
+
+hoph_status hoph_layout_starts(const hoph_sketch_params *params, uint64_t *starts) {
+    g_last_error.clear();
+    if (!params || !starts) return fail(HOPH_E_INVAL, "NULL argument");
+    hoph_sketch_params p = *params;
+    if (p.hash == HOPH_HASH_TABLE && !p.d_perm) p.d_perm = reinterpret_cast<const uint32_t *>(1);  // not read here
+    LayoutInfo lay;
+    std::string err;
+    hoph_status st = build_layout(p, lay, err);
+    if (st) return fail(st, err);
+    std::vector<uint64_t> v;
+    host_starts(lay, v);
+    std::copy(v.begin(), v.end(), starts);
+    return HOPH_OK;
+}
+
+hoph_status hoph_tail_integers(uint32_t n, hoph_ratio T, hoph_ratio eps, int32_t *j_lo, int32_t *j_hi) {
+    g_last_error.clear();
+    if (!j_lo || !j_hi) return fail(HOPH_E_INVAL, "NULL argument");
+    std::string err;
+    hoph_status st = tail_integers(n, T, eps, *j_lo, *j_hi, err);
+    if (st) return fail(st, err);
+    return HOPH_OK;
+}
+
+hoph_status hoph_build_decision_tables(const hoph_sketch_params *params, const hoph_query_params *qp, uint32_t goph,
+                                       hoph_decision_tables *out) {
+    g_last_error.clear();
+    if (!params || !qp || !out) return fail(HOPH_E_INVAL, "NULL argument");
+    if (!valid_ratio_T(qp->T)) return fail(HOPH_E_INVAL, "T must be an exact ratio in (0, 1]");
+    if (!valid_ratio_eps(qp->eps)) return fail(HOPH_E_INVAL, "eps must be in [0, 1)");
+    hoph_sketch_params p = *params;
+    if (p.hash == HOPH_HASH_TABLE && !p.d_perm) p.d_perm = reinterpret_cast<const uint32_t *>(1);  // not read here
+    LayoutInfo lay;
+    std::string err;
+    hoph_status st = build_layout(p, lay, err);
+    if (st) return fail(st, err);
+    st = build_tables(lay, *qp, goph != 0, *out, err);
+    if (st) return fail(st, err);
+    return HOPH_OK;
+}
+
+hoph_status hoph_selftest_bins(const hoph_sketch_params *params, const uint32_t *h_perm, const uint32_t *h_ids,
+                               uint64_t n, uint32_t *out_bin, uint32_t *out_off) {
+    g_last_error.clear();
+    if (!params || (n && (!h_ids || !out_bin || !out_off))) return fail(HOPH_E_INVAL, "NULL argument");
+    hoph_sketch_params p = *params;
+    if (p.hash == HOPH_HASH_TABLE) {
+        if (!h_perm) return fail(HOPH_E_INVAL, "h_perm is NULL");
+        p.d_perm = h_perm;
+    }
+    LayoutInfo lay;
+    std::string err;
+    hoph_status st = build_layout(p, lay, err);
+    if (st) return fail(st, err);
+    std::vector<uint8_t> lut;
+    std::vector<uint64_t> starts;
+    host_lut(lay, lut);
+    host_starts(lay, starts);
+    std::vector<RegionEntry> reg(lay.n_regions + 1);
+    for (uint32_t r = 0; r <= lay.n_regions; ++r)
+        reg[r] = RegionEntry{lay.reg_start[r], r < lay.n_regions ? lay.reg_magic[r] : 0};
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint64_t x = h_ids[i];
+        if (x >= p.universe) return fail(HOPH_E_RANGE, "id >= universe");
+        uint64_t v;
+        if (p.hash == HOPH_HASH_TABLE) v = h_perm[x];
+        else if (p.hash == HOPH_HASH_MODP31) v = psi_p31(x, p.hash_a, p.hash_b);
+        else v = psi_p32(x, p.hash_a, p.hash_b);
+        if (v >= lay.R) return fail(HOPH_E_RANGE, "table value >= universe");
+        uint32_t b;
+        uint64_t start;
+        locate(v, lut.data(), lay.lut_shift, reg.data(), lay.n_regions, lay.nb, starts.data(), b, start);
+        out_bin[i] = b;
+        out_off[i] = (uint32_t)(v - start);
+    }
+    return HOPH_OK;
+}
+
+hoph_status hoph_pair_counts(const hoph_index *idx, const uint32_t *d_qsigs, uint32_t n_q, const uint32_t *d_pairs,
+                             uint64_t n_pairs, uint32_t policy, uint32_t *d_m, uint32_t *d_e, void *hip_stream) {
+    g_last_error.clear();
+    if (!idx) return fail(HOPH_E_INVAL, "index is NULL");
+    if (policy > HOPH_EMPTY_EITHER) return fail(HOPH_E_INVAL, "unknown empty policy");
+    if (n_pairs == 0) return HOPH_OK;
+    if (!d_qsigs || !d_pairs || !d_m || !d_e) return fail(HOPH_E_INVAL, "NULL device pointer");
+    DeviceGuard dg(idx->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    HOPH_HIP(launch_pair_counts(idx->slab, idx->capacity, idx->n, idx->kpad, idx->lay.kp, idx->lay.L, idx->lay.k,
+                                d_qsigs, n_q, d_pairs, n_pairs, policy, d_m, d_e, s),
+             "pair counts launch");
+    HOPH_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    return HOPH_OK;
+}
+
+}  // extern "C"

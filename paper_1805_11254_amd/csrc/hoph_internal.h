@@ -1,0 +1,188 @@
+// Internal declarations shared by the host runtime and the HIP kernels of
+// libhoph.  Nothing here is part of the C ABI (include/hoph.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "hoph.h"
+
+namespace hoph {
+
+constexpr uint64_t kP31 = 2147483647ull;        // 2^31 - 1
+constexpr uint64_t kP32 = 4294967311ull;        // 2^32 + 15, prime
+constexpr uint32_t kLutMax = 4096;              // region lookup entries
+constexpr uint32_t kTile = 64;                  // sets per index tile = one wavefront
+constexpr uint32_t kMaxDepth = 4;               // coarse groups kept in registers
+
+// Device error bits (one 32-bit word per device).
+constexpr uint32_t kErrRange = 1u;              // an id >= universe, or a table value >= R
+constexpr uint32_t kErrEmptySet = 2u;           // a set with no element
+
+// ---------------------------------------------------------------------------
+// Sketch layout, passed by value to the sketch kernels.  The permuted range
+// [0, R) is cut into n_regions regions (OPH: 1 region of k bins; HIER: L
+// groups of k' bins).  Inside region r (start s_r, size z_r, n_r bins) bin t
+// starts at s_r + ceil(t z_r / n_r).
+// ---------------------------------------------------------------------------
+struct SketchDesc {
+    const uint32_t *perm;
+    uint64_t universe, ha, hb, R;
+    uint32_t hash, k, n_regions, lut_shift, lut_size, nb;   // nb = bins per region
+    uint64_t reg_start[HOPH_MAX_GROUPS + 1];                 // reg_start[n_regions] = R
+    uint64_t reg_magic[HOPH_MAX_GROUPS];                     // floor(2^64 nb / z_r), see bin_of
+};
+
+// Host view of a validated layout.
+struct LayoutInfo {
+    uint64_t R = 0;
+    uint32_t k = 0, kp = 0, L = 0, n_regions = 0, nb = 0, ra = 1, rb = 1;
+    std::vector<uint64_t> reg_start;   // n_regions + 1
+    std::vector<uint64_t> reg_magic;   // n_regions
+    uint32_t lut_shift = 0, lut_size = 0;
+};
+
+// ---------------------------------------------------------------------------
+// Exact integer decision tables, passed by value to the scan kernels.
+// ---------------------------------------------------------------------------
+struct ScanTab {
+    int64_t W[HOPH_MAX_GROUPS];
+    int64_t acc[HOPH_MAX_GROUPS];
+    int64_t rej[HOPH_MAX_GROUPS];
+    int64_t dmul[HOPH_MAX_KGROUP + 1];
+    int64_t lambda;                 // rate scale: lcm(1..k') (JOINT, EITHER) or k' (LITERAL)
+    int32_t macc0[HOPH_MAX_KGROUP + 1];   // first group, e < k': accept iff m >= macc0[e]
+    int32_t mrej0[HOPH_MAX_KGROUP + 1];   // first group, e < k': reject iff m <= mrej0[e]
+    uint32_t L, kp, policy, pad;
+};
+
+// A pair that the coarse pass could not decide: continue at group `depth`.
+struct Survivor {
+    uint32_t q, s;
+    int64_t S;
+};
+
+// ---------------------------------------------------------------------------
+// Inline arithmetic shared by the kernels and the host self-test hook.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b) {
+    return (uint64_t)(((unsigned __int128)a * b) >> 64);
+}
+
+// (a x + b) mod (2^31 - 1) for x, a, b < 2^31 - 1: Mersenne folding.
+__host__ __device__ inline uint64_t psi_p31(uint64_t x, uint64_t a, uint64_t b) {
+    uint64_t v = a * x + b;                       // < 2^62 + 2^31
+    v = (v & kP31) + (v >> 31);                   // < 2^32 + 2
+    v = (v & kP31) + (v >> 31);                   // < 2^31 + 2
+    return v >= kP31 ? v - kP31 : v;
+}
+
+// (a x + b) mod (2^32 + 15) for x < 2^32, a, b < 2^32 + 15, using 2^32 = -15 (mod p).
+__host__ __device__ inline uint64_t psi_p32(uint64_t x, uint64_t a, uint64_t b) {
+    uint64_t lo = a * x;
+    uint64_t hi = mulhi64(a, x);                  // <= 1
+    lo += b;
+    hi += (lo < b);                               // <= 2
+    // w = hi 2^64 + l1 2^32 + l0 = 225 hi - 15 l1 + l0 (mod p)
+    uint64_t l0 = lo & 0xFFFFFFFFull, l1 = lo >> 32;
+    uint64_t z = l0 + 225ull * hi + 16ull * kP32 - 15ull * l1;   // in (0, 2^37)
+    uint64_t z0 = z & 0xFFFFFFFFull, z1 = z >> 32;               // z1 < 32
+    uint64_t r = z0 + kP32 - 15ull * z1;                         // in [p - 480, 2^32 + p)
+    return r >= kP32 ? r - kP32 : r;
+}
+
+// One region of the permuted range: its first value and the reciprocal
+// M = floor(2^64 nb / z) of its size z (nb bins per region).
+struct RegionEntry {
+    uint64_t start, magic;
+};
+
+// Bin of the permuted value v and the first value of that bin.
+//  - region: lut gives the region holding the first value of v's lookup
+//    granule; later regions that start inside the granule are stepped over;
+//  - bin inside the region: t = floor(y nb / z) for y = v - start; the
+//    estimate floor(y M / 2^64) is t or t - 1 (y < 2^34), and one comparison
+//    with the next bin start settles it.
+// reg has n_regions + 1 entries (the last holds start = R); starts has k + 1.
+__host__ __device__ inline void locate(uint64_t v, const uint8_t *lut, uint32_t lut_shift, const RegionEntry *reg,
+                                       uint32_t n_regions, uint32_t nb, const uint64_t *starts, uint32_t &bin,
+                                       uint64_t &start) {
+    uint32_t r = 0;
+    if (n_regions > 1) {
+        r = lut[v >> lut_shift];
+        while (r + 1 < n_regions && v >= reg[r + 1].start) ++r;
+    }
+    const RegionEntry re = reg[r];
+    const uint32_t b = r * nb + (uint32_t)mulhi64(v - re.start, re.magic);
+    const uint64_t s0 = starts[b], s1 = starts[b + 1];
+    const bool up = v >= s1;
+    bin = b + (up ? 1u : 0u);
+    start = up ? s1 : s0;
+}
+
+// ---------------------------------------------------------------------------
+// Host runtime (host_tables.cpp)
+// ---------------------------------------------------------------------------
+hoph_status build_layout(const hoph_sketch_params &p, LayoutInfo &out, std::string &err);
+void fill_sketch_desc(const hoph_sketch_params &p, const LayoutInfo &lay, SketchDesc &d);
+void host_lut(const LayoutInfo &lay, std::vector<uint8_t> &lut);
+void host_starts(const LayoutInfo &lay, std::vector<uint64_t> &starts);
+hoph_status tail_integers(uint32_t n, hoph_ratio T, hoph_ratio eps, int32_t &j_lo, int32_t &j_hi,
+                          std::string &err);
+hoph_status build_tables(const LayoutInfo &lay, const hoph_query_params &qp, bool goph,
+                         hoph_decision_tables &out, std::string &err);
+void to_scan_tab(const hoph_decision_tables &t, ScanTab &s);
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (k_*.hip).  All return hipError_t of the launch.
+// ---------------------------------------------------------------------------
+int device_cu_count();   // compute units of the current device (cached)
+hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t value, hipStream_t st);
+hipError_t launch_sketch(const SketchDesc &d, const uint32_t *ids, const uint64_t *offsets,
+                         uint64_t n_sets, uint32_t *sigs, uint32_t *err_flag, hipStream_t st);
+hipError_t launch_index_store(const uint32_t *sigs, uint64_t n_new, uint64_t first, uint32_t k,
+                              uint32_t kp, uint32_t L, uint32_t kpad, uint64_t capacity,
+                              uint32_t *slab, hipStream_t st);
+hipError_t launch_pair_counts(const uint32_t *slab, uint64_t capacity, uint64_t n_sets, uint32_t kpad,
+                              uint32_t kp, uint32_t L, uint32_t k, const uint32_t *qsigs, uint32_t n_q,
+                              const uint32_t *pairs, uint64_t n_pairs, uint32_t policy, uint32_t *m,
+                              uint32_t *e, hipStream_t st);
+
+struct ScanLaunch {
+    const uint32_t *slab;       // index slabs (see k_index.hip for the layout)
+    uint64_t capacity;          // sets the slab can hold (multiple of 64)
+    uint64_t n_sets;
+    uint32_t kpad, kp, L, k;
+    const uint32_t *qsigs;      // row-major n_q x k
+    const uint64_t *qmasks;     // n_q x L empty-bin masks of the queries
+    uint32_t q0, q1;            // query rows [q0, q1)
+    uint32_t depth;             // coarse groups
+    uint32_t q_per_wave;
+    Survivor *surv;
+    uint64_t surv_cap;
+    uint64_t *keys;
+    uint64_t keys_cap;
+    uint64_t *counters;         // [0] survivors, [1] accepted
+};
+hipError_t launch_query_masks(const uint32_t *qsigs, uint32_t n_q, uint32_t k, uint32_t kp, uint32_t L,
+                              uint64_t *out, hipStream_t st);
+hipError_t launch_scan_coarse(const ScanLaunch &a, const ScanTab &tab, hipStream_t st);
+hipError_t launch_scan_fine(const ScanLaunch &a, const ScanTab &tab, hipStream_t st);
+hipError_t launch_oph_full(const ScanLaunch &a, hoph_ratio T, uint32_t policy, hipStream_t st);
+hipError_t launch_sort_keys(uint64_t *keys, uint64_t n, uint64_t n_pow2, hipStream_t st);
+hipError_t launch_results(const uint64_t *keys, uint64_t n, uint32_t n_q, uint64_t *offsets,
+                          uint32_t *set_ids, hipStream_t st);
+hipError_t launch_minwise_sketch(uint32_t k, uint32_t hash, uint64_t universe, const uint64_t *ha,
+                                 const uint64_t *hb, const uint32_t *ids, const uint64_t *offsets,
+                                 uint64_t n_sets, uint64_t *sigs, uint32_t *err_flag,
+                                 hipStream_t st);
+hipError_t launch_minwise_scan(uint32_t k, const uint64_t *sigs, uint64_t n_sets,
+                               const uint64_t *qsigs, uint32_t q0, uint32_t q1, hoph_ratio T,
+                               uint64_t *keys, uint64_t keys_cap, uint64_t *counters,
+                               hipStream_t st);
+
+}  // namespace hoph

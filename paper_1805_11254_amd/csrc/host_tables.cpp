@@ -1,0 +1,345 @@
+// Host side of libhoph: layout validation (Sec. 3.2, Sec. 4.1), the exact
+// binomial tail integers (Eq. 10, Def. 1) and the integer cutoff tables that
+// turn the sequential comparison of Alg. 1 / Alg. 2 into comparisons of an
+// exact 64-bit state.
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hoph_internal.h"
+
+namespace hoph {
+
+typedef __int128 i128;
+typedef unsigned __int128 u128;
+
+// ---------------------------------------------------------------------------
+// Layout
+// ---------------------------------------------------------------------------
+static uint64_t range_of(const hoph_sketch_params &p) {
+    if (p.hash == HOPH_HASH_TABLE) return p.universe;
+    if (p.hash == HOPH_HASH_MODP31) return kP31;
+    return kP32;
+}
+
+hoph_status build_layout(const hoph_sketch_params &p, LayoutInfo &out, std::string &err) {
+    if (p.layout != HOPH_LAYOUT_OPH && p.layout != HOPH_LAYOUT_HIER) { err = "unknown layout"; return HOPH_E_INVAL; }
+    if (p.k_group == 0 || p.k_group > HOPH_MAX_KGROUP) { err = "k_group must be in [1, 64]"; return HOPH_E_INVAL; }
+    if (p.k == 0 || p.k % p.k_group) { err = "k must be a positive multiple of k_group"; return HOPH_E_INVAL; }
+    if (p.k / p.k_group > HOPH_MAX_GROUPS) { err = "k / k_group must be <= 64"; return HOPH_E_INVAL; }
+    if (p.universe == 0 || p.universe > (1ull << 32)) { err = "universe must be in [1, 2^32]"; return HOPH_E_INVAL; }
+    switch (p.hash) {
+    case HOPH_HASH_TABLE:
+        if (!p.d_perm) { err = "HOPH_HASH_TABLE needs d_perm"; return HOPH_E_INVAL; }
+        break;
+    case HOPH_HASH_MODP31:
+        if (p.universe > kP31) { err = "universe exceeds 2^31 - 1 for HOPH_HASH_MODP31"; return HOPH_E_INVAL; }
+        if (p.hash_a == 0 || p.hash_a >= kP31 || p.hash_b >= kP31) { err = "hash coefficients out of range"; return HOPH_E_INVAL; }
+        break;
+    case HOPH_HASH_MODP32P15:
+        if (p.hash_a == 0 || p.hash_a >= kP32 || p.hash_b >= kP32) { err = "hash coefficients out of range"; return HOPH_E_INVAL; }
+        break;
+    default:
+        err = "unknown hash";
+        return HOPH_E_INVAL;
+    }
+    const uint64_t R = range_of(p);
+    LayoutInfo L;
+    L.R = R;
+    L.k = p.k;
+    L.kp = p.k_group;
+    L.L = p.k / p.k_group;
+    L.ra = p.layout == HOPH_LAYOUT_HIER ? p.ratio_a : 1;
+    L.rb = p.layout == HOPH_LAYOUT_HIER ? p.ratio_b : 1;
+    std::vector<uint64_t> size;
+    if (p.layout == HOPH_LAYOUT_OPH) {
+        if ((uint64_t)p.k > R) { err = "more bins than permuted values"; return HOPH_E_INVAL; }
+        L.n_regions = 1;
+        L.nb = p.k;
+        L.reg_start = {0, R};
+        size = {R};
+    } else {
+        if (p.ratio_a == 0 || p.ratio_b == 0) { err = "ratio a:b needs a, b >= 1"; return HOPH_E_INVAL; }
+        L.n_regions = L.L;
+        L.nb = p.k_group;
+        uint64_t lo = 0;
+        L.reg_start.push_back(0);
+        for (uint32_t g = 0; g + 1 < L.L; ++g) {
+            uint64_t z = (uint64_t)((u128)(R - lo) * p.ratio_a / ((uint64_t)p.ratio_a + p.ratio_b));
+            uint64_t rest = R - lo - z;
+            if (z <= p.k_group || rest <= p.k_group) {
+                err = "hierarchy deeper than the stop rule allows (a split leaves a part of at most k_group values)";
+                return HOPH_E_INVAL;
+            }
+            size.push_back(z);
+            lo += z;
+            L.reg_start.push_back(lo);
+        }
+        if (R - lo < p.k_group) { err = "last group smaller than k_group"; return HOPH_E_INVAL; }
+        size.push_back(R - lo);
+        L.reg_start.push_back(R);
+    }
+    for (uint32_t r = 0; r < L.n_regions; ++r) {
+        // widest bin of the region: ceil(z / nb)
+        if ((size[r] + L.nb - 1) / L.nb > 0xFFFFFFFFull) { err = "a bin is wider than 2^32 - 1 values"; return HOPH_E_INVAL; }
+        uint64_t M = (size[r] == L.nb) ? ~0ull : (uint64_t)(((u128)L.nb << 64) / size[r]);
+        L.reg_magic.push_back(M);
+    }
+    uint32_t sh = 0;
+    while (((R - 1) >> sh) >= kLutMax) ++sh;
+    L.lut_shift = sh;
+    L.lut_size = (uint32_t)((R - 1) >> sh) + 1;
+    out = std::move(L);
+    return HOPH_OK;
+}
+
+void fill_sketch_desc(const hoph_sketch_params &p, const LayoutInfo &lay, SketchDesc &d) {
+    std::memset(&d, 0, sizeof(d));
+    d.perm = p.d_perm;
+    d.universe = p.universe;
+    d.ha = p.hash_a;
+    d.hb = p.hash_b;
+    d.R = lay.R;
+    d.hash = p.hash;
+    d.k = lay.k;
+    d.n_regions = lay.n_regions;
+    d.lut_shift = lay.lut_shift;
+    d.lut_size = lay.lut_size;
+    d.nb = lay.nb;
+    for (uint32_t r = 0; r <= lay.n_regions; ++r) d.reg_start[r] = lay.reg_start[r];
+    for (uint32_t r = 0; r < lay.n_regions; ++r) d.reg_magic[r] = lay.reg_magic[r];
+}
+
+void host_lut(const LayoutInfo &lay, std::vector<uint8_t> &lut) {
+    lut.assign(lay.lut_size, 0);
+    for (uint32_t g = 0; g < lay.lut_size; ++g) {
+        uint64_t v = (uint64_t)g << lay.lut_shift;
+        uint32_t r = 0;
+        while (r + 1 < lay.n_regions && v >= lay.reg_start[r + 1]) ++r;
+        lut[g] = (uint8_t)r;
+    }
+}
+
+void host_starts(const LayoutInfo &lay, std::vector<uint64_t> &starts) {
+    starts.assign((size_t)lay.k + 1, 0);
+    for (uint32_t b = 0; b < lay.k; ++b) {
+        uint32_t r = b / lay.nb, t = b % lay.nb;
+        uint64_t z = lay.reg_start[r + 1] - lay.reg_start[r];
+        starts[b] = lay.reg_start[r] + (uint64_t)(((u128)t * z + lay.nb - 1) / lay.nb);
+    }
+    starts[lay.k] = lay.R;
+}
+
+// ---------------------------------------------------------------------------
+// Minimal unsigned big integers for exact binomial tails.
+// ---------------------------------------------------------------------------
+struct Big {
+    std::vector<uint32_t> d;   // little-endian limbs, no leading zeros
+    static Big of(uint64_t v) {
+        Big b;
+        while (v) { b.d.push_back((uint32_t)v); v >>= 32; }
+        return b;
+    }
+    void trim() { while (!d.empty() && d.back() == 0) d.pop_back(); }
+    void add(const Big &o) {
+        if (o.d.size() > d.size()) d.resize(o.d.size(), 0);
+        uint64_t c = 0;
+        for (size_t i = 0; i < d.size(); ++i) {
+            uint64_t s = (uint64_t)d[i] + (i < o.d.size() ? o.d[i] : 0) + c;
+            d[i] = (uint32_t)s;
+            c = s >> 32;
+        }
+        if (c) d.push_back((uint32_t)c);
+    }
+    Big mul(const Big &o) const {
+        Big r;
+        if (d.empty() || o.d.empty()) return r;
+        r.d.assign(d.size() + o.d.size(), 0);
+        for (size_t i = 0; i < d.size(); ++i) {
+            uint64_t c = 0;
+            for (size_t j = 0; j < o.d.size(); ++j) {
+                uint64_t t = (uint64_t)d[i] * o.d[j] + r.d[i + j] + c;
+                r.d[i + j] = (uint32_t)t;
+                c = t >> 32;
+            }
+            size_t k = i + o.d.size();
+            while (c) {
+                uint64_t t = (uint64_t)r.d[k] + c;
+                r.d[k++] = (uint32_t)t;
+                c = t >> 32;
+            }
+        }
+        r.trim();
+        return r;
+    }
+    static int cmp(const Big &a, const Big &b) {
+        if (a.d.size() != b.d.size()) return a.d.size() < b.d.size() ? -1 : 1;
+        for (size_t i = a.d.size(); i-- > 0;)
+            if (a.d[i] != b.d[i]) return a.d[i] < b.d[i] ? -1 : 1;
+        return 0;
+    }
+};
+
+hoph_status tail_integers(uint32_t n, hoph_ratio T, hoph_ratio eps, int32_t &j_lo, int32_t &j_hi,
+                          std::string &err) {
+    if (n == 0 || n > 256) { err = "binomial size must be in [1, 256]"; return HOPH_E_INVAL; }
+    if (T.den == 0 || T.num == 0 || T.num > T.den) { err = "T must be in (0, 1]"; return HOPH_E_INVAL; }
+    if (eps.den == 0 || eps.num >= eps.den) { err = "eps must be in [0, 1)"; return HOPH_E_INVAL; }
+    // P(X = i) td^n = C(n, i) tn^i (td - tn)^(n - i)
+    std::vector<Big> C(n + 1), pw(n + 1), pq(n + 1), term(n + 1);
+    C[0] = Big::of(1);
+    for (uint32_t row = 1; row <= n; ++row)            // Pascal's rule, right to left
+        for (uint32_t i = row; i >= 1; --i) {
+            if (i == row) C[i] = Big::of(1); else C[i].add(C[i - 1]);
+        }
+    pw[0] = Big::of(1);
+    pq[0] = Big::of(1);
+    Big btn = Big::of(T.num), bq = Big::of(T.den - T.num);
+    for (uint32_t i = 1; i <= n; ++i) { pw[i] = pw[i - 1].mul(btn); pq[i] = pq[i - 1].mul(bq); }
+    for (uint32_t i = 0; i <= n; ++i) term[i] = C[i].mul(pw[i]).mul(pq[n - i]);
+    Big total = Big::of(1);
+    Big btd = Big::of(T.den);
+    for (uint32_t i = 0; i < n; ++i) total = total.mul(btd);
+    Big rhs = total.mul(Big::of(eps.num));          // eps td^n, scaled by eps.den below
+    Big bed = Big::of(eps.den);
+    // lower tail: P(X <= j) <= eps  <=>  ed * sum_{i <= j} term_i <= en * td^n
+    j_lo = -1;
+    Big cum;
+    for (uint32_t j = 0; j <= n; ++j) {
+        cum.add(term[j]);
+        if (Big::cmp(cum.mul(bed), rhs) <= 0) j_lo = (int32_t)j; else break;
+    }
+    // upper tail: P(X >= j) <= eps
+    j_hi = (int32_t)n + 1;
+    Big cu;
+    for (int32_t j = (int32_t)n; j >= 0; --j) {
+        cu.add(term[j]);
+        if (Big::cmp(cu.mul(bed), rhs) <= 0) j_hi = j; else break;
+    }
+    return HOPH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Decision tables
+// ---------------------------------------------------------------------------
+static i128 floor_div(i128 a, i128 b) {            // b > 0
+    i128 q = a / b;
+    if ((a % b != 0) && (a < 0)) --q;
+    return q;
+}
+static i128 ceil_div(i128 a, i128 b) {             // b > 0
+    i128 q = a / b;
+    if ((a % b != 0) && (a > 0)) ++q;
+    return q;
+}
+static uint64_t gcd64(uint64_t a, uint64_t b) {
+    while (b) { uint64_t t = a % b; a = b; b = t; }
+    return a;
+}
+
+hoph_status build_tables(const LayoutInfo &lay, const hoph_query_params &qp, bool goph,
+                         hoph_decision_tables &out, std::string &err) {
+    if (qp.empty_policy > HOPH_EMPTY_EITHER) { err = "unknown empty policy"; return HOPH_E_INVAL; }
+    std::memset(&out, 0, sizeof(out));
+    const uint32_t kp = lay.kp, L = lay.L;
+    hoph_status st = tail_integers(kp, qp.T, qp.eps, out.j_lo, out.j_hi, err);
+    if (st) return st;
+    out.L = L;
+    out.k_group = kp;
+    out.empty_policy = qp.empty_policy;
+    out.goph = goph ? 1 : 0;
+    const i128 LIM = (i128)INT64_MAX - 2;
+    // rate scale: every rate m / (k' - e) is an integer multiple of 1 / lambda
+    i128 lam = 1;
+    if (qp.empty_policy == HOPH_EMPTY_LITERAL) {
+        lam = kp;
+    } else {
+        for (uint32_t i = 2; i <= kp; ++i) {
+            lam = lam / (i128)gcd64((uint64_t)(lam % i), i) * i;
+            if (lam > LIM) { err = "lcm(1..k_group) does not fit 64 bits"; return HOPH_E_UNSUPPORTED; }
+        }
+    }
+    // integer group weights W_j over wsum: GOPH 1/L; HOPH a b^(j-1) / (a+b)^j for
+    // j < L and (b / (a+b))^(L-1) for the last group
+    i128 W[HOPH_MAX_GROUPS], wsum = 0;
+    if (goph) {
+        for (uint32_t j = 0; j < L; ++j) W[j] = 1;
+        wsum = L;
+    } else {
+        const i128 a = lay.ra, b = lay.rb;
+        i128 pb = 1;                       // b^(j-1)
+        for (uint32_t j = 0; j + 1 < L; ++j) {
+            i128 w = a * pb;
+            for (uint32_t t = j + 1; t + 1 < L; ++t) {   // (a+b)^(L-1-j-1)
+                w *= (a + b);
+                if (w > LIM) { err = "group weights do not fit 64 bits"; return HOPH_E_UNSUPPORTED; }
+            }
+            W[j] = w;
+            pb *= b;
+            if (pb > LIM) { err = "group weights do not fit 64 bits"; return HOPH_E_UNSUPPORTED; }
+        }
+        W[L - 1] = pb;
+        for (uint32_t j = 0; j < L; ++j) wsum += W[j];
+    }
+    if (wsum > LIM / lam) { err = "exact decision state exceeds 64 bits for these parameters"; return HOPH_E_UNSUPPORTED; }
+    const i128 Dn = wsum * lam;            // S~ = S * Dn, S~ in [0, Dn]
+    const i128 tn = qp.T.num, td = qp.T.den;
+    out.lcm = (int64_t)lam;
+    out.wsum = (int64_t)wsum;
+    for (uint32_t e = 0; e < kp; ++e)
+        out.dmul[e] = qp.empty_policy == HOPH_EMPTY_LITERAL ? (e == 0 ? 1 : 0) : (int64_t)(lam / (kp - e));
+    out.dmul[kp] = (int64_t)lam;
+    auto clampc = [&](i128 v) -> int64_t {
+        if (v < -1) return -1;
+        if (v > Dn + 1) return (int64_t)(Dn + 1);
+        return (int64_t)v;
+    };
+    i128 Wc = 0;
+    for (uint32_t l = 0; l < L; ++l) {
+        out.W[l] = (int64_t)W[l];
+        Wc += W[l];
+        if (l + 1 == L) {
+            // after the last group: accept iff S >= T
+            i128 acc = ceil_div(tn * Dn, td);
+            out.acc[l] = clampc(acc);
+            out.rej[l] = clampc(acc - 1);
+            break;
+        }
+        const i128 rem = wsum - Wc;        // (1 - U_l) * wsum > 0
+        // P_r < T  <=>  S > T U_l  <=>  S~ > tn Wc lam / td
+        const i128 mid = floor_div(tn * Wc * lam, td);
+        // accept: P(X < x) <= eps  <=>  x <= j_lo + 1  <=>  S >= T - (j_lo + 1)(1 - U_l) / k'
+        const i128 dd = td * kp;
+        const i128 a2 = ceil_div(tn * Dn * kp - td * (i128)(out.j_lo + 1) * rem * lam, dd);
+        // reject: P(X >= x) <= eps  <=>  x > j_hi - 1  <=>  S < T - (j_hi - 1)(1 - U_l) / k'
+        const i128 r2 = ceil_div(tn * Dn * kp - td * (i128)(out.j_hi - 1) * rem * lam, dd) - 1;
+        out.acc[l] = clampc(std::max(mid + 1, a2));
+        out.rej[l] = clampc(std::min(mid, r2));
+    }
+    return HOPH_OK;
+}
+
+void to_scan_tab(const hoph_decision_tables &t, ScanTab &s) {
+    std::memset(&s, 0, sizeof(s));
+    for (uint32_t l = 0; l < t.L; ++l) { s.W[l] = t.W[l]; s.acc[l] = t.acc[l]; s.rej[l] = t.rej[l]; }
+    for (uint32_t e = 0; e <= t.k_group; ++e) s.dmul[e] = t.dmul[e];
+    s.lambda = t.lcm;
+    s.L = t.L;
+    s.kp = t.k_group;
+    s.policy = t.empty_policy;
+    // After the first group the state is W_1 * m * unit(e); for e < k' the two
+    // cutoffs become thresholds on the matched count m.
+    for (uint32_t e = 0; e <= t.k_group; ++e) {
+        s.macc0[e] = 65;
+        s.mrej0[e] = -1;
+        if (e == t.k_group) continue;                 // 0/0 group: decided from the state itself
+        const int64_t unit = t.W[0] * (t.empty_policy == HOPH_EMPTY_LITERAL ? 1 : t.dmul[e]);
+        if (unit <= 0) continue;
+        const i128 a = ceil_div((i128)t.acc[0], unit), r = floor_div((i128)t.rej[0], unit);
+        s.macc0[e] = (int32_t)std::max<i128>(0, std::min<i128>(65, a));
+        s.mrej0[e] = (int32_t)std::max<i128>(-1, std::min<i128>(64, r));
+    }
+}
+
+}  // namespace hoph

@@ -1,0 +1,426 @@
+// The grouped comparison of Alg. 1 (GOPH) and Alg. 2 ((a:b) HOPH): matched
+// and empty bins are counted group by group (Eqs. 1-4), the per-group rate
+// (Eq. 6) is added to an exact weighted state, and the pair stops as soon as
+// the small-probability event of Def. 1 decides it.  The per-step tests are
+// precomputed on the host as integer cutoffs on the state, so the device only
+// counts, multiplies, adds and compares integers.
+//
+// Coarse pass: one wavefront per (tile of 64 indexed sets, chunk of queries).
+// The tile's first G groups stay in VGPRs (one set per lane); the wavefront
+// index is made wave-uniform with readfirstlane so that every query word is a
+// scalar load, and a bin comparison is one VALU compare plus one add-with-carry.
+// With G = 1 (HOPH) the decision after the first group is a pair of thresholds
+// on the matched count; with G > 1 (GOPH) the exact 64-bit state is carried.
+// Pairs still undecided after G groups are appended to a survivor list with
+// one atomic per wavefront (ballot + rank).
+//
+// Fine pass: one wavefront per survivor, one lane per bin; counts come from
+// ballots and popcounts, the decision is wave-uniform, and the wavefront
+// leaves at the first deciding group.
+#include "hoph_internal.h"
+
+namespace hoph {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+struct CoarseArgs {
+    uint64_t capacity, n_sets, surv_cap, keys_cap;
+    uint32_t k, kp, kpad, L, q0, q1, q_per_wave, policy, depth, pad;
+};
+
+__device__ __forceinline__ uint32_t wave_id_in_block() {
+    return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+__device__ __forceinline__ uint64_t lane_rank(uint64_t mask, uint32_t lane) {
+    return __popcll(mask & ((1ull << lane) - 1ull));
+}
+
+// Append the lanes with `flag` set: one atomic per wavefront.  Returns the slot
+// of this lane (valid only where flag is set).  Call with the whole wave active.
+__device__ __forceinline__ uint64_t wave_append(bool flag, unsigned long long *counter, uint32_t lane) {
+    const uint64_t bal = __ballot(flag);
+    uint64_t base = 0;
+    if (lane == 0) base = atomicAdd(counter, (unsigned long long)__popcll(bal));
+    base = __shfl(base, 0);
+    return base + lane_rank(bal, lane);
+}
+
+// lambda * rate of one group (Eq. 6 per group) from the counts.
+__device__ __forceinline__ int64_t group_rho(uint32_t eq, uint32_t ej, uint32_t ee, uint32_t kp, uint32_t policy,
+                                             const int64_t *dmul, int64_t lambda) {
+    const uint32_t m = eq - ej;                 // equal and non-empty
+    if (policy == HOPH_EMPTY_LITERAL) return (int64_t)m;
+    const uint32_t e = policy == HOPH_EMPTY_JOINT ? ej : ee;
+    if (e == kp) return ej == kp ? lambda : 0;  // 0/0: 1 iff the group is empty in both
+    return (int64_t)m * dmul[e];
+}
+
+// Empty-bin mask of every (query, group): bit i set when bin i of the group is EMPTY.
+__global__ __launch_bounds__(kThreads) void query_masks_kernel(const uint32_t *__restrict__ qsigs, uint32_t n_q,
+                                                              uint32_t k, uint32_t kp, uint32_t L,
+                                                              uint64_t *__restrict__ out) {
+    const uint64_t n = (uint64_t)n_q * L;
+    for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < n; t += (uint64_t)gridDim.x * kThreads) {
+        const uint64_t q = t / L, g = t % L;
+        const uint32_t *w = qsigs + q * k + g * kp;
+        uint64_t m = 0;
+        for (uint32_t i = 0; i < kp; ++i) m |= (uint64_t)(w[i] == HOPH_EMPTY) << i;
+        out[t] = m;
+    }
+}
+
+template <int KPAD, int G, bool EXACT>
+__global__ __launch_bounds__(kThreads) void scan_coarse_kernel(const uint32_t *__restrict__ slab,
+                                                              const uint32_t *__restrict__ qsigs,
+                                                              const uint64_t *__restrict__ qmasks,
+                                                              Survivor *__restrict__ surv,
+                                                              uint64_t *__restrict__ keys,
+                                                              unsigned long long *__restrict__ counters,
+                                                              const CoarseArgs a, const ScanTab tab) {
+    __shared__ int64_t s_dmul[HOPH_MAX_KGROUP + 1];
+    __shared__ int32_t s_macc[HOPH_MAX_KGROUP + 1], s_mrej[HOPH_MAX_KGROUP + 1];
+    for (uint32_t i = threadIdx.x; i <= tab.kp; i += kThreads) {
+        s_dmul[i] = tab.dmul[i];
+        s_macc[i] = tab.macc0[i];
+        s_mrej[i] = tab.mrej0[i];
+    }
+    __syncthreads();
+
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t wave = (uint64_t)blockIdx.x * kWaves + wave_id_in_block();
+    const uint64_t ntiles = (a.n_sets + 63) / 64;
+    const uint32_t nq = a.q1 - a.q0;
+    const uint32_t nchunks = (nq + a.q_per_wave - 1) / a.q_per_wave;
+    if (wave >= ntiles * nchunks) return;
+    const uint64_t tile = wave % ntiles;
+    const uint32_t chunk = (uint32_t)(wave / ntiles);
+    const uint64_t s = tile * 64 + lane;
+    const bool valid = s < a.n_sets;
+    const uint32_t kp = EXACT ? KPAD : a.kp;
+    const uint64_t kpmask = kp >= 64 ? ~0ull : ((1ull << kp) - 1ull);
+    const uint64_t gstride = a.capacity * KPAD;
+    const uint32_t policy = a.policy;
+
+    uint32_t w[G][KPAD];
+    uint64_t emask[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(slab + g * gstride + tile * (KPAD * 64)) + lane;
+#pragma unroll
+        for (int qd = 0; qd < KPAD / 4; ++qd) {
+            const uint4 v = src[qd * 64];
+            w[g][4 * qd + 0] = v.x;
+            w[g][4 * qd + 1] = v.y;
+            w[g][4 * qd + 2] = v.z;
+            w[g][4 * qd + 3] = v.w;
+        }
+        uint64_t em = 0;
+#pragma unroll
+        for (int i = 0; i < KPAD; ++i) em |= (uint64_t)(w[g][i] == HOPH_EMPTY) << i;
+        emask[g] = em & kpmask;
+    }
+
+    const uint32_t qa = a.q0 + chunk * a.q_per_wave;
+    const uint32_t qb = min(a.q1, qa + a.q_per_wave);
+    for (uint32_t q = qa; q < qb; ++q) {
+        const uint32_t *qw = qsigs + (uint64_t)q * a.k;
+        const uint64_t *qmk = qmasks + (uint64_t)q * a.L;
+        int64_t S = 0;
+        bool undecided = valid, accept = false;
+        if constexpr (G == 1) {
+            uint32_t eq = 0;
+            const uint64_t qm = qmk[0];
+#pragma unroll
+            for (int i = 0; i < KPAD; ++i) {
+                if (EXACT || i < (int)kp) eq += (w[0][i] == qw[i]) ? 1u : 0u;
+            }
+            uint32_t ej = 0, e = 0;
+            if (qm != 0) ej = __popcll(emask[0] & qm);
+            if (policy == HOPH_EMPTY_JOINT) e = ej;
+            else if (policy == HOPH_EMPTY_EITHER) e = __popcll(emask[0] | qm);
+            const uint32_t m = eq - ej;
+            bool acc, rej;
+            if (e < kp) {
+                acc = (int32_t)m >= s_macc[e];
+                rej = (int32_t)m <= s_mrej[e];
+            } else {
+                const int64_t S0 = tab.W[0] * (ej == kp ? tab.lambda : 0);
+                acc = S0 >= tab.acc[0];
+                rej = S0 <= tab.rej[0];
+            }
+            accept = valid && acc;
+            undecided = valid && !acc && !rej;
+            if (__any(undecided)) {
+                // the state after the first group, for the pairs that continue
+                const int64_t rho = policy == HOPH_EMPTY_LITERAL ? (int64_t)m
+                                    : (e < kp ? (int64_t)m * s_dmul[e] : (ej == kp ? tab.lambda : 0));
+                S = tab.W[0] * rho;
+            }
+        } else {
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                if (!__any(undecided)) break;
+                const uint32_t *qg = qw + g * kp;
+                uint32_t eq = 0;
+                const uint64_t qm = qmk[g];
+#pragma unroll
+                for (int i = 0; i < KPAD; ++i) {
+                    if (EXACT || i < (int)kp) eq += (w[g][i] == qg[i]) ? 1u : 0u;
+                }
+                const uint32_t ej = qm ? (uint32_t)__popcll(emask[g] & qm) : 0u;
+                const uint32_t ee = __popcll(emask[g] | qm);
+                S += tab.W[g] * group_rho(eq, ej, ee, kp, policy, s_dmul, tab.lambda);
+                if (undecided) {
+                    if (S >= tab.acc[g]) {
+                        accept = true;
+                        undecided = false;
+                    } else if (S <= tab.rej[g]) {
+                        undecided = false;
+                    }
+                }
+            }
+        }
+        if (__any(accept)) {
+            const uint64_t slot = wave_append(accept, counters + 1, lane);
+            if (accept && slot < a.keys_cap) keys[slot] = ((uint64_t)q << 32) | s;
+        }
+        if (__any(undecided)) {
+            const uint64_t slot = wave_append(undecided, counters + 0, lane);
+            if (undecided && slot < a.surv_cap) surv[slot] = Survivor{q, (uint32_t)s, S};
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void scan_fine_kernel(const uint32_t *__restrict__ slab,
+                                                            const uint32_t *__restrict__ qsigs,
+                                                            const Survivor *__restrict__ surv,
+                                                            uint64_t *__restrict__ keys,
+                                                            unsigned long long *__restrict__ counters,
+                                                            const CoarseArgs a, const ScanTab tab) {
+    __shared__ int64_t s_dmul[HOPH_MAX_KGROUP + 1];
+    for (uint32_t i = threadIdx.x; i <= tab.kp; i += kThreads) s_dmul[i] = tab.dmul[i];
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t nw = (uint64_t)gridDim.x * kWaves;
+    const uint64_t n = min((uint64_t)counters[0], a.surv_cap);
+    const uint32_t kp = a.kp, kpad = a.kpad;
+    const bool in = lane < kp;
+    for (uint64_t idx = (uint64_t)blockIdx.x * kWaves + wave_id_in_block(); idx < n; idx += nw) {
+        const Survivor sv = surv[idx];
+        int64_t S = sv.S;
+        bool accept = false;
+        const uint64_t s = sv.s;
+        const uint32_t *qw = qsigs + (uint64_t)sv.q * a.k;
+        const uint32_t *sb = slab + (s / 64) * kpad * 64 + (lane / 4) * 256 + (s % 64) * 4 + (lane & 3);
+        for (uint32_t g = a.depth; g < a.L; ++g) {
+            uint32_t sw = 0, qv = 0;
+            if (in) {
+                sw = sb[(uint64_t)g * a.capacity * kpad];
+                qv = qw[g * kp + lane];
+            }
+            const uint64_t eqb = __ballot(in && sw == qv);
+            const uint64_t qe = __ballot(in && qv == HOPH_EMPTY);
+            const uint64_t se = __ballot(in && sw == HOPH_EMPTY);
+            const uint32_t ej = __popcll(qe & se), ee = __popcll(qe | se);
+            const uint32_t eq = __popcll(eqb);
+            S += tab.W[g] * group_rho(eq, ej, ee, kp, a.policy, s_dmul, tab.lambda);
+            if (S >= tab.acc[g]) { accept = true; break; }
+            if (S <= tab.rej[g]) break;
+        }
+        if (accept && lane == 0) {
+            const uint64_t slot = atomicAdd(counters + 1, 1ull);
+            if (slot < a.keys_cap) keys[slot] = ((uint64_t)sv.q << 32) | s;
+        }
+    }
+}
+
+// Plain OPH comparator (Eq. 6 over all k bins, no early stop).
+template <int KPAD, bool EXACT>
+__global__ __launch_bounds__(kThreads) void oph_full_kernel(const uint32_t *__restrict__ slab,
+                                                           const uint32_t *__restrict__ qsigs,
+                                                           uint64_t *__restrict__ keys,
+                                                           unsigned long long *__restrict__ counters,
+                                                           const CoarseArgs a, uint32_t tn, uint32_t td) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t wave = (uint64_t)blockIdx.x * kWaves + wave_id_in_block();
+    const uint64_t ntiles = (a.n_sets + 63) / 64;
+    const uint32_t nq = a.q1 - a.q0;
+    const uint32_t nchunks = (nq + a.q_per_wave - 1) / a.q_per_wave;
+    if (wave >= ntiles * nchunks) return;
+    const uint64_t tile = wave % ntiles;
+    const uint32_t chunk = (uint32_t)(wave / ntiles);
+    const uint64_t s = tile * 64 + lane;
+    const bool valid = s < a.n_sets;
+    const uint32_t kp = EXACT ? KPAD : a.kp, k = a.k;
+    const uint64_t gstride = a.capacity * KPAD;
+    const uint32_t qa = a.q0 + chunk * a.q_per_wave;
+    const uint32_t qb = min(a.q1, qa + a.q_per_wave);
+    for (uint32_t q = qa; q < qb; ++q) {
+        const uint32_t *qw = qsigs + (uint64_t)q * k;
+        uint32_t eq = 0, ej = 0, ee = 0;
+        for (uint32_t g = 0; g < a.L; ++g) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(slab + g * gstride + tile * (KPAD * 64)) + lane;
+            const uint32_t *qg = qw + g * kp;
+#pragma unroll
+            for (int qd = 0; qd < KPAD / 4; ++qd) {
+                const uint4 v = src[qd * 64];
+                const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int i = 4 * qd + t;
+                    if (EXACT || i < (int)kp) {
+                        const uint32_t qv = qg[i];
+                        const bool se = vv[t] == HOPH_EMPTY;
+                        eq += (vv[t] == qv) ? 1u : 0u;
+                        if (qv == HOPH_EMPTY) {
+                            ej += se ? 1u : 0u;
+                            ee += 1u;
+                        } else {
+                            ee += se ? 1u : 0u;
+                        }
+                    }
+                }
+            }
+        }
+        const uint32_t m = eq - ej;
+        bool accept;
+        if (a.policy == HOPH_EMPTY_LITERAL) {
+            accept = (uint64_t)m * td >= (uint64_t)tn * k;
+        } else {
+            const uint32_t e = a.policy == HOPH_EMPTY_JOINT ? ej : ee;
+            if (e == k) accept = ej == k;
+            else accept = (uint64_t)m * td >= (uint64_t)tn * (k - e);
+        }
+        accept = accept && valid;
+        if (__any(accept)) {
+            const uint64_t slot = wave_append(accept, counters + 1, lane);
+            if (accept && slot < a.keys_cap) keys[slot] = ((uint64_t)q << 32) | s;
+        }
+    }
+}
+
+uint32_t waves_to_blocks(uint64_t waves) { return (uint32_t)((waves + kWaves - 1) / kWaves); }
+
+CoarseArgs coarse_args(const ScanLaunch &l, uint32_t policy) {
+    CoarseArgs a{};
+    a.capacity = l.capacity;
+    a.n_sets = l.n_sets;
+    a.surv_cap = l.surv_cap;
+    a.keys_cap = l.keys_cap;
+    a.k = l.k;
+    a.kp = l.kp;
+    a.kpad = l.kpad;
+    a.L = l.L;
+    a.q0 = l.q0;
+    a.q1 = l.q1;
+    a.q_per_wave = l.q_per_wave;
+    a.policy = policy;
+    a.depth = l.depth;
+    return a;
+}
+
+template <int KPAD, bool EXACT>
+void coarse_launch(const ScanLaunch &l, const CoarseArgs &a, const ScanTab &tab, hipStream_t st, uint32_t blocks) {
+    auto *cnt = reinterpret_cast<unsigned long long *>(l.counters);
+#define HOPH_COARSE(G)                                                                                        \
+    hipLaunchKernelGGL((scan_coarse_kernel<KPAD, G, EXACT>), dim3(blocks), dim3(kThreads), 0, st, l.slab,    \
+                       l.qsigs, l.qmasks, l.surv, l.keys, cnt, a, tab)
+    switch (l.depth) {
+    case 1: HOPH_COARSE(1); break;
+    case 2: if constexpr (KPAD * 2 <= 128) HOPH_COARSE(2); break;
+    case 3: if constexpr (KPAD * 3 <= 128) HOPH_COARSE(3); break;
+    default: if constexpr (KPAD * 4 <= 128) HOPH_COARSE(4); break;
+    }
+#undef HOPH_COARSE
+}
+
+template <int KPAD>
+void coarse_kp(const ScanLaunch &l, const CoarseArgs &a, const ScanTab &tab, hipStream_t st, uint32_t blocks) {
+    if (l.kp == (uint32_t)KPAD) coarse_launch<KPAD, true>(l, a, tab, st, blocks);
+    else coarse_launch<KPAD, false>(l, a, tab, st, blocks);
+}
+
+template <int KPAD>
+void oph_kp(const ScanLaunch &l, const CoarseArgs &a, hoph_ratio T, hipStream_t st, uint32_t blocks) {
+    auto *cnt = reinterpret_cast<unsigned long long *>(l.counters);
+    if (l.kp == (uint32_t)KPAD)
+        hipLaunchKernelGGL((oph_full_kernel<KPAD, true>), dim3(blocks), dim3(kThreads), 0, st, l.slab, l.qsigs, l.keys,
+                           cnt, a, T.num, T.den);
+    else
+        hipLaunchKernelGGL((oph_full_kernel<KPAD, false>), dim3(blocks), dim3(kThreads), 0, st, l.slab, l.qsigs, l.keys,
+                           cnt, a, T.num, T.den);
+}
+
+#define HOPH_KPAD_SWITCH(F, ...)                                       \
+    switch (l.kpad) {                                                  \
+    case 4: F<4>(__VA_ARGS__); break;                                  \
+    case 8: F<8>(__VA_ARGS__); break;                                  \
+    case 12: F<12>(__VA_ARGS__); break;                                \
+    case 16: F<16>(__VA_ARGS__); break;                                \
+    case 20: F<20>(__VA_ARGS__); break;                                \
+    case 24: F<24>(__VA_ARGS__); break;                                \
+    case 28: F<28>(__VA_ARGS__); break;                                \
+    case 32: F<32>(__VA_ARGS__); break;                                \
+    case 36: F<36>(__VA_ARGS__); break;                                \
+    case 40: F<40>(__VA_ARGS__); break;                                \
+    case 44: F<44>(__VA_ARGS__); break;                                \
+    case 48: F<48>(__VA_ARGS__); break;                                \
+    case 52: F<52>(__VA_ARGS__); break;                                \
+    case 56: F<56>(__VA_ARGS__); break;                                \
+    case 60: F<60>(__VA_ARGS__); break;                                \
+    default: F<64>(__VA_ARGS__); break;                                \
+    }
+
+}  // namespace
+
+uint32_t max_depth_for_kpad(uint32_t kpad) {
+    uint32_t d = 128 / kpad;
+    return d < kMaxDepth ? d : kMaxDepth;
+}
+
+hipError_t launch_query_masks(const uint32_t *qsigs, uint32_t n_q, uint32_t k, uint32_t kp, uint32_t L,
+                              uint64_t *out, hipStream_t st) {
+    const uint64_t n = (uint64_t)n_q * L;
+    if (n == 0) return hipSuccess;
+    uint64_t blocks = (n + kThreads - 1) / kThreads;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(query_masks_kernel, dim3((uint32_t)blocks), dim3(kThreads), 0, st, qsigs, n_q, k, kp, L, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_coarse(const ScanLaunch &l, const ScanTab &tab, hipStream_t st) {
+    const uint64_t ntiles = (l.n_sets + 63) / 64;
+    const uint32_t nq = l.q1 - l.q0;
+    if (ntiles == 0 || nq == 0) return hipSuccess;
+    const uint64_t nchunks = (nq + l.q_per_wave - 1) / l.q_per_wave;
+    const uint32_t blocks = waves_to_blocks(ntiles * nchunks);
+    const CoarseArgs a = coarse_args(l, tab.policy);
+    HOPH_KPAD_SWITCH(coarse_kp, l, a, tab, st, blocks)
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_fine(const ScanLaunch &l, const ScanTab &tab, hipStream_t st) {
+    if (l.depth >= l.L) return hipSuccess;
+    const uint32_t blocks = (uint32_t)device_cu_count() * 8;
+    const CoarseArgs a = coarse_args(l, tab.policy);
+    hipLaunchKernelGGL(scan_fine_kernel, dim3(blocks), dim3(kThreads), 0, st, l.slab, l.qsigs, l.surv, l.keys,
+                       reinterpret_cast<unsigned long long *>(l.counters), a, tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_oph_full(const ScanLaunch &l, hoph_ratio T, uint32_t policy, hipStream_t st) {
+    const uint64_t ntiles = (l.n_sets + 63) / 64;
+    const uint32_t nq = l.q1 - l.q0;
+    if (ntiles == 0 || nq == 0) return hipSuccess;
+    const uint64_t nchunks = (nq + l.q_per_wave - 1) / l.q_per_wave;
+    const uint32_t blocks = waves_to_blocks(ntiles * nchunks);
+    const CoarseArgs a = coarse_args(l, policy);
+    HOPH_KPAD_SWITCH(oph_kp, l, a, T, st, blocks)
+    return hipGetLastError();
+}
+
+}  // namespace hoph

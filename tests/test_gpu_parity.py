@@ -1,0 +1,284 @@
+"""GPU parity: the HIP path against the oracle, element by element, on seeded
+inputs of the paper's workload shapes (scaled so the oracle finishes in
+seconds, spanning many 64-set tiles with a ragged tail), plus edge cases.
+Everything is exact integer work, so the bar is bit-exact equality."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import paper_1805_11254_amd as H
+from oracle import scale, tiny
+import workloads as W
+from tests.hoph_testutil import (csr_lists, dev_csr, gpu_query, gpu_sketch, oracle_query, oracle_sketch, params_of,
+                                 to_u32)
+
+pytestmark = pytest.mark.gpu
+
+
+def _print_case(name):
+    print(f"[case] {name}", flush=True)
+
+
+SMALL = {
+    "goph_tiny": lambda: W.tiny_goph(),
+    "hoph11_bovw": lambda: W.hoph_bovw(n=20_003, n_q=48, seed=11, planted_frac=0.02),
+    "hoph12_shingles": lambda: W.hoph_shingles(n=12_345, n_q=40, seed=12, ra=1, rb=2, T=(7, 10)),
+    "hoph21_shingles": lambda: W.hoph_shingles(n=9_999, n_q=33, seed=13, ra=2, rb=1, T=(1, 2)),
+    "goph_bovw_512": lambda: _goph_bovw(),
+}
+
+
+def _goph_bovw():
+    w = W.hoph_bovw(n=8_191, n_q=24, seed=14, planted_frac=0.03)
+    w.layout = W.LAYOUT_OPH
+    w.name = "goph_bovw_512"
+    return w
+
+
+_cache = {}
+
+
+def workload(name):
+    if name not in _cache:
+        _cache[name] = SMALL[name]()
+    return _cache[name]
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_sketch_bit_exact(name):
+    _print_case(f"sketch {name}")
+    w = workload(name)
+    g = to_u32(gpu_sketch(w, w.collection))
+    H.sync()
+    o = oracle_sketch(w, w.collection)
+    assert g.shape == o.shape
+    bad = np.argwhere(g != o)
+    assert len(bad) == 0, f"{len(bad)} words differ, first at {bad[:5].tolist()}"
+    gq = to_u32(gpu_sketch(w, w.queries))
+    assert (gq == oracle_sketch(w, w.queries)).all()
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_pair_counts_match_oracle(name):
+    import torch
+    _print_case(f"pair_counts {name}")
+    w = workload(name)
+    p = params_of(w)
+    sig = gpu_sketch(w, w.collection, p)
+    qsig = gpu_sketch(w, w.queries, p)
+    idx = H.Index(p, sig)
+    rng = np.random.default_rng(3)
+    pairs = [(q, s) for (q, s, _) in w.planted[:200]]
+    pairs += [(int(rng.integers(w.queries.n)), int(rng.integers(w.collection.n))) for _ in range(300)]
+    pairs += [(0, w.collection.n - 1), (w.queries.n - 1, 0)]
+    P = torch.tensor(pairs, dtype=torch.int32, device="cuda")
+    sh, qh = to_u32(sig), to_u32(qsig)
+    for policy in (H.EMPTY_JOINT, H.EMPTY_EITHER, H.EMPTY_LITERAL):
+        m, e = H.pair_counts(idx, qsig, P, policy)
+        m, e = m.cpu().numpy(), e.cpu().numpy()
+        for i, (q, s) in enumerate(pairs):
+            om, oe = scale.pair_counts(qh[q], sh[s], w.kp, policy)
+            assert m[i].tolist() == om.tolist() and e[i].tolist() == oe.tolist(), (policy, q, s)
+    idx.free()
+
+
+QUERY_GRID = [((4, 5), (1, 10_000)), ((1, 2), (1, 100)), ((9, 10), (0, 1)), ((7, 10), (1, 1000))]
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_query_candidates_bit_exact(name):
+    _print_case(f"query {name}")
+    w = workload(name)
+    p = params_of(w)
+    sig = gpu_sketch(w, w.collection, p)
+    qsig = gpu_sketch(w, w.queries, p)
+    idx = H.Index(p, sig)
+    sh, qh = to_u32(sig), to_u32(qsig)
+    kind = "goph" if w.goph else "hoph"
+    for T, eps in QUERY_GRID:
+        for policy in (H.EMPTY_JOINT, H.EMPTY_EITHER, H.EMPTY_LITERAL):
+            go, gi = gpu_query(kind, idx, qsig, T, eps, policy)
+            oo, oi = oracle_query(w, sh, qh, T, eps, policy)
+            assert go.tolist() == oo.tolist(), (T, eps, policy)
+            assert gi.tolist() == oi.tolist(), (T, eps, policy)
+    idx.free()
+
+
+@pytest.mark.parametrize("name", ["goph_tiny", "hoph11_bovw", "goph_bovw_512"])
+def test_results_do_not_depend_on_coarse_depth(name):
+    _print_case(f"depth {name}")
+    w = workload(name)
+    p = params_of(w)
+    sig = gpu_sketch(w, w.collection, p)
+    qsig = gpu_sketch(w, w.queries, p)
+    idx = H.Index(p, sig)
+    kind = "goph" if w.goph else "hoph"
+    ref = None
+    for depth in (0, 1, 2, 3, 4):
+        out = gpu_query(kind, idx, qsig, (4, 5), (1, 10_000), H.EMPTY_JOINT, coarse_depth=depth)
+        cur = (out[0].tolist(), out[1].tolist())
+        if ref is None:
+            ref = cur
+        assert cur == ref, depth
+    idx.free()
+
+
+def test_oph_full_comparator_bit_exact():
+    _print_case("oph_full")
+    for name in ("goph_tiny", "hoph11_bovw"):
+        w = workload(name)
+        p = params_of(w)
+        sig = gpu_sketch(w, w.collection, p)
+        qsig = gpu_sketch(w, w.queries, p)
+        idx = H.Index(p, sig)
+        sh, qh = to_u32(sig), to_u32(qsig)
+        for T in ((1, 2), (4, 5)):
+            for policy in (H.EMPTY_JOINT, H.EMPTY_EITHER, H.EMPTY_LITERAL):
+                go, gi = H.query_oph_full(idx, qsig, T=T, policy=policy)
+                oo, oi = scale.query_oph_full(sh, qh, T=Fraction(*T), policy=policy)
+                assert go.cpu().numpy().tolist() == oo.tolist()
+                assert to_u32(gi).tolist() == oi.tolist()
+        idx.free()
+
+
+def test_minwise_bit_exact():
+    import torch
+    _print_case("minwise")
+    for kind, p in ((W.HASH_MODP31, W.P31), (W.HASH_MODP32P15, W.P32P15)):
+        coll = W.zipf_sets(3_001, 1 << 20, 80, 0.5, 5, 400, seed=21)
+        qs = W.zipf_sets(7, 1 << 20, 80, 0.5, 5, 400, seed=22)
+        repl = {5: qs.set(0), 77: np.concatenate([qs.set(1)[:-3], np.array([5, 6, 7], dtype=np.uint32)])}
+        coll = W.replace_sets(coll, repl)
+        ha, hb = W.hash_coeffs(p, 200, 23)
+        mp = H.MinwiseParams(200, kind, 1 << 20, torch.from_numpy(ha.view(np.int64)).cuda(),
+                             torch.from_numpy(hb.view(np.int64)).cuda())
+        ids, offs = dev_csr(coll)
+        qids, qoffs = dev_csr(qs)
+        g = H.minwise_sketch(mp, ids, offs)
+        gq = H.minwise_sketch(mp, qids, qoffs)
+        o = scale.minwise_sketch(coll.ids, coll.offsets, hash_kind=kind, universe=1 << 20, ha=ha, hb=hb)
+        oq = scale.minwise_sketch(qs.ids, qs.offsets, hash_kind=kind, universe=1 << 20, ha=ha, hb=hb)
+        assert (g.cpu().numpy().view(np.uint64) == o).all()
+        assert (gq.cpu().numpy().view(np.uint64) == oq).all()
+        for T in ((1, 2), (3, 10)):
+            go, gi = H.minwise_query(mp, g, gq, T=T)
+            oo, oi = scale.minwise_query(o, oq, T=Fraction(*T))
+            assert go.cpu().numpy().tolist() == oo.tolist()
+            assert to_u32(gi).tolist() == oi.tolist()
+
+
+# ---------------------------------------------------------------------------
+# Edge cases
+# ---------------------------------------------------------------------------
+def test_edge_tiny_and_degenerate_inputs():
+    import torch
+    _print_case("edges")
+    D = 1 << 12
+    perm = W.perm_table(D, 9)
+    sets = [[5], [5], [0], [D - 1], list(range(0, D, 3)), list(range(D)), [7, 7, 7, 7], [1, 2, 3], [3, 2, 1]]
+    coll = W.csr_from_lists(sets)
+    for layout, k, kp in ((W.LAYOUT_OPH, 64, 16), (W.LAYOUT_HIER, 24, 8), (W.LAYOUT_OPH, 10, 5), (W.LAYOUT_HIER, 14, 2)):
+        w = W.Workload("edge", coll, coll, D, W.HASH_TABLE, layout, k, kp, perm=perm)
+        g = to_u32(gpu_sketch(w, coll))
+        assert (g == oracle_sketch(w, coll)).all()
+        p = params_of(w)
+        sig = gpu_sketch(w, coll, p)
+        idx = H.Index(p, sig, capacity=100)
+        for T, eps in ((1, 1), (1, 10_000)), ((1, 2), (1, 10)), ((1, 10), (0, 1)):
+            for policy in (0, 1, 2):
+                go, gi = gpu_query("goph" if w.goph else "hoph", idx, sig, T, eps, policy)
+                oo, oi = oracle_query(w, g, g, T, eps, policy)
+                assert go.tolist() == oo.tolist() and gi.tolist() == oi.tolist()
+        # no queries
+        go, gi = gpu_query("goph" if w.goph else "hoph", idx, sig[:0], (4, 5), (1, 10_000), 0)
+        assert go.tolist() == [0] and gi.size == 0
+        idx.free()
+
+
+def test_empty_index_and_append():
+    import torch
+    _print_case("append")
+    w = workload("hoph11_bovw")
+    p = params_of(w)
+    sig = gpu_sketch(w, w.collection, p)
+    qsig = gpu_sketch(w, w.queries, p)
+    idx = H.Index(p, sig[:0], capacity=w.collection.n)
+    go, gi = gpu_query("hoph", idx, qsig, (4, 5), (1, 10_000), 0)
+    assert go.tolist() == [0] * (w.queries.n + 1) and gi.size == 0
+    # append in ragged pieces
+    cuts = [0, 1, 63, 64, 65, 1000, 7777, w.collection.n]
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        idx.append(sig[a:b].contiguous())
+    assert len(idx) == w.collection.n
+    with pytest.raises(H.HophError) as ei:
+        idx.append(sig[:1].contiguous())
+    assert ei.value.status == H.HOPH_E_CAPACITY
+    go, gi = gpu_query("hoph", idx, qsig, (4, 5), (1, 10_000), 0)
+    oo, oi = oracle_query(w, to_u32(sig), to_u32(qsig), (4, 5), (1, 10_000), 0)
+    assert go.tolist() == oo.tolist() and gi.tolist() == oi.tolist()
+    idx.free()
+
+
+def test_results_capacity_reports_needed():
+    _print_case("capacity")
+    w = workload("goph_tiny")
+    p = params_of(w)
+    sig = gpu_sketch(w, w.collection, p)
+    qsig = gpu_sketch(w, w.queries, p)
+    idx = H.Index(p, sig)
+    _, full = H.query_goph(idx, qsig, T=(1, 2), eps=(1, 10_000))
+    need = full.numel()
+    assert need > 2
+    with pytest.raises(H.HophError) as ei:
+        H.query_goph(idx, qsig, T=(1, 2), eps=(1, 10_000), capacity=need - 1)
+    assert ei.value.status == H.HOPH_E_CAPACITY and ei.value.needed == need
+    _, exact = H.query_goph(idx, qsig, T=(1, 2), eps=(1, 10_000), capacity=need)
+    assert exact.numel() == need
+    idx.free()
+
+
+def test_survivor_overflow_path_matches_oracle():
+    """Near-identical collection: every pair survives the coarse pass, more
+    survivors than the survivor buffer holds, so the batch is re-run in
+    sub-batches; the result must still be exact."""
+    _print_case("survivor overflow")
+    rng = np.random.default_rng(5)
+    base = rng.choice(1 << 20, size=300, replace=False)
+    sets = []
+    for i in range(40_000):
+        s = base.copy()
+        s[rng.integers(0, 300, size=2)] = rng.integers(0, 1 << 20, size=2)
+        sets.append(s)
+    coll = W.csr_from_lists(sets)
+    qs = W.csr_from_lists(sets[:30])
+    w = W.Workload("same", coll, qs, 1 << 20, W.HASH_MODP31, W.LAYOUT_HIER, 256, 32, ha=99991, hb=5)
+    p = params_of(w)
+    sig = gpu_sketch(w, coll, p)
+    qsig = gpu_sketch(w, qs, p)
+    idx = H.Index(p, sig)
+    go, gi = gpu_query("hoph", idx, qsig, (99, 100), (1, 10 ** 6), 0, coarse_depth=1)
+    oo, oi = oracle_query(w, to_u32(sig), to_u32(qsig), (99, 100), (1, 10 ** 6), 0)
+    assert go.tolist() == oo.tolist() and gi.tolist() == oi.tolist()
+    idx.free()
+
+
+def test_device_error_flags():
+    import torch
+    _print_case("error flags")
+    p = H.SketchParams(H.LAYOUT_OPH, 64, 16, H.HASH_MODP31, 1000, hash_a=7, hash_b=1)
+    ids = torch.tensor([1, 2, 5000, 3], dtype=torch.int32, device="cuda")
+    offs = torch.tensor([0, 2, 4], dtype=torch.int64, device="cuda")
+    H.sync()
+    H.sketch_oph(p, ids, offs)
+    with pytest.raises(H.HophError) as ei:
+        H.sync()
+    assert ei.value.status == H.HOPH_E_RANGE
+    H.sync()      # cleared
+    offs2 = torch.tensor([0, 2, 2, 4], dtype=torch.int64, device="cuda")
+    ids2 = torch.tensor([1, 2, 3, 4], dtype=torch.int32, device="cuda")
+    out = H.sketch_oph(p, ids2, offs2)
+    with pytest.raises(H.HophError) as ei:
+        H.sync()
+    assert ei.value.status == H.HOPH_E_INVAL
+    assert (to_u32(out)[1] == tiny.EMPTY).all()

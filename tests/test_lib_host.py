@@ -1,0 +1,246 @@
+"""Host-side checks of libhoph that need no GPU: every symbol of include/hoph.h
+is exported, the layout and the exact decision tables agree with the oracle,
+the library's inline hash-and-bin arithmetic (run on the host through a test
+hook) agrees with the oracle's plain 128-bit arithmetic, and invalid
+parameters are refused before any launch."""
+import os
+import random
+import re
+from fractions import Fraction as F
+
+import numpy as np
+import pytest
+
+import paper_1805_11254_amd as H
+from oracle import scale, tiny
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def built():
+    if not os.path.exists(H.LIB_PATH):
+        from paper_1805_11254_amd import build
+        build.build(verbose=False)
+    H.lib()
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "hoph.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w \*]*?\b(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("defined",)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 18, names
+    lib = H.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(H.SIGNATURES), set(names) ^ set(H.SIGNATURES)
+
+
+def test_status_strings():
+    lib = H.lib()
+    for code, name in [(0, "HOPH_OK"), (-1, "HOPH_E_INVAL"), (-3, "HOPH_E_CAPACITY"), (-6, "HOPH_E_DEVICE")]:
+        assert lib.hoph_status_str(code).decode() == name
+
+
+PARAMS = [
+    H.SketchParams(H.LAYOUT_OPH, 128, 16, H.HASH_TABLE, 1 << 16),
+    H.SketchParams(H.LAYOUT_OPH, 96, 32, H.HASH_MODP32P15, 1 << 32, hash_a=123456789, hash_b=42),
+    H.SketchParams(H.LAYOUT_HIER, 512, 32, H.HASH_MODP31, 1 << 20, 1, 1, 977, 3),
+    H.SketchParams(H.LAYOUT_HIER, 256, 32, H.HASH_MODP32P15, 1 << 32, 1, 2, 4294967000, 17),
+    H.SketchParams(H.LAYOUT_HIER, 256, 32, H.HASH_MODP32P15, 1 << 32, 2, 1, 5, 4294967310),
+    H.SketchParams(H.LAYOUT_HIER, 6, 2, H.HASH_TABLE, 16),
+    H.SketchParams(H.LAYOUT_HIER, 40, 4, H.HASH_TABLE, 1000, 3, 5),
+    H.SketchParams(H.LAYOUT_OPH, 7, 7, H.HASH_TABLE, 7),
+]
+
+
+def _tiny_layout(p):
+    return tiny.Layout(p.layout, tiny.hash_range(p.hash, p.universe), p.k, p.k_group, p.ratio_a, p.ratio_b)
+
+
+@pytest.mark.parametrize("p", PARAMS, ids=lambda p: f"L{p.layout}k{p.k}kp{p.k_group}h{p.hash}r{p.ratio_a}{p.ratio_b}")
+def test_layout_starts_match_oracle(p):
+    got = H.layout_starts(p)
+    lay = _tiny_layout(p)
+    assert got.tolist() == lay.starts + [lay.R]
+    assert got.tolist() == scale.layout_starts(p.hash, p.universe, p.layout, p.k, p.k_group, p.ratio_a, p.ratio_b).tolist()
+
+
+@pytest.mark.parametrize("p", PARAMS, ids=lambda p: f"L{p.layout}k{p.k}kp{p.k_group}h{p.hash}r{p.ratio_a}{p.ratio_b}")
+def test_selftest_bins_match_oracle(p):
+    rng = np.random.default_rng(p.k + p.hash)
+    n = 3000
+    ids = rng.integers(0, p.universe, size=n, dtype=np.uint64)
+    edge = np.array([0, p.universe - 1, p.universe // 2, 1], dtype=np.uint64)
+    ids = np.concatenate([edge, ids]).astype(np.uint32)
+    perm = rng.permutation(p.universe).astype(np.uint32) if p.hash == H.HASH_TABLE else None
+    b, o = H.selftest_bins(p, ids, perm)
+    lay = _tiny_layout(p)
+    for x, bb, oo in zip(ids.tolist(), b.tolist(), o.tolist()):
+        v = tiny.permute(x, p.hash, perm, p.hash_a, p.hash_b)
+        eb = lay.bin_of(v)
+        assert (bb, oo) == (eb, v - lay.starts[eb]), (x, v)
+
+
+def test_selftest_bins_region_boundaries():
+    """Values at and next to every bin start of a hierarchical layout."""
+    for (a, b) in [(1, 1), (1, 2), (2, 1)]:
+        p = H.SketchParams(H.LAYOUT_HIER, 8 * 32, 32, H.HASH_TABLE, 1 << 20, a, b)
+        lay = _tiny_layout(p)
+        perm = np.arange(p.universe, dtype=np.uint32)           # identity: ids are the permuted values
+        vals = sorted(set(v + d for v in lay.starts for d in (-1, 0, 1) if 0 <= v + d < lay.R))
+        got_b, got_o = H.selftest_bins(p, np.array(vals, dtype=np.uint32), perm)
+        for v, bb, oo in zip(vals, got_b.tolist(), got_o.tolist()):
+            eb = lay.bin_of(v)
+            assert (bb, oo) == (eb, v - lay.starts[eb])
+
+
+def test_modp32_hash_edges():
+    """(a x + b) mod (2^32 + 15) at the extremes of a, b and x."""
+    P = tiny.P32P15
+    for a, bb in [(P - 1, P - 1), (1, 0), (P - 1, 0), (2 ** 32 - 1, P - 1), (12345, 2 ** 32)]:
+        p = H.SketchParams(H.LAYOUT_OPH, 64, 64, H.HASH_MODP32P15, 1 << 32, hash_a=a, hash_b=bb)
+        ids = np.array([0, 1, 2 ** 32 - 1, 2 ** 32 - 2, 2 ** 31, 15, 2 ** 32 - 15], dtype=np.uint32)
+        b, o = H.selftest_bins(p, ids)
+        lay = _tiny_layout(p)
+        for x, gb, go in zip(ids.tolist(), b.tolist(), o.tolist()):
+            v = (a * x + bb) % P
+            assert (gb, go) == (lay.bin_of(v), v - lay.starts[lay.bin_of(v)])
+
+
+def test_tail_integers_match_oracle():
+    for n in (1, 2, 7, 16, 32, 64, 100, 128):
+        for T in (F(1, 10), F(1, 2), F(3, 5), F(7, 10), F(4, 5), F(9, 10), F(1)):
+            for eps in (F(0), F(1, 10 ** 5), F(1, 10 ** 4), F(1, 100), F(1, 2)):
+                assert H.tail_integers(n, (T.numerator, T.denominator), (eps.numerator, eps.denominator)) == \
+                    tiny.tail_integers(n, T, eps), (n, T, eps)
+
+
+def _rand_sig_pair(rng, k, rho, p_empty):
+    q, s = [], []
+    for _ in range(k):
+        a = tiny.EMPTY if rng.random() < p_empty else rng.randrange(50)
+        if rng.random() < rho:
+            b = a
+        else:
+            b = tiny.EMPTY if rng.random() < p_empty else rng.randrange(50)
+        q.append(a)
+        s.append(b)
+    return q, s
+
+
+def _apply_tables(t, q, s, kp, policy):
+    """What the device does with the tables, written out."""
+    S = 0
+    for l in range(t["L"]):
+        m, e, aj = tiny.group_counts(q[l * kp:(l + 1) * kp], s[l * kp:(l + 1) * kp], policy)
+        if policy == tiny.EMPTY_LITERAL:
+            rho = m
+        elif e == kp:
+            rho = t["lcm"] if aj else 0
+        else:
+            rho = m * t["dmul"][e]
+        S += t["W"][l] * rho
+        if S >= t["acc"][l]:
+            return True, l + 1
+        if S <= t["rej"][l]:
+            return False, l + 1
+    raise AssertionError("tables left a pair undecided after the last group")
+
+
+TABLE_CASES = [
+    (H.SketchParams(H.LAYOUT_OPH, 128, 16, H.HASH_TABLE, 1 << 16), True),
+    (H.SketchParams(H.LAYOUT_HIER, 512, 32, H.HASH_MODP31, 1 << 20, 1, 1, 5, 7), False),
+    (H.SketchParams(H.LAYOUT_HIER, 256, 32, H.HASH_MODP32P15, 1 << 32, 1, 2, 5, 7), False),
+    (H.SketchParams(H.LAYOUT_HIER, 256, 32, H.HASH_MODP32P15, 1 << 32, 2, 1, 5, 7), False),
+    (H.SketchParams(H.LAYOUT_OPH, 512, 32, H.HASH_MODP31, 1 << 20, hash_a=5, hash_b=7), True),
+    (H.SketchParams(H.LAYOUT_HIER, 24, 4, H.HASH_TABLE, 1000, 3, 5), False),
+]
+
+
+@pytest.mark.parametrize("case", TABLE_CASES, ids=lambda c: f"{'goph' if c[1] else 'hoph'}k{c[0].k}kp{c[0].k_group}r{c[0].ratio_a}{c[0].ratio_b}")
+def test_decision_tables_reproduce_oracle_decisions(case):
+    p, goph = case
+    rng = random.Random(p.k * 7 + p.ratio_b)
+    lay = _tiny_layout(p)
+    kp = p.k_group
+    for T in (F(1, 2), F(7, 10), F(4, 5), F(9, 10)):
+        for eps in (F(1, 10 ** 4), F(1, 100), F(0)):
+            for policy in (tiny.EMPTY_JOINT, tiny.EMPTY_EITHER, tiny.EMPTY_LITERAL):
+                t = H.decision_tables(p, (T.numerator, T.denominator), (eps.numerator, eps.denominator), policy, goph)
+                for _ in range(25):
+                    rho = rng.choice([0.0, 0.3, 0.6, T * 1.0, 0.85, 0.95, 1.0])
+                    q, s = _rand_sig_pair(rng, p.k, float(rho), rng.choice([0.0, 0.05, 0.4]))
+                    want = tiny.decide(q, s, lay, goph, T, eps, policy)
+                    assert _apply_tables(t, q, s, kp, policy) == want, (T, eps, policy, rho)
+
+
+def test_worked_example_tables():
+    """The tables decide the Sec. 4.1 example pairs as the oracle does, and
+    D1 against itself is accepted."""
+    p = H.SketchParams(H.LAYOUT_HIER, 6, 2, H.HASH_TABLE, 16)
+    lay = _tiny_layout(p)
+    ident = list(range(16))
+    sets = [[1, 2, 5, 10, 12, 15], [1, 2, 6, 10, 12, 14], [2, 9, 10, 12, 14]]
+    sig = [tiny.sketch(s, lay, tiny.HASH_TABLE, ident) for s in sets]
+    for T in (F(1, 2), F(3, 5), F(5, 8)):
+        for pol in (tiny.EMPTY_JOINT, tiny.EMPTY_EITHER):
+            t = H.decision_tables(p, (T.numerator, T.denominator), (1, 10 ** 4), pol, False)
+            for a in sig:
+                for b in sig:
+                    assert _apply_tables(t, a, b, 2, pol) == tiny.decide(a, b, lay, False, T, F(1, 10 ** 4), pol)
+
+
+def expect_status(fn, status):
+    with pytest.raises(H.HophError) as ei:
+        fn()
+    assert ei.value.status == status, str(ei.value)
+
+
+def test_invalid_parameters_rejected_on_host():
+    ok = H.SketchParams(H.LAYOUT_HIER, 512, 32, H.HASH_MODP31, 1 << 20, 1, 1, 5, 7)
+    bad = [
+        H.SketchParams(H.LAYOUT_HIER, 500, 32, H.HASH_MODP31, 1 << 20, 1, 1, 5, 7),      # k % k' != 0
+        H.SketchParams(H.LAYOUT_HIER, 130, 65, H.HASH_MODP31, 1 << 20, 1, 1, 5, 7),      # k' > 64
+        H.SketchParams(H.LAYOUT_HIER, 8, 2, H.HASH_TABLE, 16),                            # stop rule (L = 4 at D = 16)
+        H.SketchParams(H.LAYOUT_HIER, 512, 32, H.HASH_MODP31, 1 << 20, 0, 1, 5, 7),      # a = 0
+        H.SketchParams(H.LAYOUT_HIER, 512, 32, H.HASH_MODP31, 1 << 31, 1, 1, 5, 7),      # D > 2^31 - 1
+        H.SketchParams(H.LAYOUT_HIER, 512, 32, H.HASH_MODP31, 1 << 20, 1, 1, 0, 7),      # a = 0 (hash)
+        H.SketchParams(H.LAYOUT_HIER, 512, 32, H.HASH_MODP31, 1 << 20, 1, 1, tiny.P31, 7),
+        H.SketchParams(H.LAYOUT_OPH, 32, 32, H.HASH_TABLE, 16),                           # k > R
+        H.SketchParams(H.LAYOUT_OPH, 1, 1, H.HASH_MODP32P15, 1 << 32, hash_a=3),          # bin wider than 2^32 - 1
+        H.SketchParams(2, 64, 32, H.HASH_MODP31, 1 << 20, hash_a=3),                      # unknown layout
+        H.SketchParams(H.LAYOUT_OPH, 64 * 65, 64, H.HASH_MODP31, 1 << 20, hash_a=3),      # more than 64 groups
+    ]
+    for p in bad:
+        expect_status(lambda: H.layout_starts(p), H.HOPH_E_INVAL)
+    H.layout_starts(ok)
+    for T, eps in [((0, 1), (1, 10)), ((6, 5), (1, 10)), ((1, 0), (1, 10)), ((4, 5), (1, 1)), ((4, 5), (3, 2))]:
+        expect_status(lambda: H.decision_tables(ok, T, eps), H.HOPH_E_INVAL)
+
+
+def test_exact_state_overflow_is_unsupported():
+    p = H.SketchParams(H.LAYOUT_HIER, 512, 32, H.HASH_MODP31, 1 << 30, 1, 2, 5, 7)     # 3^15 lcm(1..32) > 2^63
+    expect_status(lambda: H.decision_tables(p, (4, 5), (1, 10 ** 4)), H.HOPH_E_UNSUPPORTED)
+    # LITERAL needs no lcm and fits
+    H.decision_tables(p, (4, 5), (1, 10 ** 4), H.EMPTY_LITERAL)
+    # 1:1 at 16 groups of 32 fits exactly
+    H.decision_tables(H.SketchParams(H.LAYOUT_HIER, 512, 32, H.HASH_MODP31, 1 << 20, 1, 1, 5, 7), (4, 5), (1, 10 ** 4))
+
+
+def test_device_entry_points_refuse_bad_params_before_launch():
+    """Host validation runs before any device work, so it is testable without a GPU."""
+    p = H.SketchParams(H.LAYOUT_HIER, 500, 32, H.HASH_MODP31, 1 << 20, 1, 1, 5, 7)
+    pc = p.c()
+    st = H.lib().sketch_oph(pc, None, None, 0, None, None)
+    assert st == H.HOPH_E_INVAL
+    st = H.lib().build_index(pc, None, 0, 0, H.C.byref(H.vp()), None)
+    assert st == H.HOPH_E_INVAL
+    qp = H.QueryParamsC(H.Ratio(4, 5), H.Ratio(1, 10000), 0, 0)
+    res = H.ResultsC(None, None, 0, 0)
+    assert H.lib().query_hoph(None, None, 0, qp, res, None) == H.HOPH_E_INVAL
