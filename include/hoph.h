@@ -190,6 +190,62 @@ hoph_status minwise_query(const hoph_minwise_params *params, const uint64_t *d_s
                           uint64_t n_sets, const uint64_t *d_qsigs, uint32_t n_q, hoph_ratio T,
                           hoph_results *results, void *hip_stream);
 
+/* ------------------------------------------------------------------------ */
+/* Batched execution: persistent kernels, hipGraph replay, tuned tile shapes */
+/* ------------------------------------------------------------------------ */
+
+/* A plan answers batches of query *sets* against one index: sketch (chunked, so
+   sets of 10 or 10,000 ids balance), per-group query masks, coarse and fine
+   passes, per-query output -- every kernel reads the batch size from device
+   memory, so one captured graph serves every batch up to the plan's capacities.
+   Results are the same as sketch_oph followed by query_goph / query_hoph. */
+typedef struct hoph_plan hoph_plan;
+
+typedef struct {
+    uint32_t kind;            /* 0: GOPH (Alg. 1, HOPH_LAYOUT_OPH index), 1: HOPH (Alg. 2)        */
+    uint32_t max_queries;     /* query sets per batch (>= 1)                                      */
+    uint64_t max_query_ids;   /* ids of all query sets of a batch                                 */
+    uint64_t max_results;     /* accepted pairs per batch                                         */
+    uint32_t use_graph;       /* 1: capture the pipeline once and replay it for every batch       */
+    uint32_t tune;            /* 1: time candidate tile shapes on the first batch and keep the best */
+} hoph_plan_config;
+
+typedef struct {
+    uint32_t q_per_wave;          /* queries per wavefront work item in the coarse pass      */
+    uint32_t coarse_waves_per_cu; /* persistent coarse grid                                  */
+    uint32_t sketch_chunk;        /* ids per sketch work item                                */
+    uint32_t sketch_waves_per_cu; /* persistent sketch grid                                  */
+    uint32_t depth;               /* coarse groups                                           */
+    uint32_t graph;               /* 1 if batches replay a captured graph                    */
+    uint32_t tuned;               /* 1 if the shapes came from timing (or the tuning cache)  */
+    uint32_t fallbacks;           /* batches redone on the host-synchronised path            */
+    float tune_ms;                /* the chosen shapes' time on the tuning batch             */
+} hoph_plan_info;
+
+/* hoph_plan_create -- allocate a plan (device buffers sized by cfg) for index
+   and query parameters qp.  params must be the index's sketch parameters. */
+hoph_status hoph_plan_create(hoph_index *index, const hoph_sketch_params *params,
+                             const hoph_query_params *qp, const hoph_plan_config *cfg,
+                             hoph_plan **out);
+
+/* hoph_plan_run -- queue one batch of n_q query sets (device CSR; d_offsets[0] must
+   be 0 and d_offsets[n_q] == n_ids) on hip_stream.  Asynchronous: no host
+   synchronisation unless this is the first batch of a plan with tune = 1.
+   HOPH_E_CAPACITY if n_q or n_ids exceed the plan. */
+hoph_status hoph_plan_run(hoph_plan *plan, const uint32_t *d_ids, const uint64_t *d_offsets,
+                          uint32_t n_q, uint64_t n_ids, void *hip_stream);
+
+/* hoph_plan_results -- wait for the last batch and return its CSR (plan-owned device
+   memory, valid until the next run): per query ascending set ids.  A batch that
+   overflowed a device buffer or held a query with more than 4096 results is redone
+   on the host-synchronised path, so the output is always exact.  HOPH_E_CAPACITY
+   (with *n_results = pairs needed) if the batch has more than max_results pairs. */
+hoph_status hoph_plan_results(hoph_plan *plan, const uint64_t **d_offsets,
+                              const uint32_t **d_set_ids, uint64_t *n_results, void *hip_stream);
+
+hoph_status hoph_plan_get_info(const hoph_plan *plan, hoph_plan_info *info);
+void hoph_plan_free(hoph_plan *plan);
+
 /* hoph_sync -- synchronise hip_stream and report (then clear) the device error
    flags raised by earlier sketches on the current device. */
 hoph_status hoph_sync(void *hip_stream);

@@ -54,6 +54,17 @@ class DecisionTablesC(C.Structure):
                 ("dmul", i64 * 65)]
 
 
+class PlanConfigC(C.Structure):
+    _fields_ = [("kind", u32), ("max_queries", u32), ("max_query_ids", u64), ("max_results", u64),
+                ("use_graph", u32), ("tune", u32)]
+
+
+class PlanInfoC(C.Structure):
+    _fields_ = [("q_per_wave", u32), ("coarse_waves_per_cu", u32), ("sketch_chunk", u32),
+                ("sketch_waves_per_cu", u32), ("depth", u32), ("graph", u32), ("tuned", u32), ("fallbacks", u32),
+                ("tune_ms", C.c_float)]
+
+
 # name -> (restype, argtypes); every symbol declared in include/hoph.h
 SIGNATURES = {
     "sketch_oph": (C.c_int, [C.POINTER(SketchParamsC), vp, vp, u64, vp, vp]),
@@ -77,6 +88,12 @@ SIGNATURES = {
                                              C.POINTER(DecisionTablesC)]),
     "hoph_selftest_bins": (C.c_int, [C.POINTER(SketchParamsC), vp, vp, u64, vp, vp]),
     "hoph_pair_counts": (C.c_int, [vp, vp, u32, vp, u64, u32, vp, vp, vp]),
+    "hoph_plan_create": (C.c_int, [vp, C.POINTER(SketchParamsC), C.POINTER(QueryParamsC), C.POINTER(PlanConfigC),
+                                   C.POINTER(vp)]),
+    "hoph_plan_run": (C.c_int, [vp, vp, vp, u32, u64, vp]),
+    "hoph_plan_results": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(u64), vp]),
+    "hoph_plan_get_info": (C.c_int, [vp, C.POINTER(PlanInfoC)]),
+    "hoph_plan_free": (None, [vp]),
 }
 
 _lib = None
@@ -319,6 +336,79 @@ def minwise_query(params: MinwiseParams, sigs, qsigs, T=(4, 5), capacity=None, s
             continue
         _check(st, int(res.needed))
         return offsets, ids[:int(res.needed)]
+
+
+_hip = None
+
+
+def _device_copy(dst_ptr: int, src_ptr: int, nbytes: int, stream):
+    """Device-to-device copy on a stream (memory plumbing for plan outputs)."""
+    global _hip
+    if _hip is None:
+        import torch  # noqa: F401  (loads the HIP runtime)
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpyAsync.argtypes = [vp, vp, C.c_size_t, C.c_int, vp]
+        _hip.hipMemcpyAsync.restype = C.c_int
+    if nbytes:
+        rc = _hip.hipMemcpyAsync(vp(dst_ptr), vp(src_ptr), nbytes, 3, _stream(stream))
+        if rc != 0:
+            raise RuntimeError(f"hipMemcpyAsync failed ({rc})")
+
+
+class Plan:
+    """Batched GOPH/HOPH over query *sets*: sketch + scan + output per batch,
+    persistent kernels, optionally one captured hipGraph replayed per batch and
+    tile shapes tuned on the first batch."""
+
+    def __init__(self, index: Index, params: SketchParams, T=(4, 5), eps=(1, 10000), policy=EMPTY_JOINT,
+                 kind: Optional[int] = None, max_queries=4096, max_query_ids=1 << 24, max_results=1 << 20,
+                 use_graph=True, tune=False, coarse_depth=0):
+        if kind is None:
+            kind = 0 if params.layout == LAYOUT_OPH else 1
+        self.index = index          # keep the index alive
+        self.kind = kind
+        self._h = vp()
+        pc = params.c()
+        qp = QueryParamsC(_ratio(T), _ratio(eps), policy, coarse_depth)
+        cfg = PlanConfigC(kind, max_queries, max_query_ids, max_results, 1 if use_graph else 0, 1 if tune else 0)
+        _check(lib().hoph_plan_create(index.handle, C.byref(pc), C.byref(qp), C.byref(cfg), C.byref(self._h)))
+
+    def run(self, ids, offsets, stream=None):
+        import torch
+        _need_cuda(ids, "ids", (torch.int32,))
+        _need_cuda(offsets, "offsets", (torch.int64,))
+        n_q = offsets.numel() - 1
+        _check(lib().hoph_plan_run(self._h, vp(ids.data_ptr()), vp(offsets.data_ptr()), n_q, ids.numel(),
+                                   _stream(stream)))
+        self._nq = n_q
+
+    def results(self, stream=None):
+        """(offsets int64[n_q+1], set ids int32[...]) of the last batch (copies)."""
+        import torch
+        po, pi, n = vp(), vp(), u64()
+        st = lib().hoph_plan_results(self._h, C.byref(po), C.byref(pi), C.byref(n), _stream(stream))
+        _check(st, int(n.value))
+        offs = torch.empty(self._nq + 1, dtype=torch.int64, device="cuda")
+        ids = torch.empty(max(int(n.value), 1), dtype=torch.int32, device="cuda")
+        _device_copy(offs.data_ptr(), po.value, (self._nq + 1) * 8, stream)
+        _device_copy(ids.data_ptr(), pi.value, int(n.value) * 4, stream)
+        return offs, ids[:int(n.value)]
+
+    def info(self) -> dict:
+        i = PlanInfoC()
+        _check(lib().hoph_plan_get_info(self._h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in PlanInfoC._fields_}
+
+    def free(self):
+        if self._h:
+            lib().hoph_plan_free(self._h)
+            self._h = vp()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def pair_counts(index: Index, qsigs, pairs, policy=EMPTY_JOINT, stream=None):

@@ -8,18 +8,16 @@
 #include <new>
 #include <string>
 
-#include "hoph_internal.h"
+#include "runtime.h"
 
-namespace hoph {
-uint32_t max_depth_for_kpad(uint32_t kpad);
-uint64_t sort_capacity(uint64_t n);
-}  // namespace hoph
 
 using namespace hoph;
 
-namespace {
+namespace hoph {
 
 thread_local std::string g_last_error;
+
+void clear_error() { g_last_error.clear(); }
 
 hoph_status fail(hoph_status st, const std::string &msg) {
     g_last_error = msg;
@@ -29,26 +27,6 @@ hoph_status fail(hoph_status st, const std::string &msg) {
 hoph_status hip_fail(hipError_t e, const char *what) {
     return fail(HOPH_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
-
-#define HOPH_HIP(call, what)                      \
-    do {                                          \
-        hipError_t e_ = (call);                   \
-        if (e_ != hipSuccess) return hip_fail(e_, what); \
-    } while (0)
-
-// Restores the caller's current device on scope exit.
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = true;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
-        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
 
 // One 32-bit device error word per device, allocated on first use.
 constexpr int kMaxDevices = 64;
@@ -70,92 +48,7 @@ hoph_status device_err_word(uint32_t **out) {
     return HOPH_OK;
 }
 
-// Device buffers for one query at a time: survivors, accepted keys, counters.
-struct Workspace {
-    Survivor *surv = nullptr;
-    uint64_t surv_cap = 0;
-    uint64_t *keys = nullptr;
-    uint64_t keys_cap = 0;        // a power of two >= 4096
-    uint64_t *counters = nullptr; // device [0] survivors, [1] accepted
-    uint64_t *qmasks = nullptr;   // per (query, group) empty-bin masks
-    uint64_t qmask_cap = 0;
-    uint64_t *h_counters = nullptr; // pinned host mirror
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    float last_ms[3] = {0, 0, 0};
-    void release() {
-        for (auto &e : ev)
-            if (e) { (void)hipEventDestroy(e); e = nullptr; }
-        if (surv) (void)hipFree(surv);
-        if (keys) (void)hipFree(keys);
-        if (counters) (void)hipFree(counters);
-        if (qmasks) (void)hipFree(qmasks);
-        if (h_counters) (void)hipHostFree(h_counters);
-        qmasks = nullptr;
-        qmask_cap = 0;
-        surv = nullptr;
-        keys = nullptr;
-        counters = nullptr;
-        h_counters = nullptr;
-        surv_cap = keys_cap = 0;
-    }
-    hoph_status init(uint64_t surv_records, uint64_t keys_records) {
-        HOPH_HIP(hipMalloc(&counters, 64), "hipMalloc(counters)");
-        HOPH_HIP(hipHostMalloc(&h_counters, 64, hipHostMallocDefault), "hipHostMalloc(counters)");
-        for (auto &e : ev) HOPH_HIP(hipEventCreate(&e), "hipEventCreate");
-        hoph_status st = grow_surv(surv_records);
-        if (st) return st;
-        return grow_keys(keys_records);
-    }
-    hoph_status grow_surv(uint64_t n) {
-        if (n <= surv_cap) return HOPH_OK;
-        if (surv) (void)hipFree(surv);
-        surv = nullptr;
-        surv_cap = 0;
-        if (hipMalloc(&surv, n * sizeof(Survivor)) != hipSuccess) return fail(HOPH_E_NOMEM, "survivor buffer");
-        surv_cap = n;
-        return HOPH_OK;
-    }
-    hoph_status grow_qmasks(uint64_t n) {
-        if (n <= qmask_cap) return HOPH_OK;
-        if (qmasks) (void)hipFree(qmasks);
-        qmasks = nullptr;
-        qmask_cap = 0;
-        uint64_t want = 4096;
-        while (want < n) want <<= 1;
-        if (hipMalloc(&qmasks, want * sizeof(uint64_t)) != hipSuccess) return fail(HOPH_E_NOMEM, "query mask buffer");
-        qmask_cap = want;
-        return HOPH_OK;
-    }
-    hoph_status grow_keys(uint64_t n) {
-        const uint64_t want = sort_capacity(n);
-        if (want <= keys_cap) return HOPH_OK;
-        if (keys) (void)hipFree(keys);
-        keys = nullptr;
-        keys_cap = 0;
-        if (hipMalloc(&keys, want * sizeof(uint64_t)) != hipSuccess) return fail(HOPH_E_NOMEM, "key buffer");
-        keys_cap = want;
-        return HOPH_OK;
-    }
-};
 
-uint32_t round4(uint32_t x) { return (x + 3u) & ~3u; }
-
-}  // namespace
-
-struct hoph_index {
-    int device = 0;
-    hoph_sketch_params params{};
-    LayoutInfo lay;
-    uint32_t kpad = 0;
-    uint64_t n = 0;
-    uint64_t capacity = 0;        // slab capacity in sets, a multiple of 64
-    uint64_t max_sets = 0;        // the capacity the caller asked for
-    uint32_t *slab = nullptr;
-    Workspace ws;
-    std::mutex mu;
-};
-
-namespace {
 
 bool valid_ratio_T(hoph_ratio T) { return T.den != 0 && T.num != 0 && T.num <= T.den; }
 bool valid_ratio_eps(hoph_ratio e) { return e.den != 0 && e.num < e.den; }
@@ -168,7 +61,6 @@ hoph_status check_results(const hoph_results *r, uint32_t n_q) {
     return HOPH_OK;
 }
 
-enum class QueryKind { GOPH, HOPH, OPH_FULL };
 
 // Pick queries per wavefront so that the grid has enough wavefronts to fill
 // the device (about 32 per CU) without splitting the query batch further.
@@ -184,6 +76,27 @@ hoph_status copy_counters(Workspace &ws, hipStream_t st) {
     HOPH_HIP(hipMemcpyAsync(ws.h_counters, ws.counters, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, st),
              "hipMemcpyAsync(counters)");
     HOPH_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    return HOPH_OK;
+}
+
+// Accepted keys -> per-query ascending CSR in the caller's buffers: counting,
+// scan, scatter and a per-query LDS sort; the global bitonic sort is used when
+// a query holds more than 4096 ids (the device reports it in counters[3]).
+hoph_status write_output(Workspace &ws, uint64_t accepted, uint32_t n_q, hoph_results *res, hipStream_t s) {
+    hoph_status st = ws.grow_seg((uint64_t)n_q + 1);
+    if (st) return st;
+    HOPH_HIP(launch_segmented_output(ws.keys, ws.counters, ws.keys_cap, ws.qcount, nullptr, n_q, res->d_offsets,
+                                     ws.cursor, res->d_set_ids, res->capacity, ws.counters, n_q, accepted, s),
+             "output launch");
+    if (accepted > 4096) {
+        HOPH_HIP(hipMemcpyAsync(ws.h_counters + 2, ws.counters + 2, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s),
+                 "hipMemcpyAsync(flags)");
+        HOPH_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+        if (ws.h_counters[3] & 1ull) {
+            HOPH_HIP(launch_sort_keys(ws.keys, accepted, sort_capacity(accepted), s), "sort launch");
+            HOPH_HIP(launch_results(ws.keys, accepted, n_q, res->d_offsets, res->d_set_ids, s), "results launch");
+        }
+    }
     return HOPH_OK;
 }
 
@@ -240,7 +153,7 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
     if (kind != QueryKind::OPH_FULL && n_q && idx->n) {
         st = ws.grow_qmasks((uint64_t)n_q * lay.L);
         if (st) return st;
-        HOPH_HIP(launch_query_masks(d_qsigs, n_q, lay.k, lay.kp, lay.L, ws.qmasks, s), "query mask launch");
+        HOPH_HIP(launch_query_masks(d_qsigs, n_q, nullptr, lay.k, lay.kp, lay.L, ws.qmasks, s), "query mask launch");
     }
     a.qmasks = ws.qmasks;
 
@@ -315,8 +228,8 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
     }
     const bool timed = n_q && idx->n;
     if (timed) HOPH_HIP(hipEventRecord(ws.ev[2], s), "hipEventRecord");
-    HOPH_HIP(launch_sort_keys(ws.keys, accepted, sort_capacity(accepted), s), "sort launch");
-    HOPH_HIP(launch_results(ws.keys, accepted, n_q, res->d_offsets, res->d_set_ids, s), "results launch");
+    st = write_output(ws, accepted, n_q, res, s);
+    if (st) return st;
     if (timed) HOPH_HIP(hipEventRecord(ws.ev[3], s), "hipEventRecord");
     HOPH_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
     ws.last_ms[0] = ws.last_ms[1] = ws.last_ms[2] = 0.f;
@@ -332,7 +245,7 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
 std::mutex g_mw_mu;
 Workspace *g_mw_ws[kMaxDevices] = {};
 
-}  // namespace
+}  // namespace hoph
 
 extern "C" {
 
@@ -538,8 +451,8 @@ hoph_status minwise_query(const hoph_minwise_params *params, const uint64_t *d_s
     }
     res->needed = accepted;
     if (accepted > res->capacity) return fail(HOPH_E_CAPACITY, "results capacity too small");
-    HOPH_HIP(launch_sort_keys(ws.keys, accepted, sort_capacity(accepted), s), "sort launch");
-    HOPH_HIP(launch_results(ws.keys, accepted, n_q, res->d_offsets, res->d_set_ids, s), "results launch");
+    st = write_output(ws, accepted, n_q, res, s);
+    if (st) return st;
     HOPH_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
     return HOPH_OK;
 }

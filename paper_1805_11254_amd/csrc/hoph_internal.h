@@ -141,9 +141,19 @@ void to_scan_tab(const hoph_decision_tables &t, ScanTab &s);
 // Kernel launchers (k_*.hip).  All return hipError_t of the launch.
 // ---------------------------------------------------------------------------
 int device_cu_count();   // compute units of the current device (cached)
+// desc[0] = a, desc[1] = b, written by a one-thread kernel in stream order (the
+// values travel as kernel arguments, so no host buffer has to outlive the call).
+hipError_t launch_set_desc(uint64_t *desc, uint64_t a, uint64_t b, hipStream_t st);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t value, hipStream_t st);
 hipError_t launch_sketch(const SketchDesc &d, const uint32_t *ids, const uint64_t *offsets,
                          uint64_t n_sets, uint32_t *sigs, uint32_t *err_flag, hipStream_t st);
+// Sketch of a batch whose size is desc[0] (at most max_sets), split into chunks of
+// `chunk` ids so that uneven sets balance; prefix needs max_sets + 1 entries.
+// Set ranges are clamped to the first max_ids staged ids (a malformed range is empty).
+hipError_t launch_sketch_chunked(const SketchDesc &d, const uint32_t *ids, const uint64_t *offsets,
+                                 const uint64_t *desc, uint64_t *prefix, uint32_t chunk, uint32_t max_sets,
+                                 uint64_t max_ids, uint32_t *sigs, uint32_t *err_flag, uint32_t waves_per_cu,
+                                 hipStream_t st);
 hipError_t launch_index_store(const uint32_t *sigs, uint64_t n_new, uint64_t first, uint32_t k,
                               uint32_t kp, uint32_t L, uint32_t kpad, uint64_t capacity,
                               uint32_t *slab, hipStream_t st);
@@ -167,13 +177,21 @@ struct ScanLaunch {
     uint64_t *keys;
     uint64_t keys_cap;
     uint64_t *counters;         // [0] survivors, [1] accepted
+    const uint64_t *desc;       // nullable: desc[0] = n_q, desc[1] = n_sets, read on the device
+    uint32_t waves_per_cu;      // persistent grid size with desc (0 = default)
 };
-hipError_t launch_query_masks(const uint32_t *qsigs, uint32_t n_q, uint32_t k, uint32_t kp, uint32_t L,
-                              uint64_t *out, hipStream_t st);
+hipError_t launch_query_masks(const uint32_t *qsigs, uint32_t n_q, const uint64_t *desc, uint32_t k, uint32_t kp,
+                              uint32_t L, uint64_t *out, hipStream_t st);
 hipError_t launch_scan_coarse(const ScanLaunch &a, const ScanTab &tab, hipStream_t st);
 hipError_t launch_scan_fine(const ScanLaunch &a, const ScanTab &tab, hipStream_t st);
 hipError_t launch_oph_full(const ScanLaunch &a, hoph_ratio T, uint32_t policy, hipStream_t st);
 hipError_t launch_sort_keys(uint64_t *keys, uint64_t n, uint64_t n_pow2, hipStream_t st);
+// counters: [1] accepted keys (read), [2] total written, [3] flags (bit 0: a query
+// has more than 4096 ids, bit 1: total > out_cap).  desc (nullable): desc[0] = n_q.
+hipError_t launch_segmented_output(const uint64_t *keys, const uint64_t *counters_ro, uint64_t keys_cap,
+                                   uint32_t *qcount, const uint64_t *desc, uint32_t n_q, uint64_t *offsets,
+                                   uint64_t *cursor, uint32_t *ids, uint64_t out_cap, uint64_t *counters,
+                                   uint32_t max_queries, uint64_t max_keys, hipStream_t st);
 hipError_t launch_results(const uint64_t *keys, uint64_t n, uint32_t n_q, uint64_t *offsets,
                           uint32_t *set_ids, hipStream_t st);
 hipError_t launch_minwise_sketch(uint32_t k, uint32_t hash, uint64_t universe, const uint64_t *ha,

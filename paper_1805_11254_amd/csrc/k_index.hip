@@ -103,6 +103,11 @@ __global__ __launch_bounds__(kThreads) void pair_counts_kernel(const uint32_t *_
     }
 }
 
+__global__ void set_desc_kernel(uint64_t *desc, uint64_t a, uint64_t b) {
+    desc[0] = a;
+    desc[1] = b;
+}
+
 uint32_t grid_for(uint64_t work, uint32_t per_block, uint32_t cap = 65536) {
     uint64_t g = (work + per_block - 1) / per_block;
     if (g == 0) g = 1;
@@ -119,6 +124,11 @@ int device_cu_count() {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
     cached[dev] = cus;
     return cus;
+}
+
+hipError_t launch_set_desc(uint64_t *desc, uint64_t a, uint64_t b, hipStream_t st) {
+    hipLaunchKernelGGL(set_desc_kernel, dim3(1), dim3(1), 0, st, desc, a, b);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t value, hipStream_t st) {

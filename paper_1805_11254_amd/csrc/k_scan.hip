@@ -60,9 +60,10 @@ __device__ __forceinline__ int64_t group_rho(uint32_t eq, uint32_t ej, uint32_t 
 }
 
 // Empty-bin mask of every (query, group): bit i set when bin i of the group is EMPTY.
-__global__ __launch_bounds__(kThreads) void query_masks_kernel(const uint32_t *__restrict__ qsigs, uint32_t n_q,
-                                                              uint32_t k, uint32_t kp, uint32_t L,
-                                                              uint64_t *__restrict__ out) {
+__global__ __launch_bounds__(kThreads) void query_masks_kernel(const uint32_t *__restrict__ qsigs, uint32_t n_q_arg,
+                                                              const uint64_t *__restrict__ desc, uint32_t k,
+                                                              uint32_t kp, uint32_t L, uint64_t *__restrict__ out) {
+    const uint32_t n_q = desc ? (uint32_t)desc[0] : n_q_arg;
     const uint64_t n = (uint64_t)n_q * L;
     for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < n; t += (uint64_t)gridDim.x * kThreads) {
         const uint64_t q = t / L, g = t % L;
@@ -80,6 +81,7 @@ __global__ __launch_bounds__(kThreads) void scan_coarse_kernel(const uint32_t *_
                                                               Survivor *__restrict__ surv,
                                                               uint64_t *__restrict__ keys,
                                                               unsigned long long *__restrict__ counters,
+                                                              const uint64_t *__restrict__ desc,
                                                               const CoarseArgs a, const ScanTab tab) {
     __shared__ int64_t s_dmul[HOPH_MAX_KGROUP + 1];
     __shared__ int32_t s_macc[HOPH_MAX_KGROUP + 1], s_mrej[HOPH_MAX_KGROUP + 1];
@@ -91,19 +93,21 @@ __global__ __launch_bounds__(kThreads) void scan_coarse_kernel(const uint32_t *_
     __syncthreads();
 
     const uint32_t lane = threadIdx.x & 63;
-    const uint64_t wave = (uint64_t)blockIdx.x * kWaves + wave_id_in_block();
-    const uint64_t ntiles = (a.n_sets + 63) / 64;
-    const uint32_t nq = a.q1 - a.q0;
-    const uint32_t nchunks = (nq + a.q_per_wave - 1) / a.q_per_wave;
-    if (wave >= ntiles * nchunks) return;
-    const uint64_t tile = wave % ntiles;
-    const uint32_t chunk = (uint32_t)(wave / ntiles);
-    const uint64_t s = tile * 64 + lane;
-    const bool valid = s < a.n_sets;
+    const uint64_t n_sets = desc ? desc[1] : a.n_sets;
+    const uint32_t q_lo = desc ? 0u : a.q0, q_hi = desc ? (uint32_t)desc[0] : a.q1;
+    const uint64_t ntiles = (n_sets + 63) / 64;
+    const uint32_t nchunks = (q_hi - q_lo + a.q_per_wave - 1) / a.q_per_wave;
+    const uint64_t n_items = ntiles * nchunks;
+    const uint64_t wstride = (uint64_t)gridDim.x * kWaves;
     const uint32_t kp = EXACT ? KPAD : a.kp;
     const uint64_t kpmask = kp >= 64 ? ~0ull : ((1ull << kp) - 1ull);
     const uint64_t gstride = a.capacity * KPAD;
     const uint32_t policy = a.policy;
+    for (uint64_t item = (uint64_t)blockIdx.x * kWaves + wave_id_in_block(); item < n_items; item += wstride) {
+    const uint64_t tile = item % ntiles;
+    const uint32_t chunk = (uint32_t)(item / ntiles);
+    const uint64_t s = tile * 64 + lane;
+    const bool valid = s < n_sets;
 
     uint32_t w[G][KPAD];
     uint64_t emask[G];
@@ -124,8 +128,8 @@ __global__ __launch_bounds__(kThreads) void scan_coarse_kernel(const uint32_t *_
         emask[g] = em & kpmask;
     }
 
-    const uint32_t qa = a.q0 + chunk * a.q_per_wave;
-    const uint32_t qb = min(a.q1, qa + a.q_per_wave);
+    const uint32_t qa = q_lo + chunk * a.q_per_wave;
+    const uint32_t qb = min(q_hi, qa + a.q_per_wave);
     for (uint32_t q = qa; q < qb; ++q) {
         const uint32_t *qw = qsigs + (uint64_t)q * a.k;
         const uint64_t *qmk = qmasks + (uint64_t)q * a.L;
@@ -192,6 +196,7 @@ __global__ __launch_bounds__(kThreads) void scan_coarse_kernel(const uint32_t *_
             const uint64_t slot = wave_append(undecided, counters + 0, lane);
             if (undecided && slot < a.surv_cap) surv[slot] = Survivor{q, (uint32_t)s, S};
         }
+    }
     }
 }
 
@@ -328,7 +333,7 @@ void coarse_launch(const ScanLaunch &l, const CoarseArgs &a, const ScanTab &tab,
     auto *cnt = reinterpret_cast<unsigned long long *>(l.counters);
 #define HOPH_COARSE(G)                                                                                        \
     hipLaunchKernelGGL((scan_coarse_kernel<KPAD, G, EXACT>), dim3(blocks), dim3(kThreads), 0, st, l.slab,    \
-                       l.qsigs, l.qmasks, l.surv, l.keys, cnt, a, tab)
+                       l.qsigs, l.qmasks, l.surv, l.keys, cnt, l.desc, a, tab)
     switch (l.depth) {
     case 1: HOPH_COARSE(1); break;
     case 2: if constexpr (KPAD * 2 <= 128) HOPH_COARSE(2); break;
@@ -382,22 +387,29 @@ uint32_t max_depth_for_kpad(uint32_t kpad) {
     return d < kMaxDepth ? d : kMaxDepth;
 }
 
-hipError_t launch_query_masks(const uint32_t *qsigs, uint32_t n_q, uint32_t k, uint32_t kp, uint32_t L,
-                              uint64_t *out, hipStream_t st) {
-    const uint64_t n = (uint64_t)n_q * L;
+hipError_t launch_query_masks(const uint32_t *qsigs, uint32_t n_q, const uint64_t *desc, uint32_t k, uint32_t kp,
+                              uint32_t L, uint64_t *out, hipStream_t st) {
+    const uint64_t n = (uint64_t)n_q * L;         // n_q: the batch size, or its upper bound with desc
     if (n == 0) return hipSuccess;
     uint64_t blocks = (n + kThreads - 1) / kThreads;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(query_masks_kernel, dim3((uint32_t)blocks), dim3(kThreads), 0, st, qsigs, n_q, k, kp, L, out);
+    hipLaunchKernelGGL(query_masks_kernel, dim3((uint32_t)blocks), dim3(kThreads), 0, st, qsigs, n_q, desc, k, kp, L,
+                       out);
     return hipGetLastError();
 }
 
 hipError_t launch_scan_coarse(const ScanLaunch &l, const ScanTab &tab, hipStream_t st) {
-    const uint64_t ntiles = (l.n_sets + 63) / 64;
-    const uint32_t nq = l.q1 - l.q0;
-    if (ntiles == 0 || nq == 0) return hipSuccess;
-    const uint64_t nchunks = (nq + l.q_per_wave - 1) / l.q_per_wave;
-    const uint32_t blocks = waves_to_blocks(ntiles * nchunks);
+    uint32_t blocks;
+    if (l.desc) {
+        // persistent: a fixed grid walks the (tile, query chunk) items of whatever batch desc describes
+        blocks = waves_to_blocks((uint64_t)device_cu_count() * (l.waves_per_cu ? l.waves_per_cu : 16));
+    } else {
+        const uint64_t ntiles = (l.n_sets + 63) / 64;
+        const uint32_t nq = l.q1 - l.q0;
+        if (ntiles == 0 || nq == 0) return hipSuccess;
+        const uint64_t nchunks = (nq + l.q_per_wave - 1) / l.q_per_wave;
+        blocks = waves_to_blocks(ntiles * nchunks);
+    }
     const CoarseArgs a = coarse_args(l, tab.policy);
     HOPH_KPAD_SWITCH(coarse_kp, l, a, tab, st, blocks)
     return hipGetLastError();

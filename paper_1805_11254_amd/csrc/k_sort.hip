@@ -19,6 +19,10 @@ __device__ __forceinline__ void cswap(uint64_t &x, uint64_t &y, bool up) {
     }
 }
 
+__global__ __launch_bounds__(kThreads) void fill_u32_kernel_for_seg(uint32_t *p, uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kThreads) p[i] = 0;
+}
+
 // Pad [n, N) with the largest key.
 __global__ __launch_bounds__(kThreads) void pad_kernel(uint64_t *keys, uint64_t n, uint64_t N) {
     for (uint64_t i = n + blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < N; i += (uint64_t)gridDim.x * kThreads)
@@ -106,6 +110,148 @@ hipError_t launch_results(const uint64_t *keys, uint64_t n, uint32_t n_q, uint64
                           hipStream_t st) {
     hipLaunchKernelGGL(results_kernel, dim3(grid_for((n > n_q ? n : n_q) + 1)), dim3(kThreads), 0, st, keys, n, n_q,
                        offsets, set_ids);
+    return hipGetLastError();
+}
+
+}  // namespace hoph
+
+// ---------------------------------------------------------------------------
+// Per-query output without a global sort (usable with no host
+// synchronisation, e.g. inside a captured graph): count the accepted keys of
+// every query, scan the counts into CSR offsets, scatter the set ids, then sort
+// each query's ids in LDS.  A query with more than kSegMax ids, or a total above
+// the output capacity, raises a flag so the caller can take the global-sort
+// path instead.
+// ---------------------------------------------------------------------------
+namespace hoph {
+
+namespace {
+
+constexpr uint32_t kSegMax = 4096;
+constexpr int kScanThreads = 1024;
+
+__device__ __forceinline__ uint64_t count_of(const uint64_t *counters, uint64_t cap) {
+    const uint64_t c = counters[1];
+    return c < cap ? c : cap;
+}
+
+__device__ __forceinline__ uint32_t nq_of(const uint64_t *desc, uint32_t n_q) {
+    return desc ? (uint32_t)desc[0] : n_q;
+}
+
+__global__ __launch_bounds__(kThreads) void seg_count_kernel(const uint64_t *__restrict__ keys,
+                                                            const uint64_t *__restrict__ counters, uint64_t keys_cap,
+                                                            uint32_t *__restrict__ qcount) {
+    const uint64_t n = count_of(counters, keys_cap);
+    for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kThreads)
+        atomicAdd(&qcount[keys[i] >> 32], 1u);
+}
+
+// One workgroup: exclusive scan of qcount[0..n_q) into offsets[0..n_q] and
+// cursor[0..n_q); flags bit 0: a query has more than kSegMax ids; bit 1: the
+// total exceeds out_cap.  counters[2] receives the total.
+__global__ __launch_bounds__(kScanThreads) void seg_scan_kernel(const uint32_t *__restrict__ qcount,
+                                                               const uint64_t *__restrict__ desc, uint32_t n_q_arg,
+                                                               uint64_t *__restrict__ offsets,
+                                                               uint64_t *__restrict__ cursor, uint64_t out_cap,
+                                                               uint64_t *__restrict__ counters) {
+    __shared__ uint64_t s_part[kScanThreads];
+    __shared__ uint64_t s_carry;
+    __shared__ uint32_t s_big;
+    const uint32_t n_q = nq_of(desc, n_q_arg);
+    const uint32_t t = threadIdx.x;
+    if (t == 0) { s_carry = 0; s_big = 0; }
+    __syncthreads();
+    for (uint32_t base = 0; base < n_q; base += kScanThreads) {
+        const uint32_t q = base + t;
+        const uint64_t v = q < n_q ? qcount[q] : 0;
+        if (v > kSegMax) atomicOr(&s_big, 1u);
+        s_part[t] = v;
+        __syncthreads();
+        for (uint32_t d = 1; d < kScanThreads; d <<= 1) {     // inclusive Hillis-Steele scan
+            const uint64_t add = t >= d ? s_part[t - d] : 0;
+            __syncthreads();
+            s_part[t] += add;
+            __syncthreads();
+        }
+        const uint64_t excl = s_carry + s_part[t] - v;
+        if (q < n_q) {
+            offsets[q] = excl;
+            cursor[q] = excl;
+        }
+        __syncthreads();
+        if (t == kScanThreads - 1) s_carry += s_part[t];
+        __syncthreads();
+    }
+    if (t == 0) {
+        offsets[n_q] = s_carry;
+        counters[2] = s_carry;
+        counters[3] = (s_big ? 1ull : 0ull) | (s_carry > out_cap ? 2ull : 0ull);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void seg_scatter_kernel(const uint64_t *__restrict__ keys,
+                                                              const uint64_t *__restrict__ counters, uint64_t keys_cap,
+                                                              unsigned long long *__restrict__ cursor,
+                                                              uint32_t *__restrict__ ids, uint64_t out_cap) {
+    const uint64_t n = count_of(counters, keys_cap);
+    for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kThreads) {
+        const uint64_t key = keys[i];
+        const uint64_t pos = atomicAdd(&cursor[key >> 32], 1ull);
+        if (pos < out_cap) ids[pos] = (uint32_t)(key & 0xFFFFFFFFull);
+    }
+}
+
+// One workgroup per query (grid-stride): bitonic sort of the query's ids in LDS.
+__global__ __launch_bounds__(kThreads) void seg_sort_kernel(const uint64_t *__restrict__ offsets,
+                                                           const uint64_t *__restrict__ desc, uint32_t n_q_arg,
+                                                           uint32_t *__restrict__ ids, uint64_t out_cap) {
+    __shared__ uint32_t s[kSegMax];
+    const uint32_t n_q = nq_of(desc, n_q_arg);
+    for (uint32_t q = blockIdx.x; q < n_q; q += gridDim.x) {
+        const uint64_t lo = offsets[q], hi = offsets[q + 1];
+        const uint64_t len = hi - lo;
+        if (len <= 1 || len > kSegMax || hi > out_cap) continue;     // uniform per workgroup
+        uint32_t N = 2;
+        while (N < len) N <<= 1;
+        for (uint32_t i = threadIdx.x; i < N; i += kThreads) s[i] = i < len ? ids[lo + i] : 0xFFFFFFFFu;
+        __syncthreads();
+        for (uint32_t k = 2; k <= N; k <<= 1) {
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                for (uint32_t t = threadIdx.x; t < N / 2; t += kThreads) {
+                    const uint32_t i = 2 * t - (t & (j - 1));
+                    const uint32_t x = s[i], y = s[i + j];
+                    const bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        s[i] = y;
+                        s[i + j] = x;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (uint32_t i = threadIdx.x; i < len; i += kThreads) ids[lo + i] = s[i];
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_segmented_output(const uint64_t *keys, const uint64_t *counters_ro, uint64_t keys_cap,
+                                   uint32_t *qcount, const uint64_t *desc, uint32_t n_q, uint64_t *offsets,
+                                   uint64_t *cursor, uint32_t *ids, uint64_t out_cap, uint64_t *counters,
+                                   uint32_t max_queries, uint64_t max_keys, hipStream_t st) {
+    // counts
+    const uint64_t nqc = (uint64_t)max_queries + 1;
+    hipLaunchKernelGGL(fill_u32_kernel_for_seg, dim3(grid_for(nqc)), dim3(kThreads), 0, st, qcount, nqc);
+    hipLaunchKernelGGL(seg_count_kernel, dim3(grid_for(max_keys)), dim3(kThreads), 0, st, keys, counters_ro, keys_cap,
+                       qcount);
+    hipLaunchKernelGGL(seg_scan_kernel, dim3(1), dim3(kScanThreads), 0, st, qcount, desc, n_q, offsets, cursor, out_cap,
+                       counters);
+    hipLaunchKernelGGL(seg_scatter_kernel, dim3(grid_for(max_keys)), dim3(kThreads), 0, st, keys, counters_ro, keys_cap,
+                       reinterpret_cast<unsigned long long *>(cursor), ids, out_cap);
+    uint32_t blocks = max_queries < 4096 ? (max_queries ? max_queries : 1) : 4096;
+    hipLaunchKernelGGL(seg_sort_kernel, dim3(blocks), dim3(kThreads), 0, st, offsets, desc, n_q, ids, out_cap);
     return hipGetLastError();
 }
 

@@ -1,0 +1,166 @@
+// Runtime internals shared by the C ABI translation units of libhoph
+// (api.cpp, plan.cpp, server.cpp): the index object, the per-query workspace
+// and error helpers.  Not part of the C ABI.
+#pragma once
+
+#include <mutex>
+#include <string>
+
+#include "hoph_internal.h"
+
+namespace hoph {
+
+uint32_t max_depth_for_kpad(uint32_t kpad);
+uint64_t sort_capacity(uint64_t n);
+
+// Record msg as the calling thread's last error and return st.
+hoph_status fail(hoph_status st, const std::string &msg);
+hoph_status hip_fail(hipError_t e, const char *what);
+void clear_error();
+
+#define HOPH_HIP(call, what)                      \
+    do {                                          \
+        hipError_t e_ = (call);                   \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// The device error word of the current device (allocated on first use).
+hoph_status device_err_word(uint32_t **out);
+
+// Device buffers for one query at a time: survivors, accepted keys, counters.
+struct Workspace {
+    Survivor *surv = nullptr;
+    uint64_t surv_cap = 0;
+    uint64_t *keys = nullptr;
+    uint64_t keys_cap = 0;        // a power of two >= 4096
+    uint64_t *counters = nullptr; // device [0] survivors, [1] accepted
+    uint64_t *qmasks = nullptr;   // per (query, group) empty-bin masks
+    uint64_t qmask_cap = 0;
+    uint32_t *qcount = nullptr;   // per-query accepted counts (output stage)
+    uint64_t *cursor = nullptr;   // per-query scatter cursors
+    uint64_t seg_cap = 0;
+    uint64_t *h_counters = nullptr; // pinned host mirror
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    float last_ms[3] = {0, 0, 0};
+    void release() {
+        for (auto &e : ev)
+            if (e) { (void)hipEventDestroy(e); e = nullptr; }
+        if (surv) (void)hipFree(surv);
+        if (keys) (void)hipFree(keys);
+        if (counters) (void)hipFree(counters);
+        if (qmasks) (void)hipFree(qmasks);
+        if (qcount) (void)hipFree(qcount);
+        if (cursor) (void)hipFree(cursor);
+        if (h_counters) (void)hipHostFree(h_counters);
+        qmasks = nullptr;
+        qmask_cap = 0;
+        qcount = nullptr;
+        cursor = nullptr;
+        seg_cap = 0;
+        surv = nullptr;
+        keys = nullptr;
+        counters = nullptr;
+        h_counters = nullptr;
+        surv_cap = keys_cap = 0;
+    }
+    hoph_status init(uint64_t surv_records, uint64_t keys_records) {
+        HOPH_HIP(hipMalloc(&counters, 64), "hipMalloc(counters)");
+        HOPH_HIP(hipHostMalloc(&h_counters, 64, hipHostMallocDefault), "hipHostMalloc(counters)");
+        for (auto &e : ev) HOPH_HIP(hipEventCreate(&e), "hipEventCreate");
+        hoph_status st = grow_surv(surv_records);
+        if (st) return st;
+        return grow_keys(keys_records);
+    }
+    hoph_status grow_surv(uint64_t n) {
+        if (n <= surv_cap) return HOPH_OK;
+        if (surv) (void)hipFree(surv);
+        surv = nullptr;
+        surv_cap = 0;
+        if (hipMalloc(&surv, n * sizeof(Survivor)) != hipSuccess) return fail(HOPH_E_NOMEM, "survivor buffer");
+        surv_cap = n;
+        return HOPH_OK;
+    }
+    hoph_status grow_qmasks(uint64_t n) {
+        if (n <= qmask_cap) return HOPH_OK;
+        if (qmasks) (void)hipFree(qmasks);
+        qmasks = nullptr;
+        qmask_cap = 0;
+        uint64_t want = 4096;
+        while (want < n) want <<= 1;
+        if (hipMalloc(&qmasks, want * sizeof(uint64_t)) != hipSuccess) return fail(HOPH_E_NOMEM, "query mask buffer");
+        qmask_cap = want;
+        return HOPH_OK;
+    }
+    hoph_status grow_seg(uint64_t n) {
+        if (n <= seg_cap) return HOPH_OK;
+        if (qcount) (void)hipFree(qcount);
+        if (cursor) (void)hipFree(cursor);
+        qcount = nullptr;
+        cursor = nullptr;
+        seg_cap = 0;
+        uint64_t want = 1024;
+        while (want < n) want <<= 1;
+        if (hipMalloc(&qcount, want * sizeof(uint32_t)) != hipSuccess ||
+            hipMalloc(&cursor, want * sizeof(uint64_t)) != hipSuccess)
+            return fail(HOPH_E_NOMEM, "output stage buffers");
+        seg_cap = want;
+        return HOPH_OK;
+    }
+    hoph_status grow_keys(uint64_t n) {
+        const uint64_t want = sort_capacity(n);
+        if (want <= keys_cap) return HOPH_OK;
+        if (keys) (void)hipFree(keys);
+        keys = nullptr;
+        keys_cap = 0;
+        if (hipMalloc(&keys, want * sizeof(uint64_t)) != hipSuccess) return fail(HOPH_E_NOMEM, "key buffer");
+        keys_cap = want;
+        return HOPH_OK;
+    }
+};
+
+inline uint32_t round4(uint32_t x) { return (x + 3u) & ~3u; }
+
+bool valid_ratio_T(hoph_ratio T);
+bool valid_ratio_eps(hoph_ratio e);
+hoph_status check_results(const hoph_results *r, uint32_t n_q);
+
+enum class QueryKind { GOPH, HOPH, OPH_FULL };
+
+uint32_t pick_q_per_wave(uint64_t n_sets, uint32_t n_q);
+hoph_status copy_counters(Workspace &ws, hipStream_t st);
+hoph_status write_output(Workspace &ws, uint64_t accepted, uint32_t n_q, hoph_results *res, hipStream_t s);
+
+}  // namespace hoph
+
+struct hoph_index {
+    int device = 0;
+    hoph_sketch_params params{};
+    hoph::LayoutInfo lay;
+    uint32_t kpad = 0;
+    uint64_t n = 0;
+    uint64_t capacity = 0;        // slab capacity in sets, a multiple of 64
+    uint64_t max_sets = 0;        // the capacity the caller asked for
+    uint32_t *slab = nullptr;
+    hoph::Workspace ws;
+    std::mutex mu;
+};
+
+namespace hoph {
+// GOPH / HOPH / plain-OPH query through the index's own workspace (host-synchronised).
+hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t n_q, const hoph_query_params *qp,
+                      hoph_results *res, void *stream, QueryKind kind);
+}  // namespace hoph

@@ -1,0 +1,165 @@
+"""Batched execution (hoph_plan_*): persistent kernels that read the batch
+size from device memory, one captured hipGraph replayed per batch, tile shapes
+tuned on the first batch.  Results must equal the host-synchronised path
+(sketch_oph + query_goph/query_hoph) and the oracle bit for bit, for every
+batch size, with and without the graph, tuned or not, and across graph replays
+interleaved with other device work."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import paper_1805_11254_amd as H
+from oracle import scale
+import workloads as W
+from tests.hoph_testutil import dev_csr, params_of, to_u32
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(coll: W.Collection, rows):
+    return W.csr_from_lists([coll.set(i) for i in rows])
+
+
+def _host_path(w, p, idx, qc):
+    ids, offs = dev_csr(qc)
+    qsig = H.sketch_oph(p, ids, offs)
+    fn = H.query_goph if w.goph else H.query_hoph
+    o, i = fn(idx, qsig, T=w.T, eps=w.eps)
+    return o.cpu().numpy().tolist(), to_u32(i).tolist(), to_u32(qsig)
+
+
+def _plan_path(plan, qc):
+    ids, offs = dev_csr(qc)
+    plan.run(ids, offs)
+    o, i = plan.results()
+    return o.cpu().numpy().tolist(), to_u32(i).tolist()
+
+
+@pytest.fixture(scope="module")
+def bovw():
+    w = W.hoph_bovw(n=30_011, n_q=300, seed=31, planted_frac=0.05)
+    p = params_of(w)
+    ids, offs = dev_csr(w.collection)
+    sig = H.sketch_oph(p, ids, offs)
+    idx = H.Index(p, sig)
+    # query sets of very uneven sizes: the workload's queries plus long and short ones
+    rng = np.random.default_rng(4)
+    extra = [rng.choice(1 << 20, size=n, replace=False).astype(np.uint32) for n in (10, 12, 9000, 10_000, 3)]
+    qsets = [w.queries.set(i) for i in range(w.queries.n)] + extra
+    qc = W.csr_from_lists(qsets)
+    yield w, p, idx, sig, qc
+    idx.free()
+
+
+@pytest.mark.parametrize("use_graph,tune", [(False, False), (True, False), (True, True)])
+def test_plan_equals_host_path_and_oracle(bovw, use_graph, tune):
+    print(f"[case] plan graph={use_graph} tune={tune}", flush=True)
+    w, p, idx, sig, qc = bovw
+    plan = H.Plan(idx, p, T=w.T, eps=w.eps, max_queries=256, max_query_ids=400_000, max_results=1 << 16,
+                  use_graph=use_graph, tune=tune)
+    sig_h = to_u32(sig)
+    for rows in ([0], list(range(7)), list(range(150, 278)), list(range(299, 305)), [303, 304, 1, 2],
+                 list(range(256))):
+        sub = _batch(qc, rows)
+        want_o, want_i, qsig_h = _host_path(w, p, idx, sub)
+        got_o, got_i = _plan_path(plan, sub)
+        assert (got_o, got_i) == (want_o, want_i), rows[:5]
+        oo, oi, _ = scale.query(sig_h, qsig_h, goph=False, kp=w.kp, T=Fraction(*w.T), eps=Fraction(*w.eps),
+                                ra=w.ra, rb=w.rb)
+        assert (oo.tolist(), oi.tolist()) == (want_o, want_i)
+    info = plan.info()
+    assert info["graph"] == (1 if use_graph else 0) and info["tuned"] == (1 if tune else 0)
+    assert info["fallbacks"] == 0
+    plan.free()
+
+
+def test_graph_replays_interleaved_with_eager_work(bovw):
+    import torch
+    print("[case] graph replays", flush=True)
+    w, p, idx, sig, qc = bovw
+    eager = H.Plan(idx, p, T=w.T, eps=w.eps, max_queries=128, max_query_ids=400_000, max_results=1 << 15,
+                   use_graph=False)
+    graph = H.Plan(idx, p, T=w.T, eps=w.eps, max_queries=128, max_query_ids=400_000, max_results=1 << 15,
+                   use_graph=True)
+    rng = np.random.default_rng(8)
+    for rep in range(6):
+        rows = sorted(rng.choice(qc.n, size=int(rng.integers(1, 128)), replace=False).tolist())
+        sub = _batch(qc, rows)
+        want = _plan_path(eager, sub)
+        # unrelated device work between replays
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()
+        torch.cuda.synchronize()
+        got = _plan_path(graph, sub)
+        assert got == want, rep
+    assert graph.info()["graph"] == 1
+    eager.free()
+    graph.free()
+
+
+def test_plan_capacity_and_fallbacks(bovw):
+    print("[case] plan fallbacks", flush=True)
+    w, p, idx, sig, qc = bovw
+    sub = _batch(qc, list(range(40)))
+    want_o, want_i, _ = _host_path(w, p, idx, sub)
+    need = len(want_i)
+    assert need >= 2
+    small = H.Plan(idx, p, T=w.T, eps=w.eps, max_queries=64, max_query_ids=100_000, max_results=need - 1)
+    ids, offs = dev_csr(sub)
+    small.run(ids, offs)
+    with pytest.raises(H.HophError) as ei:
+        small.results()
+    assert ei.value.status == H.HOPH_E_CAPACITY and ei.value.needed == need
+    # a batch larger than the plan is refused before any launch
+    with pytest.raises(H.HophError) as ei:
+        big = _batch(qc, list(range(65)))
+        bi, bo = dev_csr(big)
+        small.run(bi, bo)
+    assert ei.value.status == H.HOPH_E_CAPACITY
+    small.free()
+
+
+def test_plan_query_with_many_results_falls_back_exactly():
+    """Near-identical collection: one query accepts more than 4096 sets, which
+    the per-query LDS sort does not take; the plan redoes the batch exactly."""
+    print("[case] plan big segment", flush=True)
+    rng = np.random.default_rng(6)
+    base = rng.choice(1 << 20, size=200, replace=False)
+    sets = []
+    for i in range(9000):
+        s = base.copy()
+        s[rng.integers(0, 200, size=3)] = rng.integers(0, 1 << 20, size=3)
+        sets.append(s)
+    coll = W.csr_from_lists(sets)
+    w = W.Workload("same", coll, coll, 1 << 20, W.HASH_MODP31, W.LAYOUT_HIER, 256, 32, ha=1234567, hb=89)
+    p = params_of(w)
+    ids, offs = dev_csr(coll)
+    sig = H.sketch_oph(p, ids, offs)
+    idx = H.Index(p, sig)
+    q = _batch(coll, [0, 1, 2])
+    want_o, want_i, _ = _host_path(w, p, idx, q)
+    assert max(np.diff(want_o)) > 4096
+    plan = H.Plan(idx, p, T=w.T, eps=w.eps, max_queries=4, max_query_ids=10_000, max_results=1 << 16)
+    got = _plan_path(plan, q)
+    assert got == (want_o, want_i)
+    assert plan.info()["fallbacks"] == 1
+    plan.free()
+    idx.free()
+
+
+def test_goph_plan_matches_oracle():
+    print("[case] goph plan", flush=True)
+    w = W.tiny_goph()
+    p = params_of(w)
+    ids, offs = dev_csr(w.collection)
+    sig = H.sketch_oph(p, ids, offs)
+    idx = H.Index(p, sig)
+    plan = H.Plan(idx, p, T=w.T, eps=w.eps, max_queries=16, max_query_ids=20_000, max_results=4096, tune=True)
+    got_o, got_i = _plan_path(plan, w.queries)
+    want_o, want_i, qsig_h = _host_path(w, p, idx, w.queries)
+    assert (got_o, got_i) == (want_o, want_i)
+    oo, oi, _ = scale.query(to_u32(sig), qsig_h, goph=True, kp=w.kp, T=Fraction(*w.T), eps=Fraction(*w.eps))
+    assert (oo.tolist(), oi.tolist()) == (want_o, want_i)
+    plan.free()
+    idx.free()
