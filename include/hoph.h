@@ -246,6 +246,72 @@ hoph_status hoph_plan_results(hoph_plan *plan, const uint64_t **d_offsets,
 hoph_status hoph_plan_get_info(const hoph_plan *plan, hoph_plan_info *info);
 void hoph_plan_free(hoph_plan *plan);
 
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of single-set queries                        */
+/* ------------------------------------------------------------------------ */
+
+/* A server keeps an index resident and answers single query sets submitted at
+   any time.  Each of `slots` workers owns a plan and a stream: a free worker takes
+   the waiting requests in arrival order while they fit its batch (queries and
+   ids: the memory each slot reserves), runs them as one batch, and hands every
+   request its own ascending result list; batches of different workers overlap on
+   the device.  A request's result does not depend on the batch it rode in. */
+typedef struct hoph_server hoph_server;
+
+typedef struct {
+    uint32_t kind;                /* 0: GOPH, 1: HOPH                                          */
+    uint32_t slots;               /* concurrent batches (>= 1)                                  */
+    uint32_t max_batch_queries;   /* requests per batch                                         */
+    uint32_t use_graph;           /* replay a captured graph per batch                          */
+    uint64_t max_batch_ids;       /* ids per batch; a request larger than this is refused       */
+    uint64_t max_batch_results;   /* accepted pairs per batch                                   */
+    uint64_t device_mem_budget;   /* bytes all slots may reserve (0: no limit); slots are
+                                     dropped until the reservation fits, at least one stays    */
+    uint32_t tune;                /* tune tile shapes on each slot's first batch               */
+    uint32_t reserved;
+} hoph_server_config;
+
+typedef struct {
+    uint64_t submitted, completed, rejected, batches, fallbacks, inserted_sets;
+    double mean_ms, p50_ms, p99_ms, max_ms;   /* submit -> result ready, completed requests */
+    double mean_batch_queries;
+    double busy_s;                /* first submit to last completion                          */
+    uint32_t slots;               /* slots that fit the memory budget                         */
+    uint32_t reserved;
+    uint64_t slot_bytes;          /* device bytes one slot reserves                            */
+} hoph_server_stats;
+
+hoph_status hoph_server_create(hoph_index *index, const hoph_sketch_params *params,
+                               const hoph_query_params *qp, const hoph_server_config *cfg,
+                               hoph_server **out);
+/* hoph_server_submit -- enqueue one query set (host ids, copied); *ticket identifies it.
+   HOPH_E_CAPACITY if the set alone exceeds a batch. */
+hoph_status hoph_server_submit(hoph_server *srv, const uint32_t *h_ids, uint64_t n_ids,
+                               uint64_t *ticket);
+/* hoph_server_wait -- block until the request is answered; copy up to cap set ids to
+   h_out (ascending) and write the count to *n_out (HOPH_E_CAPACITY if cap is too
+   small; the request stays available).  Returns the request's status. */
+hoph_status hoph_server_wait(hoph_server *srv, uint64_t ticket, uint32_t *h_out, uint64_t cap,
+                             uint64_t *n_out);
+/* hoph_server_poll -- as wait without blocking: *done = 1 when answered, else 0. */
+hoph_status hoph_server_poll(hoph_server *srv, uint64_t ticket, int32_t *done, uint32_t *h_out,
+                             uint64_t cap, uint64_t *n_out);
+/* hoph_server_insert -- sketch n_sets host sets (CSR) and append them to the index
+   (ids continue the index); they are visible to batches dispatched after the call
+   returns.  HOPH_E_CAPACITY past the index capacity. */
+hoph_status hoph_server_insert(hoph_server *srv, const uint32_t *h_ids, const uint64_t *h_offsets,
+                               uint64_t n_sets);
+/* hoph_server_replay -- native load generator: submit request i (host CSR) at
+   arrival_s[i] seconds after the call, then wait for all.  With result_offsets
+   (n_requests + 1 entries) and result_ids (result_cap entries) the results are
+   returned in request order (HOPH_E_CAPACITY if result_cap is too small). */
+hoph_status hoph_server_replay(hoph_server *srv, const uint32_t *h_ids, const uint64_t *h_offsets,
+                               uint64_t n_requests, const double *arrival_s,
+                               uint64_t *result_offsets, uint32_t *result_ids, uint64_t result_cap);
+hoph_status hoph_server_stats_get(hoph_server *srv, hoph_server_stats *stats);
+hoph_status hoph_server_reset_stats(hoph_server *srv);
+void hoph_server_destroy(hoph_server *srv);
+
 /* hoph_sync -- synchronise hip_stream and report (then clear) the device error
    flags raised by earlier sketches on the current device. */
 hoph_status hoph_sync(void *hip_stream);

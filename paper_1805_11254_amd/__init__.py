@@ -65,6 +65,19 @@ class PlanInfoC(C.Structure):
                 ("tune_ms", C.c_float)]
 
 
+class ServerConfigC(C.Structure):
+    _fields_ = [("kind", u32), ("slots", u32), ("max_batch_queries", u32), ("use_graph", u32),
+                ("max_batch_ids", u64), ("max_batch_results", u64), ("device_mem_budget", u64), ("tune", u32),
+                ("reserved", u32)]
+
+
+class ServerStatsC(C.Structure):
+    _fields_ = [("submitted", u64), ("completed", u64), ("rejected", u64), ("batches", u64), ("fallbacks", u64),
+                ("inserted_sets", u64), ("mean_ms", C.c_double), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
+                ("max_ms", C.c_double), ("mean_batch_queries", C.c_double), ("busy_s", C.c_double),
+                ("slots", u32), ("reserved", u32), ("slot_bytes", u64)]
+
+
 # name -> (restype, argtypes); every symbol declared in include/hoph.h
 SIGNATURES = {
     "sketch_oph": (C.c_int, [C.POINTER(SketchParamsC), vp, vp, u64, vp, vp]),
@@ -94,6 +107,16 @@ SIGNATURES = {
     "hoph_plan_results": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(u64), vp]),
     "hoph_plan_get_info": (C.c_int, [vp, C.POINTER(PlanInfoC)]),
     "hoph_plan_free": (None, [vp]),
+    "hoph_server_create": (C.c_int, [vp, C.POINTER(SketchParamsC), C.POINTER(QueryParamsC),
+                                     C.POINTER(ServerConfigC), C.POINTER(vp)]),
+    "hoph_server_submit": (C.c_int, [vp, vp, u64, C.POINTER(u64)]),
+    "hoph_server_wait": (C.c_int, [vp, u64, vp, u64, C.POINTER(u64)]),
+    "hoph_server_poll": (C.c_int, [vp, u64, C.POINTER(i32), vp, u64, C.POINTER(u64)]),
+    "hoph_server_insert": (C.c_int, [vp, vp, vp, u64]),
+    "hoph_server_replay": (C.c_int, [vp, vp, vp, u64, vp, vp, vp, u64]),
+    "hoph_server_stats_get": (C.c_int, [vp, C.POINTER(ServerStatsC)]),
+    "hoph_server_reset_stats": (C.c_int, [vp]),
+    "hoph_server_destroy": (None, [vp]),
 }
 
 _lib = None
@@ -407,6 +430,89 @@ class Plan:
     def __del__(self):
         try:
             self.free()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server over a resident index (host query sets in,
+    host result lists out)."""
+
+    def __init__(self, index: Index, params: SketchParams, T=(4, 5), eps=(1, 10000), policy=EMPTY_JOINT,
+                 kind: Optional[int] = None, slots=2, max_batch_queries=1024, max_batch_ids=1 << 21,
+                 max_batch_results=1 << 18, device_mem_budget=0, use_graph=True, tune=False):
+        if kind is None:
+            kind = 0 if params.layout == LAYOUT_OPH else 1
+        self.index = index
+        self._params = params          # keeps a permutation table alive
+        self._h = vp()
+        pc = params.c()
+        qp = QueryParamsC(_ratio(T), _ratio(eps), policy, 0)
+        cfg = ServerConfigC(kind, slots, max_batch_queries, 1 if use_graph else 0, max_batch_ids,
+                            max_batch_results, device_mem_budget, 1 if tune else 0, 0)
+        _check(lib().hoph_server_create(index.handle, C.byref(pc), C.byref(qp), C.byref(cfg), C.byref(self._h)))
+
+    def submit(self, ids) -> int:
+        import numpy as np
+        a = np.ascontiguousarray(ids, dtype=np.uint32)
+        t = u64()
+        _check(lib().hoph_server_submit(self._h, a.ctypes.data_as(vp), a.size, C.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, cap: int = 1 << 20):
+        import numpy as np
+        out = np.empty(max(cap, 1), dtype=np.uint32)
+        n = u64()
+        _check(lib().hoph_server_wait(self._h, ticket, out.ctypes.data_as(vp), cap, C.byref(n)), int(n.value))
+        return out[:n.value].copy()
+
+    def poll(self, ticket: int, cap: int = 1 << 20):
+        import numpy as np
+        out = np.empty(max(cap, 1), dtype=np.uint32)
+        n, done = u64(), i32()
+        _check(lib().hoph_server_poll(self._h, ticket, C.byref(done), out.ctypes.data_as(vp), cap, C.byref(n)))
+        return out[:n.value].copy() if done.value else None
+
+    def insert(self, ids, offsets):
+        import numpy as np
+        i = np.ascontiguousarray(ids, dtype=np.uint32)
+        o = np.ascontiguousarray(offsets, dtype=np.uint64)
+        _check(lib().hoph_server_insert(self._h, i.ctypes.data_as(vp), o.ctypes.data_as(vp), len(o) - 1))
+
+    def replay(self, ids, offsets, arrival_s, keep_results=False, result_cap=None):
+        """Submit request i at arrival_s[i] seconds (native driver), wait for all."""
+        import numpy as np
+        i = np.ascontiguousarray(ids, dtype=np.uint32)
+        o = np.ascontiguousarray(offsets, dtype=np.uint64)
+        t = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        n = len(o) - 1
+        if not keep_results:
+            _check(lib().hoph_server_replay(self._h, i.ctypes.data_as(vp), o.ctypes.data_as(vp), n,
+                                            t.ctypes.data_as(vp), None, None, 0))
+            return None
+        cap = result_cap if result_cap is not None else 64 * max(n, 1)
+        ro = np.zeros(n + 1, dtype=np.uint64)
+        ri = np.zeros(max(cap, 1), dtype=np.uint32)
+        _check(lib().hoph_server_replay(self._h, i.ctypes.data_as(vp), o.ctypes.data_as(vp), n,
+                                        t.ctypes.data_as(vp), ro.ctypes.data_as(vp), ri.ctypes.data_as(vp), cap))
+        return ro, ri[:int(ro[-1])]
+
+    def stats(self) -> dict:
+        s = ServerStatsC()
+        _check(lib().hoph_server_stats_get(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerStatsC._fields_ if f != "reserved"}
+
+    def reset_stats(self):
+        _check(lib().hoph_server_reset_stats(self._h))
+
+    def close(self):
+        if self._h:
+            lib().hoph_server_destroy(self._h)
+            self._h = vp()
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass
 

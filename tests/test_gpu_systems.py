@@ -163,3 +163,96 @@ def test_goph_plan_matches_oracle():
     assert (oo.tolist(), oi.tolist()) == (want_o, want_i)
     plan.free()
     idx.free()
+
+
+# ---------------------------------------------------------------------------
+# Serving loop
+# ---------------------------------------------------------------------------
+def _host_lists(w, p, idx, qc):
+    o, i, _ = _host_path(w, p, idx, qc)
+    return [i[o[j]:o[j + 1]] for j in range(len(o) - 1)]
+
+
+def test_server_results_same_alone_and_in_the_mix(bovw):
+    print("[case] server alone vs mix", flush=True)
+    w, p, idx, sig, qc = bovw
+    srv = H.Server(idx, p, T=w.T, eps=w.eps, slots=3, max_batch_queries=64, max_batch_ids=200_000,
+                   max_batch_results=1 << 15)
+    rows = list(range(0, 300, 3)) + [300, 301, 302, 303, 304]
+    sub = _batch(qc, rows)
+    want = _host_lists(w, p, idx, sub)
+    # alone: one request in flight at a time
+    alone = []
+    for j in range(sub.n):
+        t = srv.submit(sub.set(j))
+        alone.append(srv.wait(t).tolist())
+    st = srv.stats()
+    assert st["completed"] == sub.n and st["mean_batch_queries"] == 1.0
+    # in the mix: all requests arrive within a few hundred microseconds
+    srv.reset_stats()
+    arrivals = np.sort(np.random.default_rng(1).uniform(0, 3e-4, size=sub.n))
+    ro, ri = srv.replay(sub.ids, sub.offsets, arrivals, keep_results=True)
+    mix = [ri[ro[j]:ro[j + 1]].tolist() for j in range(sub.n)]
+    st = srv.stats()
+    assert st["completed"] == sub.n and st["mean_batch_queries"] > 1.0, st
+    assert alone == want
+    assert mix == want
+    assert st["p99_ms"] >= st["p50_ms"] > 0
+    srv.close()
+
+
+def test_server_online_inserts_are_visible_and_exact():
+    print("[case] server inserts", flush=True)
+    w = W.hoph_bovw(n=8_000, n_q=20, seed=41, planted_frac=0.01)
+    p = params_of(w)
+    ids, offs = dev_csr(w.collection)
+    sig = H.sketch_oph(p, ids, offs)
+    idx = H.Index(p, sig, capacity=w.collection.n + 500)
+    srv = H.Server(idx, p, T=w.T, eps=w.eps, slots=2, max_batch_queries=32, max_batch_ids=100_000,
+                   max_batch_results=1 << 14)
+    # new near-duplicates of query 0
+    Q0 = np.unique(w.queries.set(0))
+    rng = np.random.default_rng(2)
+    new_sets = [np.sort(np.concatenate([Q0[:-2], rng.integers(0, 1 << 20, size=2).astype(np.uint32)]))
+                for _ in range(5)] + [rng.integers(0, 1 << 20, size=300).astype(np.uint32) for _ in range(40)]
+    before = srv.wait(srv.submit(w.queries.set(0))).tolist()
+    new = W.csr_from_lists(new_sets)
+    srv.insert(new.ids, new.offsets)
+    assert len(idx) == w.collection.n + len(new_sets)
+    after = srv.wait(srv.submit(w.queries.set(0))).tolist()
+    added = [x for x in after if x >= w.collection.n]
+    assert before == [x for x in after if x < w.collection.n]
+    assert added == list(range(w.collection.n, w.collection.n + 5))
+    # the whole query batch against the grown index, through the host path
+    want = _host_lists(w, p, idx, w.queries)
+    ro, ri = srv.replay(w.queries.ids, w.queries.offsets, np.zeros(w.queries.n), keep_results=True)
+    assert [ri[ro[j]:ro[j + 1]].tolist() for j in range(w.queries.n)] == want
+    assert srv.stats()["inserted_sets"] == len(new_sets)
+    # past the index capacity
+    big = W.csr_from_lists([rng.integers(0, 1 << 20, size=50).astype(np.uint32) for _ in range(600)])
+    with pytest.raises(H.HophError) as ei:
+        srv.insert(big.ids, big.offsets)
+    assert ei.value.status == H.HOPH_E_CAPACITY
+    srv.close()
+    idx.free()
+
+
+def test_server_admission_by_memory(bovw):
+    print("[case] server admission", flush=True)
+    w, p, idx, sig, qc = bovw
+    one = H.Server(idx, p, T=w.T, eps=w.eps, slots=4, max_batch_queries=16, max_batch_ids=20_000,
+                   max_batch_results=4096, device_mem_budget=1)
+    st = one.stats()
+    assert st["slots"] == 1 and st["slot_bytes"] > 0
+    # a query set larger than a batch is refused, the server keeps serving
+    with pytest.raises(H.HophError) as ei:
+        one.submit(np.arange(20_001, dtype=np.uint32))
+    assert ei.value.status == H.HOPH_E_CAPACITY
+    r = one.wait(one.submit(qc.set(0))).tolist()
+    assert r == _host_lists(w, p, idx, _batch(qc, [0]))[0]
+    assert one.stats()["rejected"] == 1
+    one.close()
+    two = H.Server(idx, p, T=w.T, eps=w.eps, slots=4, max_batch_queries=16, max_batch_ids=20_000,
+                   max_batch_results=4096, device_mem_budget=2 * st["slot_bytes"] + 1)
+    assert two.stats()["slots"] == 2
+    two.close()
