@@ -83,13 +83,26 @@ typedef struct {
     const uint32_t *d_perm;   /* TABLE: device array of universe entries, a bijection    */
 } hoph_sketch_params;
 
+/* How the coarse pass compares the first coarse_depth groups of every pair.
+   Results are identical either way; only the work differs. */
+enum {
+    HOPH_COARSE_CODES = 0,    /* an 8-bit code per bin, EMPTY kept distinct (the "smallest
+                                 possible representation" of Sec. 3.2 narrowed further):
+                                 codes never under-count matched bins, so a pair is dropped
+                                 only where the full comparison rejects it too; every other
+                                 pair is re-checked on the 32-bit words (default)          */
+    HOPH_COARSE_WORDS = 1     /* the full 32-bit words, accepting and rejecting            */
+};
+
 typedef struct {
     hoph_ratio T;             /* similarity threshold, 0 < T <= 1                        */
     hoph_ratio eps;           /* error tolerance of the small-probability event, 0 <= eps < 1 */
     uint32_t empty_policy;    /* HOPH_EMPTY_*                                            */
     uint32_t coarse_depth;    /* 0 = let the library choose; else groups scanned for every
                                  pair before survivors move to the per-pair pass (a tuning
-                                 knob: results do not depend on it)                      */
+                                 knob: results do not depend on it; at most 4 with codes) */
+    uint32_t coarse_filter;   /* HOPH_COARSE_*                                           */
+    uint32_t reserved;        /* set to 0                                                */
 } hoph_query_params;
 
 /* Accepted pairs as CSR: for query i, set ids d_set_ids[d_offsets[i] .. d_offsets[i+1]),
@@ -107,8 +120,8 @@ typedef struct hoph_index hoph_index;   /* opaque, owned by the library */
  * sketch_oph -- OPH / HOPH signatures of n_sets sets (Sec. 3.2, Sec. 4.1).
  * d_sigs: n_sets * k uint32, row-major (set i at d_sigs + i * k).
  * Asynchronous.  Ids >= universe are skipped and raise HOPH_E_RANGE at the next
- * hoph_sync / query on the device; an empty set gets an all-EMPTY signature and
- * raises HOPH_E_INVAL there (Jaccard similarity is undefined for it).
+ * hoph_sync on the device; an empty set gets an all-EMPTY signature and raises
+ * HOPH_E_INVAL there (Jaccard similarity is undefined for it).
  * Host errors: HOPH_E_INVAL (bad params, null pointers with n_sets > 0).
  */
 hoph_status sketch_oph(const hoph_sketch_params *params, const uint32_t *d_ids,

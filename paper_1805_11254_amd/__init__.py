@@ -22,6 +22,7 @@ HOPH_E_NOMEM, HOPH_E_UNSUPPORTED, HOPH_E_DEVICE = -4, -5, -6
 HASH_TABLE, HASH_MODP31, HASH_MODP32P15 = 0, 1, 2
 LAYOUT_OPH, LAYOUT_HIER = 0, 1
 EMPTY_JOINT, EMPTY_LITERAL, EMPTY_EITHER = 0, 1, 2
+COARSE_CODES, COARSE_WORDS = 0, 1
 EMPTY = 0xFFFFFFFF
 
 u32, u64, i32, i64, vp = C.c_uint32, C.c_uint64, C.c_int32, C.c_int64, C.c_void_p
@@ -37,7 +38,8 @@ class SketchParamsC(C.Structure):
 
 
 class QueryParamsC(C.Structure):
-    _fields_ = [("T", Ratio), ("eps", Ratio), ("empty_policy", u32), ("coarse_depth", u32)]
+    _fields_ = [("T", Ratio), ("eps", Ratio), ("empty_policy", u32), ("coarse_depth", u32),
+                ("coarse_filter", u32), ("reserved", u32)]
 
 
 class ResultsC(C.Structure):
@@ -135,6 +137,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_1805_11254_amd.build`")
+        # torch's HIP runtime first: the library then binds to that copy
+        # (same soname) instead of loading a second runtime into the process
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
@@ -291,23 +296,23 @@ def _run_query(fn, handle, qsigs, qp: QueryParamsC, capacity, stream, device):
         return offsets, ids[:int(res.needed)]
 
 
-def _query(name, index: Index, qsigs, T, eps, policy, capacity, coarse_depth, stream):
+def _query(name, index: Index, qsigs, T, eps, policy, capacity, coarse_depth, stream, coarse=COARSE_CODES):
     import torch
     _need_cuda(qsigs, "qsigs", (torch.int32,))
-    qp = QueryParamsC(_ratio(T), _ratio(eps), policy, coarse_depth)
+    qp = QueryParamsC(_ratio(T), _ratio(eps), policy, coarse_depth, coarse, 0)
     return _run_query(getattr(lib(), name), index.handle, qsigs, qp, capacity, stream, qsigs.device)
 
 
 def query_goph(index: Index, qsigs, T=(4, 5), eps=(1, 10000), policy=EMPTY_JOINT, capacity=None,
-               coarse_depth=0, stream=None):
+               coarse_depth=0, stream=None, coarse=COARSE_CODES):
     """Alg. 1 over the index: (offsets int64[n_q+1], set ids int32[...])."""
-    return _query("query_goph", index, qsigs, T, eps, policy, capacity, coarse_depth, stream)
+    return _query("query_goph", index, qsigs, T, eps, policy, capacity, coarse_depth, stream, coarse)
 
 
 def query_hoph(index: Index, qsigs, T=(4, 5), eps=(1, 10000), policy=EMPTY_JOINT, capacity=None,
-               coarse_depth=0, stream=None):
+               coarse_depth=0, stream=None, coarse=COARSE_CODES):
     """Alg. 2 over the index: (offsets int64[n_q+1], set ids int32[...])."""
-    return _query("query_hoph", index, qsigs, T, eps, policy, capacity, coarse_depth, stream)
+    return _query("query_hoph", index, qsigs, T, eps, policy, capacity, coarse_depth, stream, coarse)
 
 
 def query_oph_full(index: Index, qsigs, T=(4, 5), policy=EMPTY_JOINT, capacity=None, stream=None):
@@ -385,14 +390,14 @@ class Plan:
 
     def __init__(self, index: Index, params: SketchParams, T=(4, 5), eps=(1, 10000), policy=EMPTY_JOINT,
                  kind: Optional[int] = None, max_queries=4096, max_query_ids=1 << 24, max_results=1 << 20,
-                 use_graph=True, tune=False, coarse_depth=0):
+                 use_graph=True, tune=False, coarse_depth=0, coarse=COARSE_CODES):
         if kind is None:
             kind = 0 if params.layout == LAYOUT_OPH else 1
         self.index = index          # keep the index alive
         self.kind = kind
         self._h = vp()
         pc = params.c()
-        qp = QueryParamsC(_ratio(T), _ratio(eps), policy, coarse_depth)
+        qp = QueryParamsC(_ratio(T), _ratio(eps), policy, coarse_depth, coarse, 0)
         cfg = PlanConfigC(kind, max_queries, max_query_ids, max_results, 1 if use_graph else 0, 1 if tune else 0)
         _check(lib().hoph_plan_create(index.handle, C.byref(pc), C.byref(qp), C.byref(cfg), C.byref(self._h)))
 
@@ -440,14 +445,14 @@ class Server:
 
     def __init__(self, index: Index, params: SketchParams, T=(4, 5), eps=(1, 10000), policy=EMPTY_JOINT,
                  kind: Optional[int] = None, slots=2, max_batch_queries=1024, max_batch_ids=1 << 21,
-                 max_batch_results=1 << 18, device_mem_budget=0, use_graph=True, tune=False):
+                 max_batch_results=1 << 18, device_mem_budget=0, use_graph=True, tune=False, coarse=COARSE_CODES):
         if kind is None:
             kind = 0 if params.layout == LAYOUT_OPH else 1
         self.index = index
         self._params = params          # keeps a permutation table alive
         self._h = vp()
         pc = params.c()
-        qp = QueryParamsC(_ratio(T), _ratio(eps), policy, 0)
+        qp = QueryParamsC(_ratio(T), _ratio(eps), policy, 0, coarse, 0)
         cfg = ServerConfigC(kind, slots, max_batch_queries, 1 if use_graph else 0, max_batch_ids,
                             max_batch_results, device_mem_budget, 1 if tune else 0, 0)
         _check(lib().hoph_server_create(index.handle, C.byref(pc), C.byref(qp), C.byref(cfg), C.byref(self._h)))
@@ -552,7 +557,7 @@ def decision_tables(params: SketchParams, T, eps, policy=EMPTY_JOINT, goph: Opti
     if goph is None:
         goph = params.layout == LAYOUT_OPH
     pc = params.c(perm_ptr=0)
-    qp = QueryParamsC(_ratio(T), _ratio(eps), policy, 0)
+    qp = QueryParamsC(_ratio(T), _ratio(eps), policy, 0, COARSE_CODES, 0)
     t = DecisionTablesC()
     _check(lib().hoph_build_decision_tables(C.byref(pc), C.byref(qp), 1 if goph else 0, C.byref(t)))
     L, kp = t.L, t.k_group

@@ -108,6 +108,7 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
     if (!valid_ratio_T(qp->T)) return fail(HOPH_E_INVAL, "T must be an exact ratio in (0, 1]");
     if (kind != QueryKind::OPH_FULL && !valid_ratio_eps(qp->eps)) return fail(HOPH_E_INVAL, "eps must be in [0, 1)");
     if (qp->empty_policy > HOPH_EMPTY_EITHER) return fail(HOPH_E_INVAL, "unknown empty policy");
+    if (qp->coarse_filter > HOPH_COARSE_WORDS) return fail(HOPH_E_INVAL, "unknown coarse filter");
     hoph_status st = check_results(res, n_q);
     if (st) return st;
     hoph_index *idx = const_cast<hoph_index *>(cidx);
@@ -124,6 +125,7 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
 
     ScanTab tab{};
     uint32_t depth = 0;
+    const bool use_codes = kind != QueryKind::OPH_FULL && qp->coarse_filter == HOPH_COARSE_CODES && idx->codes;
     if (kind != QueryKind::OPH_FULL) {
         hoph_decision_tables t;
         std::string err;
@@ -134,7 +136,7 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
         uint32_t g1 = lay.L;
         for (uint32_t l = 0; l < lay.L; ++l)
             if (t.rej[l] >= 0) { g1 = l + 1; break; }
-        const uint32_t maxd = std::min(max_depth_for_kpad(idx->kpad), lay.L);
+        const uint32_t maxd = use_codes ? idx->cg : std::min(max_depth_for_kpad(idx->kpad), lay.L);
         depth = qp->coarse_depth ? qp->coarse_depth : g1;
         depth = std::max<uint32_t>(1, std::min(depth, maxd));
     }
@@ -153,9 +155,20 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
     if (kind != QueryKind::OPH_FULL && n_q && idx->n) {
         st = ws.grow_qmasks((uint64_t)n_q * lay.L);
         if (st) return st;
-        HOPH_HIP(launch_query_masks(d_qsigs, n_q, nullptr, lay.k, lay.kp, lay.L, ws.qmasks, s), "query mask launch");
+        CodeThr thr{};
+        if (use_codes) {
+            st = ws.grow_qcodes(((uint64_t)n_q + 1) * idx->cg * code_rec_words(lay.kp));  // + a padding record
+            if (st) return st;
+            std::memcpy(thr.dthr, tab.dthr0, sizeof(thr.dthr));
+        }
+        HOPH_HIP(launch_query_masks(d_qsigs, n_q, nullptr, lay.k, lay.kp, lay.L, ws.qmasks,
+                                    use_codes ? ws.qcodes : nullptr, idx->cg, &thr, s),
+                 "query mask launch");
     }
     a.qmasks = ws.qmasks;
+    a.codes = use_codes ? idx->codes : nullptr;
+    a.qcodes = ws.qcodes;
+    a.cg = idx->cg;
 
     uint64_t accepted = 0;
     float pass_ms[2] = {0, 0};
@@ -304,19 +317,31 @@ hoph_status build_index(const hoph_sketch_params *params, const uint32_t *d_sigs
     idx->capacity = std::max<uint64_t>(64, (capacity + 63) / 64 * 64);
     idx->max_sets = capacity;
     const uint64_t words = idx->capacity * idx->kpad * idx->lay.L;
+    idx->cg = std::min<uint32_t>(kCodeGroups, idx->lay.L);
+    const uint64_t code_words_total = idx->capacity * idx->cg * code_words(idx->lay.kp);
+    auto release = [&] {
+        if (idx->slab) (void)hipFree(idx->slab);
+        if (idx->codes) (void)hipFree(idx->codes);
+        if (idx->codes) (void)hipFree(idx->codes);
+        idx->slab = nullptr;
+        idx->codes = nullptr;
+        idx->ws.release();
+    };
     if (hipMalloc(&idx->slab, words * sizeof(uint32_t)) != hipSuccess) return fail(HOPH_E_NOMEM, "index slabs");
+    if (hipMalloc(&idx->codes, code_words_total * sizeof(uint32_t)) != hipSuccess) {
+        release();
+        return fail(HOPH_E_NOMEM, "index code planes");
+    }
     st = idx->ws.init(std::max<uint64_t>(idx->capacity, 1u << 20), 1u << 16);
     if (st) {
-        (void)hipFree(idx->slab);
-        idx->ws.release();
+        release();
         return st;
     }
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     hipError_t e = launch_index_store(d_sigs, n_sets, 0, params->k, params->k_group, idx->lay.L, idx->kpad,
-                                      idx->capacity, idx->slab, s);
+                                      idx->capacity, idx->slab, idx->codes, idx->cg, s);
     if (e != hipSuccess) {
-        (void)hipFree(idx->slab);
-        idx->ws.release();
+        release();
         return hip_fail(e, "index store launch");
     }
     idx->n = n_sets;
@@ -334,7 +359,8 @@ hoph_status index_append(hoph_index *idx, const uint32_t *d_sigs, uint64_t n_new
         return fail(HOPH_E_CAPACITY, "index capacity " + std::to_string(idx->max_sets) + " exceeded");
     DeviceGuard dg(idx->device);
     HOPH_HIP(launch_index_store(d_sigs, n_new, idx->n, idx->params.k, idx->params.k_group, idx->lay.L, idx->kpad,
-                                idx->capacity, idx->slab, reinterpret_cast<hipStream_t>(hip_stream)),
+                                idx->capacity, idx->slab, idx->codes, idx->cg,
+                                reinterpret_cast<hipStream_t>(hip_stream)),
              "index store launch");
     idx->n += n_new;
     return HOPH_OK;
@@ -365,6 +391,7 @@ void hoph_index_free(hoph_index *idx) {
         DeviceGuard dg(idx->device);
         (void)hipDeviceSynchronize();
         if (idx->slab) (void)hipFree(idx->slab);
+        if (idx->codes) (void)hipFree(idx->codes);
         idx->ws.release();
     }
     delete idx;

@@ -18,6 +18,12 @@ constexpr uint64_t kP32 = 4294967311ull;        // 2^32 + 15, prime
 constexpr uint32_t kLutMax = 4096;              // region lookup entries
 constexpr uint32_t kTile = 64;                  // sets per index tile = one wavefront
 constexpr uint32_t kMaxDepth = 4;               // coarse groups kept in registers
+// Narrowed coarse pass: an 8-bit code per bin, stored as 8 bit-planes per
+// group (bit i of plane p = bit p of the code of bin i), so that one 32-bit
+// word holds one plane of 32 bins.  EMPTY has a code of its own.
+constexpr uint32_t kCodeBits = 8;
+constexpr uint32_t kCodeEmpty = 0xFFu;           // code of EMPTY; other bins map to [0, 254]
+constexpr uint32_t kCodeGroups = kMaxDepth;      // leading groups that carry codes
 
 // Device error bits (one 32-bit word per device).
 constexpr uint32_t kErrRange = 1u;              // an id >= universe, or a table value >= R
@@ -57,6 +63,10 @@ struct ScanTab {
     int64_t lambda;                 // rate scale: lcm(1..k') (JOINT, EITHER) or k' (LITERAL)
     int32_t macc0[HOPH_MAX_KGROUP + 1];   // first group, e < k': accept iff m >= macc0[e]
     int32_t mrej0[HOPH_MAX_KGROUP + 1];   // first group, e < k': reject iff m <= mrej0[e]
+    // First group on codes, by the query's empty count eq (JOINT, LITERAL):
+    // reject when the count of query-non-empty bins whose codes differ is
+    // >= dthr0[eq] (a bound that holds for every empty count the set may add).
+    int32_t dthr0[HOPH_MAX_KGROUP + 1];
     uint32_t L, kp, policy, pad;
 };
 
@@ -69,6 +79,27 @@ struct Survivor {
 // ---------------------------------------------------------------------------
 // Inline arithmetic shared by the kernels and the host self-test hook.
 // ---------------------------------------------------------------------------
+// 8-bit code of a stored bin value: EMPTY -> kCodeEmpty, any other value to
+// [0, 254] by a multiplicative mix (a bijection on 32-bit words) scaled into
+// 255 values.  Equal values have equal codes, so a count of equal codes never
+// falls below the count of equal values.
+__host__ __device__ inline uint32_t bin_code(uint32_t v) {
+    if (v == HOPH_EMPTY) return kCodeEmpty;
+    return (uint32_t)(((uint64_t)(v * 0x9E3779B1u) * 255u) >> 32);
+}
+
+// 32-bit words per plane (k' <= 32: one, else two) and words per (set, group).
+__host__ __device__ inline uint32_t code_plane_words(uint32_t kp) { return kp > 32 ? 2u : 1u; }
+__host__ __device__ inline uint32_t code_words(uint32_t kp) { return kCodeBits * code_plane_words(kp); }
+// A query's record per code group: the planes, then {non-empty mask low word,
+// high word, first-group threshold on differing non-empty bins, empty count}.
+__host__ __device__ inline uint32_t code_rec_words(uint32_t kp) { return code_words(kp) + 4u; }
+
+// First-group reject thresholds on codes by the query's empty count (ScanTab::dthr0).
+struct CodeThr {
+    int32_t dthr[HOPH_MAX_KGROUP + 1];
+};
+
 __host__ __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b) {
     return (uint64_t)(((unsigned __int128)a * b) >> 64);
 }
@@ -154,9 +185,11 @@ hipError_t launch_sketch_chunked(const SketchDesc &d, const uint32_t *ids, const
                                  const uint64_t *desc, uint64_t *prefix, uint32_t chunk, uint32_t max_sets,
                                  uint64_t max_ids, uint32_t *sigs, uint32_t *err_flag, uint32_t waves_per_cu,
                                  hipStream_t st);
+// Stores rows [first, first + n_new) into the slabs and, when codes is not
+// null, the code planes of the first cg groups (layout in k_index.hip).
 hipError_t launch_index_store(const uint32_t *sigs, uint64_t n_new, uint64_t first, uint32_t k,
                               uint32_t kp, uint32_t L, uint32_t kpad, uint64_t capacity,
-                              uint32_t *slab, hipStream_t st);
+                              uint32_t *slab, uint32_t *codes, uint32_t cg, hipStream_t st);
 hipError_t launch_pair_counts(const uint32_t *slab, uint64_t capacity, uint64_t n_sets, uint32_t kpad,
                               uint32_t kp, uint32_t L, uint32_t k, const uint32_t *qsigs, uint32_t n_q,
                               const uint32_t *pairs, uint64_t n_pairs, uint32_t policy, uint32_t *m,
@@ -169,6 +202,9 @@ struct ScanLaunch {
     uint32_t kpad, kp, L, k;
     const uint32_t *qsigs;      // row-major n_q x k
     const uint64_t *qmasks;     // n_q x L empty-bin masks of the queries
+    const uint32_t *codes;      // index code planes, or null: coarse pass on the 32-bit words
+    const uint32_t *qcodes;     // n_q x cg x code_rec_words(kp) query code records
+    uint32_t cg;                // groups with codes (index and queries)
     uint32_t q0, q1;            // query rows [q0, q1)
     uint32_t depth;             // coarse groups
     uint32_t q_per_wave;
@@ -180,8 +216,11 @@ struct ScanLaunch {
     const uint64_t *desc;       // nullable: desc[0] = n_q, desc[1] = n_sets, read on the device
     uint32_t waves_per_cu;      // persistent grid size with desc (0 = default)
 };
+// Empty-bin masks of every (query, group) and, when qcodes is not null, the code
+// records (code_rec_words each) of each query's first cg groups; thr is then required.
 hipError_t launch_query_masks(const uint32_t *qsigs, uint32_t n_q, const uint64_t *desc, uint32_t k, uint32_t kp,
-                              uint32_t L, uint64_t *out, hipStream_t st);
+                              uint32_t L, uint64_t *out, uint32_t *qcodes, uint32_t cg, const CodeThr *thr,
+                              hipStream_t st);
 hipError_t launch_scan_coarse(const ScanLaunch &a, const ScanTab &tab, hipStream_t st);
 hipError_t launch_scan_fine(const ScanLaunch &a, const ScanTab &tab, hipStream_t st);
 hipError_t launch_oph_full(const ScanLaunch &a, hoph_ratio T, uint32_t policy, hipStream_t st);

@@ -340,6 +340,22 @@ void to_scan_tab(const hoph_decision_tables &t, ScanTab &s) {
         s.macc0[e] = (int32_t)std::max<i128>(0, std::min<i128>(65, a));
         s.mrej0[e] = (int32_t)std::max<i128>(-1, std::min<i128>(64, r));
     }
+    // First group on codes: a query with eq empty bins meets sets whose empty
+    // count e is <= eq (JOINT; e == kp only when eq == kp) or 0 (LITERAL).  The
+    // pair is rejected when m <= thr for the smallest reject threshold over
+    // those e; with the code count m = (kp - eq) - dn (dn = query-non-empty bins
+    // whose codes differ) that is dn >= (kp - eq) - thr.  thr < 0: never.
+    const int32_t kp = (int32_t)t.k_group;
+    for (int32_t eq = 0; eq <= kp; ++eq) {
+        int32_t thr = -1;
+        if (t.empty_policy == HOPH_EMPTY_LITERAL) {
+            thr = s.mrej0[0];
+        } else if (t.empty_policy == HOPH_EMPTY_JOINT && eq < kp) {
+            thr = s.mrej0[0];
+            for (int32_t e = 1; e <= eq; ++e) thr = std::min(thr, s.mrej0[e]);
+        }
+        s.dthr0[eq] = thr < 0 ? kp + 1 : (kp - eq) - thr;
+    }
 }
 
 }  // namespace hoph

@@ -7,6 +7,12 @@
 // so that a wavefront reads a tile's group with fully coalesced 16-byte loads,
 // one set per lane.  kpad = k' rounded up to 4; pad words hold EMPTY and are
 // never compared.
+//
+// Code planes of the first cg groups (8-bit bin codes, see bin_code), PW =
+// code_words(k') words per (set, group), plane p of bins [32 w, 32 w + 32) at
+// word p * W + w (W = PW / 8):
+//   codes[((g * (capacity / 64) + s / 64) * 64 + s % 64) * PW + p * W + w]
+// so that a wavefront reads a tile's planes as one contiguous 64 * PW-word run.
 #include "hoph_internal.h"
 
 namespace hoph {
@@ -21,25 +27,98 @@ __global__ __launch_bounds__(kThreads) void fill_u64_kernel(uint64_t *p, uint64_
 }
 
 // 16-byte path: k' and k multiples of 4, source 16-byte aligned.
-// thread -> (group g, tile t, quad qd, lane): writes one 16-byte chunk.
+// One thread per set writes the whole row group by group, so that each
+// group's contiguous piece of a signature row is read by one wavefront (one
+// XCD's L2) and each 16-byte store instruction of a wavefront covers 1 KB of
+// the tile contiguously.  NQ = k' / 4 when known at compile time, else 0.
+// Code planes of NQ * 4 bins held as NQ uint4, written as PW contiguous words.
+template <int NQ>
+__device__ __forceinline__ void store_code_planes(const uint4 *v, uint32_t *__restrict__ dst) {
+    constexpr int W = NQ > 8 ? 2 : 1;
+    uint32_t pl[kCodeBits * W];
+#pragma unroll
+    for (int j = 0; j < (int)kCodeBits * W; ++j) pl[j] = 0;
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+        const uint32_t vals[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int i = 4 * u + t;
+            const uint32_t c = bin_code(vals[t]);
+#pragma unroll
+            for (int p = 0; p < (int)kCodeBits; ++p) pl[p * W + (i >> 5)] |= ((c >> p) & 1u) << (i & 31);
+        }
+    }
+    uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+#pragma unroll
+    for (int j = 0; j < 2 * W; ++j) d4[j] = make_uint4(pl[4 * j], pl[4 * j + 1], pl[4 * j + 2], pl[4 * j + 3]);
+}
+
+template <int NQ>
 __global__ __launch_bounds__(kThreads) void index_store_vec(const uint32_t *__restrict__ sigs, uint64_t n_new,
                                                            uint64_t first, uint32_t k, uint32_t kp, uint32_t L,
                                                            uint64_t capacity, uint64_t tile0, uint64_t ntiles,
-                                                           uint32_t *__restrict__ slab) {
-    const uint32_t nq = kp / 4;
-    const uint64_t total = (uint64_t)L * ntiles * nq * 64;
+                                                           uint32_t *__restrict__ slab, uint32_t *__restrict__ codes,
+                                                           uint32_t cg) {
+    const uint32_t nq = NQ ? NQ : kp / 4;
+    const uint64_t total = ntiles * 64;
     for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < total; i += (uint64_t)gridDim.x * kThreads) {
-        const uint32_t lane = (uint32_t)(i & 63);
-        uint64_t rest = i >> 6;
-        const uint32_t qd = (uint32_t)(rest % nq);
-        rest /= nq;
-        const uint64_t t = tile0 + rest % ntiles;
-        const uint32_t g = (uint32_t)(rest / ntiles);
-        const uint64_t s = t * 64 + lane;
+        const uint64_t s = tile0 * 64 + i;
         if (s < first || s >= first + n_new) continue;
-        const uint4 v = *reinterpret_cast<const uint4 *>(sigs + (s - first) * k + (uint64_t)g * kp + qd * 4);
-        uint4 *dst = reinterpret_cast<uint4 *>(slab + (uint64_t)g * capacity * kp + t * kp * 64 + qd * 256 + lane * 4);
-        *dst = v;
+        const uint64_t t = s >> 6;
+        const uint32_t lane = (uint32_t)(s & 63);
+        const uint4 *src = reinterpret_cast<const uint4 *>(sigs + (s - first) * k);
+        for (uint32_t g = 0; g < L; ++g) {
+            uint4 *dst = reinterpret_cast<uint4 *>(slab + (uint64_t)g * capacity * kp + t * kp * 64) + lane;
+            if constexpr (NQ > 0) {
+                uint4 v[NQ];
+#pragma unroll
+                for (int u = 0; u < NQ; ++u) v[u] = src[g * NQ + u];
+#pragma unroll
+                for (int u = 0; u < NQ; ++u) dst[u * 64] = v[u];
+                if (codes && g < cg) {
+                    constexpr uint32_t PW = kCodeBits * (NQ > 8 ? 2 : 1);
+                    store_code_planes<NQ>(v, codes + (((uint64_t)g * (capacity / 64) + t) * 64 + lane) * PW);
+                }
+            } else {
+                for (uint32_t u = 0; u < nq; ++u) dst[u * 64] = src[g * nq + u];
+            }
+        }
+    }
+}
+
+// Code planes for any k' (used where the 16-byte path does not write them):
+// one thread per (set, group < cg).
+__global__ __launch_bounds__(kThreads) void index_codes_kernel(const uint32_t *__restrict__ sigs, uint64_t n_new,
+                                                              uint64_t first, uint32_t k, uint32_t kp,
+                                                              uint64_t capacity, uint32_t cg,
+                                                              uint32_t *__restrict__ codes) {
+    const uint32_t W = code_plane_words(kp), PW = code_words(kp);
+    const uint64_t total = n_new * cg;
+    for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < total; i += (uint64_t)gridDim.x * kThreads) {
+        const uint64_t r = i / cg;
+        const uint32_t g = (uint32_t)(i % cg);
+        const uint64_t s = first + r;
+        const uint32_t *row = sigs + r * k + (uint64_t)g * kp;
+        uint32_t lo[kCodeBits], hi[kCodeBits];
+#pragma unroll
+        for (int p = 0; p < (int)kCodeBits; ++p) lo[p] = hi[p] = 0;
+        for (uint32_t b = 0; b < kp; ++b) {
+            const uint32_t c = bin_code(row[b]), bit = b & 31;
+            if (b < 32) {
+#pragma unroll
+                for (int p = 0; p < (int)kCodeBits; ++p) lo[p] |= ((c >> p) & 1u) << bit;
+            } else {
+#pragma unroll
+                for (int p = 0; p < (int)kCodeBits; ++p) hi[p] |= ((c >> p) & 1u) << bit;
+            }
+        }
+        uint32_t *dst = codes + (((uint64_t)g * (capacity / 64) + (s >> 6)) * 64 + (s & 63)) * PW;
+#pragma unroll
+        for (int p = 0; p < (int)kCodeBits; ++p) {
+            dst[p * W] = lo[p];
+            if (W == 2) dst[p * W + 1] = hi[p];
+        }
     }
 }
 
@@ -138,21 +217,40 @@ hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t value, hipStream_t 
 }
 
 hipError_t launch_index_store(const uint32_t *sigs, uint64_t n_new, uint64_t first, uint32_t k, uint32_t kp,
-                              uint32_t L, uint32_t kpad, uint64_t capacity, uint32_t *slab, hipStream_t st) {
+                              uint32_t L, uint32_t kpad, uint64_t capacity, uint32_t *slab, uint32_t *codes,
+                              uint32_t cg, hipStream_t st) {
     if (n_new == 0) return hipSuccess;
     const uint64_t tile0 = first / 64, tile1 = (first + n_new - 1) / 64;
     const uint64_t ntiles = tile1 - tile0 + 1;
     const bool vec = (kp % 4 == 0) && (k % 4 == 0) && ((reinterpret_cast<uintptr_t>(sigs) & 15u) == 0);
     if (vec) {
-        const uint64_t total = (uint64_t)L * ntiles * (kp / 4) * 64;
-        hipLaunchKernelGGL(index_store_vec, dim3(grid_for(total, kThreads)), dim3(kThreads), 0, st, sigs, n_new,
-                           first, k, kp, L, capacity, tile0, ntiles, slab);
+        const dim3 grid(grid_for(ntiles * 64, kThreads)), block(kThreads);
+        if (kp == 16)
+            hipLaunchKernelGGL(index_store_vec<4>, grid, block, 0, st, sigs, n_new, first, k, kp, L, capacity, tile0,
+                               ntiles, slab, codes, cg);
+        else if (kp == 32)
+            hipLaunchKernelGGL(index_store_vec<8>, grid, block, 0, st, sigs, n_new, first, k, kp, L, capacity, tile0,
+                               ntiles, slab, codes, cg);
+        else if (kp == 64)
+            hipLaunchKernelGGL(index_store_vec<16>, grid, block, 0, st, sigs, n_new, first, k, kp, L, capacity, tile0,
+                               ntiles, slab, codes, cg);
+        else
+            hipLaunchKernelGGL(index_store_vec<0>, grid, block, 0, st, sigs, n_new, first, k, kp, L, capacity, tile0,
+                               ntiles, slab, nullptr, 0u);
     } else {
         const uint64_t total = (uint64_t)L * ntiles * kpad * 64;
         hipLaunchKernelGGL(index_store_word, dim3(grid_for(total, kThreads)), dim3(kThreads), 0, st, sigs, n_new,
                            first, k, kp, kpad, L, capacity, tile0, ntiles, slab);
     }
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const bool fused = vec && (kp == 16 || kp == 32 || kp == 64);
+    if (codes && cg && !fused) {
+        hipLaunchKernelGGL(index_codes_kernel, dim3(grid_for(n_new * cg, kThreads)), dim3(kThreads), 0, st, sigs,
+                           n_new, first, k, kp, capacity, cg, codes);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 hipError_t launch_pair_counts(const uint32_t *slab, uint64_t capacity, uint64_t n_sets, uint32_t kpad, uint32_t kp,

@@ -28,7 +28,7 @@ constexpr int kWaves = kThreads / 64;
 
 struct CoarseArgs {
     uint64_t capacity, n_sets, surv_cap, keys_cap;
-    uint32_t k, kp, kpad, L, q0, q1, q_per_wave, policy, depth, pad;
+    uint32_t k, kp, kpad, L, q0, q1, q_per_wave, policy, depth, cg;
 };
 
 __device__ __forceinline__ uint32_t wave_id_in_block() {
@@ -59,18 +59,212 @@ __device__ __forceinline__ int64_t group_rho(uint32_t eq, uint32_t ej, uint32_t 
     return (int64_t)m * dmul[e];
 }
 
-// Empty-bin mask of every (query, group): bit i set when bin i of the group is EMPTY.
+// Empty-bin mask of every (query, group): bit i set when bin i of the group is
+// EMPTY; for the first cg groups also the query's code record: the planes (same
+// word order as the index's: plane p of bins [32 w, 32 w + 32) at p * W + w),
+// the non-empty mask, the first group's reject threshold and the empty count.
 __global__ __launch_bounds__(kThreads) void query_masks_kernel(const uint32_t *__restrict__ qsigs, uint32_t n_q_arg,
                                                               const uint64_t *__restrict__ desc, uint32_t k,
-                                                              uint32_t kp, uint32_t L, uint64_t *__restrict__ out) {
+                                                              uint32_t kp, uint32_t L, uint64_t *__restrict__ out,
+                                                              uint32_t *__restrict__ qcodes, uint32_t cg,
+                                                              const CodeThr thr) {
     const uint32_t n_q = desc ? (uint32_t)desc[0] : n_q_arg;
     const uint64_t n = (uint64_t)n_q * L;
+    const uint32_t W = code_plane_words(kp), PW = code_words(kp), RW = code_rec_words(kp);
+    const uint64_t kpmask = kp >= 64 ? ~0ull : ((1ull << kp) - 1ull);
     for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < n; t += (uint64_t)gridDim.x * kThreads) {
         const uint64_t q = t / L, g = t % L;
         const uint32_t *w = qsigs + q * k + g * kp;
         uint64_t m = 0;
         for (uint32_t i = 0; i < kp; ++i) m |= (uint64_t)(w[i] == HOPH_EMPTY) << i;
         out[t] = m;
+        if (qcodes && g < cg) {
+            uint32_t lo[kCodeBits], hi[kCodeBits];
+#pragma unroll
+            for (int p = 0; p < (int)kCodeBits; ++p) lo[p] = hi[p] = 0;
+            for (uint32_t b = 0; b < kp; ++b) {
+                const uint32_t c = bin_code(w[b]), bit = b & 31;
+                if (b < 32) {
+#pragma unroll
+                    for (int p = 0; p < (int)kCodeBits; ++p) lo[p] |= ((c >> p) & 1u) << bit;
+                } else {
+#pragma unroll
+                    for (int p = 0; p < (int)kCodeBits; ++p) hi[p] |= ((c >> p) & 1u) << bit;
+                }
+            }
+            uint32_t *dst = qcodes + (q * cg + g) * RW;
+#pragma unroll
+            for (int p = 0; p < (int)kCodeBits; ++p) {
+                dst[p * W] = lo[p];
+                if (W == 2) dst[p * W + 1] = hi[p];
+            }
+            const uint64_t nqm = ~m & kpmask;
+            const uint32_t e = (uint32_t)__popcll(m);
+            dst[PW + 0] = (uint32_t)nqm;
+            dst[PW + 1] = (uint32_t)(nqm >> 32);
+            dst[PW + 2] = (uint32_t)thr.dthr[e];
+            dst[PW + 3] = e;
+        }
+    }
+}
+
+// Bins of one group whose codes differ, as a bit mask per 32 bins: the XOR of
+// plane 0, then (acc | (set plane ^ query plane)) for the other planes in one
+// three-input bit operation each (truth table 0xF6 = F0 | (CC ^ AA)).
+template <int W>
+__device__ __forceinline__ uint32_t code_diff(const uint32_t *P, const uint32_t *__restrict__ Q, int w) {
+    uint32_t d = P[w] ^ Q[w];
+#pragma unroll
+    for (int p = 1; p < (int)kCodeBits; ++p) d = __builtin_amdgcn_bitop3_b32(d, P[p * W + w], Q[p * W + w], 0xF6);
+    return d;
+}
+
+// Coarse pass on codes (reject-only).  Same (tile, query chunk) items as the
+// word kernel below; the tile's code planes of the first G groups stay in
+// VGPRs.  Codes never under-count matched bins (equal values have equal codes)
+// and count empty bins exactly (EMPTY has a code of its own), and the per-step
+// cutoffs are monotone in the matched count, so a pair is dropped here only
+// where the exact algorithm rejects it too: at a step whose code state is at or
+// below the reject cutoff, with no earlier step at or above an accept cutoff.
+// Every other pair goes to the fine pass, which restarts from the first group
+// on the 32-bit words.  FAST (G = 1, JOINT or LITERAL): one threshold per
+// query on the count of differing query-non-empty bins.
+template <int W, int G, bool FAST>
+__global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__restrict__ codes,
+                                                             const uint32_t *__restrict__ qcodes,
+                                                             const uint64_t *__restrict__ qmasks,
+                                                             Survivor *__restrict__ surv,
+                                                             unsigned long long *__restrict__ counters,
+                                                             const uint64_t *__restrict__ desc,
+                                                             const CoarseArgs a, const ScanTab tab) {
+    constexpr int PW = (int)kCodeBits * W, RW = PW + 4;
+    __shared__ int64_t s_dmul[HOPH_MAX_KGROUP + 1];
+    if constexpr (!FAST) {
+        for (uint32_t i = threadIdx.x; i <= tab.kp; i += kThreads) s_dmul[i] = tab.dmul[i];
+        __syncthreads();
+    }
+
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t n_sets = desc ? desc[1] : a.n_sets;
+    const uint32_t q_lo = desc ? 0u : a.q0, q_hi = desc ? (uint32_t)desc[0] : a.q1;
+    const uint64_t ntiles = (n_sets + 63) / 64;
+    const uint32_t nchunks = (q_hi - q_lo + a.q_per_wave - 1) / a.q_per_wave;
+    const uint64_t n_items = ntiles * nchunks;
+    const uint64_t wstride = (uint64_t)gridDim.x * kWaves;
+    const uint32_t kp = a.kp;
+    const uint64_t kpmask = kp >= 64 ? ~0ull : ((1ull << kp) - 1ull);
+    const uint64_t ctiles = a.capacity / 64;
+    const uint32_t policy = a.policy;
+    for (uint64_t item = (uint64_t)blockIdx.x * kWaves + wave_id_in_block(); item < n_items; item += wstride) {
+    const uint64_t tile = item % ntiles;
+    const uint32_t chunk = (uint32_t)(item / ntiles);
+    const uint64_t s = tile * 64 + lane;
+    const bool valid = s < n_sets;
+
+    uint32_t P[G][PW];
+    uint32_t em[G][W];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(codes + (((uint64_t)g * ctiles + tile) * 64 + lane) * PW);
+#pragma unroll
+        for (int j = 0; j < PW / 4; ++j) {
+            const uint4 v = src[j];
+            P[g][4 * j + 0] = v.x;
+            P[g][4 * j + 1] = v.y;
+            P[g][4 * j + 2] = v.z;
+            P[g][4 * j + 3] = v.w;
+        }
+#pragma unroll
+        for (int w = 0; w < W && !FAST; ++w) {
+            // set-empty bins: code 0xFF, every plane set
+            uint32_t e = P[g][w];
+#pragma unroll
+            for (int p = 1; p < (int)kCodeBits; ++p) e &= P[g][p * W + w];
+            em[g][w] = e;
+        }
+    }
+
+    const uint32_t qa = q_lo + chunk * a.q_per_wave;
+    const uint32_t qb = min(q_hi, qa + a.q_per_wave);
+    if constexpr (FAST) {
+        // One record per query (planes, non-empty mask, threshold), read two
+        // queries ahead into alternating registers while the current one is
+        // compared; the record buffer holds one padding record past the last
+        // query, so the read-ahead stays inside it.
+        const uint64_t rstride = (uint64_t)a.cg * RW;
+        uint32_t ra[RW], rb[RW];
+#pragma unroll
+        for (int j = 0; j < RW; ++j) ra[j] = qcodes[qa * rstride + j];
+// one query's comparison and survivor append (written out twice below, on the
+// kernel's own restrict pointers, so that the record loads stay scalar)
+#define HOPH_CODE_QUERY(r, qq)                                                                     \
+        {                                                                                          \
+            uint32_t dn = 0;                                                                       \
+            _Pragma("unroll") for (int w = 0; w < W; ++w) dn +=                                    \
+                __popc(code_diff<W>(P[0], r, w) & r[PW + w]);                                      \
+            const bool survive = ((int32_t)dn < (int32_t)r[PW + 2]) & valid;                       \
+            const uint64_t bal = __builtin_amdgcn_ballot_w64(survive);                             \
+            if (bal) {                                                                             \
+                uint64_t base = 0;                                                                 \
+                if (lane == 0) base = atomicAdd(counters + 0, (unsigned long long)__popcll(bal));  \
+                base = __shfl(base, 0);                                                            \
+                const uint64_t slot = base + lane_rank(bal, lane);                                 \
+                if (survive && slot < a.surv_cap) surv[slot] = Survivor{(qq), (uint32_t)s, 0};     \
+            }                                                                                      \
+        }
+        for (uint32_t q = qa; q < qb; q += 2) {
+#pragma unroll
+            for (int j = 0; j < RW; ++j) rb[j] = qcodes[(q + 1) * rstride + j];
+            HOPH_CODE_QUERY(ra, q)
+            if (q + 1 >= qb) break;
+#pragma unroll
+            for (int j = 0; j < RW; ++j) ra[j] = qcodes[(q + 2) * rstride + j];
+            HOPH_CODE_QUERY(rb, q + 1)
+        }
+#undef HOPH_CODE_QUERY
+    } else {
+    for (uint32_t q = qa; q < qb; ++q) {
+        const uint32_t *qc = qcodes + (uint64_t)q * a.cg * RW;
+        const uint64_t *qmk = qmasks + (uint64_t)q * a.L;
+        bool survive;
+        {
+            int64_t S = 0;
+            bool undecided = valid, maybe = false;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                if (!__any(undecided)) break;
+                const uint64_t qm = qmk[g];
+                const uint64_t nqm = ~qm & kpmask;
+                uint32_t dn = 0, de = 0, ee = 0;
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    const uint32_t d = code_diff<W>(P[g], qc + g * RW, w);
+                    const uint32_t qmw = (uint32_t)(qm >> (32 * w)), nqmw = (uint32_t)(nqm >> (32 * w));
+                    dn += __popc(d & nqmw);
+                    de += __popc(d & qmw);
+                    ee += __popc(em[g][w] | qmw);
+                }
+                const uint32_t eq_q = (uint32_t)__popcll(qm);
+                const uint32_t m = kp - eq_q - dn;        // >= the matched non-empty bins
+                const uint32_t ej = eq_q - de;            // jointly empty bins, exact
+                S += tab.W[g] * group_rho(m + ej, ej, ee, kp, policy, s_dmul, tab.lambda);
+                if (undecided) {
+                    if (S >= tab.acc[g]) {
+                        maybe = true;
+                        undecided = false;
+                    } else if (S <= tab.rej[g]) {
+                        undecided = false;
+                    }
+                }
+            }
+            survive = maybe || undecided;
+        }
+        if (__any(survive)) {
+            const uint64_t slot = wave_append(survive, counters + 0, lane);
+            if (survive && slot < a.surv_cap) surv[slot] = Survivor{q, (uint32_t)s, 0};
+        }
+    }
+    }
     }
 }
 
@@ -324,8 +518,27 @@ CoarseArgs coarse_args(const ScanLaunch &l, uint32_t policy) {
     a.q1 = l.q1;
     a.q_per_wave = l.q_per_wave;
     a.policy = policy;
-    a.depth = l.depth;
+    a.depth = l.codes ? 0u : l.depth;      // where the fine pass starts
+    a.cg = l.cg;
     return a;
+}
+
+template <int W>
+void codes_launch(const ScanLaunch &l, const CoarseArgs &a, const ScanTab &tab, hipStream_t st, uint32_t blocks) {
+    auto *cnt = reinterpret_cast<unsigned long long *>(l.counters);
+#define HOPH_CODES(G, F)                                                                                      \
+    hipLaunchKernelGGL((scan_codes_kernel<W, G, F>), dim3(blocks), dim3(kThreads), 0, st, l.codes, l.qcodes, \
+                       l.qmasks, l.surv, cnt, l.desc, a, tab)
+    switch (l.depth) {
+    case 1:
+        if (tab.policy == HOPH_EMPTY_EITHER) HOPH_CODES(1, false);
+        else HOPH_CODES(1, true);
+        break;
+    case 2: HOPH_CODES(2, false); break;
+    case 3: HOPH_CODES(3, false); break;
+    default: HOPH_CODES(4, false); break;
+    }
+#undef HOPH_CODES
 }
 
 template <int KPAD, bool EXACT>
@@ -388,13 +601,17 @@ uint32_t max_depth_for_kpad(uint32_t kpad) {
 }
 
 hipError_t launch_query_masks(const uint32_t *qsigs, uint32_t n_q, const uint64_t *desc, uint32_t k, uint32_t kp,
-                              uint32_t L, uint64_t *out, hipStream_t st) {
+                              uint32_t L, uint64_t *out, uint32_t *qcodes, uint32_t cg, const CodeThr *thr,
+                              hipStream_t st) {
+    if (qcodes && !thr) return hipErrorInvalidValue;
+    CodeThr t{};
+    if (thr) t = *thr;
     const uint64_t n = (uint64_t)n_q * L;         // n_q: the batch size, or its upper bound with desc
     if (n == 0) return hipSuccess;
     uint64_t blocks = (n + kThreads - 1) / kThreads;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(query_masks_kernel, dim3((uint32_t)blocks), dim3(kThreads), 0, st, qsigs, n_q, desc, k, kp, L,
-                       out);
+                       out, qcodes, cg, t);
     return hipGetLastError();
 }
 
@@ -411,12 +628,18 @@ hipError_t launch_scan_coarse(const ScanLaunch &l, const ScanTab &tab, hipStream
         blocks = waves_to_blocks(ntiles * nchunks);
     }
     const CoarseArgs a = coarse_args(l, tab.policy);
+    if (l.codes) {
+        if (l.depth == 0 || l.depth > l.cg) return hipErrorInvalidValue;
+        if (code_plane_words(l.kp) == 1) codes_launch<1>(l, a, tab, st, blocks);
+        else codes_launch<2>(l, a, tab, st, blocks);
+        return hipGetLastError();
+    }
     HOPH_KPAD_SWITCH(coarse_kp, l, a, tab, st, blocks)
     return hipGetLastError();
 }
 
 hipError_t launch_scan_fine(const ScanLaunch &l, const ScanTab &tab, hipStream_t st) {
-    if (l.depth >= l.L) return hipSuccess;
+    if (!l.codes && l.depth >= l.L) return hipSuccess;
     const uint32_t blocks = (uint32_t)device_cu_count() * 8;
     const CoarseArgs a = coarse_args(l, tab.policy);
     hipLaunchKernelGGL(scan_fine_kernel, dim3(blocks), dim3(kThreads), 0, st, l.slab, l.qsigs, l.surv, l.keys,

@@ -5,6 +5,7 @@
 // HOPH_TUNE_CACHE).
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
@@ -80,7 +81,8 @@ struct hoph_plan {
     // device buffers
     uint32_t *q_ids = nullptr;
     uint64_t *q_offsets = nullptr, *desc = nullptr, *prefix = nullptr, *q_masks = nullptr;
-    uint32_t *q_sigs = nullptr;
+    uint32_t *q_sigs = nullptr, *q_codes = nullptr;
+    bool codes = false;           // coarse pass on code planes
     Survivor *surv = nullptr;
     uint64_t surv_cap = 0;
     uint64_t *keys = nullptr;
@@ -106,8 +108,8 @@ struct hoph_plan {
         if (graph) (void)hipGraphDestroy(graph);
         exec = nullptr;
         graph = nullptr;
-        void *bufs[] = {q_ids, q_offsets, desc, prefix, q_masks, q_sigs, surv, keys, counters, cursor, out_offsets,
-                        qcount, out_ids};
+        void *bufs[] = {q_ids, q_offsets, desc, prefix, q_masks, q_sigs, q_codes, surv, keys, counters, cursor,
+                        out_offsets, qcount, out_ids};
         for (void *p : bufs)
             if (p) (void)hipFree(p);
         if (h_counters) (void)hipHostFree(h_counters);
@@ -122,7 +124,8 @@ namespace {
 std::string shape_key(const hoph_plan *p, uint64_t n_sets, uint32_t n_q) {
     std::ostringstream os;
     os << "k" << p->params.k << "_kp" << p->params.k_group << "_lay" << p->params.layout << "_hash" << p->params.hash
-       << "_d" << p->depth << "_kind" << (p->kind == QueryKind::GOPH ? 0 : 1) << "_n" << log2_bucket(n_sets) << "_q"
+       << "_d" << p->depth << (p->codes ? "c" : "w") << "_kind" << (p->kind == QueryKind::GOPH ? 0 : 1) << "_n"
+       << log2_bucket(n_sets) << "_q"
        << log2_bucket(n_q);
     return os.str();
 }
@@ -139,6 +142,9 @@ ScanLaunch scan_launch(const hoph_plan *p, const PlanShape &s) {
     l.k = idx->lay.k;
     l.qsigs = p->q_sigs;
     l.qmasks = p->q_masks;
+    l.codes = p->codes ? idx->codes : nullptr;
+    l.qcodes = p->q_codes;
+    l.cg = idx->cg;
     l.q0 = 0;
     l.q1 = p->cfg.max_queries;
     l.depth = p->depth;
@@ -158,7 +164,10 @@ hoph_status enqueue_sketch(hoph_plan *p, const PlanShape &s, hipStream_t st) {
                                    p->cfg.max_query_ids, p->q_sigs, p->err_word, s.sketch_wpc, st),
              "batch sketch launch");
     const LayoutInfo &lay = p->idx->lay;
-    HOPH_HIP(launch_query_masks(p->q_sigs, p->cfg.max_queries, p->desc, lay.k, lay.kp, lay.L, p->q_masks, st),
+    CodeThr thr{};
+    std::memcpy(thr.dthr, p->tab.dthr0, sizeof(thr.dthr));
+    HOPH_HIP(launch_query_masks(p->q_sigs, p->cfg.max_queries, p->desc, lay.k, lay.kp, lay.L, p->q_masks,
+                                p->codes ? p->q_codes : nullptr, p->idx->cg, &thr, st),
              "query mask launch");
     return HOPH_OK;
 }
@@ -309,6 +318,8 @@ hoph_status hoph_plan_create(hoph_index *idx, const hoph_sketch_params *params, 
         params->ratio_b != idx->params.ratio_b)
         return fail(HOPH_E_INVAL, "sketch parameters differ from the index's");
     if (!valid_ratio_T(qp->T) || !valid_ratio_eps(qp->eps)) return fail(HOPH_E_INVAL, "T or eps out of range");
+    if (qp->empty_policy > HOPH_EMPTY_EITHER) return fail(HOPH_E_INVAL, "unknown empty policy");
+    if (qp->coarse_filter > HOPH_COARSE_WORDS) return fail(HOPH_E_INVAL, "unknown coarse filter");
     std::unique_ptr<hoph_plan> p(new (std::nothrow) hoph_plan());
     if (!p) return fail(HOPH_E_NOMEM, "host allocation");
     p->idx = idx;
@@ -326,7 +337,8 @@ hoph_status hoph_plan_create(hoph_index *idx, const hoph_sketch_params *params, 
     uint32_t g1 = idx->lay.L;
     for (uint32_t l = 0; l < idx->lay.L; ++l)
         if (t.rej[l] >= 0) { g1 = l + 1; break; }
-    const uint32_t maxd = std::min(max_depth_for_kpad(idx->kpad), idx->lay.L);
+    p->codes = qp->coarse_filter == HOPH_COARSE_CODES && idx->codes;
+    const uint32_t maxd = p->codes ? idx->cg : std::min(max_depth_for_kpad(idx->kpad), idx->lay.L);
     p->depth = std::max<uint32_t>(1, std::min(qp->coarse_depth ? qp->coarse_depth : g1, maxd));
     const uint64_t Q = cfg->max_queries, k = params->k, L = idx->lay.L;
     p->surv_cap = std::max<uint64_t>(idx->capacity, 1u << 20);
@@ -338,7 +350,9 @@ hoph_status hoph_plan_create(hoph_index *idx, const hoph_sketch_params *params, 
     if ((st = dalloc(&p->q_ids, cfg->max_query_ids, "plan query ids")) ||
         (st = dalloc(&p->q_offsets, Q + 1, "plan query offsets")) || (st = dalloc(&p->desc, 2, "plan descriptor")) ||
         (st = dalloc(&p->prefix, Q + 1, "plan chunk prefix")) || (st = dalloc(&p->q_sigs, Q * k, "plan signatures")) ||
-        (st = dalloc(&p->q_masks, Q * L, "plan query masks")) || (st = dalloc(&p->surv, p->surv_cap, "plan survivors")) ||
+        (st = dalloc(&p->q_masks, Q * L, "plan query masks")) ||
+        (st = dalloc(&p->q_codes, (Q + 1) * idx->cg * code_rec_words(idx->lay.kp), "plan query codes")) ||
+        (st = dalloc(&p->surv, p->surv_cap, "plan survivors")) ||
         (st = dalloc(&p->keys, p->keys_cap, "plan keys")) || (st = dalloc(&p->counters, 8, "plan counters")) ||
         (st = dalloc(&p->cursor, Q + 1, "plan cursors")) || (st = dalloc(&p->out_offsets, Q + 1, "plan offsets")) ||
         (st = dalloc(&p->qcount, Q + 1, "plan counts")) ||

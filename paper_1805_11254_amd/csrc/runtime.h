@@ -50,6 +50,8 @@ struct Workspace {
     uint64_t *counters = nullptr; // device [0] survivors, [1] accepted
     uint64_t *qmasks = nullptr;   // per (query, group) empty-bin masks
     uint64_t qmask_cap = 0;
+    uint32_t *qcodes = nullptr;   // per (query, code group) code planes
+    uint64_t qcode_cap = 0;
     uint32_t *qcount = nullptr;   // per-query accepted counts (output stage)
     uint64_t *cursor = nullptr;   // per-query scatter cursors
     uint64_t seg_cap = 0;
@@ -63,11 +65,14 @@ struct Workspace {
         if (keys) (void)hipFree(keys);
         if (counters) (void)hipFree(counters);
         if (qmasks) (void)hipFree(qmasks);
+        if (qcodes) (void)hipFree(qcodes);
         if (qcount) (void)hipFree(qcount);
         if (cursor) (void)hipFree(cursor);
         if (h_counters) (void)hipHostFree(h_counters);
         qmasks = nullptr;
         qmask_cap = 0;
+        qcodes = nullptr;
+        qcode_cap = 0;
         qcount = nullptr;
         cursor = nullptr;
         seg_cap = 0;
@@ -103,6 +108,17 @@ struct Workspace {
         while (want < n) want <<= 1;
         if (hipMalloc(&qmasks, want * sizeof(uint64_t)) != hipSuccess) return fail(HOPH_E_NOMEM, "query mask buffer");
         qmask_cap = want;
+        return HOPH_OK;
+    }
+    hoph_status grow_qcodes(uint64_t n) {
+        if (n <= qcode_cap) return HOPH_OK;
+        if (qcodes) (void)hipFree(qcodes);
+        qcodes = nullptr;
+        qcode_cap = 0;
+        uint64_t want = 1 << 16;
+        while (want < n) want <<= 1;
+        if (hipMalloc(&qcodes, want * sizeof(uint32_t)) != hipSuccess) return fail(HOPH_E_NOMEM, "query code buffer");
+        qcode_cap = want;
         return HOPH_OK;
     }
     hoph_status grow_seg(uint64_t n) {
@@ -155,6 +171,8 @@ struct hoph_index {
     uint64_t capacity = 0;        // slab capacity in sets, a multiple of 64
     uint64_t max_sets = 0;        // the capacity the caller asked for
     uint32_t *slab = nullptr;
+    uint32_t *codes = nullptr;    // code planes of the first cg groups (coarse pass on codes)
+    uint32_t cg = 0;
     hoph::Workspace ws;
     std::mutex mu;
 };

@@ -69,9 +69,13 @@ struct hoph_server {
     uint64_t submitted = 0, completed = 0, rejected = 0, batches = 0, batch_queries = 0, inserted = 0;
     bool have_first = false;
     Clock::time_point t_first, t_last;
-    // inserts
+    // inserts: grow-only device staging, so that an insert does not free
+    // memory (which would wait for every batch in flight)
     std::mutex insert_mu;
     hipStream_t insert_stream = nullptr;
+    uint32_t *ins_ids = nullptr, *ins_sigs = nullptr;
+    uint64_t *ins_offs = nullptr;
+    uint64_t ins_ids_cap = 0, ins_sets_cap = 0;
 };
 
 namespace {
@@ -147,8 +151,8 @@ uint64_t plan_bytes(const hoph_index *idx, const hoph_server_config &c) {
     const uint64_t Q = c.max_batch_queries, k = idx->lay.k, L = idx->lay.L;
     const uint64_t surv = std::max<uint64_t>(idx->capacity, 1u << 20);
     const uint64_t keys = sort_capacity(std::max<uint64_t>(c.max_batch_results, 1));
-    return 4 * c.max_batch_ids + 8 * 4 * (Q + 1) + 4 * Q * k + 8 * Q * L + 16 * surv + 8 * keys +
-           4 * c.max_batch_results + 4 * (Q + 1) + 4 * c.max_batch_ids + 8 * (Q + 1);
+    return 4 * c.max_batch_ids + 8 * 4 * (Q + 1) + 4 * Q * k + 8 * Q * L + 4 * (Q + 1) * idx->cg * code_rec_words(idx->lay.kp) +
+           16 * surv + 8 * keys + 4 * c.max_batch_results + 4 * (Q + 1) + 4 * c.max_batch_ids + 8 * (Q + 1);
 }
 
 void free_slot(Slot &s) {
@@ -295,21 +299,31 @@ hoph_status hoph_server_insert(hoph_server *srv, const uint32_t *h_ids, const ui
         if (idx->n + n_sets > idx->max_sets) return fail(HOPH_E_CAPACITY, "index capacity exceeded");
     }
     const uint64_t nnz = h_offsets[n_sets] - h_offsets[0];
-    uint32_t *d_ids = nullptr, *d_sigs = nullptr;
-    uint64_t *d_offs = nullptr;
-    auto cleanup = [&] {
-        if (d_ids) (void)hipFree(d_ids);
-        if (d_offs) (void)hipFree(d_offs);
-        if (d_sigs) (void)hipFree(d_sigs);
-    };
     std::vector<uint64_t> offs(h_offsets, h_offsets + n_sets + 1);
     for (auto &o : offs) o -= h_offsets[0];
-    if (hipMalloc(&d_ids, std::max<uint64_t>(nnz, 1) * 4) != hipSuccess ||
-        hipMalloc(&d_offs, (n_sets + 1) * 8) != hipSuccess ||
-        hipMalloc(&d_sigs, n_sets * (uint64_t)idx->lay.k * 4) != hipSuccess) {
-        cleanup();
-        return fail(HOPH_E_NOMEM, "insert staging");
+    if (nnz > srv->ins_ids_cap) {
+        // growth frees the old buffer; previous inserts were synchronised already
+        if (srv->ins_ids) (void)hipFree(srv->ins_ids);
+        srv->ins_ids = nullptr;
+        srv->ins_ids_cap = 0;
+        const uint64_t cap = std::max<uint64_t>(nnz + nnz / 2, 1 << 20);
+        if (hipMalloc(&srv->ins_ids, cap * 4) != hipSuccess) return fail(HOPH_E_NOMEM, "insert staging");
+        srv->ins_ids_cap = cap;
     }
+    if (n_sets > srv->ins_sets_cap) {
+        if (srv->ins_offs) (void)hipFree(srv->ins_offs);
+        if (srv->ins_sigs) (void)hipFree(srv->ins_sigs);
+        srv->ins_offs = nullptr;
+        srv->ins_sigs = nullptr;
+        srv->ins_sets_cap = 0;
+        const uint64_t cap = std::max<uint64_t>(n_sets + n_sets / 2, 4096);
+        if (hipMalloc(&srv->ins_offs, (cap + 1) * 8) != hipSuccess ||
+            hipMalloc(&srv->ins_sigs, cap * (uint64_t)idx->lay.k * 4) != hipSuccess)
+            return fail(HOPH_E_NOMEM, "insert staging");
+        srv->ins_sets_cap = cap;
+    }
+    uint32_t *d_ids = srv->ins_ids, *d_sigs = srv->ins_sigs;
+    uint64_t *d_offs = srv->ins_offs;
     hipStream_t st = srv->insert_stream;
     hoph_status s = HOPH_OK;
     if (hipMemcpyAsync(d_ids, h_ids + h_offsets[0], nnz * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
@@ -322,10 +336,9 @@ hoph_status hoph_server_insert(hoph_server *srv, const uint32_t *h_ids, const ui
         first = idx->n;
     }
     if (!s && launch_index_store(d_sigs, n_sets, first, idx->lay.k, idx->lay.kp, idx->lay.L, idx->kpad,
-                                 idx->capacity, idx->slab, st) != hipSuccess)
+                                 idx->capacity, idx->slab, idx->codes, idx->cg, st) != hipSuccess)
         s = fail(HOPH_E_DEVICE, "index store launch");
     if (!s && hipStreamSynchronize(st) != hipSuccess) s = fail(HOPH_E_DEVICE, "hipStreamSynchronize");
-    cleanup();
     if (s) return s;
     {
         // visible to batches dispatched from now on; batches in flight keep their snapshot
@@ -439,6 +452,9 @@ void hoph_server_destroy(hoph_server *srv) {
         DeviceGuard dg(srv->idx->device);
         for (auto &s : srv->slots) free_slot(*s);
         if (srv->insert_stream) (void)hipStreamDestroy(srv->insert_stream);
+        if (srv->ins_ids) (void)hipFree(srv->ins_ids);
+        if (srv->ins_offs) (void)hipFree(srv->ins_offs);
+        if (srv->ins_sigs) (void)hipFree(srv->ins_sigs);
     }
     delete srv;
 }

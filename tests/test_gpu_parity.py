@@ -98,10 +98,11 @@ def test_query_candidates_bit_exact(name):
     kind = "goph" if w.goph else "hoph"
     for T, eps in QUERY_GRID:
         for policy in (H.EMPTY_JOINT, H.EMPTY_EITHER, H.EMPTY_LITERAL):
-            go, gi = gpu_query(kind, idx, qsig, T, eps, policy)
             oo, oi = oracle_query(w, sh, qh, T, eps, policy)
-            assert go.tolist() == oo.tolist(), (T, eps, policy)
-            assert gi.tolist() == oi.tolist(), (T, eps, policy)
+            for coarse in (H.COARSE_CODES, H.COARSE_WORDS):
+                go, gi = gpu_query(kind, idx, qsig, T, eps, policy, coarse=coarse)
+                assert go.tolist() == oo.tolist(), (T, eps, policy, coarse)
+                assert gi.tolist() == oi.tolist(), (T, eps, policy, coarse)
     idx.free()
 
 
@@ -114,13 +115,110 @@ def test_results_do_not_depend_on_coarse_depth(name):
     qsig = gpu_sketch(w, w.queries, p)
     idx = H.Index(p, sig)
     kind = "goph" if w.goph else "hoph"
-    ref = None
-    for depth in (0, 1, 2, 3, 4):
-        out = gpu_query(kind, idx, qsig, (4, 5), (1, 10_000), H.EMPTY_JOINT, coarse_depth=depth)
-        cur = (out[0].tolist(), out[1].tolist())
-        if ref is None:
-            ref = cur
-        assert cur == ref, depth
+    for policy in (H.EMPTY_JOINT, H.EMPTY_EITHER):
+        ref = None
+        for coarse in (H.COARSE_CODES, H.COARSE_WORDS):
+            for depth in (0, 1, 2, 3, 4):
+                out = gpu_query(kind, idx, qsig, (4, 5), (1, 10_000), policy, coarse_depth=depth, coarse=coarse)
+                cur = (out[0].tolist(), out[1].tolist())
+                ref = cur if ref is None else ref
+                assert cur == ref, (policy, coarse, depth)
+    idx.free()
+
+
+# The library's 8-bit bin code (a multiplicative mix scaled into 255 values,
+# EMPTY apart), restated here only to build adversarial inputs: bins whose
+# values differ from a query's but whose codes are equal.
+def _code8(v):
+    v = np.asarray(v, dtype=np.uint64)
+    return np.where(v == tiny.EMPTY, 255, (((v * 0x9E3779B1) & 0xFFFFFFFF) * 255) >> 32).astype(np.uint64)
+
+
+def _colliding_value(v, rng):
+    """A value != v (and != EMPTY) with the same code as v."""
+    target = int(_code8(v))
+    while True:
+        cand = rng.integers(0, 1 << 32, size=4096, dtype=np.uint64)
+        hit = cand[(_code8(cand) == target) & (cand != v) & (cand != tiny.EMPTY)]
+        if hit.size:
+            return int(hit[0])
+
+
+def _policies_that_fit(p, T, eps):
+    """Empty policies whose exact tables fit 64 bits for these parameters
+    (lcm(1..k') does not for k' above 42; LITERAL needs no lcm)."""
+    out = []
+    for policy in (H.EMPTY_JOINT, H.EMPTY_EITHER, H.EMPTY_LITERAL):
+        try:
+            H.decision_tables(p, T, eps, policy)
+            out.append(policy)
+        except H.HophError as e:
+            assert e.status == H.HOPH_E_UNSUPPORTED
+    assert H.EMPTY_LITERAL in out
+    return out
+
+
+@pytest.mark.parametrize("k,kp", [(512, 32), (320, 40), (512, 64)])
+def test_code_collisions_match_oracle(k, kp):
+    """Index sets whose bins carry a query's codes but not its values (in a
+    fraction of the bins that would make the code count look like a near-
+    duplicate): the coarse pass on codes cannot reject them, every such pair
+    goes to the exact per-pair pass, and the result must equal the oracle's."""
+    import torch
+    _print_case(f"code collisions kp={kp}")
+    w = W.hoph_bovw(n=6_000, n_q=12, seed=21, k=k, kp=kp, planted_frac=0.01)
+    p = params_of(w)
+    sig = to_u32(gpu_sketch(w, w.collection, p)).copy()
+    qsig = to_u32(gpu_sketch(w, w.queries, p)).copy()
+    rng = np.random.default_rng(22)
+    table = {}
+    for s_ in range(0, w.collection.n, 2):
+        q = s_ % 4                      # queries 0..3 meet half of the collection this way
+        frac = (0.55, 0.7, 0.85, 1.0)[q]
+        for g in range(min(4, w.k // kp)):
+            bins = np.arange(g * kp, (g + 1) * kp)
+            chosen = bins[rng.random(kp) < frac]
+            for b in chosen:
+                v = int(qsig[q, b])
+                if v == tiny.EMPTY:
+                    continue
+                key = (v, int(rng.integers(4)))
+                if key not in table:
+                    table[key] = _colliding_value(v, rng)
+                sig[s_, b] = table[key]
+    dsig = torch.from_numpy(sig.view(np.int32)).to("cuda")
+    dq = torch.from_numpy(qsig.view(np.int32)).to("cuda")
+    idx = H.Index(p, dsig)
+    for T, eps in (((4, 5), (1, 10_000)), ((1, 2), (1, 100))):
+        for policy in _policies_that_fit(p, T, eps):
+            oo, oi = oracle_query(w, sig, qsig, T, eps, policy)
+            for depth in (0, 1, 3):
+                go, gi = gpu_query("hoph", idx, dq, T, eps, policy, coarse_depth=depth)
+                assert go.tolist() == oo.tolist() and gi.tolist() == oi.tolist(), (T, eps, policy, depth)
+    idx.free()
+
+
+@pytest.mark.parametrize("layout,k,kp", [(W.LAYOUT_HIER, 128, 8), (W.LAYOUT_HIER, 192, 12), (W.LAYOUT_HIER, 320, 20),
+                                         (W.LAYOUT_OPH, 120, 12), (W.LAYOUT_HIER, 320, 40), (W.LAYOUT_OPH, 448, 64)])
+def test_group_sizes_match_oracle(layout, k, kp):
+    """Group sizes other than 16 and 32: code planes of one or two words per
+    plane, index stores through the word path, both coarse filters."""
+    _print_case(f"group size layout={layout} k={k} kp={kp}")
+    w = W.hoph_bovw(n=3_001, n_q=10, seed=23 + kp, k=k, kp=kp, planted_frac=0.02)
+    w.layout = layout
+    p = params_of(w)
+    sig = gpu_sketch(w, w.collection, p)
+    qsig = gpu_sketch(w, w.queries, p)
+    sh, qh = to_u32(sig), to_u32(qsig)
+    assert (sh == oracle_sketch(w, w.collection)).all()
+    idx = H.Index(p, sig)
+    kind = "goph" if w.goph else "hoph"
+    for T, eps in (((4, 5), (1, 10_000)), ((1, 2), (1, 100))):
+        for policy in _policies_that_fit(p, T, eps):
+            oo, oi = oracle_query(w, sh, qh, T, eps, policy)
+            for coarse in (H.COARSE_CODES, H.COARSE_WORDS):
+                go, gi = gpu_query(kind, idx, qsig, T, eps, policy, coarse=coarse)
+                assert go.tolist() == oo.tolist() and gi.tolist() == oi.tolist(), (T, eps, policy, coarse)
     idx.free()
 
 
@@ -235,6 +333,9 @@ def test_results_capacity_reports_needed():
     assert ei.value.status == H.HOPH_E_CAPACITY and ei.value.needed == need
     _, exact = H.query_goph(idx, qsig, T=(1, 2), eps=(1, 10_000), capacity=need)
     assert exact.numel() == need
+    with pytest.raises(H.HophError) as ei:
+        H.query_goph(idx, qsig, T=(1, 2), eps=(1, 10_000), coarse=7)
+    assert ei.value.status == H.HOPH_E_INVAL
     idx.free()
 
 

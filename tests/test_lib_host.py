@@ -244,3 +244,35 @@ def test_device_entry_points_refuse_bad_params_before_launch():
     qp = H.QueryParamsC(H.Ratio(4, 5), H.Ratio(1, 10000), 0, 0)
     res = H.ResultsC(None, None, 0, 0)
     assert H.lib().query_hoph(None, None, 0, qp, res, None) == H.HOPH_E_INVAL
+
+
+def test_abi_struct_layouts_match_binding(tmp_path):
+    """Every struct of include/hoph.h, compiled by the C compiler, has the size
+    and field offsets that the binding's ctypes mirrors assume."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirrors = {
+        "hoph_ratio": H.Ratio, "hoph_sketch_params": H.SketchParamsC, "hoph_query_params": H.QueryParamsC,
+        "hoph_results": H.ResultsC, "hoph_minwise_params": H.MinwiseParamsC,
+        "hoph_decision_tables": H.DecisionTablesC, "hoph_plan_config": H.PlanConfigC, "hoph_plan_info": H.PlanInfoC,
+        "hoph_server_config": H.ServerConfigC, "hoph_server_stats": H.ServerStatsC,
+    }
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "hoph.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "abi.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "abi"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == H.C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
