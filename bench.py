@@ -2,9 +2,10 @@
 """Benchmark of the OPH/HOPH hot path on one MI355X.
 
 One step is the whole path over one batch: sketch every set of the collection
-(one shared universal hash, k bins, per-bin minimum), refill the resident
-index, sketch the query batch, and answer every query with the (1:1) HOPH scan
-(coarse pass, per-survivor pass, sorted CSR output).  Workload: 1,000,000
+(one shared universal hash, k bins, per-bin minimum) straight into the
+resident index (group-major slabs and the narrowed code planes of the first
+groups), sketch the query batch, and answer every query with the (1:1) HOPH
+scan (coarse pass on codes, per-survivor pass on the words, sorted CSR output).  Workload: 1,000,000
 bag-of-visual-words sets over 2^20 codewords (Zipf(1.1) codewords, log-normal
 sizes, median 600, clipped to [100, 4000]), h(x) = (a x + b) mod (2^31 - 1),
 k = 512 bins in groups of 32, 1,024 queries with 1% of the collection planted as
@@ -432,17 +433,17 @@ def main():
     cap = [None]
 
     def step(ev=None):
-        e = ev or [None] * 5
+        # one pass of the path: every set sketched straight into the resident
+        # index (slabs + code planes), the query batch sketched, the HOPH scan
+        e = ev or [None] * 4
         if e[0] is not None: e[0].record(stream)
-        H.sketch_oph(p, ids, offs, out=sig)
-        if e[1] is not None: e[1].record(stream)
         idx.reset()
-        idx.append(sig)
-        if e[2] is not None: e[2].record(stream)
+        idx.append_sets(ids, offs)
+        if e[1] is not None: e[1].record(stream)
         H.sketch_oph(p, qids, qoffs, out=qsig)
-        if e[3] is not None: e[3].record(stream)
+        if e[2] is not None: e[2].record(stream)
         out = H.query_hoph(idx, qsig, T=w.T, eps=w.eps, capacity=cap[0])
-        if e[4] is not None: e[4].record(stream)
+        if e[3] is not None: e[3].record(stream)
         return out
 
     for i in range(args.warmup):
@@ -453,13 +454,14 @@ def main():
     torch.cuda.synchronize()
     log("warm-up done")
 
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
-    qms = []
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    qms, ams = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         out = step(evs[i])
         qms.append(idx.last_query_ms())
+        ams.append(idx.last_append_ms())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1000.0 / args.steps
@@ -468,17 +470,34 @@ def main():
     def mean_ms(a, b):
         return sum(e[a].elapsed_time(e[b]) for e in evs) / len(evs)
 
-    sketch_ms = mean_ms(0, 1)
-    index_ms = mean_ms(1, 2)
-    qsketch_ms = mean_ms(2, 3)
-    query_ms = mean_ms(3, 4)
+    build_ms = mean_ms(0, 1)
+    qsketch_ms = mean_ms(1, 2)
+    query_ms = mean_ms(2, 3)
+    sketch_ms = sum(a[0] for a in ams) / len(ams)       # the sketch-into-index kernel
+    codes_ms = sum(a[1] for a in ams) / len(ams)        # code planes from the slabs
+
+    # the two-step build (row-major signatures, then the index store), for comparison
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    two = []
+    for _ in range(3):
+        e0.record(stream)
+        H.sketch_oph(p, ids, offs, out=sig)
+        e1.record(stream)
+        idx.reset()
+        idx.append(sig)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        two.append((e0.elapsed_time(e1), e1.elapsed_time(e2)))
+    two_sketch_ms = sum(t[0] for t in two) / len(two)
+    index_ms = sum(t[1] for t in two) / len(two)
     coarse_ms = sum(q[0] for q in qms) / len(qms)
     fine_ms = sum(q[1] for q in qms) / len(qms)
     sort_ms = sum(q[2] for q in qms) / len(qms)
 
     # algorithmic work per launch
-    sketch_bytes = nnz * 4 + (N + 1) * 8 + N * k * 4
+    sketch_bytes = nnz * 4 + (N + 1) * 8 + N * k * 4                 # ids, offsets in; signatures out
     code_groups = min(4, k // kp)
+    code_bytes = N * code_groups * kp * 4 + N * code_groups * 32 * (1 if kp <= 32 else 2)
     index_bytes = 2 * N * k * 4 + N * code_groups * 32 * (1 if kp <= 32 else 2)   # rows in, slabs + code planes out
     tabs = H.decision_tables(p, w.T, w.eps)
     depth = next((l + 1 for l in range(tabs["L"]) if tabs["rej"][l] >= 0), tabs["L"])
@@ -492,12 +511,19 @@ def main():
     coarse_bytes = N * 32 * W_planes * depth + Q * (32 * W_planes + 16) * depth
     traffic = load_traffic()
     kernels = {
-        "sketch_oph": {"ms": sketch_ms, "bound": "hbm", "achieved": sketch_bytes / (sketch_ms * 1e-3) / 1e9,
-                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": traffic.get("sketch_kernel"),
-                       "algorithmic_bytes": sketch_bytes, "sets_per_s": N / (sketch_ms * 1e-3)},
-        "index_store": {"ms": index_ms, "bound": "hbm", "achieved": index_bytes / (index_ms * 1e-3) / 1e9,
-                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": traffic.get("index_store_vec"),
-                        "algorithmic_bytes": index_bytes},
+        "sketch_into_index": {"ms": sketch_ms, "bound": "hbm", "achieved": sketch_bytes / (sketch_ms * 1e-3) / 1e9,
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": traffic.get("sketch_slab_kernel"),
+                              "algorithmic_bytes": sketch_bytes, "sets_per_s": N / (sketch_ms * 1e-3)},
+        "code_planes": {"ms": codes_ms, "bound": "hbm", "achieved": code_bytes / (codes_ms * 1e-3) / 1e9,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": traffic.get("codes_from_slab_kernel"),
+                        "algorithmic_bytes": code_bytes},
+        "two_step_sketch_oph": {"ms": two_sketch_ms, "bound": "hbm",
+                                "achieved": sketch_bytes / (two_sketch_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "traffic": traffic.get("sketch_kernel"),
+                                "algorithmic_bytes": sketch_bytes},
+        "two_step_index_store": {"ms": index_ms, "bound": "hbm", "achieved": index_bytes / (index_ms * 1e-3) / 1e9,
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": traffic.get("index_store_vec"),
+                                 "algorithmic_bytes": index_bytes},
         "scan_coarse": {"ms": coarse_ms, "bound": "alu", "achieved": coarse_ops / (coarse_ms * 1e-3) / 1e12,
                         "peak": ALU_PEAK_OPS / 1e12, "unit": "Tops/s (32-bit VALU lane-ops)",
                         "ops_per_pair_group": ops_per_pair_group,
@@ -511,7 +537,7 @@ def main():
     for v in kernels.values():
         if "achieved" in v:
             v["frac"] = v["achieved"] / v["peak"]
-    dom_name = max(("sketch_oph", "index_store", "scan_coarse"), key=lambda n: kernels[n]["ms"])
+    dom_name = max(("sketch_into_index", "code_planes", "scan_coarse"), key=lambda n: kernels[n]["ms"])
     dom = kernels[dom_name]
     roofline = {"kernel": dom_name, "bound": dom["bound"], "achieved": dom["achieved"], "peak": dom["peak"],
                 "unit": dom["unit"], "frac": dom["frac"], "traffic": dom["traffic"],
@@ -556,8 +582,9 @@ def main():
         "scan_pairs_per_s": N * Q / (query_ms * 1e-3),
         "scan_hbm_frac": kernels["scan_coarse"]["hbm_gbs"] / HBM_PEAK_GBS,
         "served_p99_ms": None,
-        "phase_ms": {"sketch": sketch_ms, "index": index_ms, "query_sketch": qsketch_ms, "query": query_ms,
-                     "coarse": coarse_ms, "fine": fine_ms, "sort_csr": sort_ms},
+        "phase_ms": {"build_index": build_ms, "sketch_into_index": sketch_ms, "code_planes": codes_ms,
+                     "query_sketch": qsketch_ms, "query": query_ms, "coarse": coarse_ms, "fine": fine_ms,
+                     "sort_csr": sort_ms, "two_step_sketch": two_sketch_ms, "two_step_index_store": index_ms},
         "kernels": kernels,
         "roofline": roofline,
         "accepted_pairs": len(got),

@@ -144,6 +144,20 @@ hoph_status build_index(const hoph_sketch_params *params, const uint32_t *d_sigs
 hoph_status index_append(hoph_index *index, const uint32_t *d_sigs, uint64_t n_new,
                          void *hip_stream);
 
+/*
+ * index_append_sets -- sketch n_sets sets (Sec. 3.2, Sec. 4.1, with the index's
+ * own sketch parameters, as sketch_oph) straight into the index: each
+ * signature is written into the group-major slabs (and the narrowed code
+ * planes of the first groups) without a row-major copy; ids continue from the
+ * current size.  d_ids / d_offsets as for sketch_oph (device, CSR).  Results
+ * are identical to sketch_oph followed by index_append.  HOPH_E_CAPACITY if
+ * size + n_sets > capacity.  Asynchronous; ids >= universe and empty sets are
+ * reported as by sketch_oph, at the next hoph_sync on the device.  The
+ * permutation table of a HOPH_HASH_TABLE index must stay valid.
+ */
+hoph_status index_append_sets(hoph_index *index, const uint32_t *d_ids, const uint64_t *d_offsets,
+                              uint64_t n_sets, void *hip_stream);
+
 /* hoph_index_reset -- forget every stored set (size 0, capacity kept) so the
    index can be refilled with index_append without a new allocation. */
 hoph_status hoph_index_reset(hoph_index *index);
@@ -153,6 +167,11 @@ hoph_status hoph_index_reset(hoph_index *index);
    ms[0] coarse pass, ms[1] per-survivor pass, ms[2] sort and CSR output.
    (query_oph_full reports its scan in ms[0].) */
 hoph_status hoph_query_timing(const hoph_index *index, float ms[3]);
+
+/* hoph_append_timing -- device time of the last index_append_sets call on this
+   index, in ms: ms[0] the sketch into the slabs, ms[1] the code planes (zeros
+   before any call).  Waits for that call to finish. */
+hoph_status hoph_append_timing(const hoph_index *index, float ms[2]);
 
 /* hoph_index_size -- number of sets in the index (0 for NULL). */
 uint64_t hoph_index_size(const hoph_index *index);
@@ -367,8 +386,10 @@ hoph_status hoph_build_decision_tables(const hoph_sketch_params *params,
                                        hoph_decision_tables *out);
 
 /* hoph_selftest_bins -- runs the library's own hash-and-bin arithmetic (the code
-   the sketch kernel inlines) on the host for n ids: out_bin[i], out_off[i].  A
-   test hook for checking that arithmetic without a GPU. */
+   the sketch kernel inlines) on the host for n ids: out_bin[i], out_off[i].  Both
+   bin lookups are run where the layout admits the uniform estimate, and a
+   disagreement is HOPH_E_UNSUPPORTED.  A test hook for checking that arithmetic
+   without a GPU. */
 hoph_status hoph_selftest_bins(const hoph_sketch_params *params, const uint32_t *h_perm,
                                const uint32_t *h_ids, uint64_t n, uint32_t *out_bin,
                                uint32_t *out_off);

@@ -85,6 +85,8 @@ SIGNATURES = {
     "sketch_oph": (C.c_int, [C.POINTER(SketchParamsC), vp, vp, u64, vp, vp]),
     "build_index": (C.c_int, [C.POINTER(SketchParamsC), vp, u64, u64, C.POINTER(vp), vp]),
     "index_append": (C.c_int, [vp, vp, u64, vp]),
+    "index_append_sets": (C.c_int, [vp, vp, vp, u64, vp]),
+    "hoph_append_timing": (C.c_int, [vp, C.POINTER(C.c_float)]),
     "hoph_index_size": (u64, [vp]),
     "hoph_index_reset": (C.c_int, [vp]),
     "hoph_query_timing": (C.c_int, [vp, C.POINTER(C.c_float)]),
@@ -254,6 +256,21 @@ class Index:
         import torch
         _need_cuda(sigs, "sigs", (torch.int32,))
         _check(lib().index_append(self._h, vp(sigs.data_ptr()), sigs.shape[0], _stream(stream)))
+
+    def append_sets(self, ids, offsets, stream=None):
+        """Sketch the sets (CSR on the device) straight into the index."""
+        import torch
+        _need_cuda(ids, "ids", (torch.int32,))
+        _need_cuda(offsets, "offsets", (torch.int64,))
+        n = offsets.numel() - 1
+        _check(lib().index_append_sets(self._h, vp(ids.data_ptr()), vp(offsets.data_ptr()), max(n, 0),
+                                       _stream(stream)))
+
+    def last_append_ms(self):
+        """(sketch into slabs, code planes) device ms of the last append_sets."""
+        ms = (C.c_float * 2)()
+        _check(lib().hoph_append_timing(self._h, ms))
+        return ms[0], ms[1]
 
     def __len__(self):
         return int(lib().hoph_index_size(self._h)) if self._h else 0

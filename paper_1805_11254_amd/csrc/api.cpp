@@ -100,6 +100,23 @@ hoph_status write_output(Workspace &ws, uint64_t accepted, uint32_t n_q, hoph_re
     return HOPH_OK;
 }
 
+hipError_t append_sets_async(hoph_index *idx, const uint32_t *d_ids, const uint64_t *d_offsets, uint64_t n_sets,
+                             uint64_t first, uint32_t *err_word, hipStream_t s, bool timed) {
+    SketchDesc d;
+    fill_sketch_desc(idx->params, idx->lay, d);
+    hipError_t e = hipSuccess;
+    if (timed && (e = hipEventRecord(idx->ws.aev[0], s)) != hipSuccess) return e;
+    e = launch_sketch(d, d_ids, d_offsets, n_sets, idx->slab + first * idx->lay.k, err_word, s);
+    if (e != hipSuccess) return e;
+    if (timed && (e = hipEventRecord(idx->ws.aev[1], s)) != hipSuccess) return e;
+    e = launch_codes_from_slab(idx->slab, idx->capacity, idx->lay.k, idx->lay.kp, first, n_sets, idx->codes, idx->cg,
+                               s);
+    if (e != hipSuccess) return e;
+    if (timed && (e = hipEventRecord(idx->ws.aev[2], s)) != hipSuccess) return e;
+    if (timed) idx->ws.aev_recorded = true;
+    return hipSuccess;
+}
+
 hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t n_q, const hoph_query_params *qp,
                       hoph_results *res, void *stream, QueryKind kind) {
     if (!cidx) return fail(HOPH_E_INVAL, "index is NULL");
@@ -316,7 +333,7 @@ hoph_status build_index(const hoph_sketch_params *params, const uint32_t *d_sigs
     idx->kpad = round4(params->k_group);
     idx->capacity = std::max<uint64_t>(64, (capacity + 63) / 64 * 64);
     idx->max_sets = capacity;
-    const uint64_t words = idx->capacity * idx->kpad * idx->lay.L;
+    const uint64_t words = idx->capacity * idx->lay.k;          // row-major signature words
     idx->cg = std::min<uint32_t>(kCodeGroups, idx->lay.L);
     const uint64_t code_words_total = idx->capacity * idx->cg * code_words(idx->lay.kp);
     auto release = [&] {
@@ -366,6 +383,25 @@ hoph_status index_append(hoph_index *idx, const uint32_t *d_sigs, uint64_t n_new
     return HOPH_OK;
 }
 
+hoph_status index_append_sets(hoph_index *idx, const uint32_t *d_ids, const uint64_t *d_offsets, uint64_t n_sets,
+                              void *hip_stream) {
+    g_last_error.clear();
+    if (!idx) return fail(HOPH_E_INVAL, "index is NULL");
+    if (n_sets == 0) return HOPH_OK;
+    if (!d_ids || !d_offsets) return fail(HOPH_E_INVAL, "d_ids / d_offsets is NULL");
+    std::lock_guard<std::mutex> lk(idx->mu);
+    if (idx->n + n_sets > idx->max_sets)
+        return fail(HOPH_E_CAPACITY, "index capacity " + std::to_string(idx->max_sets) + " exceeded");
+    DeviceGuard dg(idx->device);
+    uint32_t *errw = nullptr;
+    hoph_status st = device_err_word(&errw);
+    if (st) return st;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    HOPH_HIP(append_sets_async(idx, d_ids, d_offsets, n_sets, idx->n, errw, s, true), "sketch-into-index launch");
+    idx->n += n_sets;
+    return HOPH_OK;
+}
+
 uint64_t hoph_index_size(const hoph_index *idx) { return idx ? idx->n : 0; }
 
 hoph_status hoph_index_reset(hoph_index *idx) {
@@ -382,6 +418,20 @@ hoph_status hoph_query_timing(const hoph_index *idx, float ms[3]) {
     hoph_index *m = const_cast<hoph_index *>(idx);
     std::lock_guard<std::mutex> lk(m->mu);
     for (int i = 0; i < 3; ++i) ms[i] = m->ws.last_ms[i];
+    return HOPH_OK;
+}
+
+hoph_status hoph_append_timing(const hoph_index *idx, float ms[2]) {
+    g_last_error.clear();
+    if (!idx || !ms) return fail(HOPH_E_INVAL, "NULL argument");
+    hoph_index *m = const_cast<hoph_index *>(idx);
+    std::lock_guard<std::mutex> lk(m->mu);
+    ms[0] = ms[1] = 0.f;
+    if (!m->ws.aev_recorded) return HOPH_OK;
+    DeviceGuard dg(m->device);
+    HOPH_HIP(hipEventSynchronize(m->ws.aev[2]), "hipEventSynchronize");
+    (void)hipEventElapsedTime(&ms[0], m->ws.aev[0], m->ws.aev[1]);
+    (void)hipEventElapsedTime(&ms[1], m->ws.aev[1], m->ws.aev[2]);
     return HOPH_OK;
 }
 
@@ -562,6 +612,16 @@ hoph_status hoph_selftest_bins(const hoph_sketch_params *params, const uint32_t 
     std::vector<RegionEntry> reg(lay.n_regions + 1);
     for (uint32_t r = 0; r <= lay.n_regions; ++r)
         reg[r] = RegionEntry{lay.reg_start[r], r < lay.n_regions ? lay.reg_magic[r] : 0};
+    std::vector<uint32_t> s32(starts.begin(), starts.end()), rs(lay.reg_start.begin(), lay.reg_start.end());
+    std::vector<uint32_t> cells(2 * kLogCells), regs(2 * lay.n_regions);
+    if (lay.log_ok) {
+        for (uint32_t c = 0; c < kLogCells; ++c)
+            log_cell_entry(c, (uint32_t)lay.R, lay.reg_start.data(), lay.n_regions, cells[2 * c], cells[2 * c + 1]);
+        for (uint32_t r = 0; r < lay.n_regions; ++r) {
+            regs[2 * r] = (uint32_t)lay.reg_start[r];
+            regs[2 * r + 1] = lay.reg_mag32[r];
+        }
+    }
     for (uint64_t i = 0; i < n; ++i) {
         const uint64_t x = h_ids[i];
         if (x >= p.universe) return fail(HOPH_E_RANGE, "id >= universe");
@@ -570,9 +630,28 @@ hoph_status hoph_selftest_bins(const hoph_sketch_params *params, const uint32_t 
         else if (p.hash == HOPH_HASH_MODP31) v = psi_p31(x, p.hash_a, p.hash_b);
         else v = psi_p32(x, p.hash_a, p.hash_b);
         if (v >= lay.R) return fail(HOPH_E_RANGE, "table value >= universe");
+        // the region lookup always; the uniform estimate too where the device uses it
         uint32_t b;
         uint64_t start;
         locate(v, lut.data(), lay.lut_shift, reg.data(), lay.n_regions, lay.nb, starts.data(), b, start);
+        if (lay.est_ok) {
+            uint32_t be;
+            uint64_t se;
+            locate_est(v, lay.est_mul, lay.est_shift, starts.data(), be, se);
+            if (be != b || se != start) return fail(HOPH_E_UNSUPPORTED, "bin estimate and region lookup disagree");
+        }
+        if (lay.R < 0xFFFFFFFFull) {
+            // the narrow lookup the device uses when every value and start is 32-bit
+            uint32_t bn, sn;
+            locate_narrow((uint32_t)v, lut.data(), lay.lut_shift, rs.data(), lay.reg_mag32.data(), lay.n_regions,
+                          lay.nb, s32.data(), bn, sn);
+            if (bn != b || sn != start) return fail(HOPH_E_UNSUPPORTED, "narrow and wide bin lookups disagree");
+            if (lay.log_ok) {
+                locate_log((uint32_t)v, (uint32_t)(lay.R - 1), reinterpret_cast<const uint32_t(*)[2]>(cells.data()),
+                           reinterpret_cast<const uint32_t(*)[2]>(regs.data()), lay.nb, s32.data(), bn, sn);
+                if (bn != b || sn != start) return fail(HOPH_E_UNSUPPORTED, "log-cell and region lookups disagree");
+            }
+        }
         out_bin[i] = b;
         out_off[i] = (uint32_t)(v - start);
     }

@@ -39,8 +39,14 @@ struct SketchDesc {
     const uint32_t *perm;
     uint64_t universe, ha, hb, R;
     uint32_t hash, k, n_regions, lut_shift, lut_size, nb;   // nb = bins per region
+    // Uniform bin estimate (est_ok): est(v) = mulhi32(v >> est_shift, est_mul) is
+    // the bin of v or the bin before it, for every v < R (checked on the host
+    // against every bin start), so one read of a pair of bin starts settles it.
+    uint32_t est_mul, est_shift, est_ok;
+    uint32_t log_ok;     // regions by log-domain cells (see log_cell), narrow ranges only
     uint64_t reg_start[HOPH_MAX_GROUPS + 1];                 // reg_start[n_regions] = R
     uint64_t reg_magic[HOPH_MAX_GROUPS];                     // floor(2^64 nb / z_r), see bin_of
+    uint32_t reg_mag32[HOPH_MAX_GROUPS];                     // min(2^32 - 1, floor(2^32 nb / z_r))
 };
 
 // Host view of a validated layout.
@@ -49,7 +55,10 @@ struct LayoutInfo {
     uint32_t k = 0, kp = 0, L = 0, n_regions = 0, nb = 0, ra = 1, rb = 1;
     std::vector<uint64_t> reg_start;   // n_regions + 1
     std::vector<uint64_t> reg_magic;   // n_regions
+    std::vector<uint32_t> reg_mag32;   // n_regions
     uint32_t lut_shift = 0, lut_size = 0;
+    uint32_t est_mul = 0, est_shift = 0, est_ok = 0;   // see SketchDesc
+    uint32_t log_ok = 0;                               // see SketchDesc
 };
 
 // ---------------------------------------------------------------------------
@@ -104,12 +113,17 @@ __host__ __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b) {
     return (uint64_t)(((unsigned __int128)a * b) >> 64);
 }
 
-// (a x + b) mod (2^31 - 1) for x, a, b < 2^31 - 1: Mersenne folding.
+// (a x + b) mod (2^31 - 1) for x, a, b < 2^31 - 1: Mersenne folding.  With
+// P = 2^31 - 1, w = a x + b <= P (P - 1) < 2^62, and w = (w >> 31) + (w & P)
+// (mod P) where both parts are < 2^31, so every step after the one 64-bit
+// multiply-add is 32-bit.
 __host__ __device__ inline uint64_t psi_p31(uint64_t x, uint64_t a, uint64_t b) {
-    uint64_t v = a * x + b;                       // < 2^62 + 2^31
-    v = (v & kP31) + (v >> 31);                   // < 2^32 + 2
-    v = (v & kP31) + (v >> 31);                   // < 2^31 + 2
-    return v >= kP31 ? v - kP31 : v;
+    const uint64_t w = (uint64_t)(uint32_t)a * (uint32_t)x + b;   // one 32 x 32 -> 64 multiply-add
+    const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
+    uint32_t s = (lo & 0x7FFFFFFFu) + ((hi << 1) | (lo >> 31));    // <= 2^32 - 2
+    s = (s & 0x7FFFFFFFu) + (s >> 31);                              // <= P + 1
+    const uint32_t t = s - 0x7FFFFFFFu;                               // wraps above s when s < P
+    return t < s ? t : s;
 }
 
 // (a x + b) mod (2^32 + 15) for x < 2^32, a, b < 2^32 + 15, using 2^32 = -15 (mod p).
@@ -139,8 +153,9 @@ struct RegionEntry {
 //    estimate floor(y M / 2^64) is t or t - 1 (y < 2^34), and one comparison
 //    with the next bin start settles it.
 // reg has n_regions + 1 entries (the last holds start = R); starts has k + 1.
+template <typename S>
 __host__ __device__ inline void locate(uint64_t v, const uint8_t *lut, uint32_t lut_shift, const RegionEntry *reg,
-                                       uint32_t n_regions, uint32_t nb, const uint64_t *starts, uint32_t &bin,
+                                       uint32_t n_regions, uint32_t nb, const S *starts, uint32_t &bin,
                                        uint64_t &start) {
     uint32_t r = 0;
     if (n_regions > 1) {
@@ -149,6 +164,100 @@ __host__ __device__ inline void locate(uint64_t v, const uint8_t *lut, uint32_t 
     }
     const RegionEntry re = reg[r];
     const uint32_t b = r * nb + (uint32_t)mulhi64(v - re.start, re.magic);
+    const uint64_t s0 = starts[b], s1 = starts[b + 1];
+    const bool up = v >= s1;
+    bin = b + (up ? 1u : 0u);
+    start = up ? s1 : s0;
+}
+
+// Narrow bin lookup, for a permuted range below 2^32 - 1 (every value and start
+// is 32-bit): the region as in locate(), then t' = floor(y M32 / 2^32) with
+// M32 = floor(2^32 nb / z) (capped at 2^32 - 1) and y = v - start < 2^31: since
+// y nb / z - y M32 / 2^32 < y / 2^32 < 1, t' is the bin t = floor(y nb / z)
+// inside the region or t - 1, and the next bin start settles it.
+__host__ __device__ inline void locate_narrow(uint32_t v, const uint8_t *lut, uint32_t lut_shift,
+                                              const uint32_t *rstart, const uint32_t *rmag, uint32_t n_regions,
+                                              uint32_t nb, const uint32_t *starts, uint32_t &bin, uint32_t &start) {
+    uint32_t r = 0;
+    if (n_regions > 1) {
+        r = lut[v >> lut_shift];
+        while (r + 1 < n_regions && v >= rstart[r + 1]) ++r;
+    }
+    const uint32_t y = v - rstart[r];
+    const uint32_t b = r * nb + (uint32_t)(((uint64_t)y * rmag[r]) >> 32);
+    const uint32_t s0 = starts[b], s1 = starts[b + 1];
+    const bool up = v >= s1;
+    bin = b + (up ? 1u : 0u);
+    start = up ? s1 : s0;
+}
+
+// Log-domain cells of a narrow permuted range, for regions that shrink
+// geometrically towards the top (a:b HOPH): with u = max(R - 1 - v, 1), a cell
+// is the position e of the leading one of u and the four bits after it,
+// cell = 16 e + m (at most 512 cells, non-increasing in v).  When no cell holds two
+// region boundaries, a cell's first region and its one inner boundary give the
+// region of v with one comparison.
+constexpr uint32_t kLogCells = 512;     // every u < 2^32
+
+__host__ __device__ inline uint32_t clz32(uint32_t u) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return (uint32_t)__clz((int)u);
+#else
+    return u ? (uint32_t)__builtin_clz(u) : 32u;
+#endif
+}
+
+__host__ __device__ inline uint32_t log_cell(uint32_t v, uint32_t R1) {
+    uint32_t u = R1 - v;
+    u = u > 1u ? u : 1u;
+    const uint32_t lz = clz32(u);
+    return (31u - lz) * 16u + ((u << lz) >> 27 & 15u);
+}
+
+// Cell table entry c: {first region of the cell, start of the next region if
+// it lies inside the cell, else 0xFFFFFFFF}.  reg_start has n_regions + 1
+// entries (the last is R); the smallest v of a cell is found by bisection
+// (the cell index does not increase with v).
+template <typename Reg>
+__host__ __device__ inline void log_cell_entry(uint32_t c, uint32_t R, const Reg *reg_start, uint32_t n_regions,
+                                               uint32_t &first, uint32_t &bound) {
+    const uint32_t R1 = R - 1;
+    uint32_t lo = 0, hi = R;                 // smallest v with cell(v) <= c, or R
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (log_cell(mid, R1) <= c) hi = mid; else lo = mid + 1;
+    }
+    uint32_t r = 0;
+    if (lo < R)
+        while (r + 1 < n_regions && lo >= (uint32_t)reg_start[r + 1]) ++r;
+    first = r;
+    bound = 0xFFFFFFFFu;
+    if (lo < R && r + 1 < n_regions && log_cell((uint32_t)reg_start[r + 1], R1) == c) bound = (uint32_t)reg_start[r + 1];
+}
+
+// Narrow bin lookup with the cell table (cells: {first, bound}) and the region
+// table (regs: {start, 32-bit reciprocal}); see locate_narrow for the bin step.
+__host__ __device__ inline void locate_log(uint32_t v, uint32_t R1, const uint32_t (*cells)[2],
+                                           const uint32_t (*regs)[2], uint32_t nb, const uint32_t *starts,
+                                           uint32_t &bin, uint32_t &start) {
+    const uint32_t c = log_cell(v, R1);
+    const uint32_t r = cells[c][0] + (v >= cells[c][1] ? 1u : 0u);
+    const uint32_t y = v - regs[r][0];
+    const uint32_t b = r * nb + (uint32_t)(((uint64_t)y * regs[r][1]) >> 32);
+    const uint32_t s0 = starts[b], s1 = starts[b + 1];
+    const bool up = v >= s1;
+    bin = b + (up ? 1u : 0u);
+    start = up ? s1 : s0;
+}
+
+// Bin of v by the uniform estimate: est(v) is the bin of v or the one before.
+__host__ __device__ inline uint32_t bin_estimate(uint64_t v, uint32_t mul, uint32_t shift) {
+    return (uint32_t)(((uint64_t)(uint32_t)(v >> shift) * mul) >> 32);
+}
+template <typename S>
+__host__ __device__ inline void locate_est(uint64_t v, uint32_t mul, uint32_t shift, const S *starts, uint32_t &bin,
+                                           uint64_t &start) {
+    const uint32_t b = bin_estimate(v, mul, shift);
     const uint64_t s0 = starts[b], s1 = starts[b + 1];
     const bool up = v >= s1;
     bin = b + (up ? 1u : 0u);
@@ -185,8 +294,11 @@ hipError_t launch_sketch_chunked(const SketchDesc &d, const uint32_t *ids, const
                                  const uint64_t *desc, uint64_t *prefix, uint32_t chunk, uint32_t max_sets,
                                  uint64_t max_ids, uint32_t *sigs, uint32_t *err_flag, uint32_t waves_per_cu,
                                  hipStream_t st);
-// Stores rows [first, first + n_new) into the slabs and, when codes is not
-// null, the code planes of the first cg groups (layout in k_index.hip).
+// Code planes of index rows [first, first + n_new) from the rows themselves.
+hipError_t launch_codes_from_slab(const uint32_t *slab, uint64_t capacity, uint32_t k, uint32_t kp, uint64_t first,
+                                  uint64_t n_new, uint32_t *codes, uint32_t cg, hipStream_t st);
+// Copies signature rows into index rows [first, first + n_new) and, when codes
+// is not null, writes the code planes of the first cg groups (layout in k_index.hip).
 hipError_t launch_index_store(const uint32_t *sigs, uint64_t n_new, uint64_t first, uint32_t k,
                               uint32_t kp, uint32_t L, uint32_t kpad, uint64_t capacity,
                               uint32_t *slab, uint32_t *codes, uint32_t cg, hipStream_t st);
@@ -196,7 +308,7 @@ hipError_t launch_pair_counts(const uint32_t *slab, uint64_t capacity, uint64_t 
                               uint32_t *e, hipStream_t st);
 
 struct ScanLaunch {
-    const uint32_t *slab;       // index slabs (see k_index.hip for the layout)
+    const uint32_t *slab;       // index rows, k words per set (see k_index.hip)
     uint64_t capacity;          // sets the slab can hold (multiple of 64)
     uint64_t n_sets;
     uint32_t kpad, kp, L, k;

@@ -23,6 +23,8 @@ static uint64_t range_of(const hoph_sketch_params &p) {
     return kP32;
 }
 
+void choose_estimate(LayoutInfo &lay);
+
 hoph_status build_layout(const hoph_sketch_params &p, LayoutInfo &out, std::string &err) {
     if (p.layout != HOPH_LAYOUT_OPH && p.layout != HOPH_LAYOUT_HIER) { err = "unknown layout"; return HOPH_E_INVAL; }
     if (p.k_group == 0 || p.k_group > HOPH_MAX_KGROUP) { err = "k_group must be in [1, 64]"; return HOPH_E_INVAL; }
@@ -85,13 +87,53 @@ hoph_status build_layout(const hoph_sketch_params &p, LayoutInfo &out, std::stri
         if ((size[r] + L.nb - 1) / L.nb > 0xFFFFFFFFull) { err = "a bin is wider than 2^32 - 1 values"; return HOPH_E_INVAL; }
         uint64_t M = (size[r] == L.nb) ? ~0ull : (uint64_t)(((u128)L.nb << 64) / size[r]);
         L.reg_magic.push_back(M);
+        const uint64_t M32 = (uint64_t)(((u128)L.nb << 32) / size[r]);
+        L.reg_mag32.push_back((uint32_t)std::min<uint64_t>(M32, 0xFFFFFFFFull));
     }
     uint32_t sh = 0;
     while (((R - 1) >> sh) >= kLutMax) ++sh;
     L.lut_shift = sh;
     L.lut_size = (uint32_t)((R - 1) >> sh) + 1;
+    choose_estimate(L);
+    // log-domain cells: a narrow range with regions, no cell holding two boundaries
+    L.log_ok = 0;
+    if (L.n_regions > 1 && R < 0xFFFFFFFFull) {
+        bool ok = true;
+        const uint32_t R1 = (uint32_t)(R - 1);
+        for (uint32_t r = 1; r + 1 < L.n_regions && ok; ++r)
+            ok = log_cell((uint32_t)(L.reg_start[r] - 1), R1) != log_cell((uint32_t)L.reg_start[r + 1], R1);
+        L.log_ok = ok ? 1u : 0u;
+    }
     out = std::move(L);
     return HOPH_OK;
+}
+
+// The uniform bin estimate: a 32-bit reciprocal of R / k such that, for the
+// first and last value of every non-empty bin b, the estimate is b or b - 1
+// (the estimate is monotone in v, so every value of the bin then is too).
+void choose_estimate(LayoutInfo &lay) {
+    lay.est_ok = 0;
+    std::vector<uint64_t> starts;
+    host_starts(lay, starts);
+    const uint32_t sh = lay.R > (1ull << 32) ? 1u : 0u;        // v >> sh fits 32 bits for v < R
+    const uint64_t Rs = (lay.R + (1ull << sh) - 1) >> sh;
+    if (Rs <= lay.k) return;
+    const uint64_t M0 = (uint64_t)(((u128)lay.k << 32) / Rs);
+    for (uint64_t t = 0; t < 64 && t <= M0; ++t) {
+        const uint32_t M = (uint32_t)(M0 - t);
+        bool ok = true;
+        for (uint32_t b = 0; b < lay.k && ok; ++b) {
+            if (starts[b + 1] <= starts[b]) continue;                // empty bin: no value lands here
+            const int64_t lo = bin_estimate(starts[b], M, sh), hi = bin_estimate(starts[b + 1] - 1, M, sh);
+            ok = lo >= (int64_t)b - 1 && hi <= (int64_t)b;
+        }
+        if (ok) {
+            lay.est_mul = M;
+            lay.est_shift = sh;
+            lay.est_ok = 1;
+            return;
+        }
+    }
 }
 
 void fill_sketch_desc(const hoph_sketch_params &p, const LayoutInfo &lay, SketchDesc &d) {
@@ -107,8 +149,13 @@ void fill_sketch_desc(const hoph_sketch_params &p, const LayoutInfo &lay, Sketch
     d.lut_shift = lay.lut_shift;
     d.lut_size = lay.lut_size;
     d.nb = lay.nb;
+    d.est_mul = lay.est_mul;
+    d.est_shift = lay.est_shift;
+    d.est_ok = lay.est_ok;
+    d.log_ok = lay.log_ok;
     for (uint32_t r = 0; r <= lay.n_regions; ++r) d.reg_start[r] = lay.reg_start[r];
     for (uint32_t r = 0; r < lay.n_regions; ++r) d.reg_magic[r] = lay.reg_magic[r];
+    for (uint32_t r = 0; r < lay.n_regions; ++r) d.reg_mag32[r] = lay.reg_mag32[r];
 }
 
 void host_lut(const LayoutInfo &lay, std::vector<uint8_t> &lut) {

@@ -1,18 +1,11 @@
-// Index build: signatures (row-major, one row of k words per set) are stored
-// group by group (the comparison order of Sec. 3.3 / Sec. 4.1) in slabs whose
-// tiles hold 64 sets -- one wavefront -- with the words of a bin quad of the 64
-// sets contiguous:
-//   word (set s, group g, bin i) at
-//   slab[g * capacity * kpad + (s / 64) * kpad * 64 + (i / 4) * 256 + (s % 64) * 4 + i % 4]
-// so that a wavefront reads a tile's group with fully coalesced 16-byte loads,
-// one set per lane.  kpad = k' rounded up to 4; pad words hold EMPTY and are
-// never compared.
-//
-// Code planes of the first cg groups (8-bit bin codes, see bin_code), PW =
-// code_words(k') words per (set, group), plane p of bins [32 w, 32 w + 32) at
-// word p * W + w (W = PW / 8):
-//   codes[((g * (capacity / 64) + s / 64) * 64 + s % 64) * PW + p * W + w]
-// so that a wavefront reads a tile's planes as one contiguous 64 * PW-word run.
+// Index storage.  The signature words are kept row-major, one row of k words
+// per set, word (set s, bin b) at slab[s * k + b]: a set is sketched straight
+// into its row, and the per-pair pass reads one group of one row as a
+// contiguous run.  The coarse pass reads the narrowed code planes of the
+// first cg groups instead, which are tiled so that a wavefront (one set per
+// lane) reads them coalesced: PW = code_words(k') words per (set, group),
+// plane p of bins [32 w, 32 w + 32) at word p * W + w (W = PW / 8),
+//   codes[((g * (capacity / 64) + s / 64) * 64 + s % 64) * PW + p * W + w].
 #include "hoph_internal.h"
 
 namespace hoph {
@@ -26,11 +19,6 @@ __global__ __launch_bounds__(kThreads) void fill_u64_kernel(uint64_t *p, uint64_
         p[i] = value;
 }
 
-// 16-byte path: k' and k multiples of 4, source 16-byte aligned.
-// One thread per set writes the whole row group by group, so that each
-// group's contiguous piece of a signature row is read by one wavefront (one
-// XCD's L2) and each 16-byte store instruction of a wavefront covers 1 KB of
-// the tile contiguously.  NQ = k' / 4 when known at compile time, else 0.
 // Code planes of NQ * 4 bins held as NQ uint4, written as PW contiguous words.
 template <int NQ>
 __device__ __forceinline__ void store_code_planes(const uint4 *v, uint32_t *__restrict__ dst) {
@@ -54,41 +42,28 @@ __device__ __forceinline__ void store_code_planes(const uint4 *v, uint32_t *__re
     for (int j = 0; j < 2 * W; ++j) d4[j] = make_uint4(pl[4 * j], pl[4 * j + 1], pl[4 * j + 2], pl[4 * j + 3]);
 }
 
+// Code planes for k' = 4 NQ with k a multiple of 4: one thread per (group < cg,
+// row), consecutive rows in consecutive lanes; a group of a row is read as NQ
+// 16-byte loads.  sigs row r is index row first + r.
 template <int NQ>
-__global__ __launch_bounds__(kThreads) void index_store_vec(const uint32_t *__restrict__ sigs, uint64_t n_new,
-                                                           uint64_t first, uint32_t k, uint32_t kp, uint32_t L,
-                                                           uint64_t capacity, uint64_t tile0, uint64_t ntiles,
-                                                           uint32_t *__restrict__ slab, uint32_t *__restrict__ codes,
-                                                           uint32_t cg) {
-    const uint32_t nq = NQ ? NQ : kp / 4;
-    const uint64_t total = ntiles * 64;
+__global__ __launch_bounds__(kThreads) void row_codes_vec_kernel(const uint32_t *__restrict__ sigs, uint64_t n_new,
+                                                                uint64_t first, uint32_t k, uint64_t capacity,
+                                                                uint32_t cg, uint32_t *__restrict__ codes) {
+    constexpr uint32_t PW = kCodeBits * (NQ > 8 ? 2 : 1);
+    const uint64_t total = n_new * cg;
     for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < total; i += (uint64_t)gridDim.x * kThreads) {
-        const uint64_t s = tile0 * 64 + i;
-        if (s < first || s >= first + n_new) continue;
-        const uint64_t t = s >> 6;
-        const uint32_t lane = (uint32_t)(s & 63);
-        const uint4 *src = reinterpret_cast<const uint4 *>(sigs + (s - first) * k);
-        for (uint32_t g = 0; g < L; ++g) {
-            uint4 *dst = reinterpret_cast<uint4 *>(slab + (uint64_t)g * capacity * kp + t * kp * 64) + lane;
-            if constexpr (NQ > 0) {
-                uint4 v[NQ];
+        const uint32_t g = (uint32_t)(i / n_new);
+        const uint64_t r = i - (uint64_t)g * n_new, s = first + r;
+        const uint4 *src = reinterpret_cast<const uint4 *>(sigs + r * k + (uint64_t)g * 4 * NQ);
+        uint4 v[NQ];
 #pragma unroll
-                for (int u = 0; u < NQ; ++u) v[u] = src[g * NQ + u];
-#pragma unroll
-                for (int u = 0; u < NQ; ++u) dst[u * 64] = v[u];
-                if (codes && g < cg) {
-                    constexpr uint32_t PW = kCodeBits * (NQ > 8 ? 2 : 1);
-                    store_code_planes<NQ>(v, codes + (((uint64_t)g * (capacity / 64) + t) * 64 + lane) * PW);
-                }
-            } else {
-                for (uint32_t u = 0; u < nq; ++u) dst[u * 64] = src[g * nq + u];
-            }
-        }
+        for (int u = 0; u < NQ; ++u) v[u] = src[u];
+        store_code_planes<NQ>(v, codes + (((uint64_t)g * (capacity / 64) + (s >> 6)) * 64 + (s & 63)) * PW);
     }
 }
 
-// Code planes for any k' (used where the 16-byte path does not write them):
-// one thread per (set, group < cg).
+// Code planes of rows [first, first + n_new) from their signature rows (sigs
+// row r is index row first + r), any k': one thread per (set, group < cg).
 __global__ __launch_bounds__(kThreads) void index_codes_kernel(const uint32_t *__restrict__ sigs, uint64_t n_new,
                                                               uint64_t first, uint32_t k, uint32_t kp,
                                                               uint64_t capacity, uint32_t cg,
@@ -96,8 +71,8 @@ __global__ __launch_bounds__(kThreads) void index_codes_kernel(const uint32_t *_
     const uint32_t W = code_plane_words(kp), PW = code_words(kp);
     const uint64_t total = n_new * cg;
     for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < total; i += (uint64_t)gridDim.x * kThreads) {
-        const uint64_t r = i / cg;
-        const uint32_t g = (uint32_t)(i % cg);
+        const uint32_t g = (uint32_t)(i / n_new);
+        const uint64_t r = i - (uint64_t)g * n_new;
         const uint64_t s = first + r;
         const uint32_t *row = sigs + r * k + (uint64_t)g * kp;
         uint32_t lo[kCodeBits], hi[kCodeBits];
@@ -119,28 +94,6 @@ __global__ __launch_bounds__(kThreads) void index_codes_kernel(const uint32_t *_
             dst[p * W] = lo[p];
             if (W == 2) dst[p * W + 1] = hi[p];
         }
-    }
-}
-
-// word path for any k'
-__global__ __launch_bounds__(kThreads) void index_store_word(const uint32_t *__restrict__ sigs, uint64_t n_new,
-                                                            uint64_t first, uint32_t k, uint32_t kp, uint32_t kpad,
-                                                            uint32_t L, uint64_t capacity, uint64_t tile0,
-                                                            uint64_t ntiles, uint32_t *__restrict__ slab) {
-    const uint64_t total = (uint64_t)L * ntiles * kpad * 64;
-    for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < total; i += (uint64_t)gridDim.x * kThreads) {
-        const uint32_t w = (uint32_t)(i & 3);
-        const uint32_t lane = (uint32_t)((i >> 2) & 63);
-        uint64_t rest = i >> 8;
-        const uint32_t qd = (uint32_t)(rest % (kpad / 4));
-        rest /= (kpad / 4);
-        const uint64_t t = tile0 + rest % ntiles;
-        const uint32_t g = (uint32_t)(rest / ntiles);
-        const uint64_t s = t * 64 + lane;
-        if (s < first || s >= first + n_new) continue;
-        const uint32_t bin = qd * 4 + w;
-        const uint32_t v = bin < kp ? sigs[(s - first) * k + (uint64_t)g * kp + bin] : HOPH_EMPTY;
-        slab[(uint64_t)g * capacity * kpad + t * kpad * 64 + qd * 256 + lane * 4 + w] = v;
     }
 }
 
@@ -166,7 +119,7 @@ __global__ __launch_bounds__(kThreads) void pair_counts_kernel(const uint32_t *_
             const bool in = lane < kp;
             uint32_t sw = 0, qv = 0;
             if (in) {
-                sw = slab[(uint64_t)g * capacity * kpad + (s / 64) * kpad * 64 + (lane / 4) * 256 + (s % 64) * 4 + lane % 4];
+                sw = slab[s * k + (uint64_t)g * kp + lane];
                 qv = qsigs[q * k + (uint64_t)g * kp + lane];
             }
             const uint64_t eqb = __ballot(in && sw == qv);
@@ -219,38 +172,29 @@ hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t value, hipStream_t 
 hipError_t launch_index_store(const uint32_t *sigs, uint64_t n_new, uint64_t first, uint32_t k, uint32_t kp,
                               uint32_t L, uint32_t kpad, uint64_t capacity, uint32_t *slab, uint32_t *codes,
                               uint32_t cg, hipStream_t st) {
+    (void)L;
+    (void)kpad;
     if (n_new == 0) return hipSuccess;
-    const uint64_t tile0 = first / 64, tile1 = (first + n_new - 1) / 64;
-    const uint64_t ntiles = tile1 - tile0 + 1;
-    const bool vec = (kp % 4 == 0) && (k % 4 == 0) && ((reinterpret_cast<uintptr_t>(sigs) & 15u) == 0);
-    if (vec) {
-        const dim3 grid(grid_for(ntiles * 64, kThreads)), block(kThreads);
-        if (kp == 16)
-            hipLaunchKernelGGL(index_store_vec<4>, grid, block, 0, st, sigs, n_new, first, k, kp, L, capacity, tile0,
-                               ntiles, slab, codes, cg);
-        else if (kp == 32)
-            hipLaunchKernelGGL(index_store_vec<8>, grid, block, 0, st, sigs, n_new, first, k, kp, L, capacity, tile0,
-                               ntiles, slab, codes, cg);
-        else if (kp == 64)
-            hipLaunchKernelGGL(index_store_vec<16>, grid, block, 0, st, sigs, n_new, first, k, kp, L, capacity, tile0,
-                               ntiles, slab, codes, cg);
-        else
-            hipLaunchKernelGGL(index_store_vec<0>, grid, block, 0, st, sigs, n_new, first, k, kp, L, capacity, tile0,
-                               ntiles, slab, nullptr, 0u);
-    } else {
-        const uint64_t total = (uint64_t)L * ntiles * kpad * 64;
-        hipLaunchKernelGGL(index_store_word, dim3(grid_for(total, kThreads)), dim3(kThreads), 0, st, sigs, n_new,
-                           first, k, kp, kpad, L, capacity, tile0, ntiles, slab);
-    }
-    hipError_t e = hipGetLastError();
+    hipError_t e = hipMemcpyAsync(slab + first * k, sigs, n_new * k * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return e;
-    const bool fused = vec && (kp == 16 || kp == 32 || kp == 64);
-    if (codes && cg && !fused) {
-        hipLaunchKernelGGL(index_codes_kernel, dim3(grid_for(n_new * cg, kThreads)), dim3(kThreads), 0, st, sigs,
-                           n_new, first, k, kp, capacity, cg, codes);
-        e = hipGetLastError();
-    }
-    return e;
+    return launch_codes_from_slab(slab, capacity, k, kp, first, n_new, codes, cg, st);
+}
+
+hipError_t launch_codes_from_slab(const uint32_t *slab, uint64_t capacity, uint32_t k, uint32_t kp, uint64_t first,
+                                  uint64_t n_new, uint32_t *codes, uint32_t cg, hipStream_t st) {
+    if (n_new == 0 || cg == 0 || !codes) return hipSuccess;
+    const dim3 grid(grid_for(n_new * cg, kThreads)), block(kThreads);
+    const uint32_t *rows = slab + first * k;
+    const bool vec = (k % 4) == 0;
+    if (vec && kp == 16)
+        hipLaunchKernelGGL(row_codes_vec_kernel<4>, grid, block, 0, st, rows, n_new, first, k, capacity, cg, codes);
+    else if (vec && kp == 32)
+        hipLaunchKernelGGL(row_codes_vec_kernel<8>, grid, block, 0, st, rows, n_new, first, k, capacity, cg, codes);
+    else if (vec && kp == 64)
+        hipLaunchKernelGGL(row_codes_vec_kernel<16>, grid, block, 0, st, rows, n_new, first, k, capacity, cg, codes);
+    else
+        hipLaunchKernelGGL(index_codes_kernel, grid, block, 0, st, rows, n_new, first, k, kp, capacity, cg, codes);
+    return hipGetLastError();
 }
 
 hipError_t launch_pair_counts(const uint32_t *slab, uint64_t capacity, uint64_t n_sets, uint32_t kpad, uint32_t kp,

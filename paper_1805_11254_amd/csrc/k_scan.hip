@@ -49,6 +49,28 @@ __device__ __forceinline__ uint64_t wave_append(bool flag, unsigned long long *c
     return base + lane_rank(bal, lane);
 }
 
+// One group of one set row (row-major words) into registers; pad words
+// (k' not a multiple of 4) read as EMPTY.  16-byte loads when k' and k are
+// multiples of 4 (EXACT and vec).
+template <int KPAD, bool EXACT>
+__device__ __forceinline__ void load_group_row(const uint32_t *__restrict__ row, uint32_t kp, bool vec,
+                                               uint32_t (&w)[KPAD]) {
+    if (EXACT && vec) {
+        const uint4 *r4 = reinterpret_cast<const uint4 *>(row);
+#pragma unroll
+        for (int qd = 0; qd < KPAD / 4; ++qd) {
+            const uint4 v = r4[qd];
+            w[4 * qd + 0] = v.x;
+            w[4 * qd + 1] = v.y;
+            w[4 * qd + 2] = v.z;
+            w[4 * qd + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < KPAD; ++i) w[i] = (EXACT || i < (int)kp) ? row[i] : HOPH_EMPTY;
+    }
+}
+
 // lambda * rate of one group (Eq. 6 per group) from the counts.
 __device__ __forceinline__ int64_t group_rho(uint32_t eq, uint32_t ej, uint32_t ee, uint32_t kp, uint32_t policy,
                                              const int64_t *dmul, int64_t lambda) {
@@ -295,7 +317,7 @@ __global__ __launch_bounds__(kThreads) void scan_coarse_kernel(const uint32_t *_
     const uint64_t wstride = (uint64_t)gridDim.x * kWaves;
     const uint32_t kp = EXACT ? KPAD : a.kp;
     const uint64_t kpmask = kp >= 64 ? ~0ull : ((1ull << kp) - 1ull);
-    const uint64_t gstride = a.capacity * KPAD;
+    const bool vec = (a.k & 3u) == 0;
     const uint32_t policy = a.policy;
     for (uint64_t item = (uint64_t)blockIdx.x * kWaves + wave_id_in_block(); item < n_items; item += wstride) {
     const uint64_t tile = item % ntiles;
@@ -307,15 +329,9 @@ __global__ __launch_bounds__(kThreads) void scan_coarse_kernel(const uint32_t *_
     uint64_t emask[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(slab + g * gstride + tile * (KPAD * 64)) + lane;
-#pragma unroll
-        for (int qd = 0; qd < KPAD / 4; ++qd) {
-            const uint4 v = src[qd * 64];
-            w[g][4 * qd + 0] = v.x;
-            w[g][4 * qd + 1] = v.y;
-            w[g][4 * qd + 2] = v.z;
-            w[g][4 * qd + 3] = v.w;
-        }
+        // this lane's set row (rows up to the capacity exist, so rows past the
+        // last set are read and then ignored)
+        load_group_row<KPAD, EXACT>(slab + s * a.k + (uint64_t)g * kp, kp, vec, w[g]);
         uint64_t em = 0;
 #pragma unroll
         for (int i = 0; i < KPAD; ++i) em |= (uint64_t)(w[g][i] == HOPH_EMPTY) << i;
@@ -406,7 +422,7 @@ __global__ __launch_bounds__(kThreads) void scan_fine_kernel(const uint32_t *__r
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t nw = (uint64_t)gridDim.x * kWaves;
     const uint64_t n = min((uint64_t)counters[0], a.surv_cap);
-    const uint32_t kp = a.kp, kpad = a.kpad;
+    const uint32_t kp = a.kp;
     const bool in = lane < kp;
     for (uint64_t idx = (uint64_t)blockIdx.x * kWaves + wave_id_in_block(); idx < n; idx += nw) {
         const Survivor sv = surv[idx];
@@ -414,11 +430,11 @@ __global__ __launch_bounds__(kThreads) void scan_fine_kernel(const uint32_t *__r
         bool accept = false;
         const uint64_t s = sv.s;
         const uint32_t *qw = qsigs + (uint64_t)sv.q * a.k;
-        const uint32_t *sb = slab + (s / 64) * kpad * 64 + (lane / 4) * 256 + (s % 64) * 4 + (lane & 3);
+        const uint32_t *sb = slab + s * a.k + lane;
         for (uint32_t g = a.depth; g < a.L; ++g) {
             uint32_t sw = 0, qv = 0;
             if (in) {
-                sw = sb[(uint64_t)g * a.capacity * kpad];
+                sw = sb[g * kp];
                 qv = qw[g * kp + lane];
             }
             const uint64_t eqb = __ballot(in && sw == qv);
@@ -455,19 +471,19 @@ __global__ __launch_bounds__(kThreads) void oph_full_kernel(const uint32_t *__re
     const uint64_t s = tile * 64 + lane;
     const bool valid = s < a.n_sets;
     const uint32_t kp = EXACT ? KPAD : a.kp, k = a.k;
-    const uint64_t gstride = a.capacity * KPAD;
+    const bool vec = (k & 3u) == 0;
     const uint32_t qa = a.q0 + chunk * a.q_per_wave;
     const uint32_t qb = min(a.q1, qa + a.q_per_wave);
     for (uint32_t q = qa; q < qb; ++q) {
         const uint32_t *qw = qsigs + (uint64_t)q * k;
         uint32_t eq = 0, ej = 0, ee = 0;
         for (uint32_t g = 0; g < a.L; ++g) {
-            const uint4 *src = reinterpret_cast<const uint4 *>(slab + g * gstride + tile * (KPAD * 64)) + lane;
+            uint32_t row[KPAD];
+            load_group_row<KPAD, EXACT>(slab + s * k + (uint64_t)g * kp, kp, vec, row);
             const uint32_t *qg = qw + g * kp;
 #pragma unroll
             for (int qd = 0; qd < KPAD / 4; ++qd) {
-                const uint4 v = src[qd * 64];
-                const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
+                const uint32_t vv[4] = {row[4 * qd], row[4 * qd + 1], row[4 * qd + 2], row[4 * qd + 3]};
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int i = 4 * qd + t;

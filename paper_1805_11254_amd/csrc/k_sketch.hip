@@ -3,12 +3,23 @@
 // range, and each bin keeps its smallest offset from the bin start.
 //
 // One wavefront per set, persistent over sets (no workgroup barrier inside the
-// set loop).  The bin-start table, the region table and the region lookup
-// table are built once per workgroup in LDS; each wavefront owns a k-word LDS
-// signature updated with ds_min (the minimum is order-free, so the order of
-// lanes does not matter) and written back with 16-byte stores.  Element ids
-// are read with unconditional (clamped) coalesced loads, four per lane in
-// flight.
+// set loop).  The bin-start table (32-bit where the permuted range fits) and,
+// for layouts that need it, the region table and the region lookup table are
+// built once per workgroup in LDS; each wavefront owns a k-word LDS signature
+// updated with ds_min (the minimum is order-free, so the order of lanes does
+// not matter) and written back with 16-byte stores.  Element ids are read with
+// unconditional (clamped) coalesced loads, four per lane, and the next four
+// are in flight while the current ones are hashed and binned.  The element
+// path is straight-line code (out-of-range lanes are masked, only the LDS
+// minimum is predicated) so the loads of the four elements interleave.
+//
+// Bin lookup: where the bins are near-uniform (plain OPH, a:b = 1:1 HOPH) a
+// 32-bit reciprocal estimate gives the bin or the one before it and one read of
+// a pair of bin starts settles it (LOC_EST); otherwise the region of v comes
+// from the lookup table and the region's own reciprocal (LOC_REGION).
+#include <algorithm>
+#include <type_traits>
+
 #include "hoph_internal.h"
 
 namespace hoph {
@@ -28,91 +39,247 @@ __device__ __forceinline__ uint64_t permute(uint64_t x, const SketchDesc &d) {
     }
 }
 
+constexpr int LOC_EST = 0, LOC_REGION = 1, LOC_LOG = 2;
+
+// The (a x + b) mod (2^31 - 1) hash keeps every value, bin start and region
+// start in 32 bits (NARROW); the other hashes keep 64-bit values and starts.
+template <uint32_t HASH>
+constexpr bool kNarrow = HASH == HOPH_HASH_MODP31;
+template <uint32_t HASH>
+using StartT = typename std::conditional<kNarrow<HASH>, uint32_t, uint64_t>::type;
+
 // LDS layout of one workgroup (byte offsets, all 16-byte aligned).
 struct SketchLds {
     uint32_t starts, reg, lut, sigs, sig_stride, total;
 };
 
-__host__ __device__ inline SketchLds sketch_lds(uint32_t k, uint32_t nr, uint32_t lut_size, uint32_t waves) {
+__host__ __device__ inline SketchLds sketch_lds(uint32_t k, uint32_t nr, uint32_t lut_size, uint32_t waves,
+                                                bool narrow, int loc) {
     SketchLds l;
     l.starts = 0;
-    l.reg = (8u * (k + 1) + 15u) & ~15u;
-    l.lut = l.reg + 16u * (nr + 1);
-    l.sigs = (l.lut + (nr > 1 ? lut_size : 0u) + 15u) & ~15u;
+    l.reg = ((narrow ? 4u : 8u) * (k + 1) + 15u) & ~15u;
+    uint32_t reg_bytes = 0, lut_bytes = 0;
+    if (loc == LOC_REGION) {
+        reg_bytes = narrow ? (8u * nr + 4u + 15u) & ~15u : 16u * (nr + 1);
+        lut_bytes = nr > 1 ? lut_size : 0u;
+    } else if (loc == LOC_LOG) {
+        reg_bytes = 8u * nr;                       // {start, 32-bit reciprocal}
+        lut_bytes = 8u * kLogCells;                // {first region, inner boundary}
+    }
+    l.lut = (l.reg + reg_bytes + 15u) & ~15u;
+    l.sigs = (l.lut + lut_bytes + 15u) & ~15u;
     l.sig_stride = (4u * k + 15u) & ~15u;
     l.total = l.sigs + l.sig_stride * waves;
     return l;
 }
 
+template <uint32_t HASH>
+struct Tables {
+    const StartT<HASH> *start;
+    const RegionEntry *reg;                  // wide: {start, 64-bit reciprocal}, n_regions + 1
+    const uint32_t *rstart, *rmag;           // narrow: region starts (n_regions + 1), 32-bit reciprocals
+    const uint8_t *lut;
+    const uint32_t (*cells)[2];              // log cells: {first region, inner boundary}
+    const uint32_t (*regs)[2];               // log cells: {region start, 32-bit reciprocal}
+};
+
+// Builds the workgroup's LDS tables (call with the whole workgroup, then barrier).
+template <uint32_t HASH, int LOC>
+__device__ Tables<HASH> build_tables(const SketchDesc &d, unsigned char *smem, const SketchLds &L) {
+    using S = StartT<HASH>;
+    const uint32_t k = d.k, nr = d.n_regions, nb = d.nb, tid = threadIdx.x;
+    Tables<HASH> t{};
+    S *s_start = reinterpret_cast<S *>(smem + L.starts);
+    for (uint32_t b = tid; b < k; b += blockDim.x) {
+        const uint32_t r = b / nb, i = b - r * nb;
+        const uint64_t z = d.reg_start[r + 1] - d.reg_start[r];
+        s_start[b] = (S)(d.reg_start[r] + ((uint64_t)i * z + nb - 1) / nb);
+    }
+    if (tid == 0) s_start[k] = (S)d.R;
+    t.start = s_start;
+    if constexpr (LOC == LOC_LOG) {
+        uint32_t(*rg)[2] = reinterpret_cast<uint32_t(*)[2]>(smem + L.reg);
+        uint32_t(*cl)[2] = reinterpret_cast<uint32_t(*)[2]>(smem + L.lut);
+        for (uint32_t r = tid; r < nr; r += blockDim.x) {
+            rg[r][0] = (uint32_t)d.reg_start[r];
+            rg[r][1] = d.reg_mag32[r];
+        }
+        for (uint32_t c = tid; c < kLogCells; c += blockDim.x)
+            log_cell_entry(c, (uint32_t)d.R, d.reg_start, nr, cl[c][0], cl[c][1]);
+        t.regs = rg;
+        t.cells = cl;
+    }
+    if constexpr (LOC == LOC_REGION) {
+        if constexpr (kNarrow<HASH>) {
+            uint32_t *rs = reinterpret_cast<uint32_t *>(smem + L.reg), *rm = rs + nr + 1;
+            for (uint32_t r = tid; r <= nr; r += blockDim.x) rs[r] = (uint32_t)d.reg_start[r];
+            for (uint32_t r = tid; r < nr; r += blockDim.x) rm[r] = d.reg_mag32[r];
+            t.rstart = rs;
+            t.rmag = rm;
+        } else {
+            RegionEntry *re = reinterpret_cast<RegionEntry *>(smem + L.reg);
+            for (uint32_t r = tid; r <= nr; r += blockDim.x)
+                re[r] = RegionEntry{d.reg_start[r], r < nr ? d.reg_magic[r] : 0ull};
+            t.reg = re;
+        }
+        uint8_t *s_lut = smem + L.lut;
+        if (nr > 1) {
+            for (uint32_t g = tid; g < d.lut_size; g += blockDim.x) {
+                const uint64_t v = (uint64_t)g << d.lut_shift;
+                uint32_t r = 0;
+                while (r + 1 < nr && v >= d.reg_start[r + 1]) ++r;
+                s_lut[g] = (uint8_t)r;
+            }
+        }
+        t.lut = s_lut;
+    }
+    return t;
+}
+
+// Bin of the permuted value v and its offset from the bin start.
+template <uint32_t HASH, int LOC>
+__device__ __forceinline__ void bin_of(uint64_t v, const SketchDesc &d, const Tables<HASH> &t, uint32_t &b,
+                                       uint32_t &off) {
+    if constexpr (kNarrow<HASH>) {
+        const uint32_t v32 = (uint32_t)v;
+        uint32_t start;
+        if constexpr (LOC == LOC_EST) {
+            const uint32_t e = bin_estimate(v32, d.est_mul, 0);
+            const uint32_t s0 = t.start[e], s1 = t.start[e + 1];
+            const bool up = v32 >= s1;
+            b = e + (up ? 1u : 0u);
+            start = up ? s1 : s0;
+        } else if constexpr (LOC == LOC_LOG) {
+            locate_log(v32, (uint32_t)(d.R - 1), t.cells, t.regs, d.nb, t.start, b, start);
+        } else {
+            locate_narrow(v32, t.lut, d.lut_shift, t.rstart, t.rmag, d.n_regions, d.nb, t.start, b, start);
+        }
+        off = v32 - start;
+    } else {
+        uint64_t start;
+        if constexpr (LOC == LOC_EST) locate_est(v, d.est_mul, d.est_shift, t.start, b, start);
+        else locate(v, t.lut, d.lut_shift, t.reg, d.n_regions, d.nb, t.start, b, start);
+        off = (uint32_t)(v - start);
+    }
+}
+
+// Hash, bin and fold into the LDS signature the elements base + lane + 64 u,
+// u < kUnroll (FULL: all of them are below hi).  Lanes past hi or with an id
+// out of range fold EMPTY into a bin of their own (bin lane mod k: no two such
+// lanes of a wavefront hit one word), which changes nothing (EMPTY is the
+// largest word), so the path has no per-lane branch and the groups' LDS reads
+// are in flight together.  A group with no element at all (the tail of a set)
+// is skipped as a whole by a wave-uniform test.
+template <uint32_t HASH, int LOC, bool FULL>
+__device__ __forceinline__ void add_elements(const SketchDesc &d, const Tables<HASH> &t, uint32_t *sig,
+                                             const uint32_t (&x)[kUnroll], uint64_t base, uint64_t hi,
+                                             uint32_t lane, uint32_t &err) {
+    uint64_t v[kUnroll];
+    bool ok[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        if (!FULL && base + 64u * u >= hi) break;
+        const bool in = FULL || base + lane + 64u * u < hi;
+        const bool bad = in && (uint64_t)x[u] >= d.universe;
+        ok[u] = in && !bad;
+        err |= bad ? kErrRange : 0u;
+        v[u] = permute<HASH>(ok[u] ? x[u] : 0u, d);
+        if constexpr (HASH == HOPH_HASH_TABLE) {
+            const bool badv = ok[u] && v[u] >= d.R;
+            err |= badv ? kErrRange : 0u;
+            ok[u] = ok[u] && !badv;
+            v[u] = ok[u] ? v[u] : 0u;
+        }
+    }
+    // every bin lookup before the first LDS minimum: the tables and the
+    // signature share the workgroup's LDS, so a lookup written after a minimum
+    // would wait for it
+    uint32_t b[kUnroll], off[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        if (!FULL && base + 64u * u >= hi) break;
+        bin_of<HASH, LOC>(v[u], d, t, b[u], off[u]);
+    }
+    const uint32_t idle_bin = lane < d.k ? lane : lane % d.k;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        if (!FULL && base + 64u * u >= hi) break;
+        atomicMin(&sig[ok[u] ? b[u] : idle_bin], ok[u] ? off[u] : HOPH_EMPTY);
+    }
+}
+
+// Orders one wavefront's LDS accesses (the signature is private to the wavefront).
 __device__ __forceinline__ void wave_lds_fence() {
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
 
-template <uint32_t HASH, bool HIER>
+// Ids of a batch: a full batch through the wave-uniform base pointer (lane
+// offsets fixed, no clamping); the last batch of a range clamped to hi - 1.
+template <bool FULL>
+__device__ __forceinline__ void load_batch(const uint32_t *__restrict__ ids, uint64_t base, uint64_t hi,
+                                           uint32_t lane, uint32_t (&x)[kUnroll]) {
+    if constexpr (FULL) {
+        const uint32_t *p = ids + base;
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) x[u] = p[lane + 64u * u];
+    } else {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const uint64_t j = base + lane + 64u * u;
+            x[u] = ids[j < hi ? j : hi - 1];
+        }
+    }
+}
+
+// The elements [lo, hi) into the LDS signature; the next batch of ids is read
+// while the current one is processed.
+template <uint32_t HASH, int LOC>
+__device__ __forceinline__ void sketch_range(const SketchDesc &d, const Tables<HASH> &t,
+                                             const uint32_t *__restrict__ ids, uint64_t lo, uint64_t hi,
+                                             uint32_t *sig, uint32_t lane, uint32_t &err) {
+    if (hi <= lo) return;
+    constexpr uint32_t B = 64u * kUnroll;
+    uint32_t x[kUnroll];
+    if (lo + B <= hi) load_batch<true>(ids, lo, hi, lane, x);
+    else load_batch<false>(ids, lo, hi, lane, x);
+    for (uint64_t base = lo; base < hi; base += B) {
+        const uint64_t next = base + B;
+        uint32_t xn[kUnroll];
+        if (next + B <= hi) load_batch<true>(ids, next, hi, lane, xn);
+        else if (next < hi) load_batch<false>(ids, next, hi, lane, xn);
+        if (base + B <= hi) add_elements<HASH, LOC, true>(d, t, sig, x, base, hi, lane, err);
+        else add_elements<HASH, LOC, false>(d, t, sig, x, base, hi, lane, err);
+        if (next < hi) {
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) x[u] = xn[u];
+        }
+    }
+}
+
+template <uint32_t HASH, int LOC>
 __global__ __launch_bounds__(256) void sketch_kernel(SketchDesc d, const uint32_t *__restrict__ ids,
                                                      const uint64_t *__restrict__ offsets, uint64_t n_sets,
                                                      uint32_t *__restrict__ sigs, uint32_t *__restrict__ err_flag) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const uint32_t k = d.k, nr = d.n_regions, nb = d.nb;
+    const uint32_t k = d.k;
     const uint32_t waves = blockDim.x >> 6;
-    const SketchLds L = sketch_lds(k, nr, d.lut_size, waves);
-    uint64_t *s_start = reinterpret_cast<uint64_t *>(smem + L.starts);
-    RegionEntry *s_reg = reinterpret_cast<RegionEntry *>(smem + L.reg);
-    uint8_t *s_lut = smem + L.lut;
-    const uint32_t tid = threadIdx.x;
-
-    for (uint32_t r = tid; r <= nr; r += blockDim.x)
-        s_reg[r] = RegionEntry{d.reg_start[r], r < nr ? d.reg_magic[r] : 0ull};
-    for (uint32_t b = tid; b < k; b += blockDim.x) {
-        const uint32_t r = b / nb, t = b - r * nb;
-        const uint64_t z = d.reg_start[r + 1] - d.reg_start[r];
-        s_start[b] = d.reg_start[r] + ((uint64_t)t * z + nb - 1) / nb;
-    }
-    if (tid == 0) s_start[k] = d.R;
-    if constexpr (HIER) {
-        for (uint32_t g = tid; g < d.lut_size; g += blockDim.x) {
-            const uint64_t v = (uint64_t)g << d.lut_shift;
-            uint32_t r = 0;
-            while (r + 1 < nr && v >= d.reg_start[r + 1]) ++r;
-            s_lut[g] = (uint8_t)r;
-        }
-    }
+    const SketchLds L = sketch_lds(k, d.n_regions, d.lut_size, waves, kNarrow<HASH>, LOC);
+    const Tables<HASH> t = build_tables<HASH, LOC>(d, smem, L);
     __syncthreads();
 
-    const uint32_t lane = tid & 63;
-    const uint32_t wib = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint32_t *sig = reinterpret_cast<uint32_t *>(smem + L.sigs + L.sig_stride * wib);
     const bool vec_out = (k & 3u) == 0 && (reinterpret_cast<uintptr_t>(sigs) & 15u) == 0;
     uint32_t err = 0;
     const uint64_t wstride = (uint64_t)gridDim.x * waves;
     for (uint64_t set = (uint64_t)blockIdx.x * waves + wib; set < n_sets; set += wstride) {
+        const uint64_t lo = offsets[set], hi = offsets[set + 1];
         for (uint32_t b = lane; b < k; b += 64) sig[b] = HOPH_EMPTY;
         wave_lds_fence();
-        const uint64_t lo = offsets[set], hi = offsets[set + 1];
         if (hi == lo) err |= kErrEmptySet;
-        for (uint64_t base = lo; base < hi; base += 64 * kUnroll) {
-            uint32_t x[kUnroll];
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint64_t j = base + lane + 64u * u;
-                x[u] = ids[j < hi ? j : hi - 1];
-            }
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint64_t j = base + lane + 64u * u;
-                if (j >= hi) continue;
-                if ((uint64_t)x[u] >= d.universe) { err |= kErrRange; continue; }
-                const uint64_t v = permute<HASH>(x[u], d);
-                if constexpr (HASH == HOPH_HASH_TABLE) {
-                    if (v >= d.R) { err |= kErrRange; continue; }
-                }
-                uint32_t b;
-                uint64_t start;
-                locate(v, s_lut, d.lut_shift, s_reg, HIER ? nr : 1u, nb, s_start, b, start);
-                atomicMin(&sig[b], (uint32_t)(v - start));
-            }
-        }
+        sketch_range<HASH, LOC>(d, t, ids, lo, hi, sig, lane, err);
         wave_lds_fence();
         uint32_t *out = sigs + set * k;
         if (vec_out) {
@@ -183,7 +350,7 @@ __global__ __launch_bounds__(256) void fill_sigs_kernel(uint32_t *__restrict__ s
 // chunk into an LDS signature and merges it into the global signature with
 // atomicMin (the sketch of a union is the elementwise minimum of the sketches).
 // The global signatures must be EMPTY beforehand (fill_sigs_kernel).
-template <uint32_t HASH, bool HIER>
+template <uint32_t HASH, int LOC>
 __global__ __launch_bounds__(256) void sketch_chunked_kernel(SketchDesc d, const uint32_t *__restrict__ ids,
                                                              const uint64_t *__restrict__ offsets,
                                                              const uint64_t *__restrict__ desc,
@@ -191,33 +358,14 @@ __global__ __launch_bounds__(256) void sketch_chunked_kernel(SketchDesc d, const
                                                              uint64_t max_ids, uint32_t *__restrict__ sigs,
                                                              uint32_t *__restrict__ err_flag) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const uint32_t k = d.k, nr = d.n_regions, nb = d.nb;
+    const uint32_t k = d.k;
     const uint32_t waves = blockDim.x >> 6;
-    const SketchLds L = sketch_lds(k, nr, d.lut_size, waves);
-    uint64_t *s_start = reinterpret_cast<uint64_t *>(smem + L.starts);
-    RegionEntry *s_reg = reinterpret_cast<RegionEntry *>(smem + L.reg);
-    uint8_t *s_lut = smem + L.lut;
-    const uint32_t tid = threadIdx.x;
-    for (uint32_t r = tid; r <= nr; r += blockDim.x)
-        s_reg[r] = RegionEntry{d.reg_start[r], r < nr ? d.reg_magic[r] : 0ull};
-    for (uint32_t b = tid; b < k; b += blockDim.x) {
-        const uint32_t r = b / nb, t = b - r * nb;
-        const uint64_t z = d.reg_start[r + 1] - d.reg_start[r];
-        s_start[b] = d.reg_start[r] + ((uint64_t)t * z + nb - 1) / nb;
-    }
-    if (tid == 0) s_start[k] = d.R;
-    if constexpr (HIER) {
-        for (uint32_t g = tid; g < d.lut_size; g += blockDim.x) {
-            const uint64_t v = (uint64_t)g << d.lut_shift;
-            uint32_t r = 0;
-            while (r + 1 < nr && v >= d.reg_start[r + 1]) ++r;
-            s_lut[g] = (uint8_t)r;
-        }
-    }
+    const SketchLds L = sketch_lds(k, d.n_regions, d.lut_size, waves, kNarrow<HASH>, LOC);
+    const Tables<HASH> t = build_tables<HASH, LOC>(d, smem, L);
     __syncthreads();
 
-    const uint32_t lane = tid & 63;
-    const uint32_t wib = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint32_t *sig = reinterpret_cast<uint32_t *>(smem + L.sigs + L.sig_stride * wib);
     const uint64_t n_sets = desc[0];
     const uint64_t n_items = prefix[n_sets];
@@ -242,28 +390,7 @@ __global__ __launch_bounds__(256) void sketch_chunked_kernel(SketchDesc d, const
         const uint64_t hi = min(s_hi, lo + chunk);
         for (uint32_t b = lane; b < k; b += 64) sig[b] = HOPH_EMPTY;
         wave_lds_fence();
-        for (uint64_t base = lo; base < hi; base += 64 * kUnroll) {
-            uint32_t x[kUnroll];
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint64_t j = base + lane + 64u * u;
-                x[u] = ids[j < hi ? j : hi - 1];
-            }
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint64_t j = base + lane + 64u * u;
-                if (j >= hi) continue;
-                if ((uint64_t)x[u] >= d.universe) { err |= kErrRange; continue; }
-                const uint64_t v = permute<HASH>(x[u], d);
-                if constexpr (HASH == HOPH_HASH_TABLE) {
-                    if (v >= d.R) { err |= kErrRange; continue; }
-                }
-                uint32_t b;
-                uint64_t start;
-                locate(v, s_lut, d.lut_shift, s_reg, HIER ? nr : 1u, nb, s_start, b, start);
-                atomicMin(&sig[b], (uint32_t)(v - start));
-            }
-        }
+        sketch_range<HASH, LOC>(d, t, ids, lo, hi, sig, lane, err);
         wave_lds_fence();
         uint32_t *out = sigs + set * k;
         for (uint32_t b = lane; b < k; b += 64) {
@@ -275,32 +402,56 @@ __global__ __launch_bounds__(256) void sketch_chunked_kernel(SketchDesc d, const
     if (err) atomicOr(err_flag, err);
 }
 
-template <uint32_t HASH, bool HIER>
+// Waves per workgroup (LDS at most 48 KB per workgroup) and its LDS bytes.
+template <uint32_t HASH, int LOC>
+void sketch_shape(const SketchDesc &d, uint32_t &waves, size_t &lds) {
+    waves = 4;
+    auto bytes = [&](uint32_t w) {
+        return sketch_lds(d.k, d.n_regions, d.lut_size, w, kNarrow<HASH>, LOC).total;
+    };
+    while (waves > 1 && bytes(waves) > 48 * 1024) waves >>= 1;
+    lds = bytes(waves);
+}
+
+template <typename K>
+hipError_t allow_lds(K kern, size_t lds) {
+    if (lds > 64 * 1024)
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds);
+    return hipSuccess;
+}
+
+template <uint32_t HASH, int LOC>
 hipError_t launch_t(const SketchDesc &d, const uint32_t *ids, const uint64_t *offsets, uint64_t n_sets,
-                    uint32_t *sigs, uint32_t *err_flag, hipStream_t st, uint32_t threads, size_t lds,
-                    uint32_t grid) {
-    auto kern = sketch_kernel<HASH, HIER>;
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, st, d, ids, offsets, n_sets, sigs, err_flag);
+                    uint32_t *sigs, uint32_t *err_flag, hipStream_t st) {
+    uint32_t waves;
+    size_t lds;
+    sketch_shape<HASH, LOC>(d, waves, lds);
+    const uint64_t want_waves = (uint64_t)device_cu_count() * 32;
+    uint64_t grid = (n_sets + waves - 1) / waves;
+    if (grid > want_waves / waves) grid = want_waves / waves;
+    if (grid == 0) grid = 1;
+    auto kern = sketch_kernel<HASH, LOC>;
+    hipError_t e = allow_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(64 * waves), lds, st, d, ids, offsets, n_sets, sigs,
+                       err_flag);
     return hipGetLastError();
 }
 
-template <uint32_t HASH, bool HIER>
+template <uint32_t HASH, int LOC>
 hipError_t launch_chunked_t(const SketchDesc &d, const uint32_t *ids, const uint64_t *offsets, const uint64_t *desc,
                             const uint64_t *prefix, uint32_t chunk, uint64_t max_ids, uint32_t *sigs,
-                            uint32_t *err_flag, hipStream_t st, uint32_t threads, size_t lds, uint32_t grid) {
-    auto kern = sketch_chunked_kernel<HASH, HIER>;
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, st, d, ids, offsets, desc, prefix, chunk, max_ids, sigs,
-                       err_flag);
+                            uint32_t *err_flag, uint32_t waves_per_cu, hipStream_t st) {
+    uint32_t waves;
+    size_t lds;
+    sketch_shape<HASH, LOC>(d, waves, lds);
+    const uint32_t grid = (uint32_t)((uint64_t)device_cu_count() * (waves_per_cu ? waves_per_cu : 16) / waves);
+    auto kern = sketch_chunked_kernel<HASH, LOC>;
+    hipError_t e = allow_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(grid ? grid : 1), dim3(64 * waves), lds, st, d, ids, offsets, desc, prefix, chunk,
+                       max_ids, sigs, err_flag);
     return hipGetLastError();
 }
 
@@ -315,18 +466,15 @@ hipError_t launch_sketch_chunked(const SketchDesc &d, const uint32_t *ids, const
     if (fill_blocks > 4096) fill_blocks = 4096;
     if (fill_blocks == 0) fill_blocks = 1;
     hipLaunchKernelGGL(fill_sigs_kernel, dim3((uint32_t)fill_blocks), dim3(256), 0, st, sigs, desc, d.k);
-    const bool hier = d.n_regions > 1;
-    uint32_t waves = 4;
-    while (waves > 1 && sketch_lds(d.k, d.n_regions, d.lut_size, waves).total > 48 * 1024) waves >>= 1;
-    const size_t lds = sketch_lds(d.k, d.n_regions, d.lut_size, waves).total;
-    const uint32_t grid = (uint32_t)((uint64_t)device_cu_count() * (waves_per_cu ? waves_per_cu : 16) / waves);
-    const uint32_t threads = 64 * waves;
-#define HOPH_SKC(H, HI) \
-    launch_chunked_t<H, HI>(d, ids, offsets, desc, prefix, chunk, max_ids, sigs, err_flag, st, threads, lds, grid)
+#define HOPH_SKC(H, LOC) \
+    launch_chunked_t<H, LOC>(d, ids, offsets, desc, prefix, chunk, max_ids, sigs, err_flag, waves_per_cu, st)
+    const bool est = d.est_ok != 0;
     switch (d.hash) {
-    case HOPH_HASH_TABLE: return hier ? HOPH_SKC(HOPH_HASH_TABLE, true) : HOPH_SKC(HOPH_HASH_TABLE, false);
-    case HOPH_HASH_MODP31: return hier ? HOPH_SKC(HOPH_HASH_MODP31, true) : HOPH_SKC(HOPH_HASH_MODP31, false);
-    default: return hier ? HOPH_SKC(HOPH_HASH_MODP32P15, true) : HOPH_SKC(HOPH_HASH_MODP32P15, false);
+    case HOPH_HASH_TABLE: return est ? HOPH_SKC(HOPH_HASH_TABLE, LOC_EST) : HOPH_SKC(HOPH_HASH_TABLE, LOC_REGION);
+    case HOPH_HASH_MODP31:
+        return est ? HOPH_SKC(HOPH_HASH_MODP31, LOC_EST)
+                   : d.log_ok ? HOPH_SKC(HOPH_HASH_MODP31, LOC_LOG) : HOPH_SKC(HOPH_HASH_MODP31, LOC_REGION);
+    default: return est ? HOPH_SKC(HOPH_HASH_MODP32P15, LOC_EST) : HOPH_SKC(HOPH_HASH_MODP32P15, LOC_REGION);
     }
 #undef HOPH_SKC
 }
@@ -334,28 +482,16 @@ hipError_t launch_sketch_chunked(const SketchDesc &d, const uint32_t *ids, const
 hipError_t launch_sketch(const SketchDesc &d, const uint32_t *ids, const uint64_t *offsets, uint64_t n_sets,
                          uint32_t *sigs, uint32_t *err_flag, hipStream_t st) {
     if (n_sets == 0) return hipSuccess;
-    const bool hier = d.n_regions > 1;
-    // four wavefronts per workgroup unless the signatures are large
-    uint32_t waves = 4;
-    while (waves > 1 && sketch_lds(d.k, d.n_regions, d.lut_size, waves).total > 48 * 1024) waves >>= 1;
-    const size_t lds = sketch_lds(d.k, d.n_regions, d.lut_size, waves).total;
-    const uint64_t want_waves = (uint64_t)device_cu_count() * 32;
-    uint64_t grid = (n_sets + waves - 1) / waves;
-    if (grid > want_waves / waves) grid = want_waves / waves;
-    if (grid == 0) grid = 1;
-    const uint32_t threads = 64 * waves;
+    const bool est = d.est_ok != 0;
+#define HOPH_SK(H, LOC) launch_t<H, LOC>(d, ids, offsets, n_sets, sigs, err_flag, st)
     switch (d.hash) {
-    case HOPH_HASH_TABLE:
-        return hier ? launch_t<HOPH_HASH_TABLE, true>(d, ids, offsets, n_sets, sigs, err_flag, st, threads, lds, grid)
-                    : launch_t<HOPH_HASH_TABLE, false>(d, ids, offsets, n_sets, sigs, err_flag, st, threads, lds, grid);
+    case HOPH_HASH_TABLE: return est ? HOPH_SK(HOPH_HASH_TABLE, LOC_EST) : HOPH_SK(HOPH_HASH_TABLE, LOC_REGION);
     case HOPH_HASH_MODP31:
-        return hier ? launch_t<HOPH_HASH_MODP31, true>(d, ids, offsets, n_sets, sigs, err_flag, st, threads, lds, grid)
-                    : launch_t<HOPH_HASH_MODP31, false>(d, ids, offsets, n_sets, sigs, err_flag, st, threads, lds, grid);
-    default:
-        return hier ? launch_t<HOPH_HASH_MODP32P15, true>(d, ids, offsets, n_sets, sigs, err_flag, st, threads, lds, grid)
-                    : launch_t<HOPH_HASH_MODP32P15, false>(d, ids, offsets, n_sets, sigs, err_flag, st, threads, lds,
-                                                           grid);
+        return est ? HOPH_SK(HOPH_HASH_MODP31, LOC_EST)
+                   : d.log_ok ? HOPH_SK(HOPH_HASH_MODP31, LOC_LOG) : HOPH_SK(HOPH_HASH_MODP31, LOC_REGION);
+    default: return est ? HOPH_SK(HOPH_HASH_MODP32P15, LOC_EST) : HOPH_SK(HOPH_HASH_MODP32P15, LOC_REGION);
     }
+#undef HOPH_SK
 }
 
 }  // namespace hoph

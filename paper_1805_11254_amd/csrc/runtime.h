@@ -57,10 +57,15 @@ struct Workspace {
     uint64_t seg_cap = 0;
     uint64_t *h_counters = nullptr; // pinned host mirror
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t aev[3] = {nullptr, nullptr, nullptr};   // around the last append of sets
+    bool aev_recorded = false;
     float last_ms[3] = {0, 0, 0};
     void release() {
         for (auto &e : ev)
             if (e) { (void)hipEventDestroy(e); e = nullptr; }
+        for (auto &e : aev)
+            if (e) { (void)hipEventDestroy(e); e = nullptr; }
+        aev_recorded = false;
         if (surv) (void)hipFree(surv);
         if (keys) (void)hipFree(keys);
         if (counters) (void)hipFree(counters);
@@ -86,6 +91,7 @@ struct Workspace {
         HOPH_HIP(hipMalloc(&counters, 64), "hipMalloc(counters)");
         HOPH_HIP(hipHostMalloc(&h_counters, 64, hipHostMallocDefault), "hipHostMalloc(counters)");
         for (auto &e : ev) HOPH_HIP(hipEventCreate(&e), "hipEventCreate");
+        for (auto &e : aev) HOPH_HIP(hipEventCreate(&e), "hipEventCreate");
         hoph_status st = grow_surv(surv_records);
         if (st) return st;
         return grow_keys(keys_records);
@@ -178,6 +184,10 @@ struct hoph_index {
 };
 
 namespace hoph {
+// Sketch n_sets sets straight into index rows [first, first + n_sets) (slabs and
+// code planes), asynchronously on s; the caller checks capacity and owns idx->n.
+hipError_t append_sets_async(hoph_index *idx, const uint32_t *d_ids, const uint64_t *d_offsets, uint64_t n_sets,
+                             uint64_t first, uint32_t *err_word, hipStream_t s, bool timed);
 // GOPH / HOPH / plain-OPH query through the index's own workspace (host-synchronised).
 hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t n_q, const hoph_query_params *qp,
                       hoph_results *res, void *stream, QueryKind kind);

@@ -73,7 +73,7 @@ struct hoph_server {
     // memory (which would wait for every batch in flight)
     std::mutex insert_mu;
     hipStream_t insert_stream = nullptr;
-    uint32_t *ins_ids = nullptr, *ins_sigs = nullptr;
+    uint32_t *ins_ids = nullptr;
     uint64_t *ins_offs = nullptr;
     uint64_t ins_ids_cap = 0, ins_sets_cap = 0;
 };
@@ -312,32 +312,31 @@ hoph_status hoph_server_insert(hoph_server *srv, const uint32_t *h_ids, const ui
     }
     if (n_sets > srv->ins_sets_cap) {
         if (srv->ins_offs) (void)hipFree(srv->ins_offs);
-        if (srv->ins_sigs) (void)hipFree(srv->ins_sigs);
         srv->ins_offs = nullptr;
-        srv->ins_sigs = nullptr;
         srv->ins_sets_cap = 0;
         const uint64_t cap = std::max<uint64_t>(n_sets + n_sets / 2, 4096);
-        if (hipMalloc(&srv->ins_offs, (cap + 1) * 8) != hipSuccess ||
-            hipMalloc(&srv->ins_sigs, cap * (uint64_t)idx->lay.k * 4) != hipSuccess)
-            return fail(HOPH_E_NOMEM, "insert staging");
+        if (hipMalloc(&srv->ins_offs, (cap + 1) * 8) != hipSuccess) return fail(HOPH_E_NOMEM, "insert staging");
         srv->ins_sets_cap = cap;
     }
-    uint32_t *d_ids = srv->ins_ids, *d_sigs = srv->ins_sigs;
+    uint32_t *d_ids = srv->ins_ids;
     uint64_t *d_offs = srv->ins_offs;
+    uint32_t *errw = nullptr;
+    hoph_status es = device_err_word(&errw);
+    if (es) return es;
     hipStream_t st = srv->insert_stream;
     hoph_status s = HOPH_OK;
     if (hipMemcpyAsync(d_ids, h_ids + h_offsets[0], nnz * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(d_offs, offs.data(), (n_sets + 1) * 8, hipMemcpyHostToDevice, st) != hipSuccess)
         s = fail(HOPH_E_DEVICE, "insert copy");
-    if (!s) s = sketch_oph(&srv->params, d_ids, d_offs, n_sets, d_sigs, st);
     uint64_t first = 0;
     if (!s) {
         std::lock_guard<std::mutex> lk(idx->mu);
         first = idx->n;
     }
-    if (!s && launch_index_store(d_sigs, n_sets, first, idx->lay.k, idx->lay.kp, idx->lay.L, idx->kpad,
-                                 idx->capacity, idx->slab, idx->codes, idx->cg, st) != hipSuccess)
-        s = fail(HOPH_E_DEVICE, "index store launch");
+    // sketched straight into rows [first, first + n_sets): batches dispatched
+    // meanwhile read only rows below idx->n
+    if (!s && append_sets_async(idx, d_ids, d_offs, n_sets, first, errw, st, false) != hipSuccess)
+        s = fail(HOPH_E_DEVICE, "sketch-into-index launch");
     if (!s && hipStreamSynchronize(st) != hipSuccess) s = fail(HOPH_E_DEVICE, "hipStreamSynchronize");
     if (s) return s;
     {
@@ -454,7 +453,6 @@ void hoph_server_destroy(hoph_server *srv) {
         if (srv->insert_stream) (void)hipStreamDestroy(srv->insert_stream);
         if (srv->ins_ids) (void)hipFree(srv->ins_ids);
         if (srv->ins_offs) (void)hipFree(srv->ins_offs);
-        if (srv->ins_sigs) (void)hipFree(srv->ins_sigs);
     }
     delete srv;
 }

@@ -383,3 +383,82 @@ def test_device_error_flags():
         H.sync()
     assert ei.value.status == H.HOPH_E_INVAL
     assert (to_u32(out)[1] == tiny.EMPTY).all()
+
+
+def _append_sets_check(w, cuts):
+    import torch
+    p = params_of(w)
+    sig = gpu_sketch(w, w.collection, p)
+    qsig = gpu_sketch(w, w.queries, p)
+    two_step = H.Index(p, sig)
+    fused = H.Index(p, sig[:0], capacity=w.collection.n)
+    ids, offs = dev_csr(w.collection)
+    offs_h = w.collection.offsets.astype(np.int64)
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        lo = int(offs_h[a])
+        piece_offs = torch.from_numpy((offs_h[a:b + 1] - lo).copy()).to("cuda")
+        fused.append_sets(ids[lo:int(offs_h[b])].contiguous(), piece_offs)
+    H.sync()
+    assert len(fused) == w.collection.n
+    sh, qh = to_u32(sig), to_u32(qsig)
+    kind = "goph" if w.goph else "hoph"
+    T, eps = (4, 5), (1, 10_000)
+    policies = _policies_that_fit(p, T, eps)
+    for policy in policies:
+        oo, oi = oracle_query(w, sh, qh, T, eps, policy)
+        for coarse in (H.COARSE_CODES, H.COARSE_WORDS):
+            go, gi = gpu_query(kind, fused, qsig, T, eps, policy, coarse=coarse)
+            assert go.tolist() == oo.tolist() and gi.tolist() == oi.tolist(), (policy, coarse)
+    rng = np.random.default_rng(31)
+    pairs = [(int(rng.integers(w.queries.n)), int(rng.integers(w.collection.n))) for _ in range(400)]
+    pairs += [(0, 0), (w.queries.n - 1, w.collection.n - 1)]
+    P = torch.tensor(pairs, dtype=torch.int32, device="cuda")
+    for policy in policies:
+        m1, e1 = H.pair_counts(two_step, qsig, P, policy)
+        m2, e2 = H.pair_counts(fused, qsig, P, policy)
+        assert torch.equal(m1, m2) and torch.equal(e1, e2), policy
+    two_step.free()
+    fused.free()
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_append_sets_matches_oracle(name):
+    """Sketching straight into the index (ragged appends that start and end
+    inside tiles) gives the index that sketch_oph + index_append gives."""
+    _print_case(f"append_sets {name}")
+    w = workload(name)
+    n = w.collection.n
+    cuts = sorted(set([0, 1, 63, 64, 65, 130, n // 3, n // 3 + 7, n - 1, n]))
+    _append_sets_check(w, cuts)
+
+
+@pytest.mark.parametrize("layout,k,kp", [(W.LAYOUT_HIER, 192, 12), (W.LAYOUT_OPH, 120, 10), (W.LAYOUT_HIER, 320, 40)])
+def test_append_sets_group_sizes(layout, k, kp):
+    _print_case(f"append_sets group size layout={layout} k={k} kp={kp}")
+    w = W.hoph_bovw(n=2_345, n_q=8, seed=41 + kp, k=k, kp=kp, planted_frac=0.02)
+    w.layout = layout
+    _append_sets_check(w, [0, 100, 1000, 2_345])
+
+
+def test_append_sets_reports_range_and_empty_sets():
+    import torch
+    _print_case("append_sets errors")
+    p = H.SketchParams(H.LAYOUT_OPH, 64, 16, H.HASH_MODP31, 1000, hash_a=7, hash_b=1)
+    idx = H.Index(p, torch.empty((0, 64), dtype=torch.int32, device="cuda"), capacity=10)
+    H.sync()
+    idx.append_sets(torch.tensor([1, 2, 5000, 3], dtype=torch.int32, device="cuda"),
+                    torch.tensor([0, 2, 4], dtype=torch.int64, device="cuda"))
+    with pytest.raises(H.HophError) as ei:
+        H.sync()
+    assert ei.value.status == H.HOPH_E_RANGE
+    H.sync()
+    idx.append_sets(torch.tensor([1, 2], dtype=torch.int32, device="cuda"),
+                    torch.tensor([0, 2, 2], dtype=torch.int64, device="cuda"))
+    with pytest.raises(H.HophError) as ei:
+        H.sync()
+    assert ei.value.status == H.HOPH_E_INVAL
+    with pytest.raises(H.HophError) as ei:
+        idx.append_sets(torch.tensor([1] * 7, dtype=torch.int32, device="cuda"),
+                        torch.arange(8, dtype=torch.int64, device="cuda"))
+    assert ei.value.status == H.HOPH_E_CAPACITY
+    idx.free()
