@@ -44,8 +44,8 @@ def parse():
     ap.add_argument("--n-queries", type=int, default=1024)
     ap.add_argument("--seed", type=int, default=1806)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-sets", type=int, default=200_000)
-    ap.add_argument("--cpu-sample-queries", type=int, default=256)
+    ap.add_argument("--cpu-sample-sets", type=int, default=1_000_000)
+    ap.add_argument("--cpu-sample-queries", type=int, default=512)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for scaling HBM counters)")
     ap.add_argument("--mode", choices=["step", "batched", "serve", "comparators"], default="step",
@@ -512,17 +512,20 @@ def main():
     traffic = load_traffic()
     kernels = {
         "sketch_into_index": {"ms": sketch_ms, "bound": "hbm", "achieved": sketch_bytes / (sketch_ms * 1e-3) / 1e9,
-                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": traffic.get("sketch_slab_kernel"),
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": traffic.get("sketch_kernel"),
                               "algorithmic_bytes": sketch_bytes, "sets_per_s": N / (sketch_ms * 1e-3)},
         "code_planes": {"ms": codes_ms, "bound": "hbm", "achieved": code_bytes / (codes_ms * 1e-3) / 1e9,
-                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": traffic.get("codes_from_slab_kernel"),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": traffic.get("row_codes_vec_kernel"),
                         "algorithmic_bytes": code_bytes},
         "two_step_sketch_oph": {"ms": two_sketch_ms, "bound": "hbm",
                                 "achieved": sketch_bytes / (two_sketch_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                                 "unit": "GB/s", "traffic": traffic.get("sketch_kernel"),
                                 "algorithmic_bytes": sketch_bytes},
         "two_step_index_store": {"ms": index_ms, "bound": "hbm", "achieved": index_bytes / (index_ms * 1e-3) / 1e9,
-                                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": traffic.get("index_store_vec"),
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "traffic": (traffic["__amd_rocclr_copyBuffer"] + traffic["row_codes_vec_kernel"]
+                                             if "__amd_rocclr_copyBuffer" in traffic and "row_codes_vec_kernel" in traffic
+                                             else None),
                                  "algorithmic_bytes": index_bytes},
         "scan_coarse": {"ms": coarse_ms, "bound": "alu", "achieved": coarse_ops / (coarse_ms * 1e-3) / 1e12,
                         "peak": ALU_PEAK_OPS / 1e12, "unit": "Tops/s (32-bit VALU lane-ops)",
