@@ -119,9 +119,10 @@ typedef struct hoph_index hoph_index;   /* opaque, owned by the library */
 /*
  * sketch_oph -- OPH / HOPH signatures of n_sets sets (Sec. 3.2, Sec. 4.1).
  * d_sigs: n_sets * k uint32, row-major (set i at d_sigs + i * k).
- * Asynchronous.  Ids >= universe are skipped and raise HOPH_E_RANGE at the next
- * hoph_sync on the device; an empty set gets an all-EMPTY signature and raises
- * HOPH_E_INVAL there (Jaccard similarity is undefined for it).
+ * Asynchronous.  An id >= universe (or, for HOPH_HASH_TABLE, a table value >= the
+ * universe) raises HOPH_E_RANGE at the next hoph_sync on the device, and the
+ * signature of its set is then unspecified; an empty set gets an all-EMPTY
+ * signature and raises HOPH_E_INVAL there (Jaccard similarity is undefined for it).
  * Host errors: HOPH_E_INVAL (bad params, null pointers with n_sets > 0).
  */
 hoph_status sketch_oph(const hoph_sketch_params *params, const uint32_t *d_ids,
@@ -151,7 +152,7 @@ hoph_status index_append(hoph_index *index, const uint32_t *d_sigs, uint64_t n_n
  * planes of the first groups) without a row-major copy; ids continue from the
  * current size.  d_ids / d_offsets as for sketch_oph (device, CSR).  Results
  * are identical to sketch_oph followed by index_append.  HOPH_E_CAPACITY if
- * size + n_sets > capacity.  Asynchronous; ids >= universe and empty sets are
+ * size + n_sets > capacity.  Asynchronous; ids out of range and empty sets are
  * reported as by sketch_oph, at the next hoph_sync on the device.  The
  * permutation table of a HOPH_HASH_TABLE index must stay valid.
  */

@@ -117,10 +117,27 @@ __host__ __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b) {
 // P = 2^31 - 1, w = a x + b <= P (P - 1) < 2^62, and w = (w >> 31) + (w & P)
 // (mod P) where both parts are < 2^31, so every step after the one 64-bit
 // multiply-add is 32-bit.
+__host__ __device__ inline uint32_t shr31_of_64(uint32_t hi, uint32_t lo) {   // ((hi:lo) >> 31) mod 2^32
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_alignbit(hi, lo, 31);
+#else
+    return (hi << 1) | (lo >> 31);
+#endif
+}
+
+// a * b for a, b < 2^24 (full-rate 24-bit multiply on the device).
+__host__ __device__ inline uint32_t mul_u24(uint32_t a, uint32_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __umul24(a, b);
+#else
+    return a * b;
+#endif
+}
+
 __host__ __device__ inline uint64_t psi_p31(uint64_t x, uint64_t a, uint64_t b) {
     const uint64_t w = (uint64_t)(uint32_t)a * (uint32_t)x + b;   // one 32 x 32 -> 64 multiply-add
     const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
-    uint32_t s = (lo & 0x7FFFFFFFu) + ((hi << 1) | (lo >> 31));    // <= 2^32 - 2
+    uint32_t s = (lo & 0x7FFFFFFFu) + shr31_of_64(hi, lo);         // <= 2^32 - 2
     s = (s & 0x7FFFFFFFu) + (s >> 31);                              // <= P + 1
     const uint32_t t = s - 0x7FFFFFFFu;                               // wraps above s when s < P
     return t < s ? t : s;
@@ -184,7 +201,7 @@ __host__ __device__ inline void locate_narrow(uint32_t v, const uint8_t *lut, ui
         while (r + 1 < n_regions && v >= rstart[r + 1]) ++r;
     }
     const uint32_t y = v - rstart[r];
-    const uint32_t b = r * nb + (uint32_t)(((uint64_t)y * rmag[r]) >> 32);
+    const uint32_t b = mul_u24(r, nb) + (uint32_t)(((uint64_t)y * rmag[r]) >> 32);
     const uint32_t s0 = starts[b], s1 = starts[b + 1];
     const bool up = v >= s1;
     bin = b + (up ? 1u : 0u);
@@ -243,7 +260,7 @@ __host__ __device__ inline void locate_log(uint32_t v, uint32_t R1, const uint32
     const uint32_t c = log_cell(v, R1);
     const uint32_t r = cells[c][0] + (v >= cells[c][1] ? 1u : 0u);
     const uint32_t y = v - regs[r][0];
-    const uint32_t b = r * nb + (uint32_t)(((uint64_t)y * regs[r][1]) >> 32);
+    const uint32_t b = mul_u24(r, nb) + (uint32_t)(((uint64_t)y * regs[r][1]) >> 32);   // r < 64, nb <= 4096
     const uint32_t s0 = starts[b], s1 = starts[b + 1];
     const bool up = v >= s1;
     bin = b + (up ? 1u : 0u);

@@ -164,31 +164,28 @@ __device__ __forceinline__ void bin_of(uint64_t v, const SketchDesc &d, const Ta
 }
 
 // Hash, bin and fold into the LDS signature the elements base + lane + 64 u,
-// u < kUnroll (FULL: all of them are below hi).  Lanes past hi or with an id
-// out of range fold EMPTY into a bin of their own (bin lane mod k: no two such
-// lanes of a wavefront hit one word), which changes nothing (EMPTY is the
-// largest word), so the path has no per-lane branch and the groups' LDS reads
-// are in flight together.  A group with no element at all (the tail of a set)
-// is skipped as a whole by a wave-uniform test.
+// u < kUnroll (FULL: all of them are below hi).  Ids are clamped to the
+// universe (and table values to the range) so that every lookup stays in its
+// table; the largest id and table value are kept per lane and an
+// out-of-range one raises the range error once per wavefront (the signature of
+// such a set is then unspecified).  In the last batch of a set, lanes past hi
+// fold EMPTY into a bin of their own (bin lane mod k: no two such lanes of a
+// wavefront hit one word), which changes nothing, and element groups with no
+// element at all are skipped by a wave-uniform test; the path has no per-lane
+// branch, and the groups' LDS reads are issued before any LDS minimum.
 template <uint32_t HASH, int LOC, bool FULL>
 __device__ __forceinline__ void add_elements(const SketchDesc &d, const Tables<HASH> &t, uint32_t *sig,
                                              const uint32_t (&x)[kUnroll], uint64_t base, uint64_t hi,
-                                             uint32_t lane, uint32_t &err) {
+                                             uint32_t lane, uint32_t umax, uint32_t &xmax, uint64_t &vmax) {
     uint64_t v[kUnroll];
-    bool ok[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
         if (!FULL && base + 64u * u >= hi) break;
-        const bool in = FULL || base + lane + 64u * u < hi;
-        const bool bad = in && (uint64_t)x[u] >= d.universe;
-        ok[u] = in && !bad;
-        err |= bad ? kErrRange : 0u;
-        v[u] = permute<HASH>(ok[u] ? x[u] : 0u, d);
+        xmax = max(xmax, x[u]);
+        v[u] = permute<HASH>(min(x[u], umax), d);
         if constexpr (HASH == HOPH_HASH_TABLE) {
-            const bool badv = ok[u] && v[u] >= d.R;
-            err |= badv ? kErrRange : 0u;
-            ok[u] = ok[u] && !badv;
-            v[u] = ok[u] ? v[u] : 0u;
+            vmax = max(vmax, v[u]);
+            v[u] = min(v[u], d.R - 1);
         }
     }
     // every bin lookup before the first LDS minimum: the tables and the
@@ -200,12 +197,26 @@ __device__ __forceinline__ void add_elements(const SketchDesc &d, const Tables<H
         if (!FULL && base + 64u * u >= hi) break;
         bin_of<HASH, LOC>(v[u], d, t, b[u], off[u]);
     }
-    const uint32_t idle_bin = lane < d.k ? lane : lane % d.k;
+    if constexpr (FULL) {
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-        if (!FULL && base + 64u * u >= hi) break;
-        atomicMin(&sig[ok[u] ? b[u] : idle_bin], ok[u] ? off[u] : HOPH_EMPTY);
+        for (int u = 0; u < kUnroll; ++u) atomicMin(&sig[b[u]], off[u]);
+    } else {
+        const uint32_t idle_bin = lane < d.k ? lane : lane % d.k;
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (base + 64u * u >= hi) break;
+            const bool in = base + lane + 64u * u < hi;
+            atomicMin(&sig[in ? b[u] : idle_bin], in ? off[u] : HOPH_EMPTY);
+        }
     }
+}
+
+// Range errors seen by a lane (the largest id, and table value, it folded).
+template <uint32_t HASH>
+__device__ __forceinline__ uint32_t range_error(const SketchDesc &d, uint32_t xmax, uint64_t vmax) {
+    uint32_t e = (uint64_t)xmax >= d.universe ? kErrRange : 0u;
+    if constexpr (HASH == HOPH_HASH_TABLE) e |= vmax >= d.R ? kErrRange : 0u;
+    return e;
 }
 
 // Orders one wavefront's LDS accesses (the signature is private to the wavefront).
@@ -237,7 +248,8 @@ __device__ __forceinline__ void load_batch(const uint32_t *__restrict__ ids, uin
 template <uint32_t HASH, int LOC>
 __device__ __forceinline__ void sketch_range(const SketchDesc &d, const Tables<HASH> &t,
                                              const uint32_t *__restrict__ ids, uint64_t lo, uint64_t hi,
-                                             uint32_t *sig, uint32_t lane, uint32_t &err) {
+                                             uint32_t *sig, uint32_t lane, uint32_t umax, uint32_t &xmax,
+                                             uint64_t &vmax) {
     if (hi <= lo) return;
     constexpr uint32_t B = 64u * kUnroll;
     uint32_t x[kUnroll];
@@ -248,8 +260,8 @@ __device__ __forceinline__ void sketch_range(const SketchDesc &d, const Tables<H
         uint32_t xn[kUnroll];
         if (next + B <= hi) load_batch<true>(ids, next, hi, lane, xn);
         else if (next < hi) load_batch<false>(ids, next, hi, lane, xn);
-        if (base + B <= hi) add_elements<HASH, LOC, true>(d, t, sig, x, base, hi, lane, err);
-        else add_elements<HASH, LOC, false>(d, t, sig, x, base, hi, lane, err);
+        if (base + B <= hi) add_elements<HASH, LOC, true>(d, t, sig, x, base, hi, lane, umax, xmax, vmax);
+        else add_elements<HASH, LOC, false>(d, t, sig, x, base, hi, lane, umax, xmax, vmax);
         if (next < hi) {
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) x[u] = xn[u];
@@ -272,14 +284,16 @@ __global__ __launch_bounds__(256) void sketch_kernel(SketchDesc d, const uint32_
     const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint32_t *sig = reinterpret_cast<uint32_t *>(smem + L.sigs + L.sig_stride * wib);
     const bool vec_out = (k & 3u) == 0 && (reinterpret_cast<uintptr_t>(sigs) & 15u) == 0;
-    uint32_t err = 0;
+    uint32_t err = 0, xmax = 0;
+    uint64_t vmax = 0;
+    const uint32_t umax = (uint32_t)(d.universe - 1);
     const uint64_t wstride = (uint64_t)gridDim.x * waves;
     for (uint64_t set = (uint64_t)blockIdx.x * waves + wib; set < n_sets; set += wstride) {
         const uint64_t lo = offsets[set], hi = offsets[set + 1];
         for (uint32_t b = lane; b < k; b += 64) sig[b] = HOPH_EMPTY;
         wave_lds_fence();
         if (hi == lo) err |= kErrEmptySet;
-        sketch_range<HASH, LOC>(d, t, ids, lo, hi, sig, lane, err);
+        sketch_range<HASH, LOC>(d, t, ids, lo, hi, sig, lane, umax, xmax, vmax);
         wave_lds_fence();
         uint32_t *out = sigs + set * k;
         if (vec_out) {
@@ -291,6 +305,7 @@ __global__ __launch_bounds__(256) void sketch_kernel(SketchDesc d, const uint32_
         }
         wave_lds_fence();
     }
+    err |= range_error<HASH>(d, xmax, vmax);
     if (err) atomicOr(err_flag, err);
 }
 
@@ -369,7 +384,9 @@ __global__ __launch_bounds__(256) void sketch_chunked_kernel(SketchDesc d, const
     uint32_t *sig = reinterpret_cast<uint32_t *>(smem + L.sigs + L.sig_stride * wib);
     const uint64_t n_sets = desc[0];
     const uint64_t n_items = prefix[n_sets];
-    uint32_t err = 0;
+    uint32_t err = 0, xmax = 0;
+    uint64_t vmax = 0;
+    const uint32_t umax = (uint32_t)(d.universe - 1);
     const uint64_t wstride = (uint64_t)gridDim.x * waves;
     for (uint64_t item = (uint64_t)blockIdx.x * waves + wib; item < n_items; item += wstride) {
         // the set holding this item: the last set whose prefix is <= item
@@ -390,7 +407,7 @@ __global__ __launch_bounds__(256) void sketch_chunked_kernel(SketchDesc d, const
         const uint64_t hi = min(s_hi, lo + chunk);
         for (uint32_t b = lane; b < k; b += 64) sig[b] = HOPH_EMPTY;
         wave_lds_fence();
-        sketch_range<HASH, LOC>(d, t, ids, lo, hi, sig, lane, err);
+        sketch_range<HASH, LOC>(d, t, ids, lo, hi, sig, lane, umax, xmax, vmax);
         wave_lds_fence();
         uint32_t *out = sigs + set * k;
         for (uint32_t b = lane; b < k; b += 64) {
@@ -399,6 +416,7 @@ __global__ __launch_bounds__(256) void sketch_chunked_kernel(SketchDesc d, const
         }
         wave_lds_fence();
     }
+    err |= range_error<HASH>(d, xmax, vmax);
     if (err) atomicOr(err_flag, err);
 }
 
