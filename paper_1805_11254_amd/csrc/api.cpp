@@ -64,8 +64,9 @@ hoph_status check_results(const hoph_results *r, uint32_t n_q) {
 
 // Pick queries per wavefront so that the grid has enough wavefronts to fill
 // the device (about 32 per CU) without splitting the query batch further.
-uint32_t pick_q_per_wave(uint64_t n_sets, uint32_t n_q) {
-    const uint64_t ntiles = std::max<uint64_t>(1, (n_sets + 63) / 64);
+uint32_t pick_q_per_wave(uint64_t n_sets, uint32_t n_q, uint32_t tiles_per_wave) {
+    const uint64_t per_wave = 64ull * std::max<uint32_t>(1, tiles_per_wave);
+    const uint64_t ntiles = std::max<uint64_t>(1, (n_sets + per_wave - 1) / per_wave);
     uint64_t want_chunks = (8192 + ntiles - 1) / ntiles;
     if (want_chunks > n_q) want_chunks = n_q;
     if (want_chunks == 0) want_chunks = 1;
@@ -200,7 +201,7 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
             auto pass = [&](uint32_t q0, uint32_t q1) -> hoph_status {
                 a.q0 = q0;
                 a.q1 = q1;
-                a.q_per_wave = pick_q_per_wave(idx->n, q1 - q0);
+                a.q_per_wave = pick_q_per_wave(idx->n, q1 - q0, coarse_tiles_per_wave(a, tab.policy));
                 HOPH_HIP(hipEventRecord(ws.ev[0], s), "hipEventRecord");
                 if (kind == QueryKind::OPH_FULL) {
                     HOPH_HIP(launch_oph_full(a, qp->T, qp->empty_policy, s), "oph_full launch");

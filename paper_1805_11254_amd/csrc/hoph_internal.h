@@ -351,6 +351,8 @@ hipError_t launch_query_masks(const uint32_t *qsigs, uint32_t n_q, const uint64_
                               uint32_t L, uint64_t *out, uint32_t *qcodes, uint32_t cg, const CodeThr *thr,
                               hipStream_t st);
 hipError_t launch_scan_coarse(const ScanLaunch &a, const ScanTab &tab, hipStream_t st);
+// Tiles of 64 sets one wavefront of the coarse pass holds for this launch.
+uint32_t coarse_tiles_per_wave(const ScanLaunch &a, uint32_t policy);
 hipError_t launch_scan_fine(const ScanLaunch &a, const ScanTab &tab, hipStream_t st);
 hipError_t launch_oph_full(const ScanLaunch &a, hoph_ratio T, uint32_t policy, hipStream_t st);
 hipError_t launch_sort_keys(uint64_t *keys, uint64_t n, uint64_t n_pow2, hipStream_t st);

@@ -25,6 +25,8 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
+// tiles of 64 sets per wavefront in the first-group code pass, by words per plane
+constexpr int fast_tiles(int W) { return W == 1 ? 4 : 2; }
 
 struct CoarseArgs {
     uint64_t capacity, n_sets, surv_cap, keys_cap;
@@ -149,9 +151,9 @@ __device__ __forceinline__ uint32_t code_diff(const uint32_t *P, const uint32_t 
 // where the exact algorithm rejects it too: at a step whose code state is at or
 // below the reject cutoff, with no earlier step at or above an accept cutoff.
 // Every other pair goes to the fine pass, which restarts from the first group
-// on the 32-bit words.  FAST (G = 1, JOINT or LITERAL): one threshold per
-// query on the count of differing query-non-empty bins.
-template <int W, int G, bool FAST>
+// on the 32-bit words.  (G = 1 under JOINT or LITERAL runs in
+// scan_codes_fast_kernel instead.)
+template <int W, int G>
 __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__restrict__ codes,
                                                              const uint32_t *__restrict__ qcodes,
                                                              const uint64_t *__restrict__ qmasks,
@@ -161,10 +163,8 @@ __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__
                                                              const CoarseArgs a, const ScanTab tab) {
     constexpr int PW = (int)kCodeBits * W, RW = PW + 4;
     __shared__ int64_t s_dmul[HOPH_MAX_KGROUP + 1];
-    if constexpr (!FAST) {
-        for (uint32_t i = threadIdx.x; i <= tab.kp; i += kThreads) s_dmul[i] = tab.dmul[i];
-        __syncthreads();
-    }
+    for (uint32_t i = threadIdx.x; i <= tab.kp; i += kThreads) s_dmul[i] = tab.dmul[i];
+    __syncthreads();
 
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t n_sets = desc ? desc[1] : a.n_sets;
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__
             P[g][4 * j + 3] = v.w;
         }
 #pragma unroll
-        for (int w = 0; w < W && !FAST; ++w) {
+        for (int w = 0; w < W; ++w) {
             // set-empty bins: code 0xFF, every plane set
             uint32_t e = P[g][w];
 #pragma unroll
@@ -208,43 +208,6 @@ __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__
 
     const uint32_t qa = q_lo + chunk * a.q_per_wave;
     const uint32_t qb = min(q_hi, qa + a.q_per_wave);
-    if constexpr (FAST) {
-        // One record per query (planes, non-empty mask, threshold), read two
-        // queries ahead into alternating registers while the current one is
-        // compared; the record buffer holds one padding record past the last
-        // query, so the read-ahead stays inside it.
-        const uint64_t rstride = (uint64_t)a.cg * RW;
-        uint32_t ra[RW], rb[RW];
-#pragma unroll
-        for (int j = 0; j < RW; ++j) ra[j] = qcodes[qa * rstride + j];
-// one query's comparison and survivor append (written out twice below, on the
-// kernel's own restrict pointers, so that the record loads stay scalar)
-#define HOPH_CODE_QUERY(r, qq)                                                                     \
-        {                                                                                          \
-            uint32_t dn = 0;                                                                       \
-            _Pragma("unroll") for (int w = 0; w < W; ++w) dn +=                                    \
-                __popc(code_diff<W>(P[0], r, w) & r[PW + w]);                                      \
-            const bool survive = ((int32_t)dn < (int32_t)r[PW + 2]) & valid;                       \
-            const uint64_t bal = __builtin_amdgcn_ballot_w64(survive);                             \
-            if (bal) {                                                                             \
-                uint64_t base = 0;                                                                 \
-                if (lane == 0) base = atomicAdd(counters + 0, (unsigned long long)__popcll(bal));  \
-                base = __shfl(base, 0);                                                            \
-                const uint64_t slot = base + lane_rank(bal, lane);                                 \
-                if (survive && slot < a.surv_cap) surv[slot] = Survivor{(qq), (uint32_t)s, 0};     \
-            }                                                                                      \
-        }
-        for (uint32_t q = qa; q < qb; q += 2) {
-#pragma unroll
-            for (int j = 0; j < RW; ++j) rb[j] = qcodes[(q + 1) * rstride + j];
-            HOPH_CODE_QUERY(ra, q)
-            if (q + 1 >= qb) break;
-#pragma unroll
-            for (int j = 0; j < RW; ++j) ra[j] = qcodes[(q + 2) * rstride + j];
-            HOPH_CODE_QUERY(rb, q + 1)
-        }
-#undef HOPH_CODE_QUERY
-    } else {
     for (uint32_t q = qa; q < qb; ++q) {
         const uint32_t *qc = qcodes + (uint64_t)q * a.cg * RW;
         const uint64_t *qmk = qmasks + (uint64_t)q * a.L;
@@ -287,6 +250,92 @@ __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__
         }
     }
     }
+}
+
+// First-group code pass (depth 1, JOINT or LITERAL), TPW tiles of 64 indexed
+// sets per wavefront: each query's record (read with scalar loads, one query
+// ahead) is compared with TPW tiles, so the scalar work of a query is shared
+// by 64 TPW sets.  A pair is kept when its count of differing query-non-empty
+// bins is below the query's threshold (see ScanTab::dthr0).
+template <int W, int TPW>
+__global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_t *__restrict__ codes,
+                                                                  const uint32_t *__restrict__ qcodes,
+                                                                  Survivor *__restrict__ surv,
+                                                                  unsigned long long *__restrict__ counters,
+                                                                  const uint64_t *__restrict__ desc,
+                                                                  const CoarseArgs a) {
+    constexpr int PW = (int)kCodeBits * W, RW = PW + 4;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t n_sets = desc ? desc[1] : a.n_sets;
+    const uint32_t q_lo = desc ? 0u : a.q0, q_hi = desc ? (uint32_t)desc[0] : a.q1;
+    const uint64_t ntiles = (n_sets + 63) / 64;
+    const uint64_t ngroups = (ntiles + TPW - 1) / TPW;
+    const uint32_t nchunks = (q_hi - q_lo + a.q_per_wave - 1) / a.q_per_wave;
+    const uint64_t n_items = ngroups * nchunks;
+    const uint64_t wstride = (uint64_t)gridDim.x * kWaves;
+    const uint64_t ctiles = a.capacity / 64;
+    const uint64_t rstride = (uint64_t)a.cg * RW;
+    for (uint64_t item = (uint64_t)blockIdx.x * kWaves + wave_id_in_block(); item < n_items; item += wstride) {
+        const uint64_t tg = item % ngroups;
+        const uint32_t chunk = (uint32_t)(item / ngroups);
+        uint32_t P[TPW][PW];
+        bool valid[TPW];
+        uint32_t sid[TPW];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+            const uint64_t tile = tg * TPW + t;
+            const uint64_t s = tile * 64 + lane;
+            valid[t] = s < n_sets;
+            sid[t] = (uint32_t)s;
+            if (tile < ntiles) {             // wave-uniform; tiles below ntiles exist (ntiles <= ctiles)
+                const uint4 *src = reinterpret_cast<const uint4 *>(codes + (tile * 64 + lane) * PW);
+#pragma unroll
+                for (int j = 0; j < PW / 4; ++j) {
+                    const uint4 v = src[j];
+                    P[t][4 * j + 0] = v.x;
+                    P[t][4 * j + 1] = v.y;
+                    P[t][4 * j + 2] = v.z;
+                    P[t][4 * j + 3] = v.w;
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < PW; ++j) P[t][j] = 0;
+            }
+        }
+        (void)ctiles;
+        const uint32_t qa = q_lo + chunk * a.q_per_wave;
+        const uint32_t qb = min(q_hi, qa + a.q_per_wave);
+        uint32_t ra[RW], rb[RW];
+#pragma unroll
+        for (int j = 0; j < RW; ++j) ra[j] = qcodes[qa * rstride + j];
+// one query against the TPW tiles, with the survivor append per tile (written
+// out twice below, on the kernel's own restrict pointers, so that the record
+// loads stay scalar)
+#define HOPH_CODE_QUERY_T(r, qq)                                                                   \
+        _Pragma("unroll") for (int t = 0; t < TPW; ++t) {                                          \
+            uint32_t dn = 0;                                                                       \
+            _Pragma("unroll") for (int w = 0; w < W; ++w) dn +=                                    \
+                __popc(code_diff<W>(P[t], r, w) & r[PW + w]);                                      \
+            const bool survive = ((int32_t)dn < (int32_t)r[PW + 2]) & valid[t];                    \
+            const uint64_t bal = __builtin_amdgcn_ballot_w64(survive);                             \
+            if (bal) {                                                                             \
+                uint64_t base = 0;                                                                 \
+                if (lane == 0) base = atomicAdd(counters + 0, (unsigned long long)__popcll(bal));  \
+                base = __shfl(base, 0);                                                            \
+                const uint64_t slot = base + lane_rank(bal, lane);                                 \
+                if (survive && slot < a.surv_cap) surv[slot] = Survivor{(qq), sid[t], 0};          \
+            }                                                                                      \
+        }
+        for (uint32_t q = qa; q < qb; q += 2) {
+#pragma unroll
+            for (int j = 0; j < RW; ++j) rb[j] = qcodes[(q + 1) * rstride + j];
+            HOPH_CODE_QUERY_T(ra, q)
+            if (q + 1 >= qb) break;
+#pragma unroll
+            for (int j = 0; j < RW; ++j) ra[j] = qcodes[(q + 2) * rstride + j];
+            HOPH_CODE_QUERY_T(rb, q + 1)
+        }
+#undef HOPH_CODE_QUERY_T
     }
 }
 
@@ -542,17 +591,19 @@ CoarseArgs coarse_args(const ScanLaunch &l, uint32_t policy) {
 template <int W>
 void codes_launch(const ScanLaunch &l, const CoarseArgs &a, const ScanTab &tab, hipStream_t st, uint32_t blocks) {
     auto *cnt = reinterpret_cast<unsigned long long *>(l.counters);
-#define HOPH_CODES(G, F)                                                                                      \
-    hipLaunchKernelGGL((scan_codes_kernel<W, G, F>), dim3(blocks), dim3(kThreads), 0, st, l.codes, l.qcodes, \
+#define HOPH_CODES(G)                                                                                         \
+    hipLaunchKernelGGL((scan_codes_kernel<W, G>), dim3(blocks), dim3(kThreads), 0, st, l.codes, l.qcodes,    \
                        l.qmasks, l.surv, cnt, l.desc, a, tab)
     switch (l.depth) {
     case 1:
-        if (tab.policy == HOPH_EMPTY_EITHER) HOPH_CODES(1, false);
-        else HOPH_CODES(1, true);
+        if (tab.policy == HOPH_EMPTY_EITHER) HOPH_CODES(1);
+        else
+            hipLaunchKernelGGL((scan_codes_fast_kernel<W, fast_tiles(W)>), dim3(blocks), dim3(kThreads), 0, st,
+                               l.codes, l.qcodes, l.surv, cnt, l.desc, a);
         break;
-    case 2: HOPH_CODES(2, false); break;
-    case 3: HOPH_CODES(3, false); break;
-    default: HOPH_CODES(4, false); break;
+    case 2: HOPH_CODES(2); break;
+    case 3: HOPH_CODES(3); break;
+    default: HOPH_CODES(4); break;
     }
 #undef HOPH_CODES
 }
@@ -611,6 +662,11 @@ void oph_kp(const ScanLaunch &l, const CoarseArgs &a, hoph_ratio T, hipStream_t 
 
 }  // namespace
 
+uint32_t coarse_tiles_per_wave(const ScanLaunch &l, uint32_t policy) {
+    if (!(l.codes && l.depth == 1 && policy != HOPH_EMPTY_EITHER)) return 1u;
+    return (uint32_t)(code_plane_words(l.kp) == 1 ? fast_tiles(1) : fast_tiles(2));
+}
+
 uint32_t max_depth_for_kpad(uint32_t kpad) {
     uint32_t d = 128 / kpad;
     return d < kMaxDepth ? d : kMaxDepth;
@@ -641,7 +697,8 @@ hipError_t launch_scan_coarse(const ScanLaunch &l, const ScanTab &tab, hipStream
         const uint32_t nq = l.q1 - l.q0;
         if (ntiles == 0 || nq == 0) return hipSuccess;
         const uint64_t nchunks = (nq + l.q_per_wave - 1) / l.q_per_wave;
-        blocks = waves_to_blocks(ntiles * nchunks);
+        const uint32_t tpw = coarse_tiles_per_wave(l, tab.policy);
+        blocks = waves_to_blocks((ntiles + tpw - 1) / tpw * nchunks);
     }
     const CoarseArgs a = coarse_args(l, tab.policy);
     if (l.codes) {

@@ -241,7 +241,7 @@ hoph_status tune(hoph_plan *p, hipStream_t st, uint64_t n_sets, uint32_t n_q) {
     hoph_status r = enqueue_sketch(p, best, st);      // signatures for the scan candidates
     if (r) return r;
     float sc_best = 1e30f;
-    for (uint32_t qpw : {4u, 8u, 16u, 32u, 64u}) {
+    for (uint32_t qpw : {4u, 8u, 16u, 32u, 64u, 128u, 256u}) {
         for (uint32_t wpc : {8u, 16u, 32u}) {
             PlanShape s = best;
             s.q_per_wave = qpw;

@@ -162,7 +162,9 @@ hoph_status check_results(const hoph_results *r, uint32_t n_q);
 
 enum class QueryKind { GOPH, HOPH, OPH_FULL };
 
-uint32_t pick_q_per_wave(uint64_t n_sets, uint32_t n_q);
+// Queries per wavefront so that a pass has enough (tile group, query chunk) items
+// to fill the device; tiles_per_wave as coarse_tiles_per_wave reports.
+uint32_t pick_q_per_wave(uint64_t n_sets, uint32_t n_q, uint32_t tiles_per_wave);
 hoph_status copy_counters(Workspace &ws, hipStream_t st);
 hoph_status write_output(Workspace &ws, uint64_t accepted, uint32_t n_q, hoph_results *res, hipStream_t s);
 
