@@ -395,6 +395,27 @@ hoph_status hoph_selftest_bins(const hoph_sketch_params *params, const uint32_t 
                                const uint32_t *h_ids, uint64_t n, uint32_t *out_bin,
                                uint32_t *out_off);
 
+/*
+ * hoph_pair_estimates -- the similarity estimate of n_pairs pairs over their
+ * whole signatures, to report with accepted pairs (d_pairs[2i] = query row < n_q
+ * of d_qsigs, d_pairs[2i+1] = set id < index size; device, uint32):
+ *  - d_est[i] (int64): the weighted sum of group rates, Lemma 3 for an a:b HOPH
+ *    index and the mean of the group rates for a GOPH (OPH layout) index, exactly,
+ *    as an integer over *denominator (written on return, host);
+ *  - d_mb[i], d_eb[i] (uint32): matched and empty bins over all k bins (Eq. 1-4
+ *    under empty_policy), so that Eq. 6 is d_mb / (k - d_eb);
+ *  - d_var[i] (double): Eq. 8 with the observed 1/(k - N_eb) in place of its
+ *    expectation, R = the Eq. 6 estimate and g = d_unions[i] = |D1 u D2| (device,
+ *    nullable: then the large-g limit R (1 - R) / (k - N_eb)).
+ * A pair out of range gets d_est = -1, d_mb = d_eb = 0xFFFFFFFF and a NaN variance.
+ * HOPH_E_UNSUPPORTED where the exact state does not fit (as for queries).
+ * Asynchronous on hip_stream.
+ */
+hoph_status hoph_pair_estimates(const hoph_index *index, const uint32_t *d_qsigs, uint32_t n_q,
+                                const uint32_t *d_pairs, uint64_t n_pairs, uint32_t empty_policy,
+                                const double *d_unions, int64_t *d_est, uint32_t *d_mb, uint32_t *d_eb,
+                                double *d_var, int64_t *denominator, void *hip_stream);
+
 /* hoph_pair_counts -- per-group counts (m_j, e_j) under policy for n_pairs pairs
    (d_pairs[2i] = query row < n_q, d_pairs[2i+1] = set id < index size) against the
    index: d_m and d_e are n_pairs * L uint32, device; a pair out of range gets

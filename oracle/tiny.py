@@ -204,6 +204,33 @@ def hoph_estimate(q: Sequence[int], s: Sequence[int], lay: Layout, goph: bool,
     return total
 
 
+def eq8_plugin(R, nonempty: int, g: Optional[int]) -> Fraction:
+    """Eq. 8 with the expectation of 1/(k - N_eb) replaced by the observed
+    1/nonempty (nonempty = k - N_eb > 0); g = |D1 u D2|, None for the limit of
+    large g, R(1 - R)/nonempty.  Returns 0 for g <= 1."""
+    R = Fraction(R)
+    inv = Fraction(1, nonempty)
+    if g is None:
+        return R * (1 - R) * inv
+    if g <= 1:
+        return Fraction(0)
+    return R * (1 - R) * (inv * (1 + Fraction(1, g - 1)) - Fraction(1, g - 1))
+
+
+def pair_report(q: Sequence[int], s: Sequence[int], lay: Layout, goph: bool, policy: int = EMPTY_JOINT,
+                g: Optional[int] = None):
+    """What is reported with an accepted pair: the whole-signature estimate
+    (Lemma 3 for HOPH, the mean of group rates for GOPH), the matched and empty
+    bins over all k bins (Eq. 1-4), and Eq. 8 with the observed 1/(k - N_eb)
+    at R = the Eq. 6 estimate."""
+    m, e, aj = group_counts(q, s, policy)
+    k = len(q)
+    R6 = group_rate(m, e, k, aj, policy)
+    nonempty = k if policy == EMPTY_LITERAL else k - e
+    var = eq8_plugin(R6, nonempty, g) if nonempty > 0 else Fraction(0)
+    return hoph_estimate(q, s, lay, goph, policy), m, e, var
+
+
 # --------------------------------------------------------------------------
 # Binomial tails (Eq. 10, Table 2) and the small-probability event (Def. 1)
 # --------------------------------------------------------------------------

@@ -87,6 +87,7 @@ SIGNATURES = {
     "index_append": (C.c_int, [vp, vp, u64, vp]),
     "index_append_sets": (C.c_int, [vp, vp, vp, u64, vp]),
     "hoph_append_timing": (C.c_int, [vp, C.POINTER(C.c_float)]),
+    "hoph_pair_estimates": (C.c_int, [vp, vp, u32, vp, u64, u32, vp, vp, vp, vp, vp, C.POINTER(C.c_int64), vp]),
     "hoph_index_size": (u64, [vp]),
     "hoph_index_reset": (C.c_int, [vp]),
     "hoph_query_timing": (C.c_int, [vp, C.POINTER(C.c_float)]),
@@ -537,6 +538,37 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def pair_estimates(index: Index, qsigs, pairs, policy=EMPTY_JOINT, unions=None, stream=None):
+    """Whole-signature estimates of (query row, set id) pairs: a dict with
+    'est' (int64, over 'denominator'), 'mb', 'eb' (int32 holding uint32) and
+    'var' (float64, Eq. 8 with the observed 1/(k - N_eb); g from `unions`)."""
+    import torch
+    _need_cuda(qsigs, "qsigs", (torch.int32,))
+    _need_cuda(pairs, "pairs", (torch.int32,))
+    if unions is not None:
+        _need_cuda(unions, "unions", (torch.float64,))
+    n = pairs.shape[0]
+    dev = qsigs.device
+    est = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+    mb = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    eb = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    var = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    den = C.c_int64()
+    _check(lib().hoph_pair_estimates(index.handle, vp(qsigs.data_ptr()), qsigs.shape[0], vp(pairs.data_ptr()), n,
+                                     policy, vp(unions.data_ptr()) if unions is not None else None,
+                                     vp(est.data_ptr()), vp(mb.data_ptr()), vp(eb.data_ptr()), vp(var.data_ptr()),
+                                     C.byref(den), _stream(stream)))
+    return {"est": est[:n], "mb": mb[:n], "eb": eb[:n], "var": var[:n], "denominator": den.value}
+
+
+def result_pairs(offsets, ids):
+    """(query row, set id) pairs, int32 (n, 2), of a CSR result on the device."""
+    import torch
+    counts = (offsets[1:] - offsets[:-1]).to(torch.int64)
+    rows = torch.repeat_interleave(torch.arange(counts.numel(), device=offsets.device, dtype=torch.int32), counts)
+    return torch.stack([rows, ids.to(torch.int32)], dim=1).contiguous()
 
 
 def pair_counts(index: Index, qsigs, pairs, policy=EMPTY_JOINT, stream=None):

@@ -675,4 +675,32 @@ hoph_status hoph_pair_counts(const hoph_index *idx, const uint32_t *d_qsigs, uin
     return HOPH_OK;
 }
 
+hoph_status hoph_pair_estimates(const hoph_index *idx, const uint32_t *d_qsigs, uint32_t n_q, const uint32_t *d_pairs,
+                                uint64_t n_pairs, uint32_t policy, const double *d_unions, int64_t *d_est,
+                                uint32_t *d_mb, uint32_t *d_eb, double *d_var, int64_t *denominator,
+                                void *hip_stream) {
+    g_last_error.clear();
+    if (!idx) return fail(HOPH_E_INVAL, "index is NULL");
+    if (policy > HOPH_EMPTY_EITHER) return fail(HOPH_E_INVAL, "unknown empty policy");
+    hoph_query_params qp{};
+    qp.T = hoph_ratio{1, 2};                      // the weights and rate scale do not depend on T or eps
+    qp.eps = hoph_ratio{1, 2};
+    qp.empty_policy = policy;
+    hoph_decision_tables t;
+    std::string err;
+    hoph_status st = build_tables(idx->lay, qp, idx->params.layout == HOPH_LAYOUT_OPH, t, err);
+    if (st) return fail(st, err);
+    ScanTab tab{};
+    to_scan_tab(t, tab);
+    if (denominator) *denominator = (int64_t)t.wsum * tab.lambda;
+    if (n_pairs == 0) return HOPH_OK;
+    if (!d_qsigs || !d_pairs || !d_est || !d_mb || !d_eb || !d_var) return fail(HOPH_E_INVAL, "NULL device pointer");
+    DeviceGuard dg(idx->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    HOPH_HIP(launch_pair_estimates(idx->slab, idx->n, idx->lay.k, idx->lay.kp, idx->lay.L, d_qsigs, n_q, d_pairs,
+                                   n_pairs, policy, d_unions, d_est, d_mb, d_eb, d_var, tab, s),
+             "pair estimates launch");
+    return HOPH_OK;
+}
+
 }  // extern "C"

@@ -355,6 +355,10 @@ hipError_t launch_scan_coarse(const ScanLaunch &a, const ScanTab &tab, hipStream
 uint32_t coarse_tiles_per_wave(const ScanLaunch &a, uint32_t policy);
 hipError_t launch_scan_fine(const ScanLaunch &a, const ScanTab &tab, hipStream_t st);
 hipError_t launch_oph_full(const ScanLaunch &a, hoph_ratio T, uint32_t policy, hipStream_t st);
+hipError_t launch_pair_estimates(const uint32_t *slab, uint64_t n_sets, uint32_t k, uint32_t kp, uint32_t L,
+                                 const uint32_t *qsigs, uint32_t n_q, const uint32_t *pairs, uint64_t n_pairs,
+                                 uint32_t policy, const double *unions, int64_t *est, uint32_t *mb, uint32_t *eb,
+                                 double *var, const ScanTab &tab, hipStream_t st);
 hipError_t launch_sort_keys(uint64_t *keys, uint64_t n, uint64_t n_pow2, hipStream_t st);
 // counters: [1] accepted keys (read), [2] total written, [3] flags (bit 0: a query
 // has more than 4096 ids, bit 1: total > out_cap).  desc (nullable): desc[0] = n_q.

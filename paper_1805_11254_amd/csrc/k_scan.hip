@@ -502,6 +502,81 @@ __global__ __launch_bounds__(kThreads) void scan_fine_kernel(const uint32_t *__r
     }
 }
 
+// Full-signature estimate of pairs (query row q, set id s), one wavefront per
+// pair and one lane per bin: the exact weighted state over every group
+// (Lemma 3 for HOPH, the mean of the group rates for GOPH, scaled by the
+// tables' weight sum times lambda), the matched and empty counts over all k
+// bins (Eq. 6), and the variance of Eq. 8 with the observed 1 / (k - N_eb) in
+// place of its expectation and g = |D1 u D2| from `unions` (the large-g limit
+// R (1 - R) / (k - N_eb) when it is null).
+__global__ __launch_bounds__(kThreads) void pair_estimates_kernel(const uint32_t *__restrict__ slab, uint64_t n_sets,
+                                                                 uint32_t k, uint32_t kp, uint32_t L,
+                                                                 const uint32_t *__restrict__ qsigs, uint32_t n_q,
+                                                                 const uint32_t *__restrict__ pairs, uint64_t n_pairs,
+                                                                 uint32_t policy, const double *__restrict__ unions,
+                                                                 int64_t *__restrict__ est, uint32_t *__restrict__ mb,
+                                                                 uint32_t *__restrict__ eb, double *__restrict__ var,
+                                                                 const ScanTab tab) {
+    __shared__ int64_t s_dmul[HOPH_MAX_KGROUP + 1];
+    for (uint32_t i = threadIdx.x; i <= tab.kp; i += kThreads) s_dmul[i] = tab.dmul[i];
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63;
+    const bool in = lane < kp;
+    const uint64_t nw = (uint64_t)gridDim.x * kWaves;
+    for (uint64_t p = (uint64_t)blockIdx.x * kWaves + wave_id_in_block(); p < n_pairs; p += nw) {
+        const uint64_t q = pairs[2 * p], s = pairs[2 * p + 1];
+        if (q >= n_q || s >= n_sets) {
+            if (lane == 0) {
+                est[p] = -1;
+                mb[p] = eb[p] = 0xFFFFFFFFu;
+                var[p] = __builtin_nan("");
+            }
+            continue;
+        }
+        int64_t S = 0;
+        uint32_t M = 0, EJ = 0, EE = 0;
+        const uint32_t *sr = slab + s * k + lane, *qr = qsigs + q * k + lane;
+        for (uint32_t g = 0; g < L; ++g) {
+            uint32_t sw = 0, qv = 0;
+            if (in) {
+                sw = sr[g * kp];
+                qv = qr[g * kp];
+            }
+            const uint64_t eqb = __ballot(in && sw == qv);
+            const uint64_t qe = __ballot(in && qv == HOPH_EMPTY);
+            const uint64_t se = __ballot(in && sw == HOPH_EMPTY);
+            const uint32_t ej = __popcll(qe & se), ee = __popcll(qe | se), eq = __popcll(eqb);
+            S += tab.W[g] * group_rho(eq, ej, ee, kp, policy, s_dmul, tab.lambda);
+            M += eq - ej;
+            EJ += ej;
+            EE += ee;
+        }
+        if (lane == 0) {
+            const uint32_t e = policy == HOPH_EMPTY_JOINT ? EJ : policy == HOPH_EMPTY_EITHER ? EE : 0u;
+            double R, inv;
+            if (policy == HOPH_EMPTY_LITERAL) {
+                R = (double)M / k;
+                inv = 1.0 / k;
+            } else if (e < k) {
+                R = (double)M / (k - e);
+                inv = 1.0 / (k - e);
+            } else {
+                R = EJ == k ? 1.0 : 0.0;          // the 0/0 rule of the per-group rate
+                inv = 0.0;
+            }
+            double v = R * (1.0 - R) * inv;       // g -> infinity
+            if (unions) {
+                const double gg = unions[p];
+                v = gg > 1.0 ? R * (1.0 - R) * (inv * (1.0 + 1.0 / (gg - 1.0)) - 1.0 / (gg - 1.0)) : 0.0;
+            }
+            est[p] = S;
+            mb[p] = M;
+            eb[p] = e;
+            var[p] = v;
+        }
+    }
+}
+
 // Plain OPH comparator (Eq. 6 over all k bins, no early stop).
 template <int KPAD, bool EXACT>
 __global__ __launch_bounds__(kThreads) void oph_full_kernel(const uint32_t *__restrict__ slab,
@@ -717,6 +792,18 @@ hipError_t launch_scan_fine(const ScanLaunch &l, const ScanTab &tab, hipStream_t
     const CoarseArgs a = coarse_args(l, tab.policy);
     hipLaunchKernelGGL(scan_fine_kernel, dim3(blocks), dim3(kThreads), 0, st, l.slab, l.qsigs, l.surv, l.keys,
                        reinterpret_cast<unsigned long long *>(l.counters), a, tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_estimates(const uint32_t *slab, uint64_t n_sets, uint32_t k, uint32_t kp, uint32_t L,
+                                 const uint32_t *qsigs, uint32_t n_q, const uint32_t *pairs, uint64_t n_pairs,
+                                 uint32_t policy, const double *unions, int64_t *est, uint32_t *mb, uint32_t *eb,
+                                 double *var, const ScanTab &tab, hipStream_t st) {
+    if (n_pairs == 0) return hipSuccess;
+    uint64_t blocks = (n_pairs + kWaves - 1) / kWaves;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(pair_estimates_kernel, dim3((uint32_t)blocks), dim3(kThreads), 0, st, slab, n_sets, k, kp, L,
+                       qsigs, n_q, pairs, n_pairs, policy, unions, est, mb, eb, var, tab);
     return hipGetLastError();
 }
 

@@ -462,3 +462,43 @@ def test_append_sets_reports_range_and_empty_sets():
                         torch.arange(8, dtype=torch.int64, device="cuda"))
     assert ei.value.status == H.HOPH_E_CAPACITY
     idx.free()
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_pair_estimates_match_oracle(name):
+    """Whole-signature estimate (Lemma 3 / group mean, exact), Eq. 6 counts and
+    the Eq. 8 plug-in variance for accepted and random pairs."""
+    import torch
+    _print_case(f"pair_estimates {name}")
+    w = workload(name)
+    p = params_of(w)
+    sig = gpu_sketch(w, w.collection, p)
+    qsig = gpu_sketch(w, w.queries, p)
+    idx = H.Index(p, sig)
+    sh, qh = to_u32(sig), to_u32(qsig)
+    kind = "goph" if w.goph else "hoph"
+    lay = tiny.Layout(w.layout, tiny.hash_range(w.hash_kind, w.universe), w.k, w.kp, w.ra, w.rb)
+    go, gi = H.query_goph(idx, qsig) if w.goph else H.query_hoph(idx, qsig)
+    acc = H.result_pairs(go, gi)
+    rng = np.random.default_rng(7)
+    rnd = torch.tensor([(int(rng.integers(w.queries.n)), int(rng.integers(w.collection.n))) for _ in range(300)]
+                       + [(w.queries.n, 0), (0, w.collection.n)], dtype=torch.int32, device="cuda")
+    pairs = torch.cat([acc, rnd]).contiguous()
+    ph = pairs.cpu().numpy()
+    unions = torch.tensor([float(2 + (i % 5000)) for i in range(ph.shape[0])], dtype=torch.float64, device="cuda")
+    for policy in _policies_that_fit(p, (4, 5), (1, 10_000)):
+        for u in (None, unions):
+            r = H.pair_estimates(idx, qsig, pairs, policy, unions=u)
+            est, mb, eb, var = (r["est"].cpu().numpy(), r["mb"].cpu().numpy().view(np.uint32),
+                                r["eb"].cpu().numpy().view(np.uint32), r["var"].cpu().numpy())
+            den = r["denominator"]
+            for i, (q, s) in enumerate(ph.tolist()):
+                if q >= w.queries.n or s >= w.collection.n:
+                    assert est[i] == -1 and mb[i] == 0xFFFFFFFF and np.isnan(var[i])
+                    continue
+                g = None if u is None else int(unions[i].item())
+                R, m, e, v = tiny.pair_report(qh[q].tolist(), sh[s].tolist(), lay, w.goph, policy, g)
+                assert Fraction(int(est[i]), den) == R, (policy, q, s)
+                assert (int(mb[i]), int(eb[i])) == (m, e), (policy, q, s)
+                assert abs(var[i] - float(v)) <= 1e-12 * max(1.0, abs(float(v))), (policy, q, s, var[i], float(v))
+    idx.free()

@@ -332,3 +332,30 @@ def test_layout_bins_partition_range():
         assert all(c > 0 for c in counts)
         for j, (s, e) in enumerate(lay.groups):
             assert lay.starts[j * lay.kp] == s
+
+
+# ---------------------------------------------------------------------------
+# Eq. 8 as reported per accepted pair (observed 1/(k - N_eb) for its expectation)
+# ---------------------------------------------------------------------------
+def pin_eq8_plugin():
+    # where every bin always holds an element of the union (A u B = the whole
+    # universe), N_eb = 0 for every permutation, so the observed 1/k is the
+    # expectation and the plug-in must equal the exhaustive variance of Eq. 8
+    D = 8
+    for A, B in [({0, 1, 2, 3}, {2, 3, 4, 5, 6, 7}), ({0, 1, 2, 3, 4, 5}, {4, 5, 6, 7})]:
+        assert A | B == set(range(D))
+        J, g = tiny.jaccard(A, B), len(A | B)
+        for k in (2, 4, 8):
+            est = _exhaustive_estimates(A, B, D, k)
+            assert all(e == 0 for _, e in est)
+            var = sum((r - J) ** 2 for r, _ in est) / len(est)
+            assert tiny.eq8_plugin(J, k, g) == var, (A, B, k)
+    # the limit of large g is the binomial variance; no variance at R = 0 or 1
+    for R, n in [(F(1, 3), 7), (F(5, 8), 32), (F(0), 5), (F(1), 9)]:
+        assert tiny.eq8_plugin(R, n, None) == R * (1 - R) / n
+        assert abs(float(tiny.eq8_plugin(R, n, 10 ** 12)) - float(R * (1 - R) / n)) < 1e-9
+    assert tiny.eq8_plugin(F(0), 4, 10) == 0 and tiny.eq8_plugin(F(1), 4, 10) == 0
+
+
+def test_eq8_plugin():
+    pin_eq8_plugin()
