@@ -396,6 +396,18 @@ hoph_status hoph_selftest_bins(const hoph_sketch_params *params, const uint32_t 
                                uint32_t *out_off);
 
 /*
+ * hoph_self_join -- near-duplicate detection inside the collection (the query of
+ * Sec. 3.3 with q taken from the collection itself): every pair of index rows
+ * i < j that the grouped (OPH-layout index, Alg. 1) or hierarchical (HIER index,
+ * Alg. 2) comparison accepts, as CSR over the rows: for row i, the ascending j > i
+ * in d_set_ids[d_offsets[i] .. d_offsets[i+1]); d_offsets has size + 1 entries.
+ * The decision is symmetric, so the pair (j, i) is not repeated.  Errors and
+ * capacity reporting as for query_hoph.  Synchronises the stream.
+ */
+hoph_status hoph_self_join(const hoph_index *index, const hoph_query_params *qp,
+                           hoph_results *results, void *hip_stream);
+
+/*
  * hoph_pair_estimates -- the similarity estimate of n_pairs pairs over their
  * whole signatures, to report with accepted pairs (d_pairs[2i] = query row < n_q
  * of d_qsigs, d_pairs[2i+1] = set id < index size; device, uint32):

@@ -87,6 +87,7 @@ SIGNATURES = {
     "index_append": (C.c_int, [vp, vp, u64, vp]),
     "index_append_sets": (C.c_int, [vp, vp, vp, u64, vp]),
     "hoph_append_timing": (C.c_int, [vp, C.POINTER(C.c_float)]),
+    "hoph_self_join": (C.c_int, [vp, C.POINTER(QueryParamsC), C.POINTER(ResultsC), vp]),
     "hoph_pair_estimates": (C.c_int, [vp, vp, u32, vp, u64, u32, vp, vp, vp, vp, vp, C.POINTER(C.c_int64), vp]),
     "hoph_index_size": (u64, [vp]),
     "hoph_index_reset": (C.c_int, [vp]),
@@ -331,6 +332,25 @@ def query_hoph(index: Index, qsigs, T=(4, 5), eps=(1, 10000), policy=EMPTY_JOINT
                coarse_depth=0, stream=None, coarse=COARSE_CODES):
     """Alg. 2 over the index: (offsets int64[n_q+1], set ids int32[...])."""
     return _query("query_hoph", index, qsigs, T, eps, policy, capacity, coarse_depth, stream, coarse)
+
+
+def self_join(index: Index, T=(4, 5), eps=(1, 10000), policy=EMPTY_JOINT, capacity=None, coarse_depth=0,
+              stream=None, coarse=COARSE_CODES):
+    """Near-duplicate pairs i < j inside the index: (offsets int64[n+1], ids int32[...])."""
+    import torch
+    qp = QueryParamsC(_ratio(T), _ratio(eps), policy, coarse_depth, coarse, 0)
+    n = len(index)
+    offsets = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    cap = capacity if capacity is not None else max(4096, 8 * n)
+    while True:
+        ids = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
+        res = ResultsC(offsets.data_ptr(), ids.data_ptr(), cap, 0)
+        st = lib().hoph_self_join(index.handle, C.byref(qp), C.byref(res), _stream(stream))
+        if st == HOPH_E_CAPACITY and capacity is None:
+            cap = int(res.needed)
+            continue
+        _check(st, int(res.needed))
+        return offsets, ids[:int(res.needed)]
 
 
 def query_oph_full(index: Index, qsigs, T=(4, 5), policy=EMPTY_JOINT, capacity=None, stream=None):

@@ -119,9 +119,15 @@ hipError_t append_sets_async(hoph_index *idx, const uint32_t *d_ids, const uint6
 }
 
 hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t n_q, const hoph_query_params *qp,
-                      hoph_results *res, void *stream, QueryKind kind) {
+                      hoph_results *res, void *stream, QueryKind kind, bool self_join) {
     if (!cidx) return fail(HOPH_E_INVAL, "index is NULL");
     if (!qp) return fail(HOPH_E_INVAL, "query params are NULL");
+    if (self_join) {
+        // the queries are the index rows themselves; only set id > row is reported
+        if (kind == QueryKind::OPH_FULL) return fail(HOPH_E_UNSUPPORTED, "self-join of the plain OPH comparator");
+        d_qsigs = cidx->slab;
+        n_q = (uint32_t)cidx->n;
+    }
     if (n_q && !d_qsigs) return fail(HOPH_E_INVAL, "d_qsigs is NULL");
     if (!valid_ratio_T(qp->T)) return fail(HOPH_E_INVAL, "T must be an exact ratio in (0, 1]");
     if (kind != QueryKind::OPH_FULL && !valid_ratio_eps(qp->eps)) return fail(HOPH_E_INVAL, "eps must be in [0, 1)");
@@ -169,6 +175,7 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
     a.k = lay.k;
     a.qsigs = d_qsigs;
     a.depth = depth;
+    a.tri = self_join;
     a.counters = ws.counters;
     if (kind != QueryKind::OPH_FULL && n_q && idx->n) {
         st = ws.grow_qmasks((uint64_t)n_q * lay.L);
@@ -673,6 +680,14 @@ hoph_status hoph_pair_counts(const hoph_index *idx, const uint32_t *d_qsigs, uin
              "pair counts launch");
     HOPH_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
     return HOPH_OK;
+}
+
+hoph_status hoph_self_join(const hoph_index *index, const hoph_query_params *qp, hoph_results *res,
+                           void *hip_stream) {
+    g_last_error.clear();
+    if (!index) return fail(HOPH_E_INVAL, "index is NULL");
+    const QueryKind kind = index->params.layout == HOPH_LAYOUT_OPH ? QueryKind::GOPH : QueryKind::HOPH;
+    return run_query(index, nullptr, 0, qp, res, hip_stream, kind, true);
 }
 
 hoph_status hoph_pair_estimates(const hoph_index *idx, const uint32_t *d_qsigs, uint32_t n_q, const uint32_t *d_pairs,

@@ -334,6 +334,7 @@ struct ScanLaunch {
     const uint32_t *codes;      // index code planes, or null: coarse pass on the 32-bit words
     const uint32_t *qcodes;     // n_q x cg x code_rec_words(kp) query code records
     uint32_t cg;                // groups with codes (index and queries)
+    bool tri;                   // self-join (queries are the index rows): only set id > query row
     uint32_t q0, q1;            // query rows [q0, q1)
     uint32_t depth;             // coarse groups
     uint32_t q_per_wave;

@@ -31,6 +31,7 @@ constexpr int fast_tiles(int W) { return W == 1 ? 4 : 2; }
 struct CoarseArgs {
     uint64_t capacity, n_sets, surv_cap, keys_cap;
     uint32_t k, kp, kpad, L, q0, q1, q_per_wave, policy, depth, cg;
+    uint32_t tri;        // self-join: only pairs with set id > query row
 };
 
 __device__ __forceinline__ uint32_t wave_id_in_block() {
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__
         bool survive;
         {
             int64_t S = 0;
-            bool undecided = valid, maybe = false;
+            bool undecided = valid && (!a.tri || s > q), maybe = false;
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 if (!__any(undecided)) break;
@@ -305,6 +306,8 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_
         (void)ctiles;
         const uint32_t qa = q_lo + chunk * a.q_per_wave;
         const uint32_t qb = min(q_hi, qa + a.q_per_wave);
+        // self-join: no pair of this item has set id > query row
+        if (a.tri && (tg + 1) * TPW * 64 <= (uint64_t)qa + 1) continue;
         uint32_t ra[RW], rb[RW];
 #pragma unroll
         for (int j = 0; j < RW; ++j) ra[j] = qcodes[qa * rstride + j];
@@ -316,7 +319,8 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_
             uint32_t dn = 0;                                                                       \
             _Pragma("unroll") for (int w = 0; w < W; ++w) dn +=                                    \
                 __popc(code_diff<W>(P[t], r, w) & r[PW + w]);                                      \
-            const bool survive = ((int32_t)dn < (int32_t)r[PW + 2]) & valid[t];                    \
+            const bool survive = ((int32_t)dn < (int32_t)r[PW + 2]) & valid[t] &                   \
+                                 (!a.tri | (sid[t] > (qq)));                                         \
             const uint64_t bal = __builtin_amdgcn_ballot_w64(survive);                             \
             if (bal) {                                                                             \
                 uint64_t base = 0;                                                                 \
@@ -393,7 +397,7 @@ __global__ __launch_bounds__(kThreads) void scan_coarse_kernel(const uint32_t *_
         const uint32_t *qw = qsigs + (uint64_t)q * a.k;
         const uint64_t *qmk = qmasks + (uint64_t)q * a.L;
         int64_t S = 0;
-        bool undecided = valid, accept = false;
+        bool undecided = valid && (!a.tri || s > q), accept = false;
         if constexpr (G == 1) {
             uint32_t eq = 0;
             const uint64_t qm = qmk[0];
@@ -415,8 +419,9 @@ __global__ __launch_bounds__(kThreads) void scan_coarse_kernel(const uint32_t *_
                 acc = S0 >= tab.acc[0];
                 rej = S0 <= tab.rej[0];
             }
-            accept = valid && acc;
-            undecided = valid && !acc && !rej;
+            const bool pair_ok = valid && (!a.tri || s > q);
+            accept = pair_ok && acc;
+            undecided = pair_ok && !acc && !rej;
             if (__any(undecided)) {
                 // the state after the first group, for the pairs that continue
                 const int64_t rho = policy == HOPH_EMPTY_LITERAL ? (int64_t)m
@@ -660,6 +665,7 @@ CoarseArgs coarse_args(const ScanLaunch &l, uint32_t policy) {
     a.policy = policy;
     a.depth = l.codes ? 0u : l.depth;      // where the fine pass starts
     a.cg = l.cg;
+    a.tri = l.tri ? 1u : 0u;
     return a;
 }
 

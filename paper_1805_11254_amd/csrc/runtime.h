@@ -192,5 +192,5 @@ hipError_t append_sets_async(hoph_index *idx, const uint32_t *d_ids, const uint6
                              uint64_t first, uint32_t *err_word, hipStream_t s, bool timed);
 // GOPH / HOPH / plain-OPH query through the index's own workspace (host-synchronised).
 hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t n_q, const hoph_query_params *qp,
-                      hoph_results *res, void *stream, QueryKind kind);
+                      hoph_results *res, void *stream, QueryKind kind, bool self_join = false);
 }  // namespace hoph

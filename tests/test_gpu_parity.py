@@ -502,3 +502,43 @@ def test_pair_estimates_match_oracle(name):
                 assert (int(mb[i]), int(eb[i])) == (m, e), (policy, q, s)
                 assert abs(var[i] - float(v)) <= 1e-12 * max(1.0, abs(float(v))), (policy, q, s, var[i], float(v))
     idx.free()
+
+
+def _with_queries_inside(w):
+    """The workload's query sets placed in front of its collection, so that the
+    planted near-duplicates are pairs inside one collection."""
+    q, c = w.queries, w.collection
+    ids = np.concatenate([q.ids, c.ids]).astype(np.uint32)
+    offs = np.concatenate([q.offsets, c.offsets[1:] + q.offsets[-1]]).astype(np.uint64)
+    return W.Collection(ids, offs)
+
+
+SELF_JOIN = {
+    "goph_tiny": lambda: W.tiny_goph(n=1500),
+    "hoph11_bovw": lambda: W.hoph_bovw(n=3_000, n_q=40, seed=51, planted_frac=0.05),
+    "hoph12_shingles": lambda: W.hoph_shingles(n=2_500, n_q=30, seed=52, ra=1, rb=2, T=(7, 10)),
+}
+
+
+@pytest.mark.parametrize("name", list(SELF_JOIN))
+def test_self_join_matches_oracle(name):
+    """Every accepted pair i < j inside the collection, as the oracle's full
+    pair matrix restricted to j > i (the decision is symmetric)."""
+    _print_case(f"self_join {name}")
+    w = SELF_JOIN[name]()
+    coll = _with_queries_inside(w)
+    p = params_of(w)
+    sig = gpu_sketch(w, coll, p)
+    sh = to_u32(sig)
+    idx = H.Index(p, sig)
+    n = coll.n
+    for T, eps in (((4, 5), (1, 10_000)), ((1, 2), (1, 100))):
+        for policy in (H.EMPTY_JOINT, H.EMPTY_EITHER):
+            oo, oi = oracle_query(w, sh, sh, T, eps, policy)
+            want = [[j for j in row if j > i] for i, row in enumerate(csr_lists(oo, oi))]
+            assert sum(len(r) for r in want) > 0
+            for coarse in (H.COARSE_CODES, H.COARSE_WORDS):
+                go, gi = H.self_join(idx, T=T, eps=eps, policy=policy, coarse=coarse)
+                got = csr_lists(go.cpu().numpy(), to_u32(gi))
+                assert len(got) == n and got == want, (T, eps, policy, coarse)
+    idx.free()
