@@ -48,10 +48,12 @@ def parse():
     ap.add_argument("--cpu-sample-queries", type=int, default=512)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for scaling HBM counters)")
-    ap.add_argument("--mode", choices=["step", "batched", "serve", "comparators"], default="step",
+    ap.add_argument("--mode", choices=["step", "batched", "serve", "comparators", "selfjoin", "sweeps"],
+                    default="step",
                     help="step: the whole-path step (default JSON line); batched: uneven query batches through "
                          "graph-replayed plans; serve: Poisson arrivals through the serving loop; comparators: "
-                         "one-query-per-launch OPH/HOPH and MinWise on the same GPU")
+                         "one-query-per-launch OPH/HOPH and MinWise on the same GPU; selfjoin: every pair inside "
+                         "one collection; sweeps: GOPH group count, error tolerance and threshold sweeps")
     ap.add_argument("--batches", type=int, default=256)
     ap.add_argument("--rates", type=str, default="20000,50000,100000,200000")
     ap.add_argument("--serve-seconds", type=float, default=0.5)
@@ -386,6 +388,185 @@ def bench_comparators(args):
     print(json.dumps(out), flush=True)
 
 
+def _exact_j(a, b) -> float:
+    import numpy as np
+    a_ = np.unique(a)
+    b_ = np.unique(b)
+    inter = np.intersect1d(a_, b_, assume_unique=True).size
+    return inter / (a_.size + b_.size - inter)
+
+
+def _pairs_of(offs, ids):
+    """Result pairs (row, id) of a CSR answer (host arrays)."""
+    import numpy as np
+    rows = np.repeat(np.arange(len(offs) - 1, dtype=np.int64), np.diff(offs))
+    return set(zip(rows.tolist(), ids.astype(np.int64).tolist()))
+
+
+def _workload_params(H, w, k=None, kp=None, layout=None):
+    return H.SketchParams(w.layout if layout is None else layout, k or w.k, kp or w.kp, w.hash_kind, w.universe,
+                          w.ra, w.rb, w.ha, w.hb)
+
+
+def bench_selfjoin(args):
+    """Near-duplicate pairs inside one collection: the default step's 1,000,000
+    bag-of-visual-words sets with its 1,024 query sets placed in front, so that
+    each query and its planted near-duplicates are pairs inside the collection;
+    HOPH (1:1) k = 512 in groups of 32, T = 4/5, eps = 1e-4.  One call decides
+    all N(N-1)/2 pairs i < j with a triangular scan (coarse pass on the codes of
+    the first group, per-survivor pass on the words, sorted CSR output).  Recall
+    is taken over every pair inside a query's family (the query and its planted
+    copies) whose exact Jaccard similarity reaches T; precision from the exact
+    similarity of every returned pair."""
+    import numpy as np
+    import torch
+    import paper_1805_11254_amd as H
+    import workloads as W
+    w = W.hoph_bovw(n=args.n_sets or 1_000_000, n_q=args.n_queries, seed=args.seed)
+    Q = w.queries.n
+    q, c = w.queries, w.collection
+    coll = W.Collection(np.concatenate([q.ids, c.ids]).astype(np.uint32),
+                        np.concatenate([q.offsets, c.offsets[1:] + q.offsets[-1]]).astype(np.uint64))
+    N = coll.n
+    dev = torch.device("cuda")
+    p = _workload_params(H, w)
+    ids = torch.from_numpy(coll.ids.view(np.int32)).to(dev)
+    offs = torch.from_numpy(coll.offsets.view(np.int64)).to(dev)
+    idx = H.Index(p, H.sketch_oph(p, ids, offs))
+    del ids, offs
+    T = w.T[0] / w.T[1]
+    # every family pair (query and planted copies, ids shifted by Q) with exact J >= T
+    fam = {}
+    for (qi, slot, _) in w.planted:
+        fam.setdefault(qi, [qi]).append(Q + slot)
+    truth = set()
+    for members in fam.values():
+        members = sorted(members)
+        for i in range(len(members)):
+            for j in range(i + 1, len(members)):
+                if _exact_j(coll.set(members[i]), coll.set(members[j])) >= T:
+                    truth.add((members[i], members[j]))
+    log(f"self-join: {N} sets, {len(truth)} family pairs at J >= T")
+    out = {"metric": "pairs inside the collection decided/s", "unit": "pairs/s", "mode": "selfjoin",
+           "config": {"workload": "hoph_1to1_bovw_selfjoin", "n_sets": N, "k": w.k, "k_group": w.kp,
+                      "T": list(w.T), "eps": list(w.eps), "pairs": N * (N - 1) // 2}}
+    for name, coarse in (("codes", H.COARSE_CODES), ("words", H.COARSE_WORDS)):
+        for _ in range(max(1, args.warmup)):
+            H.self_join(idx, T=w.T, eps=w.eps, coarse=coarse)
+        torch.cuda.synchronize()
+        walls, passes = [], []
+        for _ in range(max(1, args.steps)):
+            t0 = time.perf_counter()
+            so, si = H.self_join(idx, T=w.T, eps=w.eps, coarse=coarse)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t0)
+            passes.append(idx.last_query_ms())
+        wall = float(np.median(walls))
+        got = _pairs_of(so.cpu().numpy(), si.cpu().numpy().view(np.uint32))
+        pr = sorted(got)
+        sample = pr[:: max(1, len(pr) // 20000)]
+        prec = sum(_exact_j(coll.set(a), coll.set(b)) >= T for (a, b) in sample) / max(1, len(sample))
+        coarse_ms, fine_ms, sort_ms = (float(np.median([x[i] for x in passes])) for i in range(3))
+        out[name] = {"seconds": wall, "pairs_per_s": N * (N - 1) / 2 / wall, "coarse_ms": coarse_ms,
+                     "fine_ms": fine_ms, "sort_ms": sort_ms, "accepted": len(got),
+                     "recall": len(truth & got) / max(1, len(truth)), "precision": prec,
+                     "precision_sample": len(sample)}
+        log(f"self-join {name}: {wall * 1e3:.1f} ms, {len(got)} pairs")
+    out["value"] = out["codes"]["pairs_per_s"]
+    out["ms_per_step"] = out["codes"]["seconds"] * 1e3
+    idx.free()
+    print(json.dumps(out), flush=True)
+
+
+def bench_sweeps(args):
+    """Synthetic versions of the paper's parameter studies (experiments
+    section): 600,000 bag-of-visual-words sets (the paper's default data
+    number) and 1,024 queries with 1% of the collection planted as
+    near-duplicates at J in [0.5, 0.98]; defaults T = 0.7, eps = 1e-4.
+    (1) GOPH group count n at k = 320 (n = 320/k' for k' in 40 ... 5);
+    (2) error tolerance eps in 1e-2 ... 1e-6 for GOPH (n = 10) and HOPH (1:1,
+    k = 512 in groups of 32); (3) threshold T in 0.5 ... 0.9 for both.  Each
+    point: the batch's device time (coarse, per-survivor, sort), the scan's
+    pairs/s, and recall / precision against exact Jaccard similarity."""
+    import numpy as np
+    import torch
+    import paper_1805_11254_amd as H
+    import workloads as W
+    N = args.n_sets or 600_000
+    w = W.hoph_bovw(n=N, n_q=args.n_queries, seed=args.seed + 11, T=(7, 10))
+    Q = w.queries.n
+    dev = torch.device("cuda")
+    ids = torch.from_numpy(w.collection.ids.view(np.int32)).to(dev)
+    offs = torch.from_numpy(w.collection.offsets.view(np.int64)).to(dev)
+    qids = torch.from_numpy(w.queries.ids.view(np.int32)).to(dev)
+    qoffs = torch.from_numpy(w.queries.offsets.view(np.int64)).to(dev)
+    jcache = {}
+
+    def exact(qi, s):
+        key = (qi, s)
+        if key not in jcache:
+            jcache[key] = _exact_j(w.queries.set(qi), w.collection.set(s))
+        return jcache[key]
+
+    planted = [(qi, s) for (qi, s, _) in w.planted]
+
+    def point(idx, qsig, goph, T, eps):
+        fn = H.query_goph if goph else H.query_hoph
+        fn(idx, qsig, T=T, eps=eps)
+        torch.cuda.synchronize()
+        ms, walls = [], []
+        for _ in range(max(1, args.steps)):
+            t0 = time.perf_counter()
+            o, i = fn(idx, qsig, T=T, eps=eps)
+            walls.append((time.perf_counter() - t0) * 1e3)
+            ms.append(idx.last_query_ms())
+        dev_ms = [float(np.median([x[j] for x in ms])) for j in range(3)]
+        got = _pairs_of(o.cpu().numpy(), i.cpu().numpy().view(np.uint32))
+        t = T[0] / T[1]
+        truth = {pq for pq in planted if exact(*pq) >= t}
+        tp = sum(exact(a, b) >= t for (a, b) in got)
+        total = sum(dev_ms)
+        # wall_ms: the whole host-synchronous call (sub-batches included, should the
+        # survivors of one pass overflow their buffer; the device times cover the first pass)
+        return {"T": list(T), "eps": list(eps), "wall_ms": float(np.median(walls)), "device_ms": total,
+                "coarse_ms": dev_ms[0],
+                "fine_ms": dev_ms[1], "sort_ms": dev_ms[2], "pairs_per_s": Q * N / (total * 1e-3),
+                "accepted": len(got), "recall": len(truth & got) / max(1, len(truth)),
+                "precision": tp / max(1, len(got))}
+
+    out = {"metric": "query x index pairs decided/s across parameter sweeps", "unit": "pairs/s",
+           "mode": "sweeps", "config": {"workload": "bovw_sweeps", "n_sets": N, "n_queries": Q}}
+    # (1) GOPH group count at k = 320: one sketch, one index per group size
+    pg = _workload_params(H, w, k=320, kp=32, layout=W.LAYOUT_OPH)
+    gsig = H.sketch_oph(pg, ids, offs)
+    gq = H.sketch_oph(pg, qids, qoffs)
+    rows = []
+    for kp in (40, 32, 20, 16, 10, 8, 5):
+        pk = _workload_params(H, w, k=320, kp=kp, layout=W.LAYOUT_OPH)
+        idx = H.Index(pk, gsig)
+        r = point(idx, gq, True, (7, 10), (1, 10000))
+        r.update(n_groups=320 // kp, k_group=kp)
+        rows.append(r)
+        log(f"GOPH n={320 // kp}: {r['device_ms']:.3f} ms")
+        if kp == 32:
+            goph10 = idx
+        else:
+            idx.free()
+    out["goph_groups"] = rows
+    # (2), (3): GOPH n = 10 and HOPH 1:1
+    ph = _workload_params(H, w)
+    hidx = H.Index(ph, H.sketch_oph(ph, ids, offs))
+    hq = H.sketch_oph(ph, qids, qoffs)
+    for name, idx, qs, goph in (("goph10", goph10, gq, True), ("hoph11", hidx, hq, False)):
+        out[f"{name}_eps"] = [point(idx, qs, goph, (7, 10), (1, e)) for e in (100, 1000, 10_000, 100_000, 1_000_000)]
+        out[f"{name}_T"] = [point(idx, qs, goph, (t, 10), (1, 10000)) for t in (5, 6, 7, 8, 9)]
+        log(f"{name}: eps and T sweeps done")
+    goph10.free()
+    hidx.free()
+    out["value"] = out["hoph11_T"][2]["pairs_per_s"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -397,7 +578,8 @@ def main():
             sys.exit(2)
         import paper_1805_11254_amd as H
         H.lib()
-        {"batched": bench_batched, "serve": bench_serve, "comparators": bench_comparators}[args.mode](args)
+        {"batched": bench_batched, "serve": bench_serve, "comparators": bench_comparators,
+         "selfjoin": bench_selfjoin, "sweeps": bench_sweeps}[args.mode](args)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "

@@ -98,9 +98,14 @@ typedef struct {
     hoph_ratio T;             /* similarity threshold, 0 < T <= 1                        */
     hoph_ratio eps;           /* error tolerance of the small-probability event, 0 <= eps < 1 */
     uint32_t empty_policy;    /* HOPH_EMPTY_*                                            */
-    uint32_t coarse_depth;    /* 0 = let the library choose; else groups scanned for every
-                                 pair before survivors move to the per-pair pass (a tuning
-                                 knob: results do not depend on it; at most 4 with codes) */
+    uint32_t coarse_depth;    /* 0 = let the library choose (the first group alone when it
+                                 rejects at least 1/8 of its match counts, else the deepest
+                                 available); else the most groups scanned for a pair before
+                                 it moves to the per-pair pass (a tuning knob: results do
+                                 not depend on it).  Clamped to the groups available: with
+                                 codes, the groups that carry codes (at least 4, about 128
+                                 bins for HOPH and 256 for GOPH, at most 24); on words, 4
+                                 groups of at most 128 bins */
     uint32_t coarse_filter;   /* HOPH_COARSE_*                                           */
     uint32_t reserved;        /* set to 0                                                */
 } hoph_query_params;

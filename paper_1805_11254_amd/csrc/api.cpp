@@ -156,13 +156,8 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
         st = build_tables(lay, *qp, kind == QueryKind::GOPH, t, err);
         if (st) return fail(st, err);
         to_scan_tab(t, tab);
-        // depth: the first step at which a pair with no matched bin is rejected
-        uint32_t g1 = lay.L;
-        for (uint32_t l = 0; l < lay.L; ++l)
-            if (t.rej[l] >= 0) { g1 = l + 1; break; }
         const uint32_t maxd = use_codes ? idx->cg : std::min(max_depth_for_kpad(idx->kpad), lay.L);
-        depth = qp->coarse_depth ? qp->coarse_depth : g1;
-        depth = std::max<uint32_t>(1, std::min(depth, maxd));
+        depth = default_coarse_depth(tab, qp->coarse_depth, maxd);
     }
 
     ScanLaunch a{};
@@ -342,7 +337,7 @@ hoph_status build_index(const hoph_sketch_params *params, const uint32_t *d_sigs
     idx->capacity = std::max<uint64_t>(64, (capacity + 63) / 64 * 64);
     idx->max_sets = capacity;
     const uint64_t words = idx->capacity * idx->lay.k;          // row-major signature words
-    idx->cg = std::min<uint32_t>(kCodeGroups, idx->lay.L);
+    idx->cg = code_groups(idx->lay.kp, idx->lay.L, params->layout == HOPH_LAYOUT_HIER);
     const uint64_t code_words_total = idx->capacity * idx->cg * code_words(idx->lay.kp);
     auto release = [&] {
         if (idx->slab) (void)hipFree(idx->slab);

@@ -23,7 +23,22 @@ constexpr uint32_t kMaxDepth = 4;               // coarse groups kept in registe
 // word holds one plane of 32 bins.  EMPTY has a code of its own.
 constexpr uint32_t kCodeBits = 8;
 constexpr uint32_t kCodeEmpty = 0xFFu;           // code of EMPTY; other bins map to [0, 254]
-constexpr uint32_t kCodeGroups = kMaxDepth;      // leading groups that carry codes
+// Leading groups that carry codes: at least the register-resident depth and
+// enough groups to cover a bin budget, at most max_code_groups (the deep code
+// pass stages that many groups of one tile, 64 lanes x (planes + set-empty
+// masks), in under 64 KB of LDS: 24 groups of one plane word, 12 of two).  GOPH
+// weighs its groups equally and, with small groups or a low threshold, can
+// first reject only after one to two hundred bins; HOPH decides most pairs in
+// its heavy first group.
+constexpr uint32_t kCodeBinsHier = 128;
+constexpr uint32_t kCodeBinsFlat = 256;
+inline uint32_t max_code_groups(uint32_t kp) { return kp > 32 ? 12u : 24u; }
+inline uint32_t code_groups(uint32_t kp, uint32_t L, bool hier) {
+    const uint32_t bins = hier ? kCodeBinsHier : kCodeBinsFlat, cap = max_code_groups(kp);
+    uint32_t g = (bins + kp - 1) / kp;
+    g = g < kMaxDepth ? kMaxDepth : (g > cap ? cap : g);
+    return g < L ? g : L;
+}
 
 // Device error bits (one 32-bit word per device).
 constexpr uint32_t kErrRange = 1u;              // an id >= universe, or a table value >= R
@@ -293,6 +308,13 @@ hoph_status tail_integers(uint32_t n, hoph_ratio T, hoph_ratio eps, int32_t &j_l
 hoph_status build_tables(const LayoutInfo &lay, const hoph_query_params &qp, bool goph,
                          hoph_decision_tables &out, std::string &err);
 void to_scan_tab(const hoph_decision_tables &t, ScanTab &s);
+// Coarse depth when the caller leaves it to the library: the first group alone
+// when it rejects at least one eighth of its bins' match counts (the
+// one-group pass, whose survivors are then sparse), else the deepest available
+// depth (the coarse kernels stop walking once every lane is decided, so depth
+// costs only where pairs are still open); `requested` > 0 wins, clamped to
+// [1, maxd].
+uint32_t default_coarse_depth(const ScanTab &tab, uint32_t requested, uint32_t maxd);
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (k_*.hip).  All return hipError_t of the launch.

@@ -405,4 +405,10 @@ void to_scan_tab(const hoph_decision_tables &t, ScanTab &s) {
     }
 }
 
+uint32_t default_coarse_depth(const ScanTab &tab, uint32_t requested, uint32_t maxd) {
+    uint32_t d = requested;
+    if (d == 0) d = (8 * (int64_t)tab.mrej0[0] >= (int64_t)tab.kp && tab.mrej0[0] >= 0) ? 1u : maxd;
+    return std::max<uint32_t>(1, std::min(d, maxd));
+}
+
 }  // namespace hoph

@@ -144,6 +144,40 @@ __device__ __forceinline__ uint32_t code_diff(const uint32_t *P, const uint32_t 
     return d;
 }
 
+// One group of the coarse pass on codes: the group's planes P and set-empty
+// masks em against the query's record, added to the weighted state S, and the
+// step's cutoffs applied to a lane still undecided (maybe: an accept cutoff
+// was reached, so the pair must go on to the fine pass).
+template <int W>
+__device__ __forceinline__ void code_group_step(const uint32_t *P, const uint32_t *em,
+                                                const uint32_t *__restrict__ qrec, uint64_t qm, uint64_t kpmask,
+                                                uint32_t kp, uint32_t policy, const int64_t *s_dmul, int64_t lambda,
+                                                int64_t Wg, int64_t accg, int64_t rejg, int64_t &S, bool &undecided,
+                                                bool &maybe) {
+    const uint64_t nqm = ~qm & kpmask;
+    uint32_t dn = 0, de = 0, ee = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const uint32_t d = code_diff<W>(P, qrec, w);
+        const uint32_t qmw = (uint32_t)(qm >> (32 * w)), nqmw = (uint32_t)(nqm >> (32 * w));
+        dn += __popc(d & nqmw);
+        de += __popc(d & qmw);
+        ee += __popc(em[w] | qmw);
+    }
+    const uint32_t eq_q = (uint32_t)__popcll(qm);
+    const uint32_t m = kp - eq_q - dn;        // >= the matched non-empty bins
+    const uint32_t ej = eq_q - de;            // jointly empty bins, exact
+    S += Wg * group_rho(m + ej, ej, ee, kp, policy, s_dmul, lambda);
+    if (undecided) {
+        if (S >= accg) {
+            maybe = true;
+            undecided = false;
+        } else if (S <= rejg) {
+            undecided = false;
+        }
+    }
+}
+
 // Coarse pass on codes (reject-only).  Same (tile, query chunk) items as the
 // word kernel below; the tile's code planes of the first G groups stay in
 // VGPRs.  Codes never under-count matched bins (equal values have equal codes)
@@ -181,6 +215,8 @@ __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__
     for (uint64_t item = (uint64_t)blockIdx.x * kWaves + wave_id_in_block(); item < n_items; item += wstride) {
     const uint64_t tile = item % ntiles;
     const uint32_t chunk = (uint32_t)(item / ntiles);
+    // self-join: skip (before any load) a tile with no set id above the chunk's first query row
+    if (a.tri && tile * 64 + 63 <= (uint64_t)q_lo + (uint64_t)chunk * a.q_per_wave) continue;
     const uint64_t s = tile * 64 + lane;
     const bool valid = s < n_sets;
 
@@ -219,29 +255,8 @@ __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 if (!__any(undecided)) break;
-                const uint64_t qm = qmk[g];
-                const uint64_t nqm = ~qm & kpmask;
-                uint32_t dn = 0, de = 0, ee = 0;
-#pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    const uint32_t d = code_diff<W>(P[g], qc + g * RW, w);
-                    const uint32_t qmw = (uint32_t)(qm >> (32 * w)), nqmw = (uint32_t)(nqm >> (32 * w));
-                    dn += __popc(d & nqmw);
-                    de += __popc(d & qmw);
-                    ee += __popc(em[g][w] | qmw);
-                }
-                const uint32_t eq_q = (uint32_t)__popcll(qm);
-                const uint32_t m = kp - eq_q - dn;        // >= the matched non-empty bins
-                const uint32_t ej = eq_q - de;            // jointly empty bins, exact
-                S += tab.W[g] * group_rho(m + ej, ej, ee, kp, policy, s_dmul, tab.lambda);
-                if (undecided) {
-                    if (S >= tab.acc[g]) {
-                        maybe = true;
-                        undecided = false;
-                    } else if (S <= tab.rej[g]) {
-                        undecided = false;
-                    }
-                }
+                code_group_step<W>(P[g], em[g], qc + g * RW, qmk[g], kpmask, kp, policy, s_dmul, tab.lambda,
+                                   tab.W[g], tab.acc[g], tab.rej[g], S, undecided, maybe);
             }
             survive = maybe || undecided;
         }
@@ -250,6 +265,132 @@ __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__
             if (survive && slot < a.surv_cap) surv[slot] = Survivor{q, (uint32_t)s, 0};
         }
     }
+    }
+}
+
+// Coarse pass on codes deeper than the register-resident groups (GOPH with
+// small groups or a low threshold, whose first useful rejecting step comes
+// many groups in).  One wavefront per block, one (tile, query chunk) item at a
+// time.  The first kMaxDepth groups of the tile stay in VGPRs as in
+// scan_codes_kernel; the later ones are staged in LDS group by group, the
+// first time a query of the chunk reaches that group (each lane only reads
+// back its own words, so the wavefront's program order is the only ordering
+// needed).  Each query walks the groups until every lane is decided.
+template <int W>
+__global__ __launch_bounds__(64) void scan_codes_deep_kernel(const uint32_t *__restrict__ codes,
+                                                           const uint32_t *__restrict__ qcodes,
+                                                           const uint64_t *__restrict__ qmasks,
+                                                           Survivor *__restrict__ surv,
+                                                           unsigned long long *__restrict__ counters,
+                                                           const uint64_t *__restrict__ desc, const CoarseArgs a,
+                                                           const ScanTab tab, uint32_t cd) {
+    constexpr int PW = (int)kCodeBits * W, RW = PW + 4, PV = PW / 4, R = (int)kMaxDepth;
+    extern __shared__ uint4 s_pl[];      // groups >= R: [group - R][PV][lane] planes, then [group - R][W][lane] masks
+    __shared__ int64_t s_dmul[HOPH_MAX_KGROUP + 1];
+    uint32_t *s_em = reinterpret_cast<uint32_t *>(s_pl + (size_t)(cd - R) * PV * 64);
+    for (uint32_t i = threadIdx.x; i <= tab.kp; i += 64) s_dmul[i] = tab.dmul[i];
+    __syncthreads();
+
+    const uint32_t lane = threadIdx.x;
+    const uint64_t n_sets = desc ? desc[1] : a.n_sets;
+    const uint32_t q_lo = desc ? 0u : a.q0, q_hi = desc ? (uint32_t)desc[0] : a.q1;
+    const uint64_t ntiles = (n_sets + 63) / 64;
+    const uint32_t nchunks = (q_hi - q_lo + a.q_per_wave - 1) / a.q_per_wave;
+    const uint64_t n_items = ntiles * nchunks;
+    const uint32_t kp = a.kp;
+    const uint64_t kpmask = kp >= 64 ? ~0ull : ((1ull << kp) - 1ull);
+    const uint64_t ctiles = a.capacity / 64;
+    const uint32_t policy = a.policy;
+    for (uint64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const uint64_t tile = item % ntiles;
+        const uint32_t chunk = (uint32_t)(item / ntiles);
+        const uint32_t qa = q_lo + chunk * a.q_per_wave;
+        // self-join: skip a tile with no set id above the chunk's first query row
+        if (a.tri && tile * 64 + 63 <= (uint64_t)qa) continue;
+        const uint32_t qb = min(q_hi, qa + a.q_per_wave);
+        const uint64_t s = tile * 64 + lane;
+        const bool valid = s < n_sets;
+
+        uint32_t P[R][PW], em[R][W];
+#pragma unroll
+        for (int g = 0; g < R; ++g) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(codes + (((uint64_t)g * ctiles + tile) * 64 + lane) * PW);
+#pragma unroll
+            for (int j = 0; j < PV; ++j) {
+                const uint4 v = src[j];
+                P[g][4 * j + 0] = v.x;
+                P[g][4 * j + 1] = v.y;
+                P[g][4 * j + 2] = v.z;
+                P[g][4 * j + 3] = v.w;
+            }
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                // set-empty bins: code 0xFF, every plane set
+                uint32_t e = P[g][w];
+#pragma unroll
+                for (int p = 1; p < (int)kCodeBits; ++p) e &= P[g][p * W + w];
+                em[g][w] = e;
+            }
+        }
+
+        uint32_t staged = R;
+        for (uint32_t q = qa; q < qb; ++q) {
+            const uint32_t *qc = qcodes + (uint64_t)q * a.cg * RW;
+            const uint64_t *qmk = qmasks + (uint64_t)q * a.L;
+            int64_t S = 0;
+            bool undecided = valid && (!a.tri || s > q), maybe = false;
+#pragma unroll
+            for (int g = 0; g < R; ++g) {
+                if (!__any(undecided)) break;
+                code_group_step<W>(P[g], em[g], qc + g * RW, qmk[g], kpmask, kp, policy, s_dmul, tab.lambda,
+                                   tab.W[g], tab.acc[g], tab.rej[g], S, undecided, maybe);
+            }
+            for (uint32_t g = R; g < cd; ++g) {
+                if (!__any(undecided)) break;
+                uint32_t Pg[PW], emg[W];
+                const size_t r = g - R;
+                if (g == staged) {           // wave-uniform: first query of the item to reach group g
+                    const uint4 *src =
+                        reinterpret_cast<const uint4 *>(codes + (((uint64_t)g * ctiles + tile) * 64 + lane) * PW);
+#pragma unroll
+                    for (int j = 0; j < PV; ++j) {
+                        const uint4 v = src[j];
+                        s_pl[(r * PV + j) * 64 + lane] = v;
+                        Pg[4 * j + 0] = v.x;
+                        Pg[4 * j + 1] = v.y;
+                        Pg[4 * j + 2] = v.z;
+                        Pg[4 * j + 3] = v.w;
+                    }
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        uint32_t e = Pg[w];
+#pragma unroll
+                        for (int p = 1; p < (int)kCodeBits; ++p) e &= Pg[p * W + w];
+                        emg[w] = e;
+                        s_em[(r * W + w) * 64 + lane] = e;
+                    }
+                    ++staged;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < PV; ++j) {
+                        const uint4 v = s_pl[(r * PV + j) * 64 + lane];
+                        Pg[4 * j + 0] = v.x;
+                        Pg[4 * j + 1] = v.y;
+                        Pg[4 * j + 2] = v.z;
+                        Pg[4 * j + 3] = v.w;
+                    }
+#pragma unroll
+                    for (int w = 0; w < W; ++w) emg[w] = s_em[(r * W + w) * 64 + lane];
+                }
+                code_group_step<W>(Pg, emg, qc + g * RW, qmk[g], kpmask, kp, policy, s_dmul, tab.lambda, tab.W[g],
+                                   tab.acc[g], tab.rej[g], S, undecided, maybe);
+            }
+            const bool survive = maybe || undecided;
+            if (__any(survive)) {
+                const uint64_t slot = wave_append(survive, counters + 0, lane);
+                if (survive && slot < a.surv_cap) surv[slot] = Survivor{q, (uint32_t)s, 0};
+            }
+        }
     }
 }
 
@@ -279,6 +420,10 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_
     for (uint64_t item = (uint64_t)blockIdx.x * kWaves + wave_id_in_block(); item < n_items; item += wstride) {
         const uint64_t tg = item % ngroups;
         const uint32_t chunk = (uint32_t)(item / ngroups);
+        const uint32_t qa = q_lo + chunk * a.q_per_wave;
+        const uint32_t qb = min(q_hi, qa + a.q_per_wave);
+        // self-join: skip (before any load) an item with no set id above its first query row
+        if (a.tri && (tg + 1) * TPW * 64 <= (uint64_t)qa + 1) continue;
         uint32_t P[TPW][PW];
         bool valid[TPW];
         uint32_t sid[TPW];
@@ -304,10 +449,6 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_
             }
         }
         (void)ctiles;
-        const uint32_t qa = q_lo + chunk * a.q_per_wave;
-        const uint32_t qb = min(q_hi, qa + a.q_per_wave);
-        // self-join: no pair of this item has set id > query row
-        if (a.tri && (tg + 1) * TPW * 64 <= (uint64_t)qa + 1) continue;
         uint32_t ra[RW], rb[RW];
 #pragma unroll
         for (int j = 0; j < RW; ++j) ra[j] = qcodes[qa * rstride + j];
@@ -375,6 +516,8 @@ __global__ __launch_bounds__(kThreads) void scan_coarse_kernel(const uint32_t *_
     for (uint64_t item = (uint64_t)blockIdx.x * kWaves + wave_id_in_block(); item < n_items; item += wstride) {
     const uint64_t tile = item % ntiles;
     const uint32_t chunk = (uint32_t)(item / ntiles);
+    // self-join: skip (before any load) a tile with no set id above the chunk's first query row
+    if (a.tri && tile * 64 + 63 <= (uint64_t)q_lo + (uint64_t)chunk * a.q_per_wave) continue;
     const uint64_t s = tile * 64 + lane;
     const bool valid = s < n_sets;
 
@@ -684,7 +827,7 @@ void codes_launch(const ScanLaunch &l, const CoarseArgs &a, const ScanTab &tab, 
         break;
     case 2: HOPH_CODES(2); break;
     case 3: HOPH_CODES(3); break;
-    default: HOPH_CODES(4); break;
+    default: HOPH_CODES(4); break;     // depth 4 (deeper runs in scan_codes_deep_kernel)
     }
 #undef HOPH_CODES
 }
@@ -784,6 +927,28 @@ hipError_t launch_scan_coarse(const ScanLaunch &l, const ScanTab &tab, hipStream
     const CoarseArgs a = coarse_args(l, tab.policy);
     if (l.codes) {
         if (l.depth == 0 || l.depth > l.cg) return hipErrorInvalidValue;
+        if (l.depth > kMaxDepth) {
+            // past the register-resident groups: one wavefront per block, planes staged in LDS
+            const uint32_t W = code_plane_words(l.kp);
+            if (l.depth > max_code_groups(l.kp)) return hipErrorInvalidValue;
+            uint64_t waves;
+            if (l.desc) {
+                waves = (uint64_t)device_cu_count() * (l.waves_per_cu ? l.waves_per_cu : 16);
+            } else {
+                const uint64_t ntiles = (l.n_sets + 63) / 64;
+                waves = ntiles * ((l.q1 - l.q0 + l.q_per_wave - 1) / l.q_per_wave);
+            }
+            const uint32_t deep_blocks = (uint32_t)std::min<uint64_t>(waves, 1u << 30);
+            const size_t lds = (size_t)(l.depth - kMaxDepth) * 64 * (code_words(l.kp) * 4 + 4 * W);
+            auto *cnt = reinterpret_cast<unsigned long long *>(l.counters);
+            if (W == 1)
+                hipLaunchKernelGGL(scan_codes_deep_kernel<1>, dim3(deep_blocks), dim3(64), lds, st, l.codes, l.qcodes,
+                                   l.qmasks, l.surv, cnt, l.desc, a, tab, l.depth);
+            else
+                hipLaunchKernelGGL(scan_codes_deep_kernel<2>, dim3(deep_blocks), dim3(64), lds, st, l.codes, l.qcodes,
+                                   l.qmasks, l.surv, cnt, l.desc, a, tab, l.depth);
+            return hipGetLastError();
+        }
         if (code_plane_words(l.kp) == 1) codes_launch<1>(l, a, tab, st, blocks);
         else codes_launch<2>(l, a, tab, st, blocks);
         return hipGetLastError();

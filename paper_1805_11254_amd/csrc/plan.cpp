@@ -334,12 +334,9 @@ hoph_status hoph_plan_create(hoph_index *idx, const hoph_sketch_params *params, 
     hoph_status st = build_tables(idx->lay, *qp, cfg->kind == 0, t, err);
     if (st) return fail(st, err);
     to_scan_tab(t, p->tab);
-    uint32_t g1 = idx->lay.L;
-    for (uint32_t l = 0; l < idx->lay.L; ++l)
-        if (t.rej[l] >= 0) { g1 = l + 1; break; }
     p->codes = qp->coarse_filter == HOPH_COARSE_CODES && idx->codes;
     const uint32_t maxd = p->codes ? idx->cg : std::min(max_depth_for_kpad(idx->kpad), idx->lay.L);
-    p->depth = std::max<uint32_t>(1, std::min(qp->coarse_depth ? qp->coarse_depth : g1, maxd));
+    p->depth = default_coarse_depth(p->tab, qp->coarse_depth, maxd);
     const uint64_t Q = cfg->max_queries, k = params->k, L = idx->lay.L;
     p->surv_cap = std::max<uint64_t>(idx->capacity, 1u << 20);
     p->keys_cap = sort_capacity(std::max<uint64_t>(cfg->max_results, 1));

@@ -199,7 +199,8 @@ def test_code_collisions_match_oracle(k, kp):
 
 
 @pytest.mark.parametrize("layout,k,kp", [(W.LAYOUT_HIER, 128, 8), (W.LAYOUT_HIER, 192, 12), (W.LAYOUT_HIER, 320, 20),
-                                         (W.LAYOUT_OPH, 120, 12), (W.LAYOUT_HIER, 320, 40), (W.LAYOUT_OPH, 448, 64)])
+                                         (W.LAYOUT_OPH, 120, 12), (W.LAYOUT_HIER, 320, 40), (W.LAYOUT_OPH, 448, 64),
+                                         (W.LAYOUT_OPH, 160, 8), (W.LAYOUT_OPH, 160, 5)])
 def test_group_sizes_match_oracle(layout, k, kp):
     """Group sizes other than 16 and 32: code planes of one or two words per
     plane, index stores through the word path, both coarse filters."""
@@ -541,4 +542,51 @@ def test_self_join_matches_oracle(name):
                 go, gi = H.self_join(idx, T=T, eps=eps, policy=policy, coarse=coarse)
                 got = csr_lists(go.cpu().numpy(), to_u32(gi))
                 assert len(got) == n and got == want, (T, eps, policy, coarse)
+    idx.free()
+
+
+def _code_groups(kp, L, hier=False):
+    """Groups that carry codes in the index (at least 4, about 128 bins for HOPH
+    and 256 for GOPH, at most 24)."""
+    return min(L, max(4, min(12 if kp > 32 else 24, -(-(128 if hier else 256) // kp))))
+
+
+@pytest.mark.parametrize("k,kp", [(160, 8), (160, 5), (320, 10), (320, 40)])
+def test_deep_code_pass_matches_oracle(k, kp):
+    """GOPH with small groups: the coarse pass on codes at every depth from 1
+    to the number of groups that carry codes (past 4 it stages a tile's planes
+    in LDS), for queries and the self-join."""
+    _print_case(f"deep code pass k={k} kp={kp}")
+    w = W.hoph_bovw(n=2_500, n_q=12, seed=61 + kp, k=k, kp=kp, planted_frac=0.03, T=(7, 10))
+    w.layout = W.LAYOUT_OPH
+    p = params_of(w)
+    sig = gpu_sketch(w, w.collection, p)
+    qsig = gpu_sketch(w, w.queries, p)
+    sh, qh = to_u32(sig), to_u32(qsig)
+    idx = H.Index(p, sig)
+    cg = _code_groups(kp, k // kp)
+    depths = sorted({1, 3, 4, 5, cg // 2 + 1, cg})
+    for T, eps in (((7, 10), (1, 10_000)), ((1, 2), (1, 1000))):
+        for policy in _policies_that_fit(p, T, eps):
+            oo, oi = oracle_query(w, sh, qh, T, eps, policy)
+            for depth in depths:
+                go, gi = gpu_query("goph", idx, qsig, T, eps, policy, coarse_depth=depth)
+                assert go.tolist() == oo.tolist() and gi.tolist() == oi.tolist(), (T, eps, policy, depth)
+    T, eps = (7, 10), (1, 10_000)
+    oo, oi = oracle_query(w, sh, sh, T, eps, H.EMPTY_JOINT)
+    want = [[j for j in row if j > i] for i, row in enumerate(csr_lists(oo, oi))]
+    for depth in (0, cg):
+        go, gi = H.self_join(idx, T=T, eps=eps, coarse_depth=depth)
+        assert csr_lists(go.cpu().numpy(), to_u32(gi)) == want, depth
+    # persistent plan kernels (eager and graph-replayed) on the same deep pass
+    oo, oi = oracle_query(w, sh, qh, T, eps, H.EMPTY_JOINT)
+    qids, qoffs = dev_csr(w.queries)
+    for use_graph in (False, True):
+        plan = H.Plan(idx, p, T=T, eps=eps, max_queries=16, max_query_ids=int(w.queries.ids.size) + 16,
+                      max_results=1 << 16, use_graph=use_graph, tune=True)
+        for rep in range(3):
+            plan.run(qids, qoffs)
+            po, pi = plan.results()
+            assert po.cpu().numpy().tolist() == oo.tolist() and to_u32(pi).tolist() == oi.tolist(), (use_graph, rep)
+        plan.free()
     idx.free()
