@@ -678,12 +678,17 @@ def main():
 
     # algorithmic work per launch
     sketch_bytes = nnz * 4 + (N + 1) * 8 + N * k * 4                 # ids, offsets in; signatures out
-    code_groups = min(4, k // kp)
+    # groups that carry 8-bit codes: at least 4, about 128 bins (HOPH) or 256 (GOPH), at most 24 (12 for k' > 32)
+    L_groups = k // kp
+    code_groups = min(L_groups, max(4, min(12 if kp > 32 else 24, -(-(256 if w.goph else 128) // kp))))
     code_bytes = N * code_groups * kp * 4 + N * code_groups * 32 * (1 if kp <= 32 else 2)
     index_bytes = 2 * N * k * 4 + N * code_groups * 32 * (1 if kp <= 32 else 2)   # rows in, slabs + code planes out
+    # coarse depth as the library picks it: the first group alone when it rejects at
+    # least 1/8 of its match counts (no empty bins), else every group that carries codes
     tabs = H.decision_tables(p, w.T, w.eps)
-    depth = next((l + 1 for l in range(tabs["L"]) if tabs["rej"][l] >= 0), tabs["L"])
-    depth = min(depth, 4, tabs["L"])
+    unit0 = tabs["W"][0] * tabs["dmul"][0]
+    m_rej0 = tabs["rej"][0] // unit0 if tabs["rej"][0] >= 0 else -1
+    depth = 1 if (m_rej0 >= 0 and 8 * m_rej0 >= kp) else code_groups
     # coarse pass on 8-bit bin codes held as 8 bit-planes of 32 bins per word:
     # per (pair, group) 8 W plane operations, W masks, W popcounts, 1 compare
     W_planes = 1 if kp <= 32 else 2
@@ -713,7 +718,7 @@ def main():
                         "peak": ALU_PEAK_OPS / 1e12, "unit": "Tops/s (32-bit VALU lane-ops)",
                         "ops_per_pair_group": ops_per_pair_group,
                         "bin_compares_per_s": coarse_bins / (coarse_ms * 1e-3),
-                        "traffic": traffic.get("scan_codes_kernel"), "algorithmic_bytes": coarse_bytes,
+                        "traffic": traffic.get("scan_codes_fast_kernel"), "algorithmic_bytes": coarse_bytes,
                         "hbm_gbs": coarse_bytes / (coarse_ms * 1e-3) / 1e9, "depth": depth},
         "scan_fine": {"ms": fine_ms},
         "sort_and_csr": {"ms": sort_ms},

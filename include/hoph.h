@@ -365,6 +365,14 @@ const char *hoph_last_error(void);    /* thread-local; "" when none */
    starts[k] = R (Sec. 3.2 / Sec. 4.1).  starts: host array of k + 1 entries. */
 hoph_status hoph_layout_starts(const hoph_sketch_params *params, uint64_t *starts);
 
+/* hoph_layout_lookups -- which bin lookups the sketch kernels may use for this
+   layout (a test hook, so that tests can tell which ones hoph_selftest_bins
+   cross-checks): bit 0 the uniform bin estimate, bit 1 log-domain region cells,
+   bit 2 power-of-two regions and bins.  The (a x + b) mod (2^31 - 1) kernels take
+   the first that applies of power-of-two, estimate, cells, region search; the
+   other hashes the estimate or the region search.  *mask: host. */
+hoph_status hoph_layout_lookups(const hoph_sketch_params *params, uint32_t *mask);
+
 /* hoph_tail_integers -- for X ~ Bin(n, T) (Eq. 10): *j_lo = max{j >= -1 : P(X <= j) <= eps},
    *j_hi = min{j <= n + 1 : P(X >= j) <= eps}, computed exactly.  n <= 256. */
 hoph_status hoph_tail_integers(uint32_t n, hoph_ratio T, hoph_ratio eps, int32_t *j_lo,

@@ -102,6 +102,7 @@ SIGNATURES = {
     "hoph_status_str": (C.c_char_p, [C.c_int]),
     "hoph_last_error": (C.c_char_p, []),
     "hoph_layout_starts": (C.c_int, [C.POINTER(SketchParamsC), vp]),
+    "hoph_layout_lookups": (C.c_int, [C.POINTER(SketchParamsC), C.POINTER(u32)]),
     "hoph_tail_integers": (C.c_int, [u32, Ratio, Ratio, C.POINTER(i32), C.POINTER(i32)]),
     "hoph_build_decision_tables": (C.c_int, [C.POINTER(SketchParamsC), C.POINTER(QueryParamsC), u32,
                                              C.POINTER(DecisionTablesC)]),
@@ -614,6 +615,18 @@ def layout_starts(params: SketchParams):
     pc = params.c(perm_ptr=0)
     _check(lib().hoph_layout_starts(C.byref(pc), out.ctypes.data_as(vp)))
     return out
+
+
+LOOKUP_ESTIMATE, LOOKUP_LOG_CELLS, LOOKUP_POW2 = 1, 2, 4
+
+
+def layout_lookups(params: SketchParams) -> int:
+    """Bit mask of the bin lookups the sketch kernels may use for this layout
+    (LOOKUP_ESTIMATE | LOOKUP_LOG_CELLS | LOOKUP_POW2)."""
+    m = u32()
+    pc = params.c(perm_ptr=0)
+    _check(lib().hoph_layout_lookups(C.byref(pc), C.byref(m)))
+    return int(m.value)
 
 
 def tail_integers(n: int, T, eps) -> Tuple[int, int]:

@@ -569,6 +569,19 @@ hoph_status hoph_layout_starts(const hoph_sketch_params *params, uint64_t *start
     return HOPH_OK;
 }
 
+hoph_status hoph_layout_lookups(const hoph_sketch_params *params, uint32_t *mask) {
+    g_last_error.clear();
+    if (!params || !mask) return fail(HOPH_E_INVAL, "NULL argument");
+    hoph_sketch_params p = *params;
+    if (p.hash == HOPH_HASH_TABLE && !p.d_perm) p.d_perm = reinterpret_cast<const uint32_t *>(1);  // not read here
+    LayoutInfo lay;
+    std::string err;
+    hoph_status st = build_layout(p, lay, err);
+    if (st) return fail(st, err);
+    *mask = (lay.est_ok ? 1u : 0u) | (lay.log_ok ? 2u : 0u) | (lay.pow2_ok ? 4u : 0u);
+    return HOPH_OK;
+}
+
 hoph_status hoph_tail_integers(uint32_t n, hoph_ratio T, hoph_ratio eps, int32_t *j_lo, int32_t *j_hi) {
     g_last_error.clear();
     if (!j_lo || !j_hi) return fail(HOPH_E_INVAL, "NULL argument");
@@ -653,6 +666,13 @@ hoph_status hoph_selftest_bins(const hoph_sketch_params *params, const uint32_t 
                 locate_log((uint32_t)v, (uint32_t)(lay.R - 1), reinterpret_cast<const uint32_t(*)[2]>(cells.data()),
                            reinterpret_cast<const uint32_t(*)[2]>(regs.data()), lay.nb, s32.data(), bn, sn);
                 if (bn != b || sn != start) return fail(HOPH_E_UNSUPPORTED, "log-cell and region lookups disagree");
+            }
+            if (lay.pow2_ok) {
+                uint32_t bp, op;
+                locate_pow2((uint32_t)v, (uint32_t)(lay.R - 1), reinterpret_cast<const uint32_t(*)[4]>(lay.pow2.data()),
+                            bp, op);
+                if (bp != b || op != (uint32_t)(v - start))
+                    return fail(HOPH_E_UNSUPPORTED, "power-of-two and region lookups disagree");
             }
         }
         out_bin[i] = b;

@@ -59,6 +59,8 @@ struct SketchDesc {
     // against every bin start), so one read of a pair of bin starts settles it.
     uint32_t est_mul, est_shift, est_ok;
     uint32_t log_ok;     // regions by log-domain cells (see log_cell), narrow ranges only
+    uint32_t pow2_ok;    // power-of-two regions and bins (see locate_pow2), narrow ranges only
+    uint32_t pow2[32][4];                                    // locate_pow2 table, by leading-zero count
     uint64_t reg_start[HOPH_MAX_GROUPS + 1];                 // reg_start[n_regions] = R
     uint64_t reg_magic[HOPH_MAX_GROUPS];                     // floor(2^64 nb / z_r), see bin_of
     uint32_t reg_mag32[HOPH_MAX_GROUPS];                     // min(2^32 - 1, floor(2^32 nb / z_r))
@@ -74,6 +76,8 @@ struct LayoutInfo {
     uint32_t lut_shift = 0, lut_size = 0;
     uint32_t est_mul = 0, est_shift = 0, est_ok = 0;   // see SketchDesc
     uint32_t log_ok = 0;                               // see SketchDesc
+    uint32_t pow2_ok = 0;                              // see SketchDesc
+    std::vector<uint32_t> pow2;                        // 32 x {region start, shift, first bin, mask}
 };
 
 // ---------------------------------------------------------------------------
@@ -149,11 +153,14 @@ __host__ __device__ inline uint32_t mul_u24(uint32_t a, uint32_t b) {
 #endif
 }
 
+// (a x + b) mod (2^31 - 1) for x, a, b < P = 2^31 - 1 (the host checks a, b and the
+// universe; ids are clamped below it).  Then w = a x + b <= P (P - 1), so with
+// w = h 2^31 + l (2^31 = 1 mod P): h <= 2^31 - 3 and s = l + h <= 2P - 2 < 2P,
+// and one conditional subtraction finishes the reduction.
 __host__ __device__ inline uint64_t psi_p31(uint64_t x, uint64_t a, uint64_t b) {
     const uint64_t w = (uint64_t)(uint32_t)a * (uint32_t)x + b;   // one 32 x 32 -> 64 multiply-add
     const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
-    uint32_t s = (lo & 0x7FFFFFFFu) + shr31_of_64(hi, lo);         // <= 2^32 - 2
-    s = (s & 0x7FFFFFFFu) + (s >> 31);                              // <= P + 1
+    const uint32_t s = (lo & 0x7FFFFFFFu) + shr31_of_64(hi, lo);   // l + h < 2P
     const uint32_t t = s - 0x7FFFFFFFu;                               // wraps above s when s < P
     return t < s ? t : s;
 }
@@ -269,6 +276,24 @@ __host__ __device__ inline void log_cell_entry(uint32_t c, uint32_t R, const Reg
 
 // Narrow bin lookup with the cell table (cells: {first, bound}) and the region
 // table (regs: {start, 32-bit reciprocal}); see locate_narrow for the bin step.
+// Power-of-two regions: where every region's bins are 2^s values wide (bin t
+// of region r starts at s_r + t 2^s; the last one may be shorter) and every
+// class of u = max(R - 1 - v, 1) with one leading-zero count lies inside one
+// region (the 1:1 hierarchy over R = 2^31 - 1 splits exactly there), the
+// leading-zero count of u names the region: tab[clz(u)] = {region start, s,
+// first bin of the region, 2^s - 1}, and the bin and the offset are a shift
+// and a mask of v minus the region start.  The host checks both conditions.
+constexpr uint32_t kPow2Classes = 32;
+__host__ __device__ inline void locate_pow2(uint32_t v, uint32_t R1, const uint32_t (*tab)[4], uint32_t &bin,
+                                            uint32_t &off) {
+    uint32_t u = R1 - v;
+    u = u > 1u ? u : 1u;
+    const uint32_t *e = tab[clz32(u)];
+    const uint32_t d = v - e[0];
+    bin = e[2] + (d >> e[1]);
+    off = d & e[3];
+}
+
 __host__ __device__ inline void locate_log(uint32_t v, uint32_t R1, const uint32_t (*cells)[2],
                                            const uint32_t (*regs)[2], uint32_t nb, const uint32_t *starts,
                                            uint32_t &bin, uint32_t &start) {

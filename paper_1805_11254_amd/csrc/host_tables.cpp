@@ -24,6 +24,7 @@ static uint64_t range_of(const hoph_sketch_params &p) {
 }
 
 void choose_estimate(LayoutInfo &lay);
+void choose_pow2(LayoutInfo &lay);
 
 hoph_status build_layout(const hoph_sketch_params &p, LayoutInfo &out, std::string &err) {
     if (p.layout != HOPH_LAYOUT_OPH && p.layout != HOPH_LAYOUT_HIER) { err = "unknown layout"; return HOPH_E_INVAL; }
@@ -104,6 +105,7 @@ hoph_status build_layout(const hoph_sketch_params &p, LayoutInfo &out, std::stri
             ok = log_cell((uint32_t)(L.reg_start[r] - 1), R1) != log_cell((uint32_t)L.reg_start[r + 1], R1);
         L.log_ok = ok ? 1u : 0u;
     }
+    choose_pow2(L);
     out = std::move(L);
     return HOPH_OK;
 }
@@ -136,6 +138,46 @@ void choose_estimate(LayoutInfo &lay) {
     }
 }
 
+// The power-of-two lookup (see locate_pow2), for a narrow range: each region's
+// bin starts must be t 2^s from the region start, and the values of each
+// leading-zero class of u = max(R - 1 - v, 1) must lie in one region.
+void choose_pow2(LayoutInfo &lay) {
+    lay.pow2_ok = 0;
+    lay.pow2.assign(4 * kPow2Classes, 0);
+    if (lay.R < 2 || lay.R >= 0xFFFFFFFFull) return;
+    const uint64_t nb = lay.nb;
+    std::vector<uint32_t> shift(lay.n_regions);
+    for (uint32_t r = 0; r < lay.n_regions; ++r) {
+        const uint64_t s0 = lay.reg_start[r], z = lay.reg_start[r + 1] - s0;
+        uint32_t sh = 0;
+        while (sh < 31 && (nb << sh) < z) ++sh;                 // smallest s with nb 2^s >= z
+        if ((nb << sh) < z) return;
+        for (uint64_t t = 0; t < nb; ++t)
+            if ((t * z + nb - 1) / nb != (t << sh)) return;     // bin t starts at t 2^s
+        shift[r] = sh;
+    }
+    const uint64_t R1 = lay.R - 1;
+    auto region_of = [&](uint64_t v) {
+        uint32_t r = 0;
+        while (r + 1 < lay.n_regions && v >= lay.reg_start[r + 1]) ++r;
+        return r;
+    };
+    for (uint32_t lz = 0; lz < kPow2Classes; ++lz) {
+        const uint64_t ulo = 1ull << (31 - lz), uhi = (1ull << (32 - lz)) - 1;
+        if (ulo > R1) continue;                                 // no value has this class
+        const uint64_t vlo = R1 - std::min(uhi, R1);
+        const uint64_t vhi = ulo == 1 ? R1 : R1 - ulo;          // u = 1 also for v = R - 1
+        const uint32_t r = region_of(vlo);
+        if (region_of(vhi) != r) return;
+        uint32_t *e = &lay.pow2[4 * lz];
+        e[0] = (uint32_t)lay.reg_start[r];
+        e[1] = shift[r];
+        e[2] = (uint32_t)(r * nb);
+        e[3] = (uint32_t)((1ull << shift[r]) - 1);
+    }
+    lay.pow2_ok = 1;
+}
+
 void fill_sketch_desc(const hoph_sketch_params &p, const LayoutInfo &lay, SketchDesc &d) {
     std::memset(&d, 0, sizeof(d));
     d.perm = p.d_perm;
@@ -153,6 +195,9 @@ void fill_sketch_desc(const hoph_sketch_params &p, const LayoutInfo &lay, Sketch
     d.est_shift = lay.est_shift;
     d.est_ok = lay.est_ok;
     d.log_ok = lay.log_ok;
+    d.pow2_ok = lay.pow2_ok;
+    for (uint32_t c = 0; c < kPow2Classes; ++c)
+        for (int j = 0; j < 4; ++j) d.pow2[c][j] = lay.pow2[4 * c + j];
     for (uint32_t r = 0; r <= lay.n_regions; ++r) d.reg_start[r] = lay.reg_start[r];
     for (uint32_t r = 0; r < lay.n_regions; ++r) d.reg_magic[r] = lay.reg_magic[r];
     for (uint32_t r = 0; r < lay.n_regions; ++r) d.reg_mag32[r] = lay.reg_mag32[r];

@@ -13,10 +13,15 @@
 // path is straight-line code (out-of-range lanes are masked, only the LDS
 // minimum is predicated) so the loads of the four elements interleave.
 //
-// Bin lookup: where the bins are near-uniform (plain OPH, a:b = 1:1 HOPH) a
-// 32-bit reciprocal estimate gives the bin or the one before it and one read of
-// a pair of bin starts settles it (LOC_EST); otherwise the region of v comes
-// from the lookup table and the region's own reciprocal (LOC_REGION).
+// Bin lookup: where regions and bins fall on powers of two (the 1:1 hierarchy
+// and power-of-two k over R = 2^31 - 1) one read of a 32-entry table indexed
+// by a leading-zero count gives the region, and a shift and a mask give the
+// bin and the offset (LOC_POW2); where the bins are near-uniform (plain OPH,
+// a:b = 1:1 HOPH) a 32-bit reciprocal estimate gives the bin or the one before
+// it and one read of a pair of bin starts settles it (LOC_EST); narrow ranges
+// with geometric regions find the region from log-domain cells (LOC_LOG);
+// otherwise from the lookup table and the region's own reciprocal
+// (LOC_REGION).
 #include <algorithm>
 #include <type_traits>
 
@@ -39,7 +44,7 @@ __device__ __forceinline__ uint64_t permute(uint64_t x, const SketchDesc &d) {
     }
 }
 
-constexpr int LOC_EST = 0, LOC_REGION = 1, LOC_LOG = 2;
+constexpr int LOC_EST = 0, LOC_REGION = 1, LOC_LOG = 2, LOC_POW2 = 3;
 
 // The (a x + b) mod (2^31 - 1) hash keeps every value, bin start and region
 // start in 32 bits (NARROW); the other hashes keep 64-bit values and starts.
@@ -65,6 +70,8 @@ __host__ __device__ inline SketchLds sketch_lds(uint32_t k, uint32_t nr, uint32_
     } else if (loc == LOC_LOG) {
         reg_bytes = 8u * nr;                       // {start, 32-bit reciprocal}
         lut_bytes = 8u * kLogCells;                // {first region, inner boundary}
+    } else if (loc == LOC_POW2) {
+        lut_bytes = 16u * kPow2Classes;            // {region start, shift, first bin, mask}
     }
     l.lut = (l.reg + reg_bytes + 15u) & ~15u;
     l.sigs = (l.lut + lut_bytes + 15u) & ~15u;
@@ -81,6 +88,7 @@ struct Tables {
     const uint8_t *lut;
     const uint32_t (*cells)[2];              // log cells: {first region, inner boundary}
     const uint32_t (*regs)[2];               // log cells: {region start, 32-bit reciprocal}
+    const uint4 *pow2;                       // power-of-two regions, by leading-zero count
 };
 
 // Builds the workgroup's LDS tables (call with the whole workgroup, then barrier).
@@ -89,6 +97,14 @@ __device__ Tables<HASH> build_tables(const SketchDesc &d, unsigned char *smem, c
     using S = StartT<HASH>;
     const uint32_t k = d.k, nr = d.n_regions, nb = d.nb, tid = threadIdx.x;
     Tables<HASH> t{};
+    if constexpr (LOC == LOC_POW2) {
+        // only the 32-entry table: no bin starts are read
+        uint4 *pt = reinterpret_cast<uint4 *>(smem + L.lut);
+        for (uint32_t c = tid; c < kPow2Classes; c += blockDim.x)
+            pt[c] = make_uint4(d.pow2[c][0], d.pow2[c][1], d.pow2[c][2], d.pow2[c][3]);
+        t.pow2 = pt;
+        return t;
+    }
     S *s_start = reinterpret_cast<S *>(smem + L.starts);
     for (uint32_t b = tid; b < k; b += blockDim.x) {
         const uint32_t r = b / nb, i = b - r * nb;
@@ -140,7 +156,15 @@ __device__ Tables<HASH> build_tables(const SketchDesc &d, unsigned char *smem, c
 template <uint32_t HASH, int LOC>
 __device__ __forceinline__ void bin_of(uint64_t v, const SketchDesc &d, const Tables<HASH> &t, uint32_t &b,
                                        uint32_t &off) {
-    if constexpr (kNarrow<HASH>) {
+    if constexpr (kNarrow<HASH> && LOC == LOC_POW2) {
+        const uint32_t v32 = (uint32_t)v;
+        uint32_t u = (uint32_t)(d.R - 1) - v32;
+        u = u > 1u ? u : 1u;
+        const uint4 e = t.pow2[clz32(u)];          // few distinct entries: mostly broadcast reads
+        const uint32_t dl = v32 - e.x;
+        b = e.z + (dl >> e.y);
+        off = dl & e.w;
+    } else if constexpr (kNarrow<HASH>) {
         const uint32_t v32 = (uint32_t)v;
         uint32_t start;
         if constexpr (LOC == LOC_EST) {
@@ -490,8 +514,10 @@ hipError_t launch_sketch_chunked(const SketchDesc &d, const uint32_t *ids, const
     switch (d.hash) {
     case HOPH_HASH_TABLE: return est ? HOPH_SKC(HOPH_HASH_TABLE, LOC_EST) : HOPH_SKC(HOPH_HASH_TABLE, LOC_REGION);
     case HOPH_HASH_MODP31:
-        return est ? HOPH_SKC(HOPH_HASH_MODP31, LOC_EST)
-                   : d.log_ok ? HOPH_SKC(HOPH_HASH_MODP31, LOC_LOG) : HOPH_SKC(HOPH_HASH_MODP31, LOC_REGION);
+        return d.pow2_ok ? HOPH_SKC(HOPH_HASH_MODP31, LOC_POW2)
+               : est     ? HOPH_SKC(HOPH_HASH_MODP31, LOC_EST)
+               : d.log_ok ? HOPH_SKC(HOPH_HASH_MODP31, LOC_LOG)
+                          : HOPH_SKC(HOPH_HASH_MODP31, LOC_REGION);
     default: return est ? HOPH_SKC(HOPH_HASH_MODP32P15, LOC_EST) : HOPH_SKC(HOPH_HASH_MODP32P15, LOC_REGION);
     }
 #undef HOPH_SKC
@@ -505,8 +531,10 @@ hipError_t launch_sketch(const SketchDesc &d, const uint32_t *ids, const uint64_
     switch (d.hash) {
     case HOPH_HASH_TABLE: return est ? HOPH_SK(HOPH_HASH_TABLE, LOC_EST) : HOPH_SK(HOPH_HASH_TABLE, LOC_REGION);
     case HOPH_HASH_MODP31:
-        return est ? HOPH_SK(HOPH_HASH_MODP31, LOC_EST)
-                   : d.log_ok ? HOPH_SK(HOPH_HASH_MODP31, LOC_LOG) : HOPH_SK(HOPH_HASH_MODP31, LOC_REGION);
+        return d.pow2_ok ? HOPH_SK(HOPH_HASH_MODP31, LOC_POW2)
+               : est     ? HOPH_SK(HOPH_HASH_MODP31, LOC_EST)
+               : d.log_ok ? HOPH_SK(HOPH_HASH_MODP31, LOC_LOG)
+                          : HOPH_SK(HOPH_HASH_MODP31, LOC_REGION);
     default: return est ? HOPH_SK(HOPH_HASH_MODP32P15, LOC_EST) : HOPH_SK(HOPH_HASH_MODP32P15, LOC_REGION);
     }
 #undef HOPH_SK

@@ -113,6 +113,67 @@ def test_modp32_hash_edges():
             assert (gb, go) == (lay.bin_of(v), v - lay.starts[lay.bin_of(v)])
 
 
+def test_modp31_hash_edges():
+    """(a x + b) mod (2^31 - 1) at the extremes of a, b and x (universe = P): the
+    largest w = a x + b, and values whose low 31 bits and high part are both large."""
+    P = (1 << 31) - 1
+    rng = np.random.default_rng(31)
+    coeffs = [(P - 1, P - 1), (1, 0), (P - 1, 0), (1, P - 1), (1 << 30, P - 1), (P - 2, P - 3)]
+    coeffs += [(int(rng.integers(1, P)), int(rng.integers(0, P))) for _ in range(4)]
+    for a, bb in coeffs:
+        p = H.SketchParams(H.LAYOUT_HIER, 512, 32, H.HASH_MODP31, P, hash_a=a, hash_b=bb)
+        xs = [0, 1, 2, P - 1, P - 2, 1 << 30, (1 << 30) + 1, (P - 1) // 2]
+        # ids that put the low 31 bits of w at or near 2^31 - 1
+        for t in range(3):
+            x = (((P - 1 - t - bb) % P) * pow(a, -1, P)) % P
+            xs.append(int(x))
+        xs += rng.integers(0, P, size=200).tolist()
+        ids = np.array(xs, dtype=np.uint32)
+        b, o = H.selftest_bins(p, ids)
+        lay = _tiny_layout(p)
+        for x, gb, go in zip(ids.tolist(), b.tolist(), o.tolist()):
+            v = (a * x + bb) % P
+            assert (gb, go) == (lay.bin_of(v), v - lay.starts[lay.bin_of(v)]), (a, bb, x)
+
+
+def test_lookup_modes_cover_the_bench_layouts():
+    """The power-of-two lookup applies to the 1:1 hierarchy and power-of-two k
+    over R = 2^31 - 1 (so the self-test cross-checks it there) and not where
+    regions or bins miss the powers of two."""
+    P = (1 << 31) - 1
+    def mask(layout, k, kp, a=1, b=1, h=H.HASH_MODP31, u=1 << 20):
+        return H.layout_lookups(H.SketchParams(layout, k, kp, h, u, a, b, hash_a=12345, hash_b=678))
+    assert mask(H.LAYOUT_HIER, 512, 32) & H.LOOKUP_POW2
+    assert mask(H.LAYOUT_HIER, 256, 32) & H.LOOKUP_POW2
+    assert mask(H.LAYOUT_OPH, 512, 32) & H.LOOKUP_POW2
+    assert mask(H.LAYOUT_HIER, 128, 8, u=P) & H.LOOKUP_POW2
+    assert not mask(H.LAYOUT_OPH, 320, 32) & H.LOOKUP_POW2
+    assert not mask(H.LAYOUT_HIER, 256, 32, 1, 2) & H.LOOKUP_POW2
+    assert not mask(H.LAYOUT_HIER, 256, 32, 2, 1) & H.LOOKUP_POW2
+    assert not mask(H.LAYOUT_HIER, 512, 32, h=H.HASH_MODP32P15, u=1 << 32) & H.LOOKUP_POW2
+    assert mask(H.LAYOUT_HIER, 256, 32, 1, 2) & H.LOOKUP_LOG_CELLS
+
+
+@pytest.mark.parametrize("layout,k,kp", [(H.LAYOUT_HIER, 512, 32), (H.LAYOUT_HIER, 256, 32), (H.LAYOUT_OPH, 512, 32),
+                                         (H.LAYOUT_HIER, 128, 8), (H.LAYOUT_OPH, 256, 16)])
+def test_pow2_lookup_matches_oracle_at_region_edges(layout, k, kp):
+    """Every region and bin edge of a power-of-two layout, and values next to
+    them, through the library's lookups (the self-test runs the power-of-two
+    table against the region search for each) against the oracle's bins."""
+    P = (1 << 31) - 1
+    p = H.SketchParams(layout, k, kp, H.HASH_MODP31, P, hash_a=1, hash_b=0)   # v = x
+    assert H.layout_lookups(p) & H.LOOKUP_POW2
+    lay = _tiny_layout(p)
+    vals = sorted(set(v + dd for v in lay.starts + [lay.R] for dd in (-2, -1, 0, 1) if 0 <= v + dd < lay.R))
+    vals += [(1 << e) + dd for e in range(31) for dd in (-1, 0, 1) if 0 <= (1 << e) + dd < lay.R]
+    vals += [lay.R - 1 - ((1 << e) + dd) for e in range(31) for dd in (-1, 0, 1) if 0 <= (1 << e) + dd < lay.R]
+    vals = sorted(set(vals))
+    b, o = H.selftest_bins(p, np.array(vals, dtype=np.uint32))
+    for v, gb, go in zip(vals, b.tolist(), o.tolist()):
+        eb = lay.bin_of(v)
+        assert (gb, go) == (eb, v - lay.starts[eb]), v
+
+
 def test_tail_integers_match_oracle():
     for n in (1, 2, 7, 16, 32, 64, 100, 128):
         for T in (F(1, 10), F(1, 2), F(3, 5), F(7, 10), F(4, 5), F(9, 10), F(1)):
