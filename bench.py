@@ -690,9 +690,20 @@ def main():
     m_rej0 = tabs["rej"][0] // unit0 if tabs["rej"][0] >= 0 else -1
     depth = 1 if (m_rej0 >= 0 and 8 * m_rej0 >= kp) else code_groups
     # coarse pass on 8-bit bin codes held as 8 bit-planes of 32 bins per word:
-    # per (pair, group) 8 W plane operations, W masks, W popcounts, 1 compare
+    # per (pair, group) 8 W plane operations, W masks, W popcounts, 1 compare.
+    # The first-group pass compares the first P1 planes of every pair first and
+    # the rest only where a lane might still survive (P1 = 2 when the threshold
+    # on differing bins is at most half the bins, 4 when at most three
+    # quarters): the work every pair gets is then P1 W plane operations, W
+    # masks, W popcounts and 1 compare.
     W_planes = 1 if kp <= 32 else 2
     ops_per_pair_group = 10 * W_planes + 1
+    plane_split = 0
+    if depth == 1 and w.T is not None:
+        dthr = kp + 1 if m_rej0 < 0 else kp - m_rej0
+        plane_split = 2 if 2 * dthr <= kp else (4 if 4 * dthr <= 3 * kp else 0)
+        if plane_split:
+            ops_per_pair_group = W_planes * (plane_split + 2) + 1
     coarse_ops = Q * N * depth * ops_per_pair_group
     coarse_bins = Q * N * kp * depth
     coarse_bytes = N * 32 * W_planes * depth + Q * (32 * W_planes + 16) * depth
@@ -716,7 +727,7 @@ def main():
                                  "algorithmic_bytes": index_bytes},
         "scan_coarse": {"ms": coarse_ms, "bound": "alu", "achieved": coarse_ops / (coarse_ms * 1e-3) / 1e12,
                         "peak": ALU_PEAK_OPS / 1e12, "unit": "Tops/s (32-bit VALU lane-ops)",
-                        "ops_per_pair_group": ops_per_pair_group,
+                        "ops_per_pair_group": ops_per_pair_group, "first_phase_planes": plane_split,
                         "bin_compares_per_s": coarse_bins / (coarse_ms * 1e-3),
                         "traffic": traffic.get("scan_codes_fast_kernel"), "algorithmic_bytes": coarse_bytes,
                         "hbm_gbs": coarse_bytes / (coarse_ms * 1e-3) / 1e9, "depth": depth},

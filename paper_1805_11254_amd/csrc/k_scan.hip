@@ -144,6 +144,18 @@ __device__ __forceinline__ uint32_t code_diff(const uint32_t *P, const uint32_t 
     return d;
 }
 
+// The differing-bin mask over planes [P0, P1) only, continuing the chain from d
+// (d is ignored when P0 = 0).  A mask over the first planes is a subset of the
+// mask over all of them.
+template <int W, int P0, int P1>
+__device__ __forceinline__ uint32_t code_diff_part(uint32_t d, const uint32_t *P, const uint32_t *__restrict__ Q,
+                                                   int w) {
+#pragma unroll
+    for (int p = P0; p < P1; ++p)
+        d = p == 0 ? (P[w] ^ Q[w]) : __builtin_amdgcn_bitop3_b32(d, P[p * W + w], Q[p * W + w], 0xF6);
+    return d;
+}
+
 // One group of the coarse pass on codes: the group's planes P and set-empty
 // masks em against the query's record, added to the weighted state S, and the
 // step's cutoffs applied to a lane still undecided (maybe: an accept cutoff
@@ -398,8 +410,13 @@ __global__ __launch_bounds__(64) void scan_codes_deep_kernel(const uint32_t *__r
 // sets per wavefront: each query's record (read with scalar loads, one query
 // ahead) is compared with TPW tiles, so the scalar work of a query is shared
 // by 64 TPW sets.  A pair is kept when its count of differing query-non-empty
-// bins is below the query's threshold (see ScanTab::dthr0).
-template <int W, int TPW>
+// bins is below the query's threshold (see ScanTab::dthr0).  With P1 > 0 the
+// first P1 planes are compared first, for all TPW tiles: bins that differ
+// there differ in the full code too, so when no lane's partial count is below
+// the threshold the query is done with these tiles (the usual case for pairs
+// far from the threshold), and otherwise the remaining planes continue each
+// tile's chain.
+template <int W, int TPW, int P1>
 __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_t *__restrict__ codes,
                                                                   const uint32_t *__restrict__ qcodes,
                                                                   Survivor *__restrict__ surv,
@@ -456,19 +473,41 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_
 // out twice below, on the kernel's own restrict pointers, so that the record
 // loads stay scalar)
 #define HOPH_CODE_QUERY_T(r, qq)                                                                   \
-        _Pragma("unroll") for (int t = 0; t < TPW; ++t) {                                          \
-            uint32_t dn = 0;                                                                       \
-            _Pragma("unroll") for (int w = 0; w < W; ++w) dn +=                                    \
-                __popc(code_diff<W>(P[t], r, w) & r[PW + w]);                                      \
-            const bool survive = ((int32_t)dn < (int32_t)r[PW + 2]) & valid[t] &                   \
-                                 (!a.tri | (sid[t] > (qq)));                                         \
-            const uint64_t bal = __builtin_amdgcn_ballot_w64(survive);                             \
-            if (bal) {                                                                             \
-                uint64_t base = 0;                                                                 \
-                if (lane == 0) base = atomicAdd(counters + 0, (unsigned long long)__popcll(bal));  \
-                base = __shfl(base, 0);                                                            \
-                const uint64_t slot = base + lane_rank(bal, lane);                                 \
-                if (survive && slot < a.surv_cap) surv[slot] = Survivor{(qq), sid[t], 0};          \
+        {                                                                                          \
+            uint32_t dd[TPW][W];                                                                   \
+            bool open = true;                                                                      \
+            if constexpr (P1 > 0) {                                                                \
+                bool keep = false;                                                                 \
+                _Pragma("unroll") for (int t = 0; t < TPW; ++t) {                                  \
+                    uint32_t dn = 0;                                                               \
+                    _Pragma("unroll") for (int w = 0; w < W; ++w) {                                \
+                        dd[t][w] = code_diff_part<W, 0, P1>(0u, P[t], r, w);                       \
+                        dn += __popc(dd[t][w] & r[PW + w]);                                        \
+                    }                                                                              \
+                    keep |= ((int32_t)dn < (int32_t)r[PW + 2]) & valid[t] & (!a.tri | (sid[t] > (qq)));  \
+                }                                                                                  \
+                open = __any(keep);                                                                \
+            }                                                                                      \
+            if (open) {                                                                            \
+                _Pragma("unroll") for (int t = 0; t < TPW; ++t) {                                  \
+                    uint32_t dn = 0;                                                               \
+                    _Pragma("unroll") for (int w = 0; w < W; ++w) {                                \
+                        const uint32_t d = P1 > 0                                                  \
+                            ? code_diff_part<W, P1, (int)kCodeBits>(dd[t][w], P[t], r, w)          \
+                            : code_diff<W>(P[t], r, w);                                            \
+                        dn += __popc(d & r[PW + w]);                                               \
+                    }                                                                              \
+                    const bool survive = ((int32_t)dn < (int32_t)r[PW + 2]) & valid[t] &           \
+                                         (!a.tri | (sid[t] > (qq)));                                 \
+                    const uint64_t bal = __builtin_amdgcn_ballot_w64(survive);                     \
+                    if (bal) {                                                                     \
+                        uint64_t base = 0;                                                         \
+                        if (lane == 0) base = atomicAdd(counters + 0, (unsigned long long)__popcll(bal));  \
+                        base = __shfl(base, 0);                                                    \
+                        const uint64_t slot = base + lane_rank(bal, lane);                         \
+                        if (survive && slot < a.surv_cap) surv[slot] = Survivor{(qq), sid[t], 0};  \
+                    }                                                                              \
+                }                                                                                  \
             }                                                                                      \
         }
         for (uint32_t q = qa; q < qb; q += 2) {
@@ -820,10 +859,24 @@ void codes_launch(const ScanLaunch &l, const CoarseArgs &a, const ScanTab &tab, 
                        l.qmasks, l.surv, cnt, l.desc, a, tab)
     switch (l.depth) {
     case 1:
-        if (tab.policy == HOPH_EMPTY_EITHER) HOPH_CODES(1);
-        else
-            hipLaunchKernelGGL((scan_codes_fast_kernel<W, fast_tiles(W)>), dim3(blocks), dim3(kThreads), 0, st,
-                               l.codes, l.qcodes, l.surv, cnt, l.desc, a);
+        if (tab.policy == HOPH_EMPTY_EITHER) {
+            HOPH_CODES(1);
+        } else {
+            // planes compared first: a non-matching bin differs in the first p planes
+            // with probability 1 - 2^-p under uniform codes, so a pair far from the
+            // threshold (most of them) is settled by 2 planes when the threshold is
+            // at most half the bins, by 4 when at most three quarters
+            const int32_t thr = tab.dthr0[0], kp = (int32_t)l.kp;
+            if (2 * thr <= kp)
+                hipLaunchKernelGGL((scan_codes_fast_kernel<W, fast_tiles(W), 2>), dim3(blocks), dim3(kThreads), 0, st,
+                                   l.codes, l.qcodes, l.surv, cnt, l.desc, a);
+            else if (4 * thr <= 3 * kp)
+                hipLaunchKernelGGL((scan_codes_fast_kernel<W, fast_tiles(W), 4>), dim3(blocks), dim3(kThreads), 0, st,
+                                   l.codes, l.qcodes, l.surv, cnt, l.desc, a);
+            else
+                hipLaunchKernelGGL((scan_codes_fast_kernel<W, fast_tiles(W), 0>), dim3(blocks), dim3(kThreads), 0, st,
+                                   l.codes, l.qcodes, l.surv, cnt, l.desc, a);
+        }
         break;
     case 2: HOPH_CODES(2); break;
     case 3: HOPH_CODES(3); break;

@@ -189,7 +189,8 @@ def test_code_collisions_match_oracle(k, kp):
     dsig = torch.from_numpy(sig.view(np.int32)).to("cuda")
     dq = torch.from_numpy(qsig.view(np.int32)).to("cuda")
     idx = H.Index(p, dsig)
-    for T, eps in (((4, 5), (1, 10_000)), ((1, 2), (1, 100))):
+    # T = 4/5, 7/10 and 1/2 take the code pass's three plane splits (2, 4, all 8 first)
+    for T, eps in (((4, 5), (1, 10_000)), ((7, 10), (1, 10_000)), ((1, 2), (1, 100))):
         for policy in _policies_that_fit(p, T, eps):
             oo, oi = oracle_query(w, sig, qsig, T, eps, policy)
             for depth in (0, 1, 3):
