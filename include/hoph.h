@@ -175,9 +175,19 @@ hoph_status hoph_index_reset(hoph_index *index);
 hoph_status hoph_query_timing(const hoph_index *index, float ms[3]);
 
 /* hoph_append_timing -- device time of the last index_append_sets call on this
-   index, in ms: ms[0] the sketch into the slabs, ms[1] the code planes (zeros
-   before any call).  Waits for that call to finish. */
+   index, in ms: ms[0] the sketch into the index rows, ms[1] the code planes of
+   the new rows (zeros before any call).  Waits for that call to finish. */
 hoph_status hoph_append_timing(const hoph_index *index, float ms[2]);
+
+/* hoph_index_code_planes -- copies the index's narrowed code planes (a test
+   hook, for comparing how they were written): dims[0] = groups that carry codes
+   (cg), dims[1] = rows (the capacity), dims[2] = words per (row, group) (PW);
+   word w of (group g, row s) is at ((g * dims[1] / 64 + s / 64) * 64 + s % 64) *
+   dims[2] + w, and only rows below the index size are defined.  d_out: device,
+   out_words >= dims[0] * dims[1] * dims[2], else HOPH_E_CAPACITY (dims are
+   written either way).  Asynchronous on hip_stream. */
+hoph_status hoph_index_code_planes(const hoph_index *index, uint32_t *d_out, uint64_t out_words, uint64_t dims[3],
+                                   void *hip_stream);
 
 /* hoph_index_size -- number of sets in the index (0 for NULL). */
 uint64_t hoph_index_size(const hoph_index *index);

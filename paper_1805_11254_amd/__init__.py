@@ -91,6 +91,7 @@ SIGNATURES = {
     "hoph_pair_estimates": (C.c_int, [vp, vp, u32, vp, u64, u32, vp, vp, vp, vp, vp, C.POINTER(C.c_int64), vp]),
     "hoph_index_size": (u64, [vp]),
     "hoph_index_reset": (C.c_int, [vp]),
+    "hoph_index_code_planes": (C.c_int, [vp, vp, u64, C.POINTER(u64), vp]),
     "hoph_query_timing": (C.c_int, [vp, C.POINTER(C.c_float)]),
     "hoph_index_free": (None, [vp]),
     "query_goph": (C.c_int, [vp, vp, u32, C.POINTER(QueryParamsC), C.POINTER(ResultsC), vp]),
@@ -269,8 +270,22 @@ class Index:
         _check(lib().index_append_sets(self._h, vp(ids.data_ptr()), vp(offsets.data_ptr()), max(n, 0),
                                        _stream(stream)))
 
+    def code_planes(self, stream=None):
+        """The index's code planes as int32 [cg, capacity / 64, 64, PW] (rows past
+        the index size undefined), a copy."""
+        import torch
+        dims = (u64 * 3)()
+        st = lib().hoph_index_code_planes(self._h, None, 0, dims, _stream(stream))   # sizes only
+        if st not in (0, HOPH_E_CAPACITY):
+            _check(st)
+        cg, rows, pw = int(dims[0]), int(dims[1]), int(dims[2])
+        out = torch.empty(max(cg * rows * pw, 1), dtype=torch.int32, device="cuda")
+        _check(lib().hoph_index_code_planes(self._h, vp(out.data_ptr()), out.numel(), dims, _stream(stream)))
+        return out[:cg * rows * pw].view(cg, rows // 64, 64, pw)
+
     def last_append_ms(self):
-        """(sketch into slabs, code planes) device ms of the last append_sets."""
+        """(sketch into the rows, code planes of the new rows) device ms of the
+        last append_sets."""
         ms = (C.c_float * 2)()
         _check(lib().hoph_append_timing(self._h, ms))
         return ms[0], ms[1]

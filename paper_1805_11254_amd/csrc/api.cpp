@@ -407,6 +407,25 @@ hoph_status index_append_sets(hoph_index *idx, const uint32_t *d_ids, const uint
 
 uint64_t hoph_index_size(const hoph_index *idx) { return idx ? idx->n : 0; }
 
+hoph_status hoph_index_code_planes(const hoph_index *idx, uint32_t *d_out, uint64_t out_words, uint64_t dims[3],
+                                   void *hip_stream) {
+    g_last_error.clear();
+    if (!idx || !dims) return fail(HOPH_E_INVAL, "NULL argument");
+    dims[0] = idx->cg;
+    dims[1] = idx->capacity;
+    dims[2] = code_words(idx->lay.kp);
+    const uint64_t words = dims[0] * dims[1] * dims[2];
+    if (!idx->codes || words == 0) return HOPH_OK;
+    if (out_words < words) return fail(HOPH_E_CAPACITY, "output smaller than the code planes");
+    if (!d_out) return fail(HOPH_E_INVAL, "d_out is NULL");
+    DeviceGuard dg(idx->device);
+    if (!dg.ok) return fail(HOPH_E_DEVICE, "cannot select the index device");
+    HOPH_HIP(hipMemcpyAsync(d_out, idx->codes, words * 4, hipMemcpyDeviceToDevice,
+                            reinterpret_cast<hipStream_t>(hip_stream)),
+             "hipMemcpyAsync(code planes)");
+    return HOPH_OK;
+}
+
 hoph_status hoph_index_reset(hoph_index *idx) {
     g_last_error.clear();
     if (!idx) return fail(HOPH_E_INVAL, "index is NULL");

@@ -249,47 +249,48 @@ __device__ __forceinline__ void wave_lds_fence() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// Ids of a batch: a full batch through the wave-uniform base pointer (lane
-// offsets fixed, no clamping); the last batch of a range clamped to hi - 1.
-template <bool FULL>
-__device__ __forceinline__ void load_batch(const uint32_t *__restrict__ ids, uint64_t base, uint64_t hi,
-                                           uint32_t lane, uint32_t (&x)[kUnroll]) {
-    if constexpr (FULL) {
-        const uint32_t *p = ids + base;
+// A batch of ids: the 64 kUnroll ids from p (wave-uniform), lane byte offsets
+// off[u] = 4 (lane + 64 u) clamped to the range's last id (`last4` = 4 (n - 1),
+// n >= 1 ids left from p): one load site with one clamp per load, so that the
+// loads of the next batch stay in flight while the current batch is processed.
+__device__ __forceinline__ void load_batch_at(const uint32_t *__restrict__ p, uint32_t last4,
+                                              const uint32_t (&off)[kUnroll], uint32_t (&x)[kUnroll]) {
+    const unsigned char *b = reinterpret_cast<const unsigned char *>(p);
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) x[u] = p[lane + 64u * u];
-    } else {
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const uint64_t j = base + lane + 64u * u;
-            x[u] = ids[j < hi ? j : hi - 1];
-        }
-    }
+    for (int u = 0; u < kUnroll; ++u) x[u] = *reinterpret_cast<const uint32_t *>(b + min(off[u], last4));
 }
 
-// The elements [lo, hi) into the LDS signature; the next batch of ids is read
-// while the current one is processed.
+__device__ __forceinline__ uint32_t last_byte(uint64_t from, uint64_t end) {
+    const uint64_t n = end - from;
+    return (uint32_t)(n < 64u * kUnroll ? n - 1 : 64u * kUnroll - 1) * 4u;
+}
+
+// The elements [lo, hi) into the LDS signature.  x holds the first batch of
+// [lo, hi) on entry; the next batch is read while the current one is
+// processed, and during the last batch the first batch of the next set's range
+// [nlo, nhi) (or, with none, this batch again) is read into x.
 template <uint32_t HASH, int LOC>
 __device__ __forceinline__ void sketch_range(const SketchDesc &d, const Tables<HASH> &t,
                                              const uint32_t *__restrict__ ids, uint64_t lo, uint64_t hi,
-                                             uint32_t *sig, uint32_t lane, uint32_t umax, uint32_t &xmax,
-                                             uint64_t &vmax) {
-    if (hi <= lo) return;
+                                             uint64_t nlo, uint64_t nhi, const uint32_t (&off)[kUnroll],
+                                             uint32_t (&x)[kUnroll], uint32_t *sig, uint32_t lane, uint32_t umax,
+                                             uint32_t &xmax, uint64_t &vmax) {
     constexpr uint32_t B = 64u * kUnroll;
-    uint32_t x[kUnroll];
-    if (lo + B <= hi) load_batch<true>(ids, lo, hi, lane, x);
-    else load_batch<false>(ids, lo, hi, lane, x);
+    if (hi <= lo) {
+        if (nlo < nhi) load_batch_at(ids + nlo, last_byte(nlo, nhi), off, x);
+        return;
+    }
     for (uint64_t base = lo; base < hi; base += B) {
         const uint64_t next = base + B;
+        const bool more = next < hi, ahead = nlo < nhi;
+        const uint64_t src = more ? next : (ahead ? nlo : base);
+        const uint64_t end = more ? hi : (ahead ? nhi : hi);
         uint32_t xn[kUnroll];
-        if (next + B <= hi) load_batch<true>(ids, next, hi, lane, xn);
-        else if (next < hi) load_batch<false>(ids, next, hi, lane, xn);
+        load_batch_at(ids + src, last_byte(src, end), off, xn);
         if (base + B <= hi) add_elements<HASH, LOC, true>(d, t, sig, x, base, hi, lane, umax, xmax, vmax);
         else add_elements<HASH, LOC, false>(d, t, sig, x, base, hi, lane, umax, xmax, vmax);
-        if (next < hi) {
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) x[u] = xn[u];
-        }
+        for (int u = 0; u < kUnroll; ++u) x[u] = xn[u];
     }
 }
 
@@ -312,12 +313,27 @@ __global__ __launch_bounds__(256) void sketch_kernel(SketchDesc d, const uint32_
     uint64_t vmax = 0;
     const uint32_t umax = (uint32_t)(d.universe - 1);
     const uint64_t wstride = (uint64_t)gridDim.x * waves;
-    for (uint64_t set = (uint64_t)blockIdx.x * waves + wib; set < n_sets; set += wstride) {
-        const uint64_t lo = offsets[set], hi = offsets[set + 1];
+    uint32_t off[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) off[u] = 4u * (lane + 64u * u);
+    uint64_t set = (uint64_t)blockIdx.x * waves + wib, lo = 0, hi = 0;
+    uint32_t x[kUnroll];
+    if (set < n_sets) {
+        lo = offsets[set];
+        hi = offsets[set + 1];
+        if (lo < hi) load_batch_at(ids + lo, last_byte(lo, hi), off, x);
+    }
+    for (; set < n_sets; set += wstride) {
+        const uint64_t nset = set + wstride;
+        uint64_t nlo = 0, nhi = 0;
+        if (nset < n_sets) {
+            nlo = offsets[nset];
+            nhi = offsets[nset + 1];
+        }
         for (uint32_t b = lane; b < k; b += 64) sig[b] = HOPH_EMPTY;
         wave_lds_fence();
         if (hi == lo) err |= kErrEmptySet;
-        sketch_range<HASH, LOC>(d, t, ids, lo, hi, sig, lane, umax, xmax, vmax);
+        sketch_range<HASH, LOC>(d, t, ids, lo, hi, nlo, nhi, off, x, sig, lane, umax, xmax, vmax);
         wave_lds_fence();
         uint32_t *out = sigs + set * k;
         if (vec_out) {
@@ -328,6 +344,8 @@ __global__ __launch_bounds__(256) void sketch_kernel(SketchDesc d, const uint32_
             for (uint32_t i = lane; i < k; i += 64) out[i] = sig[i];
         }
         wave_lds_fence();
+        lo = nlo;
+        hi = nhi;
     }
     err |= range_error<HASH>(d, xmax, vmax);
     if (err) atomicOr(err_flag, err);
@@ -431,7 +449,11 @@ __global__ __launch_bounds__(256) void sketch_chunked_kernel(SketchDesc d, const
         const uint64_t hi = min(s_hi, lo + chunk);
         for (uint32_t b = lane; b < k; b += 64) sig[b] = HOPH_EMPTY;
         wave_lds_fence();
-        sketch_range<HASH, LOC>(d, t, ids, lo, hi, sig, lane, umax, xmax, vmax);
+        uint32_t off[kUnroll], x[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) off[u] = 4u * (lane + 64u * u);
+        if (lo < hi) load_batch_at(ids + lo, last_byte(lo, hi), off, x);
+        sketch_range<HASH, LOC>(d, t, ids, lo, hi, 0, 0, off, x, sig, lane, umax, xmax, vmax);
         wave_lds_fence();
         uint32_t *out = sigs + set * k;
         for (uint32_t b = lane; b < k; b += 64) {

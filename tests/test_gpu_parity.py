@@ -419,8 +419,31 @@ def _append_sets_check(w, cuts):
         m1, e1 = H.pair_counts(two_step, qsig, P, policy)
         m2, e2 = H.pair_counts(fused, qsig, P, policy)
         assert torch.equal(m1, m2) and torch.equal(e1, e2), policy
+    # the code planes written after sketching into the rows are the ones the
+    # index store writes from given signatures, word for word
+    n = w.collection.n
+    ca, cb = two_step.code_planes(), fused.code_planes()
+    assert ca.shape == cb.shape
+    cg, tiles, _, pw = ca.shape
+    ra, rb = ca.reshape(cg, tiles * 64, pw)[:, :n], cb.reshape(cg, tiles * 64, pw)[:, :n]
+    assert torch.equal(ra, rb)
     two_step.free()
     fused.free()
+    return sh, ra.cpu().numpy().view(np.uint32)
+
+
+def _planes_from_rows(sh, kp, cg):
+    """Code planes restated from signature rows: bit i of word p W + w of (row,
+    group g) is bit p of the code of bin 32 w + i of the group."""
+    n = sh.shape[0]
+    W_ = 1 if kp <= 32 else 2
+    out = np.zeros((cg, n, 8 * W_), dtype=np.uint64)
+    for g in range(cg):
+        codes = _code8(sh[:, g * kp:(g + 1) * kp])               # n x kp
+        for i in range(kp):
+            for pl in range(8):
+                out[g, :, pl * W_ + i // 32] |= ((codes[:, i] >> np.uint64(pl)) & np.uint64(1)) << np.uint64(i % 32)
+    return out.astype(np.uint32)
 
 
 @pytest.mark.parametrize("name", list(SMALL))
@@ -434,12 +457,19 @@ def test_append_sets_matches_oracle(name):
     _append_sets_check(w, cuts)
 
 
-@pytest.mark.parametrize("layout,k,kp", [(W.LAYOUT_HIER, 192, 12), (W.LAYOUT_OPH, 120, 10), (W.LAYOUT_HIER, 320, 40)])
+@pytest.mark.parametrize("layout,k,kp", [(W.LAYOUT_HIER, 192, 12), (W.LAYOUT_OPH, 120, 10), (W.LAYOUT_HIER, 320, 40),
+                                         (W.LAYOUT_HIER, 320, 20), (W.LAYOUT_OPH, 320, 40), (W.LAYOUT_OPH, 160, 5),
+                                         (W.LAYOUT_HIER, 512, 32), (W.LAYOUT_OPH, 512, 64)])
 def test_append_sets_group_sizes(layout, k, kp):
+    """Group sizes of one and two plane words, odd and even counts of groups
+    that carry codes, every sketch lookup; the planes also against a restatement
+    from the rows."""
     _print_case(f"append_sets group size layout={layout} k={k} kp={kp}")
     w = W.hoph_bovw(n=2_345, n_q=8, seed=41 + kp, k=k, kp=kp, planted_frac=0.02)
     w.layout = layout
-    _append_sets_check(w, [0, 100, 1000, 2_345])
+    sh, planes = _append_sets_check(w, [0, 100, 1000, 2_345])
+    cg = planes.shape[0]
+    assert (planes == _planes_from_rows(sh, kp, cg)).all()
 
 
 def test_append_sets_reports_range_and_empty_sets():
