@@ -106,13 +106,20 @@ hipError_t append_sets_async(hoph_index *idx, const uint32_t *d_ids, const uint6
     SketchDesc d;
     fill_sketch_desc(idx->params, idx->lay, d);
     hipError_t e = hipSuccess;
+    // code planes of the new rows: the row kernel where it reads a group as
+    // 16-byte loads, else the sketch writes them from its LDS signature (then
+    // aev[1]..aev[2] spans no work)
+    const bool fused = idx->codes && !codes_have_row_kernel(idx->lay.k, idx->lay.kp);
+    const CodeSink sink = fused ? CodeSink{idx->codes, first, idx->capacity / 64, idx->cg, idx->lay.kp} : CodeSink{};
     if (timed && (e = hipEventRecord(idx->ws.aev[0], s)) != hipSuccess) return e;
-    e = launch_sketch(d, d_ids, d_offsets, n_sets, idx->slab + first * idx->lay.k, err_word, s);
+    e = launch_sketch(d, d_ids, d_offsets, n_sets, idx->slab + first * idx->lay.k, err_word, s, sink);
     if (e != hipSuccess) return e;
     if (timed && (e = hipEventRecord(idx->ws.aev[1], s)) != hipSuccess) return e;
-    e = launch_codes_from_slab(idx->slab, idx->capacity, idx->lay.k, idx->lay.kp, first, n_sets, idx->codes, idx->cg,
-                               s);
-    if (e != hipSuccess) return e;
+    if (!fused) {
+        e = launch_codes_from_slab(idx->slab, idx->capacity, idx->lay.k, idx->lay.kp, first, n_sets, idx->codes,
+                                   idx->cg, s);
+        if (e != hipSuccess) return e;
+    }
     if (timed && (e = hipEventRecord(idx->ws.aev[2], s)) != hipSuccess) return e;
     if (timed) idx->ws.aev_recorded = true;
     return hipSuccess;

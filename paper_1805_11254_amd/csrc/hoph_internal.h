@@ -349,8 +349,17 @@ int device_cu_count();   // compute units of the current device (cached)
 // values travel as kernel arguments, so no host buffer has to outlive the call).
 hipError_t launch_set_desc(uint64_t *desc, uint64_t a, uint64_t b, hipStream_t st);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t value, hipStream_t st);
+// Where the sketch of an index append also writes the new rows' code planes
+// (the index's tiled layout, see k_index.hip): set i of the launch is index row
+// first + i.  codes == nullptr: signatures only.
+struct CodeSink {
+    uint32_t *codes;
+    uint64_t first, ctiles;          // ctiles = index capacity / 64
+    uint32_t cg, kp;
+};
 hipError_t launch_sketch(const SketchDesc &d, const uint32_t *ids, const uint64_t *offsets,
-                         uint64_t n_sets, uint32_t *sigs, uint32_t *err_flag, hipStream_t st);
+                         uint64_t n_sets, uint32_t *sigs, uint32_t *err_flag, hipStream_t st,
+                         const CodeSink &sink = CodeSink{});
 // Sketch of a batch whose size is desc[0] (at most max_sets), split into chunks of
 // `chunk` ids so that uneven sets balance; prefix needs max_sets + 1 entries.
 // Set ranges are clamped to the first max_ids staged ids (a malformed range is empty).
@@ -359,6 +368,10 @@ hipError_t launch_sketch_chunked(const SketchDesc &d, const uint32_t *ids, const
                                  uint64_t max_ids, uint32_t *sigs, uint32_t *err_flag, uint32_t waves_per_cu,
                                  hipStream_t st);
 // Code planes of index rows [first, first + n_new) from the rows themselves.
+// Whether the code planes of new rows have a row kernel reading each group as
+// 16-byte loads (k' = 16, 32, 64 with k a multiple of 4); otherwise the sketch
+// of an append writes them from its LDS signature.
+bool codes_have_row_kernel(uint32_t k, uint32_t kp);
 hipError_t launch_codes_from_slab(const uint32_t *slab, uint64_t capacity, uint32_t k, uint32_t kp, uint64_t first,
                                   uint64_t n_new, uint32_t *codes, uint32_t cg, hipStream_t st);
 // Copies signature rows into index rows [first, first + n_new) and, when codes

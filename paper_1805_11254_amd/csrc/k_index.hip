@@ -180,6 +180,8 @@ hipError_t launch_index_store(const uint32_t *sigs, uint64_t n_new, uint64_t fir
     return launch_codes_from_slab(slab, capacity, k, kp, first, n_new, codes, cg, st);
 }
 
+bool codes_have_row_kernel(uint32_t k, uint32_t kp) { return (k % 4) == 0 && (kp == 16 || kp == 32 || kp == 64); }
+
 hipError_t launch_codes_from_slab(const uint32_t *slab, uint64_t capacity, uint32_t k, uint32_t kp, uint64_t first,
                                   uint64_t n_new, uint32_t *codes, uint32_t cg, hipStream_t st) {
     if (n_new == 0 || cg == 0 || !codes) return hipSuccess;

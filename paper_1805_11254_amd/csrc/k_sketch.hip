@@ -243,6 +243,59 @@ __device__ __forceinline__ uint32_t range_error(const SketchDesc &d, uint32_t xm
     return e;
 }
 
+// The code planes of the first cg groups of a finished LDS signature: one lane
+// per bin, one ballot per code bit gives the plane words of 32 bins (the low
+// and high halves: two groups of k' <= 32, or both words of one group of up
+// to 64 bins); lane 0 stores each group's PW words.  Bins past k' are 0.
+__device__ __forceinline__ void sketch_code_planes(const uint32_t *sig, const CodeSink &cs, uint64_t set,
+                                                   uint32_t lane) {
+    const uint64_t row = cs.first + set;
+    const uint64_t tile_off = (row >> 6) * 64 + (row & 63);
+    const uint32_t kp = cs.kp;
+    if (kp <= 32) {
+        for (uint32_t g0 = 0; g0 < cs.cg; g0 += 2) {
+            const uint32_t g = g0 + (lane >> 5), i = lane & 31;
+            const bool in = g < cs.cg && i < kp;
+            const uint32_t c = in ? bin_code(sig[g * kp + i]) : 0u;
+            uint32_t lo[kCodeBits], hi[kCodeBits];
+#pragma unroll
+            for (int p = 0; p < (int)kCodeBits; ++p) {
+                const uint64_t m = __ballot((c >> p) & 1u);
+                lo[p] = (uint32_t)m;
+                hi[p] = (uint32_t)(m >> 32);
+            }
+            if (lane == 0) {
+                uint4 *d0 = reinterpret_cast<uint4 *>(cs.codes + ((uint64_t)g0 * cs.ctiles * 64 + tile_off) * 8);
+                d0[0] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+                d0[1] = make_uint4(lo[4], lo[5], lo[6], lo[7]);
+                if (g0 + 1 < cs.cg) {
+                    uint4 *d1 =
+                        reinterpret_cast<uint4 *>(cs.codes + ((uint64_t)(g0 + 1) * cs.ctiles * 64 + tile_off) * 8);
+                    d1[0] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+                    d1[1] = make_uint4(hi[4], hi[5], hi[6], hi[7]);
+                }
+            }
+        }
+    } else {
+        for (uint32_t g = 0; g < cs.cg; ++g) {
+            const bool in = lane < kp;
+            const uint32_t c = in ? bin_code(sig[g * kp + lane]) : 0u;
+            uint32_t pl[2 * kCodeBits];
+#pragma unroll
+            for (int p = 0; p < (int)kCodeBits; ++p) {
+                const uint64_t m = __ballot((c >> p) & 1u);
+                pl[2 * p] = (uint32_t)m;
+                pl[2 * p + 1] = (uint32_t)(m >> 32);
+            }
+            if (lane == 0) {
+                uint4 *d = reinterpret_cast<uint4 *>(cs.codes + ((uint64_t)g * cs.ctiles * 64 + tile_off) * 16);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) d[j] = make_uint4(pl[4 * j], pl[4 * j + 1], pl[4 * j + 2], pl[4 * j + 3]);
+            }
+        }
+    }
+}
+
 // Orders one wavefront's LDS accesses (the signature is private to the wavefront).
 __device__ __forceinline__ void wave_lds_fence() {
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -294,10 +347,11 @@ __device__ __forceinline__ void sketch_range(const SketchDesc &d, const Tables<H
     }
 }
 
-template <uint32_t HASH, int LOC>
+template <uint32_t HASH, int LOC, bool CODES>
 __global__ __launch_bounds__(256) void sketch_kernel(SketchDesc d, const uint32_t *__restrict__ ids,
                                                      const uint64_t *__restrict__ offsets, uint64_t n_sets,
-                                                     uint32_t *__restrict__ sigs, uint32_t *__restrict__ err_flag) {
+                                                     uint32_t *__restrict__ sigs, uint32_t *__restrict__ err_flag,
+                                                     const CodeSink cs) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t k = d.k;
     const uint32_t waves = blockDim.x >> 6;
@@ -343,6 +397,7 @@ __global__ __launch_bounds__(256) void sketch_kernel(SketchDesc d, const uint32_
         } else {
             for (uint32_t i = lane; i < k; i += 64) out[i] = sig[i];
         }
+        if constexpr (CODES) sketch_code_planes(sig, cs, set, lane);
         wave_lds_fence();
         lo = nlo;
         hi = nhi;
@@ -487,7 +542,7 @@ hipError_t allow_lds(K kern, size_t lds) {
 
 template <uint32_t HASH, int LOC>
 hipError_t launch_t(const SketchDesc &d, const uint32_t *ids, const uint64_t *offsets, uint64_t n_sets,
-                    uint32_t *sigs, uint32_t *err_flag, hipStream_t st) {
+                    uint32_t *sigs, uint32_t *err_flag, hipStream_t st, const CodeSink &cs) {
     uint32_t waves;
     size_t lds;
     sketch_shape<HASH, LOC>(d, waves, lds);
@@ -495,11 +550,11 @@ hipError_t launch_t(const SketchDesc &d, const uint32_t *ids, const uint64_t *of
     uint64_t grid = (n_sets + waves - 1) / waves;
     if (grid > want_waves / waves) grid = want_waves / waves;
     if (grid == 0) grid = 1;
-    auto kern = sketch_kernel<HASH, LOC>;
+    auto kern = cs.codes ? sketch_kernel<HASH, LOC, true> : sketch_kernel<HASH, LOC, false>;
     hipError_t e = allow_lds(kern, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(64 * waves), lds, st, d, ids, offsets, n_sets, sigs,
-                       err_flag);
+                       err_flag, cs);
     return hipGetLastError();
 }
 
@@ -546,10 +601,12 @@ hipError_t launch_sketch_chunked(const SketchDesc &d, const uint32_t *ids, const
 }
 
 hipError_t launch_sketch(const SketchDesc &d, const uint32_t *ids, const uint64_t *offsets, uint64_t n_sets,
-                         uint32_t *sigs, uint32_t *err_flag, hipStream_t st) {
+                         uint32_t *sigs, uint32_t *err_flag, hipStream_t st, const CodeSink &cs) {
     if (n_sets == 0) return hipSuccess;
+    if (cs.codes && (cs.cg == 0 || cs.kp == 0 || cs.kp > 64 || (uint64_t)cs.cg * cs.kp > d.k))
+        return hipErrorInvalidValue;
     const bool est = d.est_ok != 0;
-#define HOPH_SK(H, LOC) launch_t<H, LOC>(d, ids, offsets, n_sets, sigs, err_flag, st)
+#define HOPH_SK(H, LOC) launch_t<H, LOC>(d, ids, offsets, n_sets, sigs, err_flag, st, cs)
     switch (d.hash) {
     case HOPH_HASH_TABLE: return est ? HOPH_SK(HOPH_HASH_TABLE, LOC_EST) : HOPH_SK(HOPH_HASH_TABLE, LOC_REGION);
     case HOPH_HASH_MODP31:
