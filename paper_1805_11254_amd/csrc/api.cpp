@@ -67,7 +67,7 @@ hoph_status check_results(const hoph_results *r, uint32_t n_q) {
 uint32_t pick_q_per_wave(uint64_t n_sets, uint32_t n_q, uint32_t tiles_per_wave) {
     const uint64_t per_wave = 64ull * std::max<uint32_t>(1, tiles_per_wave);
     const uint64_t ntiles = std::max<uint64_t>(1, (n_sets + per_wave - 1) / per_wave);
-    uint64_t want_chunks = (8192 + ntiles - 1) / ntiles;
+    uint64_t want_chunks = (4 * 8192ull + ntiles - 1) / ntiles;   // about four rounds of items
     if (want_chunks > n_q) want_chunks = n_q;
     if (want_chunks == 0) want_chunks = 1;
     return (uint32_t)((n_q + want_chunks - 1) / want_chunks);

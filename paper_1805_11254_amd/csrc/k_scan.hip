@@ -415,8 +415,9 @@ __global__ __launch_bounds__(64) void scan_codes_deep_kernel(const uint32_t *__r
 // there differ in the full code too, so when no lane's partial count is below
 // the threshold the query is done with these tiles (the usual case for pairs
 // far from the threshold), and otherwise the remaining planes continue each
-// tile's chain.
-template <int W, int TPW, int P1>
+// tile's chain.  TRI: the self-join's upper-triangle filter.  Lane sets are
+// combined as 64-bit wave masks (one ballot per tile and test).
+template <int W, int TPW, int P1, bool TRI>
 __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_t *__restrict__ codes,
                                                                   const uint32_t *__restrict__ qcodes,
                                                                   Survivor *__restrict__ surv,
@@ -440,15 +441,15 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_
         const uint32_t qa = q_lo + chunk * a.q_per_wave;
         const uint32_t qb = min(q_hi, qa + a.q_per_wave);
         // self-join: skip (before any load) an item with no set id above its first query row
-        if (a.tri && (tg + 1) * TPW * 64 <= (uint64_t)qa + 1) continue;
+        if (TRI && (tg + 1) * TPW * 64 <= (uint64_t)qa + 1) continue;
         uint32_t P[TPW][PW];
-        bool valid[TPW];
+        uint64_t vmask[TPW];                 // lanes holding an indexed set, per tile
         uint32_t sid[TPW];
 #pragma unroll
         for (int t = 0; t < TPW; ++t) {
             const uint64_t tile = tg * TPW + t;
             const uint64_t s = tile * 64 + lane;
-            valid[t] = s < n_sets;
+            vmask[t] = __builtin_amdgcn_ballot_w64(s < n_sets);
             sid[t] = (uint32_t)s;
             if (tile < ntiles) {             // wave-uniform; tiles below ntiles exist (ntiles <= ctiles)
                 const uint4 *src = reinterpret_cast<const uint4 *>(codes + (tile * 64 + lane) * PW);
@@ -474,19 +475,22 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_
 // loads stay scalar)
 #define HOPH_CODE_QUERY_T(r, qq)                                                                   \
         {                                                                                          \
+            uint64_t lanes[TPW];                                                                   \
+            _Pragma("unroll") for (int t = 0; t < TPW; ++t)                                        \
+                lanes[t] = TRI ? vmask[t] & __builtin_amdgcn_ballot_w64(sid[t] > (qq)) : vmask[t]; \
             uint32_t dd[TPW][W];                                                                   \
             bool open = true;                                                                      \
             if constexpr (P1 > 0) {                                                                \
-                bool keep = false;                                                                 \
+                uint64_t keep = 0;                                                                 \
                 _Pragma("unroll") for (int t = 0; t < TPW; ++t) {                                  \
                     uint32_t dn = 0;                                                               \
                     _Pragma("unroll") for (int w = 0; w < W; ++w) {                                \
                         dd[t][w] = code_diff_part<W, 0, P1>(0u, P[t], r, w);                       \
                         dn += __popc(dd[t][w] & r[PW + w]);                                        \
                     }                                                                              \
-                    keep |= ((int32_t)dn < (int32_t)r[PW + 2]) & valid[t] & (!a.tri | (sid[t] > (qq)));  \
+                    keep |= __builtin_amdgcn_ballot_w64((int32_t)dn < (int32_t)r[PW + 2]) & lanes[t];  \
                 }                                                                                  \
-                open = __any(keep);                                                                \
+                open = keep != 0;                                                                  \
             }                                                                                      \
             if (open) {                                                                            \
                 _Pragma("unroll") for (int t = 0; t < TPW; ++t) {                                  \
@@ -497,10 +501,10 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_
                             : code_diff<W>(P[t], r, w);                                            \
                         dn += __popc(d & r[PW + w]);                                               \
                     }                                                                              \
-                    const bool survive = ((int32_t)dn < (int32_t)r[PW + 2]) & valid[t] &           \
-                                         (!a.tri | (sid[t] > (qq)));                                 \
-                    const uint64_t bal = __builtin_amdgcn_ballot_w64(survive);                     \
+                    const uint64_t bal =                                                           \
+                        __builtin_amdgcn_ballot_w64((int32_t)dn < (int32_t)r[PW + 2]) & lanes[t];   \
                     if (bal) {                                                                     \
+                        const bool survive = (bal >> lane) & 1ull;                                 \
                         uint64_t base = 0;                                                         \
                         if (lane == 0) base = atomicAdd(counters + 0, (unsigned long long)__popcll(bal));  \
                         base = __shfl(base, 0);                                                    \
@@ -867,15 +871,20 @@ void codes_launch(const ScanLaunch &l, const CoarseArgs &a, const ScanTab &tab, 
             // threshold (most of them) is settled by 2 planes when the threshold is
             // at most half the bins, by 4 when at most three quarters
             const int32_t thr = tab.dthr0[0], kp = (int32_t)l.kp;
-            if (2 * thr <= kp)
-                hipLaunchKernelGGL((scan_codes_fast_kernel<W, fast_tiles(W), 2>), dim3(blocks), dim3(kThreads), 0, st,
-                                   l.codes, l.qcodes, l.surv, cnt, l.desc, a);
-            else if (4 * thr <= 3 * kp)
-                hipLaunchKernelGGL((scan_codes_fast_kernel<W, fast_tiles(W), 4>), dim3(blocks), dim3(kThreads), 0, st,
-                                   l.codes, l.qcodes, l.surv, cnt, l.desc, a);
-            else
-                hipLaunchKernelGGL((scan_codes_fast_kernel<W, fast_tiles(W), 0>), dim3(blocks), dim3(kThreads), 0, st,
-                                   l.codes, l.qcodes, l.surv, cnt, l.desc, a);
+            const int split = 2 * thr <= kp ? 2 : (4 * thr <= 3 * kp ? 4 : 0);
+#define HOPH_FAST(P1, TRI)                                                                                     \
+    hipLaunchKernelGGL((scan_codes_fast_kernel<W, fast_tiles(W), P1, TRI>), dim3(blocks), dim3(kThreads), 0, st, \
+                       l.codes, l.qcodes, l.surv, cnt, l.desc, a)
+            if (l.tri) {
+                if (split == 2) HOPH_FAST(2, true);
+                else if (split == 4) HOPH_FAST(4, true);
+                else HOPH_FAST(0, true);
+            } else {
+                if (split == 2) HOPH_FAST(2, false);
+                else if (split == 4) HOPH_FAST(4, false);
+                else HOPH_FAST(0, false);
+            }
+#undef HOPH_FAST
         }
         break;
     case 2: HOPH_CODES(2); break;
