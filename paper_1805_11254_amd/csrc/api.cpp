@@ -81,15 +81,19 @@ hoph_status copy_counters(Workspace &ws, hipStream_t st) {
 }
 
 // Accepted keys -> per-query ascending CSR in the caller's buffers: counting,
-// scan, scatter and a per-query LDS sort; the global bitonic sort is used when
-// a query holds more than 4096 ids (the device reports it in counters[3]).
+// scan, scatter and a per-query LDS sort of up to seg_max ids, seg_max the
+// total's power of two up to 16384, so that below that total no query can
+// exceed it and no flag has to be read back; above it the device reports a
+// larger query in counters[3] and the global bitonic sort takes over.
 hoph_status write_output(Workspace &ws, uint64_t accepted, uint32_t n_q, hoph_results *res, hipStream_t s) {
     hoph_status st = ws.grow_seg((uint64_t)n_q + 1);
     if (st) return st;
+    uint32_t seg_max = 2;
+    while (seg_max < accepted && seg_max < 16384) seg_max <<= 1;
     HOPH_HIP(launch_segmented_output(ws.keys, ws.counters, ws.keys_cap, ws.qcount, nullptr, n_q, res->d_offsets,
-                                     ws.cursor, res->d_set_ids, res->capacity, ws.counters, n_q, accepted, s),
+                                     ws.cursor, res->d_set_ids, res->capacity, ws.counters, n_q, accepted, seg_max, s),
              "output launch");
-    if (accepted > 4096) {
+    if (accepted > seg_max) {
         HOPH_HIP(hipMemcpyAsync(ws.h_counters + 2, ws.counters + 2, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s),
                  "hipMemcpyAsync(flags)");
         HOPH_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
@@ -205,6 +209,7 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
         a.keys = ws.keys;
         a.keys_cap = ws.keys_cap;
         HOPH_HIP(launch_fill_u64(ws.counters, 2, 0, s), "fill counters");
+        bool fresh = false;                 // h_counters hold this attempt's device counters
         if (n_q && idx->n) {
             // one pass over the whole batch; on survivor overflow, redo in sub-batches
             auto pass = [&](uint32_t q0, uint32_t q1) -> hoph_status {
@@ -252,9 +257,11 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
                     q = q1;
                 }
             }
+            fresh = true;
         }
-        st = copy_counters(ws, s);
-        if (st) return st;
+        if (!fresh) {
+            ws.h_counters[0] = ws.h_counters[1] = 0;     // nothing was scanned
+        }
         accepted = ws.h_counters[1];
         if (accepted <= ws.keys_cap) break;
         if (accepted > res->capacity) break;      // reported below; no need to keep every key

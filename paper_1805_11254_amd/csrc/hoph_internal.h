@@ -422,11 +422,13 @@ hipError_t launch_pair_estimates(const uint32_t *slab, uint64_t n_sets, uint32_t
                                  double *var, const ScanTab &tab, hipStream_t st);
 hipError_t launch_sort_keys(uint64_t *keys, uint64_t n, uint64_t n_pow2, hipStream_t st);
 // counters: [1] accepted keys (read), [2] total written, [3] flags (bit 0: a query
-// has more than 4096 ids, bit 1: total > out_cap).  desc (nullable): desc[0] = n_q.
+// has more than seg_max ids, bit 1: total > out_cap).  desc (nullable): desc[0] =
+// n_q.  seg_max: ids per query sorted in LDS, a power of two in [2, 16384].
+constexpr uint32_t kSegMaxPlan = 4096;
 hipError_t launch_segmented_output(const uint64_t *keys, const uint64_t *counters_ro, uint64_t keys_cap,
                                    uint32_t *qcount, const uint64_t *desc, uint32_t n_q, uint64_t *offsets,
                                    uint64_t *cursor, uint32_t *ids, uint64_t out_cap, uint64_t *counters,
-                                   uint32_t max_queries, uint64_t max_keys, hipStream_t st);
+                                   uint32_t max_queries, uint64_t max_keys, uint32_t seg_max, hipStream_t st);
 hipError_t launch_results(const uint64_t *keys, uint64_t n, uint32_t n_q, uint64_t *offsets,
                           uint32_t *set_ids, hipStream_t st);
 hipError_t launch_minwise_sketch(uint32_t k, uint32_t hash, uint64_t universe, const uint64_t *ha,

@@ -119,15 +119,16 @@ hipError_t launch_results(const uint64_t *keys, uint64_t n, uint32_t n_q, uint64
 // Per-query output without a global sort (usable with no host
 // synchronisation, e.g. inside a captured graph): count the accepted keys of
 // every query, scan the counts into CSR offsets, scatter the set ids, then sort
-// each query's ids in LDS.  A query with more than kSegMax ids, or a total above
-// the output capacity, raises a flag so the caller can take the global-sort
-// path instead.
+// each query's ids in LDS (at most seg_max <= kSegMaxLimit ids per query, a
+// power of two chosen by the caller).  A query with more than seg_max ids, or a
+// total above the output capacity, raises a flag so the caller can take the
+// global-sort path instead.
 // ---------------------------------------------------------------------------
 namespace hoph {
 
 namespace {
 
-constexpr uint32_t kSegMax = 4096;
+constexpr uint32_t kSegMaxLimit = 16384;   // 64 KB of LDS
 constexpr int kScanThreads = 1024;
 
 __device__ __forceinline__ uint64_t count_of(const uint64_t *counters, uint64_t cap) {
@@ -148,13 +149,13 @@ __global__ __launch_bounds__(kThreads) void seg_count_kernel(const uint64_t *__r
 }
 
 // One workgroup: exclusive scan of qcount[0..n_q) into offsets[0..n_q] and
-// cursor[0..n_q); flags bit 0: a query has more than kSegMax ids; bit 1: the
+// cursor[0..n_q); flags bit 0: a query has more than seg_max ids; bit 1: the
 // total exceeds out_cap.  counters[2] receives the total.
 __global__ __launch_bounds__(kScanThreads) void seg_scan_kernel(const uint32_t *__restrict__ qcount,
                                                                const uint64_t *__restrict__ desc, uint32_t n_q_arg,
                                                                uint64_t *__restrict__ offsets,
                                                                uint64_t *__restrict__ cursor, uint64_t out_cap,
-                                                               uint64_t *__restrict__ counters) {
+                                                               uint64_t *__restrict__ counters, uint32_t seg_max) {
     __shared__ uint64_t s_part[kScanThreads];
     __shared__ uint64_t s_carry;
     __shared__ uint32_t s_big;
@@ -165,7 +166,7 @@ __global__ __launch_bounds__(kScanThreads) void seg_scan_kernel(const uint32_t *
     for (uint32_t base = 0; base < n_q; base += kScanThreads) {
         const uint32_t q = base + t;
         const uint64_t v = q < n_q ? qcount[q] : 0;
-        if (v > kSegMax) atomicOr(&s_big, 1u);
+        if (v > seg_max) atomicOr(&s_big, 1u);
         s_part[t] = v;
         __syncthreads();
         for (uint32_t d = 1; d < kScanThreads; d <<= 1) {     // inclusive Hillis-Steele scan
@@ -205,13 +206,14 @@ __global__ __launch_bounds__(kThreads) void seg_scatter_kernel(const uint64_t *_
 // One workgroup per query (grid-stride): bitonic sort of the query's ids in LDS.
 __global__ __launch_bounds__(kThreads) void seg_sort_kernel(const uint64_t *__restrict__ offsets,
                                                            const uint64_t *__restrict__ desc, uint32_t n_q_arg,
-                                                           uint32_t *__restrict__ ids, uint64_t out_cap) {
-    __shared__ uint32_t s[kSegMax];
+                                                           uint32_t *__restrict__ ids, uint64_t out_cap,
+                                                           uint32_t seg_max) {
+    extern __shared__ uint32_t s[];          // seg_max words
     const uint32_t n_q = nq_of(desc, n_q_arg);
     for (uint32_t q = blockIdx.x; q < n_q; q += gridDim.x) {
         const uint64_t lo = offsets[q], hi = offsets[q + 1];
         const uint64_t len = hi - lo;
-        if (len <= 1 || len > kSegMax || hi > out_cap) continue;     // uniform per workgroup
+        if (len <= 1 || len > seg_max || hi > out_cap) continue;     // uniform per workgroup
         uint32_t N = 2;
         while (N < len) N <<= 1;
         for (uint32_t i = threadIdx.x; i < N; i += kThreads) s[i] = i < len ? ids[lo + i] : 0xFFFFFFFFu;
@@ -240,18 +242,20 @@ __global__ __launch_bounds__(kThreads) void seg_sort_kernel(const uint64_t *__re
 hipError_t launch_segmented_output(const uint64_t *keys, const uint64_t *counters_ro, uint64_t keys_cap,
                                    uint32_t *qcount, const uint64_t *desc, uint32_t n_q, uint64_t *offsets,
                                    uint64_t *cursor, uint32_t *ids, uint64_t out_cap, uint64_t *counters,
-                                   uint32_t max_queries, uint64_t max_keys, hipStream_t st) {
+                                   uint32_t max_queries, uint64_t max_keys, uint32_t seg_max, hipStream_t st) {
+    if (seg_max < 2 || seg_max > kSegMaxLimit || (seg_max & (seg_max - 1))) return hipErrorInvalidValue;
     // counts
     const uint64_t nqc = (uint64_t)max_queries + 1;
     hipLaunchKernelGGL(fill_u32_kernel_for_seg, dim3(grid_for(nqc)), dim3(kThreads), 0, st, qcount, nqc);
     hipLaunchKernelGGL(seg_count_kernel, dim3(grid_for(max_keys)), dim3(kThreads), 0, st, keys, counters_ro, keys_cap,
                        qcount);
     hipLaunchKernelGGL(seg_scan_kernel, dim3(1), dim3(kScanThreads), 0, st, qcount, desc, n_q, offsets, cursor, out_cap,
-                       counters);
+                       counters, seg_max);
     hipLaunchKernelGGL(seg_scatter_kernel, dim3(grid_for(max_keys)), dim3(kThreads), 0, st, keys, counters_ro, keys_cap,
                        reinterpret_cast<unsigned long long *>(cursor), ids, out_cap);
     uint32_t blocks = max_queries < 4096 ? (max_queries ? max_queries : 1) : 4096;
-    hipLaunchKernelGGL(seg_sort_kernel, dim3(blocks), dim3(kThreads), 0, st, offsets, desc, n_q, ids, out_cap);
+    hipLaunchKernelGGL(seg_sort_kernel, dim3(blocks), dim3(kThreads), (size_t)seg_max * 4, st, offsets, desc, n_q, ids,
+                       out_cap, seg_max);
     return hipGetLastError();
 }
 

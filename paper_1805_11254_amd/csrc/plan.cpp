@@ -183,7 +183,7 @@ hoph_status enqueue_scan(hoph_plan *p, const PlanShape &s, hipStream_t st, bool 
 hoph_status enqueue_output(hoph_plan *p, hipStream_t st) {
     HOPH_HIP(launch_segmented_output(p->keys, p->counters, p->keys_cap, p->qcount, p->desc, p->cfg.max_queries,
                                      p->out_offsets, p->cursor, p->out_ids, p->cfg.max_results, p->counters,
-                                     p->cfg.max_queries, p->keys_cap, st),
+                                     p->cfg.max_queries, p->keys_cap, kSegMaxPlan, st),
              "output launch");
     return HOPH_OK;
 }

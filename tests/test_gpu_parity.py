@@ -621,3 +621,30 @@ def test_deep_code_pass_matches_oracle(k, kp):
             assert po.cpu().numpy().tolist() == oo.tolist() and to_u32(pi).tolist() == oi.tolist(), (use_graph, rep)
         plan.free()
     idx.free()
+
+
+@pytest.mark.parametrize("n_sets", [9_000, 20_000])
+def test_queries_with_thousands_of_results_match_oracle(n_sets):
+    """Near-identical collections: each query accepts thousands of sets, sorted
+    in LDS per query up to 16384 ids, by the global sort beyond."""
+    _print_case(f"big segments n={n_sets}")
+    rng = np.random.default_rng(n_sets)
+    base = rng.choice(1 << 20, size=200, replace=False)
+    sets = []
+    for _ in range(n_sets):
+        s = base.copy()
+        s[rng.integers(0, 200, size=3)] = rng.integers(0, 1 << 20, size=3)
+        sets.append(s)
+    coll = W.csr_from_lists(sets)
+    w = W.Workload("same", coll, coll, 1 << 20, W.HASH_MODP31, W.LAYOUT_HIER, 256, 32, ha=1234567, hb=89)
+    p = params_of(w)
+    sig = gpu_sketch(w, coll, p)
+    sh = to_u32(sig)
+    idx = H.Index(p, sig)
+    qsig = sig[[0, 1, n_sets - 1]].contiguous()
+    qh = to_u32(qsig)
+    oo, oi = oracle_query(w, sh, qh, w.T, w.eps, H.EMPTY_JOINT)
+    assert max(np.diff(oo)) > (4096 if n_sets < 16384 else 16384)
+    go, gi = gpu_query("hoph", idx, qsig, w.T, w.eps, H.EMPTY_JOINT)
+    assert go.tolist() == oo.tolist() and gi.tolist() == oi.tolist()
+    idx.free()
