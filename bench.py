@@ -672,6 +672,36 @@ def main():
         two.append((e0.elapsed_time(e1), e1.elapsed_time(e2)))
     two_sketch_ms = sum(t[0] for t in two) / len(two)
     index_ms = sum(t[1] for t in two) / len(two)
+
+    # the HBM rate a plain device copy reaches here (2 GiB, same stream): the
+    # practical ceiling the sketch's rate is also compared with
+    cbuf = torch.empty(1 << 29, dtype=torch.int32, device=dev)
+    cdst = torch.empty_like(cbuf)
+    cdst.copy_(cbuf)
+    e0.record(stream)
+    for _ in range(5):
+        cdst.copy_(cbuf)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * cbuf.numel() * 4 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del cbuf, cdst
+    # the sketch with the sets handed over in pinned host memory: host-to-device
+    # copy of ids and offsets, then the sketch (the resident copies are overwritten
+    # with the same contents)
+    ids_pin = torch.from_numpy(w.collection.ids.view(np.int32)).pin_memory()
+    offs_pin = torch.from_numpy(w.collection.offsets.view(np.int64)).pin_memory()
+    h2d = []
+    for _ in range(2):
+        e0.record(stream)
+        ids.copy_(ids_pin, non_blocking=True)
+        offs.copy_(offs_pin, non_blocking=True)
+        e1.record(stream)
+        H.sketch_oph(p, ids, offs, out=sig)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        h2d.append((e0.elapsed_time(e1), e0.elapsed_time(e2)))
+    h2d_copy_ms, h2d_total_ms = min(h[0] for h in h2d), min(h[1] for h in h2d)
+    del ids_pin, offs_pin
     coarse_ms = sum(q[0] for q in qms) / len(qms)
     fine_ms = sum(q[1] for q in qms) / len(qms)
     sort_ms = sum(q[2] for q in qms) / len(qms)
@@ -780,6 +810,10 @@ def main():
                    "k": k, "k_group": kp, "groups": k // kp, "ratio": "1:1", "hash": "(a x + b) mod (2^31 - 1)",
                    "T": "4/5", "eps": "1/10000", "empty_policy": "joint", "parallelism": "single GPU"},
         "sets_sketched_per_s": N / (sketch_ms * 1e-3),
+        "sets_sketched_per_s_with_h2d": N / (h2d_total_ms * 1e-3),
+        "h2d_gbs": (nnz * 4 + (N + 1) * 8) / (h2d_copy_ms * 1e-3) / 1e9,
+        "copy_ceiling_gbs": copy_gbs,
+        "sketch_frac_of_copy": kernels["sketch_into_index"]["achieved"] / copy_gbs,
         "scan_pairs_per_s": N * Q / (query_ms * 1e-3),
         "scan_hbm_frac": kernels["scan_coarse"]["hbm_gbs"] / HBM_PEAK_GBS,
         "served_p99_ms": None,
