@@ -201,6 +201,59 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
     a.qcodes = ws.qcodes;
     a.cg = idx->cg;
 
+    // one pass over queries [q0, q1) (coarse, then per-survivor), events ev[0..2]
+    auto pass = [&](uint32_t q0, uint32_t q1) -> hoph_status {
+        a.q0 = q0;
+        a.q1 = q1;
+        a.q_per_wave = pick_q_per_wave(idx->n, q1 - q0, coarse_tiles_per_wave(a, tab.policy));
+        HOPH_HIP(hipEventRecord(ws.ev[0], s), "hipEventRecord");
+        if (kind == QueryKind::OPH_FULL) {
+            HOPH_HIP(launch_oph_full(a, qp->T, qp->empty_policy, s), "oph_full launch");
+            HOPH_HIP(hipEventRecord(ws.ev[1], s), "hipEventRecord");
+        } else {
+            HOPH_HIP(launch_scan_coarse(a, tab, s), "coarse scan launch");
+            HOPH_HIP(hipEventRecord(ws.ev[1], s), "hipEventRecord");
+            HOPH_HIP(launch_scan_fine(a, tab, s), "fine scan launch");
+        }
+        HOPH_HIP(hipEventRecord(ws.ev[2], s), "hipEventRecord");
+        return HOPH_OK;
+    };
+    auto record_timing = [&]() {
+        (void)hipEventElapsedTime(&ws.last_ms[0], ws.ev[0], ws.ev[1]);
+        (void)hipEventElapsedTime(&ws.last_ms[1], ws.ev[1], ws.ev[2]);
+        (void)hipEventElapsedTime(&ws.last_ms[2], ws.ev[2], ws.ev[3]);
+    };
+
+    if (n_q && idx->n) {
+        // Optimistic path, one read-back: the pass and the output stage (which takes
+        // its counts from the device) back to back, then the counters and flags.  It
+        // stands when no buffer overflowed and no query holds more ids than the
+        // per-query sort takes; otherwise the careful path below redoes the query.
+        st = ws.grow_seg((uint64_t)n_q + 1);
+        if (st) return st;
+        a.surv = ws.surv;
+        a.surv_cap = ws.surv_cap;
+        a.keys = ws.keys;
+        a.keys_cap = ws.keys_cap;
+        HOPH_HIP(launch_fill_u64(ws.counters, 4, 0, s), "fill counters");
+        st = pass(0, n_q);
+        if (st) return st;
+        HOPH_HIP(launch_segmented_output(ws.keys, ws.counters, ws.keys_cap, ws.qcount, nullptr, n_q, res->d_offsets,
+                                         ws.cursor, res->d_set_ids, res->capacity, ws.counters, n_q, ws.keys_cap,
+                                         kSegMaxPlan, s),
+                 "output launch");
+        HOPH_HIP(hipEventRecord(ws.ev[3], s), "hipEventRecord");
+        HOPH_HIP(hipMemcpyAsync(ws.h_counters, ws.counters, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, s),
+                 "hipMemcpyAsync(counters)");
+        HOPH_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+        const uint64_t surv = ws.h_counters[0], acc = ws.h_counters[1], flags = ws.h_counters[3];
+        if (surv <= ws.surv_cap && acc <= ws.keys_cap && acc <= res->capacity && (flags & 3ull) == 0) {
+            res->needed = acc;
+            record_timing();
+            return HOPH_OK;
+        }
+    }
+
     uint64_t accepted = 0;
     float pass_ms[2] = {0, 0};
     for (int attempt = 0; attempt < 2; ++attempt) {
@@ -212,22 +265,6 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
         bool fresh = false;                 // h_counters hold this attempt's device counters
         if (n_q && idx->n) {
             // one pass over the whole batch; on survivor overflow, redo in sub-batches
-            auto pass = [&](uint32_t q0, uint32_t q1) -> hoph_status {
-                a.q0 = q0;
-                a.q1 = q1;
-                a.q_per_wave = pick_q_per_wave(idx->n, q1 - q0, coarse_tiles_per_wave(a, tab.policy));
-                HOPH_HIP(hipEventRecord(ws.ev[0], s), "hipEventRecord");
-                if (kind == QueryKind::OPH_FULL) {
-                    HOPH_HIP(launch_oph_full(a, qp->T, qp->empty_policy, s), "oph_full launch");
-                    HOPH_HIP(hipEventRecord(ws.ev[1], s), "hipEventRecord");
-                } else {
-                    HOPH_HIP(launch_scan_coarse(a, tab, s), "coarse scan launch");
-                    HOPH_HIP(hipEventRecord(ws.ev[1], s), "hipEventRecord");
-                    HOPH_HIP(launch_scan_fine(a, tab, s), "fine scan launch");
-                }
-                HOPH_HIP(hipEventRecord(ws.ev[2], s), "hipEventRecord");
-                return HOPH_OK;
-            };
             st = pass(0, n_q);
             if (st) return st;
             st = copy_counters(ws, s);
