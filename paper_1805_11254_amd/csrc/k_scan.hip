@@ -25,6 +25,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
+constexpr int kFineAhead = 4;          // groups read ahead per survivor in the fine pass
 // tiles of 64 sets per wavefront in the first-group code pass, by words per plane
 constexpr int fast_tiles(int W) { return W == 1 ? 4 : 2; }
 
@@ -671,20 +672,33 @@ __global__ __launch_bounds__(kThreads) void scan_fine_kernel(const uint32_t *__r
         const uint64_t s = sv.s;
         const uint32_t *qw = qsigs + (uint64_t)sv.q * a.k;
         const uint32_t *sb = slab + s * a.k + lane;
-        for (uint32_t g = a.depth; g < a.L; ++g) {
-            uint32_t sw = 0, qv = 0;
-            if (in) {
-                sw = sb[g * kp];
-                qv = qw[g * kp + lane];
+        // kFineAhead groups are read at once (independent loads in flight), then
+        // decided in order; reads past the deciding group are discarded
+        bool done = false;
+        for (uint32_t g0 = a.depth; g0 < a.L && !done; g0 += kFineAhead) {
+            uint32_t sw[kFineAhead], qv[kFineAhead];
+#pragma unroll
+            for (int c = 0; c < kFineAhead; ++c) {
+                const uint32_t g = g0 + c;
+                sw[c] = qv[c] = 0;
+                if (in && g < a.L) {
+                    sw[c] = sb[g * kp];
+                    qv[c] = qw[g * kp + lane];
+                }
             }
-            const uint64_t eqb = __ballot(in && sw == qv);
-            const uint64_t qe = __ballot(in && qv == HOPH_EMPTY);
-            const uint64_t se = __ballot(in && sw == HOPH_EMPTY);
-            const uint32_t ej = __popcll(qe & se), ee = __popcll(qe | se);
-            const uint32_t eq = __popcll(eqb);
-            S += tab.W[g] * group_rho(eq, ej, ee, kp, a.policy, s_dmul, tab.lambda);
-            if (S >= tab.acc[g]) { accept = true; break; }
-            if (S <= tab.rej[g]) break;
+#pragma unroll
+            for (int c = 0; c < kFineAhead; ++c) {
+                const uint32_t g = g0 + c;
+                if (g >= a.L) break;
+                const uint64_t eqb = __ballot(in && sw[c] == qv[c]);
+                const uint64_t qe = __ballot(in && qv[c] == HOPH_EMPTY);
+                const uint64_t se = __ballot(in && sw[c] == HOPH_EMPTY);
+                const uint32_t ej = __popcll(qe & se), ee = __popcll(qe | se);
+                const uint32_t eq = __popcll(eqb);
+                S += tab.W[g] * group_rho(eq, ej, ee, kp, a.policy, s_dmul, tab.lambda);
+                if (S >= tab.acc[g]) { accept = true; done = true; break; }
+                if (S <= tab.rej[g]) { done = true; break; }
+            }
         }
         if (accept && lane == 0) {
             const uint64_t slot = atomicAdd(counters + 1, 1ull);
