@@ -1,7 +1,8 @@
 """Parity at full workload sizes, in the launch configuration bench.py times:
 every signature of the 1,000,000-set bag-of-visual-words collection against the
 oracle, and the candidate lists of a sample of queries (the GPU answers all
-1,024, the oracle the sample); the 500,000-set shingle collection (one GPU's
+1,024, the oracle the sample); the self-join of that collection with its
+queries in front (sampled rows, every j > i); the 500,000-set shingle collection (one GPU's
 share of the 4,000,000-set workload over eight) with (1:2) HOPH, and sampled
 MinWise signatures."""
 from fractions import Fraction
@@ -51,6 +52,44 @@ def test_bovw_1M_full_signatures_and_sampled_queries():
     assert bad.size == 0, f"{bad.size} signatures differ, first sets {bad[:5].tolist()}"
     assert (oracle_sketch(w, w.queries) == qsig_h).all()
     _check_queries(w, osig, qsig_h, go, gi, _sample_queries(w.queries.n, 14, 1))
+    idx.free()
+
+
+def test_bovw_1M_self_join_sampled_rows():
+    """Self-join of the bench's self-join collection (the 1,024 query sets in
+    front of the 1,000,000 sets: 1,001,024 rows, 5·10^11 pairs), in the launch
+    configuration bench.py times: every signature against the oracle, and for
+    sampled rows i (query rows with planted copies among them) the full list
+    of accepted j > i against the oracle's decisions over all j."""
+    print("[case] bovw 1M self-join", flush=True)
+    w = W.hoph_bovw()
+    q, c = w.queries, w.collection
+    coll = W.Collection(np.concatenate([q.ids, c.ids]).astype(np.uint32),
+                        np.concatenate([q.offsets, c.offsets[1:] + q.offsets[-1]]).astype(np.uint64))
+    n = coll.n
+    p = params_of(w)
+    ids, offs = dev_csr(coll)
+    sig = H.sketch_oph(p, ids, offs)
+    H.sync()
+    idx = H.Index(p, sig)
+    go, gi = H.self_join(idx, T=w.T, eps=w.eps)
+    go, gi = go.cpu().numpy(), to_u32(gi)
+    sig_h = to_u32(sig)
+    del sig, ids, offs
+    osig = oracle_sketch(w, coll)
+    assert (osig == sig_h).all()
+    rng = np.random.default_rng(5)
+    sample = sorted(set([0, 1, q.n - 1, q.n, n - 2, n - 1] + rng.choice(q.n, size=6, replace=False).tolist()
+                        + rng.choice(n, size=8, replace=False).tolist()))
+    oo, oi, _ = scale.query(osig, osig[sample], goph=w.goph, kp=w.kp, T=Fraction(*w.T), eps=Fraction(*w.eps),
+                            ra=w.ra, rb=w.rb)
+    planted_rows = 0
+    for j, i in enumerate(sample):
+        want = [x for x in oi[oo[j]:oo[j + 1]].tolist() if x > i]
+        got = gi[go[i]:go[i + 1]].tolist()
+        assert got == want, (i, len(got), len(want))
+        planted_rows += i < q.n and len(want) > 0
+    assert planted_rows > 0
     idx.free()
 
 
