@@ -205,7 +205,7 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
     auto pass = [&](uint32_t q0, uint32_t q1) -> hoph_status {
         a.q0 = q0;
         a.q1 = q1;
-        a.q_per_wave = pick_q_per_wave(idx->n, q1 - q0, coarse_tiles_per_wave(a, tab.policy));
+        a.q_per_wave = pick_q_per_wave(idx->n, q1 - q0, coarse_tiles_per_wave(a, tab));
         HOPH_HIP(hipEventRecord(ws.ev[0], s), "hipEventRecord");
         if (kind == QueryKind::OPH_FULL) {
             HOPH_HIP(launch_oph_full(a, qp->T, qp->empty_policy, s), "oph_full launch");

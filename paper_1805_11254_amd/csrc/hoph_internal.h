@@ -413,7 +413,7 @@ hipError_t launch_query_masks(const uint32_t *qsigs, uint32_t n_q, const uint64_
                               hipStream_t st);
 hipError_t launch_scan_coarse(const ScanLaunch &a, const ScanTab &tab, hipStream_t st);
 // Tiles of 64 sets one wavefront of the coarse pass holds for this launch.
-uint32_t coarse_tiles_per_wave(const ScanLaunch &a, uint32_t policy);
+uint32_t coarse_tiles_per_wave(const ScanLaunch &a, const ScanTab &tab);
 hipError_t launch_scan_fine(const ScanLaunch &a, const ScanTab &tab, hipStream_t st);
 hipError_t launch_oph_full(const ScanLaunch &a, hoph_ratio T, uint32_t policy, hipStream_t st);
 hipError_t launch_pair_estimates(const uint32_t *slab, uint64_t n_sets, uint32_t k, uint32_t kp, uint32_t L,

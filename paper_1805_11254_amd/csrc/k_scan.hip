@@ -27,7 +27,20 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kFineAhead = 4;          // groups read ahead per survivor in the fine pass
 // tiles of 64 sets per wavefront in the first-group code pass, by words per plane
-constexpr int fast_tiles(int W) { return W == 1 ? 4 : 2; }
+// Tiles of 64 sets per wavefront in the first-group code pass: eight for the
+// two-plane first phase over one plane word (its registers hold 8 planes of 8
+// tiles), else four (two with two plane words).
+constexpr int fast_tiles(int W, int P1) { return W == 1 ? (P1 == 2 ? 8 : 4) : 2; }
+
+// Planes compared first in the first-group code pass: a non-matching bin
+// differs in the first p planes with probability 1 - 2^-p under uniform codes,
+// so a pair far from the threshold (most of them) is settled by 2 planes when
+// the threshold on differing bins is at most half the bins, by 4 when at most
+// three quarters; 0: all 8 planes in one phase.
+int plane_split(const ScanTab &tab, uint32_t kp) {
+    const int32_t thr = tab.dthr0[0], k = (int32_t)kp;
+    return 2 * thr <= k ? 2 : (4 * thr <= 3 * k ? 4 : 0);
+}
 
 struct CoarseArgs {
     uint64_t capacity, n_sets, surv_cap, keys_cap;
@@ -880,14 +893,9 @@ void codes_launch(const ScanLaunch &l, const CoarseArgs &a, const ScanTab &tab, 
         if (tab.policy == HOPH_EMPTY_EITHER) {
             HOPH_CODES(1);
         } else {
-            // planes compared first: a non-matching bin differs in the first p planes
-            // with probability 1 - 2^-p under uniform codes, so a pair far from the
-            // threshold (most of them) is settled by 2 planes when the threshold is
-            // at most half the bins, by 4 when at most three quarters
-            const int32_t thr = tab.dthr0[0], kp = (int32_t)l.kp;
-            const int split = 2 * thr <= kp ? 2 : (4 * thr <= 3 * kp ? 4 : 0);
+            const int split = plane_split(tab, l.kp);
 #define HOPH_FAST(P1, TRI)                                                                                     \
-    hipLaunchKernelGGL((scan_codes_fast_kernel<W, fast_tiles(W), P1, TRI>), dim3(blocks), dim3(kThreads), 0, st, \
+    hipLaunchKernelGGL((scan_codes_fast_kernel<W, fast_tiles(W, P1), P1, TRI>), dim3(blocks), dim3(kThreads), 0, st, \
                        l.codes, l.qcodes, l.surv, cnt, l.desc, a)
             if (l.tri) {
                 if (split == 2) HOPH_FAST(2, true);
@@ -962,9 +970,10 @@ void oph_kp(const ScanLaunch &l, const CoarseArgs &a, hoph_ratio T, hipStream_t 
 
 }  // namespace
 
-uint32_t coarse_tiles_per_wave(const ScanLaunch &l, uint32_t policy) {
+uint32_t coarse_tiles_per_wave(const ScanLaunch &l, const ScanTab &tab) {
+    const uint32_t policy = tab.policy;
     if (!(l.codes && l.depth == 1 && policy != HOPH_EMPTY_EITHER)) return 1u;
-    return (uint32_t)(code_plane_words(l.kp) == 1 ? fast_tiles(1) : fast_tiles(2));
+    return (uint32_t)fast_tiles((int)code_plane_words(l.kp), plane_split(tab, l.kp));
 }
 
 uint32_t max_depth_for_kpad(uint32_t kpad) {
@@ -997,7 +1006,7 @@ hipError_t launch_scan_coarse(const ScanLaunch &l, const ScanTab &tab, hipStream
         const uint32_t nq = l.q1 - l.q0;
         if (ntiles == 0 || nq == 0) return hipSuccess;
         const uint64_t nchunks = (nq + l.q_per_wave - 1) / l.q_per_wave;
-        const uint32_t tpw = coarse_tiles_per_wave(l, tab.policy);
+        const uint32_t tpw = coarse_tiles_per_wave(l, tab);
         blocks = waves_to_blocks((ntiles + tpw - 1) / tpw * nchunks);
     }
     const CoarseArgs a = coarse_args(l, tab.policy);
