@@ -5,18 +5,20 @@
 // precomputed on the host as integer cutoffs on the state, so the device only
 // counts, multiplies, adds and compares integers.
 //
-// Coarse pass: one wavefront per (tile of 64 indexed sets, chunk of queries).
-// The tile's first G groups stay in VGPRs (one set per lane); the wavefront
-// index is made wave-uniform with readfirstlane so that every query word is a
-// scalar load, and a bin comparison is one VALU compare plus one add-with-carry.
-// With G = 1 (HOPH) the decision after the first group is a pair of thresholds
-// on the matched count; with G > 1 (GOPH) the exact 64-bit state is carried.
-// Pairs still undecided after G groups are appended to a survivor list with
-// one atomic per wavefront (ballot + rank).
+// Coarse pass: one wavefront per (tile(s) of 64 indexed sets, chunk of
+// queries), one set per lane, every query word a scalar load.  By default it
+// compares 8-bit bin codes held as bit-planes and only rejects
+// (scan_codes_fast_kernel for the first group, in two phases of planes;
+// scan_codes_kernel for 2-4 groups in VGPRs; scan_codes_deep_kernel past that,
+// later groups staged in LDS); on request it compares the 32-bit words and
+// accepts too (scan_coarse_kernel: with G = 1 the decision after the first
+// group is a pair of thresholds on the matched count, with G > 1 the exact
+// 64-bit state is carried).  Pairs not rejected are appended to a survivor
+// list with one atomic per wavefront (ballot + rank).
 //
-// Fine pass: one wavefront per survivor, one lane per bin; counts come from
-// ballots and popcounts, the decision is wave-uniform, and the wavefront
-// leaves at the first deciding group.
+// Fine pass: one wavefront per survivor, one lane per bin, groups read a few
+// at a time; counts come from ballots and popcounts, the decision is
+// wave-uniform, and the wavefront leaves at the first deciding group.
 #include "hoph_internal.h"
 
 namespace hoph {
@@ -26,7 +28,6 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kFineAhead = 4;          // groups read ahead per survivor in the fine pass
-// tiles of 64 sets per wavefront in the first-group code pass, by words per plane
 // Tiles of 64 sets per wavefront in the first-group code pass: eight for the
 // two-plane first phase over one plane word (its registers hold 8 planes of 8
 // tiles), else four (two with two plane words).

@@ -8,10 +8,13 @@
 // built once per workgroup in LDS; each wavefront owns a k-word LDS signature
 // updated with ds_min (the minimum is order-free, so the order of lanes does
 // not matter) and written back with 16-byte stores.  Element ids are read with
-// unconditional (clamped) coalesced loads, four per lane, and the next four
-// are in flight while the current ones are hashed and binned.  The element
-// path is straight-line code (out-of-range lanes are masked, only the LDS
-// minimum is predicated) so the loads of the four elements interleave.
+// unconditional (clamped) coalesced loads from one load site, four per lane;
+// the next four are in flight while the current ones are hashed and binned,
+// and a set's first ids are read during the previous set's last batch.  The
+// element path is straight-line code (out-of-range lanes are masked, only the
+// LDS minimum is predicated) so the loads of the four elements interleave.
+// An index append with no 16-byte code-plane row kernel (k' other than 16, 32,
+// 64) also writes the new rows' code planes from the LDS signature.
 //
 // Bin lookup: where regions and bins fall on powers of two (the 1:1 hierarchy
 // and power-of-two k over R = 2^31 - 1) one read of a 32-entry table indexed
