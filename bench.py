@@ -485,9 +485,11 @@ def bench_sweeps(args):
     near-duplicates at J in [0.5, 0.98]; defaults T = 0.7, eps = 1e-4.
     (1) GOPH group count n at k = 320 (n = 320/k' for k' in 40 ... 5);
     (2) error tolerance eps in 1e-2 ... 1e-6 for GOPH (n = 10) and HOPH (1:1,
-    k = 512 in groups of 32); (3) threshold T in 0.5 ... 0.9 for both.  Each
-    point: the batch's device time (coarse, per-survivor, sort), the scan's
-    pairs/s, and recall / precision against exact Jaccard similarity."""
+    k = 512 in groups of 32); (3) threshold T in 0.5 ... 0.9 for both; (4) the
+    paper's methods side by side: GOPH, HOPH 1:2 / 1:1 / 2:1, plain OPH and
+    MinWise.  Each point: the batch's device time (coarse, per-survivor, sort),
+    the scan's pairs/s, and recall / precision against exact Jaccard
+    similarity."""
     import numpy as np
     import torch
     import paper_1805_11254_amd as H
@@ -510,27 +512,31 @@ def bench_sweeps(args):
 
     planted = [(qi, s) for (qi, s, _) in w.planted]
 
-    def point(idx, qsig, goph, T, eps):
+    def point(idx, qsig, goph, T, eps, call=None, nq=None):
         fn = H.query_goph if goph else H.query_hoph
-        fn(idx, qsig, T=T, eps=eps)
+        call = call or (lambda: fn(idx, qsig, T=T, eps=eps))
+        call()
         torch.cuda.synchronize()
         ms, walls = [], []
         for _ in range(max(1, args.steps)):
             t0 = time.perf_counter()
-            o, i = fn(idx, qsig, T=T, eps=eps)
+            o, i = call()
+            torch.cuda.synchronize()
             walls.append((time.perf_counter() - t0) * 1e3)
-            ms.append(idx.last_query_ms())
-        dev_ms = [float(np.median([x[j] for x in ms])) for j in range(3)]
+            if idx is not None:
+                ms.append(idx.last_query_ms())
+        dev_ms = [float(np.median([x[j] for x in ms])) for j in range(3)] if ms else [float(np.median(walls)), 0.0, 0.0]
         got = _pairs_of(o.cpu().numpy(), i.cpu().numpy().view(np.uint32))
         t = T[0] / T[1]
-        truth = {pq for pq in planted if exact(*pq) >= t}
+        nq = Q if nq is None else nq
+        truth = {pq for pq in planted if exact(*pq) >= t and pq[0] < nq}
         tp = sum(exact(a, b) >= t for (a, b) in got)
         total = sum(dev_ms)
         # wall_ms: the whole host-synchronous call (sub-batches included, should the
         # survivors of one pass overflow their buffer; the device times cover the first pass)
         return {"T": list(T), "eps": list(eps), "wall_ms": float(np.median(walls)), "device_ms": total,
-                "coarse_ms": dev_ms[0],
-                "fine_ms": dev_ms[1], "sort_ms": dev_ms[2], "pairs_per_s": Q * N / (total * 1e-3),
+                "coarse_ms": dev_ms[0], "queries": nq,
+                "fine_ms": dev_ms[1], "sort_ms": dev_ms[2], "pairs_per_s": nq * N / (total * 1e-3),
                 "accepted": len(got), "recall": len(truth & got) / max(1, len(truth)),
                 "precision": tp / max(1, len(got))}
 
@@ -561,6 +567,32 @@ def bench_sweeps(args):
         out[f"{name}_eps"] = [point(idx, qs, goph, (7, 10), (1, e)) for e in (100, 1000, 10_000, 100_000, 1_000_000)]
         out[f"{name}_T"] = [point(idx, qs, goph, (t, 10), (1, 10000)) for t in (5, 6, 7, 8, 9)]
         log(f"{name}: eps and T sweeps done")
+    # (4) the paper's methods on the same data at the defaults: GOPH n = 10 (above),
+    # HOPH 1:2, 1:1, 2:1 and plain OPH over all bins at k = 256 in groups of 32 (ratios
+    # other than 1:1 need the smaller k for the exact 64-bit state), MinWise with 256
+    # hashes (host wall time per batch of 128 queries, its kernel has no device timer)
+    T7, e4 = (7, 10), (1, 10000)
+    meth = {"goph_n10_k320": out["goph10_T"][2]}
+    for ra, rb in ((1, 2), (1, 1), (2, 1)):
+        pr = H.SketchParams(W.LAYOUT_HIER, 256, 32, w.hash_kind, w.universe, ra, rb, w.ha, w.hb)
+        ix = H.Index(pr, H.sketch_oph(pr, ids, offs))
+        meth[f"hoph{ra}{rb}_k256"] = point(ix, H.sketch_oph(pr, qids, qoffs), False, T7, e4)
+        ix.free()
+    po = H.SketchParams(W.LAYOUT_OPH, 256, 32, w.hash_kind, w.universe, 1, 1, w.ha, w.hb)
+    ix = H.Index(po, H.sketch_oph(po, ids, offs))
+    oq = H.sketch_oph(po, qids, qoffs)
+    meth["oph_full_k256"] = point(ix, oq, True, T7, e4, call=lambda: H.query_oph_full(ix, oq, T=T7))
+    ix.free()
+    ha, hb = W.hash_coeffs(W.P31, 256, args.seed + 5)
+    mp = H.MinwiseParams(256, W.HASH_MODP31, w.universe, torch.from_numpy(ha.view(np.int64)).to(dev),
+                         torch.from_numpy(hb.view(np.int64)).to(dev))
+    msig = H.minwise_sketch(mp, ids, offs)
+    mq = H.minwise_sketch(mp, qids, qoffs)[:128].contiguous()
+    meth["minwise_k256_128q"] = point(None, None, False, T7, e4, nq=128,
+                                      call=lambda: H.minwise_query(mp, msig, mq, T=T7))
+    del msig, mq
+    out["methods"] = meth
+    log("methods done")
     goph10.free()
     hidx.free()
     out["value"] = out["hoph11_T"][2]["pairs_per_s"]
