@@ -110,8 +110,8 @@ hipError_t append_sets_async(hoph_index *idx, const uint32_t *d_ids, const uint6
     SketchDesc d;
     fill_sketch_desc(idx->params, idx->lay, d);
     hipError_t e = hipSuccess;
-    // code planes of the new rows: the row kernel where it reads a group as
-    // 16-byte loads, else the sketch writes them from its LDS signature (then
+    // code planes of the new rows: the row kernel where it reads a group with
+    // vector loads, else the sketch writes them from its LDS signature (then
     // aev[1]..aev[2] spans no work)
     const bool fused = idx->codes && !codes_have_row_kernel(idx->lay.k, idx->lay.kp);
     const CodeSink sink = fused ? CodeSink{idx->codes, first, idx->capacity / 64, idx->cg, idx->lay.kp} : CodeSink{};

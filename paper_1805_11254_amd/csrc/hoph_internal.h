@@ -367,11 +367,11 @@ hipError_t launch_sketch_chunked(const SketchDesc &d, const uint32_t *ids, const
                                  const uint64_t *desc, uint64_t *prefix, uint32_t chunk, uint32_t max_sets,
                                  uint64_t max_ids, uint32_t *sigs, uint32_t *err_flag, uint32_t waves_per_cu,
                                  hipStream_t st);
-// Code planes of index rows [first, first + n_new) from the rows themselves.
 // Whether the code planes of new rows have a row kernel reading each group as
-// 16-byte loads (k' = 16, 32, 64 with k a multiple of 4); otherwise the sketch
-// of an append writes them from its LDS signature.
+// 16- or 8-byte loads (k' and k even); otherwise a plain per-(set, group) kernel
+// writes them, and the sketch of an append writes them from its LDS signature.
 bool codes_have_row_kernel(uint32_t k, uint32_t kp);
+// Code planes of index rows [first, first + n_new) from the rows themselves.
 hipError_t launch_codes_from_slab(const uint32_t *slab, uint64_t capacity, uint32_t k, uint32_t kp, uint64_t first,
                                   uint64_t n_new, uint32_t *codes, uint32_t cg, hipStream_t st);
 // Copies signature rows into index rows [first, first + n_new) and, when codes

@@ -19,47 +19,76 @@ __global__ __launch_bounds__(kThreads) void fill_u64_kernel(uint64_t *p, uint64_
         p[i] = value;
 }
 
-// Code planes of NQ * 4 bins held as NQ uint4, written as PW contiguous words.
-template <int NQ>
-__device__ __forceinline__ void store_code_planes(const uint4 *v, uint32_t *__restrict__ dst) {
-    constexpr int W = NQ > 8 ? 2 : 1;
+// Code planes of the KP bins v[0..KP), written as PW contiguous words (bins
+// past KP in a plane word are 0).
+template <int KP>
+__device__ __forceinline__ void store_code_planes(const uint32_t (&v)[KP], uint32_t *__restrict__ dst) {
+    constexpr int W = KP > 32 ? 2 : 1;
     uint32_t pl[kCodeBits * W];
 #pragma unroll
     for (int j = 0; j < (int)kCodeBits * W; ++j) pl[j] = 0;
 #pragma unroll
-    for (int u = 0; u < NQ; ++u) {
-        const uint32_t vals[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+    for (int i = 0; i < KP; ++i) {
+        const uint32_t c = bin_code(v[i]);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int i = 4 * u + t;
-            const uint32_t c = bin_code(vals[t]);
-#pragma unroll
-            for (int p = 0; p < (int)kCodeBits; ++p) pl[p * W + (i >> 5)] |= ((c >> p) & 1u) << (i & 31);
-        }
+        for (int p = 0; p < (int)kCodeBits; ++p) pl[p * W + (i >> 5)] |= ((c >> p) & 1u) << (i & 31);
     }
     uint4 *d4 = reinterpret_cast<uint4 *>(dst);
 #pragma unroll
     for (int j = 0; j < 2 * W; ++j) d4[j] = make_uint4(pl[4 * j], pl[4 * j + 1], pl[4 * j + 2], pl[4 * j + 3]);
 }
 
-// Code planes for k' = 4 NQ with k a multiple of 4: one thread per (group < cg,
-// row), consecutive rows in consecutive lanes; a group of a row is read as NQ
-// 16-byte loads.  sigs row r is index row first + r.
-template <int NQ>
+// Code planes for an even k' = KP with k even: one thread per (group < cg,
+// row), consecutive rows in consecutive lanes; a group of a row is read as
+// 16-byte loads (QUAD: KP and k multiples of 4) or 8-byte loads.  sigs row r
+// is index row first + r.
+template <int KP, bool QUAD>
 __global__ __launch_bounds__(kThreads) void row_codes_vec_kernel(const uint32_t *__restrict__ sigs, uint64_t n_new,
                                                                 uint64_t first, uint32_t k, uint64_t capacity,
                                                                 uint32_t cg, uint32_t *__restrict__ codes) {
-    constexpr uint32_t PW = kCodeBits * (NQ > 8 ? 2 : 1);
+    static_assert(!QUAD || KP % 4 == 0, "16-byte loads need k' a multiple of 4");
+    constexpr uint32_t PW = kCodeBits * (KP > 32 ? 2 : 1);
     const uint64_t total = n_new * cg;
     for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < total; i += (uint64_t)gridDim.x * kThreads) {
         const uint32_t g = (uint32_t)(i / n_new);
         const uint64_t r = i - (uint64_t)g * n_new, s = first + r;
-        const uint4 *src = reinterpret_cast<const uint4 *>(sigs + r * k + (uint64_t)g * 4 * NQ);
-        uint4 v[NQ];
+        const uint32_t *row = sigs + r * k + (uint64_t)g * KP;
+        uint32_t v[KP];
+        if constexpr (QUAD) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(row);
 #pragma unroll
-        for (int u = 0; u < NQ; ++u) v[u] = src[u];
-        store_code_planes<NQ>(v, codes + (((uint64_t)g * (capacity / 64) + (s >> 6)) * 64 + (s & 63)) * PW);
+            for (int u = 0; u < KP / 4; ++u) {
+                const uint4 q = src[u];
+                v[4 * u] = q.x;
+                v[4 * u + 1] = q.y;
+                v[4 * u + 2] = q.z;
+                v[4 * u + 3] = q.w;
+            }
+        } else {
+            const uint2 *src = reinterpret_cast<const uint2 *>(row);
+#pragma unroll
+            for (int u = 0; u < KP / 2; ++u) {
+                const uint2 q = src[u];
+                v[2 * u] = q.x;
+                v[2 * u + 1] = q.y;
+            }
+        }
+        store_code_planes<KP>(v, codes + (((uint64_t)g * (capacity / 64) + (s >> 6)) * 64 + (s & 63)) * PW);
     }
+}
+
+template <int KP>
+void launch_row_codes(dim3 grid, dim3 block, hipStream_t st, const uint32_t *rows, uint64_t n_new, uint64_t first,
+                      uint32_t k, uint64_t capacity, uint32_t cg, uint32_t *codes) {
+    if constexpr (KP % 4 == 0) {
+        if ((k & 3u) == 0) {
+            hipLaunchKernelGGL((row_codes_vec_kernel<KP, true>), grid, block, 0, st, rows, n_new, first, k, capacity,
+                               cg, codes);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((row_codes_vec_kernel<KP, false>), grid, block, 0, st, rows, n_new, first, k, capacity, cg,
+                       codes);
 }
 
 // Code planes of rows [first, first + n_new) from their signature rows (sigs
@@ -180,22 +209,30 @@ hipError_t launch_index_store(const uint32_t *sigs, uint64_t n_new, uint64_t fir
     return launch_codes_from_slab(slab, capacity, k, kp, first, n_new, codes, cg, st);
 }
 
-bool codes_have_row_kernel(uint32_t k, uint32_t kp) { return (k % 4) == 0 && (kp == 16 || kp == 32 || kp == 64); }
+bool codes_have_row_kernel(uint32_t k, uint32_t kp) { return (k % 2) == 0 && (kp % 2) == 0 && kp <= 64; }
 
 hipError_t launch_codes_from_slab(const uint32_t *slab, uint64_t capacity, uint32_t k, uint32_t kp, uint64_t first,
                                   uint64_t n_new, uint32_t *codes, uint32_t cg, hipStream_t st) {
     if (n_new == 0 || cg == 0 || !codes) return hipSuccess;
     const dim3 grid(grid_for(n_new * cg, kThreads)), block(kThreads);
     const uint32_t *rows = slab + first * k;
-    const bool vec = (k % 4) == 0;
-    if (vec && kp == 16)
-        hipLaunchKernelGGL(row_codes_vec_kernel<4>, grid, block, 0, st, rows, n_new, first, k, capacity, cg, codes);
-    else if (vec && kp == 32)
-        hipLaunchKernelGGL(row_codes_vec_kernel<8>, grid, block, 0, st, rows, n_new, first, k, capacity, cg, codes);
-    else if (vec && kp == 64)
-        hipLaunchKernelGGL(row_codes_vec_kernel<16>, grid, block, 0, st, rows, n_new, first, k, capacity, cg, codes);
-    else
+    if (codes_have_row_kernel(k, kp)) {
+        switch (kp) {
+#define HOPH_ROW_CODES(KP)                                                                                      \
+    case KP: launch_row_codes<KP>(grid, block, st, rows, n_new, first, k, capacity, cg, codes); break;
+            HOPH_ROW_CODES(2) HOPH_ROW_CODES(4) HOPH_ROW_CODES(6) HOPH_ROW_CODES(8) HOPH_ROW_CODES(10)
+            HOPH_ROW_CODES(12) HOPH_ROW_CODES(14) HOPH_ROW_CODES(16) HOPH_ROW_CODES(18) HOPH_ROW_CODES(20)
+            HOPH_ROW_CODES(22) HOPH_ROW_CODES(24) HOPH_ROW_CODES(26) HOPH_ROW_CODES(28) HOPH_ROW_CODES(30)
+            HOPH_ROW_CODES(32) HOPH_ROW_CODES(34) HOPH_ROW_CODES(36) HOPH_ROW_CODES(38) HOPH_ROW_CODES(40)
+            HOPH_ROW_CODES(42) HOPH_ROW_CODES(44) HOPH_ROW_CODES(46) HOPH_ROW_CODES(48) HOPH_ROW_CODES(50)
+            HOPH_ROW_CODES(52) HOPH_ROW_CODES(54) HOPH_ROW_CODES(56) HOPH_ROW_CODES(58) HOPH_ROW_CODES(60)
+            HOPH_ROW_CODES(62) HOPH_ROW_CODES(64)
+#undef HOPH_ROW_CODES
+        default: return hipErrorInvalidValue;
+        }
+    } else {
         hipLaunchKernelGGL(index_codes_kernel, grid, block, 0, st, rows, n_new, first, k, kp, capacity, cg, codes);
+    }
     return hipGetLastError();
 }
 

@@ -13,8 +13,8 @@
 // and a set's first ids are read during the previous set's last batch.  The
 // element path is straight-line code (out-of-range lanes are masked, only the
 // LDS minimum is predicated) so the loads of the four elements interleave.
-// An index append with no 16-byte code-plane row kernel (k' other than 16, 32,
-// 64) also writes the new rows' code planes from the LDS signature.
+// An index append with no vector-load code-plane row kernel (odd k' or k) also
+// writes the new rows' code planes from the LDS signature.
 //
 // Bin lookup: where regions and bins fall on powers of two (the 1:1 hierarchy
 // and power-of-two k over R = 2^31 - 1) one read of a 32-entry table indexed
