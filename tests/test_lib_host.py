@@ -305,6 +305,22 @@ def test_device_entry_points_refuse_bad_params_before_launch():
     qp = H.QueryParamsC(H.Ratio(4, 5), H.Ratio(1, 10000), 0, 0)
     res = H.ResultsC(None, None, 0, 0)
     assert H.lib().query_hoph(None, None, 0, qp, res, None) == H.HOPH_E_INVAL
+    # the entry points on an index refuse a NULL index before anything else
+    L = H.lib()
+    assert L.hoph_self_join(None, qp, res, None) == H.HOPH_E_INVAL
+    assert L.hoph_pair_counts(None, None, 0, None, 1, 0, None, None, None) == H.HOPH_E_INVAL
+    den = H.C.c_int64()
+    assert L.hoph_pair_estimates(None, None, 0, None, 1, 0, None, None, None, None, None,
+                                 H.C.byref(den), None) == H.HOPH_E_INVAL
+    dims = (H.u64 * 3)()
+    assert L.hoph_index_code_planes(None, None, 0, dims, None) == H.HOPH_E_INVAL
+    ms = (H.C.c_float * 3)()
+    assert L.hoph_query_timing(None, ms) == H.HOPH_E_INVAL
+    assert L.hoph_append_timing(None, ms) == H.HOPH_E_INVAL
+    assert L.index_append_sets(None, None, None, 1, None) == H.HOPH_E_INVAL
+    m = H.u32()
+    assert L.hoph_layout_lookups(None, H.C.byref(m)) == H.HOPH_E_INVAL
+    assert L.hoph_layout_lookups(pc, None) == H.HOPH_E_INVAL
 
 
 def test_abi_struct_layouts_match_binding(tmp_path):
