@@ -740,11 +740,15 @@ def main():
 
     # algorithmic work per launch
     sketch_bytes = nnz * 4 + (N + 1) * 8 + N * k * 4                 # ids, offsets in; signatures out
-    # groups that carry 8-bit codes: at least 4, about 128 bins (HOPH) or 256 (GOPH), at most 24 (12 for k' > 32)
+    # groups that carry 8-bit codes, in code units of pk whole groups (pk = min(32 // k', L)
+    # for k' <= 16, else 1): at least 4 units, about 128 bins (HOPH) or 256 (GOPH), at most
+    # 24 units (12 for k' > 32), none past the row
     L_groups = k // kp
-    code_groups = min(L_groups, max(4, min(12 if kp > 32 else 24, -(-(256 if w.goph else 128) // kp))))
-    code_bytes = N * code_groups * kp * 4 + N * code_groups * 32 * (1 if kp <= 32 else 2)
-    index_bytes = 2 * N * k * 4 + N * code_groups * 32 * (1 if kp <= 32 else 2)   # rows in, slabs + code planes out
+    pk = min(32 // kp, L_groups) if kp <= 16 else 1
+    code_units = min(L_groups // pk, max(4, min(12 if kp > 32 else 24, -(-(256 if w.goph else 128) // (pk * kp)))))
+    code_groups = code_units * pk
+    code_bytes = N * code_groups * kp * 4 + N * code_units * 32 * (1 if kp <= 32 else 2)
+    index_bytes = 2 * N * k * 4 + N * code_units * 32 * (1 if kp <= 32 else 2)   # rows in, slabs + code planes out
     # coarse depth as the library picks it: the first group alone when it rejects at
     # least 1/8 of its match counts (no empty bins), else every group that carries codes
     tabs = H.decision_tables(p, w.T, w.eps)

@@ -103,9 +103,11 @@ typedef struct {
                                  available); else the most groups scanned for a pair before
                                  it moves to the per-pair pass (a tuning knob: results do
                                  not depend on it).  Clamped to the groups available: with
-                                 codes, the groups that carry codes (at least 4, about 128
-                                 bins for HOPH and 256 for GOPH, at most 24); on words, 4
-                                 groups of at most 128 bins */
+                                 codes, the groups that carry codes (whole code units of
+                                 pk groups, pk = min(floor(32 / k'), L) for k' <= 16, else 1:
+                                 at least 4 units, about 128 bins for HOPH and 256 for GOPH,
+                                 at most 24 units, 12 when k' > 32); on words, 4 groups of
+                                 at most 128 bins */
     uint32_t coarse_filter;   /* HOPH_COARSE_*                                           */
     uint32_t reserved;        /* set to 0                                                */
 } hoph_query_params;
@@ -181,9 +183,12 @@ hoph_status hoph_query_timing(const hoph_index *index, float ms[3]);
 hoph_status hoph_append_timing(const hoph_index *index, float ms[2]);
 
 /* hoph_index_code_planes -- copies the index's narrowed code planes (a test
-   hook, for comparing how they were written): dims[0] = groups that carry codes
-   (cg), dims[1] = rows (the capacity), dims[2] = words per (row, group) (PW);
-   word w of (group g, row s) is at ((g * dims[1] / 64 + s / 64) * 64 + s % 64) *
+   hook, for comparing how they were written): dims[0] = code units that carry
+   codes (a unit is pk whole consecutive groups, pk = min(floor(32 / k'), L)
+   when k' <= 16, else one group), dims[1] = rows (the capacity), dims[2] =
+   words per (row, unit) (PW = 8 W, W = 1 plane word, 2 when k' > 32; word
+   p W + w holds bit p of the 8-bit codes of the unit's bins 32 w .. 32 w + 31);
+   word w of (unit u, row s) is at ((u * dims[1] / 64 + s / 64) * 64 + s % 64) *
    dims[2] + w, and only rows below the index size are defined.  d_out: device,
    out_words >= dims[0] * dims[1] * dims[2], else HOPH_E_CAPACITY (dims are
    written either way).  Asynchronous on hip_stream. */

@@ -271,17 +271,18 @@ class Index:
                                        _stream(stream)))
 
     def code_planes(self, stream=None):
-        """The index's code planes as int32 [cg, capacity / 64, 64, PW] (rows past
-        the index size undefined), a copy."""
+        """The index's code planes as int32 [code units, capacity / 64, 64, PW]
+        (rows past the index size undefined), a copy.  A code unit holds
+        min(32 // k', L) whole groups when k' <= 16, else one group."""
         import torch
         dims = (u64 * 3)()
         st = lib().hoph_index_code_planes(self._h, None, 0, dims, _stream(stream))   # sizes only
         if st not in (0, HOPH_E_CAPACITY):
             _check(st)
-        cg, rows, pw = int(dims[0]), int(dims[1]), int(dims[2])
-        out = torch.empty(max(cg * rows * pw, 1), dtype=torch.int32, device="cuda")
+        cu, rows, pw = int(dims[0]), int(dims[1]), int(dims[2])
+        out = torch.empty(max(cu * rows * pw, 1), dtype=torch.int32, device="cuda")
         _check(lib().hoph_index_code_planes(self._h, vp(out.data_ptr()), out.numel(), dims, _stream(stream)))
-        return out[:cg * rows * pw].view(cg, rows // 64, 64, pw)
+        return out[:cu * rows * pw].view(cu, rows // 64, 64, pw)
 
     def last_append_ms(self):
         """(sketch into the rows, code planes of the new rows) device ms of the

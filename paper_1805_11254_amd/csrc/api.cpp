@@ -113,15 +113,15 @@ hipError_t append_sets_async(hoph_index *idx, const uint32_t *d_ids, const uint6
     // code planes of the new rows: the row kernel where it reads a group with
     // vector loads, else the sketch writes them from its LDS signature (then
     // aev[1]..aev[2] spans no work)
-    const bool fused = idx->codes && !codes_have_row_kernel(idx->lay.k, idx->lay.kp);
-    const CodeSink sink = fused ? CodeSink{idx->codes, first, idx->capacity / 64, idx->cg, idx->lay.kp} : CodeSink{};
+    const uint32_t ub = code_unit_bins(idx->lay.kp, idx->lay.L), cu = code_units(idx->cg, idx->lay.kp, idx->lay.L);
+    const bool fused = idx->codes && !codes_have_row_kernel(idx->lay.k, ub);
+    const CodeSink sink = fused ? CodeSink{idx->codes, first, idx->capacity / 64, cu, ub} : CodeSink{};
     if (timed && (e = hipEventRecord(idx->ws.aev[0], s)) != hipSuccess) return e;
     e = launch_sketch(d, d_ids, d_offsets, n_sets, idx->slab + first * idx->lay.k, err_word, s, sink);
     if (e != hipSuccess) return e;
     if (timed && (e = hipEventRecord(idx->ws.aev[1], s)) != hipSuccess) return e;
     if (!fused) {
-        e = launch_codes_from_slab(idx->slab, idx->capacity, idx->lay.k, idx->lay.kp, first, n_sets, idx->codes,
-                                   idx->cg, s);
+        e = launch_codes_from_slab(idx->slab, idx->capacity, idx->lay.k, ub, first, n_sets, idx->codes, cu, s);
         if (e != hipSuccess) return e;
     }
     if (timed && (e = hipEventRecord(idx->ws.aev[2], s)) != hipSuccess) return e;
@@ -389,7 +389,8 @@ hoph_status build_index(const hoph_sketch_params *params, const uint32_t *d_sigs
     idx->max_sets = capacity;
     const uint64_t words = idx->capacity * idx->lay.k;          // row-major signature words
     idx->cg = code_groups(idx->lay.kp, idx->lay.L, params->layout == HOPH_LAYOUT_HIER);
-    const uint64_t code_words_total = idx->capacity * idx->cg * code_words(idx->lay.kp);
+    const uint32_t ub = code_unit_bins(idx->lay.kp, idx->lay.L), cu = code_units(idx->cg, idx->lay.kp, idx->lay.L);
+    const uint64_t code_words_total = idx->capacity * cu * code_words(idx->lay.kp);
     auto release = [&] {
         if (idx->slab) (void)hipFree(idx->slab);
         if (idx->codes) (void)hipFree(idx->codes);
@@ -409,8 +410,7 @@ hoph_status build_index(const hoph_sketch_params *params, const uint32_t *d_sigs
         return st;
     }
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-    hipError_t e = launch_index_store(d_sigs, n_sets, 0, params->k, params->k_group, idx->lay.L, idx->kpad,
-                                      idx->capacity, idx->slab, idx->codes, idx->cg, s);
+    hipError_t e = launch_index_store(d_sigs, n_sets, 0, params->k, idx->capacity, idx->slab, idx->codes, ub, cu, s);
     if (e != hipSuccess) {
         release();
         return hip_fail(e, "index store launch");
@@ -429,8 +429,8 @@ hoph_status index_append(hoph_index *idx, const uint32_t *d_sigs, uint64_t n_new
     if (idx->n + n_new > idx->max_sets)
         return fail(HOPH_E_CAPACITY, "index capacity " + std::to_string(idx->max_sets) + " exceeded");
     DeviceGuard dg(idx->device);
-    HOPH_HIP(launch_index_store(d_sigs, n_new, idx->n, idx->params.k, idx->params.k_group, idx->lay.L, idx->kpad,
-                                idx->capacity, idx->slab, idx->codes, idx->cg,
+    HOPH_HIP(launch_index_store(d_sigs, n_new, idx->n, idx->params.k, idx->capacity, idx->slab, idx->codes,
+                                code_unit_bins(idx->lay.kp, idx->lay.L), code_units(idx->cg, idx->lay.kp, idx->lay.L),
                                 reinterpret_cast<hipStream_t>(hip_stream)),
              "index store launch");
     idx->n += n_new;
@@ -462,7 +462,7 @@ hoph_status hoph_index_code_planes(const hoph_index *idx, uint32_t *d_out, uint6
                                    void *hip_stream) {
     g_last_error.clear();
     if (!idx || !dims) return fail(HOPH_E_INVAL, "NULL argument");
-    dims[0] = idx->cg;
+    dims[0] = code_units(idx->cg, idx->lay.kp, idx->lay.L);
     dims[1] = idx->capacity;
     dims[2] = code_words(idx->lay.kp);
     const uint64_t words = dims[0] * dims[1] * dims[2];

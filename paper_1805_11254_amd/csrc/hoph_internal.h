@@ -17,28 +17,42 @@ constexpr uint64_t kP31 = 2147483647ull;        // 2^31 - 1
 constexpr uint64_t kP32 = 4294967311ull;        // 2^32 + 15, prime
 constexpr uint32_t kLutMax = 4096;              // region lookup entries
 constexpr uint32_t kTile = 64;                  // sets per index tile = one wavefront
-constexpr uint32_t kMaxDepth = 4;               // coarse groups kept in registers
+constexpr uint32_t kMaxDepth = 4;               // coarse groups (code units) kept in registers
 // Narrowed coarse pass: an 8-bit code per bin, stored as 8 bit-planes per
-// group (bit i of plane p = bit p of the code of bin i), so that one 32-bit
-// word holds one plane of 32 bins.  EMPTY has a code of its own.
+// code unit (bit i of plane p = bit p of the code of bin i of the unit), so
+// that one 32-bit word holds one plane of 32 bins.  EMPTY has a code of its own.
 constexpr uint32_t kCodeBits = 8;
 constexpr uint32_t kCodeEmpty = 0xFFu;           // code of EMPTY; other bins map to [0, 254]
-// Leading groups that carry codes: at least the register-resident depth and
-// enough groups to cover a bin budget, at most max_code_groups (the deep code
-// pass stages that many groups of one tile, 64 lanes x (planes + set-empty
-// masks), in under 64 KB of LDS: 24 groups of one plane word, 12 of two).  GOPH
-// weighs its groups equally and, with small groups or a low threshold, can
-// first reject only after one to two hundred bins; HOPH decides most pairs in
-// its heavy first group.
+// Small groups share plane words: a code unit is pk consecutive whole groups
+// (pk = floor(32 / k') for k' <= 16, at most L; else 1), so a unit spans
+// pk k' <= 32 bins (k' <= 32) or one group of two plane words (k' > 32), and
+// its planes are written and read as those of one group of pk k' bins.
+__host__ __device__ inline uint32_t code_pack(uint32_t kp, uint32_t L) {
+    const uint32_t pk = kp <= 16 ? 32u / kp : 1u;
+    return pk < L ? pk : (L > 0 ? L : 1u);
+}
+// Leading groups that carry codes, in whole units: at least the
+// register-resident depth in units and enough units to cover a bin budget, at
+// most max_code_units (the deep code pass stages that many units of one tile,
+// 64 lanes x (planes + set-empty masks), in under 64 KB of LDS: 24 units of one
+// plane word, 12 of two), and no unit past the row.  GOPH weighs its groups
+// equally and, with small groups or a low threshold, can first reject only
+// after one to two hundred bins; HOPH decides most pairs in its heavy first
+// group.
 constexpr uint32_t kCodeBinsHier = 128;
 constexpr uint32_t kCodeBinsFlat = 256;
-inline uint32_t max_code_groups(uint32_t kp) { return kp > 32 ? 12u : 24u; }
+inline uint32_t max_code_units(uint32_t kp) { return kp > 32 ? 12u : 24u; }
 inline uint32_t code_groups(uint32_t kp, uint32_t L, bool hier) {
-    const uint32_t bins = hier ? kCodeBinsHier : kCodeBinsFlat, cap = max_code_groups(kp);
-    uint32_t g = (bins + kp - 1) / kp;
-    g = g < kMaxDepth ? kMaxDepth : (g > cap ? cap : g);
-    return g < L ? g : L;
+    const uint32_t pk = code_pack(kp, L), ub = pk * kp;
+    const uint32_t bins = hier ? kCodeBinsHier : kCodeBinsFlat, cap = max_code_units(kp);
+    uint32_t u = (bins + ub - 1) / ub;
+    u = u < kMaxDepth ? kMaxDepth : (u > cap ? cap : u);
+    const uint32_t whole = L / pk;            // units inside the row (pk <= L)
+    return (u < whole ? u : whole) * pk;
 }
+// Bins of one code unit, and code units of cg groups.
+__host__ __device__ inline uint32_t code_unit_bins(uint32_t kp, uint32_t L) { return code_pack(kp, L) * kp; }
+__host__ __device__ inline uint32_t code_units(uint32_t cg, uint32_t kp, uint32_t L) { return cg / code_pack(kp, L); }
 
 // Device error bits (one 32-bit word per device).
 constexpr uint32_t kErrRange = 1u;              // an id >= universe, or a table value >= R
@@ -355,7 +369,7 @@ hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t value, hipStream_t 
 struct CodeSink {
     uint32_t *codes;
     uint64_t first, ctiles;          // ctiles = index capacity / 64
-    uint32_t cg, kp;
+    uint32_t cu, ub;                 // code units, bins per unit
 };
 hipError_t launch_sketch(const SketchDesc &d, const uint32_t *ids, const uint64_t *offsets,
                          uint64_t n_sets, uint32_t *sigs, uint32_t *err_flag, hipStream_t st,
@@ -367,18 +381,20 @@ hipError_t launch_sketch_chunked(const SketchDesc &d, const uint32_t *ids, const
                                  const uint64_t *desc, uint64_t *prefix, uint32_t chunk, uint32_t max_sets,
                                  uint64_t max_ids, uint32_t *sigs, uint32_t *err_flag, uint32_t waves_per_cu,
                                  hipStream_t st);
-// Whether the code planes of new rows have a row kernel reading each group as
-// 16- or 8-byte loads (k' and k even); otherwise a plain per-(set, group) kernel
-// writes them, and the sketch of an append writes them from its LDS signature.
-bool codes_have_row_kernel(uint32_t k, uint32_t kp);
-// Code planes of index rows [first, first + n_new) from the rows themselves.
-hipError_t launch_codes_from_slab(const uint32_t *slab, uint64_t capacity, uint32_t k, uint32_t kp, uint64_t first,
-                                  uint64_t n_new, uint32_t *codes, uint32_t cg, hipStream_t st);
+// Whether the code planes of new rows have a row kernel reading each code unit
+// (ub bins) as 16- or 8-byte loads (ub and k even); otherwise a plain
+// per-(set, unit) kernel writes them, and the sketch of an append writes them
+// from its LDS signature.
+bool codes_have_row_kernel(uint32_t k, uint32_t ub);
+// Code planes of index rows [first, first + n_new) from the rows themselves:
+// cu code units of ub bins each.
+hipError_t launch_codes_from_slab(const uint32_t *slab, uint64_t capacity, uint32_t k, uint32_t ub, uint64_t first,
+                                  uint64_t n_new, uint32_t *codes, uint32_t cu, hipStream_t st);
 // Copies signature rows into index rows [first, first + n_new) and, when codes
-// is not null, writes the code planes of the first cg groups (layout in k_index.hip).
-hipError_t launch_index_store(const uint32_t *sigs, uint64_t n_new, uint64_t first, uint32_t k,
-                              uint32_t kp, uint32_t L, uint32_t kpad, uint64_t capacity,
-                              uint32_t *slab, uint32_t *codes, uint32_t cg, hipStream_t st);
+// is not null, writes the code planes of the first cu code units of ub bins
+// each (layout in k_index.hip).
+hipError_t launch_index_store(const uint32_t *sigs, uint64_t n_new, uint64_t first, uint32_t k, uint64_t capacity,
+                              uint32_t *slab, uint32_t *codes, uint32_t ub, uint32_t cu, hipStream_t st);
 hipError_t launch_pair_counts(const uint32_t *slab, uint64_t capacity, uint64_t n_sets, uint32_t kpad,
                               uint32_t kp, uint32_t L, uint32_t k, const uint32_t *qsigs, uint32_t n_q,
                               const uint32_t *pairs, uint64_t n_pairs, uint32_t policy, uint32_t *m,

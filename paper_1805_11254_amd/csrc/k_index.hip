@@ -2,10 +2,12 @@
 // per set, word (set s, bin b) at slab[s * k + b]: a set is sketched straight
 // into its row, and the per-pair pass reads one group of one row as a
 // contiguous run.  The coarse pass reads the narrowed code planes of the
-// first cg groups instead, which are tiled so that a wavefront (one set per
-// lane) reads them coalesced: PW = code_words(k') words per (set, group),
-// plane p of bins [32 w, 32 w + 32) at word p * W + w (W = PW / 8),
-//   codes[((g * (capacity / 64) + s / 64) * 64 + s % 64) * PW + p * W + w].
+// first cg groups instead, in code units of pk whole groups (ub = pk k' bins,
+// code_pack), tiled so that a wavefront (one set per lane) reads them
+// coalesced: PW = code_words(k') words per (set, unit u), plane p of the
+// unit's bins [32 w, 32 w + 32) at word p * W + w (W = PW / 8),
+//   codes[((u * (capacity / 64) + s / 64) * 64 + s % 64) * PW + p * W + w].
+// The writers below take the unit as a group of ub bins.
 #include "hoph_internal.h"
 
 namespace hoph {
@@ -198,15 +200,12 @@ hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t value, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_index_store(const uint32_t *sigs, uint64_t n_new, uint64_t first, uint32_t k, uint32_t kp,
-                              uint32_t L, uint32_t kpad, uint64_t capacity, uint32_t *slab, uint32_t *codes,
-                              uint32_t cg, hipStream_t st) {
-    (void)L;
-    (void)kpad;
+hipError_t launch_index_store(const uint32_t *sigs, uint64_t n_new, uint64_t first, uint32_t k, uint64_t capacity,
+                              uint32_t *slab, uint32_t *codes, uint32_t ub, uint32_t cu, hipStream_t st) {
     if (n_new == 0) return hipSuccess;
     hipError_t e = hipMemcpyAsync(slab + first * k, sigs, n_new * k * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return e;
-    return launch_codes_from_slab(slab, capacity, k, kp, first, n_new, codes, cg, st);
+    return launch_codes_from_slab(slab, capacity, k, ub, first, n_new, codes, cu, st);
 }
 
 bool codes_have_row_kernel(uint32_t k, uint32_t kp) { return (k % 2) == 0 && (kp % 2) == 0 && kp <= 64; }

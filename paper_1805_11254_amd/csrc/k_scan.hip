@@ -9,8 +9,9 @@
 // queries), one set per lane, every query word a scalar load.  By default it
 // compares 8-bit bin codes held as bit-planes and only rejects
 // (scan_codes_fast_kernel for the first group, in two phases of planes;
-// scan_codes_kernel for 2-4 groups in VGPRs; scan_codes_deep_kernel past that,
-// later groups staged in LDS); on request it compares the 32-bit words and
+// scan_codes_kernel for up to 4 code units in VGPRs, a unit being one group or
+// several small ones sharing plane words; scan_codes_deep_kernel past that,
+// later units staged in LDS); on request it compares the 32-bit words and
 // accepts too (scan_coarse_kernel: with G = 1 the decision after the first
 // group is a pair of thresholds on the matched count, with G > 1 the exact
 // 64-bit state is carried).  Pairs not rejected are appended to a survivor
@@ -47,6 +48,8 @@ struct CoarseArgs {
     uint64_t capacity, n_sets, surv_cap, keys_cap;
     uint32_t k, kp, kpad, L, q0, q1, q_per_wave, policy, depth, cg;
     uint32_t tri;        // self-join: only pairs with set id > query row
+    uint32_t pk;         // groups per code unit
+    uint32_t cdepth;     // groups the code pass walks
 };
 
 __device__ __forceinline__ uint32_t wave_id_in_block() {
@@ -100,9 +103,11 @@ __device__ __forceinline__ int64_t group_rho(uint32_t eq, uint32_t ej, uint32_t 
 }
 
 // Empty-bin mask of every (query, group): bit i set when bin i of the group is
-// EMPTY; for the first cg groups also the query's code record: the planes (same
-// word order as the index's: plane p of bins [32 w, 32 w + 32) at p * W + w),
-// the non-empty mask, the first group's reject threshold and the empty count.
+// EMPTY; for the first cg groups also the query's code record: the planes of
+// the group's code unit (same word order as the index's: plane p of the unit's
+// bins [32 w, 32 w + 32) at p * W + w; every group of a unit holds the same
+// planes), the group's non-empty mask (bits from 0), the first group's reject
+// threshold and the group's empty count.
 __global__ __launch_bounds__(kThreads) void query_masks_kernel(const uint32_t *__restrict__ qsigs, uint32_t n_q_arg,
                                                               const uint64_t *__restrict__ desc, uint32_t k,
                                                               uint32_t kp, uint32_t L, uint64_t *__restrict__ out,
@@ -111,6 +116,7 @@ __global__ __launch_bounds__(kThreads) void query_masks_kernel(const uint32_t *_
     const uint32_t n_q = desc ? (uint32_t)desc[0] : n_q_arg;
     const uint64_t n = (uint64_t)n_q * L;
     const uint32_t W = code_plane_words(kp), PW = code_words(kp), RW = code_rec_words(kp);
+    const uint32_t pk = code_pack(kp, L), ub = pk * kp;
     const uint64_t kpmask = kp >= 64 ? ~0ull : ((1ull << kp) - 1ull);
     for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < n; t += (uint64_t)gridDim.x * kThreads) {
         const uint64_t q = t / L, g = t % L;
@@ -119,11 +125,12 @@ __global__ __launch_bounds__(kThreads) void query_masks_kernel(const uint32_t *_
         for (uint32_t i = 0; i < kp; ++i) m |= (uint64_t)(w[i] == HOPH_EMPTY) << i;
         out[t] = m;
         if (qcodes && g < cg) {
+            const uint32_t *wu = qsigs + q * k + (g / pk) * ub;      // the group's code unit (cg <= L / pk * pk)
             uint32_t lo[kCodeBits], hi[kCodeBits];
 #pragma unroll
             for (int p = 0; p < (int)kCodeBits; ++p) lo[p] = hi[p] = 0;
-            for (uint32_t b = 0; b < kp; ++b) {
-                const uint32_t c = bin_code(w[b]), bit = b & 31;
+            for (uint32_t b = 0; b < ub; ++b) {
+                const uint32_t c = bin_code(wu[b]), bit = b & 31;
                 if (b < 32) {
 #pragma unroll
                     for (int p = 0; p < (int)kCodeBits; ++p) lo[p] |= ((c >> p) & 1u) << bit;
@@ -171,25 +178,26 @@ __device__ __forceinline__ uint32_t code_diff_part(uint32_t d, const uint32_t *P
     return d;
 }
 
-// One group of the coarse pass on codes: the group's planes P and set-empty
-// masks em against the query's record, added to the weighted state S, and the
-// step's cutoffs applied to a lane still undecided (maybe: an accept cutoff
-// was reached, so the pair must go on to the fine pass).
+// One group of the coarse pass on codes: bits [o, o + k') of its code unit's
+// differing-code mask d and set-empty mask em (o = 0 unless small groups share
+// a unit) against the query's empty mask qm of the group, added to the
+// weighted state S, and the step's cutoffs applied to a lane still undecided
+// (maybe: an accept cutoff was reached, so the pair must go on to the fine
+// pass).
 template <int W>
-__device__ __forceinline__ void code_group_step(const uint32_t *P, const uint32_t *em,
-                                                const uint32_t *__restrict__ qrec, uint64_t qm, uint64_t kpmask,
-                                                uint32_t kp, uint32_t policy, const int64_t *s_dmul, int64_t lambda,
-                                                int64_t Wg, int64_t accg, int64_t rejg, int64_t &S, bool &undecided,
-                                                bool &maybe) {
+__device__ __forceinline__ void code_group_step(const uint32_t (&d)[W], const uint32_t *em, uint32_t o, uint64_t qm,
+                                                uint64_t kpmask, uint32_t kp, uint32_t policy, const int64_t *s_dmul,
+                                                int64_t lambda, int64_t Wg, int64_t accg, int64_t rejg, int64_t &S,
+                                                bool &undecided, bool &maybe) {
     const uint64_t nqm = ~qm & kpmask;
     uint32_t dn = 0, de = 0, ee = 0;
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-        const uint32_t d = code_diff<W>(P, qrec, w);
-        const uint32_t qmw = (uint32_t)(qm >> (32 * w)), nqmw = (uint32_t)(nqm >> (32 * w));
-        dn += __popc(d & nqmw);
-        de += __popc(d & qmw);
-        ee += __popc(em[w] | qmw);
+        const uint32_t qmw = (uint32_t)(qm >> (32 * w)) << o, nqmw = (uint32_t)(nqm >> (32 * w)) << o;
+        const uint32_t gmw = (uint32_t)(kpmask >> (32 * w)) << o;
+        dn += __popc(d[w] & nqmw);
+        de += __popc(d[w] & qmw);
+        ee += __popc((em[w] & gmw) | qmw);
     }
     const uint32_t eq_q = (uint32_t)__popcll(qm);
     const uint32_t m = kp - eq_q - dn;        // >= the matched non-empty bins
@@ -205,17 +213,44 @@ __device__ __forceinline__ void code_group_step(const uint32_t *P, const uint32_
     }
 }
 
+// The groups of code unit u (planes P, set-empty masks em) for one query, up
+// to group cd: the unit's differing-code mask is formed once and each of its
+// groups (pk of them; one without PACK) takes its own bits.
+template <int W, bool PACK>
+__device__ __forceinline__ void code_unit_steps(uint32_t u, const uint32_t *P, const uint32_t *em,
+                                                const uint32_t *__restrict__ qc, const uint64_t *__restrict__ qmk,
+                                                uint32_t pk, uint32_t cd, uint64_t kpmask, uint32_t kp,
+                                                uint32_t policy, const int64_t *s_dmul, const ScanTab &tab,
+                                                int64_t &S, bool &undecided, bool &maybe) {
+    constexpr int RW = (int)kCodeBits * W + 4;
+    const uint32_t g0 = PACK ? u * pk : u;
+    uint32_t d[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) d[w] = code_diff<W>(P, qc + (uint64_t)g0 * RW, w);
+    if constexpr (PACK) {
+        for (uint32_t j = 0, g = g0; j < pk && g < cd; ++j, ++g) {
+            if (j > 0 && !__any(undecided)) break;
+            code_group_step<W>(d, em, j * kp, qmk[g], kpmask, kp, policy, s_dmul, tab.lambda, tab.W[g], tab.acc[g],
+                               tab.rej[g], S, undecided, maybe);
+        }
+    } else {
+        code_group_step<W>(d, em, 0u, qmk[g0], kpmask, kp, policy, s_dmul, tab.lambda, tab.W[g0], tab.acc[g0],
+                           tab.rej[g0], S, undecided, maybe);
+    }
+}
+
 // Coarse pass on codes (reject-only).  Same (tile, query chunk) items as the
-// word kernel below; the tile's code planes of the first G groups stay in
+// word kernel below; the tile's code planes of the first G code units stay in
 // VGPRs.  Codes never under-count matched bins (equal values have equal codes)
 // and count empty bins exactly (EMPTY has a code of its own), and the per-step
 // cutoffs are monotone in the matched count, so a pair is dropped here only
 // where the exact algorithm rejects it too: at a step whose code state is at or
 // below the reject cutoff, with no earlier step at or above an accept cutoff.
 // Every other pair goes to the fine pass, which restarts from the first group
-// on the 32-bit words.  (G = 1 under JOINT or LITERAL runs in
-// scan_codes_fast_kernel instead.)
-template <int W, int G>
+// on the 32-bit words.  PACK: units of several small groups, walked up to group
+// a.cdepth.  (Depth 1 under JOINT or LITERAL runs in scan_codes_fast_kernel
+// instead.)
+template <int W, int G, bool PACK>
 __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__restrict__ codes,
                                                              const uint32_t *__restrict__ qcodes,
                                                              const uint64_t *__restrict__ qmasks,
@@ -235,7 +270,7 @@ __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__
     const uint32_t nchunks = (q_hi - q_lo + a.q_per_wave - 1) / a.q_per_wave;
     const uint64_t n_items = ntiles * nchunks;
     const uint64_t wstride = (uint64_t)gridDim.x * kWaves;
-    const uint32_t kp = a.kp;
+    const uint32_t kp = a.kp, pk = a.pk, cd = a.cdepth;
     const uint64_t kpmask = kp >= 64 ? ~0ull : ((1ull << kp) - 1ull);
     const uint64_t ctiles = a.capacity / 64;
     const uint32_t policy = a.policy;
@@ -250,23 +285,23 @@ __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__
     uint32_t P[G][PW];
     uint32_t em[G][W];
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(codes + (((uint64_t)g * ctiles + tile) * 64 + lane) * PW);
+    for (int u = 0; u < G; ++u) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(codes + (((uint64_t)u * ctiles + tile) * 64 + lane) * PW);
 #pragma unroll
         for (int j = 0; j < PW / 4; ++j) {
             const uint4 v = src[j];
-            P[g][4 * j + 0] = v.x;
-            P[g][4 * j + 1] = v.y;
-            P[g][4 * j + 2] = v.z;
-            P[g][4 * j + 3] = v.w;
+            P[u][4 * j + 0] = v.x;
+            P[u][4 * j + 1] = v.y;
+            P[u][4 * j + 2] = v.z;
+            P[u][4 * j + 3] = v.w;
         }
 #pragma unroll
         for (int w = 0; w < W; ++w) {
             // set-empty bins: code 0xFF, every plane set
-            uint32_t e = P[g][w];
+            uint32_t e = P[u][w];
 #pragma unroll
-            for (int p = 1; p < (int)kCodeBits; ++p) e &= P[g][p * W + w];
-            em[g][w] = e;
+            for (int p = 1; p < (int)kCodeBits; ++p) e &= P[u][p * W + w];
+            em[u][w] = e;
         }
     }
 
@@ -280,10 +315,10 @@ __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__
             int64_t S = 0;
             bool undecided = valid && (!a.tri || s > q), maybe = false;
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
+            for (int u = 0; u < G; ++u) {
                 if (!__any(undecided)) break;
-                code_group_step<W>(P[g], em[g], qc + g * RW, qmk[g], kpmask, kp, policy, s_dmul, tab.lambda,
-                                   tab.W[g], tab.acc[g], tab.rej[g], S, undecided, maybe);
+                code_unit_steps<W, PACK>((uint32_t)u, P[u], em[u], qc, qmk, pk, cd, kpmask, kp, policy, s_dmul, tab,
+                                         S, undecided, maybe);
             }
             survive = maybe || undecided;
         }
@@ -295,26 +330,27 @@ __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__
     }
 }
 
-// Coarse pass on codes deeper than the register-resident groups (GOPH with
+// Coarse pass on codes deeper than the register-resident units (GOPH with
 // small groups or a low threshold, whose first useful rejecting step comes
 // many groups in).  One wavefront per block, one (tile, query chunk) item at a
-// time.  The first kMaxDepth groups of the tile stay in VGPRs as in
-// scan_codes_kernel; the later ones are staged in LDS group by group, the
-// first time a query of the chunk reaches that group (each lane only reads
-// back its own words, so the wavefront's program order is the only ordering
-// needed).  Each query walks the groups until every lane is decided.
-template <int W>
+// time.  The first kMaxDepth code units of the tile stay in VGPRs as in
+// scan_codes_kernel; the later ones (up to unit cu) are staged in LDS unit by
+// unit, the first time a query of the chunk reaches that unit (each lane only
+// reads back its own words, so the wavefront's program order is the only
+// ordering needed).  Each query walks the groups, up to group a.cdepth, until
+// every lane is decided.
+template <int W, bool PACK>
 __global__ __launch_bounds__(64) void scan_codes_deep_kernel(const uint32_t *__restrict__ codes,
                                                            const uint32_t *__restrict__ qcodes,
                                                            const uint64_t *__restrict__ qmasks,
                                                            Survivor *__restrict__ surv,
                                                            unsigned long long *__restrict__ counters,
                                                            const uint64_t *__restrict__ desc, const CoarseArgs a,
-                                                           const ScanTab tab, uint32_t cd) {
+                                                           const ScanTab tab, uint32_t cu) {
     constexpr int PW = (int)kCodeBits * W, RW = PW + 4, PV = PW / 4, R = (int)kMaxDepth;
-    extern __shared__ uint4 s_pl[];      // groups >= R: [group - R][PV][lane] planes, then [group - R][W][lane] masks
+    extern __shared__ uint4 s_pl[];      // units >= R: [unit - R][PV][lane] planes, then [unit - R][W][lane] masks
     __shared__ int64_t s_dmul[HOPH_MAX_KGROUP + 1];
-    uint32_t *s_em = reinterpret_cast<uint32_t *>(s_pl + (size_t)(cd - R) * PV * 64);
+    uint32_t *s_em = reinterpret_cast<uint32_t *>(s_pl + (size_t)(cu - R) * PV * 64);
     for (uint32_t i = threadIdx.x; i <= tab.kp; i += 64) s_dmul[i] = tab.dmul[i];
     __syncthreads();
 
@@ -324,7 +360,7 @@ __global__ __launch_bounds__(64) void scan_codes_deep_kernel(const uint32_t *__r
     const uint64_t ntiles = (n_sets + 63) / 64;
     const uint32_t nchunks = (q_hi - q_lo + a.q_per_wave - 1) / a.q_per_wave;
     const uint64_t n_items = ntiles * nchunks;
-    const uint32_t kp = a.kp;
+    const uint32_t kp = a.kp, pk = a.pk, cd = a.cdepth;
     const uint64_t kpmask = kp >= 64 ? ~0ull : ((1ull << kp) - 1ull);
     const uint64_t ctiles = a.capacity / 64;
     const uint32_t policy = a.policy;
@@ -340,23 +376,23 @@ __global__ __launch_bounds__(64) void scan_codes_deep_kernel(const uint32_t *__r
 
         uint32_t P[R][PW], em[R][W];
 #pragma unroll
-        for (int g = 0; g < R; ++g) {
-            const uint4 *src = reinterpret_cast<const uint4 *>(codes + (((uint64_t)g * ctiles + tile) * 64 + lane) * PW);
+        for (int u = 0; u < R; ++u) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(codes + (((uint64_t)u * ctiles + tile) * 64 + lane) * PW);
 #pragma unroll
             for (int j = 0; j < PV; ++j) {
                 const uint4 v = src[j];
-                P[g][4 * j + 0] = v.x;
-                P[g][4 * j + 1] = v.y;
-                P[g][4 * j + 2] = v.z;
-                P[g][4 * j + 3] = v.w;
+                P[u][4 * j + 0] = v.x;
+                P[u][4 * j + 1] = v.y;
+                P[u][4 * j + 2] = v.z;
+                P[u][4 * j + 3] = v.w;
             }
 #pragma unroll
             for (int w = 0; w < W; ++w) {
                 // set-empty bins: code 0xFF, every plane set
-                uint32_t e = P[g][w];
+                uint32_t e = P[u][w];
 #pragma unroll
-                for (int p = 1; p < (int)kCodeBits; ++p) e &= P[g][p * W + w];
-                em[g][w] = e;
+                for (int p = 1; p < (int)kCodeBits; ++p) e &= P[u][p * W + w];
+                em[u][w] = e;
             }
         }
 
@@ -367,33 +403,33 @@ __global__ __launch_bounds__(64) void scan_codes_deep_kernel(const uint32_t *__r
             int64_t S = 0;
             bool undecided = valid && (!a.tri || s > q), maybe = false;
 #pragma unroll
-            for (int g = 0; g < R; ++g) {
+            for (int u = 0; u < R; ++u) {
                 if (!__any(undecided)) break;
-                code_group_step<W>(P[g], em[g], qc + g * RW, qmk[g], kpmask, kp, policy, s_dmul, tab.lambda,
-                                   tab.W[g], tab.acc[g], tab.rej[g], S, undecided, maybe);
+                code_unit_steps<W, PACK>((uint32_t)u, P[u], em[u], qc, qmk, pk, cd, kpmask, kp, policy, s_dmul, tab,
+                                         S, undecided, maybe);
             }
-            for (uint32_t g = R; g < cd; ++g) {
+            for (uint32_t u = R; u < cu; ++u) {
                 if (!__any(undecided)) break;
-                uint32_t Pg[PW], emg[W];
-                const size_t r = g - R;
-                if (g == staged) {           // wave-uniform: first query of the item to reach group g
+                uint32_t Pu[PW], emu[W];
+                const size_t r = u - R;
+                if (u == staged) {           // wave-uniform: first query of the item to reach unit u
                     const uint4 *src =
-                        reinterpret_cast<const uint4 *>(codes + (((uint64_t)g * ctiles + tile) * 64 + lane) * PW);
+                        reinterpret_cast<const uint4 *>(codes + (((uint64_t)u * ctiles + tile) * 64 + lane) * PW);
 #pragma unroll
                     for (int j = 0; j < PV; ++j) {
                         const uint4 v = src[j];
                         s_pl[(r * PV + j) * 64 + lane] = v;
-                        Pg[4 * j + 0] = v.x;
-                        Pg[4 * j + 1] = v.y;
-                        Pg[4 * j + 2] = v.z;
-                        Pg[4 * j + 3] = v.w;
+                        Pu[4 * j + 0] = v.x;
+                        Pu[4 * j + 1] = v.y;
+                        Pu[4 * j + 2] = v.z;
+                        Pu[4 * j + 3] = v.w;
                     }
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
-                        uint32_t e = Pg[w];
+                        uint32_t e = Pu[w];
 #pragma unroll
-                        for (int p = 1; p < (int)kCodeBits; ++p) e &= Pg[p * W + w];
-                        emg[w] = e;
+                        for (int p = 1; p < (int)kCodeBits; ++p) e &= Pu[p * W + w];
+                        emu[w] = e;
                         s_em[(r * W + w) * 64 + lane] = e;
                     }
                     ++staged;
@@ -401,16 +437,16 @@ __global__ __launch_bounds__(64) void scan_codes_deep_kernel(const uint32_t *__r
 #pragma unroll
                     for (int j = 0; j < PV; ++j) {
                         const uint4 v = s_pl[(r * PV + j) * 64 + lane];
-                        Pg[4 * j + 0] = v.x;
-                        Pg[4 * j + 1] = v.y;
-                        Pg[4 * j + 2] = v.z;
-                        Pg[4 * j + 3] = v.w;
+                        Pu[4 * j + 0] = v.x;
+                        Pu[4 * j + 1] = v.y;
+                        Pu[4 * j + 2] = v.z;
+                        Pu[4 * j + 3] = v.w;
                     }
 #pragma unroll
-                    for (int w = 0; w < W; ++w) emg[w] = s_em[(r * W + w) * 64 + lane];
+                    for (int w = 0; w < W; ++w) emu[w] = s_em[(r * W + w) * 64 + lane];
                 }
-                code_group_step<W>(Pg, emg, qc + g * RW, qmk[g], kpmask, kp, policy, s_dmul, tab.lambda, tab.W[g],
-                                   tab.acc[g], tab.rej[g], S, undecided, maybe);
+                code_unit_steps<W, PACK>(u, Pu, emu, qc, qmk, pk, cd, kpmask, kp, policy, s_dmul, tab, S, undecided,
+                                         maybe);
             }
             const bool survive = maybe || undecided;
             if (__any(survive)) {
@@ -880,39 +916,42 @@ CoarseArgs coarse_args(const ScanLaunch &l, uint32_t policy) {
     a.depth = l.codes ? 0u : l.depth;      // where the fine pass starts
     a.cg = l.cg;
     a.tri = l.tri ? 1u : 0u;
+    a.pk = code_pack(l.kp, l.L);
+    a.cdepth = l.depth;
     return a;
 }
 
-template <int W>
-void codes_launch(const ScanLaunch &l, const CoarseArgs &a, const ScanTab &tab, hipStream_t st, uint32_t blocks) {
+// The code pass over du code units held in VGPRs (du <= kMaxDepth): depth 1
+// (JOINT or LITERAL) in scan_codes_fast_kernel, else scan_codes_kernel.
+template <int W, bool PACK>
+void codes_launch(const ScanLaunch &l, const CoarseArgs &a, const ScanTab &tab, hipStream_t st, uint32_t blocks,
+                  uint32_t du) {
     auto *cnt = reinterpret_cast<unsigned long long *>(l.counters);
 #define HOPH_CODES(G)                                                                                         \
-    hipLaunchKernelGGL((scan_codes_kernel<W, G>), dim3(blocks), dim3(kThreads), 0, st, l.codes, l.qcodes,    \
-                       l.qmasks, l.surv, cnt, l.desc, a, tab)
-    switch (l.depth) {
-    case 1:
-        if (tab.policy == HOPH_EMPTY_EITHER) {
-            HOPH_CODES(1);
-        } else {
-            const int split = plane_split(tab, l.kp);
+    hipLaunchKernelGGL((scan_codes_kernel<W, G, PACK>), dim3(blocks), dim3(kThreads), 0, st, l.codes,        \
+                       l.qcodes, l.qmasks, l.surv, cnt, l.desc, a, tab)
+    if (l.depth == 1 && tab.policy != HOPH_EMPTY_EITHER) {
+        const int split = plane_split(tab, l.kp);
 #define HOPH_FAST(P1, TRI)                                                                                     \
     hipLaunchKernelGGL((scan_codes_fast_kernel<W, fast_tiles(W, P1), P1, TRI>), dim3(blocks), dim3(kThreads), 0, st, \
                        l.codes, l.qcodes, l.surv, cnt, l.desc, a)
-            if (l.tri) {
-                if (split == 2) HOPH_FAST(2, true);
-                else if (split == 4) HOPH_FAST(4, true);
-                else HOPH_FAST(0, true);
-            } else {
-                if (split == 2) HOPH_FAST(2, false);
-                else if (split == 4) HOPH_FAST(4, false);
-                else HOPH_FAST(0, false);
-            }
-#undef HOPH_FAST
+        if (l.tri) {
+            if (split == 2) HOPH_FAST(2, true);
+            else if (split == 4) HOPH_FAST(4, true);
+            else HOPH_FAST(0, true);
+        } else {
+            if (split == 2) HOPH_FAST(2, false);
+            else if (split == 4) HOPH_FAST(4, false);
+            else HOPH_FAST(0, false);
         }
-        break;
+#undef HOPH_FAST
+        return;
+    }
+    switch (du) {
+    case 1: HOPH_CODES(1); break;
     case 2: HOPH_CODES(2); break;
     case 3: HOPH_CODES(3); break;
-    default: HOPH_CODES(4); break;     // depth 4 (deeper runs in scan_codes_deep_kernel)
+    default: HOPH_CODES(4); break;     // 4 units (deeper runs in scan_codes_deep_kernel)
     }
 #undef HOPH_CODES
 }
@@ -1013,10 +1052,11 @@ hipError_t launch_scan_coarse(const ScanLaunch &l, const ScanTab &tab, hipStream
     const CoarseArgs a = coarse_args(l, tab.policy);
     if (l.codes) {
         if (l.depth == 0 || l.depth > l.cg) return hipErrorInvalidValue;
-        if (l.depth > kMaxDepth) {
-            // past the register-resident groups: one wavefront per block, planes staged in LDS
-            const uint32_t W = code_plane_words(l.kp);
-            if (l.depth > max_code_groups(l.kp)) return hipErrorInvalidValue;
+        const uint32_t W = code_plane_words(l.kp), pk = a.pk, du = (l.depth + pk - 1) / pk;   // code units walked
+        const bool pack = pk > 1;            // only with one plane word (k' <= 16)
+        if (du > kMaxDepth) {
+            // past the register-resident units: one wavefront per block, planes staged in LDS
+            if (du > max_code_units(l.kp)) return hipErrorInvalidValue;
             uint64_t waves;
             if (l.desc) {
                 waves = (uint64_t)device_cu_count() * (l.waves_per_cu ? l.waves_per_cu : 16);
@@ -1025,18 +1065,24 @@ hipError_t launch_scan_coarse(const ScanLaunch &l, const ScanTab &tab, hipStream
                 waves = ntiles * ((l.q1 - l.q0 + l.q_per_wave - 1) / l.q_per_wave);
             }
             const uint32_t deep_blocks = (uint32_t)std::min<uint64_t>(waves, 1u << 30);
-            const size_t lds = (size_t)(l.depth - kMaxDepth) * 64 * (code_words(l.kp) * 4 + 4 * W);
+            const size_t lds = (size_t)(du - kMaxDepth) * 64 * (code_words(l.kp) * 4 + 4 * W);
             auto *cnt = reinterpret_cast<unsigned long long *>(l.counters);
-            if (W == 1)
-                hipLaunchKernelGGL(scan_codes_deep_kernel<1>, dim3(deep_blocks), dim3(64), lds, st, l.codes, l.qcodes,
-                                   l.qmasks, l.surv, cnt, l.desc, a, tab, l.depth);
-            else
-                hipLaunchKernelGGL(scan_codes_deep_kernel<2>, dim3(deep_blocks), dim3(64), lds, st, l.codes, l.qcodes,
-                                   l.qmasks, l.surv, cnt, l.desc, a, tab, l.depth);
+#define HOPH_DEEP(WW, PACK)                                                                                        hipLaunchKernelGGL((scan_codes_deep_kernel<WW, PACK>), dim3(deep_blocks), dim3(64), lds, st, l.codes,                            l.qcodes, l.qmasks, l.surv, cnt, l.desc, a, tab, du)
+            if (W == 1) {
+                if (pack) HOPH_DEEP(1, true);
+                else HOPH_DEEP(1, false);
+            } else {
+                HOPH_DEEP(2, false);
+            }
+#undef HOPH_DEEP
             return hipGetLastError();
         }
-        if (code_plane_words(l.kp) == 1) codes_launch<1>(l, a, tab, st, blocks);
-        else codes_launch<2>(l, a, tab, st, blocks);
+        if (W == 1) {
+            if (pack) codes_launch<1, true>(l, a, tab, st, blocks, du);
+            else codes_launch<1, false>(l, a, tab, st, blocks, du);
+        } else {
+            codes_launch<2, false>(l, a, tab, st, blocks, du);
+        }
         return hipGetLastError();
     }
     HOPH_KPAD_SWITCH(coarse_kp, l, a, tab, st, blocks)

@@ -246,20 +246,21 @@ __device__ __forceinline__ uint32_t range_error(const SketchDesc &d, uint32_t xm
     return e;
 }
 
-// The code planes of the first cg groups of a finished LDS signature: one lane
-// per bin, one ballot per code bit gives the plane words of 32 bins (the low
-// and high halves: two groups of k' <= 32, or both words of one group of up
-// to 64 bins); lane 0 stores each group's PW words.  Bins past k' are 0.
+// The code planes of the first cu code units (ub bins each) of a finished LDS
+// signature: one lane per bin, one ballot per code bit gives the plane words
+// of 32 bins (the low and high halves: two units of ub <= 32 bins, or both
+// words of one unit of up to 64 bins); lane 0 stores each unit's PW words.
+// Bins past ub are 0.
 __device__ __forceinline__ void sketch_code_planes(const uint32_t *sig, const CodeSink &cs, uint64_t set,
                                                    uint32_t lane) {
     const uint64_t row = cs.first + set;
     const uint64_t tile_off = (row >> 6) * 64 + (row & 63);
-    const uint32_t kp = cs.kp;
-    if (kp <= 32) {
-        for (uint32_t g0 = 0; g0 < cs.cg; g0 += 2) {
+    const uint32_t ub = cs.ub;
+    if (ub <= 32) {
+        for (uint32_t g0 = 0; g0 < cs.cu; g0 += 2) {
             const uint32_t g = g0 + (lane >> 5), i = lane & 31;
-            const bool in = g < cs.cg && i < kp;
-            const uint32_t c = in ? bin_code(sig[g * kp + i]) : 0u;
+            const bool in = g < cs.cu && i < ub;
+            const uint32_t c = in ? bin_code(sig[g * ub + i]) : 0u;
             uint32_t lo[kCodeBits], hi[kCodeBits];
 #pragma unroll
             for (int p = 0; p < (int)kCodeBits; ++p) {
@@ -271,7 +272,7 @@ __device__ __forceinline__ void sketch_code_planes(const uint32_t *sig, const Co
                 uint4 *d0 = reinterpret_cast<uint4 *>(cs.codes + ((uint64_t)g0 * cs.ctiles * 64 + tile_off) * 8);
                 d0[0] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
                 d0[1] = make_uint4(lo[4], lo[5], lo[6], lo[7]);
-                if (g0 + 1 < cs.cg) {
+                if (g0 + 1 < cs.cu) {
                     uint4 *d1 =
                         reinterpret_cast<uint4 *>(cs.codes + ((uint64_t)(g0 + 1) * cs.ctiles * 64 + tile_off) * 8);
                     d1[0] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
@@ -280,9 +281,9 @@ __device__ __forceinline__ void sketch_code_planes(const uint32_t *sig, const Co
             }
         }
     } else {
-        for (uint32_t g = 0; g < cs.cg; ++g) {
-            const bool in = lane < kp;
-            const uint32_t c = in ? bin_code(sig[g * kp + lane]) : 0u;
+        for (uint32_t g = 0; g < cs.cu; ++g) {
+            const bool in = lane < ub;
+            const uint32_t c = in ? bin_code(sig[g * ub + lane]) : 0u;
             uint32_t pl[2 * kCodeBits];
 #pragma unroll
             for (int p = 0; p < (int)kCodeBits; ++p) {
@@ -606,7 +607,7 @@ hipError_t launch_sketch_chunked(const SketchDesc &d, const uint32_t *ids, const
 hipError_t launch_sketch(const SketchDesc &d, const uint32_t *ids, const uint64_t *offsets, uint64_t n_sets,
                          uint32_t *sigs, uint32_t *err_flag, hipStream_t st, const CodeSink &cs) {
     if (n_sets == 0) return hipSuccess;
-    if (cs.codes && (cs.cg == 0 || cs.kp == 0 || cs.kp > 64 || (uint64_t)cs.cg * cs.kp > d.k))
+    if (cs.codes && (cs.cu == 0 || cs.ub == 0 || cs.ub > 64 || (uint64_t)cs.cu * cs.ub > d.k))
         return hipErrorInvalidValue;
     const bool est = d.est_ok != 0;
 #define HOPH_SK(H, LOC) launch_t<H, LOC>(d, ids, offsets, n_sets, sigs, err_flag, st, cs)

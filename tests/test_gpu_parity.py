@@ -424,25 +424,30 @@ def _append_sets_check(w, cuts):
     n = w.collection.n
     ca, cb = two_step.code_planes(), fused.code_planes()
     assert ca.shape == cb.shape
-    cg, tiles, _, pw = ca.shape
-    ra, rb = ca.reshape(cg, tiles * 64, pw)[:, :n], cb.reshape(cg, tiles * 64, pw)[:, :n]
+    cu, tiles, _, pw = ca.shape
+    ra, rb = ca.reshape(cu, tiles * 64, pw)[:, :n], cb.reshape(cu, tiles * 64, pw)[:, :n]
     assert torch.equal(ra, rb)
     two_step.free()
     fused.free()
     return sh, ra.cpu().numpy().view(np.uint32)
 
 
-def _planes_from_rows(sh, kp, cg):
-    """Code planes restated from signature rows: bit i of word p W + w of (row,
-    group g) is bit p of the code of bin 32 w + i of the group."""
-    n = sh.shape[0]
-    W_ = 1 if kp <= 32 else 2
-    out = np.zeros((cg, n, 8 * W_), dtype=np.uint64)
-    for g in range(cg):
-        codes = _code8(sh[:, g * kp:(g + 1) * kp])               # n x kp
-        for i in range(kp):
+def _planes_from_rows(sh, kp, cu):
+    """Code planes restated from signature rows: groups of k' <= 16 bins share a
+    code unit, pk = min(32 // k', L) whole groups (else one group per unit);
+    bit i of word p W + w of (row, unit u) is bit p of the code of bin 32 w + i
+    of the unit."""
+    n, k = sh.shape
+    L = k // kp
+    pk = min(32 // kp, L) if kp <= 16 else 1
+    ub = pk * kp
+    W_ = 1 if ub <= 32 else 2
+    out = np.zeros((cu, n, 8 * W_), dtype=np.uint64)
+    for u in range(cu):
+        codes = _code8(sh[:, u * ub:(u + 1) * ub])               # n x ub
+        for i in range(ub):
             for pl in range(8):
-                out[g, :, pl * W_ + i // 32] |= ((codes[:, i] >> np.uint64(pl)) & np.uint64(1)) << np.uint64(i % 32)
+                out[u, :, pl * W_ + i // 32] |= ((codes[:, i] >> np.uint64(pl)) & np.uint64(1)) << np.uint64(i % 32)
     return out.astype(np.uint32)
 
 
@@ -459,17 +464,19 @@ def test_append_sets_matches_oracle(name):
 
 @pytest.mark.parametrize("layout,k,kp", [(W.LAYOUT_HIER, 192, 12), (W.LAYOUT_OPH, 120, 10), (W.LAYOUT_HIER, 320, 40),
                                          (W.LAYOUT_HIER, 320, 20), (W.LAYOUT_OPH, 320, 40), (W.LAYOUT_OPH, 160, 5),
-                                         (W.LAYOUT_HIER, 512, 32), (W.LAYOUT_OPH, 512, 64)])
+                                         (W.LAYOUT_HIER, 512, 32), (W.LAYOUT_OPH, 512, 64), (W.LAYOUT_OPH, 270, 9),
+                                         (W.LAYOUT_OPH, 24, 8), (W.LAYOUT_HIER, 256, 16)])
 def test_append_sets_group_sizes(layout, k, kp):
-    """Group sizes of one and two plane words, odd and even counts of groups
-    that carry codes, every sketch lookup; the planes also against a restatement
-    from the rows."""
+    """Group sizes of one and two plane words, code units of several small
+    groups (odd and even unit widths, a unit that spans the whole row), odd and
+    even counts of units, every sketch lookup; the planes also against a
+    restatement from the rows."""
     _print_case(f"append_sets group size layout={layout} k={k} kp={kp}")
     w = W.hoph_bovw(n=2_345, n_q=8, seed=41 + kp, k=k, kp=kp, planted_frac=0.02)
     w.layout = layout
     sh, planes = _append_sets_check(w, [0, 100, 1000, 2_345])
-    cg = planes.shape[0]
-    assert (planes == _planes_from_rows(sh, kp, cg)).all()
+    cu = planes.shape[0]
+    assert (planes == _planes_from_rows(sh, kp, cu)).all()
 
 
 def test_append_sets_reports_range_and_empty_sets():
@@ -577,16 +584,22 @@ def test_self_join_matches_oracle(name):
 
 
 def _code_groups(kp, L, hier=False):
-    """Groups that carry codes in the index (at least 4, about 128 bins for HOPH
-    and 256 for GOPH, at most 24)."""
-    return min(L, max(4, min(12 if kp > 32 else 24, -(-(128 if hier else 256) // kp))))
+    """Groups that carry codes in the index and groups per code unit: units of
+    pk = min(32 // k', L) whole groups when k' <= 16 (else 1); at least 4 units,
+    about 128 bins for HOPH and 256 for GOPH, at most 24 units (12 when
+    k' > 32), none past the row."""
+    pk = min(32 // kp, L) if kp <= 16 else 1
+    units = min(L // pk, max(4, min(12 if kp > 32 else 24, -(-(128 if hier else 256) // (pk * kp)))))
+    return units * pk, pk
 
 
-@pytest.mark.parametrize("k,kp", [(160, 8), (160, 5), (320, 10), (320, 40)])
+@pytest.mark.parametrize("k,kp", [(160, 8), (160, 5), (320, 10), (320, 40), (270, 9), (150, 3), (24, 8)])
 def test_deep_code_pass_matches_oracle(k, kp):
     """GOPH with small groups: the coarse pass on codes at every depth from 1
-    to the number of groups that carry codes (past 4 it stages a tile's planes
-    in LDS), for queries and the self-join."""
+    to the number of groups that carry codes, across the boundaries of code
+    units (several small groups per unit) and of the register-resident units
+    (past 4 units it stages a tile's planes in LDS), for queries and the
+    self-join."""
     _print_case(f"deep code pass k={k} kp={kp}")
     w = W.hoph_bovw(n=2_500, n_q=12, seed=61 + kp, k=k, kp=kp, planted_frac=0.03, T=(7, 10))
     w.layout = W.LAYOUT_OPH
@@ -595,8 +608,9 @@ def test_deep_code_pass_matches_oracle(k, kp):
     qsig = gpu_sketch(w, w.queries, p)
     sh, qh = to_u32(sig), to_u32(qsig)
     idx = H.Index(p, sig)
-    cg = _code_groups(kp, k // kp)
-    depths = sorted({1, 3, 4, 5, cg // 2 + 1, cg})
+    cg, pk = _code_groups(kp, k // kp)
+    assert idx.code_planes().shape[0] * pk == cg
+    depths = sorted(d for d in {1, 2, 3, 4, 5, pk, pk + 1, 4 * pk, 4 * pk + 1, cg // 2 + 1, cg} if 1 <= d <= cg)
     for T, eps in (((7, 10), (1, 10_000)), ((1, 2), (1, 1000))):
         for policy in _policies_that_fit(p, T, eps):
             oo, oi = oracle_query(w, sh, qh, T, eps, policy)
