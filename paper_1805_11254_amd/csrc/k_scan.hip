@@ -15,7 +15,9 @@
 // accepts too (scan_coarse_kernel: with G = 1 the decision after the first
 // group is a pair of thresholds on the matched count, with G > 1 the exact
 // 64-bit state is carried).  Pairs not rejected are appended to a survivor
-// list with one atomic per wavefront (ballot + rank).
+// list: the code passes gather a wavefront's survivors in LDS and append them
+// in batches (one atomic per batch), the word pass with one atomic per
+// wavefront and step (ballot + rank).
 //
 // Fine pass: one wavefront per survivor, one lane per bin, groups read a few
 // at a time; counts come from ballots and popcounts, the decision is
@@ -69,6 +71,49 @@ __device__ __forceinline__ uint64_t wave_append(bool flag, unsigned long long *c
     base = __shfl(base, 0);
     return base + lane_rank(bal, lane);
 }
+
+// Orders one wavefront's LDS accesses across its lanes.
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// A wavefront's survivors gathered in its own LDS buffer and appended to the
+// list in batches of up to N: one atomic on the counter per batch.  One atomic
+// per (query, tile) that has a survivor serialises on the counter when
+// survivors are spread thinly over many (query, tile) items (about 12 ns each:
+// 2.5 ms for the 2*10^5 survivors of 3*10^8 pairs).  The order of the list is
+// not specified (the output is sorted per query).  Every call with the whole
+// wave active; `n` is wave-uniform.
+template <uint32_t N>
+struct SurvBatch {
+    Survivor *buf;                   // this wavefront's N entries in LDS
+    uint32_t n;
+
+    __device__ __forceinline__ void flush(Survivor *__restrict__ surv, uint64_t cap, unsigned long long *counter,
+                                          uint32_t lane) {
+        if (n == 0) return;
+        wave_lds_fence();
+        uint64_t base = 0;
+        if (lane == 0) base = atomicAdd(counter, (unsigned long long)n);
+        base = __shfl(base, 0);
+        for (uint32_t j = lane; j < n; j += 64)
+            if (base + j < cap) surv[base + j] = buf[j];
+        wave_lds_fence();
+        n = 0;
+    }
+    // bal: the surviving lanes (wave-uniform); this lane's pair is (q, s).
+    __device__ __forceinline__ void push(uint64_t bal, uint32_t q, uint32_t s, Survivor *__restrict__ surv,
+                                         uint64_t cap, unsigned long long *counter, uint32_t lane) {
+        const uint32_t c = (uint32_t)__popcll(bal);
+        if (c == 0) return;
+        if (n + c > N) flush(surv, cap, counter, lane);
+        if ((bal >> lane) & 1ull) buf[n + (uint32_t)lane_rank(bal, lane)] = Survivor{q, s, 0};
+        n += c;
+    }
+};
+constexpr uint32_t kSurvBatch = 128;       // per wavefront: 2 KB of LDS
+constexpr uint32_t kSurvBatchDeep = 64;    // the deep pass's LDS is mostly its staging
 
 // One group of one set row (row-major words) into registers; pad words
 // (k' not a multiple of 4) read as EMPTY.  16-byte loads when k' and k are
@@ -263,7 +308,9 @@ __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__
     for (uint32_t i = threadIdx.x; i <= tab.kp; i += kThreads) s_dmul[i] = tab.dmul[i];
     __syncthreads();
 
+    __shared__ Survivor s_surv[kWaves][kSurvBatch];
     const uint32_t lane = threadIdx.x & 63;
+    SurvBatch<kSurvBatch> sb{s_surv[wave_id_in_block()], 0};
     const uint64_t n_sets = desc ? desc[1] : a.n_sets;
     const uint32_t q_lo = desc ? 0u : a.q0, q_hi = desc ? (uint32_t)desc[0] : a.q1;
     const uint64_t ntiles = (n_sets + 63) / 64;
@@ -322,12 +369,10 @@ __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__
             }
             survive = maybe || undecided;
         }
-        if (__any(survive)) {
-            const uint64_t slot = wave_append(survive, counters + 0, lane);
-            if (survive && slot < a.surv_cap) surv[slot] = Survivor{q, (uint32_t)s, 0};
-        }
+        sb.push(__ballot(survive), q, (uint32_t)s, surv, a.surv_cap, counters + 0, lane);
     }
     }
+    sb.flush(surv, a.surv_cap, counters + 0, lane);
 }
 
 // Coarse pass on codes deeper than the register-resident units (GOPH with
@@ -350,6 +395,8 @@ __global__ __launch_bounds__(64) void scan_codes_deep_kernel(const uint32_t *__r
     constexpr int PW = (int)kCodeBits * W, RW = PW + 4, PV = PW / 4, R = (int)kMaxDepth;
     extern __shared__ uint4 s_pl[];      // units >= R: [unit - R][PV][lane] planes, then [unit - R][W][lane] masks
     __shared__ int64_t s_dmul[HOPH_MAX_KGROUP + 1];
+    __shared__ Survivor s_surv[kSurvBatchDeep];
+    SurvBatch<kSurvBatchDeep> sb{s_surv, 0};
     uint32_t *s_em = reinterpret_cast<uint32_t *>(s_pl + (size_t)(cu - R) * PV * 64);
     for (uint32_t i = threadIdx.x; i <= tab.kp; i += 64) s_dmul[i] = tab.dmul[i];
     __syncthreads();
@@ -449,12 +496,10 @@ __global__ __launch_bounds__(64) void scan_codes_deep_kernel(const uint32_t *__r
                                          maybe);
             }
             const bool survive = maybe || undecided;
-            if (__any(survive)) {
-                const uint64_t slot = wave_append(survive, counters + 0, lane);
-                if (survive && slot < a.surv_cap) surv[slot] = Survivor{q, (uint32_t)s, 0};
-            }
+            sb.push(__ballot(survive), q, (uint32_t)s, surv, a.surv_cap, counters + 0, lane);
         }
     }
+    sb.flush(surv, a.surv_cap, counters + 0, lane);
 }
 
 // First-group code pass (depth 1, JOINT or LITERAL), TPW tiles of 64 indexed
@@ -476,7 +521,9 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_
                                                                   const uint64_t *__restrict__ desc,
                                                                   const CoarseArgs a) {
     constexpr int PW = (int)kCodeBits * W, RW = PW + 4;
+    __shared__ Survivor s_surv[kWaves][kSurvBatch];
     const uint32_t lane = threadIdx.x & 63;
+    SurvBatch<kSurvBatch> sb{s_surv[wave_id_in_block()], 0};
     const uint64_t n_sets = desc ? desc[1] : a.n_sets;
     const uint32_t q_lo = desc ? 0u : a.q0, q_hi = desc ? (uint32_t)desc[0] : a.q1;
     const uint64_t ntiles = (n_sets + 63) / 64;
@@ -554,14 +601,7 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_
                     }                                                                              \
                     const uint64_t bal =                                                           \
                         __builtin_amdgcn_ballot_w64((int32_t)dn < (int32_t)r[PW + 2]) & lanes[t];   \
-                    if (bal) {                                                                     \
-                        const bool survive = (bal >> lane) & 1ull;                                 \
-                        uint64_t base = 0;                                                         \
-                        if (lane == 0) base = atomicAdd(counters + 0, (unsigned long long)__popcll(bal));  \
-                        base = __shfl(base, 0);                                                    \
-                        const uint64_t slot = base + lane_rank(bal, lane);                         \
-                        if (survive && slot < a.surv_cap) surv[slot] = Survivor{(qq), sid[t], 0};  \
-                    }                                                                              \
+                    sb.push(bal, (qq), sid[t], surv, a.surv_cap, counters + 0, lane);              \
                 }                                                                                  \
             }                                                                                      \
         }
@@ -576,6 +616,7 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_
         }
 #undef HOPH_CODE_QUERY_T
     }
+    sb.flush(surv, a.surv_cap, counters + 0, lane);
 }
 
 template <int KPAD, int G, bool EXACT>
