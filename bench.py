@@ -614,7 +614,7 @@ def main():
          "selfjoin": bench_selfjoin, "sweeps": bench_sweeps}[args.mode](args)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
+        print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}); "
               f"run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np

@@ -341,11 +341,17 @@ def test_results_capacity_reports_needed():
     idx.free()
 
 
-def test_survivor_overflow_path_matches_oracle():
+@pytest.mark.parametrize("layout,k,kp,kind,depth", [(W.LAYOUT_HIER, 256, 32, "hoph", 1),
+                                                     (W.LAYOUT_HIER, 256, 32, "hoph", 4),
+                                                     (W.LAYOUT_OPH, 320, 10, "goph", 27)])
+def test_survivor_overflow_path_matches_oracle(layout, k, kp, kind, depth):
     """Near-identical collection: every pair survives the coarse pass, more
     survivors than the survivor buffer holds, so the batch is re-run in
-    sub-batches; the result must still be exact."""
-    _print_case("survivor overflow")
+    sub-batches; the result must still be exact.  The first-group pass, the
+    register-resident pass over 4 groups and the LDS-staged deep pass (GOPH,
+    27 groups of 10 bins in 9 code units) each append through their
+    wavefront's batch."""
+    _print_case(f"survivor overflow layout={layout} k={k} kp={kp} depth={depth}")
     rng = np.random.default_rng(5)
     base = rng.choice(1 << 20, size=300, replace=False)
     sets = []
@@ -355,12 +361,12 @@ def test_survivor_overflow_path_matches_oracle():
         sets.append(s)
     coll = W.csr_from_lists(sets)
     qs = W.csr_from_lists(sets[:30])
-    w = W.Workload("same", coll, qs, 1 << 20, W.HASH_MODP31, W.LAYOUT_HIER, 256, 32, ha=99991, hb=5)
+    w = W.Workload("same", coll, qs, 1 << 20, W.HASH_MODP31, layout, k, kp, ha=99991, hb=5)
     p = params_of(w)
     sig = gpu_sketch(w, coll, p)
     qsig = gpu_sketch(w, qs, p)
     idx = H.Index(p, sig)
-    go, gi = gpu_query("hoph", idx, qsig, (99, 100), (1, 10 ** 6), 0, coarse_depth=1)
+    go, gi = gpu_query(kind, idx, qsig, (99, 100), (1, 10 ** 6), 0, coarse_depth=depth)
     oo, oi = oracle_query(w, to_u32(sig), to_u32(qsig), (99, 100), (1, 10 ** 6), 0)
     assert go.tolist() == oo.tolist() and gi.tolist() == oi.tolist()
     idx.free()
