@@ -21,29 +21,67 @@ __global__ __launch_bounds__(kThreads) void fill_u64_kernel(uint64_t *p, uint64_
         p[i] = value;
 }
 
+// 8 x 8 bit transpose of a 64-bit word (byte r = row r, bit c = column c):
+// three exchanges of off-diagonal blocks of 1, 2 and 4 bits.  Byte p of the
+// result holds bit p of each of the eight input bytes.
+__device__ __forceinline__ uint64_t transpose8x8(uint64_t x) {
+    uint64_t t = (x ^ (x >> 7)) & 0x00AA00AA00AA00AAull;
+    x = x ^ t ^ (t << 7);
+    t = (x ^ (x >> 14)) & 0x0000CCCC0000CCCCull;
+    x = x ^ t ^ (t << 14);
+    t = (x ^ (x >> 28)) & 0x00000000F0F0F0F0ull;
+    return x ^ t ^ (t << 28);
+}
+
 // Code planes of the KP bins v[0..KP), written as PW contiguous words (bins
-// past KP in a plane word are 0).
+// past KP in a plane word are 0).  KP <= 32: the codes are packed as bytes,
+// eight bins to a 64-bit word, and one bit transpose per word gives the eight
+// plane bytes of those bins, which are then gathered into the plane words.
 template <int KP>
 __device__ __forceinline__ void store_code_planes(const uint32_t (&v)[KP], uint32_t *__restrict__ dst) {
     constexpr int W = KP > 32 ? 2 : 1;
     uint32_t pl[kCodeBits * W];
+    if constexpr (KP <= 32) {
+        uint32_t half[8];                    // plane bytes: half[2 j] bits 0..31, half[2 j + 1] bits 32..63 of word j
 #pragma unroll
-    for (int j = 0; j < (int)kCodeBits * W; ++j) pl[j] = 0;
+        for (int j = 0; j < 4; ++j) {
+            uint32_t lo = 0, hi = 0;
 #pragma unroll
-    for (int i = 0; i < KP; ++i) {
-        const uint32_t c = bin_code(v[i]);
+            for (int b = 0; b < 4; ++b) {
+                if (8 * j + b < KP) lo |= bin_code(v[8 * j + b]) << (8 * b);
+                if (8 * j + 4 + b < KP) hi |= bin_code(v[8 * j + 4 + b]) << (8 * b);
+            }
+            const uint64_t x = (8 * j < KP) ? transpose8x8(((uint64_t)hi << 32) | lo) : 0ull;
+            half[2 * j] = (uint32_t)x;
+            half[2 * j + 1] = (uint32_t)(x >> 32);
+        }
 #pragma unroll
-        for (int p = 0; p < (int)kCodeBits; ++p) pl[p * W + (i >> 5)] |= ((c >> p) & 1u) << (i & 31);
+        for (int p = 0; p < (int)kCodeBits; ++p) {
+            const int h = p >> 2, sh = 8 * (p & 3);
+            pl[p] = ((half[h] >> sh) & 0xFFu) | (((half[2 + h] >> sh) & 0xFFu) << 8) |
+                    (((half[4 + h] >> sh) & 0xFFu) << 16) | (((half[6 + h] >> sh) & 0xFFu) << 24);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < (int)kCodeBits * W; ++j) pl[j] = 0;
+#pragma unroll
+        for (int i = 0; i < KP; ++i) {
+            const uint32_t c = bin_code(v[i]);
+#pragma unroll
+            for (int p = 0; p < (int)kCodeBits; ++p) pl[p * W + (i >> 5)] |= ((c >> p) & 1u) << (i & 31);
+        }
     }
     uint4 *d4 = reinterpret_cast<uint4 *>(dst);
 #pragma unroll
     for (int j = 0; j < 2 * W; ++j) d4[j] = make_uint4(pl[4 * j], pl[4 * j + 1], pl[4 * j + 2], pl[4 * j + 3]);
 }
 
-// Code planes for an even k' = KP with k even: one thread per (group < cg,
-// row), consecutive rows in consecutive lanes; a group of a row is read as
-// 16-byte loads (QUAD: KP and k multiples of 4) or 8-byte loads.  sigs row r
-// is index row first + r.
+// Code planes for an even unit width KP with k even: one thread per (row,
+// unit < cg), the units of a row in consecutive lanes, so that a wavefront
+// reads contiguous runs of the rows it covers (ordering the threads unit-major
+// instead read 128 bytes of each 2 KB row per pass, at 0.45 against 0.29 ms
+// for 10^6 rows of 9 units); a unit of a row is read as 16-byte loads (QUAD:
+// KP and k multiples of 4) or 8-byte loads.  sigs row r is index row first + r.
 template <int KP, bool QUAD>
 __global__ __launch_bounds__(kThreads) void row_codes_vec_kernel(const uint32_t *__restrict__ sigs, uint64_t n_new,
                                                                 uint64_t first, uint32_t k, uint64_t capacity,
@@ -52,8 +90,9 @@ __global__ __launch_bounds__(kThreads) void row_codes_vec_kernel(const uint32_t 
     constexpr uint32_t PW = kCodeBits * (KP > 32 ? 2 : 1);
     const uint64_t total = n_new * cg;
     for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < total; i += (uint64_t)gridDim.x * kThreads) {
-        const uint32_t g = (uint32_t)(i / n_new);
-        const uint64_t r = i - (uint64_t)g * n_new, s = first + r;
+        const uint64_t r = i / cg;           // the units of one row are adjacent threads: a wavefront
+        const uint32_t g = (uint32_t)(i - r * cg);    // reads whole runs of each row it touches
+        const uint64_t s = first + r;
         const uint32_t *row = sigs + r * k + (uint64_t)g * KP;
         uint32_t v[KP];
         if constexpr (QUAD) {
@@ -94,7 +133,8 @@ void launch_row_codes(dim3 grid, dim3 block, hipStream_t st, const uint32_t *row
 }
 
 // Code planes of rows [first, first + n_new) from their signature rows (sigs
-// row r is index row first + r), any k': one thread per (set, group < cg).
+// row r is index row first + r), any unit width: one thread per (set, unit < cg),
+// the units of a row in consecutive threads.
 __global__ __launch_bounds__(kThreads) void index_codes_kernel(const uint32_t *__restrict__ sigs, uint64_t n_new,
                                                               uint64_t first, uint32_t k, uint32_t kp,
                                                               uint64_t capacity, uint32_t cg,
@@ -102,8 +142,8 @@ __global__ __launch_bounds__(kThreads) void index_codes_kernel(const uint32_t *_
     const uint32_t W = code_plane_words(kp), PW = code_words(kp);
     const uint64_t total = n_new * cg;
     for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < total; i += (uint64_t)gridDim.x * kThreads) {
-        const uint32_t g = (uint32_t)(i / n_new);
-        const uint64_t r = i - (uint64_t)g * n_new;
+        const uint64_t r = i / cg;           // units of one row in adjacent threads
+        const uint32_t g = (uint32_t)(i - r * cg);
         const uint64_t s = first + r;
         const uint32_t *row = sigs + r * k + (uint64_t)g * kp;
         uint32_t lo[kCodeBits], hi[kCodeBits];
