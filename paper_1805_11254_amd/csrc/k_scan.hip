@@ -378,13 +378,13 @@ __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__
 // Coarse pass on codes deeper than the register-resident units (GOPH with
 // small groups or a low threshold, whose first useful rejecting step comes
 // many groups in).  One wavefront per block, one (tile, query chunk) item at a
-// time.  The first kMaxDepth code units of the tile stay in VGPRs as in
+// time.  The first R code units of the tile (R <= cu) stay in VGPRs as in
 // scan_codes_kernel; the later ones (up to unit cu) are staged in LDS unit by
 // unit, the first time a query of the chunk reaches that unit (each lane only
 // reads back its own words, so the wavefront's program order is the only
 // ordering needed).  Each query walks the groups, up to group a.cdepth, until
 // every lane is decided.
-template <int W, bool PACK>
+template <int W, bool PACK, int R>
 __global__ __launch_bounds__(64) void scan_codes_deep_kernel(const uint32_t *__restrict__ codes,
                                                            const uint32_t *__restrict__ qcodes,
                                                            const uint64_t *__restrict__ qmasks,
@@ -392,7 +392,7 @@ __global__ __launch_bounds__(64) void scan_codes_deep_kernel(const uint32_t *__r
                                                            unsigned long long *__restrict__ counters,
                                                            const uint64_t *__restrict__ desc, const CoarseArgs a,
                                                            const ScanTab tab, uint32_t cu) {
-    constexpr int PW = (int)kCodeBits * W, RW = PW + 4, PV = PW / 4, R = (int)kMaxDepth;
+    constexpr int PW = (int)kCodeBits * W, RW = PW + 4, PV = PW / 4;
     extern __shared__ uint4 s_pl[];      // units >= R: [unit - R][PV][lane] planes, then [unit - R][W][lane] masks
     __shared__ int64_t s_dmul[HOPH_MAX_KGROUP + 1];
     __shared__ Survivor s_surv[kSurvBatchDeep];
@@ -1106,14 +1106,30 @@ hipError_t launch_scan_coarse(const ScanLaunch &l, const ScanTab &tab, hipStream
                 waves = ntiles * ((l.q1 - l.q0 + l.q_per_wave - 1) / l.q_per_wave);
             }
             const uint32_t deep_blocks = (uint32_t)std::min<uint64_t>(waves, 1u << 30);
-            const size_t lds = (size_t)(du - kMaxDepth) * 64 * (code_words(l.kp) * 4 + 4 * W);
+            // Units held in VGPRs: 8 (no or little LDS staging, 4 wavefronts per SIMD
+            // by registers) when a unit packs several groups or the first step that
+            // can reject lies past the fourth unit, so that most pairs walk that far;
+            // else 4, the rest staged only when a query reaches it (plain groups that
+            // reject within 4 units: loading 8 up front cost 16% at k' = 32).
+            uint32_t g1 = 0;                 // first step with a reject cutoff (0-based)
+            while (g1 < l.depth && tab.rej[g1] < 0) ++g1;
+            const bool r8 = W == 1 && du >= 8 && (pk > 1 || g1 / pk + 1 > kMaxDepth);
+            const uint32_t R = r8 ? 8u : kMaxDepth;
+            const size_t lds = (size_t)(du - R) * 64 * (code_words(l.kp) * 4 + 4 * W);
             auto *cnt = reinterpret_cast<unsigned long long *>(l.counters);
-#define HOPH_DEEP(WW, PACK)                                                                                        hipLaunchKernelGGL((scan_codes_deep_kernel<WW, PACK>), dim3(deep_blocks), dim3(64), lds, st, l.codes,                            l.qcodes, l.qmasks, l.surv, cnt, l.desc, a, tab, du)
+#define HOPH_DEEP(WW, PACK, RR)                                                                                \
+    hipLaunchKernelGGL((scan_codes_deep_kernel<WW, PACK, RR>), dim3(deep_blocks), dim3(64), lds, st, l.codes,  \
+                       l.qcodes, l.qmasks, l.surv, cnt, l.desc, a, tab, du)
             if (W == 1) {
-                if (pack) HOPH_DEEP(1, true);
-                else HOPH_DEEP(1, false);
+                if (r8) {
+                    if (pack) HOPH_DEEP(1, true, 8);
+                    else HOPH_DEEP(1, false, 8);
+                } else {
+                    if (pack) HOPH_DEEP(1, true, 4);
+                    else HOPH_DEEP(1, false, 4);
+                }
             } else {
-                HOPH_DEEP(2, false);
+                HOPH_DEEP(2, false, 4);
             }
 #undef HOPH_DEEP
             return hipGetLastError();

@@ -599,7 +599,7 @@ def _code_groups(kp, L, hier=False):
     return units * pk, pk
 
 
-@pytest.mark.parametrize("k,kp", [(160, 8), (160, 5), (320, 10), (320, 40), (270, 9), (150, 3), (24, 8)])
+@pytest.mark.parametrize("k,kp", [(160, 8), (160, 5), (320, 10), (320, 20), (320, 40), (270, 9), (150, 3), (24, 8)])
 def test_deep_code_pass_matches_oracle(k, kp):
     """GOPH with small groups: the coarse pass on codes at every depth from 1
     to the number of groups that carry codes, across the boundaries of code
