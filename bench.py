@@ -750,11 +750,16 @@ def main():
     code_bytes = N * code_groups * kp * 4 + N * code_units * 32 * (1 if kp <= 32 else 2)
     index_bytes = 2 * N * k * 4 + N * code_units * 32 * (1 if kp <= 32 else 2)   # rows in, slabs + code planes out
     # coarse depth as the library picks it: the first group alone when it rejects at
-    # least 1/8 of its match counts (no empty bins), else every group that carries codes
+    # least 1/8 of its match counts (no empty bins), else one group past the first
+    # step with a reject cutoff, rounded up to whole code units
     tabs = H.decision_tables(p, w.T, w.eps)
     unit0 = tabs["W"][0] * tabs["dmul"][0]
     m_rej0 = tabs["rej"][0] // unit0 if tabs["rej"][0] >= 0 else -1
-    depth = 1 if (m_rej0 >= 0 and 8 * m_rej0 >= kp) else code_groups
+    if m_rej0 >= 0 and 8 * m_rej0 >= kp:
+        depth = 1
+    else:   # one group past the first step with a reject cutoff, in whole code units
+        g1 = next((l + 1 for l, r in enumerate(tabs["rej"]) if r >= 0), None)
+        depth = code_groups if g1 is None else min(code_groups, -(-(g1 + 1) // pk) * pk)
     # coarse pass on 8-bit bin codes held as 8 bit-planes of 32 bins per word:
     # per (pair, group) 8 W plane operations, W masks, W popcounts, 1 compare.
     # The first-group pass compares the first P1 planes of every pair first and

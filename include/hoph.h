@@ -99,9 +99,11 @@ typedef struct {
     hoph_ratio eps;           /* error tolerance of the small-probability event, 0 <= eps < 1 */
     uint32_t empty_policy;    /* HOPH_EMPTY_*                                            */
     uint32_t coarse_depth;    /* 0 = let the library choose (the first group alone when it
-                                 rejects at least 1/8 of its match counts, else the deepest
-                                 available); else the most groups scanned for a pair before
-                                 it moves to the per-pair pass (a tuning knob: results do
+                                 rejects at least 1/8 of its match counts, else one group
+                                 past the first step that has a reject cutoff, in whole code
+                                 units; a batch whose survivors overflow at that depth is
+                                 re-run at the deepest available); else the most groups
+                                 scanned for a pair before it moves to the per-pair pass (a tuning knob: results do
                                  not depend on it).  Clamped to the groups available: with
                                  codes, the groups that carry codes (whole code units of
                                  pk groups, pk = min(floor(32 / k'), L) for k' <= 16, else 1:

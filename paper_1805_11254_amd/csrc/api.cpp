@@ -159,7 +159,7 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
     Workspace &ws = idx->ws;
 
     ScanTab tab{};
-    uint32_t depth = 0;
+    uint32_t depth = 0, maxd = 0;
     const bool use_codes = kind != QueryKind::OPH_FULL && qp->coarse_filter == HOPH_COARSE_CODES && idx->codes;
     if (kind != QueryKind::OPH_FULL) {
         hoph_decision_tables t;
@@ -167,8 +167,8 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
         st = build_tables(lay, *qp, kind == QueryKind::GOPH, t, err);
         if (st) return fail(st, err);
         to_scan_tab(t, tab);
-        const uint32_t maxd = use_codes ? idx->cg : std::min(max_depth_for_kpad(idx->kpad), lay.L);
-        depth = default_coarse_depth(tab, qp->coarse_depth, maxd);
+        maxd = use_codes ? idx->cg : std::min(max_depth_for_kpad(idx->kpad), lay.L);
+        depth = default_coarse_depth(tab, qp->coarse_depth, maxd, use_codes ? code_pack(lay.kp, lay.L) : 1u);
     }
 
     ScanLaunch a{};
@@ -252,6 +252,9 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
             record_timing();
             return HOPH_OK;
         }
+        // survivors overflowed at the library's depth: walk every group that can be
+        // walked before splitting the batch (a deeper pass keeps fewer pairs)
+        if (surv > ws.surv_cap && qp->coarse_depth == 0 && a.depth < maxd) a.depth = maxd;
     }
 
     uint64_t accepted = 0;

@@ -349,11 +349,14 @@ hoph_status build_tables(const LayoutInfo &lay, const hoph_query_params &qp, boo
 void to_scan_tab(const hoph_decision_tables &t, ScanTab &s);
 // Coarse depth when the caller leaves it to the library: the first group alone
 // when it rejects at least one eighth of its bins' match counts (the
-// one-group pass, whose survivors are then sparse), else the deepest available
-// depth (the coarse kernels stop walking once every lane is decided, so depth
-// costs only where pairs are still open); `requested` > 0 wins, clamped to
-// [1, maxd].
-uint32_t default_coarse_depth(const ScanTab &tab, uint32_t requested, uint32_t maxd);
+// one-group pass, whose survivors are then sparse); else one group past the
+// first step that has a reject cutoff, rounded up to a whole code unit of pk
+// groups (a pass that stops before any step can reject keeps every pair; one
+// more step settles most of the rest, and the per-survivor pass the few left);
+// at most maxd.  `requested` > 0 wins, clamped to [1, maxd].  A query whose
+// pass at the library's depth overflows the survivor buffer is re-run at maxd
+// before it is split into sub-batches.
+uint32_t default_coarse_depth(const ScanTab &tab, uint32_t requested, uint32_t maxd, uint32_t pk);
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (k_*.hip).  All return hipError_t of the launch.

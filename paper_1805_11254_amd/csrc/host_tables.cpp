@@ -450,9 +450,18 @@ void to_scan_tab(const hoph_decision_tables &t, ScanTab &s) {
     }
 }
 
-uint32_t default_coarse_depth(const ScanTab &tab, uint32_t requested, uint32_t maxd) {
+uint32_t default_coarse_depth(const ScanTab &tab, uint32_t requested, uint32_t maxd, uint32_t pk) {
     uint32_t d = requested;
-    if (d == 0) d = (8 * (int64_t)tab.mrej0[0] >= (int64_t)tab.kp && tab.mrej0[0] >= 0) ? 1u : maxd;
+    if (d == 0) {
+        if (8 * (int64_t)tab.mrej0[0] >= (int64_t)tab.kp && tab.mrej0[0] >= 0) {
+            d = 1;
+        } else {
+            uint32_t g = 0;                  // groups up to and including the first with a reject cutoff
+            while (g < tab.L && tab.rej[g] < 0) ++g;
+            d = g < tab.L ? g + 2 : maxd;    // one group past it
+            if (pk > 1) d = (d + pk - 1) / pk * pk;
+        }
+    }
     return std::max<uint32_t>(1, std::min(d, maxd));
 }
 

@@ -336,7 +336,7 @@ hoph_status hoph_plan_create(hoph_index *idx, const hoph_sketch_params *params, 
     to_scan_tab(t, p->tab);
     p->codes = qp->coarse_filter == HOPH_COARSE_CODES && idx->codes;
     const uint32_t maxd = p->codes ? idx->cg : std::min(max_depth_for_kpad(idx->kpad), idx->lay.L);
-    p->depth = default_coarse_depth(p->tab, qp->coarse_depth, maxd);
+    p->depth = default_coarse_depth(p->tab, qp->coarse_depth, maxd, p->codes ? code_pack(idx->lay.kp, idx->lay.L) : 1u);
     const uint64_t Q = cfg->max_queries, k = params->k, L = idx->lay.L;
     p->surv_cap = std::max<uint64_t>(idx->capacity, 1u << 20);
     p->keys_cap = sort_capacity(std::max<uint64_t>(cfg->max_results, 1));

@@ -343,14 +343,17 @@ def test_results_capacity_reports_needed():
 
 @pytest.mark.parametrize("layout,k,kp,kind,depth", [(W.LAYOUT_HIER, 256, 32, "hoph", 1),
                                                      (W.LAYOUT_HIER, 256, 32, "hoph", 4),
-                                                     (W.LAYOUT_OPH, 320, 10, "goph", 27)])
+                                                     (W.LAYOUT_OPH, 320, 10, "goph", 27),
+                                                     (W.LAYOUT_HIER, 256, 32, "hoph", 0),
+                                                     (W.LAYOUT_OPH, 320, 10, "goph", 0)])
 def test_survivor_overflow_path_matches_oracle(layout, k, kp, kind, depth):
     """Near-identical collection: every pair survives the coarse pass, more
     survivors than the survivor buffer holds, so the batch is re-run in
     sub-batches; the result must still be exact.  The first-group pass, the
     register-resident pass over 4 groups and the LDS-staged deep pass (GOPH,
     27 groups of 10 bins in 9 code units) each append through their
-    wavefront's batch."""
+    wavefront's batch; at the library's own depth (0) the overflowing batch
+    is first re-run at the deepest depth, then split."""
     _print_case(f"survivor overflow layout={layout} k={k} kp={kp} depth={depth}")
     rng = np.random.default_rng(5)
     base = rng.choice(1 << 20, size=300, replace=False)
