@@ -646,6 +646,44 @@ def test_deep_code_pass_matches_oracle(k, kp):
     idx.free()
 
 
+def _default_depth(p, T, eps, kp, cg, pk):
+    """The documented default coarse depth: the first group alone when it
+    rejects at least 1/8 of its match counts, else one group past the first
+    step with a reject cutoff, rounded up to whole code units, at most cg."""
+    t = H.decision_tables(p, T, eps)
+    unit0 = t["W"][0] * t["dmul"][0]
+    m0 = t["rej"][0] // unit0 if t["rej"][0] >= 0 else -1
+    if m0 >= 0 and 8 * m0 >= kp:
+        return 1
+    g1 = next((l + 1 for l, r in enumerate(t["rej"]) if r >= 0), None)
+    return cg if g1 is None else min(cg, -(-(g1 + 1) // pk) * pk)
+
+
+@pytest.mark.parametrize("layout,k,kp,ra,rb,T,want", [(W.LAYOUT_OPH, 320, 32, 1, 1, (7, 10), 4),
+                                                      (W.LAYOUT_OPH, 320, 10, 1, 1, (7, 10), 12),
+                                                      (W.LAYOUT_OPH, 320, 10, 1, 1, (1, 2), 18),
+                                                      (W.LAYOUT_HIER, 512, 32, 1, 1, (4, 5), 1),
+                                                      (W.LAYOUT_HIER, 256, 16, 1, 2, (1, 2), None)])
+def test_default_coarse_depth(layout, k, kp, ra, rb, T, want):
+    """The plan reports the depth the library picked when the caller leaves it
+    open, which is the documented rule (worked values: GOPH k' = 32 at T = 0.7
+    first rejects at group 3, so 4; k' = 10 at group 10, so 11, rounded up to
+    the 3-group code unit: 12)."""
+    _print_case(f"default depth layout={layout} k={k} kp={kp} {ra}:{rb} T={T}")
+    w = W.hoph_bovw(n=500, n_q=4, seed=7, k=k, kp=kp)
+    w.layout, w.ra, w.rb = layout, ra, rb
+    p = params_of(w)
+    idx = H.Index(p, gpu_sketch(w, w.collection, p))
+    cg, pk = _code_groups(kp, k // kp, hier=layout == W.LAYOUT_HIER)
+    expect = _default_depth(p, T, (1, 10_000), kp, cg, pk)
+    if want is not None:
+        assert expect == want
+    plan = H.Plan(idx, p, T=T, eps=(1, 10_000), max_queries=8, max_query_ids=1 << 16, use_graph=False)
+    assert plan.info()["depth"] == expect
+    plan.free()
+    idx.free()
+
+
 @pytest.mark.parametrize("n_sets", [9_000, 20_000])
 def test_queries_with_thousands_of_results_match_oracle(n_sets):
     """Near-identical collections: each query accepts thousands of sets, sorted
