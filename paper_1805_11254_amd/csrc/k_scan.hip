@@ -19,9 +19,10 @@
 // in batches (one atomic per batch), the word pass with one atomic per
 // wavefront and step (ballot + rank).
 //
-// Fine pass: one wavefront per survivor, one lane per bin, groups read a few
-// at a time; counts come from ballots and popcounts, the decision is
-// wave-uniform, and the wavefront leaves at the first deciding group.
+// Fine pass: one wavefront per survivor; floor(64 / k') groups side by side
+// across the lanes of a load (one lane per bin) and two to four loads per
+// step; counts come from ballots and popcounts, the decision is wave-uniform,
+// and the wavefront leaves at the first deciding group.
 #include "hoph_internal.h"
 
 namespace hoph {
@@ -30,7 +31,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kFineAhead = 4;          // groups read ahead per survivor in the fine pass
+constexpr int kFineAhead = 4;          // most loads per step in the fine pass (k' > 32; else 2)
 // Tiles of 64 sets per wavefront in the first-group code pass: eight for the
 // two-plane first phase over one plane word (its registers hold 8 planes of 8
 // tiles), else four (two with two plane words).
@@ -755,40 +756,52 @@ __global__ __launch_bounds__(kThreads) void scan_fine_kernel(const uint32_t *__r
     const uint64_t nw = (uint64_t)gridDim.x * kWaves;
     const uint64_t n = min((uint64_t)counters[0], a.surv_cap);
     const uint32_t kp = a.kp;
-    const bool in = lane < kp;
+    // P groups side by side across the lanes of one load (lane = c k' + bin),
+    // R loads per step: P R groups are read at once (independent loads in
+    // flight), then decided in order; reads past the deciding group are discarded
+    const uint32_t P = 64u / kp, R = kp > 32 ? (uint32_t)kFineAhead : 2u, span = P * R;
+    const uint32_t lc = lane / kp, lb = lane - lc * kp;
+    const bool in = lc < P;
+    const uint64_t kpmask = kp >= 64 ? ~0ull : ((1ull << kp) - 1ull);
     for (uint64_t idx = (uint64_t)blockIdx.x * kWaves + wave_id_in_block(); idx < n; idx += nw) {
         const Survivor sv = surv[idx];
         int64_t S = sv.S;
         bool accept = false;
         const uint64_t s = sv.s;
-        const uint32_t *qw = qsigs + (uint64_t)sv.q * a.k;
-        const uint32_t *sb = slab + s * a.k + lane;
-        // kFineAhead groups are read at once (independent loads in flight), then
-        // decided in order; reads past the deciding group are discarded
+        const uint32_t *qw = qsigs + (uint64_t)sv.q * a.k + lb;
+        const uint32_t *sb = slab + s * a.k + lb;
         bool done = false;
-        for (uint32_t g0 = a.depth; g0 < a.L && !done; g0 += kFineAhead) {
+        for (uint32_t g0 = a.depth; g0 < a.L && !done; g0 += span) {
             uint32_t sw[kFineAhead], qv[kFineAhead];
 #pragma unroll
-            for (int c = 0; c < kFineAhead; ++c) {
-                const uint32_t g = g0 + c;
-                sw[c] = qv[c] = 0;
-                if (in && g < a.L) {
-                    sw[c] = sb[g * kp];
-                    qv[c] = qw[g * kp + lane];
+            for (int r = 0; r < kFineAhead; ++r) {
+                const uint32_t g = g0 + (uint32_t)r * P + lc;
+                sw[r] = qv[r] = 0;
+                if ((uint32_t)r < R && in && g < a.L) {
+                    sw[r] = sb[g * kp];
+                    qv[r] = qw[g * kp];
                 }
             }
 #pragma unroll
-            for (int c = 0; c < kFineAhead; ++c) {
-                const uint32_t g = g0 + c;
-                if (g >= a.L) break;
-                const uint64_t eqb = __ballot(in && sw[c] == qv[c]);
-                const uint64_t qe = __ballot(in && qv[c] == HOPH_EMPTY);
-                const uint64_t se = __ballot(in && sw[c] == HOPH_EMPTY);
-                const uint32_t ej = __popcll(qe & se), ee = __popcll(qe | se);
-                const uint32_t eq = __popcll(eqb);
-                S += tab.W[g] * group_rho(eq, ej, ee, kp, a.policy, s_dmul, tab.lambda);
-                if (S >= tab.acc[g]) { accept = true; done = true; break; }
-                if (S <= tab.rej[g]) { done = true; break; }
+            for (int r = 0; r < kFineAhead; ++r) {
+                if ((uint32_t)r >= R || done) break;
+                const uint32_t gr = g0 + (uint32_t)r * P;
+                if (gr >= a.L) break;
+                const bool live = in && gr + lc < a.L;
+                const uint64_t eqb = __ballot(live && sw[r] == qv[r]);
+                const uint64_t qe = __ballot(live && qv[r] == HOPH_EMPTY);
+                const uint64_t se = __ballot(live && sw[r] == HOPH_EMPTY);
+                for (uint32_t c = 0; c < P; ++c) {
+                    const uint32_t g = gr + c;
+                    if (g >= a.L) break;
+                    const uint32_t sh = c * kp;
+                    const uint64_t qec = (qe >> sh) & kpmask, sec = (se >> sh) & kpmask;
+                    const uint32_t ej = __popcll(qec & sec), ee = __popcll(qec | sec);
+                    const uint32_t eq = __popcll((eqb >> sh) & kpmask);
+                    S += tab.W[g] * group_rho(eq, ej, ee, kp, a.policy, s_dmul, tab.lambda);
+                    if (S >= tab.acc[g]) { accept = true; done = true; break; }
+                    if (S <= tab.rej[g]) { done = true; break; }
+                }
             }
         }
         if (accept && lane == 0) {
