@@ -229,8 +229,8 @@ __device__ __forceinline__ uint32_t code_diff_part(uint32_t d, const uint32_t *P
 // a unit) against the query's empty mask qm of the group, added to the
 // weighted state S, and the step's cutoffs applied to a lane still undecided
 // (maybe: an accept cutoff was reached, so the pair must go on to the fine
-// pass).
-template <int W>
+// pass).  UNITW: every weight is 1 (GOPH), no multiply.
+template <int W, bool UNITW>
 __device__ __forceinline__ void code_group_step(const uint32_t (&d)[W], const uint32_t *em, uint32_t o, uint64_t qm,
                                                 uint64_t kpmask, uint32_t kp, uint32_t policy, const int64_t *s_dmul,
                                                 int64_t lambda, int64_t Wg, int64_t accg, int64_t rejg, int64_t &S,
@@ -248,7 +248,9 @@ __device__ __forceinline__ void code_group_step(const uint32_t (&d)[W], const ui
     const uint32_t eq_q = (uint32_t)__popcll(qm);
     const uint32_t m = kp - eq_q - dn;        // >= the matched non-empty bins
     const uint32_t ej = eq_q - de;            // jointly empty bins, exact
-    S += Wg * group_rho(m + ej, ej, ee, kp, policy, s_dmul, lambda);
+    const int64_t rho = group_rho(m + ej, ej, ee, kp, policy, s_dmul, lambda);
+    if constexpr (UNITW) S += rho;
+    else S += Wg * rho;
     if (undecided) {
         if (S >= accg) {
             maybe = true;
@@ -262,7 +264,7 @@ __device__ __forceinline__ void code_group_step(const uint32_t (&d)[W], const ui
 // The groups of code unit u (planes P, set-empty masks em) for one query, up
 // to group cd: the unit's differing-code mask is formed once and each of its
 // groups (pk of them; one without PACK) takes its own bits.
-template <int W, bool PACK>
+template <int W, bool PACK, bool UNITW>
 __device__ __forceinline__ void code_unit_steps(uint32_t u, const uint32_t *P, const uint32_t *em,
                                                 const uint32_t *__restrict__ qc, const uint64_t *__restrict__ qmk,
                                                 uint32_t pk, uint32_t cd, uint64_t kpmask, uint32_t kp,
@@ -276,11 +278,11 @@ __device__ __forceinline__ void code_unit_steps(uint32_t u, const uint32_t *P, c
     if constexpr (PACK) {
         for (uint32_t j = 0, g = g0; j < pk && g < cd; ++j, ++g) {
             if (j > 0 && !__any(undecided)) break;
-            code_group_step<W>(d, em, j * kp, qmk[g], kpmask, kp, policy, s_dmul, tab.lambda, tab.W[g], tab.acc[g],
+            code_group_step<W, UNITW>(d, em, j * kp, qmk[g], kpmask, kp, policy, s_dmul, tab.lambda, tab.W[g], tab.acc[g],
                                tab.rej[g], S, undecided, maybe);
         }
     } else {
-        code_group_step<W>(d, em, 0u, qmk[g0], kpmask, kp, policy, s_dmul, tab.lambda, tab.W[g0], tab.acc[g0],
+        code_group_step<W, UNITW>(d, em, 0u, qmk[g0], kpmask, kp, policy, s_dmul, tab.lambda, tab.W[g0], tab.acc[g0],
                            tab.rej[g0], S, undecided, maybe);
     }
 }
@@ -294,9 +296,9 @@ __device__ __forceinline__ void code_unit_steps(uint32_t u, const uint32_t *P, c
 // below the reject cutoff, with no earlier step at or above an accept cutoff.
 // Every other pair goes to the fine pass, which restarts from the first group
 // on the 32-bit words.  PACK: units of several small groups, walked up to group
-// a.cdepth.  (Depth 1 under JOINT or LITERAL runs in scan_codes_fast_kernel
-// instead.)
-template <int W, int G, bool PACK>
+// a.cdepth; UNITW: every weight up to that depth is 1.  (Depth 1 under JOINT or
+// LITERAL runs in scan_codes_fast_kernel instead.)
+template <int W, int G, bool PACK, bool UNITW>
 __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__restrict__ codes,
                                                              const uint32_t *__restrict__ qcodes,
                                                              const uint64_t *__restrict__ qmasks,
@@ -365,8 +367,8 @@ __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__
 #pragma unroll
             for (int u = 0; u < G; ++u) {
                 if (!__any(undecided)) break;
-                code_unit_steps<W, PACK>((uint32_t)u, P[u], em[u], qc, qmk, pk, cd, kpmask, kp, policy, s_dmul, tab,
-                                         S, undecided, maybe);
+                code_unit_steps<W, PACK, UNITW>((uint32_t)u, P[u], em[u], qc, qmk, pk, cd, kpmask, kp, policy, s_dmul,
+                                                tab, S, undecided, maybe);
             }
             survive = maybe || undecided;
         }
@@ -385,7 +387,7 @@ __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__
 // reads back its own words, so the wavefront's program order is the only
 // ordering needed).  Each query walks the groups, up to group a.cdepth, until
 // every lane is decided.
-template <int W, bool PACK, int R>
+template <int W, bool PACK, int R, bool UNITW>
 __global__ __launch_bounds__(64) void scan_codes_deep_kernel(const uint32_t *__restrict__ codes,
                                                            const uint32_t *__restrict__ qcodes,
                                                            const uint64_t *__restrict__ qmasks,
@@ -453,8 +455,8 @@ __global__ __launch_bounds__(64) void scan_codes_deep_kernel(const uint32_t *__r
 #pragma unroll
             for (int u = 0; u < R; ++u) {
                 if (!__any(undecided)) break;
-                code_unit_steps<W, PACK>((uint32_t)u, P[u], em[u], qc, qmk, pk, cd, kpmask, kp, policy, s_dmul, tab,
-                                         S, undecided, maybe);
+                code_unit_steps<W, PACK, UNITW>((uint32_t)u, P[u], em[u], qc, qmk, pk, cd, kpmask, kp, policy, s_dmul,
+                                                tab, S, undecided, maybe);
             }
             for (uint32_t u = R; u < cu; ++u) {
                 if (!__any(undecided)) break;
@@ -493,8 +495,8 @@ __global__ __launch_bounds__(64) void scan_codes_deep_kernel(const uint32_t *__r
 #pragma unroll
                     for (int w = 0; w < W; ++w) emu[w] = s_em[(r * W + w) * 64 + lane];
                 }
-                code_unit_steps<W, PACK>(u, Pu, emu, qc, qmk, pk, cd, kpmask, kp, policy, s_dmul, tab, S, undecided,
-                                         maybe);
+                code_unit_steps<W, PACK, UNITW>(u, Pu, emu, qc, qmk, pk, cd, kpmask, kp, policy, s_dmul, tab, S,
+                                                undecided, maybe);
             }
             const bool survive = maybe || undecided;
             sb.push(__ballot(survive), q, (uint32_t)s, surv, a.surv_cap, counters + 0, lane);
@@ -977,12 +979,12 @@ CoarseArgs coarse_args(const ScanLaunch &l, uint32_t policy) {
 
 // The code pass over du code units held in VGPRs (du <= kMaxDepth): depth 1
 // (JOINT or LITERAL) in scan_codes_fast_kernel, else scan_codes_kernel.
-template <int W, bool PACK>
+template <int W, bool PACK, bool UNITW>
 void codes_launch(const ScanLaunch &l, const CoarseArgs &a, const ScanTab &tab, hipStream_t st, uint32_t blocks,
                   uint32_t du) {
     auto *cnt = reinterpret_cast<unsigned long long *>(l.counters);
 #define HOPH_CODES(G)                                                                                         \
-    hipLaunchKernelGGL((scan_codes_kernel<W, G, PACK>), dim3(blocks), dim3(kThreads), 0, st, l.codes,        \
+    hipLaunchKernelGGL((scan_codes_kernel<W, G, PACK, UNITW>), dim3(blocks), dim3(kThreads), 0, st, l.codes, \
                        l.qcodes, l.qmasks, l.surv, cnt, l.desc, a, tab)
     if (l.depth == 1 && tab.policy != HOPH_EMPTY_EITHER) {
         const int split = plane_split(tab, l.kp);
@@ -1108,6 +1110,8 @@ hipError_t launch_scan_coarse(const ScanLaunch &l, const ScanTab &tab, hipStream
         if (l.depth == 0 || l.depth > l.cg) return hipErrorInvalidValue;
         const uint32_t W = code_plane_words(l.kp), pk = a.pk, du = (l.depth + pk - 1) / pk;   // code units walked
         const bool pack = pk > 1;            // only with one plane word (k' <= 16)
+        bool unitw = true;                   // every weight the pass can reach is 1 (GOPH)
+        for (uint32_t g = 0; g < std::min<uint32_t>(du * pk, tab.L); ++g) unitw = unitw && tab.W[g] == 1;
         if (du > kMaxDepth) {
             // past the register-resident units: one wavefront per block, planes staged in LDS
             if (du > max_code_units(l.kp)) return hipErrorInvalidValue;
@@ -1131,8 +1135,14 @@ hipError_t launch_scan_coarse(const ScanLaunch &l, const ScanTab &tab, hipStream
             const size_t lds = (size_t)(du - R) * 64 * (code_words(l.kp) * 4 + 4 * W);
             auto *cnt = reinterpret_cast<unsigned long long *>(l.counters);
 #define HOPH_DEEP(WW, PACK, RR)                                                                                \
-    hipLaunchKernelGGL((scan_codes_deep_kernel<WW, PACK, RR>), dim3(deep_blocks), dim3(64), lds, st, l.codes,  \
-                       l.qcodes, l.qmasks, l.surv, cnt, l.desc, a, tab, du)
+    do {                                                                                                       \
+        if (unitw)                                                                                             \
+            hipLaunchKernelGGL((scan_codes_deep_kernel<WW, PACK, RR, true>), dim3(deep_blocks), dim3(64), lds,  \
+                               st, l.codes, l.qcodes, l.qmasks, l.surv, cnt, l.desc, a, tab, du);               \
+        else                                                                                                   \
+            hipLaunchKernelGGL((scan_codes_deep_kernel<WW, PACK, RR, false>), dim3(deep_blocks), dim3(64), lds, \
+                               st, l.codes, l.qcodes, l.qmasks, l.surv, cnt, l.desc, a, tab, du);               \
+    } while (0)
             if (W == 1) {
                 if (r8) {
                     if (pack) HOPH_DEEP(1, true, 8);
@@ -1148,10 +1158,16 @@ hipError_t launch_scan_coarse(const ScanLaunch &l, const ScanTab &tab, hipStream
             return hipGetLastError();
         }
         if (W == 1) {
-            if (pack) codes_launch<1, true>(l, a, tab, st, blocks, du);
-            else codes_launch<1, false>(l, a, tab, st, blocks, du);
+            if (pack) {
+                if (unitw) codes_launch<1, true, true>(l, a, tab, st, blocks, du);
+                else codes_launch<1, true, false>(l, a, tab, st, blocks, du);
+            } else {
+                if (unitw) codes_launch<1, false, true>(l, a, tab, st, blocks, du);
+                else codes_launch<1, false, false>(l, a, tab, st, blocks, du);
+            }
         } else {
-            codes_launch<2, false>(l, a, tab, st, blocks, du);
+            if (unitw) codes_launch<2, false, true>(l, a, tab, st, blocks, du);
+            else codes_launch<2, false, false>(l, a, tab, st, blocks, du);
         }
         return hipGetLastError();
     }
