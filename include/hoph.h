@@ -180,8 +180,8 @@ hoph_status hoph_query_timing(const hoph_index *index, float ms[3]);
 
 /* hoph_append_timing -- device time of the last index_append_sets call on this
    index, in ms: ms[0] the sketch into the index rows, ms[1] the code planes of
-   the new rows (0 where the sketch writes them itself: odd k' or k) (zeros
-   before any call).  Waits for that call to finish. */
+   the new rows (0 where the sketch writes them itself: an odd code-unit width
+   or odd k) (zeros before any call).  Waits for that call to finish. */
 hoph_status hoph_append_timing(const hoph_index *index, float ms[2]);
 
 /* hoph_index_code_planes -- copies the index's narrowed code planes (a test
