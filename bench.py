@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--batches", type=int, default=256)
     ap.add_argument("--rates", type=str, default="20000,50000,100000,200000")
     ap.add_argument("--serve-seconds", type=float, default=0.5)
+    ap.add_argument("--serve-rate", type=float, default=50_000,
+                    help="offered queries/s of the step's serving measurement (0 = skip it)")
     return ap.parse_args()
 
 
@@ -273,6 +275,10 @@ def bench_serve(args):
 
     for r in rates:
         n = max(1, int(r * args.serve_seconds))
+        # 0.1 s at this rate first: the batch shapes it forms are tuned and
+        # captured before the measurement
+        t_w, wq = W.poisson_arrivals(r, max(1, int(r * 0.1)), args.seed + 1 + int(r))
+        srv.replay(wq.ids, wq.offsets, t_w - t_w[0])
         t, q = W.poisson_arrivals(r, n, args.seed + int(r))
         srv.reset_stats()
         stop = threading.Event()
@@ -867,6 +873,29 @@ def main():
         "recall_planted": recall,
         "precision_exact_jaccard": precision,
     }
+    if args.serve_rate > 0:
+        # serving on the same resident index, outside the timed region: Poisson
+        # arrivals of single query sets (log-normal sizes, median 800 ids) at a
+        # fixed rate, after a warm-up replay (tuning, graph capture); latency per
+        # request from arrival to its result list
+        log(f"serving at {args.serve_rate:.0f} q/s for {args.serve_seconds} s")
+        srv = H.Server(idx, p, T=w.T, eps=w.eps, slots=4, max_batch_queries=2048, max_batch_ids=1 << 22,
+                       max_batch_results=1 << 20, use_graph=True, tune=True)
+        # warm-up at the measured rate, so that the batch shapes it forms are
+        # tuned and captured before the measurement
+        t_w, wq = W.poisson_arrivals(args.serve_rate, max(1, int(args.serve_rate * 0.1)), args.seed + 70)
+        srv.replay(wq.ids, wq.offsets, t_w - t_w[0])
+        n_req = max(1, int(args.serve_rate * args.serve_seconds))
+        t_s, sq = W.poisson_arrivals(args.serve_rate, n_req, args.seed + 71)
+        srv.reset_stats()
+        srv.replay(sq.ids, sq.offsets, t_s - t_s[0])
+        st = srv.stats()
+        srv.close()
+        rec["served_p99_ms"] = st["p99_ms"]
+        rec["serving"] = {"offered_qps": args.serve_rate, "requests": n_req,
+                          "served_qps": st["completed"] / max(st["busy_s"], 1e-9), "p50_ms": st["p50_ms"],
+                          "p99_ms": st["p99_ms"], "mean_batch": st["mean_batch_queries"],
+                          "index_sets": len(idx)}
     idx.free()
     if not args.no_cpu_baseline:
         log("timing the oracle on a CPU sample")
