@@ -455,3 +455,43 @@ void hoph_plan_free(hoph_plan *p) {
 }
 
 }  // extern "C"
+
+namespace hoph {
+
+hoph_status plan_results_to_host(hoph_plan *p, uint64_t *h_offsets, uint32_t *h_ids, uint64_t pre,
+                                 uint64_t *n_results, hipStream_t st) {
+    if (!p || !h_offsets || !h_ids || !n_results) return fail(HOPH_E_INVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (!p->pending) return fail(HOPH_E_INVAL, "no batch has been run");
+    DeviceGuard dg(p->idx->device);
+    const uint32_t n_q = p->last_nq;
+    pre = std::min<uint64_t>(pre, p->cfg.max_results);
+    HOPH_HIP(hipMemcpyAsync(p->h_counters, p->counters, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, st),
+             "read counters");
+    HOPH_HIP(hipMemcpyAsync(h_offsets, p->out_offsets, ((uint64_t)n_q + 1) * 8, hipMemcpyDeviceToHost, st),
+             "read result offsets");
+    if (pre) HOPH_HIP(hipMemcpyAsync(h_ids, p->out_ids, pre * 4, hipMemcpyDeviceToHost, st), "read result ids");
+    HOPH_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    const uint64_t surv = p->h_counters[0], acc = p->h_counters[1], total = p->h_counters[2], flags = p->h_counters[3];
+    uint64_t n = total, have = pre;
+    if (!(surv <= p->surv_cap && acc <= p->keys_cap && (flags & 3ull) == 0)) {
+        // redo on the host-synchronised path with the batch's signatures
+        ++p->fallbacks;
+        hoph_results r{p->out_offsets, p->out_ids, p->cfg.max_results, 0};
+        hoph_status s = run_query(p->idx, p->q_sigs, n_q, &p->qp, &r, st, p->kind);
+        if (s) return s;
+        n = r.needed;
+        HOPH_HIP(hipMemcpyAsync(h_offsets, p->out_offsets, ((uint64_t)n_q + 1) * 8, hipMemcpyDeviceToHost, st),
+                 "read result offsets");
+        have = 0;
+    }
+    if (n > p->cfg.max_results) return fail(HOPH_E_CAPACITY, "batch results exceed the plan's max_results");
+    if (n > have)
+        HOPH_HIP(hipMemcpyAsync(h_ids + have, p->out_ids + have, (n - have) * 4, hipMemcpyDeviceToHost, st),
+                 "read result ids");
+    if (n > have || have == 0) HOPH_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    *n_results = n;
+    return HOPH_OK;
+}
+
+}  // namespace hoph

@@ -193,4 +193,11 @@ hipError_t append_sets_async(hoph_index *idx, const uint32_t *d_ids, const uint6
 // GOPH / HOPH / plain-OPH query through the index's own workspace (host-synchronised).
 hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t n_q, const hoph_query_params *qp,
                       hoph_results *res, void *stream, QueryKind kind, bool self_join = false);
+// The results of a plan's last batch copied to host buffers with one stream
+// synchronisation in the usual case: the counters, the CSR offsets (n_q + 1)
+// and the first `pre` ids are read together; more ids are read only when the
+// batch returned more than `pre`, or when it took the host-synchronised
+// fallback.  h_ids holds the plan's max_results ids; pre <= max_results.
+hoph_status plan_results_to_host(hoph_plan *p, uint64_t *h_offsets, uint32_t *h_ids, uint64_t pre,
+                                 uint64_t *n_results, hipStream_t st);
 }  // namespace hoph

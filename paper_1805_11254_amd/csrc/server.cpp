@@ -24,6 +24,7 @@ using namespace hoph;
 namespace {
 
 using Clock = std::chrono::steady_clock;
+constexpr uint64_t kResultsPrefetch = 4096;   // result ids read back with the counters (16 KB)
 
 struct Request {
     uint64_t ticket = 0;
@@ -97,16 +98,11 @@ hoph_status run_batch(hoph_server *srv, Slot &sl, std::vector<std::shared_ptr<Re
              "stage request offsets");
     hoph_status st = hoph_plan_run(sl.plan, sl.d_ids, sl.d_offs, n_q, n_ids, sl.stream);
     if (st) return st;
-    const uint64_t *d_ro = nullptr;
-    const uint32_t *d_ri = nullptr;
+    // counters, offsets and the first ids in one read-back (a second only for
+    // a batch with more results, or one that fell back)
     uint64_t n_res = 0;
-    st = hoph_plan_results(sl.plan, &d_ro, &d_ri, &n_res, sl.stream);
+    st = plan_results_to_host(sl.plan, sl.h_res_offs, sl.h_res_ids, kResultsPrefetch, &n_res, sl.stream);
     if (st) return st;
-    HOPH_HIP(hipMemcpyAsync(sl.h_res_offs, d_ro, ((uint64_t)n_q + 1) * 8, hipMemcpyDeviceToHost, sl.stream),
-             "read result offsets");
-    if (n_res)
-        HOPH_HIP(hipMemcpyAsync(sl.h_res_ids, d_ri, n_res * 4, hipMemcpyDeviceToHost, sl.stream), "read result ids");
-    HOPH_HIP(hipStreamSynchronize(sl.stream), "hipStreamSynchronize");
     for (size_t i = 0; i < batch.size(); ++i)
         batch[i]->result.assign(sl.h_res_ids + sl.h_res_offs[i], sl.h_res_ids + sl.h_res_offs[i + 1]);
     return HOPH_OK;
