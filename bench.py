@@ -104,10 +104,13 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hoph11_bovw_1M_pmc_traffic.txt")
 
 
 def kernel_source_hash() -> str:
+    """SHA-256 of the device code (the HIP kernels and the header they share):
+    the counters in the profiles depend on nothing else."""
     import glob
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1805_11254_amd", "csrc", "*"))):
+    csrc = os.path.join(ROOT, "paper_1805_11254_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "k_*.hip")) + [os.path.join(csrc, "hoph_internal.h")]):
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
