@@ -25,6 +25,14 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 constexpr uint64_t kResultsPrefetch = 4096;   // result ids read back with the counters (16 KB)
+// Under load (at least kGatherBusy other slots running a batch) a free worker
+// waits up to kGatherUs for kGatherQueries requests before it starts: every
+// batch re-reads the whole index's first-group codes, so a few larger batches
+// serve more queries per second than many small ones.  With the device idle a
+// request starts at once.
+constexpr uint32_t kGatherBusy = 2;
+constexpr size_t kGatherQueries = 64;
+constexpr int kGatherUs = 200;
 
 struct Request {
     uint64_t ticket = 0;
@@ -65,6 +73,7 @@ struct hoph_server {
     std::unordered_map<uint64_t, std::shared_ptr<Request>> table;
     uint64_t next_ticket = 1;
     bool stop = false;
+    uint32_t running = 0;            // slots running a batch
     // statistics
     std::vector<double> lat_ms;
     uint64_t submitted = 0, completed = 0, rejected = 0, batches = 0, batch_queries = 0, inserted = 0;
@@ -116,6 +125,11 @@ void worker_loop(hoph_server *srv, Slot *sl) {
             std::unique_lock<std::mutex> lk(srv->mu);
             srv->cv_work.wait(lk, [&] { return srv->stop || !srv->queue.empty(); });
             if (srv->stop && srv->queue.empty()) return;
+            if (!srv->stop && srv->running >= kGatherBusy && srv->queue.size() < kGatherQueries) {
+                srv->cv_work.wait_for(lk, std::chrono::microseconds(kGatherUs),
+                                      [&] { return srv->stop || srv->queue.size() >= kGatherQueries; });
+                if (srv->queue.empty()) continue;     // another worker took them
+            }
             uint64_t ids = 0;
             while (!srv->queue.empty() && batch.size() < srv->cfg.max_batch_queries) {
                 const auto &r = srv->queue.front();
@@ -124,11 +138,13 @@ void worker_loop(hoph_server *srv, Slot *sl) {
                 batch.push_back(r);
                 srv->queue.pop_front();
             }
+            ++srv->running;
         }
         const hoph_status st = run_batch(srv, *sl, batch);
         const auto now = Clock::now();
         {
             std::lock_guard<std::mutex> lk(srv->mu);
+            --srv->running;
             for (auto &r : batch) {
                 r->status = st;
                 r->done = true;
