@@ -55,7 +55,7 @@ def parse():
                          "one-query-per-launch OPH/HOPH and MinWise on the same GPU; selfjoin: every pair inside "
                          "one collection; sweeps: GOPH group count, error tolerance and threshold sweeps")
     ap.add_argument("--batches", type=int, default=256)
-    ap.add_argument("--rates", type=str, default="20000,50000,100000,200000")
+    ap.add_argument("--rates", type=str, default="20000,50000,100000,200000,300000")
     ap.add_argument("--serve-seconds", type=float, default=0.5)
     ap.add_argument("--serve-rate", type=float, default=50_000,
                     help="offered queries/s of the step's serving measurement (0 = skip it)")
