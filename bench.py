@@ -278,8 +278,8 @@ def bench_serve(args):
 
     for r in rates:
         n = max(1, int(r * args.serve_seconds))
-        # 0.1 s at this rate first: the batch shapes it forms are tuned and
-        # captured before the measurement
+        # 0.1 s at this rate first, so that the slots this rate keeps busy have
+        # run (tuned and captured on) their first batch before the measurement
         t_w, wq = W.poisson_arrivals(r, max(1, int(r * 0.1)), args.seed + 1 + int(r))
         srv.replay(wq.ids, wq.offsets, t_w - t_w[0])
         t, q = W.poisson_arrivals(r, n, args.seed + int(r))
@@ -884,8 +884,8 @@ def main():
         log(f"serving at {args.serve_rate:.0f} q/s for {args.serve_seconds} s")
         srv = H.Server(idx, p, T=w.T, eps=w.eps, slots=4, max_batch_queries=2048, max_batch_ids=1 << 22,
                        max_batch_results=1 << 20, use_graph=True, tune=True)
-        # warm-up at the measured rate, so that the batch shapes it forms are
-        # tuned and captured before the measurement
+        # warm-up at the measured rate, so that every slot has run (tuned and
+        # captured its graph on) its first batch before the measurement
         t_w, wq = W.poisson_arrivals(args.serve_rate, max(1, int(args.serve_rate * 0.1)), args.seed + 70)
         srv.replay(wq.ids, wq.offsets, t_w - t_w[0])
         n_req = max(1, int(args.serve_rate * args.serve_seconds))
