@@ -646,6 +646,37 @@ def test_deep_code_pass_matches_oracle(k, kp):
     idx.free()
 
 
+@pytest.mark.parametrize("k,kp,ra,rb", [(256, 16, 1, 2), (256, 16, 2, 1), (128, 8, 1, 2), (96, 12, 2, 1)])
+def test_hoph_ratios_with_code_units(k, kp, ra, rb):
+    """HOPH with unequal weights (1:2, 2:1) and groups small enough to share
+    plane words (code units of 2-4 groups): every depth across the unit
+    boundaries and the library's own, for each empty policy whose tables fit,
+    against the oracle; also the self-join."""
+    _print_case(f"hoph ratios with code units k={k} kp={kp} {ra}:{rb}")
+    w = W.hoph_bovw(n=2_000, n_q=10, seed=71 + kp + ra, k=k, kp=kp, planted_frac=0.03, T=(7, 10))
+    w.layout, w.ra, w.rb = W.LAYOUT_HIER, ra, rb
+    p = params_of(w)
+    sig = gpu_sketch(w, w.collection, p)
+    qsig = gpu_sketch(w, w.queries, p)
+    sh, qh = to_u32(sig), to_u32(qsig)
+    idx = H.Index(p, sig)
+    cg, pk = _code_groups(kp, k // kp, hier=True)
+    assert pk > 1 and idx.code_planes().shape[0] * pk == cg
+    depths = sorted(d for d in {0, 1, 2, pk, pk + 1, cg} if 0 <= d <= cg)
+    for T, eps in (((7, 10), (1, 10_000)), ((1, 2), (1, 1000))):
+        for policy in _policies_that_fit(p, T, eps):
+            oo, oi = oracle_query(w, sh, qh, T, eps, policy)
+            for depth in depths:
+                go, gi = gpu_query("hoph", idx, qsig, T, eps, policy, coarse_depth=depth)
+                assert go.tolist() == oo.tolist() and gi.tolist() == oi.tolist(), (T, eps, policy, depth)
+    T, eps = (7, 10), (1, 10_000)
+    oo, oi = oracle_query(w, sh, sh, T, eps, H.EMPTY_LITERAL)
+    want = [[j for j in row if j > i] for i, row in enumerate(csr_lists(oo, oi))]
+    go, gi = H.self_join(idx, T=T, eps=eps, policy=H.EMPTY_LITERAL)
+    assert csr_lists(go.cpu().numpy(), to_u32(gi)) == want
+    idx.free()
+
+
 def _default_depth(p, T, eps, kp, cg, pk):
     """The documented default coarse depth: the first group alone when it
     rejects at least 1/8 of its match counts, else one group past the first
