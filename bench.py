@@ -3,8 +3,8 @@
 
 One step is the whole path over one batch: sketch every set of the collection
 (one shared universal hash, k bins, per-bin minimum) straight into the
-resident index (group-major slabs and the narrowed code planes of the first
-groups), sketch the query batch, and answer every query with the (1:1) HOPH
+resident index (row-major signature rows and the narrowed code planes of the
+first groups), sketch the query batch, and answer every query with the (1:1) HOPH
 scan (coarse pass on codes, per-survivor pass on the words, sorted CSR output).  Workload: 1,000,000
 bag-of-visual-words sets over 2^20 codewords (Zipf(1.1) codewords, log-normal
 sizes, median 600, clipped to [100, 4000]), h(x) = (a x + b) mod (2^31 - 1),
@@ -48,7 +48,11 @@ def parse():
     ap.add_argument("--cpu-sample-queries", type=int, default=512)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for scaling HBM counters)")
-    ap.add_argument("--mode", choices=["step", "batched", "serve", "comparators", "selfjoin", "sweeps"],
+    ap.add_argument("--sweep-q", type=str, default="1,2,4,8,16,32,64,128,256,1024,4096",
+                    help="scansweep: query batch sizes")
+    ap.add_argument("--sweep-sets", type=str, default="1000000,8000000",
+                    help="scansweep: index sizes (k = 512 up to 2,000,000 sets, else 256)")
+    ap.add_argument("--mode", choices=["step", "batched", "serve", "comparators", "selfjoin", "sweeps", "scansweep"],
                     default="step",
                     help="step: the whole-path step (default JSON line); batched: uneven query batches through "
                          "graph-replayed plans; serve: Poisson arrivals through the serving loop; comparators: "
@@ -608,6 +612,92 @@ def bench_sweeps(args):
     print(json.dumps(out), flush=True)
 
 
+def _code_pass_shape(H, p, T, eps, goph=False):
+    """(depth, plane words W, first-phase planes P1, lane-ops per pair and coded
+    group, bytes of one query record) of the coarse pass on codes, as the
+    library picks them (see the step's accounting below)."""
+    tabs = H.decision_tables(p, T, eps)
+    kp, k = p.k_group, p.k
+    unit0 = tabs["W"][0] * tabs["dmul"][0]
+    m_rej0 = tabs["rej"][0] // unit0 if tabs["rej"][0] >= 0 else -1
+    W_planes = 1 if kp <= 32 else 2
+    depth, split = None, 0
+    if m_rej0 >= 0 and 8 * m_rej0 >= kp:
+        depth = 1
+        dthr = kp - m_rej0
+        split = 2 if 2 * dthr <= kp else (4 if 4 * dthr <= 3 * kp else 0)
+    ops = W_planes * (split + 2) + 1 if split else 10 * W_planes + 1
+    rec_bytes = (8 * W_planes + 4) * 4
+    return depth, W_planes, split, ops, rec_bytes
+
+
+def bench_scansweep(args):
+    """The coarse pass (first group on 8-bit codes) against the query batch
+    size Q on two resident HOPH (1:1) indexes: the default step's 1,000,000
+    bag-of-visual-words sets at k = 512, and 8,000,000 sets at k = 256 (the
+    serving index), groups of 32, T = 4/5, eps = 1e-4.  Per Q: the mean device
+    time of one coarse pass (launches back to back between HIP events), its
+    algorithmic bytes (each set's first-group code planes, 32 bytes, plus the
+    query records) over that time against the HBM peak, its 32-bit lane-ops
+    against the VALU peak, and the host wall time of one whole query_hoph call
+    (tables, records, coarse and fine passes, output, read-back)."""
+    import numpy as np
+    import torch
+    import paper_1805_11254_amd as H
+    import workloads as W
+    dev = torch.device("cuda")
+    qs_list = [int(x) for x in args.sweep_q.split(",")]
+    a, b = W.hash_coeffs(W.P31, 1, args.seed + 3)
+    T, eps = (4, 5), (1, 10000)
+    qmax = max(qs_list)
+    qsets = W.zipf_sets(qmax, 1 << 20, 600, 0.75, 100, 4000, args.seed + 1)
+    out = {"metric": "coarse pass HBM rate against query batch size", "unit": "GB/s", "mode": "scansweep",
+           "indexes": []}
+    sizes = [int(x) for x in args.sweep_sets.split(",")]
+    for N in sizes:
+        k = 512 if N <= 2_000_000 else 256
+        p = H.SketchParams(W.LAYOUT_HIER, k, 32, W.HASH_MODP31, 1 << 20, 1, 1, int(a[0]), int(b[0]))
+        idx = _resident_index(H, p, N, args.seed)
+        qids, qoffs = (torch.from_numpy(qsets.ids.view(np.int32)).to(dev),
+                       torch.from_numpy(qsets.offsets.view(np.int64)).to(dev))
+        qsig = H.sketch_oph(p, qids, qoffs)
+        H.sync()
+        depth, Wp, split, ops, rec_bytes = _code_pass_shape(H, p, T, eps)
+        rows = []
+        for Q in qs_list:
+            q = qsig[:Q].contiguous()
+            reps = max(5, min(200, int(2e9 // (N * 32 + 1) // max(1, Q // 16 + 1))))
+            kms = min(H.scan_timing(idx, q, T=T, eps=eps, reps=reps) for _ in range(3))
+            H.query_hoph(idx, q, T=T, eps=eps)        # warm (tables cached, buffers grown)
+            walls, phases = [], []
+            for _ in range(max(5, args.steps)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                H.query_hoph(idx, q, T=T, eps=eps)
+                walls.append(time.perf_counter() - t0)
+                phases.append(idx.last_query_ms())
+            byts = N * 32 * Wp * depth + Q * rec_bytes * depth
+            gbs = byts / (kms * 1e-3) / 1e9
+            valu = Q * N * depth * ops / (kms * 1e-3)
+            rows.append({"Q": Q, "coarse_kernel_ms": kms, "launches_timed": reps, "algorithmic_bytes": byts,
+                         "hbm_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS, "valu_ops_per_s": valu,
+                         "valu_frac": valu / ALU_PEAK_OPS, "pairs_per_s_kernel": Q * N / (kms * 1e-3),
+                         "query_call_ms_p50": 1e3 * float(np.median(walls)),
+                         "query_events_ms": [float(np.median([x[i] for x in phases])) for i in range(3)]})
+            log(f"N={N} Q={Q}: coarse {kms * 1e3:.1f} us, {gbs:.0f} GB/s ({gbs / HBM_PEAK_GBS:.2f}), "
+                f"VALU {valu / ALU_PEAK_OPS:.2f}, call {rows[-1]['query_call_ms_p50']:.3f} ms")
+        # the ridge: the largest Q whose pass is still at least 0.6 of the peak rate
+        hbm_ok = [r["Q"] for r in rows if r["hbm_frac"] >= 0.6]
+        out["indexes"].append({"n_sets": N, "k": k, "k_group": 32, "depth": depth, "first_phase_planes": split,
+                               "ops_per_pair": ops, "rows": rows,
+                               "largest_q_at_0_6_hbm": max(hbm_ok) if hbm_ok else None})
+        idx.free()
+        del qsig
+        torch.cuda.empty_cache()
+    out["value"] = max(r["hbm_gbs"] for ix in out["indexes"] for r in ix["rows"])
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -620,7 +710,7 @@ def main():
         import paper_1805_11254_amd as H
         H.lib()
         {"batched": bench_batched, "serve": bench_serve, "comparators": bench_comparators,
-         "selfjoin": bench_selfjoin, "sweeps": bench_sweeps}[args.mode](args)
+         "selfjoin": bench_selfjoin, "sweeps": bench_sweeps, "scansweep": bench_scansweep}[args.mode](args)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}); "
@@ -657,7 +747,7 @@ def main():
 
     def step(ev=None):
         # one pass of the path: every set sketched straight into the resident
-        # index (slabs + code planes), the query batch sketched, the HOPH scan
+        # index (rows + code planes), the query batch sketched, the HOPH scan
         e = ev or [None] * 4
         if e[0] is not None: e[0].record(stream)
         idx.reset()
@@ -697,7 +787,7 @@ def main():
     qsketch_ms = mean_ms(1, 2)
     query_ms = mean_ms(2, 3)
     sketch_ms = sum(a[0] for a in ams) / len(ams)       # the sketch-into-index kernel
-    codes_ms = sum(a[1] for a in ams) / len(ams)        # code planes from the slabs
+    codes_ms = sum(a[1] for a in ams) / len(ams)        # code planes from the rows
 
     # the two-step build (row-major signatures, then the index store), for comparison
     e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
@@ -757,7 +847,7 @@ def main():
     code_units = min(L_groups // pk, max(4, min(12 if kp > 32 else 24, -(-(256 if w.goph else 128) // (pk * kp)))))
     code_groups = code_units * pk
     code_bytes = N * code_groups * kp * 4 + N * code_units * 32 * (1 if kp <= 32 else 2)
-    index_bytes = 2 * N * k * 4 + N * code_units * 32 * (1 if kp <= 32 else 2)   # rows in, slabs + code planes out
+    index_bytes = 2 * N * k * 4 + N * code_units * 32 * (1 if kp <= 32 else 2)   # rows in, index rows + code planes out
     # coarse depth as the library picks it: the first group alone when it rejects at
     # least 1/8 of its match counts (no empty bins), else one group past the first
     # step with a reject cutoff, rounded up to whole code units

@@ -131,7 +131,9 @@ typedef struct hoph_index hoph_index;   /* opaque, owned by the library */
  * Asynchronous.  An id >= universe (or, for HOPH_HASH_TABLE, a table value >= the
  * universe) raises HOPH_E_RANGE at the next hoph_sync on the device, and the
  * signature of its set is then unspecified; an empty set gets an all-EMPTY
- * signature and raises HOPH_E_INVAL there (Jaccard similarity is undefined for it).
+ * signature and raises HOPH_E_INVAL there (Jaccard similarity is undefined for it),
+ * and so does a set whose end offset is below its start (none of its ids is read).
+ * Offsets must stay within d_ids: the device cannot check that bound.
  * Host errors: HOPH_E_INVAL (bad params, null pointers with n_sets > 0).
  */
 hoph_status sketch_oph(const hoph_sketch_params *params, const uint32_t *d_ids,
@@ -139,9 +141,13 @@ hoph_status sketch_oph(const hoph_sketch_params *params, const uint32_t *d_ids,
                        void *hip_stream);
 
 /*
- * build_index -- a resident index of signatures in group-major slabs (the
- * per-group comparison order of Sec. 3.3 / Sec. 4.1).  capacity >= n_sets is the
- * number of sets the index can hold (index_append grows it up to capacity).
+ * build_index -- a resident index of signatures: the signature words in
+ * row-major rows (one set's k words contiguous, so the per-pair pass of
+ * Sec. 3.3 / Sec. 4.1 reads one group of one set as one run) plus, for the
+ * first groups, 8-bit bin codes stored as bit planes in tiles of 64 sets (the
+ * coarse pass's input; hoph_index_code_planes gives their layout).
+ * capacity >= n_sets is the number of sets the index can hold (index_append
+ * grows it up to capacity).
  * d_sigs: n_sets * k uint32 row-major, as written by sketch_oph.  Allocates device
  * memory (the only allocation point besides first-use workspace growth).
  * Asynchronous on hip_stream; *out is valid on return.
@@ -157,8 +163,8 @@ hoph_status index_append(hoph_index *index, const uint32_t *d_sigs, uint64_t n_n
 /*
  * index_append_sets -- sketch n_sets sets (Sec. 3.2, Sec. 4.1, with the index's
  * own sketch parameters, as sketch_oph) straight into the index: each
- * signature is written into the group-major slabs (and the narrowed code
- * planes of the first groups) without a row-major copy; ids continue from the
+ * signature is written into its index row (and the narrowed code planes of
+ * the first groups) without an intermediate copy; ids continue from the
  * current size.  d_ids / d_offsets as for sketch_oph (device, CSR).  Results
  * are identical to sketch_oph followed by index_append.  HOPH_E_CAPACITY if
  * size + n_sets > capacity.  Asynchronous; ids out of range and empty sets are
@@ -177,6 +183,15 @@ hoph_status hoph_index_reset(hoph_index *index);
    ms[0] coarse pass, ms[1] per-survivor pass, ms[2] sort and CSR output.
    (query_oph_full reports its scan in ms[0].) */
 hoph_status hoph_query_timing(const hoph_index *index, float ms[3]);
+
+/* hoph_scan_timing -- a measurement hook: the coarse pass of query_goph /
+   query_hoph (by the index layout) for the n_q query signatures d_qsigs, timed
+   alone.  The per-query records are built once, the pass runs once untimed and
+   then reps times back to back between two HIP events on hip_stream; the mean
+   duration of one pass in milliseconds is written to *ms_per_launch.  No
+   results are produced.  Synchronises hip_stream. */
+hoph_status hoph_scan_timing(const hoph_index *index, const uint32_t *d_qsigs, uint32_t n_q,
+                             const hoph_query_params *qp, uint32_t reps, float *ms_per_launch, void *hip_stream);
 
 /* hoph_append_timing -- device time of the last index_append_sets call on this
    index, in ms: ms[0] the sketch into the index rows, ms[1] the code planes of

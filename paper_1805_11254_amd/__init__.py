@@ -93,6 +93,7 @@ SIGNATURES = {
     "hoph_index_reset": (C.c_int, [vp]),
     "hoph_index_code_planes": (C.c_int, [vp, vp, u64, C.POINTER(u64), vp]),
     "hoph_query_timing": (C.c_int, [vp, C.POINTER(C.c_float)]),
+    "hoph_scan_timing": (C.c_int, [vp, vp, u32, C.POINTER(QueryParamsC), u32, C.POINTER(C.c_float), vp]),
     "hoph_index_free": (None, [vp]),
     "query_goph": (C.c_int, [vp, vp, u32, C.POINTER(QueryParamsC), C.POINTER(ResultsC), vp]),
     "query_hoph": (C.c_int, [vp, vp, u32, C.POINTER(QueryParamsC), C.POINTER(ResultsC), vp]),
@@ -349,6 +350,19 @@ def query_hoph(index: Index, qsigs, T=(4, 5), eps=(1, 10000), policy=EMPTY_JOINT
                coarse_depth=0, stream=None, coarse=COARSE_CODES):
     """Alg. 2 over the index: (offsets int64[n_q+1], set ids int32[...])."""
     return _query("query_hoph", index, qsigs, T, eps, policy, capacity, coarse_depth, stream, coarse)
+
+
+def scan_timing(index: Index, qsigs, T=(4, 5), eps=(1, 10000), policy=EMPTY_JOINT, reps=20, coarse_depth=0,
+                coarse=COARSE_CODES, stream=None) -> float:
+    """Mean device time (ms) of one coarse pass over the index for these query
+    signatures, reps launches back to back between two HIP events."""
+    import torch
+    _need_cuda(qsigs, "qsigs", (torch.int32,))
+    qp = QueryParamsC(_ratio(T), _ratio(eps), policy, coarse_depth, coarse, 0)
+    ms = C.c_float()
+    _check(lib().hoph_scan_timing(index.handle, vp(qsigs.data_ptr()), qsigs.shape[0], C.byref(qp), reps,
+                                  C.byref(ms), _stream(stream)))
+    return float(ms.value)
 
 
 def self_join(index: Index, T=(4, 5), eps=(1, 10000), policy=EMPTY_JOINT, capacity=None, coarse_depth=0,

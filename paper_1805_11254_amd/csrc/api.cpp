@@ -129,8 +129,42 @@ hipError_t append_sets_async(hoph_index *idx, const uint32_t *d_ids, const uint6
     return hipSuccess;
 }
 
-hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t n_q, const hoph_query_params *qp,
-                      hoph_results *res, void *stream, QueryKind kind, bool self_join) {
+hoph_status cached_scan_tab(hoph_index *idx, const hoph_query_params &qp, bool goph, ScanTab &out) {
+    for (const TabEntry &e : idx->tabs) {
+        if (e.T.num == qp.T.num && e.T.den == qp.T.den && e.eps.num == qp.eps.num && e.eps.den == qp.eps.den &&
+            e.policy == qp.empty_policy && e.goph == (goph ? 1u : 0u)) {
+            out = e.tab;
+            return HOPH_OK;
+        }
+    }
+    hoph_decision_tables t;
+    std::string err;
+    hoph_status st = build_tables(idx->lay, qp, goph, t, err);
+    if (st) return fail(st, err);
+    TabEntry e;
+    e.T = qp.T;
+    e.eps = qp.eps;
+    e.policy = qp.empty_policy;
+    e.goph = goph ? 1u : 0u;
+    to_scan_tab(t, e.tab);
+    out = e.tab;
+    if (idx->tabs.size() < kTabCache) {
+        idx->tabs.push_back(e);                  // within the capacity reserved at build
+    } else {
+        idx->tabs[idx->tab_next] = e;
+        idx->tab_next = (idx->tab_next + 1) % kTabCache;
+    }
+    return HOPH_OK;
+}
+
+namespace {
+
+// time_reps > 0: a measurement run instead of a query -- the coarse pass alone,
+// time_reps launches back to back between two events, the mean written to
+// *time_ms; no output is written (res may be a dummy).
+hoph_status run_query_impl(const hoph_index *cidx, Workspace *ws_in, const uint32_t *d_qsigs, uint32_t n_q,
+                           const hoph_query_params *qp, hoph_results *res, void *stream, QueryKind kind,
+                           bool self_join, uint64_t n_limit, uint32_t time_reps = 0, float *time_ms = nullptr) {
     if (!cidx) return fail(HOPH_E_INVAL, "index is NULL");
     if (!qp) return fail(HOPH_E_INVAL, "query params are NULL");
     if (self_join) {
@@ -156,17 +190,16 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
     if (!dg.ok) return fail(HOPH_E_DEVICE, "cannot select the index device");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const LayoutInfo &lay = idx->lay;
-    Workspace &ws = idx->ws;
+    const uint64_t n_sets = std::min(idx->n, n_limit);   // rows this call compares against
+    Workspace &ws = ws_in ? *ws_in : idx->ws;
+    const bool timed_ev = ws.ev[0] != nullptr;       // a fixed workspace has no events
 
     ScanTab tab{};
     uint32_t depth = 0, maxd = 0;
     const bool use_codes = kind != QueryKind::OPH_FULL && qp->coarse_filter == HOPH_COARSE_CODES && idx->codes;
     if (kind != QueryKind::OPH_FULL) {
-        hoph_decision_tables t;
-        std::string err;
-        st = build_tables(lay, *qp, kind == QueryKind::GOPH, t, err);
-        if (st) return fail(st, err);
-        to_scan_tab(t, tab);
+        st = cached_scan_tab(idx, *qp, kind == QueryKind::GOPH, tab);
+        if (st) return st;
         maxd = use_codes ? idx->cg : std::min(max_depth_for_kpad(idx->kpad), lay.L);
         depth = default_coarse_depth(tab, qp->coarse_depth, maxd, use_codes ? code_pack(lay.kp, lay.L) : 1u);
     }
@@ -174,7 +207,7 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
     ScanLaunch a{};
     a.slab = idx->slab;
     a.capacity = idx->capacity;
-    a.n_sets = idx->n;
+    a.n_sets = n_sets;
     a.kpad = idx->kpad;
     a.kp = lay.kp;
     a.L = lay.L;
@@ -183,7 +216,7 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
     a.depth = depth;
     a.tri = self_join;
     a.counters = ws.counters;
-    if (kind != QueryKind::OPH_FULL && n_q && idx->n) {
+    if (kind != QueryKind::OPH_FULL && n_q && n_sets) {
         st = ws.grow_qmasks((uint64_t)n_q * lay.L);
         if (st) return st;
         CodeThr thr{};
@@ -205,26 +238,50 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
     auto pass = [&](uint32_t q0, uint32_t q1) -> hoph_status {
         a.q0 = q0;
         a.q1 = q1;
-        a.q_per_wave = pick_q_per_wave(idx->n, q1 - q0, coarse_tiles_per_wave(a, tab));
-        HOPH_HIP(hipEventRecord(ws.ev[0], s), "hipEventRecord");
+        a.q_per_wave = pick_q_per_wave(n_sets, q1 - q0, coarse_tiles_per_wave(a, tab));
+        if (timed_ev) HOPH_HIP(hipEventRecord(ws.ev[0], s), "hipEventRecord");
         if (kind == QueryKind::OPH_FULL) {
             HOPH_HIP(launch_oph_full(a, qp->T, qp->empty_policy, s), "oph_full launch");
-            HOPH_HIP(hipEventRecord(ws.ev[1], s), "hipEventRecord");
+            if (timed_ev) HOPH_HIP(hipEventRecord(ws.ev[1], s), "hipEventRecord");
         } else {
             HOPH_HIP(launch_scan_coarse(a, tab, s), "coarse scan launch");
-            HOPH_HIP(hipEventRecord(ws.ev[1], s), "hipEventRecord");
+            if (timed_ev) HOPH_HIP(hipEventRecord(ws.ev[1], s), "hipEventRecord");
             HOPH_HIP(launch_scan_fine(a, tab, s), "fine scan launch");
         }
-        HOPH_HIP(hipEventRecord(ws.ev[2], s), "hipEventRecord");
+        if (timed_ev) HOPH_HIP(hipEventRecord(ws.ev[2], s), "hipEventRecord");
         return HOPH_OK;
     };
+    if (time_reps) {
+        if (!timed_ev || kind == QueryKind::OPH_FULL) return fail(HOPH_E_INVAL, "coarse-pass timing needs the index workspace");
+        *time_ms = 0.f;
+        if (!n_q || !n_sets) return HOPH_OK;
+        a.surv = ws.surv;
+        a.surv_cap = ws.surv_cap;
+        a.keys = ws.keys;
+        a.keys_cap = ws.keys_cap;
+        a.q0 = 0;
+        a.q1 = n_q;
+        a.q_per_wave = pick_q_per_wave(n_sets, n_q, coarse_tiles_per_wave(a, tab));
+        HOPH_HIP(launch_fill_u64(ws.counters, 4, 0, s), "fill counters");
+        HOPH_HIP(launch_scan_coarse(a, tab, s), "coarse scan launch");    // warm: code object, caches
+        HOPH_HIP(hipEventRecord(ws.ev[0], s), "hipEventRecord");
+        // survivors past the buffer are counted, not written, so repeated passes stay in bounds
+        for (uint32_t r = 0; r < time_reps; ++r) HOPH_HIP(launch_scan_coarse(a, tab, s), "coarse scan launch");
+        HOPH_HIP(hipEventRecord(ws.ev[1], s), "hipEventRecord");
+        HOPH_HIP(hipEventSynchronize(ws.ev[1]), "hipEventSynchronize");
+        float ms = 0.f;
+        HOPH_HIP(hipEventElapsedTime(&ms, ws.ev[0], ws.ev[1]), "hipEventElapsedTime");
+        *time_ms = ms / (float)time_reps;
+        return HOPH_OK;
+    }
     auto record_timing = [&]() {
+        if (!timed_ev) return;
         (void)hipEventElapsedTime(&ws.last_ms[0], ws.ev[0], ws.ev[1]);
         (void)hipEventElapsedTime(&ws.last_ms[1], ws.ev[1], ws.ev[2]);
         (void)hipEventElapsedTime(&ws.last_ms[2], ws.ev[2], ws.ev[3]);
     };
 
-    if (n_q && idx->n) {
+    if (n_q && n_sets) {
         // Optimistic path, one read-back: the pass and the output stage (which takes
         // its counts from the device) back to back, then the counters and flags.  It
         // stands when no buffer overflowed and no query holds more ids than the
@@ -242,7 +299,7 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
                                          ws.cursor, res->d_set_ids, res->capacity, ws.counters, n_q, ws.keys_cap,
                                          kSegMaxPlan, s),
                  "output launch");
-        HOPH_HIP(hipEventRecord(ws.ev[3], s), "hipEventRecord");
+        if (timed_ev) HOPH_HIP(hipEventRecord(ws.ev[3], s), "hipEventRecord");
         HOPH_HIP(hipMemcpyAsync(ws.h_counters, ws.counters, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, s),
                  "hipMemcpyAsync(counters)");
         HOPH_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
@@ -266,14 +323,16 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
         a.keys_cap = ws.keys_cap;
         HOPH_HIP(launch_fill_u64(ws.counters, 2, 0, s), "fill counters");
         bool fresh = false;                 // h_counters hold this attempt's device counters
-        if (n_q && idx->n) {
+        if (n_q && n_sets) {
             // one pass over the whole batch; on survivor overflow, redo in sub-batches
             st = pass(0, n_q);
             if (st) return st;
             st = copy_counters(ws, s);
             if (st) return st;
-            (void)hipEventElapsedTime(&pass_ms[0], ws.ev[0], ws.ev[1]);
-            (void)hipEventElapsedTime(&pass_ms[1], ws.ev[1], ws.ev[2]);
+            if (timed_ev) {
+                (void)hipEventElapsedTime(&pass_ms[0], ws.ev[0], ws.ev[1]);
+                (void)hipEventElapsedTime(&pass_ms[1], ws.ev[1], ws.ev[2]);
+            }
             if (ws.h_counters[0] > ws.surv_cap) {
                 const uint64_t seen = ws.h_counters[0];
                 HOPH_HIP(launch_fill_u64(ws.counters, 2, 0, s), "fill counters");
@@ -288,7 +347,9 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
                     st = copy_counters(ws, s);
                     if (st) return st;
                     if (ws.h_counters[0] > ws.surv_cap) {
-                        if (sub == 1) return fail(HOPH_E_NOMEM, "survivor buffer smaller than the index");
+                        if (sub == 1)
+                            return fail(ws.fixed ? HOPH_E_CAPACITY : HOPH_E_NOMEM,
+                                        "one query keeps more survivors than the survivor buffer holds");
                         sub = std::max<uint32_t>(1, sub / 2);
                         HOPH_HIP(launch_fill_u64(ws.counters + 1, 1, acc_before, s), "fill counters");
                         continue;
@@ -313,19 +374,41 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
         return fail(HOPH_E_CAPACITY, "results capacity " + std::to_string(res->capacity) + " < " +
                                          std::to_string(accepted) + " accepted pairs");
     }
-    const bool timed = n_q && idx->n;
-    if (timed) HOPH_HIP(hipEventRecord(ws.ev[2], s), "hipEventRecord");
+    const bool timed = n_q && n_sets;
+    if (timed && timed_ev) HOPH_HIP(hipEventRecord(ws.ev[2], s), "hipEventRecord");
     st = write_output(ws, accepted, n_q, res, s);
     if (st) return st;
-    if (timed) HOPH_HIP(hipEventRecord(ws.ev[3], s), "hipEventRecord");
+    if (timed && timed_ev) HOPH_HIP(hipEventRecord(ws.ev[3], s), "hipEventRecord");
     HOPH_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
     ws.last_ms[0] = ws.last_ms[1] = ws.last_ms[2] = 0.f;
-    if (timed) {
+    if (timed && timed_ev) {
         ws.last_ms[0] = pass_ms[0];
         ws.last_ms[1] = pass_ms[1];
         (void)hipEventElapsedTime(&ws.last_ms[2], ws.ev[2], ws.ev[3]);
     }
     return HOPH_OK;
+}
+
+}  // namespace
+
+hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t n_q, const hoph_query_params *qp,
+                      hoph_results *res, void *stream, QueryKind kind, bool self_join, uint64_t n_limit) {
+    return run_query_impl(cidx, nullptr, d_qsigs, n_q, qp, res, stream, kind, self_join, n_limit);
+}
+
+hoph_status scan_timing(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t n_q, const hoph_query_params *qp,
+                        uint32_t reps, float *ms, void *stream) {
+    if (!cidx || !ms) return fail(HOPH_E_INVAL, "NULL argument");
+    if (reps == 0) return fail(HOPH_E_INVAL, "reps must be >= 1");
+    const QueryKind kind = cidx->params.layout == HOPH_LAYOUT_OPH ? QueryKind::GOPH : QueryKind::HOPH;
+    uint64_t dummy_off = 0;
+    hoph_results r{&dummy_off, nullptr, 0, 0};
+    return run_query_impl(cidx, nullptr, d_qsigs, n_q, qp, &r, stream, kind, false, ~0ull, reps, ms);
+}
+
+hoph_status run_query_in(const hoph_index *cidx, Workspace &ws, const uint32_t *d_qsigs, uint32_t n_q,
+                         const hoph_query_params *qp, hoph_results *res, void *stream, QueryKind kind) {
+    return run_query_impl(cidx, &ws, d_qsigs, n_q, qp, res, stream, kind, false, ~0ull);
 }
 
 // Workspace for MinWise queries, one per device.
@@ -419,6 +502,7 @@ hoph_status build_index(const hoph_sketch_params *params, const uint32_t *d_sigs
         return hip_fail(e, "index store launch");
     }
     idx->n = n_sets;
+    idx->tabs.reserve(kTabCache);
     *out = idx.release();
     return HOPH_OK;
 }
@@ -495,6 +579,12 @@ hoph_status hoph_query_timing(const hoph_index *idx, float ms[3]) {
     std::lock_guard<std::mutex> lk(m->mu);
     for (int i = 0; i < 3; ++i) ms[i] = m->ws.last_ms[i];
     return HOPH_OK;
+}
+
+hoph_status hoph_scan_timing(const hoph_index *index, const uint32_t *d_qsigs, uint32_t n_q,
+                             const hoph_query_params *qp, uint32_t reps, float *ms_per_launch, void *hip_stream) {
+    g_last_error.clear();
+    return scan_timing(index, d_qsigs, n_q, qp, reps, ms_per_launch, hip_stream);
 }
 
 hoph_status hoph_append_timing(const hoph_index *idx, float ms[2]) {
@@ -622,6 +712,7 @@ hoph_status hoph_sync(void *hip_stream) {
     if (h) {
         HOPH_HIP(hipMemset(errw, 0, sizeof(uint32_t)), "hipMemset(error word)");
         if (h & kErrRange) return fail(HOPH_E_RANGE, "an id >= universe (or a table value >= universe) was skipped");
+        if (h & kErrBadRange) return fail(HOPH_E_INVAL, "a set's end offset is below its start (nothing was read)");
         return fail(HOPH_E_INVAL, "an empty set was sketched (its signature is all EMPTY)");
     }
     return HOPH_OK;

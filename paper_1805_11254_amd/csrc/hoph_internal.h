@@ -57,6 +57,7 @@ __host__ __device__ inline uint32_t code_units(uint32_t cg, uint32_t kp, uint32_
 // Device error bits (one 32-bit word per device).
 constexpr uint32_t kErrRange = 1u;              // an id >= universe, or a table value >= R
 constexpr uint32_t kErrEmptySet = 2u;           // a set with no element
+constexpr uint32_t kErrBadRange = 4u;           // a set whose end offset is below its start
 
 // ---------------------------------------------------------------------------
 // Sketch layout, passed by value to the sketch kernels.  The permuted range

@@ -390,7 +390,7 @@ __global__ __launch_bounds__(256) void sketch_kernel(SketchDesc d, const uint32_
         }
         for (uint32_t b = lane; b < k; b += 64) sig[b] = HOPH_EMPTY;
         wave_lds_fence();
-        if (hi == lo) err |= kErrEmptySet;
+        if (hi <= lo) err |= hi == lo ? kErrEmptySet : kErrBadRange;   // a decreasing range reads nothing
         sketch_range<HASH, LOC>(d, t, ids, lo, hi, nlo, nhi, off, x, sig, lane, umax, xmax, vmax);
         wave_lds_fence();
         uint32_t *out = sigs + set * k;

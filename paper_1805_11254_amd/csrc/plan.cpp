@@ -99,6 +99,7 @@ struct hoph_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint32_t last_nq = 0;
+    uint64_t last_nsets = 0;      // index size the last batch was dispatched against
     bool pending = false;
     uint32_t fallbacks = 0;
     std::mutex mu;
@@ -398,6 +399,7 @@ hoph_status hoph_plan_run(hoph_plan *p, const uint32_t *d_ids, const uint64_t *d
         if (r) return r;
     }
     p->last_nq = n_q;
+    p->last_nsets = n_sets;
     p->pending = true;
     return HOPH_OK;
 }
@@ -420,7 +422,8 @@ hoph_status hoph_plan_results(hoph_plan *p, const uint64_t **d_offsets, const ui
         // redo on the host-synchronised path with the batch's signatures
         ++p->fallbacks;
         hoph_results r{p->out_offsets, p->out_ids, p->cfg.max_results, 0};
-        hoph_status s = run_query(p->idx, p->q_sigs, p->last_nq, &p->qp, &r, hip_stream, p->kind);
+        hoph_status s = run_query(p->idx, p->q_sigs, p->last_nq, &p->qp, &r, hip_stream, p->kind, false,
+                                  p->last_nsets);
         *n_results = r.needed;
         if (s) return s;
     }
@@ -478,7 +481,7 @@ hoph_status plan_results_to_host(hoph_plan *p, uint64_t *h_offsets, uint32_t *h_
         // redo on the host-synchronised path with the batch's signatures
         ++p->fallbacks;
         hoph_results r{p->out_offsets, p->out_ids, p->cfg.max_results, 0};
-        hoph_status s = run_query(p->idx, p->q_sigs, n_q, &p->qp, &r, st, p->kind);
+        hoph_status s = run_query(p->idx, p->q_sigs, n_q, &p->qp, &r, st, p->kind, false, p->last_nsets);
         if (s) return s;
         n = r.needed;
         HOPH_HIP(hipMemcpyAsync(h_offsets, p->out_offsets, ((uint64_t)n_q + 1) * 8, hipMemcpyDeviceToHost, st),

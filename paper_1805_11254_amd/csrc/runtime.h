@@ -5,6 +5,7 @@
 
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "hoph_internal.h"
 
@@ -42,7 +43,12 @@ struct DeviceGuard {
 hoph_status device_err_word(uint32_t **out);
 
 // Device buffers for one query at a time: survivors, accepted keys, counters.
+// A fixed workspace is a view of memory someone else owns (the library's
+// static scratch): its grow_* calls never allocate and report
+// HOPH_E_CAPACITY when a request exceeds what the view holds, and it has no
+// events (no timing).
 struct Workspace {
+    bool fixed = false;
     Survivor *surv = nullptr;
     uint64_t surv_cap = 0;
     uint64_t *keys = nullptr;
@@ -61,6 +67,7 @@ struct Workspace {
     bool aev_recorded = false;
     float last_ms[3] = {0, 0, 0};
     void release() {
+        if (fixed) return;                 // a view: nothing of its own to free
         for (auto &e : ev)
             if (e) { (void)hipEventDestroy(e); e = nullptr; }
         for (auto &e : aev)
@@ -98,6 +105,7 @@ struct Workspace {
     }
     hoph_status grow_surv(uint64_t n) {
         if (n <= surv_cap) return HOPH_OK;
+        if (fixed) return fail(HOPH_E_CAPACITY, "survivor records exceed the fixed scratch");
         if (surv) (void)hipFree(surv);
         surv = nullptr;
         surv_cap = 0;
@@ -107,6 +115,7 @@ struct Workspace {
     }
     hoph_status grow_qmasks(uint64_t n) {
         if (n <= qmask_cap) return HOPH_OK;
+        if (fixed) return fail(HOPH_E_CAPACITY, "query masks exceed the fixed scratch");
         if (qmasks) (void)hipFree(qmasks);
         qmasks = nullptr;
         qmask_cap = 0;
@@ -118,6 +127,7 @@ struct Workspace {
     }
     hoph_status grow_qcodes(uint64_t n) {
         if (n <= qcode_cap) return HOPH_OK;
+        if (fixed) return fail(HOPH_E_CAPACITY, "query code records exceed the fixed scratch");
         if (qcodes) (void)hipFree(qcodes);
         qcodes = nullptr;
         qcode_cap = 0;
@@ -129,6 +139,7 @@ struct Workspace {
     }
     hoph_status grow_seg(uint64_t n) {
         if (n <= seg_cap) return HOPH_OK;
+        if (fixed) return fail(HOPH_E_CAPACITY, "per-query output counters exceed the fixed scratch");
         if (qcount) (void)hipFree(qcount);
         if (cursor) (void)hipFree(cursor);
         qcount = nullptr;
@@ -145,6 +156,9 @@ struct Workspace {
     hoph_status grow_keys(uint64_t n) {
         const uint64_t want = sort_capacity(n);
         if (want <= keys_cap) return HOPH_OK;
+        if (fixed)
+            return fail(HOPH_E_CAPACITY, std::to_string(n) + " accepted pairs exceed the fixed scratch's " +
+                                             std::to_string(keys_cap) + " keys");
         if (keys) (void)hipFree(keys);
         keys = nullptr;
         keys_cap = 0;
@@ -170,6 +184,16 @@ hoph_status write_output(Workspace &ws, uint64_t accepted, uint32_t n_q, hoph_re
 
 }  // namespace hoph
 
+namespace hoph {
+// Decision tables of one (T, eps, empty policy, weights) for an index's layout.
+struct TabEntry {
+    hoph_ratio T{}, eps{};
+    uint32_t policy = 0, goph = 0;
+    ScanTab tab{};
+};
+constexpr size_t kTabCache = 16;
+}  // namespace hoph
+
 struct hoph_index {
     int device = 0;
     hoph_sketch_params params{};
@@ -182,6 +206,11 @@ struct hoph_index {
     uint32_t *codes = nullptr;    // code planes of the first cg groups (coarse pass on codes)
     uint32_t cg = 0;
     hoph::Workspace ws;
+    // the exact tables of the last kTabCache query parameter sets (reserved at
+    // build, replaced oldest first), so that a repeated query does not rebuild
+    // them on the host (about 30 us at k' = 32)
+    std::vector<hoph::TabEntry> tabs;
+    size_t tab_next = 0;
     std::mutex mu;
 };
 
@@ -190,9 +219,20 @@ namespace hoph {
 // code planes), asynchronously on s; the caller checks capacity and owns idx->n.
 hipError_t append_sets_async(hoph_index *idx, const uint32_t *d_ids, const uint64_t *d_offsets, uint64_t n_sets,
                              uint64_t first, uint32_t *err_word, hipStream_t s, bool timed);
-// GOPH / HOPH / plain-OPH query through the index's own workspace (host-synchronised).
+// GOPH / HOPH / plain-OPH query through the index's own workspace (host-synchronised),
+// against the index rows below min(index size, n_limit): a batch that a plan
+// dispatched against a snapshot of the size and then redoes here keeps it.
 hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t n_q, const hoph_query_params *qp,
-                      hoph_results *res, void *stream, QueryKind kind, bool self_join = false);
+                      hoph_results *res, void *stream, QueryKind kind, bool self_join = false,
+                      uint64_t n_limit = ~0ull);
+// The same with a caller-supplied workspace (a fixed view: nothing is allocated).
+hoph_status run_query_in(const hoph_index *cidx, Workspace &ws, const uint32_t *d_qsigs, uint32_t n_q,
+                         const hoph_query_params *qp, hoph_results *res, void *stream, QueryKind kind);
+// The coarse pass alone, reps launches back to back between two events (hoph_scan_timing).
+hoph_status scan_timing(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t n_q, const hoph_query_params *qp,
+                        uint32_t reps, float *ms, void *stream);
+// The scan tables for qp on idx's layout, from the index's cache (caller holds idx->mu).
+hoph_status cached_scan_tab(hoph_index *idx, const hoph_query_params &qp, bool goph, ScanTab &out);
 // The results of a plan's last batch copied to host buffers with one stream
 // synchronisation in the usual case: the counters, the CSR offsets (n_q + 1)
 // and the first `pre` ids are read together; more ids are read only when the

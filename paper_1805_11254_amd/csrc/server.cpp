@@ -310,6 +310,10 @@ hoph_status hoph_server_insert(hoph_server *srv, const uint32_t *h_ids, const ui
         std::lock_guard<std::mutex> lk(idx->mu);
         if (idx->n + n_sets > idx->max_sets) return fail(HOPH_E_CAPACITY, "index capacity exceeded");
     }
+    // the offsets are on the host: a decreasing pair would make the device read
+    // a range that wraps past the staged ids
+    for (uint64_t i = 0; i < n_sets; ++i)
+        if (h_offsets[i + 1] < h_offsets[i]) return fail(HOPH_E_INVAL, "insert offsets decrease");
     const uint64_t nnz = h_offsets[n_sets] - h_offsets[0];
     std::vector<uint64_t> offs(h_offsets, h_offsets + n_sets + 1);
     for (auto &o : offs) o -= h_offsets[0];
