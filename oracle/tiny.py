@@ -329,16 +329,25 @@ def oph_full_decide(q, s, T, policy=EMPTY_JOINT) -> bool:
 # --------------------------------------------------------------------------
 # MinWise comparator (Sec. 1/2: k independent permutations, compare all k)
 # --------------------------------------------------------------------------
-def minwise_sketch(elements: Iterable[int], kind: int, coeffs: Sequence[Tuple[int, int]]) -> List[int]:
-    """k independent hashes (a_i*x + b_i) mod p; keep each minimum."""
+def minwise_sketch(elements: Iterable[int], kind: int, coeffs: Sequence) -> List[int]:
+    """k independent random permutations, each applied to every element; keep
+    each permutation's minimum (2^64 - 1 for an empty set).  With kind
+    HASH_TABLE, coeffs holds the k permutation tables of [0, D); otherwise the
+    k pairs (a_i, b_i) of the hashes (a_i*x + b_i) mod p."""
     els = [int(x) for x in elements]
     out = []
-    for (a, b) in coeffs:
-        out.append(min((permute(x, kind, None, a, b) for x in els), default=(1 << 64) - 1))
+    for c in coeffs:
+        if kind == HASH_TABLE:
+            vals = (permute(x, kind, c) for x in els)
+        else:
+            a, b = c
+            vals = (permute(x, kind, None, a, b) for x in els)
+        out.append(min(vals, default=(1 << 64) - 1))
     return out
 
 
 def minwise_decide(q: Sequence[int], s: Sequence[int], T) -> bool:
+    """Accept iff the fraction of equal minima reaches T."""
     eq = sum(1 for a, b in zip(q, s) if a == b)
     return Fraction(eq, len(q)) >= Fraction(T)
 

@@ -9,7 +9,8 @@ from oracle import tiny
 import tests.test_oracle_pins as P
 
 PINS = [P.pin_oph_example, P.pin_hoph_example, P.pin_table2, P.pin_example1, P.pin_example2,
-        P.pin_unbiased_and_variance, P.pin_invariants]
+        P.pin_unbiased_and_variance, P.pin_invariants, P.pin_minwise_oracle, P.pin_goph_whole_estimate,
+        P.pin_hoph_weights_are_range_fractions]
 
 
 def _any_pin_fails():
@@ -174,10 +175,59 @@ def mut_transposed_bin_formula(mp):
     mp.setattr(tiny.Layout, "bin_of", lambda self, v: orig_bin(self, self.R - 1 - v))
 
 
+def mut_minwise_max(mp):
+    def mw(elements, kind, coeffs):
+        els = [int(x) for x in elements]
+        return [max((tiny.permute(x, kind, c) if kind == tiny.HASH_TABLE else tiny.permute(x, kind, None, *c)
+                     for x in els), default=(1 << 64) - 1) for c in coeffs]
+    mp.setattr(tiny, "minwise_sketch", mw)
+
+
+def mut_minwise_inverse_permutation(mp):
+    f = _orig("minwise_sketch")
+
+    def mw(elements, kind, coeffs):
+        if kind != tiny.HASH_TABLE:
+            return f(elements, kind, coeffs)
+        inv = [tuple(sorted(range(len(c)), key=lambda x: c[x])) for c in coeffs]
+        return f(elements, kind, inv)
+    mp.setattr(tiny, "minwise_sketch", mw)
+
+
+def mut_minwise_threshold_exclusive(mp):
+    mp.setattr(tiny, "minwise_decide",
+               lambda q, s, T: Fraction(sum(1 for a, b in zip(q, s) if a == b), len(q)) > Fraction(T))
+
+
+def mut_hoph_weights_swapped_ratio(mp):
+    """a:b read as b:a in the weights only (the layout still splits a:b)."""
+    f = tiny.Layout.weights
+
+    def weights(self, goph):
+        if goph:
+            return f(self, goph)
+        self.ra, self.rb = self.rb, self.ra
+        try:
+            return f(self, goph)
+        finally:
+            self.ra, self.rb = self.rb, self.ra
+    mp.setattr(tiny.Layout, "weights", weights)
+
+
+def mut_goph_estimate_sum_of_rates(mp):
+    f = _orig("hoph_estimate")
+
+    def est(q, s, lay, goph, policy=tiny.EMPTY_JOINT):
+        return f(q, s, lay, goph, policy) * (lay.L if goph else 1)
+    mp.setattr(tiny, "hoph_estimate", est)
+
+
 MUTATIONS = [mut_no_empty_correction, mut_uniform_hoph_weights, mut_lower_tail_inclusive,
              mut_upper_tail_exclusive, mut_success_prob_flipped, mut_offset_from_group_start,
              mut_max_instead_of_min, mut_remaining_fraction_off_by_one, mut_cases_swapped,
-             mut_sign_of_remaining_rate, mut_either_counts_joint_only, mut_transposed_bin_formula]
+             mut_sign_of_remaining_rate, mut_either_counts_joint_only, mut_transposed_bin_formula,
+             mut_minwise_max, mut_minwise_inverse_permutation, mut_minwise_threshold_exclusive,
+             mut_goph_estimate_sum_of_rates, mut_hoph_weights_swapped_ratio]
 
 
 @pytest.mark.parametrize("mutation", MUTATIONS, ids=lambda m: m.__name__)

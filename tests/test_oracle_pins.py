@@ -5,6 +5,7 @@ collision probability, and invariants.  The functions named ``pin_*`` are
 also run against deliberately broken copies of the oracle in
 test_oracle_mutations.py, to show that each plausible mistake fails a pin."""
 import itertools
+import random
 import json
 import os
 from fractions import Fraction as F
@@ -221,6 +222,83 @@ def test_minwise_collision_exhaustive():
     pin_minwise_collision()
 
 
+MINWISE_PAIRS_D7 = [({0, 1, 2}, {1, 2, 3, 4}), ({0, 6}, {1, 2, 6}), ({3}, {3}), ({0, 1}, {5, 6})]
+
+
+def pin_minwise_oracle(D=7, pairs=MINWISE_PAIRS_D7):
+    """The oracle's MinWise comparator (Sec. 1-2), with all D! permutations of
+    [0, D) as its k = D! independent permutations: the fraction of equal
+    minima is exactly J (the min-wise collision probability), the decision is
+    accept iff that fraction reaches T, and a single known permutation gives
+    the smallest permuted element."""
+    perms = list(itertools.permutations(range(D)))
+    ident = tuple(range(D))
+    rev = tuple(range(D - 1, -1, -1))
+    shift = tuple((x + 1) % D for x in range(D))        # not its own inverse
+    for A, B in pairs:
+        J = tiny.jaccard(A, B)
+        qa = tiny.minwise_sketch(sorted(A), tiny.HASH_TABLE, perms)
+        qb = tiny.minwise_sketch(sorted(B), tiny.HASH_TABLE, perms)
+        assert len(qa) == len(perms)
+        eq = sum(1 for a, b in zip(qa, qb) if a == b)
+        assert F(eq, len(perms)) == J, (A, B)
+        assert tiny.minwise_decide(qa, qb, J)                       # inclusive at T = J
+        if J < 1:
+            assert not tiny.minwise_decide(qa, qb, J + F(1, 10 ** 6))
+        if J > 0:
+            assert tiny.minwise_decide(qa, qb, J - F(1, 10 ** 6))
+        for S in (A, B):
+            assert tiny.minwise_sketch(sorted(S), tiny.HASH_TABLE, [ident]) == [min(S)]
+            assert tiny.minwise_sketch(sorted(S), tiny.HASH_TABLE, [rev]) == [D - 1 - max(S)]
+            assert tiny.minwise_sketch(sorted(S), tiny.HASH_TABLE, [shift]) == [min((x + 1) % D for x in S)]
+    assert tiny.minwise_sketch([], tiny.HASH_TABLE, [ident]) == [(1 << 64) - 1]
+
+
+def test_minwise_oracle_exhaustive():
+    pin_minwise_oracle()
+
+
+def pin_goph_whole_estimate(seed=5, rounds=200):
+    """The whole-signature estimate reported with a GOPH pair (the mean of its
+    group rates) against what it reduces to: under LITERAL it is the matched
+    bins over all k bins, Alg. 1's accumulated matches over n k'; under JOINT
+    with no jointly empty bin it is Eq. 6 over all k bins; and over every
+    permutation of a universe of D = k ids (each bin then holds exactly one id)
+    its mean is J, as Eq. 7 states for one group."""
+    rng = random.Random(seed)
+    for _ in range(rounds):
+        kp = rng.choice([1, 2, 3, 4, 8])
+        L = rng.choice([1, 2, 3, 5])
+        k = kp * L
+        lay = tiny.Layout(tiny.LAYOUT_OPH, 1 << 12, k, kp)
+        vals = [tiny.EMPTY, 0, 1, 2]
+        q = [rng.choice(vals) for _ in range(k)]
+        s = [rng.choice(vals) for _ in range(k)]
+        m = sum(1 for a, b in zip(q, s) if a == b and a != tiny.EMPTY)
+        est, mb, eb, _ = tiny.pair_report(q, s, lay, True, tiny.EMPTY_LITERAL)
+        assert est == F(m, k) and mb == m and eb == 0
+        s_full = [b if b != tiny.EMPTY or a != tiny.EMPTY else 3 for a, b in zip(q, s)]   # no joint empties
+        m2 = sum(1 for a, b in zip(q, s_full) if a == b and a != tiny.EMPTY)
+        est2, _, eb2, _ = tiny.pair_report(q, s_full, lay, True, tiny.EMPTY_JOINT)
+        assert eb2 == 0 and est2 == F(m2, k) == tiny.oph_estimate(q, s_full, tiny.EMPTY_JOINT)
+    D, kp = 6, 2
+    lay = tiny.Layout(tiny.LAYOUT_OPH, D, D, kp)
+    for A, B in [({0, 1, 2, 3}, {2, 3, 4, 5}), ({0, 1, 2, 3, 4, 5}, {0, 1, 2, 3, 4, 5}), ({0, 1, 2}, {3, 4, 5})]:
+        assert A | B == set(range(D))
+        tot = F(0)
+        n = 0
+        for perm in itertools.permutations(range(D)):
+            qa = tiny.sketch(sorted(A), lay, tiny.HASH_TABLE, perm)
+            qb = tiny.sketch(sorted(B), lay, tiny.HASH_TABLE, perm)
+            tot += tiny.pair_report(qa, qb, lay, True, tiny.EMPTY_JOINT)[0]
+            n += 1
+        assert tot / n == tiny.jaccard(A, B)
+
+
+def test_goph_whole_estimate():
+    pin_goph_whole_estimate()
+
+
 # ---------------------------------------------------------------------------
 # Invariants
 # ---------------------------------------------------------------------------
@@ -291,6 +369,38 @@ def test_weights_sum_to_one():
         w = lay.weights(False)
         assert sum(w) == 1 and w[0] == F(a, a + b)
     assert tiny.Layout(tiny.LAYOUT_HIER, 16, 6, 2).weights(False) == [F(1, 2), F(1, 4), F(1, 4)]
+
+
+def pin_hoph_weights_are_range_fractions():
+    """Lemma 3 weights each group by the share of the permuted range it covers
+    (r^j of the space; the a:b split of Sec. 4.1).  Where the recursive split
+    is exact -- R a multiple of (a+b)^(L-1) -- the weights the oracle applies
+    must equal each region's size over R, which the layout computes by a
+    different route (repeated floor splits), for any a:b, not only 1:1.  Each
+    region must also hold exactly k' bins of near-equal width, and with k' | a
+    region the bins are equal (Sec. 4.1's k' equal-sized bins per group)."""
+    for (a, b) in [(1, 1), (1, 2), (2, 1), (1, 3), (3, 1), (2, 3), (3, 5)]:
+        for L in (2, 3, 4, 5):
+            kp = 4
+            R = (a + b) ** (L - 1) * kp * 11
+            lay = tiny.Layout(tiny.LAYOUT_HIER, R, kp * L, kp, a, b)
+            w = lay.weights(False)
+            sizes = [e - s_ for (s_, e) in lay.groups]
+            assert sum(sizes) == R
+            assert w == [F(z, R) for z in sizes], (a, b, L)
+            ends = lay.starts[1:] + [R]
+            for j in range(L):
+                widths = [ends[i] - lay.starts[i] for i in range(j * kp, (j + 1) * kp)]
+                assert sum(widths) == sizes[j] and max(widths) - min(widths) <= 1
+                if sizes[j] % kp == 0:
+                    assert len(set(widths)) == 1
+    # the GOPH weights are the equal shares of the n groups of an OPH layout
+    lay = tiny.Layout(tiny.LAYOUT_OPH, 1 << 12, 32, 8)
+    assert lay.weights(True) == [F(e - s_, lay.R) for (s_, e) in lay.groups]
+
+
+def test_hoph_weights_are_range_fractions():
+    pin_hoph_weights_are_range_fractions()
 
 
 def _is_prime(n):
