@@ -185,13 +185,20 @@ hoph_status hoph_index_reset(hoph_index *index);
 hoph_status hoph_query_timing(const hoph_index *index, float ms[3]);
 
 /* hoph_scan_timing -- a measurement hook: the coarse pass of query_goph /
-   query_hoph (by the index layout) for the n_q query signatures d_qsigs, timed
-   alone.  The per-query records are built once, the pass runs once untimed and
-   then reps times back to back between two HIP events on hip_stream; the mean
-   duration of one pass in milliseconds is written to *ms_per_launch.  No
-   results are produced.  Synchronises hip_stream. */
+   query_hoph (by the index layout; Alg. 1 / Alg. 2 up to the coarse depth) for
+   the n_q query signatures d_qsigs, timed alone.  The per-query records are
+   built once, the pass runs once untimed and then reps times back to back
+   between two HIP events on hip_stream; the mean duration of one pass in
+   milliseconds is written to *ms_per_launch.  With flush_bytes > 0 (at least
+   4 MiB; pick it larger than the device's last-level cache), d_flush (device,
+   caller-owned, 16-byte aligned, flush_bytes long) is read before every timed
+   pass, so that each pass reads the index from HBM into caches that hold only
+   clean lines, and the time of those reads alone (timed the same way right
+   after) is subtracted; its first 4 MiB may be overwritten.  No results are
+   produced.  Synchronises hip_stream. */
 hoph_status hoph_scan_timing(const hoph_index *index, const uint32_t *d_qsigs, uint32_t n_q,
-                             const hoph_query_params *qp, uint32_t reps, float *ms_per_launch, void *hip_stream);
+                             const hoph_query_params *qp, uint32_t reps, void *d_flush, uint64_t flush_bytes,
+                             float *ms_per_launch, void *hip_stream);
 
 /* hoph_append_timing -- device time of the last index_append_sets call on this
    index, in ms: ms[0] the sketch into the index rows, ms[1] the code planes of
@@ -211,6 +218,14 @@ hoph_status hoph_append_timing(const hoph_index *index, float ms[2]);
    written either way).  Asynchronous on hip_stream. */
 hoph_status hoph_index_code_planes(const hoph_index *index, uint32_t *d_out, uint64_t out_words, uint64_t dims[3],
                                    void *hip_stream);
+
+/* hoph_index_rows -- copies the signatures of index rows first .. first + n - 1
+   (uint32[n][k], row-major, the layout sketch_oph writes: the OPH bins of
+   Sec. 3.2 or the hierarchical bins of Sec. 4.1) into d_out (device, caller-owned,
+   n * k words).  HOPH_E_RANGE when first + n exceeds the index size.
+   Asynchronous on hip_stream. */
+hoph_status hoph_index_rows(const hoph_index *index, uint64_t first, uint64_t n, uint32_t *d_out,
+                            void *hip_stream);
 
 /* hoph_index_size -- number of sets in the index (0 for NULL). */
 uint64_t hoph_index_size(const hoph_index *index);
@@ -313,6 +328,13 @@ hoph_status hoph_plan_run(hoph_plan *plan, const uint32_t *d_ids, const uint64_t
    (with *n_results = pairs needed) if the batch has more than max_results pairs. */
 hoph_status hoph_plan_results(hoph_plan *plan, const uint64_t **d_offsets,
                               const uint32_t **d_set_ids, uint64_t *n_results, void *hip_stream);
+
+/* hoph_plan_query_sigs -- the OPH signatures (uint32[n_q][k], row-major, Sec. 3.2 /
+   Sec. 4.1 bins) that the last batch's chunked sketch wrote: plan-owned device
+   memory, valid until the next run, ordered after the batch on hip_stream (the
+   caller synchronises that stream before reading it).  *n_q is the batch size.
+   HOPH_E_INVAL when no batch has been run. */
+hoph_status hoph_plan_query_sigs(const hoph_plan *plan, const uint32_t **d_qsigs, uint32_t *n_q);
 
 hoph_status hoph_plan_get_info(const hoph_plan *plan, hoph_plan_info *info);
 void hoph_plan_free(hoph_plan *plan);

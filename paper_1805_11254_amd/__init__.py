@@ -89,11 +89,12 @@ SIGNATURES = {
     "hoph_append_timing": (C.c_int, [vp, C.POINTER(C.c_float)]),
     "hoph_self_join": (C.c_int, [vp, C.POINTER(QueryParamsC), C.POINTER(ResultsC), vp]),
     "hoph_pair_estimates": (C.c_int, [vp, vp, u32, vp, u64, u32, vp, vp, vp, vp, vp, C.POINTER(C.c_int64), vp]),
+    "hoph_index_rows": (C.c_int, [vp, u64, u64, vp, vp]),
     "hoph_index_size": (u64, [vp]),
     "hoph_index_reset": (C.c_int, [vp]),
     "hoph_index_code_planes": (C.c_int, [vp, vp, u64, C.POINTER(u64), vp]),
     "hoph_query_timing": (C.c_int, [vp, C.POINTER(C.c_float)]),
-    "hoph_scan_timing": (C.c_int, [vp, vp, u32, C.POINTER(QueryParamsC), u32, C.POINTER(C.c_float), vp]),
+    "hoph_scan_timing": (C.c_int, [vp, vp, u32, C.POINTER(QueryParamsC), u32, vp, u64, C.POINTER(C.c_float), vp]),
     "hoph_index_free": (None, [vp]),
     "query_goph": (C.c_int, [vp, vp, u32, C.POINTER(QueryParamsC), C.POINTER(ResultsC), vp]),
     "query_hoph": (C.c_int, [vp, vp, u32, C.POINTER(QueryParamsC), C.POINTER(ResultsC), vp]),
@@ -114,6 +115,7 @@ SIGNATURES = {
                                    C.POINTER(vp)]),
     "hoph_plan_run": (C.c_int, [vp, vp, vp, u32, u64, vp]),
     "hoph_plan_results": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(u64), vp]),
+    "hoph_plan_query_sigs": (C.c_int, [vp, C.POINTER(vp), C.POINTER(u32)]),
     "hoph_plan_get_info": (C.c_int, [vp, C.POINTER(PlanInfoC)]),
     "hoph_plan_free": (None, [vp]),
     "hoph_server_create": (C.c_int, [vp, C.POINTER(SketchParamsC), C.POINTER(QueryParamsC),
@@ -285,6 +287,15 @@ class Index:
         _check(lib().hoph_index_code_planes(self._h, vp(out.data_ptr()), out.numel(), dims, _stream(stream)))
         return out[:cu * rows * pw].view(cu, rows // 64, 64, pw)
 
+    def rows(self, first=0, n=None, stream=None):
+        """Signatures int32[n][k] of index rows first .. first + n - 1 (a copy)."""
+        import torch
+        if n is None:
+            n = len(self) - first
+        out = torch.empty((max(n, 0), self.params.k), dtype=torch.int32, device="cuda")
+        _check(lib().hoph_index_rows(self._h, first, n, vp(out.data_ptr()), _stream(stream)))
+        return out
+
     def last_append_ms(self):
         """(sketch into the rows, code planes of the new rows) device ms of the
         last append_sets."""
@@ -353,14 +364,18 @@ def query_hoph(index: Index, qsigs, T=(4, 5), eps=(1, 10000), policy=EMPTY_JOINT
 
 
 def scan_timing(index: Index, qsigs, T=(4, 5), eps=(1, 10000), policy=EMPTY_JOINT, reps=20, coarse_depth=0,
-                coarse=COARSE_CODES, stream=None) -> float:
+                coarse=COARSE_CODES, flush=None, stream=None) -> float:
     """Mean device time (ms) of one coarse pass over the index for these query
-    signatures, reps launches back to back between two HIP events."""
+    signatures, reps launches back to back between two HIP events; with a
+    flush tensor (device memory larger than the last-level cache, at least
+    4 MiB, its first 4 MiB may be overwritten), each pass follows a read of it
+    and the reads' own time is subtracted."""
     import torch
     _need_cuda(qsigs, "qsigs", (torch.int32,))
     qp = QueryParamsC(_ratio(T), _ratio(eps), policy, coarse_depth, coarse, 0)
     ms = C.c_float()
-    _check(lib().hoph_scan_timing(index.handle, vp(qsigs.data_ptr()), qsigs.shape[0], C.byref(qp), reps,
+    fp, fb = (vp(flush.data_ptr()), flush.numel() * flush.element_size()) if flush is not None else (None, 0)
+    _check(lib().hoph_scan_timing(index.handle, vp(qsigs.data_ptr()), qsigs.shape[0], C.byref(qp), reps, fp, fb,
                                   C.byref(ms), _stream(stream)))
     return float(ms.value)
 
@@ -490,6 +505,15 @@ class Plan:
         _device_copy(offs.data_ptr(), po.value, (self._nq + 1) * 8, stream)
         _device_copy(ids.data_ptr(), pi.value, int(n.value) * 4, stream)
         return offs, ids[:int(n.value)]
+
+    def query_sigs(self, k: int, stream=None):
+        """Signatures int32[n_q][k] of the last batch's query sets (a copy)."""
+        import torch
+        pq, n = vp(), u32()
+        _check(lib().hoph_plan_query_sigs(self._h, C.byref(pq), C.byref(n)))
+        out = torch.empty((int(n.value), k), dtype=torch.int32, device="cuda")
+        _device_copy(out.data_ptr(), pq.value, int(n.value) * k * 4, stream)
+        return out
 
     def info(self) -> dict:
         i = PlanInfoC()

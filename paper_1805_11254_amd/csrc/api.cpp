@@ -63,12 +63,14 @@ hoph_status check_results(const hoph_results *r, uint32_t n_q) {
 
 
 // Pick queries per wavefront so that the grid has enough wavefronts to fill
-// the device (about 32 per CU) without splitting the query batch further.
+// the device (about 32 per CU) without splitting the query batch further, and
+// into at most one chunk per kChunkQueries queries (each chunk reads the
+// index's planes again).
 uint32_t pick_q_per_wave(uint64_t n_sets, uint32_t n_q, uint32_t tiles_per_wave) {
     const uint64_t per_wave = 64ull * std::max<uint32_t>(1, tiles_per_wave);
     const uint64_t ntiles = std::max<uint64_t>(1, (n_sets + per_wave - 1) / per_wave);
     uint64_t want_chunks = (4 * 8192ull + ntiles - 1) / ntiles;   // about four rounds of items
-    if (want_chunks > n_q) want_chunks = n_q;
+    want_chunks = std::min<uint64_t>(want_chunks, std::max<uint64_t>(1, n_q / kChunkQueries));
     if (want_chunks == 0) want_chunks = 1;
     return (uint32_t)((n_q + want_chunks - 1) / want_chunks);
 }
@@ -161,10 +163,14 @@ namespace {
 
 // time_reps > 0: a measurement run instead of a query -- the coarse pass alone,
 // time_reps launches back to back between two events, the mean written to
-// *time_ms; no output is written (res may be a dummy).
+// *time_ms; no output is written (res may be a dummy).  With flush_bytes > 0 a
+// read of flush[0 .. flush_bytes) precedes every timed pass, so that each pass
+// starts with the index's planes out of the caches (which then hold clean
+// lines only), and the time of the same reads alone is taken off.
 hoph_status run_query_impl(const hoph_index *cidx, Workspace *ws_in, const uint32_t *d_qsigs, uint32_t n_q,
                            const hoph_query_params *qp, hoph_results *res, void *stream, QueryKind kind,
-                           bool self_join, uint64_t n_limit, uint32_t time_reps = 0, float *time_ms = nullptr) {
+                           bool self_join, uint64_t n_limit, uint32_t time_reps = 0, float *time_ms = nullptr,
+                           uint32_t *flush = nullptr, uint64_t flush_bytes = 0) {
     if (!cidx) return fail(HOPH_E_INVAL, "index is NULL");
     if (!qp) return fail(HOPH_E_INVAL, "query params are NULL");
     if (self_join) {
@@ -264,14 +270,25 @@ hoph_status run_query_impl(const hoph_index *cidx, Workspace *ws_in, const uint3
         a.q_per_wave = pick_q_per_wave(n_sets, n_q, coarse_tiles_per_wave(a, tab));
         HOPH_HIP(launch_fill_u64(ws.counters, 4, 0, s), "fill counters");
         HOPH_HIP(launch_scan_coarse(a, tab, s), "coarse scan launch");    // warm: code object, caches
+        if (flush_bytes) HOPH_HIP(launch_read_sweep(flush, flush_bytes, flush, s), "flush read");   // warm it
         HOPH_HIP(hipEventRecord(ws.ev[0], s), "hipEventRecord");
         // survivors past the buffer are counted, not written, so repeated passes stay in bounds
-        for (uint32_t r = 0; r < time_reps; ++r) HOPH_HIP(launch_scan_coarse(a, tab, s), "coarse scan launch");
+        for (uint32_t r = 0; r < time_reps; ++r) {
+            if (flush_bytes) HOPH_HIP(launch_read_sweep(flush, flush_bytes, flush, s), "flush read");
+            HOPH_HIP(launch_scan_coarse(a, tab, s), "coarse scan launch");
+        }
         HOPH_HIP(hipEventRecord(ws.ev[1], s), "hipEventRecord");
-        HOPH_HIP(hipEventSynchronize(ws.ev[1]), "hipEventSynchronize");
-        float ms = 0.f;
+        if (flush_bytes) {
+            HOPH_HIP(hipEventRecord(ws.ev[2], s), "hipEventRecord");
+            for (uint32_t r = 0; r < time_reps; ++r)
+                HOPH_HIP(launch_read_sweep(flush, flush_bytes, flush, s), "flush read");
+            HOPH_HIP(hipEventRecord(ws.ev[3], s), "hipEventRecord");
+        }
+        HOPH_HIP(hipEventSynchronize(flush_bytes ? ws.ev[3] : ws.ev[1]), "hipEventSynchronize");
+        float ms = 0.f, flush_ms = 0.f;
         HOPH_HIP(hipEventElapsedTime(&ms, ws.ev[0], ws.ev[1]), "hipEventElapsedTime");
-        *time_ms = ms / (float)time_reps;
+        if (flush_bytes) HOPH_HIP(hipEventElapsedTime(&flush_ms, ws.ev[2], ws.ev[3]), "hipEventElapsedTime");
+        *time_ms = std::max(0.f, ms - flush_ms) / (float)time_reps;
         return HOPH_OK;
     }
     auto record_timing = [&]() {
@@ -397,13 +414,18 @@ hoph_status run_query(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t 
 }
 
 hoph_status scan_timing(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t n_q, const hoph_query_params *qp,
-                        uint32_t reps, float *ms, void *stream) {
+                        uint32_t reps, void *d_flush, uint64_t flush_bytes, float *ms, void *stream) {
     if (!cidx || !ms) return fail(HOPH_E_INVAL, "NULL argument");
     if (reps == 0) return fail(HOPH_E_INVAL, "reps must be >= 1");
+    if (flush_bytes && !d_flush) return fail(HOPH_E_INVAL, "d_flush is NULL");
+    if (reinterpret_cast<uintptr_t>(d_flush) % 16) return fail(HOPH_E_INVAL, "d_flush must be 16-byte aligned");
+    if (flush_bytes && flush_bytes < kSweepSinkBytes)
+        return fail(HOPH_E_INVAL, "flush_bytes must be 0 or at least 4 MiB");
     const QueryKind kind = cidx->params.layout == HOPH_LAYOUT_OPH ? QueryKind::GOPH : QueryKind::HOPH;
     uint64_t dummy_off = 0;
     hoph_results r{&dummy_off, nullptr, 0, 0};
-    return run_query_impl(cidx, nullptr, d_qsigs, n_q, qp, &r, stream, kind, false, ~0ull, reps, ms);
+    return run_query_impl(cidx, nullptr, d_qsigs, n_q, qp, &r, stream, kind, false, ~0ull, reps, ms,
+                          static_cast<uint32_t *>(d_flush), flush_bytes / 16 * 16);
 }
 
 hoph_status run_query_in(const hoph_index *cidx, Workspace &ws, const uint32_t *d_qsigs, uint32_t n_q,
@@ -564,6 +586,21 @@ hoph_status hoph_index_code_planes(const hoph_index *idx, uint32_t *d_out, uint6
     return HOPH_OK;
 }
 
+hoph_status hoph_index_rows(const hoph_index *idx, uint64_t first, uint64_t n, uint32_t *d_out, void *hip_stream) {
+    g_last_error.clear();
+    if (!idx) return fail(HOPH_E_INVAL, "index is NULL");
+    if (first > idx->n || n > idx->n - first) return fail(HOPH_E_RANGE, "rows past the index size");
+    if (n == 0) return HOPH_OK;
+    if (!d_out) return fail(HOPH_E_INVAL, "d_out is NULL");
+    DeviceGuard dg(idx->device);
+    if (!dg.ok) return fail(HOPH_E_DEVICE, "cannot select the index device");
+    const uint64_t k = idx->lay.k;
+    HOPH_HIP(hipMemcpyAsync(d_out, idx->slab + first * k, n * k * 4, hipMemcpyDeviceToDevice,
+                            reinterpret_cast<hipStream_t>(hip_stream)),
+             "hipMemcpyAsync(index rows)");
+    return HOPH_OK;
+}
+
 hoph_status hoph_index_reset(hoph_index *idx) {
     g_last_error.clear();
     if (!idx) return fail(HOPH_E_INVAL, "index is NULL");
@@ -582,9 +619,10 @@ hoph_status hoph_query_timing(const hoph_index *idx, float ms[3]) {
 }
 
 hoph_status hoph_scan_timing(const hoph_index *index, const uint32_t *d_qsigs, uint32_t n_q,
-                             const hoph_query_params *qp, uint32_t reps, float *ms_per_launch, void *hip_stream) {
+                             const hoph_query_params *qp, uint32_t reps, void *d_flush, uint64_t flush_bytes,
+                             float *ms_per_launch, void *hip_stream) {
     g_last_error.clear();
-    return scan_timing(index, d_qsigs, n_q, qp, reps, ms_per_launch, hip_stream);
+    return scan_timing(index, d_qsigs, n_q, qp, reps, d_flush, flush_bytes, ms_per_launch, hip_stream);
 }
 
 hoph_status hoph_append_timing(const hoph_index *idx, float ms[2]) {

@@ -18,6 +18,11 @@ constexpr uint64_t kP32 = 4294967311ull;        // 2^32 + 15, prime
 constexpr uint32_t kLutMax = 4096;              // region lookup entries
 constexpr uint32_t kTile = 64;                  // sets per index tile = one wavefront
 constexpr uint32_t kMaxDepth = 4;               // coarse groups (code units) kept in registers
+// Queries per chunk of the coarse pass, at least (up to the batch size): every
+// chunk reads the index's code planes once, and up to about this many queries a
+// pass reads more bytes than its integer work hides (32 bytes of planes per set
+// against 5-11 lane-operations per pair).
+constexpr uint32_t kChunkQueries = 64;
 // Narrowed coarse pass: an 8-bit code per bin, stored as 8 bit-planes per
 // code unit (bit i of plane p = bit p of the code of bin i of the unit), so
 // that one 32-bit word holds one plane of 32 bins.  EMPTY has a code of its own.
@@ -367,6 +372,10 @@ int device_cu_count();   // compute units of the current device (cached)
 // values travel as kernel arguments, so no host buffer has to outlive the call).
 hipError_t launch_set_desc(uint64_t *desc, uint64_t a, uint64_t b, hipStream_t st);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t value, hipStream_t st);
+// Reads bytes (a multiple of 16) at p, 4096 x 256 threads; a thread may write
+// its own word of sink (kSweepSinkBytes) only in a case the data never meets.
+constexpr uint64_t kSweepSinkBytes = 4096ull * 256 * 4;
+hipError_t launch_read_sweep(const void *p, uint64_t bytes, uint32_t *sink, hipStream_t st);
 // Where the sketch of an index append also writes the new rows' code planes
 // (the index's tiled layout, see k_index.hip): set i of the launch is index row
 // first + i.  codes == nullptr: signatures only.

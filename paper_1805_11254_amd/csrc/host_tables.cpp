@@ -224,91 +224,146 @@ void host_starts(const LayoutInfo &lay, std::vector<uint64_t> &starts) {
 }
 
 // ---------------------------------------------------------------------------
-// Minimal unsigned big integers for exact binomial tails.
+// Minimal unsigned big integers for exact binomial tails, in fixed storage (no
+// heap use, so that table construction allocates nothing).
 // ---------------------------------------------------------------------------
 struct Big {
-    std::vector<uint32_t> d;   // little-endian limbs, no leading zeros
+    // every value below fits: terms and sums are at most td^n * 2^41 and
+    // td^n * ed <= 2^(32 n + 32) for n <= 256 binomial trials
+    static constexpr uint32_t kLimbs = 264;
+    uint32_t d[kLimbs];        // little-endian limbs; d[n..] are not kept
+    uint32_t n = 0;            // limbs in use, no leading zeros
+    bool overflow = false;
     static Big of(uint64_t v) {
         Big b;
-        while (v) { b.d.push_back((uint32_t)v); v >>= 32; }
+        while (v) { b.d[b.n++] = (uint32_t)v; v >>= 32; }
         return b;
     }
-    void trim() { while (!d.empty() && d.back() == 0) d.pop_back(); }
+    bool zero() const { return n == 0; }
+    void trim() { while (n && d[n - 1] == 0) --n; }
     void add(const Big &o) {
-        if (o.d.size() > d.size()) d.resize(o.d.size(), 0);
+        overflow |= o.overflow;
+        const uint32_t m = n > o.n ? n : o.n;
         uint64_t c = 0;
-        for (size_t i = 0; i < d.size(); ++i) {
-            uint64_t s = (uint64_t)d[i] + (i < o.d.size() ? o.d[i] : 0) + c;
+        for (uint32_t i = 0; i < m; ++i) {
+            const uint64_t s = (uint64_t)(i < n ? d[i] : 0) + (i < o.n ? o.d[i] : 0) + c;
             d[i] = (uint32_t)s;
             c = s >> 32;
         }
-        if (c) d.push_back((uint32_t)c);
+        n = m;
+        if (c) {
+            if (n == kLimbs) { overflow = true; return; }
+            d[n++] = (uint32_t)c;
+        }
     }
-    Big mul(const Big &o) const {
-        Big r;
-        if (d.empty() || o.d.empty()) return r;
-        r.d.assign(d.size() + o.d.size(), 0);
-        for (size_t i = 0; i < d.size(); ++i) {
+    // *this *= v (v < 2^64): two passes of 32-bit factors, every partial
+    // product and carry within 64 bits
+    void mul_small(uint64_t v) {
+        if (v == 0 || n == 0) { n = 0; return; }
+        uint32_t tmp[kLimbs + 2] = {};
+        for (uint32_t pass = 0; pass < 2; ++pass) {
+            const uint32_t f = (uint32_t)(v >> (32 * pass));
+            if (!f) continue;
             uint64_t c = 0;
-            for (size_t j = 0; j < o.d.size(); ++j) {
-                uint64_t t = (uint64_t)d[i] * o.d[j] + r.d[i + j] + c;
-                r.d[i + j] = (uint32_t)t;
+            for (uint32_t i = 0; i < n; ++i) {
+                const uint64_t t = (uint64_t)d[i] * f + tmp[i + pass] + c;
+                tmp[i + pass] = (uint32_t)t;
                 c = t >> 32;
             }
-            size_t k = i + o.d.size();
-            while (c) {
-                uint64_t t = (uint64_t)r.d[k] + c;
-                r.d[k++] = (uint32_t)t;
+            for (uint32_t k = n + pass; c; ++k) {      // k <= n + 1: the product has at most n + 2 limbs
+                const uint64_t t = (uint64_t)tmp[k] + c;
+                tmp[k] = (uint32_t)t;
                 c = t >> 32;
             }
         }
-        r.trim();
-        return r;
+        uint32_t m = n + 2;
+        while (m && tmp[m - 1] == 0) --m;
+        if (m > kLimbs) { overflow = true; return; }
+        for (uint32_t i = 0; i < m; ++i) d[i] = tmp[i];
+        n = m;
+    }
+    // *this /= v where v (0 < v < 2^64) divides *this exactly; false otherwise
+    bool div_exact_small(uint64_t v) {
+        unsigned __int128 r = 0;
+        for (uint32_t i = n; i-- > 0;) {
+            const unsigned __int128 cur = (r << 32) | d[i];
+            d[i] = (uint32_t)(cur / v);
+            r = cur % v;
+        }
+        trim();
+        return r == 0;
     }
     static int cmp(const Big &a, const Big &b) {
-        if (a.d.size() != b.d.size()) return a.d.size() < b.d.size() ? -1 : 1;
-        for (size_t i = a.d.size(); i-- > 0;)
+        if (a.n != b.n) return a.n < b.n ? -1 : 1;
+        for (uint32_t i = a.n; i-- > 0;)
             if (a.d[i] != b.d[i]) return a.d[i] < b.d[i] ? -1 : 1;
         return 0;
     }
 };
 
+// With X ~ Bin(n, T), T = tn/td, and q = td - tn:
+//   P(X = i) td^n = C(n, i) tn^i q^(n - i) =: term_i,
+// term_{i+1} = term_i (n - i) tn / ((i + 1) q) and term_{i-1} = term_i i q / ((n - i + 1) tn),
+// both exact divisions, so each tail is accumulated one term at a time.
 hoph_status tail_integers(uint32_t n, hoph_ratio T, hoph_ratio eps, int32_t &j_lo, int32_t &j_hi,
                           std::string &err) {
     if (n == 0 || n > 256) { err = "binomial size must be in [1, 256]"; return HOPH_E_INVAL; }
     if (T.den == 0 || T.num == 0 || T.num > T.den) { err = "T must be in (0, 1]"; return HOPH_E_INVAL; }
     if (eps.den == 0 || eps.num >= eps.den) { err = "eps must be in [0, 1)"; return HOPH_E_INVAL; }
-    // P(X = i) td^n = C(n, i) tn^i (td - tn)^(n - i)
-    std::vector<Big> C(n + 1), pw(n + 1), pq(n + 1), term(n + 1);
-    C[0] = Big::of(1);
-    for (uint32_t row = 1; row <= n; ++row)            // Pascal's rule, right to left
-        for (uint32_t i = row; i >= 1; --i) {
-            if (i == row) C[i] = Big::of(1); else C[i].add(C[i - 1]);
-        }
-    pw[0] = Big::of(1);
-    pq[0] = Big::of(1);
-    Big btn = Big::of(T.num), bq = Big::of(T.den - T.num);
-    for (uint32_t i = 1; i <= n; ++i) { pw[i] = pw[i - 1].mul(btn); pq[i] = pq[i - 1].mul(bq); }
-    for (uint32_t i = 0; i <= n; ++i) term[i] = C[i].mul(pw[i]).mul(pq[n - i]);
-    Big total = Big::of(1);
-    Big btd = Big::of(T.den);
-    for (uint32_t i = 0; i < n; ++i) total = total.mul(btd);
-    Big rhs = total.mul(Big::of(eps.num));          // eps td^n, scaled by eps.den below
-    Big bed = Big::of(eps.den);
-    // lower tail: P(X <= j) <= eps  <=>  ed * sum_{i <= j} term_i <= en * td^n
+    const uint64_t tn = T.num, q = (uint64_t)T.den - T.num;
+    // rhs = eps.num td^n; the tail test is eps.den * tail <= rhs
+    Big rhs = Big::of(eps.num);
+    for (uint32_t i = 0; i < n; ++i) rhs.mul_small(T.den);
+    bool exact = true;
+    // lower tail: P(X <= j) <= eps, terms from i = 0 upwards
     j_lo = -1;
-    Big cum;
-    for (uint32_t j = 0; j <= n; ++j) {
-        cum.add(term[j]);
-        if (Big::cmp(cum.mul(bed), rhs) <= 0) j_lo = (int32_t)j; else break;
+    {
+        Big term = Big::of(1);                         // term_0 = q^n
+        for (uint32_t i = 0; i < n; ++i) term.mul_small(q);
+        Big cum;
+        for (uint32_t j = 0; j <= n; ++j) {
+            if (j > 0) {
+                if (q == 0) {                          // T = 1: only term_n = tn^n is not zero
+                    term = Big();
+                    if (j == n) {
+                        term = Big::of(1);
+                        for (uint32_t i = 0; i < n; ++i) term.mul_small(tn);
+                    }
+                } else {
+                    term.mul_small((uint64_t)(n - j + 1) * tn);
+                    exact &= term.div_exact_small((uint64_t)j * q);
+                }
+            }
+            cum.add(term);
+            Big lhs = cum;
+            lhs.mul_small(eps.den);
+            if (Big::cmp(lhs, rhs) <= 0) j_lo = (int32_t)j; else break;
+        }
+        exact &= !cum.overflow && !term.overflow;
     }
-    // upper tail: P(X >= j) <= eps
+    // upper tail: P(X >= j) <= eps, terms from i = n downwards
     j_hi = (int32_t)n + 1;
-    Big cu;
-    for (int32_t j = (int32_t)n; j >= 0; --j) {
-        cu.add(term[j]);
-        if (Big::cmp(cu.mul(bed), rhs) <= 0) j_hi = j; else break;
+    {
+        Big term = Big::of(1);                         // term_n = tn^n
+        for (uint32_t i = 0; i < n; ++i) term.mul_small(tn);
+        Big cu;
+        for (int32_t j = (int32_t)n; j >= 0; --j) {
+            if (j < (int32_t)n) {
+                if (q == 0) {
+                    term = Big();
+                } else {                                // term_j from term_{j+1}
+                    term.mul_small((uint64_t)(j + 1) * q);
+                    exact &= term.div_exact_small((uint64_t)(n - (uint32_t)j) * tn);
+                }
+            }
+            cu.add(term);
+            Big lhs = cu;
+            lhs.mul_small(eps.den);
+            if (Big::cmp(lhs, rhs) <= 0) j_hi = j; else break;
+        }
+        exact &= !cu.overflow && !term.overflow;
     }
+    if (!exact || rhs.overflow) { err = "internal error: binomial tail arithmetic"; return HOPH_E_UNSUPPORTED; }
     return HOPH_OK;
 }
 

@@ -21,6 +21,20 @@ __global__ __launch_bounds__(kThreads) void fill_u64_kernel(uint64_t *p, uint64_
         p[i] = value;
 }
 
+// Reads p[0 .. n) (16-byte words) and keeps nothing: a measurement helper that
+// replaces the caches' contents with clean lines.  The store below happens only
+// when the words' XOR equals `never`, which the caller picks so that it does not
+// (it keeps the loads from being removed).
+__global__ __launch_bounds__(kThreads) void read_sweep_kernel(const uint4 *p, uint64_t n, uint32_t never,
+                                                               uint32_t *sink) {
+    uint32_t acc = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kThreads) {
+        const uint4 v = p[i];
+        acc ^= v.x ^ v.y ^ v.z ^ v.w;
+    }
+    if (acc == never) sink[blockIdx.x * kThreads + threadIdx.x] = acc;
+}
+
 // 8 x 8 bit transpose of a 64-bit word (byte r = row r, bit c = column c):
 // three exchanges of off-diagonal blocks of 1, 2 and 4 bits.  Byte p of the
 // result holds bit p of each of the eight input bytes.
@@ -237,6 +251,14 @@ hipError_t launch_set_desc(uint64_t *desc, uint64_t a, uint64_t b, hipStream_t s
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t value, hipStream_t st) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(n, kThreads, 4096)), dim3(kThreads), 0, st, p, n, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_read_sweep(const void *p, uint64_t bytes, uint32_t *sink, hipStream_t st) {
+    const uint64_t n = bytes / 16;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(read_sweep_kernel, dim3(4096), dim3(kThreads), 0, st, static_cast<const uint4 *>(p), n,
+                       0x9E3779B9u, sink);
     return hipGetLastError();
 }
 

@@ -63,6 +63,14 @@ __device__ __forceinline__ uint64_t lane_rank(uint64_t mask, uint32_t lane) {
     return __popcll(mask & ((1ull << lane) - 1ull));
 }
 
+// Queries per (tile, query chunk) work item.  A plan's kernels read the batch
+// size from the descriptor, so the tuned chunk is raised here to the whole
+// batch up to kChunkQueries (a batch split into chunks reads the planes once per
+// chunk).  Never 0 (a.q_per_wave >= 1).
+__device__ __forceinline__ uint32_t chunk_queries(const CoarseArgs &a, const uint64_t *desc, uint32_t nq) {
+    return desc ? max(a.q_per_wave, min(nq, kChunkQueries)) : a.q_per_wave;
+}
+
 // Append the lanes with `flag` set: one atomic per wavefront.  Returns the slot
 // of this lane (valid only where flag is set).  Call with the whole wave active.
 __device__ __forceinline__ uint64_t wave_append(bool flag, unsigned long long *counter, uint32_t lane) {
@@ -316,8 +324,9 @@ __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__
     SurvBatch<kSurvBatch> sb{s_surv[wave_id_in_block()], 0};
     const uint64_t n_sets = desc ? desc[1] : a.n_sets;
     const uint32_t q_lo = desc ? 0u : a.q0, q_hi = desc ? (uint32_t)desc[0] : a.q1;
+    const uint32_t qpw = chunk_queries(a, desc, q_hi - q_lo);
     const uint64_t ntiles = (n_sets + 63) / 64;
-    const uint32_t nchunks = (q_hi - q_lo + a.q_per_wave - 1) / a.q_per_wave;
+    const uint32_t nchunks = (q_hi - q_lo + qpw - 1) / qpw;
     const uint64_t n_items = ntiles * nchunks;
     const uint64_t wstride = (uint64_t)gridDim.x * kWaves;
     const uint32_t kp = a.kp, pk = a.pk, cd = a.cdepth;
@@ -328,7 +337,7 @@ __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__
     const uint64_t tile = item % ntiles;
     const uint32_t chunk = (uint32_t)(item / ntiles);
     // self-join: skip (before any load) a tile with no set id above the chunk's first query row
-    if (a.tri && tile * 64 + 63 <= (uint64_t)q_lo + (uint64_t)chunk * a.q_per_wave) continue;
+    if (a.tri && tile * 64 + 63 <= (uint64_t)q_lo + (uint64_t)chunk * qpw) continue;
     const uint64_t s = tile * 64 + lane;
     const bool valid = s < n_sets;
 
@@ -355,8 +364,8 @@ __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__
         }
     }
 
-    const uint32_t qa = q_lo + chunk * a.q_per_wave;
-    const uint32_t qb = min(q_hi, qa + a.q_per_wave);
+    const uint32_t qa = q_lo + chunk * qpw;
+    const uint32_t qb = min(q_hi, qa + qpw);
     for (uint32_t q = qa; q < qb; ++q) {
         const uint32_t *qc = qcodes + (uint64_t)q * a.cg * RW;
         const uint64_t *qmk = qmasks + (uint64_t)q * a.L;
@@ -407,8 +416,9 @@ __global__ __launch_bounds__(64) void scan_codes_deep_kernel(const uint32_t *__r
     const uint32_t lane = threadIdx.x;
     const uint64_t n_sets = desc ? desc[1] : a.n_sets;
     const uint32_t q_lo = desc ? 0u : a.q0, q_hi = desc ? (uint32_t)desc[0] : a.q1;
+    const uint32_t qpw = chunk_queries(a, desc, q_hi - q_lo);
     const uint64_t ntiles = (n_sets + 63) / 64;
-    const uint32_t nchunks = (q_hi - q_lo + a.q_per_wave - 1) / a.q_per_wave;
+    const uint32_t nchunks = (q_hi - q_lo + qpw - 1) / qpw;
     const uint64_t n_items = ntiles * nchunks;
     const uint32_t kp = a.kp, pk = a.pk, cd = a.cdepth;
     const uint64_t kpmask = kp >= 64 ? ~0ull : ((1ull << kp) - 1ull);
@@ -417,10 +427,10 @@ __global__ __launch_bounds__(64) void scan_codes_deep_kernel(const uint32_t *__r
     for (uint64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
         const uint64_t tile = item % ntiles;
         const uint32_t chunk = (uint32_t)(item / ntiles);
-        const uint32_t qa = q_lo + chunk * a.q_per_wave;
+        const uint32_t qa = q_lo + chunk * qpw;
         // self-join: skip a tile with no set id above the chunk's first query row
         if (a.tri && tile * 64 + 63 <= (uint64_t)qa) continue;
-        const uint32_t qb = min(q_hi, qa + a.q_per_wave);
+        const uint32_t qb = min(q_hi, qa + qpw);
         const uint64_t s = tile * 64 + lane;
         const bool valid = s < n_sets;
 
@@ -529,9 +539,10 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_
     SurvBatch<kSurvBatch> sb{s_surv[wave_id_in_block()], 0};
     const uint64_t n_sets = desc ? desc[1] : a.n_sets;
     const uint32_t q_lo = desc ? 0u : a.q0, q_hi = desc ? (uint32_t)desc[0] : a.q1;
+    const uint32_t qpw = chunk_queries(a, desc, q_hi - q_lo);
     const uint64_t ntiles = (n_sets + 63) / 64;
     const uint64_t ngroups = (ntiles + TPW - 1) / TPW;
-    const uint32_t nchunks = (q_hi - q_lo + a.q_per_wave - 1) / a.q_per_wave;
+    const uint32_t nchunks = (q_hi - q_lo + qpw - 1) / qpw;
     const uint64_t n_items = ngroups * nchunks;
     const uint64_t wstride = (uint64_t)gridDim.x * kWaves;
     const uint64_t ctiles = a.capacity / 64;
@@ -539,8 +550,8 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_
     for (uint64_t item = (uint64_t)blockIdx.x * kWaves + wave_id_in_block(); item < n_items; item += wstride) {
         const uint64_t tg = item % ngroups;
         const uint32_t chunk = (uint32_t)(item / ngroups);
-        const uint32_t qa = q_lo + chunk * a.q_per_wave;
-        const uint32_t qb = min(q_hi, qa + a.q_per_wave);
+        const uint32_t qa = q_lo + chunk * qpw;
+        const uint32_t qb = min(q_hi, qa + qpw);
         // self-join: skip (before any load) an item with no set id above its first query row
         if (TRI && (tg + 1) * TPW * 64 <= (uint64_t)qa + 1) continue;
         uint32_t P[TPW][PW];
@@ -643,8 +654,9 @@ __global__ __launch_bounds__(kThreads) void scan_coarse_kernel(const uint32_t *_
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t n_sets = desc ? desc[1] : a.n_sets;
     const uint32_t q_lo = desc ? 0u : a.q0, q_hi = desc ? (uint32_t)desc[0] : a.q1;
+    const uint32_t qpw = chunk_queries(a, desc, q_hi - q_lo);
     const uint64_t ntiles = (n_sets + 63) / 64;
-    const uint32_t nchunks = (q_hi - q_lo + a.q_per_wave - 1) / a.q_per_wave;
+    const uint32_t nchunks = (q_hi - q_lo + qpw - 1) / qpw;
     const uint64_t n_items = ntiles * nchunks;
     const uint64_t wstride = (uint64_t)gridDim.x * kWaves;
     const uint32_t kp = EXACT ? KPAD : a.kp;
@@ -655,7 +667,7 @@ __global__ __launch_bounds__(kThreads) void scan_coarse_kernel(const uint32_t *_
     const uint64_t tile = item % ntiles;
     const uint32_t chunk = (uint32_t)(item / ntiles);
     // self-join: skip (before any load) a tile with no set id above the chunk's first query row
-    if (a.tri && tile * 64 + 63 <= (uint64_t)q_lo + (uint64_t)chunk * a.q_per_wave) continue;
+    if (a.tri && tile * 64 + 63 <= (uint64_t)q_lo + (uint64_t)chunk * qpw) continue;
     const uint64_t s = tile * 64 + lane;
     const bool valid = s < n_sets;
 
@@ -672,8 +684,8 @@ __global__ __launch_bounds__(kThreads) void scan_coarse_kernel(const uint32_t *_
         emask[g] = em & kpmask;
     }
 
-    const uint32_t qa = q_lo + chunk * a.q_per_wave;
-    const uint32_t qb = min(q_hi, qa + a.q_per_wave);
+    const uint32_t qa = q_lo + chunk * qpw;
+    const uint32_t qb = min(q_hi, qa + qpw);
     for (uint32_t q = qa; q < qb; ++q) {
         const uint32_t *qw = qsigs + (uint64_t)q * a.k;
         const uint64_t *qmk = qmasks + (uint64_t)q * a.L;

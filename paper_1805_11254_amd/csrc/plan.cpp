@@ -432,6 +432,15 @@ hoph_status hoph_plan_results(hoph_plan *p, const uint64_t **d_offsets, const ui
     return HOPH_OK;
 }
 
+hoph_status hoph_plan_query_sigs(const hoph_plan *p, const uint32_t **d_qsigs, uint32_t *n_q) {
+    clear_error();
+    if (!p || !d_qsigs || !n_q) return fail(HOPH_E_INVAL, "NULL argument");
+    if (!p->pending) return fail(HOPH_E_INVAL, "no batch has been run");
+    *d_qsigs = p->q_sigs;
+    *n_q = p->last_nq;
+    return HOPH_OK;
+}
+
 hoph_status hoph_plan_get_info(const hoph_plan *p, hoph_plan_info *info) {
     clear_error();
     if (!p || !info) return fail(HOPH_E_INVAL, "NULL argument");

@@ -230,7 +230,7 @@ hoph_status run_query_in(const hoph_index *cidx, Workspace &ws, const uint32_t *
                          const hoph_query_params *qp, hoph_results *res, void *stream, QueryKind kind);
 // The coarse pass alone, reps launches back to back between two events (hoph_scan_timing).
 hoph_status scan_timing(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t n_q, const hoph_query_params *qp,
-                        uint32_t reps, float *ms, void *stream);
+                        uint32_t reps, void *d_flush, uint64_t flush_bytes, float *ms, void *stream);
 // The scan tables for qp on idx's layout, from the index's cache (caller holds idx->mu).
 hoph_status cached_scan_tab(hoph_index *idx, const hoph_query_params &qp, bool goph, ScanTab &out);
 // The results of a plan's last batch copied to host buffers with one stream

@@ -180,6 +180,12 @@ def test_tail_integers_match_oracle():
             for eps in (F(0), F(1, 10 ** 5), F(1, 10 ** 4), F(1, 100), F(1, 2)):
                 assert H.tail_integers(n, (T.numerator, T.denominator), (eps.numerator, eps.denominator)) == \
                     tiny.tail_integers(n, T, eps), (n, T, eps)
+    # the largest sizes and 32-bit numerators and denominators (widest big integers)
+    big = (1 << 32) - 1
+    for n, T, eps in ((256, F(big - 1, big), F(1, big)), (256, F(1, 3), F(big - 2, big)),
+                      (200, F(1, big), F(1, 10 ** 4))):
+        assert H.tail_integers(n, (T.numerator, T.denominator), (eps.numerator, eps.denominator)) == \
+            tiny.tail_integers(n, T, eps), (n, T, eps)
 
 
 def _rand_sig_pair(rng, k, rho, p_empty):

@@ -200,23 +200,54 @@ def plant(coll: Collection, queries: Collection, per_query: int, j_lo: float, j_
     truth = []
     for qi in range(nq):
         Q = np.unique(queries.set(qi))
-        m = len(Q)
         for r in range(per_query):
             J = rng.uniform(j_lo, j_hi)
-            x = int(round(m * (1 - J) / (1 + J)))
-            x = max(0, min(x, m - 1))
-            keep = rng.choice(Q, size=m - x, replace=False)
-            add = np.zeros(0, dtype=np.uint32)
-            while len(add) < x:
-                cand = np.unique(np.asarray(fresh(rng, 4 * x + 8), dtype=np.uint32))
-                cand = cand[~np.isin(cand, Q)]
-                add = np.unique(np.concatenate([add, cand]))
-            add = rng.permutation(add)[:x]
-            newset = np.sort(np.concatenate([keep, add]).astype(np.uint32))
+            newset, Jx = _perturb(rng, Q, J, fresh)
             slot = int(slots[qi * per_query + r])
             repl[slot] = newset
-            truth.append((qi, slot, (m - x) / (m + x)))
+            truth.append((qi, slot, Jx))
     return replace_sets(coll, repl), truth
+
+
+def _perturb(rng, Q: np.ndarray, J: float, fresh) -> Tuple[np.ndarray, float]:
+    """A set at Jaccard about J from the distinct ids Q: drop x of its m ids and
+    add x fresh ones, x = round(m (1 - J) / (1 + J)); returns it (sorted) and its
+    exact J = (m - x) / (m + x)."""
+    m = len(Q)
+    x = int(round(m * (1 - J) / (1 + J)))
+    x = max(0, min(x, m - 1))
+    keep = rng.choice(Q, size=m - x, replace=False)
+    add = np.zeros(0, dtype=np.uint32)
+    while len(add) < x:
+        cand = np.unique(np.asarray(fresh(rng, 4 * x + 8), dtype=np.uint32))
+        cand = cand[~np.isin(cand, Q)]
+        add = np.unique(np.concatenate([add, cand]))
+    add = rng.permutation(add)[:x]
+    return np.sort(np.concatenate([keep, add]).astype(np.uint32)), (m - x) / (m + x)
+
+
+def plant_queries(batches: List[Collection], source: Collection, frac: float, j_lo: float, j_hi: float,
+                  fresh, seed: int, row_offset: int = 0):
+    """Replace a fraction of the queries of each batch with near-duplicates of
+    random sets of `source` (the collection, or a prefix of it) at J in
+    [j_lo, j_hi].  Returns the new batches and (batch, query, source row +
+    row_offset, exact J) per planted query."""
+    rng = np.random.default_rng(seed)
+    out, truth = [], []
+    for bi, b in enumerate(batches):
+        n_dup = int(rng.binomial(b.n, frac))
+        if n_dup == 0:
+            out.append(b)
+            continue
+        which = np.sort(rng.choice(b.n, size=n_dup, replace=False))
+        sets = [b.set(i) for i in range(b.n)]
+        for qi in which.tolist():
+            row = int(rng.integers(0, source.n))
+            J = rng.uniform(j_lo, j_hi)
+            sets[qi], Jx = _perturb(rng, np.unique(source.set(row)), J, fresh)
+            truth.append((bi, qi, row + row_offset, Jx))
+        out.append(csr_from_lists(sets))
+    return out, truth
 
 
 def replace_sets(coll: Collection, repl: dict) -> Collection:
