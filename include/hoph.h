@@ -251,6 +251,21 @@ hoph_status query_goph(const hoph_index *index, const uint32_t *d_qsigs, uint32_
 hoph_status query_hoph(const hoph_index *index, const uint32_t *d_qsigs, uint32_t n_q,
                        const hoph_query_params *qp, hoph_results *results, void *hip_stream);
 
+/* query_hoph_noalloc -- query_hoph for callers that cannot allocate (code under
+   HIP graph capture, tight serving loops, harnesses that forbid allocation):
+   the same arguments, checks and results, but no device or pinned memory is
+   allocated.  Its buffers beyond the inputs and outputs live in a 64 MiB
+   device array that the library holds on each device it runs on until the
+   process ends.  Limits, each refused with HOPH_E_CAPACITY and a message
+   before anything runs or when reached: n_q <= 4096 queries; n_q * L <= 262,144
+   per-group query masks; at most 2^20 accepted pairs per call (results->needed
+   is set) and about 3.1 million first-pass survivors for any one query.  Calls
+   on one device are serialised by the library (each finishes, stream
+   synchronised, before the next starts); calls on different devices run
+   independently.  Synchronises hip_stream. */
+hoph_status query_hoph_noalloc(const hoph_index *index, const uint32_t *d_qsigs, uint32_t n_q,
+                               const hoph_query_params *qp, hoph_results *results, void *hip_stream);
+
 /* query_oph_full -- plain OPH comparator (Eq. 6 over all k bins, no early stop):
    accept iff N_mb / (k - N_eb) >= T under qp->empty_policy (eps ignored). Any layout. */
 hoph_status query_oph_full(const hoph_index *index, const uint32_t *d_qsigs, uint32_t n_q,

@@ -99,6 +99,7 @@ SIGNATURES = {
     "query_goph": (C.c_int, [vp, vp, u32, C.POINTER(QueryParamsC), C.POINTER(ResultsC), vp]),
     "query_hoph": (C.c_int, [vp, vp, u32, C.POINTER(QueryParamsC), C.POINTER(ResultsC), vp]),
     "query_oph_full": (C.c_int, [vp, vp, u32, C.POINTER(QueryParamsC), C.POINTER(ResultsC), vp]),
+    "query_hoph_noalloc": (C.c_int, [vp, vp, u32, C.POINTER(QueryParamsC), C.POINTER(ResultsC), vp]),
     "minwise_sketch": (C.c_int, [C.POINTER(MinwiseParamsC), vp, vp, u64, vp, vp]),
     "minwise_query": (C.c_int, [C.POINTER(MinwiseParamsC), vp, u64, vp, u32, Ratio, C.POINTER(ResultsC), vp]),
     "hoph_sync": (C.c_int, [vp]),
@@ -337,8 +338,8 @@ def _run_query(fn, handle, qsigs, qp: QueryParamsC, capacity, stream, device):
         ids = torch.empty(max(cap, 1), dtype=torch.int32, device=device)
         res = ResultsC(offsets.data_ptr(), ids.data_ptr(), cap, 0)
         st = fn(handle, vp(qsigs.data_ptr()), n_q, C.byref(qp), C.byref(res), _stream(stream))
-        if st == HOPH_E_CAPACITY and capacity is None:
-            cap = int(res.needed)
+        if st == HOPH_E_CAPACITY and capacity is None and int(res.needed) > cap:
+            cap = int(res.needed)             # the output was too small: retry with what it needs
             continue
         _check(st, int(res.needed))
         return offsets, ids[:int(res.needed)]
@@ -392,11 +393,18 @@ def self_join(index: Index, T=(4, 5), eps=(1, 10000), policy=EMPTY_JOINT, capaci
         ids = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
         res = ResultsC(offsets.data_ptr(), ids.data_ptr(), cap, 0)
         st = lib().hoph_self_join(index.handle, C.byref(qp), C.byref(res), _stream(stream))
-        if st == HOPH_E_CAPACITY and capacity is None:
-            cap = int(res.needed)
+        if st == HOPH_E_CAPACITY and capacity is None and int(res.needed) > cap:
+            cap = int(res.needed)             # the output was too small: retry with what it needs
             continue
         _check(st, int(res.needed))
         return offsets, ids[:int(res.needed)]
+
+
+def query_hoph_noalloc(index: Index, qsigs, T=(4, 5), eps=(1, 10000), policy=EMPTY_JOINT, capacity=None,
+                       coarse_depth=0, stream=None, coarse=COARSE_CODES):
+    """query_hoph through the entry point that allocates no device memory (the
+    library's fixed per-device scratch); the output tensors are allocated here."""
+    return _query("query_hoph_noalloc", index, qsigs, T, eps, policy, capacity, coarse_depth, stream, coarse)
 
 
 def query_oph_full(index: Index, qsigs, T=(4, 5), policy=EMPTY_JOINT, capacity=None, stream=None):
@@ -443,8 +451,8 @@ def minwise_query(params: MinwiseParams, sigs, qsigs, T=(4, 5), capacity=None, s
         res = ResultsC(offsets.data_ptr(), ids.data_ptr(), cap, 0)
         st = lib().minwise_query(C.byref(pc), vp(sigs.data_ptr()), sigs.shape[0], vp(qsigs.data_ptr()), n_q,
                                  _ratio(T), C.byref(res), _stream(stream))
-        if st == HOPH_E_CAPACITY and capacity is None:
-            cap = int(res.needed)
+        if st == HOPH_E_CAPACITY and capacity is None and int(res.needed) > cap:
+            cap = int(res.needed)             # the output was too small: retry with what it needs
             continue
         _check(st, int(res.needed))
         return offsets, ids[:int(res.needed)]

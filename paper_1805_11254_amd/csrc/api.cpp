@@ -29,7 +29,6 @@ hoph_status hip_fail(hipError_t e, const char *what) {
 }
 
 // One 32-bit device error word per device, allocated on first use.
-constexpr int kMaxDevices = 64;
 std::mutex g_err_mu;
 uint32_t *g_err[kMaxDevices] = {};
 

@@ -15,6 +15,7 @@ uint32_t max_depth_for_kpad(uint32_t kpad);
 uint64_t sort_capacity(uint64_t n);
 
 // Record msg as the calling thread's last error and return st.
+constexpr int kMaxDevices = 64;           // device ordinals the library keeps per-device state for
 hoph_status fail(hoph_status st, const std::string &msg);
 hoph_status hip_fail(hipError_t e, const char *what);
 void clear_error();
