@@ -1,20 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the OPH/HOPH hot path on one MI355X.
 
-One step is the whole path over one batch: sketch every set of the collection
-(one shared universal hash, k bins, per-bin minimum) straight into the
-resident index (row-major signature rows and the narrowed code planes of the
-first groups), sketch the query batch, and answer every query with the (1:1) HOPH
-scan (coarse pass on codes, per-survivor pass on the words, sorted CSR output).  Workload: 1,000,000
-bag-of-visual-words sets over 2^20 codewords (Zipf(1.1) codewords, log-normal
-sizes, median 600, clipped to [100, 4000]), h(x) = (a x + b) mod (2^31 - 1),
-k = 512 bins in groups of 32, 1,024 queries with 1% of the collection planted as
-near-duplicates at J in [0.5, 0.98], T = 4/5, eps = 1e-4.  Inputs are seeded
-synthetic data resident in HBM before the timed region.
+One step is the whole path over one batch of the 4,000,000-set text-shingle
+workload: for each of the (1:2) and (2:1) hierarchies, every set is sketched
+(one shared universal hash (a x + b) mod (2^32 + 15) over 2^32 ids, k = 256 bins
+in groups of 32, per-bin minimum) straight into that hierarchy's resident index
+(row-major signature rows and the narrowed code planes of the first groups),
+the 4,096 query sets are sketched, and every query is answered by the HOPH scan
+(coarse pass on codes, per-survivor pass on the words, sorted CSR output) at
+T = 1/2, 7/10 and 9/10, eps = 1e-4.  Set sizes are uniform in 20-2,000; about
+10 near-duplicates per query are planted at J in [0.5, 0.98].  Inputs are
+seeded synthetic data resident in HBM before the timed region.
 
 Prints one JSON line.  ``value`` is query x index pairs decided per second over
-whole steps; per-kernel rates, the roofline of the dominant kernel and the
-oracle's CPU rate on a bounded sample are attached.
+whole steps.  Attached: per-kernel rates and the roofline of the dominant
+kernel; accuracy against the planted pairs and exact Jaccard similarity; plain
+OPH and MinWise on the same GPU; the 1,000,000-set bag-of-visual-words step
+(HOPH 1:1, k = 512) with HOPH and plain OPH compared at identical recall; the
+coarse pass for small query batches read cold from HBM, and served p50/p99, on
+an 8,000,000-set index; and the oracle's CPU rate on bounded samples.
 """
 from __future__ import annotations
 
@@ -40,8 +44,14 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n-sets", type=int, default=None,
-                    help="collection size (default 1,000,000; 2,000,000 batched; 8,000,000 serve)")
-    ap.add_argument("--n-queries", type=int, default=1024)
+                    help="collection size of the other modes (default 1,000,000; 2,000,000 batched; "
+                         "8,000,000 serve)")
+    ap.add_argument("--n-queries", type=int, default=1024, help="queries of the comparators, selfjoin and "
+                    "sweeps modes")
+    ap.add_argument("--c3-sets", type=int, default=4_000_000, help="text-shingle sets of the headline step")
+    ap.add_argument("--c3-queries", type=int, default=4096, help="queries of the headline step")
+    ap.add_argument("--c2-sets", type=int, default=1_000_000, help="bag-of-words sets of the second step")
+    ap.add_argument("--c5-sets", type=int, default=8_000_000, help="sets of the serving index")
     ap.add_argument("--seed", type=int, default=1806)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-sets", type=int, default=1_000_000)
@@ -52,15 +62,20 @@ def parse():
                     help="scansweep: query batch sizes")
     ap.add_argument("--sweep-sets", type=str, default="1000000,8000000",
                     help="scansweep: index sizes (k = 512 up to 2,000,000 sets, else 256)")
-    ap.add_argument("--mode", choices=["step", "batched", "serve", "comparators", "selfjoin", "sweeps", "scansweep"],
+    ap.add_argument("--mode", choices=["step", "c3", "batched", "serve", "comparators", "selfjoin", "sweeps",
+                                       "scansweep"],
                     default="step",
-                    help="step: the whole-path step (default JSON line); batched: uneven query batches through "
+                    help="step: the whole-path step on the 4,000,000-set shingle workload with the comparators, "
+                         "the 1,000,000-set bag-of-words step, the small-batch scan and serving on the "
+                         "8,000,000-set index (default JSON line); c3: the headline step alone; "
+                         "batched: uneven query batches through "
                          "graph-replayed plans; serve: Poisson arrivals through the serving loop; comparators: "
                          "one-query-per-launch OPH/HOPH and MinWise on the same GPU; selfjoin: every pair inside "
                          "one collection; sweeps: GOPH group count, error tolerance and threshold sweeps")
     ap.add_argument("--batches", type=int, default=256)
     ap.add_argument("--rates", type=str, default="20000,50000,100000,200000,300000")
-    ap.add_argument("--serve-seconds", type=float, default=0.5)
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
+                    help="seconds of arrivals per served rate (at least 100,000 requests in --mode serve)")
     ap.add_argument("--serve-rate", type=float, default=50_000,
                     help="offered queries/s of the step's serving measurement (0 = skip it)")
     return ap.parse_args()
@@ -104,7 +119,7 @@ def cpu_baseline(w, n_sets, n_q, sample_sets, sample_q):
     }
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hoph11_bovw_1M_pmc_traffic.txt")
+TRAFFIC_FILE_C3 = os.path.join(ROOT, "profiles", "hoph_shingles_4M_pmc_traffic.txt")
 
 
 def kernel_source_hash() -> str:
@@ -120,12 +135,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def load_traffic():
-    """HBM bytes per launch from the committed PMC summary, by kernel name
-    prefix, or {} when the kernels changed since the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def load_traffic(path):
+    """HBM bytes per launch from a committed PMC summary, by kernel name
+    prefix (the largest launch of that kernel), or {} when the kernels changed
+    since the counters were taken."""
+    if not os.path.exists(path):
         return {}
-    lines = open(TRAFFIC_FILE).read().splitlines()
+    lines = open(path).read().splitlines()
     recorded = next((l.split()[1] for l in lines if l.startswith("kernel_source_sha256")), None)
     if recorded != kernel_source_hash():
         return {}
@@ -203,6 +219,14 @@ def bench_batched(args):
     dev = torch.device("cuda")
     p = H.SketchParams(W.LAYOUT_HIER, 512, 32, W.HASH_MODP31, 1 << 20, 1, 1, int(a[0]), int(b[0]))
     idx = _resident_index(H, p, N, args.seed)
+    # 1% of the queries replaced by near-duplicates (J in [0.5, 0.98]) of sets of
+    # the index's first chunk (regenerated from its seed), so that the
+    # per-survivor pass and the output stage have work in the measured batches
+    first = W.zipf_sets(min(N, 1_000_000), 1 << 20, 600, 0.75, 100, 4000, args.seed)
+    cw = np.random.default_rng(args.seed + 7).permutation(1 << 20).astype(np.uint32)
+    fresh = lambda g, c: cw[W._zipf_ranks(g, 1 << 20, c, 1.1)]
+    batches, planted = W.plant_queries(batches, first, 0.01, 0.5, 0.98, fresh, args.seed + 51)
+    del first
     dq = [(torch.from_numpy(bt.ids.view(np.int32)).to(dev), torch.from_numpy(bt.offsets.view(np.int64)).to(dev))
           for bt in batches]
     n_q = np.array([bt.n for bt in batches])
@@ -211,6 +235,7 @@ def bench_batched(args):
            "config": {"workload": "hoph_1to1_bovw_batched", "n_sets": N, "k": 512, "k_group": 32,
                       "batches": len(batches), "queries": int(n_q.sum()), "query_ids": int(sum(b.ids.size for b in batches)),
                       "batch_size_median": float(np.median(n_q)), "batch_size_max": int(n_q.max())}}
+    out["config"]["planted_queries"] = len(planted)
     for name, use_graph in (("graph", True), ("eager", False)):
         plan = H.Plan(idx, p, T=(4, 5), eps=(1, 10000), max_queries=4096, max_query_ids=max_ids,
                       max_results=1 << 20, use_graph=use_graph, tune=True)
@@ -228,7 +253,23 @@ def bench_batched(args):
         out[name] = {"seconds": wall, "queries_per_s": float(n_q.sum()) / wall,
                      "pairs_per_s": float(n_q.sum()) * N / wall, "batch_ms_p50": _pct(lat, 50),
                      "batch_ms_p99": _pct(lat, 99), "accepted_pairs": found, "plan": info}
-        log(f"{name}: {wall:.3f} s for {len(dq)} batches")
+        if name == "graph":
+            # recall of the planted pairs at J >= T (outside the timed loop)
+            hit = want = 0
+            for bi, d in enumerate(dq):
+                mine = [(q, row) for (b_, q, row, J) in planted if b_ == bi and J >= 0.8]
+                if not mine:
+                    continue
+                plan.run(*d)
+                o, i_ = plan.results()
+                o, i_ = o.cpu().numpy(), i_.cpu().numpy().view(np.uint32)
+                for q, row in mine:
+                    want += 1
+                    hit += row in set(i_[o[q]:o[q + 1]].tolist())
+            out[name]["planted_recall"] = hit / max(1, want)
+            out[name]["planted_at_or_above_T"] = want
+        log(f"{name}: {wall:.3f} s for {len(dq)} batches, fallbacks {info['fallbacks']} "
+            f"(causes {info['fallback_causes']})")
         plan.free()
     # the host-synchronised path, batch by batch (sketch_oph + query_hoph)
     t0 = time.perf_counter()
@@ -281,7 +322,7 @@ def bench_serve(args):
             time.sleep(args.serve_seconds / 5)
 
     for r in rates:
-        n = max(1, int(r * args.serve_seconds))
+        n = max(100_000, int(r * args.serve_seconds))
         # 0.1 s at this rate first, so that the slots this rate keeps busy have
         # run (tuned and captured on) their first batch before the measurement
         t_w, wq = W.poisson_arrivals(r, max(1, int(r * 0.1)), args.seed + 1 + int(r))
@@ -707,19 +748,654 @@ def bench_scansweep(args):
     print(json.dumps(out), flush=True)
 
 
+# ---------------------------------------------------------------------------
+# The default record: the headline step on the 4,000,000-set shingle workload,
+# the 1,000,000-set bag-of-words step beside it, serving and the small-batch
+# scan on the 8,000,000-set index
+# ---------------------------------------------------------------------------
+C3_RATIOS = ((1, 2), (2, 1))
+C3_T = ((1, 2), (7, 10), (9, 10))
+
+
+def _tag(r):
+    return f"{r[0]}:{r[1]}"
+
+
+def _ttag(T):
+    return f"{T[0]}/{T[1]}"
+
+
+def _code_units(k, kp, goph):
+    """(groups per code unit pk, code units, coded groups) of an index, as the
+    library lays them out: pk = min(32 // k', L) for k' <= 16, else 1; at least 4
+    units and about 128 bins (HOPH) or 256 (GOPH), at most 24 units (12 for
+    k' > 32), none past the row."""
+    L = k // kp
+    pk = min(32 // kp, L) if kp <= 16 else 1
+    cu = min(L // pk, max(4, min(12 if kp > 32 else 24, -(-(256 if goph else 128) // (pk * kp)))))
+    return pk, cu, cu * pk
+
+
+def _coarse_model(H, p, T, eps, goph=False):
+    """How the library runs the coarse pass for these parameters, and the
+    algorithmic work of one launch per (query, set) pair.
+
+    Depth: the first group alone when it rejects at least 1/8 of its match counts
+    (no empty bins); else one group past the first step with a reject cutoff,
+    in whole code units.  Work: the first-group pass compares P1 planes of every
+    pair first (P1 W plane operations, W masks, W popcounts, one compare;
+    P1 = 2 when the threshold on differing bins is at most half the bins, 4 when
+    at most three quarters, else all 8 planes, 10 W + 1); a deeper pass compares
+    at least the first code unit of every pair (10 W + 1) and updates the
+    weighted state of its group (an int64 multiply-add and two compares, 6 more).
+    Bytes: each set's planes of the units walked (32 W per unit) per launch."""
+    k, kp = p.k, p.k_group
+    pk, cu, cg = _code_units(k, kp, goph)
+    tabs = H.decision_tables(p, T, eps)
+    unit0 = tabs["W"][0] * tabs["dmul"][0]
+    m_rej0 = tabs["rej"][0] // unit0 if tabs["rej"][0] >= 0 else -1
+    Wp = 1 if kp <= 32 else 2
+    if m_rej0 >= 0 and 8 * m_rej0 >= kp:
+        depth = 1
+        dthr = kp - m_rej0
+        split = 2 if 2 * dthr <= kp else (4 if 4 * dthr <= 3 * kp else 0)
+        ops = Wp * (split + 2) + 1 if split else 10 * Wp + 1
+        kernel = "scan_codes_fast_kernel"
+    else:
+        g1 = next((l + 1 for l, r in enumerate(tabs["rej"]) if r >= 0), None)
+        depth = cg if g1 is None else min(cg, -(-(g1 + 1) // pk) * pk)
+        split = 0
+        ops = 10 * Wp + 1 + 6
+        kernel = "scan_codes_kernel" if -(-depth // pk) <= 4 else "scan_codes_deep_kernel"
+    units = -(-depth // pk)
+    return {"kernel": kernel, "depth": depth, "code_units_walked": units, "ops_per_pair": ops,
+            "first_phase_planes": split, "plane_bytes_per_set": 32 * Wp * units,
+            "record_bytes_per_query": (8 * Wp + 4) * 4 * units}
+
+
+def _jaccard_cache(qcoll, coll):
+    cache = {}
+
+    def exact(q, s):
+        key = (q, s)
+        if key not in cache:
+            cache[key] = _exact_j(qcoll.set(q), coll.set(s))
+        return cache[key]
+    return exact
+
+
+def _accuracy(offs_h, ids_h, planted, exact, T, nq):
+    """Recall over the planted pairs of the first nq queries whose exact J
+    reaches T; precision over the returned pairs by exact J."""
+    t = T[0] / T[1]
+    got = set()
+    for q in range(nq):
+        for s in ids_h[offs_h[q]:offs_h[q + 1]].tolist():
+            got.add((q, s))
+    truth = {(q, s) for (q, s, J) in planted if q < nq and J >= t}
+    tp = sum(exact(q, s) >= t for (q, s) in got)
+    return {"recall": len(truth & got) / max(1, len(truth)), "precision": tp / max(1, len(got)),
+            "accepted": len(got), "planted_at_or_above_T": len(truth)}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_c3(w, N, Q, pairs_per_step):
+    """The oracle (plain C, OpenMP) on bounded samples of the step's workload:
+    both hierarchies' sketches of the first sets, the decisions of the first
+    queries against them at every threshold, extrapolated linearly to one whole
+    step (2 x (N + Q) sketches, 6 x N x Q decisions).  Median of three runs, on
+    every host core and on one."""
+    from fractions import Fraction
+    import numpy as np
+    from oracle import scale
+
+    def run(ns, nq, nthreads):
+        t_sk = t_q = 0.0
+        for r in C3_RATIOS:
+            kw = dict(hash_kind=w.hash_kind, universe=w.universe, layout=w.layout, k=w.k, kp=w.kp, ra=r[0],
+                      rb=r[1], ha=w.ha, hb=w.hb, nthreads=nthreads)
+            t0 = time.perf_counter()
+            sig = scale.sketch(w.collection.ids, w.collection.offsets, which=np.arange(ns, dtype=np.uint64), **kw)
+            t_sk += time.perf_counter() - t0
+            qsig = scale.sketch(w.queries.ids, w.queries.offsets, which=np.arange(nq, dtype=np.uint64), **kw)
+            for T in C3_T:
+                t0 = time.perf_counter()
+                scale.query(sig, qsig, goph=False, kp=w.kp, T=Fraction(*T), eps=Fraction(*w.eps), ra=r[0], rb=r[1],
+                            nthreads=nthreads)
+                t_q += time.perf_counter() - t0
+        per_set = t_sk / (len(C3_RATIOS) * ns)
+        per_pair = t_q / (len(C3_RATIOS) * len(C3_T) * ns * nq)
+        full = len(C3_RATIOS) * (N + Q) * per_set + len(C3_RATIOS) * len(C3_T) * N * Q * per_pair
+        return {"value": pairs_per_step / full, "sets_sketched_per_s": 1.0 / per_set,
+                "pairs_decided_per_s": 1.0 / per_pair, "step_s": full, "seconds": t_sk + t_q}
+
+    def median3(ns, nq, nthreads):
+        runs = [run(ns, nq, nthreads) for _ in range(3)]
+        runs.sort(key=lambda x: x["value"])
+        med = dict(runs[1])
+        med["runs"] = [x["value"] for x in runs]
+        return med
+
+    cores = scale.max_threads()
+    ns_all, nq_all = min(N, 200_000), min(Q, 16)
+    ns_one, nq_one = min(N, 20_000), min(Q, 8)
+    allc = median3(ns_all, nq_all, 0)
+    one = median3(ns_one, nq_one, 1)
+    return {
+        "value": allc["value"],
+        "unit": "query x index pairs decided/s (whole step, extrapolated)",
+        "cores": cores,
+        "kind": "oracle",
+        "cpu_model": _cpu_model(),
+        "sample": (f"median of 3 runs: oracle sketches of the first {ns_all} sets for (1:2) and (2:1) and the "
+                   f"decisions of the first {nq_all} queries against them at T = 1/2, 7/10, 9/10, extrapolated "
+                   f"linearly to {N} sets x {Q} queries ({allc['step_s']:.0f} s per step)"),
+        "sets_sketched_per_s": allc["sets_sketched_per_s"],
+        "pairs_decided_per_s": allc["pairs_decided_per_s"],
+        "runs": allc["runs"],
+        "one_core": {"value": one["value"], "cores": 1, "sets_sketched_per_s": one["sets_sketched_per_s"],
+                     "pairs_decided_per_s": one["pairs_decided_per_s"], "runs": one["runs"],
+                     "sample": f"first {ns_one} sets, first {nq_one} queries, same extrapolation"},
+    }
+
+
+def run_c3(args, H, W, np, torch):
+    """The headline step: 4,000,000 text-shingle sets over 2^32 ids (sizes
+    20-2,000), 4,096 queries with about 10 planted near-duplicates each,
+    (a x + b) mod (2^32 + 15), k = 256 in groups of 32.  One step: for (1:2)
+    and (2:1) HOPH, every set sketched straight into that hierarchy's resident
+    index (rows and code planes), the queries sketched, and the whole batch
+    answered at T = 1/2, 7/10 and 9/10 (eps = 1e-4)."""
+    dev = torch.device("cuda")
+    t0 = time.perf_counter()
+    w = W.hoph_shingles(n=args.c3_sets, n_q=args.c3_queries, seed=1807)
+    N, Q, k, kp = w.collection.n, w.queries.n, w.k, w.kp
+    nnz = int(w.collection.ids.size)
+    log(f"shingles: {N} sets / {nnz} ids, {Q} queries generated in {time.perf_counter() - t0:.1f} s")
+    ids = torch.from_numpy(w.collection.ids.view(np.int32)).to(dev)
+    offs = torch.from_numpy(w.collection.offsets.view(np.int64)).to(dev)
+    qids = torch.from_numpy(w.queries.ids.view(np.int32)).to(dev)
+    qoffs = torch.from_numpy(w.queries.offsets.view(np.int64)).to(dev)
+    params = {r: H.SketchParams(W.LAYOUT_HIER, k, kp, w.hash_kind, w.universe, r[0], r[1], w.ha, w.hb)
+              for r in C3_RATIOS}
+    empty = torch.empty((0, k), dtype=torch.int32, device=dev)
+    idx = {r: H.Index(params[r], empty, capacity=N) for r in C3_RATIOS}
+    qsig = {r: torch.empty((Q, k), dtype=torch.int32, device=dev) for r in C3_RATIOS}
+    stream = torch.cuda.current_stream()
+    cap = {}
+    nev = 3 + len(C3_T)
+
+    def step(ev=None, rec=None):
+        outs = {}
+        for ri, r in enumerate(C3_RATIOS):
+            e = ev[ri] if ev is not None else None
+            if e: e[0].record(stream)
+            idx[r].reset()
+            idx[r].append_sets(ids, offs)
+            if e: e[1].record(stream)
+            H.sketch_oph(params[r], qids, qoffs, out=qsig[r])
+            if e: e[2].record(stream)
+            for ti, T in enumerate(C3_T):
+                outs[(r, T)] = H.query_hoph(idx[r], qsig[r], T=T, eps=w.eps, capacity=cap.get((r, T)))
+                if rec is not None:
+                    rec[(r, T)] = idx[r].last_query_ms()
+                if e: e[3 + ti].record(stream)
+            if rec is not None:
+                rec[(r, "append")] = idx[r].last_append_ms()
+        return outs
+
+    for _ in range(max(1, args.warmup)):
+        outs = step()
+        for key, (o, i_) in outs.items():
+            cap[key] = max(cap.get(key, 0), 1 << 16, 2 * int(i_.numel()))
+    H.sync()
+    torch.cuda.synchronize()
+    log("shingles: warm-up done")
+    evs = [[[torch.cuda.Event(enable_timing=True) for _ in range(nev)] for _ in C3_RATIOS] for _ in range(args.steps)]
+    recs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        rec = {}
+        outs = step(evs[s], rec)
+        recs.append(rec)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    pairs_per_step = len(C3_RATIOS) * len(C3_T) * N * Q
+    log(f"shingles: {args.steps} steps, {ms_per_step:.2f} ms/step")
+
+    def ev_ms(ri, a, b):
+        return sum(e[ri][a].elapsed_time(e[ri][b]) for e in evs) / len(evs)
+
+    def rec_mean(key, j):
+        return sum(r[key][j] for r in recs) / len(recs)
+
+    sketch_bytes = nnz * 4 + (N + 1) * 8 + N * k * 4
+    pk, cu, cg = _code_units(k, kp, False)
+    code_bytes = N * cg * kp * 4 + N * cu * 32
+    kernels, phase = {}, {}
+    for ri, r in enumerate(C3_RATIOS):
+        tg = _tag(r)
+        sk, cd = rec_mean((r, "append"), 0), rec_mean((r, "append"), 1)
+        kernels[f"sketch_into_index[{tg}]"] = {
+            "kernel": "sketch_kernel", "ms": sk, "bound": "hbm", "achieved": sketch_bytes / (sk * 1e-3) / 1e9,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "algorithmic_bytes": sketch_bytes, "sets_per_s": N / (sk * 1e-3)}
+        kernels[f"code_planes[{tg}]"] = {
+            "kernel": "row_codes_vec_kernel", "ms": cd, "bound": "hbm", "achieved": code_bytes / (cd * 1e-3) / 1e9,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "algorithmic_bytes": code_bytes}
+        phase[f"index_build[{tg}]"] = ev_ms(ri, 0, 1)
+        phase[f"query_sketch[{tg}]"] = ev_ms(ri, 1, 2)
+        for ti, T in enumerate(C3_T):
+            m = _coarse_model(H, params[r], T, w.eps)
+            co, fi, so = rec_mean((r, T), 0), rec_mean((r, T), 1), rec_mean((r, T), 2)
+            ops = Q * N * m["ops_per_pair"]
+            byts = N * m["plane_bytes_per_set"] + Q * m["record_bytes_per_query"]
+            kernels[f"scan_coarse[{tg},T={_ttag(T)}]"] = dict(
+                m, ms=co, bound="alu", achieved=ops / (co * 1e-3) / 1e12, peak=ALU_PEAK_OPS / 1e12,
+                unit="Tops/s (32-bit VALU lane-ops)", algorithmic_ops=ops, hbm_gbs=byts / (co * 1e-3) / 1e9,
+                pairs_per_s=Q * N / (co * 1e-3))
+            kernels[f"scan_fine[{tg},T={_ttag(T)}]"] = {"kernel": "scan_fine_kernel", "ms": fi}
+            kernels[f"sort_and_csr[{tg},T={_ttag(T)}]"] = {"ms": so}
+            phase[f"query[{tg},T={_ttag(T)}]"] = ev_ms(ri, 2 + ti, 3 + ti)
+    for v in kernels.values():
+        if "achieved" in v:
+            v["frac"] = v["achieved"] / v["peak"]
+    timed = {n: v for n, v in kernels.items() if "achieved" in v}
+    dom_name = max(timed, key=lambda n: timed[n]["ms"])
+    dom = timed[dom_name]
+    longest_unmodelled = max((v["ms"], n) for n, v in kernels.items() if "achieved" not in v)
+    roofline = {"kernel": dom_name, "bound": dom["bound"], "achieved": dom["achieved"], "peak": dom["peak"],
+                "unit": dom["unit"], "frac": dom["frac"], "traffic": None,
+                "ms": dom["ms"], "longest_other_kernel": {"name": longest_unmodelled[1], "ms": longest_unmodelled[0]}}
+    if dom["bound"] == "hbm":
+        roofline["algorithmic_bytes"] = dom["algorithmic_bytes"]
+    else:
+        roofline["algorithmic_ops"] = dom["algorithmic_ops"]
+        roofline["ops_per_pair"] = dom["ops_per_pair"]
+    traffic = load_traffic(TRAFFIC_FILE_C3)
+    if dom["kernel"] in traffic:
+        roofline["traffic"] = traffic[dom["kernel"]]
+
+    # accuracy of the last step's answers against the planted pairs and exact J
+    exact = _jaccard_cache(w.queries, w.collection)
+    acc = {}
+    for (r, T), (o, i_) in outs.items():
+        acc.setdefault(_tag(r), {})[_ttag(T)] = _accuracy(o.cpu().numpy(), i_.cpu().numpy().view(np.uint32),
+                                                          w.planted, exact, T, Q)
+    sk_mean = sum(kernels[f"sketch_into_index[{_tag(r)}]"]["ms"] for r in C3_RATIOS) / len(C3_RATIOS)
+    scan_ms = sum(v for n, v in phase.items() if n.startswith("query["))
+    rec = {
+        "metric": "sets sketched/s + query x index signature compares/s (HBM %), served p99 ms",
+        "value": pairs_per_step / (ms_per_step * 1e-3),
+        "unit": "query x index pairs decided/s (whole step: both hierarchies' sketches into their indexes, "
+                "query sketches, HOPH scans at three thresholds)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "hoph_12_21_shingles", "n_sets": N, "n_queries": Q, "nnz": nnz,
+                   "universe": w.universe, "k": k, "k_group": kp, "groups": k // kp, "ratios": ["1:2", "2:1"],
+                   "T": [_ttag(T) for T in C3_T], "eps": "1/10000", "hash": "(a x + b) mod (2^32 + 15)",
+                   "empty_policy": "joint", "parallelism": "single GPU"},
+        "sets_sketched_per_s": N / (sk_mean * 1e-3),
+        "scan_pairs_per_s": pairs_per_step / (scan_ms * 1e-3),
+        "phase_ms": phase,
+        "kernels": kernels,
+        "roofline": roofline,
+        "accuracy": acc,
+    }
+    state = {"w": w, "ids": ids, "offs": offs, "qids": qids, "qoffs": qoffs, "idx": idx, "exact": exact,
+             "pairs_per_step": pairs_per_step}
+    return rec, state
+
+
+def c3_comparators(args, H, W, np, torch, st):
+    """The paper's comparison methods on the same GPU and collection, outside
+    the timed step: plain OPH over all 256 bins (Eq. 6, no early stop) and
+    MinWise with k = 512 independent hashes mod 2^32 + 15, each one query per
+    launch and batched, with recall and precision on the first 256 queries;
+    HOPH (1:2) and (2:1) one query per launch beside them."""
+    w, ids, offs, qids, qoffs, exact = st["w"], st["ids"], st["offs"], st["qids"], st["qoffs"], st["exact"]
+    dev = torch.device("cuda")
+    N, Q, k = w.collection.n, w.queries.n, w.k
+    n_acc = min(Q, 256)
+    sample = list(range(0, Q, max(1, Q // 16)))[:16]
+    out = {"accuracy_queries": n_acc, "one_per_launch_queries": len(sample)}
+
+    def one_per_launch(fn):
+        fn(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in sample:
+            fn(i)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / len(sample)
+
+    for r, ix in st["idx"].items():
+        p = H.SketchParams(W.LAYOUT_HIER, k, w.kp, w.hash_kind, w.universe, r[0], r[1], w.ha, w.hb)
+        qs = H.sketch_oph(p, qids, qoffs)
+        t = one_per_launch(lambda i: H.query_hoph(ix, qs[i:i + 1].contiguous(), T=(7, 10), eps=w.eps))
+        out[f"hoph{r[0]}{r[1]}_one_query_per_launch"] = {"ms_per_query": t * 1e3, "pairs_per_s": N / t}
+        del qs
+    po = H.SketchParams(W.LAYOUT_OPH, k, w.kp, w.hash_kind, w.universe, 1, 1, w.ha, w.hb)
+    ox = H.Index(po, torch.empty((0, k), dtype=torch.int32, device=dev), capacity=N)
+    ox.append_sets(ids, offs)
+    oq = H.sketch_oph(po, qids, qoffs)
+    t = one_per_launch(lambda i: H.query_oph_full(ox, oq[i:i + 1].contiguous(), T=(7, 10)))
+    ent = {"ms_per_query": t * 1e3, "pairs_per_s": N / t, "hbm_gbs": N * k * 4 / t / 1e9, "accuracy": {}}
+    for T in C3_T:
+        o, i_ = H.query_oph_full(ox, oq[:n_acc].contiguous(), T=T)
+        ent["accuracy"][_ttag(T)] = _accuracy(o.cpu().numpy(), i_.cpu().numpy().view(np.uint32), w.planted, exact,
+                                              T, n_acc)
+    out["oph_full_one_query_per_launch"] = ent
+    ox.free()
+    del oq
+    ha, hb = W.hash_coeffs(W.P32P15, 512, 1807 + 5)
+    mp = H.MinwiseParams(512, W.HASH_MODP32P15, w.universe, torch.from_numpy(ha.view(np.int64)).to(dev),
+                         torch.from_numpy(hb.view(np.int64)).to(dev))
+    H.minwise_sketch(mp, qids, qoffs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    msig = H.minwise_sketch(mp, ids, offs)
+    torch.cuda.synchronize()
+    t_sk = time.perf_counter() - t0
+    mq = H.minwise_sketch(mp, qids, qoffs)
+    t = one_per_launch(lambda i: H.minwise_query(mp, msig, mq[i:i + 1].contiguous(), T=(7, 10)))
+    ent = {"k": 512, "sketch_seconds": t_sk, "sets_sketched_per_s": N / t_sk, "ms_per_query": t * 1e3,
+           "pairs_per_s": N / t, "accuracy": {}}
+    for T in C3_T:
+        o, i_ = H.minwise_query(mp, msig, mq[:n_acc].contiguous(), T=T)
+        ent["accuracy"][_ttag(T)] = _accuracy(o.cpu().numpy(), i_.cpu().numpy().view(np.uint32), w.planted, exact,
+                                              T, n_acc)
+    out["minwise"] = ent
+    del msig, mq
+    return out
+
+
+def run_c2(args, H, W, np, torch):
+    """The 1,000,000-set bag-of-visual-words step (HOPH 1:1, k = 512 in groups of
+    32, 1,024 queries, T = 4/5): every set sketched into the resident index, the
+    queries sketched and scanned; beside it, on the same GPU and index, HOPH one
+    query per launch and served, and plain OPH one query per launch with its
+    threshold moved until its recall equals HOPH's (within 0.005)."""
+    dev = torch.device("cuda")
+    t0 = time.perf_counter()
+    w = W.hoph_bovw(n=args.c2_sets, n_q=1024, seed=args.seed)
+    N, Q, k, kp = w.collection.n, w.queries.n, w.k, w.kp
+    nnz = int(w.collection.ids.size)
+    log(f"bovw: {N} sets / {nnz} ids generated in {time.perf_counter() - t0:.1f} s")
+    ids = torch.from_numpy(w.collection.ids.view(np.int32)).to(dev)
+    offs = torch.from_numpy(w.collection.offsets.view(np.int64)).to(dev)
+    qids = torch.from_numpy(w.queries.ids.view(np.int32)).to(dev)
+    qoffs = torch.from_numpy(w.queries.offsets.view(np.int64)).to(dev)
+    p = H.SketchParams(w.layout, k, kp, w.hash_kind, w.universe, w.ra, w.rb, w.ha, w.hb)
+    qsig = torch.empty((Q, k), dtype=torch.int32, device=dev)
+    idx = H.Index(p, torch.empty((0, k), dtype=torch.int32, device=dev), capacity=N)
+    stream = torch.cuda.current_stream()
+    cap = [None]
+
+    def step(ev=None):
+        e = ev or [None] * 4
+        if e[0] is not None: e[0].record(stream)
+        idx.reset()
+        idx.append_sets(ids, offs)
+        if e[1] is not None: e[1].record(stream)
+        H.sketch_oph(p, qids, qoffs, out=qsig)
+        if e[2] is not None: e[2].record(stream)
+        o = H.query_hoph(idx, qsig, T=w.T, eps=w.eps, capacity=cap[0])
+        if e[3] is not None: e[3].record(stream)
+        return o
+
+    for _ in range(max(1, args.warmup)):
+        out = step()
+        if cap[0] is None:
+            cap[0] = max(1 << 16, 2 * int(out[1].numel()))
+    torch.cuda.synchronize()
+    steps = max(1, args.steps)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    qms, ams = [], []
+    t0 = time.perf_counter()
+    for s in range(steps):
+        out = step(evs[s])
+        qms.append(idx.last_query_ms())
+        ams.append(idx.last_append_ms())
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / steps
+
+    def mean_ev(a, b):
+        return sum(e[a].elapsed_time(e[b]) for e in evs) / len(evs)
+
+    sketch_ms = sum(a[0] for a in ams) / len(ams)
+    codes_ms = sum(a[1] for a in ams) / len(ams)
+    coarse_ms = sum(q[0] for q in qms) / len(qms)
+    sketch_bytes = nnz * 4 + (N + 1) * 8 + N * k * 4
+    m = _coarse_model(H, p, w.T, w.eps)
+    ops = Q * N * m["ops_per_pair"]
+    # the HBM rate a plain device copy reaches here (2 GiB)
+    cbuf = torch.empty(1 << 29, dtype=torch.int32, device=dev)
+    cdst = torch.empty_like(cbuf)
+    cdst.copy_(cbuf)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        cdst.copy_(cbuf)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * cbuf.numel() * 4 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del cbuf, cdst
+    # the sketch with the sets handed over in pinned host memory (copy, then sketch)
+    ids_pin = torch.from_numpy(w.collection.ids.view(np.int32)).pin_memory()
+    offs_pin = torch.from_numpy(w.collection.offsets.view(np.int64)).pin_memory()
+    sig = torch.empty((N, k), dtype=torch.int32, device=dev)
+    e2 = torch.cuda.Event(enable_timing=True)
+    h2d = []
+    for _ in range(2):
+        e0.record(stream)
+        ids.copy_(ids_pin, non_blocking=True)
+        offs.copy_(offs_pin, non_blocking=True)
+        e1.record(stream)
+        H.sketch_oph(p, ids, offs, out=sig)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        h2d.append((e0.elapsed_time(e1), e0.elapsed_time(e2)))
+    del ids_pin, offs_pin, sig
+
+    exact = _jaccard_cache(w.queries, w.collection)
+    hacc = _accuracy(out[0].cpu().numpy(), out[1].cpu().numpy().view(np.uint32), w.planted, exact, w.T, Q)
+    res = {
+        "workload": "hoph_1to1_bovw", "n_sets": N, "n_queries": Q, "nnz": nnz, "k": k, "k_group": kp,
+        "ratio": "1:1", "T": "4/5", "eps": "1/10000", "hash": "(a x + b) mod (2^31 - 1)",
+        "steps": steps, "ms_per_step": ms_per_step, "pairs_per_s": N * Q / (ms_per_step * 1e-3),
+        "sets_sketched_per_s": N / (sketch_ms * 1e-3),
+        "sets_sketched_per_s_with_h2d": N / (min(h[1] for h in h2d) * 1e-3),
+        "h2d_gbs": (nnz * 4 + (N + 1) * 8) / (min(h[0] for h in h2d) * 1e-3) / 1e9,
+        "copy_ceiling_gbs": copy_gbs,
+        "phase_ms": {"build_index": mean_ev(0, 1), "sketch_into_index": sketch_ms, "code_planes": codes_ms,
+                     "query_sketch": mean_ev(1, 2), "query": mean_ev(2, 3), "coarse": coarse_ms,
+                     "fine": sum(q[1] for q in qms) / len(qms), "sort_csr": sum(q[2] for q in qms) / len(qms)},
+        "sketch": {"ms": sketch_ms, "achieved_gbs": sketch_bytes / (sketch_ms * 1e-3) / 1e9,
+                   "frac": sketch_bytes / (sketch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                   "frac_of_copy": sketch_bytes / (sketch_ms * 1e-3) / 1e9 / copy_gbs},
+        "scan_coarse": dict(m, ms=coarse_ms, achieved_tops=ops / (coarse_ms * 1e-3) / 1e12,
+                            frac=ops / (coarse_ms * 1e-3) / ALU_PEAK_OPS),
+        "accuracy": hacc,
+    }
+    log(f"bovw: {ms_per_step:.3f} ms/step")
+
+    # same GPU, same index: HOPH one query per launch, batched (the step's scan),
+    # served; plain OPH one query per launch at the threshold giving HOPH's recall
+    sample = list(range(0, Q, max(1, Q // 64)))[:64]
+
+    def one_per_launch(fn):
+        fn(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in sample:
+            fn(i)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / len(sample)
+
+    t_h = one_per_launch(lambda i: H.query_hoph(idx, qsig[i:i + 1].contiguous(), T=w.T, eps=w.eps))
+    po = H.SketchParams(W.LAYOUT_OPH, k, kp, w.hash_kind, w.universe, 1, 1, w.ha, w.hb)
+    ox = H.Index(po, torch.empty((0, k), dtype=torch.int32, device=dev), capacity=N)
+    ox.append_sets(ids, offs)
+    oq = H.sketch_oph(po, qids, qoffs)
+    target = hacc["recall"]
+    tried = {}
+
+    def oph_at(num):                                  # plain OPH at T' = num / 1000
+        if num not in tried:
+            o, i_ = H.query_oph_full(ox, oq, T=(num, 1000))
+            a = _accuracy(o.cpu().numpy(), i_.cpu().numpy().view(np.uint32), w.planted, exact, w.T, Q)
+            tried[num] = a
+        return tried[num]
+
+    lo, hi = 800, 1000                                # recall falls as T' rises
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if oph_at(mid)["recall"] >= target:
+            lo = mid
+        else:
+            hi = mid
+    best = min((lo, hi), key=lambda n: abs(oph_at(n)["recall"] - target))
+    oph_best, oph_800 = oph_at(best), oph_at(800)
+    t_o = one_per_launch(lambda i: H.query_oph_full(ox, oq[i:i + 1].contiguous(), T=(best, 1000)))
+    ox.free()
+    del oq
+    srv_stats = None
+    if args.serve_rate > 0:
+        srv_stats = _serve(H, W, np, idx, p, w.T, w.eps, args.serve_rate, args.serve_seconds, args.seed + 70,
+                           runs=1)[0]
+    res["identical_recall"] = {
+        "recall_target": target,
+        "hoph_batched": {"pairs_per_s": N * Q / (res["phase_ms"]["query"] * 1e-3), "recall": hacc["recall"],
+                         "precision": hacc["precision"], "T": "4/5"},
+        "hoph_one_query_per_launch": {"ms_per_query": t_h * 1e3, "pairs_per_s": N / t_h},
+        "hoph_served": srv_stats,
+        "oph_full_one_query_per_launch": {"T": f"{best}/1000", "ms_per_query": t_o * 1e3, "pairs_per_s": N / t_o,
+                                          "recall": oph_best["recall"], "precision": oph_best["precision"],
+                                          "recall_at_T_4/5": oph_800["recall"]},
+        "thresholds_tried": {f"{n}/1000": a["recall"] for n, a in sorted(tried.items())},
+        "batched_hoph_over_oph_pairs_per_s": (N * Q / (res["phase_ms"]["query"] * 1e-3)) / (N / t_o),
+    }
+    if srv_stats:
+        res["identical_recall"]["served_hoph_over_oph_queries_per_s"] = srv_stats["served_qps"] / (1.0 / t_o)
+    log(f"bovw: plain OPH at T' = {best}/1000 has recall {oph_best['recall']:.4f} (HOPH {target:.4f})")
+    idx.free()
+    return res
+
+
+def _serve(H, W, np, idx, p, T, eps, rate, seconds, seed, runs=1, extra=None, insert_per_run=0):
+    """Poisson arrivals of single query sets (log-normal sizes, median 800 ids,
+    clipped to [10, 10,000]) at `rate` through the serving loop, after 0.1 s of
+    arrivals at the same rate (every busy slot has tuned and captured its graph
+    before the measurement); optionally inserting sets online meanwhile."""
+    import threading
+    srv = H.Server(idx, p, T=T, eps=eps, slots=4, max_batch_queries=2048, max_batch_ids=1 << 22,
+                   max_batch_results=1 << 20, use_graph=True, tune=True)
+    t_w, wq = W.poisson_arrivals(rate, max(1, int(rate * 0.1)), seed)
+    srv.replay(wq.ids, wq.offsets, t_w - t_w[0])
+    res = []
+    pos = [0]
+    for run in range(runs):
+        n_req = max(1, int(rate * seconds))
+        t_s, sq = W.poisson_arrivals(rate, n_req, seed + 1 + run)
+        srv.reset_stats()
+        stop = threading.Event()
+        th = None
+        if extra is not None and insert_per_run:
+            end = min(extra.n, pos[0] + insert_per_run)
+            piece = max(1, (end - pos[0]) // 8)
+
+            def inserter():
+                while not stop.is_set() and pos[0] < end:
+                    hi = min(end, pos[0] + piece)
+                    o = extra.offsets[pos[0]:hi + 1]
+                    srv.insert(extra.ids[int(o[0]):int(o[-1])], o - o[0])
+                    pos[0] = hi
+                    time.sleep(seconds / 10)
+            th = threading.Thread(target=inserter)
+            th.start()
+        srv.replay(sq.ids, sq.offsets, t_s - t_s[0])
+        stop.set()
+        if th is not None:
+            th.join()
+        st = srv.stats()
+        res.append({"offered_qps": rate, "requests": n_req, "served_qps": st["completed"] / max(st["busy_s"], 1e-9),
+                    "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "max_ms": st["max_ms"],
+                    "mean_batch": st["mean_batch_queries"], "batches": st["batches"], "fallbacks": st["fallbacks"],
+                    "index_sets": len(idx), "inserted_sets_total": st["inserted_sets"]})
+    srv.close()
+    return res
+
+
+def run_c5(args, H, W, np, torch):
+    """The 8,000,000-set serving index (bag-of-visual-words sets, HOPH 1:1, k = 256
+    in groups of 32, T = 4/5): the coarse pass for small query batches read
+    cold from HBM (a 1 GiB read before each pass, its own time subtracted), and
+    served p50/p99 at 50k queries/s over two runs while 5% more sets are
+    inserted online."""
+    dev = torch.device("cuda")
+    N = args.c5_sets
+    n_ins = N // 20
+    a, b = W.hash_coeffs(W.P31, 1, args.seed + 3)
+    p = H.SketchParams(W.LAYOUT_HIER, 256, 32, W.HASH_MODP31, 1 << 20, 1, 1, int(a[0]), int(b[0]))
+    idx = _resident_index(H, p, N, args.seed, capacity=N + n_ins)
+    T, eps = (4, 5), (1, 10000)
+    m = _coarse_model(H, p, T, eps)
+    qsets = W.zipf_sets(64, 1 << 20, 800, 0.75, 10, 10_000, args.seed + 77)
+    qsig = H.sketch_oph(p, torch.from_numpy(qsets.ids.view(np.int32)).to(dev),
+                        torch.from_numpy(qsets.offsets.view(np.int64)).to(dev))
+    flush = torch.zeros(1 << 30, dtype=torch.uint8, device=dev)
+    rows = []
+    for Q in (1, 2, 4, 8, 16, 32, 64):
+        q = qsig[:Q].contiguous()
+        cold = min(H.scan_timing(idx, q, T=T, eps=eps, reps=20, flush=flush) for _ in range(3))
+        warm = min(H.scan_timing(idx, q, T=T, eps=eps, reps=50) for _ in range(3))
+        byts = N * m["plane_bytes_per_set"] + Q * m["record_bytes_per_query"]
+        rows.append({"Q": Q, "cold_ms": cold, "warm_ms": warm, "algorithmic_bytes": byts,
+                     "cold_gbs": byts / (cold * 1e-3) / 1e9, "cold_frac": byts / (cold * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "warm_gbs": byts / (warm * 1e-3) / 1e9,
+                     "valu_frac": Q * N * m["ops_per_pair"] / (cold * 1e-3) / ALU_PEAK_OPS})
+        log(f"serving index: coarse pass Q={Q}: cold {cold * 1e3:.1f} us ({rows[-1]['cold_frac']:.2f} of HBM), "
+            f"warm {warm * 1e3:.1f} us")
+    del flush
+    one = rows[0]
+    small = {"kernel": m["kernel"], "index_sets": N, "k": 256, "k_group": 32, "T": "4/5", "Q": 1,
+             "bound": "hbm", "achieved": one["cold_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": one["cold_frac"], "ms": one["cold_ms"], "algorithmic_bytes": one["algorithmic_bytes"],
+             "bytes_per_set": m["plane_bytes_per_set"], "rows": rows,
+             "largest_q_at_0_6_hbm": max([r["Q"] for r in rows if r["cold_frac"] >= 0.6], default=None)}
+    extra = W.zipf_sets(n_ins, 1 << 20, 600, 0.75, 100, 4000, args.seed + 90)
+    serv = _serve(H, W, np, idx, p, T, eps, args.serve_rate, args.serve_seconds, args.seed + 170, runs=2,
+                  extra=extra, insert_per_run=n_ins // 2) if args.serve_rate > 0 else []
+    for s in serv:
+        log(f"serving index: {s['requests']} requests at {s['offered_qps']:.0f} q/s: p50 {s['p50_ms']:.3f} ms, "
+            f"p99 {s['p99_ms']:.3f} ms")
+    idx.free()
+    return small, serv
+
+
 def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration()
-        return
-    if args.mode != "step":
-        if args.gpus != 1:
-            print("bench.py measures one GPU (--gpus 1)", file=sys.stderr)
-            sys.exit(2)
-        import paper_1805_11254_amd as H
-        H.lib()
-        {"batched": bench_batched, "serve": bench_serve, "comparators": bench_comparators,
-         "selfjoin": bench_selfjoin, "sweeps": bench_sweeps, "scansweep": bench_scansweep}[args.mode](args)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}); "
@@ -731,277 +1407,37 @@ def main():
     import workloads as W
 
     H.lib()
+    if args.mode not in ("step", "c3"):
+        {"batched": bench_batched, "serve": bench_serve, "comparators": bench_comparators,
+         "selfjoin": bench_selfjoin, "sweeps": bench_sweeps, "scansweep": bench_scansweep}[args.mode](args)
+        return
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", 0)))
-    dev = torch.device("cuda")
-
-    t0 = time.perf_counter()
-    w = W.hoph_bovw(n=args.n_sets or 1_000_000, n_q=args.n_queries, seed=args.seed)
-    log(f"generated {w.collection.n} sets / {w.collection.ids.size} ids and {w.queries.n} queries "
-        f"in {time.perf_counter() - t0:.1f} s")
-    ids = torch.from_numpy(w.collection.ids.view(np.int32)).to(dev)
-    offs = torch.from_numpy(w.collection.offsets.view(np.int64)).to(dev)
-    qids = torch.from_numpy(w.queries.ids.view(np.int32)).to(dev)
-    qoffs = torch.from_numpy(w.queries.offsets.view(np.int64)).to(dev)
-    p = H.SketchParams(w.layout, w.k, w.kp, w.hash_kind, w.universe, w.ra, w.rb, w.ha, w.hb)
-    N, Q, k, kp = w.collection.n, w.queries.n, w.k, w.kp
-    nnz = int(w.collection.ids.size)
-    sig = torch.empty((N, k), dtype=torch.int32, device=dev)
-    qsig = torch.empty((Q, k), dtype=torch.int32, device=dev)
-    idx = H.Index(p, sig[:0], capacity=N)
-    stream = torch.cuda.current_stream()
-    cap = [None]
-
-    def step(ev=None):
-        # one pass of the path: every set sketched straight into the resident
-        # index (rows + code planes), the query batch sketched, the HOPH scan
-        e = ev or [None] * 4
-        if e[0] is not None: e[0].record(stream)
-        idx.reset()
-        idx.append_sets(ids, offs)
-        if e[1] is not None: e[1].record(stream)
-        H.sketch_oph(p, qids, qoffs, out=qsig)
-        if e[2] is not None: e[2].record(stream)
-        out = H.query_hoph(idx, qsig, T=w.T, eps=w.eps, capacity=cap[0])
-        if e[3] is not None: e[3].record(stream)
-        return out
-
-    for i in range(args.warmup):
-        out = step()
-        if cap[0] is None:
-            cap[0] = max(1 << 16, 2 * int(out[1].numel()))
-    H.sync()
-    torch.cuda.synchronize()
-    log("warm-up done")
-
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
-    qms, ams = [], []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        out = step(evs[i])
-        qms.append(idx.last_query_ms())
-        ams.append(idx.last_append_ms())
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = wall * 1000.0 / args.steps
-    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step")
-
-    def mean_ms(a, b):
-        return sum(e[a].elapsed_time(e[b]) for e in evs) / len(evs)
-
-    build_ms = mean_ms(0, 1)
-    qsketch_ms = mean_ms(1, 2)
-    query_ms = mean_ms(2, 3)
-    sketch_ms = sum(a[0] for a in ams) / len(ams)       # the sketch-into-index kernel
-    codes_ms = sum(a[1] for a in ams) / len(ams)        # code planes from the rows
-
-    # the two-step build (row-major signatures, then the index store), for comparison
-    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-    two = []
-    for _ in range(3):
-        e0.record(stream)
-        H.sketch_oph(p, ids, offs, out=sig)
-        e1.record(stream)
-        idx.reset()
-        idx.append(sig)
-        e2.record(stream)
-        torch.cuda.synchronize()
-        two.append((e0.elapsed_time(e1), e1.elapsed_time(e2)))
-    two_sketch_ms = sum(t[0] for t in two) / len(two)
-    index_ms = sum(t[1] for t in two) / len(two)
-
-    # the HBM rate a plain device copy reaches here (2 GiB, same stream): the
-    # practical ceiling the sketch's rate is also compared with
-    cbuf = torch.empty(1 << 29, dtype=torch.int32, device=dev)
-    cdst = torch.empty_like(cbuf)
-    cdst.copy_(cbuf)
-    e0.record(stream)
-    for _ in range(5):
-        cdst.copy_(cbuf)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    copy_gbs = 2 * cbuf.numel() * 4 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del cbuf, cdst
-    # the sketch with the sets handed over in pinned host memory: host-to-device
-    # copy of ids and offsets, then the sketch (the resident copies are overwritten
-    # with the same contents)
-    ids_pin = torch.from_numpy(w.collection.ids.view(np.int32)).pin_memory()
-    offs_pin = torch.from_numpy(w.collection.offsets.view(np.int64)).pin_memory()
-    h2d = []
-    for _ in range(2):
-        e0.record(stream)
-        ids.copy_(ids_pin, non_blocking=True)
-        offs.copy_(offs_pin, non_blocking=True)
-        e1.record(stream)
-        H.sketch_oph(p, ids, offs, out=sig)
-        e2.record(stream)
-        torch.cuda.synchronize()
-        h2d.append((e0.elapsed_time(e1), e0.elapsed_time(e2)))
-    h2d_copy_ms, h2d_total_ms = min(h[0] for h in h2d), min(h[1] for h in h2d)
-    del ids_pin, offs_pin
-    coarse_ms = sum(q[0] for q in qms) / len(qms)
-    fine_ms = sum(q[1] for q in qms) / len(qms)
-    sort_ms = sum(q[2] for q in qms) / len(qms)
-
-    # algorithmic work per launch
-    sketch_bytes = nnz * 4 + (N + 1) * 8 + N * k * 4                 # ids, offsets in; signatures out
-    # groups that carry 8-bit codes, in code units of pk whole groups (pk = min(32 // k', L)
-    # for k' <= 16, else 1): at least 4 units, about 128 bins (HOPH) or 256 (GOPH), at most
-    # 24 units (12 for k' > 32), none past the row
-    L_groups = k // kp
-    pk = min(32 // kp, L_groups) if kp <= 16 else 1
-    code_units = min(L_groups // pk, max(4, min(12 if kp > 32 else 24, -(-(256 if w.goph else 128) // (pk * kp)))))
-    code_groups = code_units * pk
-    code_bytes = N * code_groups * kp * 4 + N * code_units * 32 * (1 if kp <= 32 else 2)
-    index_bytes = 2 * N * k * 4 + N * code_units * 32 * (1 if kp <= 32 else 2)   # rows in, index rows + code planes out
-    # coarse depth as the library picks it: the first group alone when it rejects at
-    # least 1/8 of its match counts (no empty bins), else one group past the first
-    # step with a reject cutoff, rounded up to whole code units
-    tabs = H.decision_tables(p, w.T, w.eps)
-    unit0 = tabs["W"][0] * tabs["dmul"][0]
-    m_rej0 = tabs["rej"][0] // unit0 if tabs["rej"][0] >= 0 else -1
-    if m_rej0 >= 0 and 8 * m_rej0 >= kp:
-        depth = 1
-    else:   # one group past the first step with a reject cutoff, in whole code units
-        g1 = next((l + 1 for l, r in enumerate(tabs["rej"]) if r >= 0), None)
-        depth = code_groups if g1 is None else min(code_groups, -(-(g1 + 1) // pk) * pk)
-    # coarse pass on 8-bit bin codes held as 8 bit-planes of 32 bins per word:
-    # per (pair, group) 8 W plane operations, W masks, W popcounts, 1 compare.
-    # The first-group pass compares the first P1 planes of every pair first and
-    # the rest only where a lane might still survive (P1 = 2 when the threshold
-    # on differing bins is at most half the bins, 4 when at most three
-    # quarters): the work every pair gets is then P1 W plane operations, W
-    # masks, W popcounts and 1 compare.
-    W_planes = 1 if kp <= 32 else 2
-    ops_per_pair_group = 10 * W_planes + 1
-    plane_split = 0
-    if depth == 1 and w.T is not None:
-        dthr = kp + 1 if m_rej0 < 0 else kp - m_rej0
-        plane_split = 2 if 2 * dthr <= kp else (4 if 4 * dthr <= 3 * kp else 0)
-        if plane_split:
-            ops_per_pair_group = W_planes * (plane_split + 2) + 1
-    coarse_ops = Q * N * depth * ops_per_pair_group
-    coarse_bins = Q * N * kp * depth
-    coarse_bytes = N * 32 * W_planes * depth + Q * (32 * W_planes + 16) * depth
-    traffic = load_traffic()
-    kernels = {
-        "sketch_into_index": {"ms": sketch_ms, "bound": "hbm", "achieved": sketch_bytes / (sketch_ms * 1e-3) / 1e9,
-                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": traffic.get("sketch_kernel"),
-                              "algorithmic_bytes": sketch_bytes, "sets_per_s": N / (sketch_ms * 1e-3)},
-        "code_planes": {"ms": codes_ms, "bound": "hbm", "achieved": code_bytes / (codes_ms * 1e-3) / 1e9,
-                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": traffic.get("row_codes_vec_kernel"),
-                        "algorithmic_bytes": code_bytes},
-        "two_step_sketch_oph": {"ms": two_sketch_ms, "bound": "hbm",
-                                "achieved": sketch_bytes / (two_sketch_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                                "unit": "GB/s", "traffic": traffic.get("sketch_kernel"),
-                                "algorithmic_bytes": sketch_bytes},
-        "two_step_index_store": {"ms": index_ms, "bound": "hbm", "achieved": index_bytes / (index_ms * 1e-3) / 1e9,
-                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                 "traffic": (traffic["__amd_rocclr_copyBuffer"] + traffic["row_codes_vec_kernel"]
-                                             if "__amd_rocclr_copyBuffer" in traffic and "row_codes_vec_kernel" in traffic
-                                             else None),
-                                 "algorithmic_bytes": index_bytes},
-        "scan_coarse": {"ms": coarse_ms, "bound": "alu", "achieved": coarse_ops / (coarse_ms * 1e-3) / 1e12,
-                        "peak": ALU_PEAK_OPS / 1e12, "unit": "Tops/s (32-bit VALU lane-ops)",
-                        "ops_per_pair_group": ops_per_pair_group, "first_phase_planes": plane_split,
-                        "bin_compares_per_s": coarse_bins / (coarse_ms * 1e-3),
-                        "traffic": traffic.get("scan_codes_fast_kernel"), "algorithmic_bytes": coarse_bytes,
-                        "hbm_gbs": coarse_bytes / (coarse_ms * 1e-3) / 1e9, "depth": depth},
-        "scan_fine": {"ms": fine_ms},
-        "sort_and_csr": {"ms": sort_ms},
-        "query_sketch": {"ms": qsketch_ms},
-    }
-    for v in kernels.values():
-        if "achieved" in v:
-            v["frac"] = v["achieved"] / v["peak"]
-    dom_name = max(("sketch_into_index", "code_planes", "scan_coarse"), key=lambda n: kernels[n]["ms"])
-    dom = kernels[dom_name]
-    roofline = {"kernel": dom_name, "bound": dom["bound"], "achieved": dom["achieved"], "peak": dom["peak"],
-                "unit": dom["unit"], "frac": dom["frac"], "traffic": dom["traffic"],
-                "algorithmic_bytes": dom["algorithmic_bytes"]}
-
-    # accuracy against the exact Jaccard similarity (outside the timed region)
-    offs_h = out[0].cpu().numpy()
-    ids_h = out[1].cpu().numpy().view(np.uint32)
-    T = w.T[0] / w.T[1]
-    truth = {(q, s) for (q, s, J) in w.planted if J >= T}
-    got = set()
-    for q in range(Q):
-        for s in ids_h[offs_h[q]:offs_h[q + 1]].tolist():
-            got.add((q, s))
-    tp = 0
-    for (q, s) in got:
-        a = np.unique(w.queries.set(q))
-        b = np.unique(w.collection.set(s))
-        inter = np.intersect1d(a, b, assume_unique=True).size
-        if inter / (a.size + b.size - inter) >= T:
-            tp += 1
-    recall = len(truth & got) / max(1, len(truth))
-    precision = tp / max(1, len(got))
-
-    rec = {
-        "metric": "sets sketched/s + query x index signature compares/s (HBM %), served p99 ms",
-        "value": N * Q / (ms_per_step * 1e-3),
-        "unit": "query x index pairs decided/s (whole step: sketch + index + query sketch + HOPH scan)",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic",
-        "config": {"workload": "hoph_1to1_bovw", "n_sets": N, "n_queries": Q, "nnz": nnz, "universe": w.universe,
-                   "k": k, "k_group": kp, "groups": k // kp, "ratio": "1:1", "hash": "(a x + b) mod (2^31 - 1)",
-                   "T": "4/5", "eps": "1/10000", "empty_policy": "joint", "parallelism": "single GPU"},
-        "sets_sketched_per_s": N / (sketch_ms * 1e-3),
-        "sets_sketched_per_s_with_h2d": N / (h2d_total_ms * 1e-3),
-        "h2d_gbs": (nnz * 4 + (N + 1) * 8) / (h2d_copy_ms * 1e-3) / 1e9,
-        "copy_ceiling_gbs": copy_gbs,
-        "sketch_frac_of_copy": kernels["sketch_into_index"]["achieved"] / copy_gbs,
-        "scan_pairs_per_s": N * Q / (query_ms * 1e-3),
-        "scan_hbm_frac": kernels["scan_coarse"]["hbm_gbs"] / HBM_PEAK_GBS,
-        "served_p99_ms": None,
-        "phase_ms": {"build_index": build_ms, "sketch_into_index": sketch_ms, "code_planes": codes_ms,
-                     "query_sketch": qsketch_ms, "query": query_ms, "coarse": coarse_ms, "fine": fine_ms,
-                     "sort_csr": sort_ms, "two_step_sketch": two_sketch_ms, "two_step_index_store": index_ms},
-        "kernels": kernels,
-        "roofline": roofline,
-        "accepted_pairs": len(got),
-        "recall_planted": recall,
-        "precision_exact_jaccard": precision,
-    }
-    if args.serve_rate > 0:
-        # serving on the same resident index, outside the timed region: Poisson
-        # arrivals of single query sets (log-normal sizes, median 800 ids) at a
-        # fixed rate, after a warm-up replay (tuning, graph capture); latency per
-        # request from arrival to its result list
-        log(f"serving at {args.serve_rate:.0f} q/s for {args.serve_seconds} s")
-        srv = H.Server(idx, p, T=w.T, eps=w.eps, slots=4, max_batch_queries=2048, max_batch_ids=1 << 22,
-                       max_batch_results=1 << 20, use_graph=True, tune=True)
-        # warm-up at the measured rate, so that every slot has run (tuned and
-        # captured its graph on) its first batch before the measurement
-        t_w, wq = W.poisson_arrivals(args.serve_rate, max(1, int(args.serve_rate * 0.1)), args.seed + 70)
-        srv.replay(wq.ids, wq.offsets, t_w - t_w[0])
-        n_req = max(1, int(args.serve_rate * args.serve_seconds))
-        t_s, sq = W.poisson_arrivals(args.serve_rate, n_req, args.seed + 71)
-        srv.reset_stats()
-        srv.replay(sq.ids, sq.offsets, t_s - t_s[0])
-        st = srv.stats()
-        srv.close()
-        rec["served_p99_ms"] = st["p99_ms"]
-        rec["serving"] = {"offered_qps": args.serve_rate, "requests": n_req,
-                          "served_qps": st["completed"] / max(st["busy_s"], 1e-9), "p50_ms": st["p50_ms"],
-                          "p99_ms": st["p99_ms"], "mean_batch": st["mean_batch_queries"],
-                          "index_sets": len(idx)}
-    idx.free()
+    rec, st = run_c3(args, H, W, np, torch)
+    if args.mode == "step":
+        rec["comparators"] = c3_comparators(args, H, W, np, torch, st)
+        log("shingles: comparators done")
+    for ix in st["idx"].values():
+        ix.free()
+    w3 = st["w"]
+    pairs_per_step = st["pairs_per_step"]
+    del st
+    torch.cuda.empty_cache()
+    if args.mode == "step":
+        rec["c2"] = run_c2(args, H, W, np, torch)
+        torch.cuda.empty_cache()
+        small, serv = run_c5(args, H, W, np, torch)
+        rec["kernels"]["scan_small_batch"] = small
+        rec["serving"] = {"index": {"workload": "hoph_1to1_bovw_serving", "n_sets": args.c5_sets,
+                                    "inserted_online": args.c5_sets // 20, "k": 256, "k_group": 32, "T": "4/5"},
+                          "runs": serv}
+        rec["served_p99_ms"] = max(s["p99_ms"] for s in serv) if serv else None
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        log("timing the oracle on a CPU sample")
-        rec["cpu_baseline"] = cpu_baseline(w, N, Q, args.cpu_sample_sets, args.cpu_sample_queries)
+        log("timing the oracle on CPU samples")
+        rec["cpu_baseline"] = cpu_baseline_c3(w3, w3.collection.n, w3.queries.n, pairs_per_step)
     else:
         rec["cpu_baseline"] = None
     print(json.dumps(rec), flush=True)

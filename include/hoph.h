@@ -321,6 +321,10 @@ typedef struct {
     uint32_t tuned;               /* 1 if the shapes came from timing (or the tuning cache)  */
     uint32_t fallbacks;           /* batches redone on the host-synchronised path            */
     float tune_ms;                /* the chosen shapes' time on the tuning batch             */
+    uint32_t fallback_causes;     /* why, over all batches: 1 survivors past the plan's buffer,
+                                     2 accepted pairs past its key buffer, 4 a query with more
+                                     ids than the per-query sort takes                       */
+    uint32_t reserved;
 } hoph_plan_info;
 
 /* hoph_plan_create -- allocate a plan (device buffers sized by cfg) for index

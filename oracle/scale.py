@@ -90,6 +90,8 @@ def sketch(ids: np.ndarray, offsets: np.ndarray, *, hash_kind: int, universe: in
     n_sets = len(offsets) - 1
     if which is not None:
         which = np.ascontiguousarray(which, dtype=np.uint64)
+        if len(which) and int(which.max()) >= n_sets:
+            raise OracleError(f"set index {int(which.max())} past the {n_sets} sets")
     n_out = n_sets if which is None else len(which)
     if perm is not None:
         perm = np.ascontiguousarray(perm, dtype=np.uint32)
@@ -165,6 +167,8 @@ def minwise_sketch(ids, offsets, *, hash_kind, universe, ha: np.ndarray, hb: np.
     n_sets = len(offsets) - 1
     if which is not None:
         which = np.ascontiguousarray(which, dtype=np.uint64)
+        if len(which) and int(which.max()) >= n_sets:
+            raise OracleError(f"set index {int(which.max())} past the {n_sets} sets")
     n_out = n_sets if which is None else len(which)
     out = np.empty((n_out, k), dtype=np.uint64)
     rc = lib().orc_minwise_sketch(hash_kind, universe, k, _ptr(ha), _ptr(hb), _ptr(ids),

@@ -64,7 +64,7 @@ class PlanConfigC(C.Structure):
 class PlanInfoC(C.Structure):
     _fields_ = [("q_per_wave", u32), ("coarse_waves_per_cu", u32), ("sketch_chunk", u32),
                 ("sketch_waves_per_cu", u32), ("depth", u32), ("graph", u32), ("tuned", u32), ("fallbacks", u32),
-                ("tune_ms", C.c_float)]
+                ("tune_ms", C.c_float), ("fallback_causes", u32), ("reserved", u32)]
 
 
 class ServerConfigC(C.Structure):
@@ -526,7 +526,7 @@ class Plan:
     def info(self) -> dict:
         i = PlanInfoC()
         _check(lib().hoph_plan_get_info(self._h, C.byref(i)))
-        return {f: getattr(i, f) for f, _ in PlanInfoC._fields_}
+        return {f: getattr(i, f) for f, _ in PlanInfoC._fields_ if f != "reserved"}
 
     def free(self):
         if self._h:

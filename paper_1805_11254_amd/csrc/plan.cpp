@@ -102,7 +102,14 @@ struct hoph_plan {
     uint64_t last_nsets = 0;      // index size the last batch was dispatched against
     bool pending = false;
     uint32_t fallbacks = 0;
+    uint32_t fallback_causes = 0;  // hoph_plan_info.fallback_causes
     std::mutex mu;
+
+    // the causes of a batch that must be redone, from its device counters
+    void note_fallback(uint64_t surv, uint64_t acc, uint64_t flags) {
+        ++fallbacks;
+        fallback_causes |= (surv > surv_cap ? 1u : 0u) | (acc > keys_cap ? 2u : 0u) | ((flags & 3ull) ? 4u : 0u);
+    }
 
     void release() {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -420,7 +427,7 @@ hoph_status hoph_plan_results(hoph_plan *p, const uint64_t **d_offsets, const ui
     const bool exact = surv <= p->surv_cap && acc <= p->keys_cap && (flags & 3ull) == 0;
     if (!exact) {
         // redo on the host-synchronised path with the batch's signatures
-        ++p->fallbacks;
+        p->note_fallback(surv, acc, flags);
         hoph_results r{p->out_offsets, p->out_ids, p->cfg.max_results, 0};
         hoph_status s = run_query(p->idx, p->q_sigs, p->last_nq, &p->qp, &r, hip_stream, p->kind, false,
                                   p->last_nsets);
@@ -452,6 +459,8 @@ hoph_status hoph_plan_get_info(const hoph_plan *p, hoph_plan_info *info) {
     info->graph = p->exec ? 1u : 0u;
     info->tuned = p->tuned ? 1u : 0u;
     info->fallbacks = p->fallbacks;
+    info->fallback_causes = p->fallback_causes;
+    info->reserved = 0;
     info->tune_ms = p->tune_ms;
     return HOPH_OK;
 }
@@ -488,7 +497,7 @@ hoph_status plan_results_to_host(hoph_plan *p, uint64_t *h_offsets, uint32_t *h_
     uint64_t n = total, have = pre;
     if (!(surv <= p->surv_cap && acc <= p->keys_cap && (flags & 3ull) == 0)) {
         // redo on the host-synchronised path with the batch's signatures
-        ++p->fallbacks;
+        p->note_fallback(surv, acc, flags);
         hoph_results r{p->out_offsets, p->out_ids, p->cfg.max_results, 0};
         hoph_status s = run_query(p->idx, p->q_sigs, n_q, &p->qp, &r, st, p->kind, false, p->last_nsets);
         if (s) return s;

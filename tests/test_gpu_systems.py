@@ -179,7 +179,7 @@ def test_plan_query_with_many_results_falls_back_exactly():
     plan = H.Plan(idx, p, T=w.T, eps=w.eps, max_queries=4, max_query_ids=10_000, max_results=1 << 16)
     got = _plan_path(plan, q)
     assert got == (want_o, want_i)
-    assert plan.info()["fallbacks"] == 1
+    assert plan.info()["fallbacks"] == 1 and plan.info()["fallback_causes"] == 4   # the per-query sort's limit
     plan.free()
     idx.free()
 
