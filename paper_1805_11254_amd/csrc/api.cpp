@@ -221,23 +221,26 @@ hoph_status run_query_impl(const hoph_index *cidx, Workspace *ws_in, const uint3
     a.depth = depth;
     a.tri = self_join;
     a.counters = ws.counters;
+    a.codes = use_codes ? idx->codes : nullptr;
+    a.cg = idx->cg;
     if (kind != QueryKind::OPH_FULL && n_q && n_sets) {
         st = ws.grow_qmasks((uint64_t)n_q * lay.L);
         if (st) return st;
         CodeThr thr{};
+        LinTab lin;
+        bool with_lin = false;
         if (use_codes) {
             st = ws.grow_qcodes(((uint64_t)n_q + 1) * idx->cg * code_rec_words(lay.kp));  // + a padding record
             if (st) return st;
             std::memcpy(thr.dthr, tab.dthr0, sizeof(thr.dthr));
+            with_lin = lin_records(a, tab, &lin);
         }
         HOPH_HIP(launch_query_masks(d_qsigs, n_q, nullptr, lay.k, lay.kp, lay.L, ws.qmasks,
-                                    use_codes ? ws.qcodes : nullptr, idx->cg, &thr, s),
+                                    use_codes ? ws.qcodes : nullptr, idx->cg, &thr, s, with_lin ? &lin : nullptr),
                  "query mask launch");
     }
     a.qmasks = ws.qmasks;
-    a.codes = use_codes ? idx->codes : nullptr;
     a.qcodes = ws.qcodes;
-    a.cg = idx->cg;
 
     // one pass over queries [q0, q1) (coarse, then per-survivor), events ev[0..2]
     auto pass = [&](uint32_t q0, uint32_t q1) -> hoph_status {
@@ -829,11 +832,16 @@ hoph_status hoph_selftest_bins(const hoph_sketch_params *params, const uint32_t 
     std::vector<RegionEntry> reg(lay.n_regions + 1);
     for (uint32_t r = 0; r <= lay.n_regions; ++r)
         reg[r] = RegionEntry{lay.reg_start[r], r < lay.n_regions ? lay.reg_magic[r] : 0};
-    std::vector<uint32_t> s32(starts.begin(), starts.end()), rs(lay.reg_start.begin(), lay.reg_start.end());
+    // the device's 32-bit narrow view (see narrow_value): starts clamped to 2^32 - 1
+    const bool narrow = p.hash != HOPH_HASH_TABLE && narrow_view_ok(lay);
+    std::vector<uint32_t> s32(starts.size()), rs(lay.reg_start.size());
+    for (size_t i = 0; i < starts.size(); ++i) s32[i] = narrow_start(starts[i]);
+    for (size_t i = 0; i < rs.size(); ++i) rs[i] = narrow_start(lay.reg_start[i]);
     std::vector<uint32_t> cells(2 * kLogCells), regs(2 * lay.n_regions);
     if (lay.log_ok) {
         for (uint32_t c = 0; c < kLogCells; ++c)
-            log_cell_entry(c, (uint32_t)lay.R, lay.reg_start.data(), lay.n_regions, cells[2 * c], cells[2 * c + 1]);
+            log_cell_entry(c, narrow_r1(lay.R) + 1u, lay.reg_start.data(), lay.n_regions, cells[2 * c],
+                           cells[2 * c + 1]);
         for (uint32_t r = 0; r < lay.n_regions; ++r) {
             regs[2 * r] = (uint32_t)lay.reg_start[r];
             regs[2 * r + 1] = lay.reg_mag32[r];
@@ -857,16 +865,25 @@ hoph_status hoph_selftest_bins(const hoph_sketch_params *params, const uint32_t 
             locate_est(v, lay.est_mul, lay.est_shift, starts.data(), be, se);
             if (be != b || se != start) return fail(HOPH_E_UNSUPPORTED, "bin estimate and region lookup disagree");
         }
-        if (lay.R < 0xFFFFFFFFull) {
-            // the narrow lookup the device uses when every value and start is 32-bit
+        if (narrow) {
+            // the narrow lookups the device uses: the bin of the clamped value and the
+            // offset of the value itself in 32-bit arithmetic
+            const uint32_t v32 = narrow_value(v);
             uint32_t bn, sn;
-            locate_narrow((uint32_t)v, lut.data(), lay.lut_shift, rs.data(), lay.reg_mag32.data(), lay.n_regions,
+            locate_narrow(v32, lut.data(), lay.lut_shift, rs.data(), lay.reg_mag32.data(), lay.n_regions,
                           lay.nb, s32.data(), bn, sn);
-            if (bn != b || sn != start) return fail(HOPH_E_UNSUPPORTED, "narrow and wide bin lookups disagree");
+            if (bn != b || (uint32_t)v - sn != (uint32_t)(v - start))
+                return fail(HOPH_E_UNSUPPORTED, "narrow and wide bin lookups disagree");
+            if (lay.est_ok) {
+                const uint32_t e = bin_estimate(v32, lay.est_mul, lay.est_shift);
+                const uint32_t be = e + (v32 >= s32[e + 1] ? 1u : 0u);
+                if (be != b) return fail(HOPH_E_UNSUPPORTED, "narrow bin estimate and region lookup disagree");
+            }
             if (lay.log_ok) {
-                locate_log((uint32_t)v, (uint32_t)(lay.R - 1), reinterpret_cast<const uint32_t(*)[2]>(cells.data()),
+                locate_log(v32, narrow_r1(lay.R), reinterpret_cast<const uint32_t(*)[2]>(cells.data()),
                            reinterpret_cast<const uint32_t(*)[2]>(regs.data()), lay.nb, s32.data(), bn, sn);
-                if (bn != b || sn != start) return fail(HOPH_E_UNSUPPORTED, "log-cell and region lookups disagree");
+                if (bn != b || (uint32_t)v - sn != (uint32_t)(v - start))
+                    return fail(HOPH_E_UNSUPPORTED, "log-cell and region lookups disagree");
             }
             if (lay.pow2_ok) {
                 uint32_t bp, op;

@@ -140,8 +140,32 @@ __host__ __device__ inline uint32_t bin_code(uint32_t v) {
 __host__ __device__ inline uint32_t code_plane_words(uint32_t kp) { return kp > 32 ? 2u : 1u; }
 __host__ __device__ inline uint32_t code_words(uint32_t kp) { return kCodeBits * code_plane_words(kp); }
 // A query's record per code group: the planes, then {non-empty mask low word,
-// high word, first-group threshold on differing non-empty bins, empty count}.
-__host__ __device__ inline uint32_t code_rec_words(uint32_t kp) { return code_words(kp) + 4u; }
+// high word, first-group threshold on differing non-empty bins, empty count},
+// then the group's words of the linear bound {c, z, y, 0} (LinTab).
+__host__ __device__ inline uint32_t code_rec_words(uint32_t kp) { return code_words(kp) + 8u; }
+
+// The multi-group code pass (HOPH or GOPH over 2-4 groups of k' <= 32 bins,
+// JOINT or LITERAL) bounds each group's rate from above using the query's
+// own empty count e_g only: the codes of the query-non-empty bins that differ
+// (dn_g) are real differences, and the set's empty bins there differ too, so
+// m_g <= (k' - e_g) - dn_g, and the joint empty count is at most e_g, so
+// (JOINT) the state term W_g m_g lambda / (k' - ej) is at most
+// C_g ((k' - e_g) - dn_g) with C_g = W_g lambda / (k' - e_g) (LITERAL: C_g = W_g).
+// A step's test on the exact state then becomes a test on sum_g C_g dn_g,
+// linear in the counts: reject when it reaches Z_s = sum_g C_g (k' - e_g) -
+// rej_s, keep ("maybe": an accept cutoff may be reached) when it is at most
+// Y_s = sum_g C_g (k' - e_g) - acc_s.  Per query the record of group g holds
+// c_g = floor(C_g / 2^shift), z_g = ceil(Z_g / 2^shift) (UINT32_MAX: no reject
+// cutoff) and y_g = floor(Y_g / 2^shift) (-1: no accept cutoff reachable); the
+// rounding keeps both tests on the safe side (fewer rejects, more keeps).
+constexpr uint32_t kLinMaxSteps = 4;
+struct LinTab {
+    int64_t W[kLinMaxSteps], acc[kLinMaxSteps], rej[kLinMaxSteps];
+    int64_t dmul[HOPH_MAX_KGROUP + 1];
+    int64_t lambda;
+    uint32_t steps;                 // groups with linear words (0: none)
+    uint32_t shift, policy, kp;
+};
 
 // First-group reject thresholds on codes by the query's empty count (ScanTab::dthr0).
 struct CodeThr {
@@ -185,19 +209,33 @@ __host__ __device__ inline uint64_t psi_p31(uint64_t x, uint64_t a, uint64_t b) 
     return t < s ? t : s;
 }
 
-// (a x + b) mod (2^32 + 15) for x < 2^32, a, b < 2^32 + 15, using 2^32 = -15 (mod p).
+// (a x + b) mod p, p = 2^32 + 15, for x < 2^32 and a, b < p.  With a = a1 2^32 + a0,
+// b = b1 2^32 + b0 (a1, b1 in {0, 1}) and 2^32 = -15 (mod p):
+//   a x + b = (a0 x + b0) + (a1 x + b1) 2^32, and a0 x + b0 = h 2^32 + l (one
+//   32 x 32 -> 64 multiply-add, below 2^64), so a x + b = l - 15 t (mod p) with
+//   t = h + a1 x + b1 < 2^33.
+// z = l + 32 p - 15 t lies in (0, 2^38) (15 t < 32 p); with z = z1 2^32 + z0
+// (z1 < 64), r = z0 + p - 15 z1 = z (mod p) lies in [p - 945, 2^32 + p), and one
+// conditional subtraction of p finishes.
 __host__ __device__ inline uint64_t psi_p32(uint64_t x, uint64_t a, uint64_t b) {
-    uint64_t lo = a * x;
-    uint64_t hi = mulhi64(a, x);                  // <= 1
-    lo += b;
-    hi += (lo < b);                               // <= 2
-    // w = hi 2^64 + l1 2^32 + l0 = 225 hi - 15 l1 + l0 (mod p)
-    uint64_t l0 = lo & 0xFFFFFFFFull, l1 = lo >> 32;
-    uint64_t z = l0 + 225ull * hi + 16ull * kP32 - 15ull * l1;   // in (0, 2^37)
-    uint64_t z0 = z & 0xFFFFFFFFull, z1 = z >> 32;               // z1 < 32
-    uint64_t r = z0 + kP32 - 15ull * z1;                         // in [p - 480, 2^32 + p)
+    const uint64_t w = (uint64_t)(uint32_t)a * (uint32_t)x + (uint32_t)b;
+    const uint64_t t = (w >> 32) + ((a >> 32) ? x : 0ull) + (b >> 32);
+    const uint64_t z = (w & 0xFFFFFFFFull) + 32ull * kP32 - 15ull * t;
+    const uint64_t r = (z & 0xFFFFFFFFull) + kP32 - 15ull * (z >> 32);
     return r >= kP32 ? r - kP32 : r;
 }
+
+// The narrow (32-bit) view of a permuted range that may reach past 2^32 - 1
+// (R = 2^32 + 15): values at or above kNarrowTop are looked up as kNarrowTop,
+// which lies in the last bin as they do (the host checks that the last bin
+// starts below it), and every start above it, including the end sentinel R,
+// reads as 2^32 - 1, so a value never reaches the end sentinel.  The offset
+// from the bin start, below 2^32, is exact in 32-bit arithmetic.
+constexpr uint32_t kNarrowTop = 0xFFFFFFFEu;
+__host__ __device__ inline uint32_t narrow_value(uint64_t v) { return v > kNarrowTop ? kNarrowTop : (uint32_t)v; }
+__host__ __device__ inline uint32_t narrow_start(uint64_t s) { return s > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)s; }
+// R - 1 of the narrow view: the value the log-domain cells count down from.
+__host__ __device__ inline uint32_t narrow_r1(uint64_t R) { return (uint32_t)(R - 1 > kNarrowTop ? kNarrowTop : R - 1); }
 
 // One region of the permuted range: its first value and the reciprocal
 // M = floor(2^64 nb / z) of its size z (nb bins per region).
@@ -345,6 +383,7 @@ __host__ __device__ inline void locate_est(uint64_t v, uint32_t mul, uint32_t sh
 // Host runtime (host_tables.cpp)
 // ---------------------------------------------------------------------------
 hoph_status build_layout(const hoph_sketch_params &p, LayoutInfo &out, std::string &err);
+bool narrow_view_ok(const LayoutInfo &L);
 void fill_sketch_desc(const hoph_sketch_params &p, const LayoutInfo &lay, SketchDesc &d);
 void host_lut(const LayoutInfo &lay, std::vector<uint8_t> &lut);
 void host_starts(const LayoutInfo &lay, std::vector<uint64_t> &starts);
@@ -437,9 +476,15 @@ struct ScanLaunch {
 };
 // Empty-bin masks of every (query, group) and, when qcodes is not null, the code
 // records (code_rec_words each) of each query's first cg groups; thr is then required.
+// lin (nullable): the linear-bound words of the first lin->steps groups.
 hipError_t launch_query_masks(const uint32_t *qsigs, uint32_t n_q, const uint64_t *desc, uint32_t k, uint32_t kp,
                               uint32_t L, uint64_t *out, uint32_t *qcodes, uint32_t cg, const CodeThr *thr,
-                              hipStream_t st);
+                              hipStream_t st, const LinTab *lin = nullptr);
+// Whether query records for this index and these parameters carry the words of
+// the linear bound (the multi-group code pass may run at some depth); if so
+// and lin is not null, its LinTab for launch_query_masks.  a needs codes, tri,
+// kp, L and cg set.
+bool lin_records(const ScanLaunch &a, const ScanTab &tab, LinTab *lin);
 hipError_t launch_scan_coarse(const ScanLaunch &a, const ScanTab &tab, hipStream_t st);
 // Tiles of 64 sets one wavefront of the coarse pass holds for this launch.
 uint32_t coarse_tiles_per_wave(const ScanLaunch &a, const ScanTab &tab);

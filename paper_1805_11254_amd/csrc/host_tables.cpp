@@ -26,6 +26,20 @@ static uint64_t range_of(const hoph_sketch_params &p) {
 void choose_estimate(LayoutInfo &lay);
 void choose_pow2(LayoutInfo &lay);
 
+// Whether the 32-bit narrow view of the permuted range (narrow_value) is exact
+// for this layout: the range ends at or below 2^32 - 1, or (2^32 + 15) every
+// region and the last bin start below kNarrowTop, so every value it clamps lies
+// in the last bin.
+bool narrow_view_ok(const LayoutInfo &L) {
+    if (L.R <= 0xFFFFFFFFull) return true;
+    std::vector<uint64_t> starts;
+    host_starts(L, starts);
+    if (starts.size() < 2 || starts[L.k - 1] > kNarrowTop) return false;
+    for (uint32_t r = 0; r < L.n_regions; ++r)
+        if (L.reg_start[r] >= kNarrowTop) return false;
+    return true;
+}
+
 hoph_status build_layout(const hoph_sketch_params &p, LayoutInfo &out, std::string &err) {
     if (p.layout != HOPH_LAYOUT_OPH && p.layout != HOPH_LAYOUT_HIER) { err = "unknown layout"; return HOPH_E_INVAL; }
     if (p.k_group == 0 || p.k_group > HOPH_MAX_KGROUP) { err = "k_group must be in [1, 64]"; return HOPH_E_INVAL; }
@@ -96,16 +110,23 @@ hoph_status build_layout(const hoph_sketch_params &p, LayoutInfo &out, std::stri
     L.lut_shift = sh;
     L.lut_size = (uint32_t)((R - 1) >> sh) + 1;
     choose_estimate(L);
-    // log-domain cells: a narrow range with regions, no cell holding two boundaries
+    // log-domain cells: a narrow range with regions, no cell holding two
+    // boundaries; over 2^32 + 15 the narrow view (narrow_value) holds when every
+    // region and the last bin start below kNarrowTop
     L.log_ok = 0;
-    if (L.n_regions > 1 && R < 0xFFFFFFFFull) {
+    if (L.n_regions > 1 && narrow_view_ok(L)) {
         bool ok = true;
-        const uint32_t R1 = (uint32_t)(R - 1);
+        const uint32_t R1 = narrow_r1(R);
         for (uint32_t r = 1; r + 1 < L.n_regions && ok; ++r)
             ok = log_cell((uint32_t)(L.reg_start[r] - 1), R1) != log_cell((uint32_t)L.reg_start[r + 1], R1);
         L.log_ok = ok ? 1u : 0u;
     }
     choose_pow2(L);
+    if (p.hash == HOPH_HASH_MODP32P15 && !narrow_view_ok(L)) {
+        // the sketch looks bins up in 32 bits, which needs the last bin to start below 2^32 - 2
+        err = "a bin at the top of the range is narrower than the 32-bit lookup needs (layout too deep)";
+        return HOPH_E_UNSUPPORTED;
+    }
     out = std::move(L);
     return HOPH_OK;
 }

@@ -23,6 +23,9 @@
 // across the lanes of a load (one lane per bin) and two to four loads per
 // step; counts come from ballots and popcounts, the decision is wave-uniform,
 // and the wavefront leaves at the first deciding group.
+#include <cmath>
+#include <cstring>
+
 #include "hoph_internal.h"
 
 namespace hoph {
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(kThreads) void query_masks_kernel(const uint32_t *_
                                                               const uint64_t *__restrict__ desc, uint32_t k,
                                                               uint32_t kp, uint32_t L, uint64_t *__restrict__ out,
                                                               uint32_t *__restrict__ qcodes, uint32_t cg,
-                                                              const CodeThr thr) {
+                                                              const CodeThr thr, const LinTab lin) {
     const uint32_t n_q = desc ? (uint32_t)desc[0] : n_q_arg;
     const uint64_t n = (uint64_t)n_q * L;
     const uint32_t W = code_plane_words(kp), PW = code_words(kp), RW = code_rec_words(kp);
@@ -205,6 +208,39 @@ __global__ __launch_bounds__(kThreads) void query_masks_kernel(const uint32_t *_
             dst[PW + 1] = (uint32_t)(nqm >> 32);
             dst[PW + 2] = (uint32_t)thr.dthr[e];
             dst[PW + 3] = e;
+            uint32_t lc = 0, lz = 0xFFFFFFFFu, ly = 0xFFFFFFFFu;
+            if (g < lin.steps) {
+                // linear bound of step g (see LinTab): sums over this query's groups 0..g
+                int64_t sum_ck = 0, cg_here = 0;
+                for (uint32_t h = 0; h <= g; ++h) {
+                    uint32_t eh = 0;
+                    const uint32_t *wh = qsigs + q * k + h * kp;
+                    for (uint32_t i = 0; i < kp; ++i) eh += wh[i] == HOPH_EMPTY ? 1u : 0u;
+                    int64_t c, ck;
+                    if (lin.policy == HOPH_EMPTY_LITERAL) {
+                        c = eh < kp ? lin.W[h] : 0;
+                        ck = lin.W[h] * (int64_t)(kp - eh);
+                    } else {                      // JOINT: C (k' - e) = W lambda
+                        c = eh < kp ? lin.W[h] * lin.dmul[eh] : 0;
+                        ck = lin.W[h] * lin.lambda;
+                    }
+                    sum_ck += ck;
+                    if (h == g) cg_here = c;
+                }
+                const int64_t one = (int64_t)1 << lin.shift;
+                lc = (uint32_t)(cg_here >> lin.shift);
+                if (lin.rej[g] >= 0) {
+                    const int64_t Z = sum_ck - lin.rej[g];
+                    const int64_t zc = Z <= 0 ? 0 : (Z + one - 1) >> lin.shift;
+                    lz = zc >= (int64_t)0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)zc;
+                }
+                const int64_t Y = sum_ck - lin.acc[g];
+                if (Y >= 0) ly = (uint32_t)min<int64_t>(Y >> lin.shift, 0x7FFFFFFFll);
+            }
+            dst[PW + 4] = lc;
+            dst[PW + 5] = lz;
+            dst[PW + 6] = ly;
+            dst[PW + 7] = 0;
         }
     }
 }
@@ -278,7 +314,7 @@ __device__ __forceinline__ void code_unit_steps(uint32_t u, const uint32_t *P, c
                                                 uint32_t pk, uint32_t cd, uint64_t kpmask, uint32_t kp,
                                                 uint32_t policy, const int64_t *s_dmul, const ScanTab &tab,
                                                 int64_t &S, bool &undecided, bool &maybe) {
-    constexpr int RW = (int)kCodeBits * W + 4;
+    constexpr int RW = (int)kCodeBits * W + 8;           // record stride (code_rec_words)
     const uint32_t g0 = PACK ? u * pk : u;
     uint32_t d[W];
 #pragma unroll
@@ -314,7 +350,7 @@ __global__ __launch_bounds__(kThreads) void scan_codes_kernel(const uint32_t *__
                                                              unsigned long long *__restrict__ counters,
                                                              const uint64_t *__restrict__ desc,
                                                              const CoarseArgs a, const ScanTab tab) {
-    constexpr int PW = (int)kCodeBits * W, RW = PW + 4;
+    constexpr int PW = (int)kCodeBits * W, RW = PW + 8;     // RW: record stride (code_rec_words)
     __shared__ int64_t s_dmul[HOPH_MAX_KGROUP + 1];
     for (uint32_t i = threadIdx.x; i <= tab.kp; i += kThreads) s_dmul[i] = tab.dmul[i];
     __syncthreads();
@@ -404,7 +440,7 @@ __global__ __launch_bounds__(64) void scan_codes_deep_kernel(const uint32_t *__r
                                                            unsigned long long *__restrict__ counters,
                                                            const uint64_t *__restrict__ desc, const CoarseArgs a,
                                                            const ScanTab tab, uint32_t cu) {
-    constexpr int PW = (int)kCodeBits * W, RW = PW + 4, PV = PW / 4;
+    constexpr int PW = (int)kCodeBits * W, RW = PW + 8, PV = PW / 4;     // RW: record stride
     extern __shared__ uint4 s_pl[];      // units >= R: [unit - R][PV][lane] planes, then [unit - R][W][lane] masks
     __shared__ int64_t s_dmul[HOPH_MAX_KGROUP + 1];
     __shared__ Survivor s_surv[kSurvBatchDeep];
@@ -533,7 +569,7 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_
                                                                   unsigned long long *__restrict__ counters,
                                                                   const uint64_t *__restrict__ desc,
                                                                   const CoarseArgs a) {
-    constexpr int PW = (int)kCodeBits * W, RW = PW + 4;
+    constexpr int PW = (int)kCodeBits * W, RW = PW + 4, RS = PW + 8;   // words read per record, record stride
     __shared__ Survivor s_surv[kWaves][kSurvBatch];
     const uint32_t lane = threadIdx.x & 63;
     SurvBatch<kSurvBatch> sb{s_surv[wave_id_in_block()], 0};
@@ -546,7 +582,7 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_
     const uint64_t n_items = ngroups * nchunks;
     const uint64_t wstride = (uint64_t)gridDim.x * kWaves;
     const uint64_t ctiles = a.capacity / 64;
-    const uint64_t rstride = (uint64_t)a.cg * RW;
+    const uint64_t rstride = (uint64_t)a.cg * RS;
     for (uint64_t item = (uint64_t)blockIdx.x * kWaves + wave_id_in_block(); item < n_items; item += wstride) {
         const uint64_t tg = item % ngroups;
         const uint32_t chunk = (uint32_t)(item / ngroups);
@@ -629,6 +665,138 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_
             HOPH_CODE_QUERY_T(rb, q + 1)
         }
 #undef HOPH_CODE_QUERY_T
+    }
+    sb.flush(surv, a.surv_cap, counters + 0, lane);
+}
+
+// Multi-group code pass with the linear bound of LinTab: D groups (one per
+// code unit, k' <= 32 bins, one plane word), TPW tiles of 64 indexed sets per
+// wavefront sharing each query's scalar work (its record: planes, non-empty
+// mask and the words c, z, y of every group), one set per lane.  The state of a
+// pair after step s is st_s = sum_{g <= s} c_g dn_g, dn_g the query-non-empty
+// bins of group g whose codes differ; st_s <= y_s keeps the pair ("maybe": an
+// accept cutoff may be reached), else st_s >= z_s rejects it.
+// Phase 1 (P1 > 0) compares the first P1 planes of groups 0..R, R the first
+// step with a reject cutoff: a bin that differs there differs in the full
+// code, so the partial state never exceeds the full one.  A lane whose partial
+// state is rejected at step R and kept at no step up to R is rejected by the
+// full test too (the steps before R cannot reject), so when no lane of the
+// wavefront is kept the query is done with these tiles.  Phase 2 continues the
+// plane chains and takes the steps in order; pairs still undecided after D
+// groups are kept.  Kept pairs go on to the fine pass from the first group.
+template <int D, int TPW, int P1>
+__global__ __launch_bounds__(kThreads) void scan_codes_lin_kernel(const uint32_t *__restrict__ codes,
+                                                                 const uint32_t *__restrict__ qcodes,
+                                                                 Survivor *__restrict__ surv,
+                                                                 unsigned long long *__restrict__ counters,
+                                                                 const uint64_t *__restrict__ desc,
+                                                                 const CoarseArgs a, const uint32_t R) {
+    constexpr int PW = (int)kCodeBits, RS = PW + 8;       // planes per unit, record stride
+    __shared__ Survivor s_surv[kWaves][kSurvBatch];
+    const uint32_t lane = threadIdx.x & 63;
+    SurvBatch<kSurvBatch> sb{s_surv[wave_id_in_block()], 0};
+    const uint64_t n_sets = desc ? desc[1] : a.n_sets;
+    const uint32_t q_lo = desc ? 0u : a.q0, q_hi = desc ? (uint32_t)desc[0] : a.q1;
+    const uint32_t qpw = chunk_queries(a, desc, q_hi - q_lo);
+    const uint64_t ntiles = (n_sets + 63) / 64;
+    const uint64_t ngroups = (ntiles + TPW - 1) / TPW;
+    const uint32_t nchunks = (q_hi - q_lo + qpw - 1) / qpw;
+    const uint64_t n_items = ngroups * nchunks;
+    const uint64_t wstride = (uint64_t)gridDim.x * kWaves;
+    const uint64_t ctiles = a.capacity / 64;
+    const uint64_t rstride = (uint64_t)a.cg * RS;
+    for (uint64_t item = (uint64_t)blockIdx.x * kWaves + wave_id_in_block(); item < n_items; item += wstride) {
+        const uint64_t tg = item % ngroups;
+        const uint32_t chunk = (uint32_t)(item / ngroups);
+        const uint32_t qa = q_lo + chunk * qpw;
+        const uint32_t qb = min(q_hi, qa + qpw);
+        uint32_t P[TPW][D][PW];
+        uint64_t vmask[TPW];
+        uint32_t sid[TPW];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+            const uint64_t tile = tg * TPW + t;
+            const uint64_t s = tile * 64 + lane;
+            vmask[t] = __builtin_amdgcn_ballot_w64(s < n_sets);
+            sid[t] = (uint32_t)s;
+            if (tile < ntiles) {             // wave-uniform; tiles below ntiles exist (ntiles <= ctiles)
+#pragma unroll
+                for (int u = 0; u < D; ++u) {
+                    const uint4 *src = reinterpret_cast<const uint4 *>(codes + (((uint64_t)u * ctiles + tile) * 64 + lane) * PW);
+#pragma unroll
+                    for (int j = 0; j < PW / 4; ++j) {
+                        const uint4 v = src[j];
+                        P[t][u][4 * j + 0] = v.x;
+                        P[t][u][4 * j + 1] = v.y;
+                        P[t][u][4 * j + 2] = v.z;
+                        P[t][u][4 * j + 3] = v.w;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < D; ++u)
+#pragma unroll
+                    for (int j = 0; j < PW; ++j) P[t][u][j] = 0;
+            }
+        }
+        for (uint32_t q = qa; q < qb; ++q) {
+            const uint32_t *rec = qcodes + (uint64_t)q * rstride;
+            uint32_t nq[D], c[D], z[D];
+            int32_t y[D];
+#pragma unroll
+            for (int g = 0; g < D; ++g) {
+                nq[g] = rec[g * RS + PW];
+                c[g] = rec[g * RS + PW + 4];
+                z[g] = rec[g * RS + PW + 5];
+                y[g] = (int32_t)rec[g * RS + PW + 6];
+            }
+            const uint32_t zR = rec[R * RS + PW + 5];        // the reject cutoff of step R
+            uint32_t dd[TPW][D];
+            bool open = true;
+            if constexpr (P1 > 0) {
+                uint64_t keep = 0;
+#pragma unroll
+                for (int t = 0; t < TPW; ++t) {
+                    uint32_t st = 0;
+                    bool mb = false;
+#pragma unroll
+                    for (int g = 0; g < D; ++g) {
+                        if ((uint32_t)g <= R) {
+                            dd[t][g] = code_diff_part<1, 0, P1>(0u, P[t][g], rec + g * RS, 0);
+                            st += __umul24(c[g], (uint32_t)__popc(dd[t][g] & nq[g]));
+                            mb = mb || (int32_t)st <= y[g];
+                        }
+                    }
+                    keep |= __builtin_amdgcn_ballot_w64(mb || st < zR) & vmask[t];
+                }
+                open = keep != 0;
+            }
+            if (open) {
+#pragma unroll
+                for (int t = 0; t < TPW; ++t) {
+                    uint32_t st = 0;
+                    bool und = true, mb = false;
+#pragma unroll
+                    for (int g = 0; g < D; ++g) {
+                        if ((uint32_t)g > R && !__any(und)) break;
+                        const uint32_t d = (P1 > 0 && (uint32_t)g <= R)
+                                               ? code_diff_part<1, P1, (int)kCodeBits>(dd[t][g], P[t][g], rec + g * RS, 0)
+                                               : code_diff<1>(P[t][g], rec + g * RS, 0);
+                        st += __umul24(c[g], (uint32_t)__popc(d & nq[g]));
+                        if (und) {
+                            if ((int32_t)st <= y[g]) {
+                                mb = true;
+                                und = false;
+                            } else if (st >= z[g]) {
+                                und = false;
+                            }
+                        }
+                    }
+                    const uint64_t bal = __builtin_amdgcn_ballot_w64(mb || und) & vmask[t];
+                    sb.push(bal, q, sid[t], surv, a.surv_cap, counters + 0, lane);
+                }
+            }
+        }
     }
     sb.flush(surv, a.surv_cap, counters + 0, lane);
 }
@@ -1078,8 +1246,73 @@ void oph_kp(const ScanLaunch &l, const CoarseArgs &a, hoph_ratio T, hipStream_t 
 
 }  // namespace
 
+// Whether the index and query parameters allow linear-bound records (see
+// LinTab): code planes, one plane word (k' <= 32), one group per code unit,
+// JOINT or LITERAL, not the self-join; then lin (if not null) gets the table
+// for the first min(cg, kLinMaxSteps) groups.
+bool lin_records(const ScanLaunch &l, const ScanTab &tab, LinTab *lin) {
+    if (!l.codes || l.tri || l.kp > 32 || code_pack(l.kp, l.L) != 1) return false;
+    if (tab.policy != HOPH_EMPTY_JOINT && tab.policy != HOPH_EMPTY_LITERAL) return false;
+    if (lin) {
+        std::memset(lin, 0, sizeof(*lin));
+        lin->steps = std::min<uint32_t>(l.cg, kLinMaxSteps);
+        lin->policy = tab.policy;
+        lin->kp = l.kp;
+        lin->lambda = tab.lambda;
+        for (uint32_t e = 0; e <= l.kp; ++e) lin->dmul[e] = tab.dmul[e];
+        // the largest C_g over every empty count: W_g lambda (JOINT, k' - e = 1) or W_g
+        uint64_t cmax = 1;
+        for (uint32_t g = 0; g < lin->steps; ++g) {
+            lin->W[g] = tab.W[g];
+            lin->acc[g] = tab.acc[g];
+            lin->rej[g] = tab.rej[g];
+            const uint64_t cg = (uint64_t)tab.W[g] * (tab.policy == HOPH_EMPTY_LITERAL ? 1u : (uint64_t)tab.lambda);
+            cmax = std::max(cmax, cg);
+        }
+        // c_g below 2^24: one 24-bit multiply per group and a sum below 2^31 (4 groups x 32 bins)
+        uint32_t bits = 0;
+        while (bits < 64 && (cmax >> bits) != 0) ++bits;
+        lin->shift = bits > 24 ? bits - 24 : 0;
+    }
+    return true;
+}
+
+// The first step (0-based) with a reject cutoff, or L.
+static uint32_t first_reject_step(const ScanTab &tab) {
+    uint32_t r = 0;
+    while (r < tab.L && tab.rej[r] < 0) ++r;
+    return r;
+}
+
+static bool lin_code_pass(const ScanLaunch &l, const ScanTab &tab, LinTab *lin) {
+    if (!lin_records(l, tab, lin)) return false;
+    const uint32_t du = l.depth;                     // one group per unit
+    return du >= 2 && du <= kLinMaxSteps && du <= l.cg && first_reject_step(tab) < du;
+}
+
+// Tiles per wavefront of the linear-bound pass: 4 for two groups, else 2
+// (the planes of D groups of TPW tiles stay in VGPRs).
+static constexpr int lin_tiles(int D) { return D == 2 ? 4 : 2; }
+
+// Planes of phase 1 of the linear-bound pass: a background pair matches a
+// bin's first p planes with probability 2^-p, so phase 1 settles it when that
+// fraction of matches, summed over the weighted groups 0..R, stays well below
+// the reject cutoff of step R (a third of the largest reject fraction tau);
+// 0: one phase over all 8 planes.
+static int lin_plane_split(const ScanTab &tab, uint32_t kp, uint32_t R) {
+    if (R >= tab.L || tab.rej[R] < 0) return 0;
+    const double unit = tab.policy == HOPH_EMPTY_LITERAL ? 1.0 : (double)tab.dmul[0];
+    double full = 0;
+    for (uint32_t g = 0; g <= R; ++g) full += (double)tab.W[g] * unit * kp;
+    const double tau = (double)tab.rej[R] / full;
+    for (int p = 2; p <= 4; ++p)
+        if (std::ldexp(1.0, -p) * 3.0 <= tau) return p;
+    return 0;
+}
+
 uint32_t coarse_tiles_per_wave(const ScanLaunch &l, const ScanTab &tab) {
     const uint32_t policy = tab.policy;
+    if (lin_code_pass(l, tab, nullptr)) return (uint32_t)lin_tiles((int)l.depth);
     if (!(l.codes && l.depth == 1 && policy != HOPH_EMPTY_EITHER)) return 1u;
     return (uint32_t)fast_tiles((int)code_plane_words(l.kp), plane_split(tab, l.kp));
 }
@@ -1091,16 +1324,19 @@ uint32_t max_depth_for_kpad(uint32_t kpad) {
 
 hipError_t launch_query_masks(const uint32_t *qsigs, uint32_t n_q, const uint64_t *desc, uint32_t k, uint32_t kp,
                               uint32_t L, uint64_t *out, uint32_t *qcodes, uint32_t cg, const CodeThr *thr,
-                              hipStream_t st) {
+                              hipStream_t st, const LinTab *lin) {
     if (qcodes && !thr) return hipErrorInvalidValue;
     CodeThr t{};
     if (thr) t = *thr;
+    LinTab lt;
+    std::memset(&lt, 0, sizeof(lt));
+    if (lin && qcodes) lt = *lin;
     const uint64_t n = (uint64_t)n_q * L;         // n_q: the batch size, or its upper bound with desc
     if (n == 0) return hipSuccess;
     uint64_t blocks = (n + kThreads - 1) / kThreads;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(query_masks_kernel, dim3((uint32_t)blocks), dim3(kThreads), 0, st, qsigs, n_q, desc, k, kp, L,
-                       out, qcodes, cg, t);
+                       out, qcodes, cg, t, lt);
     return hipGetLastError();
 }
 
@@ -1118,6 +1354,30 @@ hipError_t launch_scan_coarse(const ScanLaunch &l, const ScanTab &tab, hipStream
         blocks = waves_to_blocks((ntiles + tpw - 1) / tpw * nchunks);
     }
     const CoarseArgs a = coarse_args(l, tab.policy);
+    if (l.codes && lin_code_pass(l, tab, nullptr)) {
+        // two to four groups with the linear bound (the query records carry its words)
+        const uint32_t R = first_reject_step(tab);
+        const int p1 = lin_plane_split(tab, l.kp, R);
+        auto *cnt = reinterpret_cast<unsigned long long *>(l.counters);
+#define HOPH_LIN(DD, P1)                                                                                      \
+    hipLaunchKernelGGL((scan_codes_lin_kernel<DD, lin_tiles(DD), P1>), dim3(blocks), dim3(kThreads), 0, st,   \
+                       l.codes, l.qcodes, l.surv, cnt, l.desc, a, R)
+#define HOPH_LIN_P(DD)                                 \
+    do {                                               \
+        if (p1 == 4) HOPH_LIN(DD, 4);                  \
+        else if (p1 == 3) HOPH_LIN(DD, 3);             \
+        else if (p1 == 2) HOPH_LIN(DD, 2);             \
+        else HOPH_LIN(DD, 0);                          \
+    } while (0)
+        switch (l.depth) {
+        case 2: HOPH_LIN_P(2); break;
+        case 3: HOPH_LIN_P(3); break;
+        default: HOPH_LIN_P(4); break;
+        }
+#undef HOPH_LIN_P
+#undef HOPH_LIN
+        return hipGetLastError();
+    }
     if (l.codes) {
         if (l.depth == 0 || l.depth > l.cg) return hipErrorInvalidValue;
         const uint32_t W = code_plane_words(l.kp), pk = a.pk, du = (l.depth + pk - 1) / pk;   // code units walked

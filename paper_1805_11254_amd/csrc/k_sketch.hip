@@ -49,10 +49,11 @@ __device__ __forceinline__ uint64_t permute(uint64_t x, const SketchDesc &d) {
 
 constexpr int LOC_EST = 0, LOC_REGION = 1, LOC_LOG = 2, LOC_POW2 = 3;
 
-// The (a x + b) mod (2^31 - 1) hash keeps every value, bin start and region
-// start in 32 bits (NARROW); the other hashes keep 64-bit values and starts.
+// The (a x + b) mod (2^31 - 1) and (a x + b) mod (2^32 + 15) hashes look bins
+// up in 32 bits (NARROW: values clamped to kNarrowTop, starts to 2^32 - 1, see
+// narrow_value); the table hash keeps 64-bit values and starts.
 template <uint32_t HASH>
-constexpr bool kNarrow = HASH == HOPH_HASH_MODP31;
+constexpr bool kNarrow = HASH != HOPH_HASH_TABLE;
 template <uint32_t HASH>
 using StartT = typename std::conditional<kNarrow<HASH>, uint32_t, uint64_t>::type;
 
@@ -112,9 +113,14 @@ __device__ Tables<HASH> build_tables(const SketchDesc &d, unsigned char *smem, c
     for (uint32_t b = tid; b < k; b += blockDim.x) {
         const uint32_t r = b / nb, i = b - r * nb;
         const uint64_t z = d.reg_start[r + 1] - d.reg_start[r];
-        s_start[b] = (S)(d.reg_start[r] + ((uint64_t)i * z + nb - 1) / nb);
+        const uint64_t s = d.reg_start[r] + ((uint64_t)i * z + nb - 1) / nb;
+        if constexpr (kNarrow<HASH>) s_start[b] = narrow_start(s);
+        else s_start[b] = (S)s;
     }
-    if (tid == 0) s_start[k] = (S)d.R;
+    if (tid == 0) {
+        if constexpr (kNarrow<HASH>) s_start[k] = narrow_start(d.R);
+        else s_start[k] = (S)d.R;
+    }
     t.start = s_start;
     if constexpr (LOC == LOC_LOG) {
         uint32_t(*rg)[2] = reinterpret_cast<uint32_t(*)[2]>(smem + L.reg);
@@ -124,14 +130,14 @@ __device__ Tables<HASH> build_tables(const SketchDesc &d, unsigned char *smem, c
             rg[r][1] = d.reg_mag32[r];
         }
         for (uint32_t c = tid; c < kLogCells; c += blockDim.x)
-            log_cell_entry(c, (uint32_t)d.R, d.reg_start, nr, cl[c][0], cl[c][1]);
+            log_cell_entry(c, narrow_r1(d.R) + 1u, d.reg_start, nr, cl[c][0], cl[c][1]);
         t.regs = rg;
         t.cells = cl;
     }
     if constexpr (LOC == LOC_REGION) {
         if constexpr (kNarrow<HASH>) {
             uint32_t *rs = reinterpret_cast<uint32_t *>(smem + L.reg), *rm = rs + nr + 1;
-            for (uint32_t r = tid; r <= nr; r += blockDim.x) rs[r] = (uint32_t)d.reg_start[r];
+            for (uint32_t r = tid; r <= nr; r += blockDim.x) rs[r] = narrow_start(d.reg_start[r]);
             for (uint32_t r = tid; r < nr; r += blockDim.x) rm[r] = d.reg_mag32[r];
             t.rstart = rs;
             t.rmag = rm;
@@ -160,7 +166,7 @@ template <uint32_t HASH, int LOC>
 __device__ __forceinline__ void bin_of(uint64_t v, const SketchDesc &d, const Tables<HASH> &t, uint32_t &b,
                                        uint32_t &off) {
     if constexpr (kNarrow<HASH> && LOC == LOC_POW2) {
-        const uint32_t v32 = (uint32_t)v;
+        const uint32_t v32 = (uint32_t)v;              // the power-of-two lookup needs R <= 2^32 - 1
         uint32_t u = (uint32_t)(d.R - 1) - v32;
         u = u > 1u ? u : 1u;
         const uint4 e = t.pow2[clz32(u)];          // few distinct entries: mostly broadcast reads
@@ -168,20 +174,20 @@ __device__ __forceinline__ void bin_of(uint64_t v, const SketchDesc &d, const Ta
         b = e.z + (dl >> e.y);
         off = dl & e.w;
     } else if constexpr (kNarrow<HASH>) {
-        const uint32_t v32 = (uint32_t)v;
+        const uint32_t v32 = narrow_value(v);
         uint32_t start;
         if constexpr (LOC == LOC_EST) {
-            const uint32_t e = bin_estimate(v32, d.est_mul, 0);
+            const uint32_t e = bin_estimate(v32, d.est_mul, d.est_shift);
             const uint32_t s0 = t.start[e], s1 = t.start[e + 1];
             const bool up = v32 >= s1;
             b = e + (up ? 1u : 0u);
             start = up ? s1 : s0;
         } else if constexpr (LOC == LOC_LOG) {
-            locate_log(v32, (uint32_t)(d.R - 1), t.cells, t.regs, d.nb, t.start, b, start);
+            locate_log(v32, narrow_r1(d.R), t.cells, t.regs, d.nb, t.start, b, start);
         } else {
             locate_narrow(v32, t.lut, d.lut_shift, t.rstart, t.rmag, d.n_regions, d.nb, t.start, b, start);
         }
-        off = v32 - start;
+        off = (uint32_t)v - start;                     // below 2^32 (the bin's width)
     } else {
         uint64_t start;
         if constexpr (LOC == LOC_EST) locate_est(v, d.est_mul, d.est_shift, t.start, b, start);
@@ -599,7 +605,10 @@ hipError_t launch_sketch_chunked(const SketchDesc &d, const uint32_t *ids, const
                : est     ? HOPH_SKC(HOPH_HASH_MODP31, LOC_EST)
                : d.log_ok ? HOPH_SKC(HOPH_HASH_MODP31, LOC_LOG)
                           : HOPH_SKC(HOPH_HASH_MODP31, LOC_REGION);
-    default: return est ? HOPH_SKC(HOPH_HASH_MODP32P15, LOC_EST) : HOPH_SKC(HOPH_HASH_MODP32P15, LOC_REGION);
+    default:
+        return est        ? HOPH_SKC(HOPH_HASH_MODP32P15, LOC_EST)
+               : d.log_ok ? HOPH_SKC(HOPH_HASH_MODP32P15, LOC_LOG)
+                          : HOPH_SKC(HOPH_HASH_MODP32P15, LOC_REGION);
     }
 #undef HOPH_SKC
 }
@@ -618,7 +627,10 @@ hipError_t launch_sketch(const SketchDesc &d, const uint32_t *ids, const uint64_
                : est     ? HOPH_SK(HOPH_HASH_MODP31, LOC_EST)
                : d.log_ok ? HOPH_SK(HOPH_HASH_MODP31, LOC_LOG)
                           : HOPH_SK(HOPH_HASH_MODP31, LOC_REGION);
-    default: return est ? HOPH_SK(HOPH_HASH_MODP32P15, LOC_EST) : HOPH_SK(HOPH_HASH_MODP32P15, LOC_REGION);
+    default:
+        return est        ? HOPH_SK(HOPH_HASH_MODP32P15, LOC_EST)
+               : d.log_ok ? HOPH_SK(HOPH_HASH_MODP32P15, LOC_LOG)
+                          : HOPH_SK(HOPH_HASH_MODP32P15, LOC_REGION);
     }
 #undef HOPH_SK
 }

@@ -174,8 +174,10 @@ hoph_status enqueue_sketch(hoph_plan *p, const PlanShape &s, hipStream_t st) {
     const LayoutInfo &lay = p->idx->lay;
     CodeThr thr{};
     std::memcpy(thr.dthr, p->tab.dthr0, sizeof(thr.dthr));
+    LinTab lin;
+    const bool with_lin = p->codes && lin_records(scan_launch(p, s), p->tab, &lin);
     HOPH_HIP(launch_query_masks(p->q_sigs, p->cfg.max_queries, p->desc, lay.k, lay.kp, lay.L, p->q_masks,
-                                p->codes ? p->q_codes : nullptr, p->idx->cg, &thr, st),
+                                p->codes ? p->q_codes : nullptr, p->idx->cg, &thr, st, with_lin ? &lin : nullptr),
              "query mask launch");
     return HOPH_OK;
 }

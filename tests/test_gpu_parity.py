@@ -126,6 +126,73 @@ def test_results_do_not_depend_on_coarse_depth(name):
     idx.free()
 
 
+@pytest.mark.parametrize("ra,rb", [(1, 2), (2, 1), (1, 1)])
+def test_multi_group_code_pass_matches_oracle(ra, rb):
+    """The coarse pass over 2-4 groups of 32 bins on codes (its state bounded
+    per group from the query's own empty count) at the library's depth and at
+    depths 2, 3 and 4, for JOINT and LITERAL, at thresholds whose first reject
+    cutoff comes at the first or a later group; collections of large sets and of
+    sets of 20-60 ids (most bins empty), with planted near-duplicates."""
+    _print_case(f"multi-group code pass {ra}:{rb}")
+    big = W.hoph_shingles(n=6_007, n_q=24, seed=21 + ra, ra=ra, rb=rb)
+    small = W.hoph_shingles(n=3_001, n_q=16, seed=31 + ra, ra=ra, rb=rb)
+    small.collection = W.csr_from_lists([big.collection.set(i)[:20 + i % 41] for i in range(3_001)])
+    small.queries = W.csr_from_lists([small.collection.set(i * 7) for i in range(16)])
+    for w in (big, small):
+        p = params_of(w)
+        sig = gpu_sketch(w, w.collection, p)
+        qsig = gpu_sketch(w, w.queries, p)
+        idx = H.Index(p, sig)
+        sh, qh = to_u32(sig), to_u32(qsig)
+        found = 0
+        for T in ((1, 2), (3, 5), (7, 10)):
+            for policy in (H.EMPTY_JOINT, H.EMPTY_LITERAL):
+                oo, oi = oracle_query(w, sh, qh, T, (1, 10_000), policy)
+                found += len(oi)
+                for depth in (0, 2, 3, 4):
+                    go, gi = gpu_query("hoph", idx, qsig, T, (1, 10_000), policy, coarse_depth=depth)
+                    assert go.tolist() == oo.tolist(), (T, policy, depth)
+                    assert gi.tolist() == oi.tolist(), (T, policy, depth)
+        assert found > 0
+        idx.free()
+
+
+def test_modp32_top_of_range_signatures():
+    """Sets whose ids hash to the top of the (a x + b) mod (2^32 + 15) range
+    (2^32 - 3 .. 2^32 + 14, the values the sketch's 32-bit view clamps): every
+    signature against the oracle's, for plain OPH and the 1:1, 1:2 and 2:1
+    hierarchies, in the host path and the chunked sketch of a plan."""
+    _print_case("modp32 top of range")
+    P = tiny.P32P15
+    a, bb = 2_654_435_761, 97
+    inv = pow(a, -1, P)
+    top = [((v - bb) * inv) % P for v in range((1 << 32) - 3, P)]
+    top = [x for x in top if x < (1 << 32)]
+    assert any((a * x + bb) % P >= (1 << 32) for x in top)
+    rng = np.random.default_rng(33)
+    sets = []
+    for i in range(300):
+        s = rng.integers(0, 1 << 32, size=int(rng.integers(1, 400)), dtype=np.uint64)
+        s = np.concatenate([s, np.array(top[: 1 + i % len(top)], dtype=np.uint64)]) if i % 3 else s
+        sets.append(np.unique(s).astype(np.uint32))
+    sets.append(np.array(top[:1], dtype=np.uint32))                  # a set of one top id
+    coll = W.csr_from_lists(sets)
+    for layout, ra, rb in [(W.LAYOUT_OPH, 1, 1), (W.LAYOUT_HIER, 1, 1), (W.LAYOUT_HIER, 1, 2), (W.LAYOUT_HIER, 2, 1)]:
+        w = W.Workload("top", coll, coll, 1 << 32, W.HASH_MODP32P15, layout, 256, 32, ra=ra, rb=rb, ha=a, hb=bb)
+        p = params_of(w)
+        osig = oracle_sketch(w, coll)
+        assert (to_u32(gpu_sketch(w, coll, p)) == osig).all(), (layout, ra, rb)
+        if layout == W.LAYOUT_HIER:
+            idx = H.Index(p, gpu_sketch(w, coll, p))
+            plan = H.Plan(idx, p, max_queries=512, max_query_ids=200_000, max_results=1 << 16, use_graph=False)
+            ids, offs = dev_csr(coll)
+            plan.run(ids, offs)
+            plan.results()
+            assert (to_u32(plan.query_sigs(256)) == osig).all(), (ra, rb)
+            plan.free()
+            idx.free()
+
+
 # The library's 8-bit bin code (a multiplicative mix scaled into 255 values,
 # EMPTY apart), restated here only to build adversarial inputs: bins whose
 # values differ from a query's but whose codes are equal.

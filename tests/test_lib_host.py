@@ -113,6 +113,40 @@ def test_modp32_hash_edges():
             assert (gb, go) == (lay.bin_of(v), v - lay.starts[lay.bin_of(v)])
 
 
+def _top_of_range_ids(a, b, P, count=40):
+    """Ids whose (a x + b) mod P lands in the top values of the range: the last
+    values below 2^32 and every value from 2^32 to P - 1."""
+    inv = pow(a, -1, P)
+    out = []
+    for v in list(range((1 << 32) - 3, P)):
+        x = ((v - b) * inv) % P
+        if x < (1 << 32):
+            out.append(x)
+    return out[:count]
+
+
+def test_modp32_top_of_range_every_layout():
+    """(a x + b) mod (2^32 + 15) values at the top of the range (2^32 - 3 ..
+    2^32 + 14), which the sketch looks up through its 32-bit view of the range:
+    bins and offsets of every lookup the device uses against the oracle's
+    layout, for plain OPH and the 1:1, 1:2 and 2:1 hierarchies, k = 256 and 512."""
+    P = tiny.P32P15
+    rng = np.random.default_rng(32)
+    for a, bb in [(12345, 6789), (P - 1, P - 1), (2 ** 32 + 3, 7), (int(rng.integers(1, P)), int(rng.integers(0, P)))]:
+        xs = _top_of_range_ids(a, bb, P)
+        assert any((a * x + bb) % P >= (1 << 32) for x in xs)
+        xs += rng.integers(0, 1 << 32, size=200, dtype=np.uint64).tolist()
+        ids = np.array(xs, dtype=np.uint32)
+        for layout, k, ra, rb in [(H.LAYOUT_OPH, 256, 1, 1), (H.LAYOUT_HIER, 256, 1, 1), (H.LAYOUT_HIER, 256, 1, 2),
+                                  (H.LAYOUT_HIER, 256, 2, 1), (H.LAYOUT_HIER, 512, 1, 2)]:
+            p = H.SketchParams(layout, k, 32, H.HASH_MODP32P15, 1 << 32, ra, rb, hash_a=a, hash_b=bb)
+            b, o = H.selftest_bins(p, ids)
+            lay = _tiny_layout(p)
+            for x, gb, go in zip(ids.tolist(), b.tolist(), o.tolist()):
+                v = (a * x + bb) % P
+                assert (gb, go) == (lay.bin_of(v), v - lay.starts[lay.bin_of(v)]), (a, bb, layout, ra, rb, x)
+
+
 def test_modp31_hash_edges():
     """(a x + b) mod (2^31 - 1) at the extremes of a, b and x (universe = P): the
     largest w = a x + b, and values whose low 31 bits and high part are both large."""
