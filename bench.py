@@ -777,19 +777,27 @@ def _code_units(k, kp, goph):
 
 
 def _coarse_model(H, p, T, eps, goph=False):
-    """How the library runs the coarse pass for these parameters, and the
-    algorithmic work of one launch per (query, set) pair.
+    """How the library runs the coarse pass for these parameters (JOINT, a
+    query path), and the algorithmic work of one launch per (query, set) pair.
 
     Depth: the first group alone when it rejects at least 1/8 of its match counts
     (no empty bins); else one group past the first step with a reject cutoff,
-    in whole code units.  Work: the first-group pass compares P1 planes of every
-    pair first (P1 W plane operations, W masks, W popcounts, one compare;
-    P1 = 2 when the threshold on differing bins is at most half the bins, 4 when
-    at most three quarters, else all 8 planes, 10 W + 1); a deeper pass compares
-    at least the first code unit of every pair (10 W + 1) and updates the
-    weighted state of its group (an int64 multiply-add and two compares, 6 more).
-    Bytes: each set's planes of the units walked (32 W per unit) per launch."""
+    in whole code units.  Kernel and minimum work per pair:
+    - one group: the first-group pass compares P1 planes of every pair first
+      (P1 W plane operations, W masks, W popcounts, one compare; P1 = 2 when the
+      threshold on differing bins is at most half the bins, 4 when at most three
+      quarters), else all 8 planes (10 W + 1);
+    - two to four groups of 17-32 bins: the linear-bound pass compares P1 planes
+      of groups 1..R+1 (R+1 the first step with a reject cutoff; P1 the smallest
+      of 2, 3, 4 planes whose chance match rate is at most a third of that
+      step's reject fraction) with a plane chain, a mask, a popcount and a
+      24-bit multiply-add per group and two compares, else all 8 planes of
+      every group (11 per group and two compares);
+    - otherwise at least the first code unit of every pair (10 W + 1) and its
+      weighted state update (an int64 multiply-add and two compares, 6 more).
+    Bytes: each set's planes of the units the kernel loads (32 W per unit) per launch."""
     k, kp = p.k, p.k_group
+    L = k // kp
     pk, cu, cg = _code_units(k, kp, goph)
     tabs = H.decision_tables(p, T, eps)
     unit0 = tabs["W"][0] * tabs["dmul"][0]
@@ -804,13 +812,21 @@ def _coarse_model(H, p, T, eps, goph=False):
     else:
         g1 = next((l + 1 for l, r in enumerate(tabs["rej"]) if r >= 0), None)
         depth = cg if g1 is None else min(cg, -(-(g1 + 1) // pk) * pk)
-        split = 0
-        ops = 10 * Wp + 1 + 6
-        kernel = "scan_codes_kernel" if -(-depth // pk) <= 4 else "scan_codes_deep_kernel"
+        R = (g1 - 1) if g1 is not None else L
+        if kp <= 32 and pk == 1 and 2 <= depth <= 4 and R < depth:
+            kernel = "scan_codes_lin_kernel"
+            full = sum(tabs["W"][g] * tabs["dmul"][0] * kp for g in range(R + 1))
+            tau = tabs["rej"][R] / full
+            split = next((s for s in (2, 3, 4) if 3.0 * 2.0 ** -s <= tau), 0)
+            ops = (R + 1) * (split + 3) + 2 if split else depth * 11 + 2
+        else:
+            split = 0
+            ops = 10 * Wp + 1 + 6
+            kernel = "scan_codes_kernel" if -(-depth // pk) <= 4 else "scan_codes_deep_kernel"
     units = -(-depth // pk)
     return {"kernel": kernel, "depth": depth, "code_units_walked": units, "ops_per_pair": ops,
             "first_phase_planes": split, "plane_bytes_per_set": 32 * Wp * units,
-            "record_bytes_per_query": (8 * Wp + 4) * 4 * units}
+            "record_bytes_per_query": (8 * Wp + 8) * 4 * units}
 
 
 def _jaccard_cache(qcoll, coll):

@@ -801,6 +801,135 @@ __global__ __launch_bounds__(kThreads) void scan_codes_lin_kernel(const uint32_t
     sb.flush(surv, a.surv_cap, counters + 0, lane);
 }
 
+// The linear-bound pass when a first phase of P1 planes decides the
+// background pairs (see scan_codes_lin_kernel): only the first P1 planes of
+// groups 0..G1-1 (G1 = R + 1) stay in VGPRs, so TPW tiles of 64 sets share each
+// query's scalar work; a tile with a lane that phase 1 keeps reads its full
+// planes of all D groups again (from L2 or HBM) and takes the steps in order.
+// A lane that phase 1 does not keep is rejected by the full test (see
+// scan_codes_lin_kernel), so running the full test on every lane of such a tile
+// gives the same pairs.
+template <int G1, int D, int TPW, int P1>
+__global__ __launch_bounds__(kThreads) void scan_codes_lin1_kernel(const uint32_t *__restrict__ codes,
+                                                                  const uint32_t *__restrict__ qcodes,
+                                                                  Survivor *__restrict__ surv,
+                                                                  unsigned long long *__restrict__ counters,
+                                                                  const uint64_t *__restrict__ desc,
+                                                                  const CoarseArgs a) {
+    constexpr int PW = (int)kCodeBits, RS = PW + 8, R = G1 - 1;
+    static_assert(P1 >= 1 && P1 <= 4 && G1 >= 1 && G1 <= D, "phase-1 shape");
+    __shared__ Survivor s_surv[kWaves][kSurvBatch];
+    const uint32_t lane = threadIdx.x & 63;
+    SurvBatch<kSurvBatch> sb{s_surv[wave_id_in_block()], 0};
+    const uint64_t n_sets = desc ? desc[1] : a.n_sets;
+    const uint32_t q_lo = desc ? 0u : a.q0, q_hi = desc ? (uint32_t)desc[0] : a.q1;
+    const uint32_t qpw = chunk_queries(a, desc, q_hi - q_lo);
+    const uint64_t ntiles = (n_sets + 63) / 64;
+    const uint64_t ngroups = (ntiles + TPW - 1) / TPW;
+    const uint32_t nchunks = (q_hi - q_lo + qpw - 1) / qpw;
+    const uint64_t n_items = ngroups * nchunks;
+    const uint64_t wstride = (uint64_t)gridDim.x * kWaves;
+    const uint64_t ctiles = a.capacity / 64;
+    const uint64_t rstride = (uint64_t)a.cg * RS;
+    for (uint64_t item = (uint64_t)blockIdx.x * kWaves + wave_id_in_block(); item < n_items; item += wstride) {
+        const uint64_t tg = item % ngroups;
+        const uint32_t chunk = (uint32_t)(item / ngroups);
+        const uint32_t qa = q_lo + chunk * qpw;
+        const uint32_t qb = min(q_hi, qa + qpw);
+        uint32_t P[TPW][G1][P1];
+        uint64_t vmask[TPW];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+            const uint64_t tile = tg * TPW + t;
+            vmask[t] = __builtin_amdgcn_ballot_w64(tile * 64 + lane < n_sets);
+            if (tile < ntiles) {             // wave-uniform; tiles below ntiles exist (ntiles <= ctiles)
+#pragma unroll
+                for (int u = 0; u < G1; ++u) {
+                    const uint4 v =
+                        *reinterpret_cast<const uint4 *>(codes + (((uint64_t)u * ctiles + tile) * 64 + lane) * PW);
+                    const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int j = 0; j < P1; ++j) P[t][u][j] = w4[j];
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < G1; ++u)
+#pragma unroll
+                    for (int j = 0; j < P1; ++j) P[t][u][j] = 0;
+            }
+        }
+        for (uint32_t q = qa; q < qb; ++q) {
+            const uint32_t *rec = qcodes + (uint64_t)q * rstride;
+            uint32_t nq[G1], c[G1];
+            int32_t y[G1];
+#pragma unroll
+            for (int g = 0; g < G1; ++g) {
+                nq[g] = rec[g * RS + PW];
+                c[g] = rec[g * RS + PW + 4];
+                y[g] = (int32_t)rec[g * RS + PW + 6];
+            }
+            // keep at step R when st < zk: below the reject cutoff, or at or below
+            // the maybe cutoff (y_R + 1 > z_R only when rounding meets them)
+            const uint32_t zR = rec[R * RS + PW + 5];
+            const uint32_t zk = (y[R] >= 0 && (uint32_t)y[R] + 1u > zR) ? (uint32_t)y[R] + 1u : zR;
+            uint32_t tiles_kept = 0;         // bit t: a lane of tile t is kept
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                uint32_t st = 0;
+                bool mb = false;
+#pragma unroll
+                for (int g = 0; g < G1; ++g) {
+                    const uint32_t d = code_diff_part<1, 0, P1>(0u, P[t][g], rec + g * RS, 0);
+                    st += __umul24(c[g], (uint32_t)__popc(d & nq[g]));
+                    if (g < R) mb = mb || (int32_t)st <= y[g];
+                }
+                tiles_kept |= (__builtin_amdgcn_ballot_w64(mb || st < zk) & vmask[t]) ? (1u << t) : 0u;
+            }
+            if (tiles_kept == 0) continue;
+            // phase 2 (rare): full planes of every group, steps in order
+            uint32_t nqf[D], cf[D], zf[D];
+            int32_t yf[D];
+#pragma unroll
+            for (int g = 0; g < D; ++g) {
+                nqf[g] = rec[g * RS + PW];
+                cf[g] = rec[g * RS + PW + 4];
+                zf[g] = rec[g * RS + PW + 5];
+                yf[g] = (int32_t)rec[g * RS + PW + 6];
+            }
+            // one tile at a time (not unrolled: the full planes of one tile are live at once)
+#pragma unroll 1
+            for (int t = 0; t < TPW; ++t) {
+                if (!((tiles_kept >> t) & 1u)) continue;
+                const uint64_t tile = tg * TPW + t;
+                const uint64_t vm = __builtin_amdgcn_ballot_w64(tile * 64 + lane < n_sets);
+                uint32_t st = 0;
+                bool und = true, mb = false;
+#pragma unroll
+                for (int g = 0; g < D; ++g) {
+                    if (g > R && !__any(und)) break;
+                    const uint4 *src =
+                        reinterpret_cast<const uint4 *>(codes + (((uint64_t)g * ctiles + tile) * 64 + lane) * PW);
+                    const uint4 v0 = src[0], v1 = src[1];
+                    const uint32_t Pf[PW] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+                    const uint32_t d = code_diff<1>(Pf, rec + g * RS, 0);
+                    st += __umul24(cf[g], (uint32_t)__popc(d & nqf[g]));
+                    if (und) {
+                        if ((int32_t)st <= yf[g]) {
+                            mb = true;
+                            und = false;
+                        } else if (st >= zf[g]) {
+                            und = false;
+                        }
+                    }
+                }
+                const uint64_t bal = __builtin_amdgcn_ballot_w64(mb || und) & vm;
+                sb.push(bal, q, (uint32_t)(tile * 64 + lane), surv, a.surv_cap, counters + 0, lane);
+            }
+        }
+    }
+    sb.flush(surv, a.surv_cap, counters + 0, lane);
+}
+
 template <int KPAD, int G, bool EXACT>
 __global__ __launch_bounds__(kThreads) void scan_coarse_kernel(const uint32_t *__restrict__ slab,
                                                               const uint32_t *__restrict__ qsigs,
@@ -1291,8 +1420,11 @@ static bool lin_code_pass(const ScanLaunch &l, const ScanTab &tab, LinTab *lin) 
 }
 
 // Tiles per wavefront of the linear-bound pass: 4 for two groups, else 2
-// (the planes of D groups of TPW tiles stay in VGPRs).
+// (the planes of D groups of TPW tiles stay in VGPRs); with a first phase
+// (only its P1 <= 4 planes of G1 groups in VGPRs): 8 for one or two groups,
+// else 4.
 static constexpr int lin_tiles(int D) { return D == 2 ? 4 : 2; }
+static constexpr int lin1_tiles(int G1) { return G1 <= 2 ? 8 : 4; }
 
 // Planes of phase 1 of the linear-bound pass: a background pair matches a
 // bin's first p planes with probability 2^-p, so phase 1 settles it when that
@@ -1312,7 +1444,10 @@ static int lin_plane_split(const ScanTab &tab, uint32_t kp, uint32_t R) {
 
 uint32_t coarse_tiles_per_wave(const ScanLaunch &l, const ScanTab &tab) {
     const uint32_t policy = tab.policy;
-    if (lin_code_pass(l, tab, nullptr)) return (uint32_t)lin_tiles((int)l.depth);
+    if (lin_code_pass(l, tab, nullptr)) {
+        const uint32_t R = first_reject_step(tab);
+        return (uint32_t)(lin_plane_split(tab, l.kp, R) > 0 ? lin1_tiles((int)R + 1) : lin_tiles((int)l.depth));
+    }
     if (!(l.codes && l.depth == 1 && policy != HOPH_EMPTY_EITHER)) return 1u;
     return (uint32_t)fast_tiles((int)code_plane_words(l.kp), plane_split(tab, l.kp));
 }
@@ -1359,6 +1494,32 @@ hipError_t launch_scan_coarse(const ScanLaunch &l, const ScanTab &tab, hipStream
         const uint32_t R = first_reject_step(tab);
         const int p1 = lin_plane_split(tab, l.kp, R);
         auto *cnt = reinterpret_cast<unsigned long long *>(l.counters);
+        if (p1 > 0) {
+            // phase-1 planes of groups 0..R in VGPRs, the rest read again where a lane is kept
+#define HOPH_LIN1(G1, DD, P1)                                                                                    \
+    hipLaunchKernelGGL((scan_codes_lin1_kernel<G1, DD, lin1_tiles(G1), P1>), dim3(blocks), dim3(kThreads), 0, st, \
+                       l.codes, l.qcodes, l.surv, cnt, l.desc, a)
+#define HOPH_LIN1_P(G1, DD)                  \
+    do {                                     \
+        if (p1 == 4) HOPH_LIN1(G1, DD, 4);   \
+        else if (p1 == 3) HOPH_LIN1(G1, DD, 3); \
+        else HOPH_LIN1(G1, DD, 2);           \
+    } while (0)
+            switch (l.depth * 4 + R) {
+            case 2 * 4 + 0: HOPH_LIN1_P(1, 2); break;
+            case 2 * 4 + 1: HOPH_LIN1_P(2, 2); break;
+            case 3 * 4 + 0: HOPH_LIN1_P(1, 3); break;
+            case 3 * 4 + 1: HOPH_LIN1_P(2, 3); break;
+            case 3 * 4 + 2: HOPH_LIN1_P(3, 3); break;
+            case 4 * 4 + 0: HOPH_LIN1_P(1, 4); break;
+            case 4 * 4 + 1: HOPH_LIN1_P(2, 4); break;
+            case 4 * 4 + 2: HOPH_LIN1_P(3, 4); break;
+            default: HOPH_LIN1_P(4, 4); break;
+            }
+#undef HOPH_LIN1_P
+#undef HOPH_LIN1
+            return hipGetLastError();
+        }
 #define HOPH_LIN(DD, P1)                                                                                      \
     hipLaunchKernelGGL((scan_codes_lin_kernel<DD, lin_tiles(DD), P1>), dim3(blocks), dim3(kThreads), 0, st,   \
                        l.codes, l.qcodes, l.surv, cnt, l.desc, a, R)
