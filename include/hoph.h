@@ -200,6 +200,13 @@ hoph_status hoph_scan_timing(const hoph_index *index, const uint32_t *d_qsigs, u
                              const hoph_query_params *qp, uint32_t reps, void *d_flush, uint64_t flush_bytes,
                              float *ms_per_launch, void *hip_stream);
 
+/* hoph_stream_timing -- a measurement hook for the HBM ceilings the kernels are
+   compared with: mean device ms of one pass, over reps passes back to back, of
+   ms[0] reading d_a (bytes, 16-byte aligned; its first 4 MiB may be
+   overwritten), ms[1] writing d_b (bytes, 8-byte aligned), ms[2] copying d_a to
+   d_b (device to device).  bytes >= 4 MiB.  Synchronises hip_stream. */
+hoph_status hoph_stream_timing(void *d_a, void *d_b, uint64_t bytes, uint32_t reps, float ms[3], void *hip_stream);
+
 /* hoph_append_timing -- device time of the last index_append_sets call on this
    index, in ms: ms[0] the sketch into the index rows, ms[1] the code planes of
    the new rows (0 where the sketch writes them itself: an odd code-unit width
@@ -379,7 +386,9 @@ typedef struct {
     uint64_t max_batch_results;   /* accepted pairs per batch                                   */
     uint64_t device_mem_budget;   /* bytes all slots may reserve (0: no limit); slots are
                                      dropped until the reservation fits, at least one stays    */
-    uint32_t tune;                /* tune tile shapes on each slot's first batch               */
+    uint32_t tune;                /* tune tile shapes at creation on one synthetic batch (up
+                                     to 64 sets of up to 800 pseudo-random ids below the
+                                     universe) and give them to every slot                   */
     uint32_t reserved;
 } hoph_server_config;
 
@@ -393,6 +402,9 @@ typedef struct {
     uint64_t slot_bytes;          /* device bytes one slot reserves                            */
 } hoph_server_stats;
 
+/* hoph_server_create -- slots (plans, streams, pinned staging) and the insert
+   staging are allocated, tuned and graph-captured here, so that no request or
+   insert waits for an allocation, a tuning or a capture. */
 hoph_status hoph_server_create(hoph_index *index, const hoph_sketch_params *params,
                                const hoph_query_params *qp, const hoph_server_config *cfg,
                                hoph_server **out);
@@ -409,8 +421,11 @@ hoph_status hoph_server_wait(hoph_server *srv, uint64_t ticket, uint32_t *h_out,
 hoph_status hoph_server_poll(hoph_server *srv, uint64_t ticket, int32_t *done, uint32_t *h_out,
                              uint64_t cap, uint64_t *n_out);
 /* hoph_server_insert -- sketch n_sets host sets (CSR) and append them to the index
-   (ids continue the index); they are visible to batches dispatched after the call
-   returns.  HOPH_E_CAPACITY past the index capacity. */
+   (ids continue the index), in pieces of at most 65,536 sets and max(max_batch_ids,
+   2^20) ids through staging allocated at creation; each piece is visible to
+   batches dispatched after it is sketched, all of them when the call returns.
+   HOPH_E_CAPACITY past the index capacity or for a set larger than a piece
+   (nothing is inserted then); HOPH_E_INVAL for decreasing offsets. */
 hoph_status hoph_server_insert(hoph_server *srv, const uint32_t *h_ids, const uint64_t *h_offsets,
                                uint64_t n_sets);
 /* hoph_server_replay -- native load generator: submit request i (host CSR) at

@@ -87,6 +87,7 @@ SIGNATURES = {
     "index_append": (C.c_int, [vp, vp, u64, vp]),
     "index_append_sets": (C.c_int, [vp, vp, vp, u64, vp]),
     "hoph_append_timing": (C.c_int, [vp, C.POINTER(C.c_float)]),
+    "hoph_stream_timing": (C.c_int, [vp, vp, u64, u32, C.POINTER(C.c_float), vp]),
     "hoph_self_join": (C.c_int, [vp, C.POINTER(QueryParamsC), C.POINTER(ResultsC), vp]),
     "hoph_pair_estimates": (C.c_int, [vp, vp, u32, vp, u64, u32, vp, vp, vp, vp, vp, C.POINTER(C.c_int64), vp]),
     "hoph_index_rows": (C.c_int, [vp, u64, u64, vp, vp]),
@@ -379,6 +380,18 @@ def scan_timing(index: Index, qsigs, T=(4, 5), eps=(1, 10000), policy=EMPTY_JOIN
     _check(lib().hoph_scan_timing(index.handle, vp(qsigs.data_ptr()), qsigs.shape[0], C.byref(qp), reps, fp, fb,
                                   C.byref(ms), _stream(stream)))
     return float(ms.value)
+
+
+def stream_timing(a, b, reps=10, stream=None):
+    """Mean device ms of one read of a, one write of b and one copy a -> b
+    (device tensors of equal byte size, at least 4 MiB; a's first 4 MiB may
+    be overwritten)."""
+    nbytes = a.numel() * a.element_size()
+    if b.numel() * b.element_size() != nbytes:
+        raise ValueError("a and b must have the same size in bytes")
+    ms = (C.c_float * 3)()
+    _check(lib().hoph_stream_timing(vp(a.data_ptr()), vp(b.data_ptr()), nbytes, reps, ms, _stream(stream)))
+    return float(ms[0]), float(ms[1]), float(ms[2])
 
 
 def self_join(index: Index, T=(4, 5), eps=(1, 10000), policy=EMPTY_JOINT, capacity=None, coarse_depth=0,

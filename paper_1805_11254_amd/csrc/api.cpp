@@ -627,6 +627,37 @@ hoph_status hoph_scan_timing(const hoph_index *index, const uint32_t *d_qsigs, u
     return scan_timing(index, d_qsigs, n_q, qp, reps, d_flush, flush_bytes, ms_per_launch, hip_stream);
 }
 
+hoph_status hoph_stream_timing(void *d_a, void *d_b, uint64_t bytes, uint32_t reps, float ms[3], void *hip_stream) {
+    g_last_error.clear();
+    if (!d_a || !d_b || !ms) return fail(HOPH_E_INVAL, "NULL argument");
+    if (bytes < kSweepSinkBytes || reps == 0) return fail(HOPH_E_INVAL, "bytes must be at least 4 MiB, reps >= 1");
+    if (reinterpret_cast<uintptr_t>(d_a) % 16 || reinterpret_cast<uintptr_t>(d_b) % 8)
+        return fail(HOPH_E_INVAL, "d_a must be 16-byte and d_b 8-byte aligned");
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    hipEvent_t e[2] = {nullptr, nullptr};
+    for (auto &x : e)
+        if (hipEventCreate(&x) != hipSuccess) return fail(HOPH_E_DEVICE, "hipEventCreate");
+    hoph_status st = HOPH_OK;
+    for (int kind = 0; kind < 3 && st == HOPH_OK; ++kind) {
+        auto once = [&]() -> hipError_t {
+            if (kind == 0) return launch_read_sweep(d_a, bytes / 16 * 16, static_cast<uint32_t *>(d_a), s);
+            if (kind == 1) return launch_fill_u64(static_cast<uint64_t *>(d_b), bytes / 8, 1, s);
+            return hipMemcpyAsync(d_b, d_a, bytes, hipMemcpyDeviceToDevice, s);
+        };
+        hipError_t err = once();                              // warm
+        if (err == hipSuccess) err = hipEventRecord(e[0], s);
+        for (uint32_t r = 0; r < reps && err == hipSuccess; ++r) err = once();
+        if (err == hipSuccess) err = hipEventRecord(e[1], s);
+        if (err == hipSuccess) err = hipEventSynchronize(e[1]);
+        float t = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&t, e[0], e[1]);
+        if (err != hipSuccess) st = hip_fail(err, "stream timing");
+        ms[kind] = t / (float)reps;
+    }
+    for (auto &x : e) (void)hipEventDestroy(x);
+    return st;
+}
+
 hoph_status hoph_append_timing(const hoph_index *idx, float ms[2]) {
     g_last_error.clear();
     if (!idx || !ms) return fail(HOPH_E_INVAL, "NULL argument");

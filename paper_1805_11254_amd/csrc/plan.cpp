@@ -348,7 +348,7 @@ hoph_status hoph_plan_create(hoph_index *idx, const hoph_sketch_params *params, 
     const uint32_t maxd = p->codes ? idx->cg : std::min(max_depth_for_kpad(idx->kpad), idx->lay.L);
     p->depth = default_coarse_depth(p->tab, qp->coarse_depth, maxd, p->codes ? code_pack(idx->lay.kp, idx->lay.L) : 1u);
     const uint64_t Q = cfg->max_queries, k = params->k, L = idx->lay.L;
-    p->surv_cap = std::max<uint64_t>(idx->capacity, 1u << 20);
+    p->surv_cap = plan_survivor_capacity(idx->capacity, cfg->max_queries);
     p->keys_cap = sort_capacity(std::max<uint64_t>(cfg->max_results, 1));
     auto cleanup = [&](hoph_status s) {
         p->release();
@@ -480,6 +480,24 @@ void hoph_plan_free(hoph_plan *p) {
 }  // extern "C"
 
 namespace hoph {
+
+uint64_t plan_survivor_capacity(uint64_t index_capacity, uint32_t max_queries) {
+    // first-pass survivors grow with the batch: the index capacity per 1,024 queries
+    return std::max<uint64_t>(index_capacity, 1u << 20) * std::max<uint64_t>(1, (max_queries + 1023) / 1024);
+}
+
+hoph_status plan_adopt_and_capture(hoph_plan *p, const hoph_plan *from) {
+    if (!p) return fail(HOPH_E_INVAL, "plan is NULL");
+    std::lock_guard<std::mutex> lk(p->mu);
+    DeviceGuard dg(p->idx->device);
+    if (from) {
+        p->shape = from->shape;
+        p->tuned = from->tuned;
+        p->tune_ms = from->tune_ms;
+    }
+    if (p->cfg.use_graph && !p->exec) return capture(p);
+    return HOPH_OK;
+}
 
 hoph_status plan_results_to_host(hoph_plan *p, uint64_t *h_offsets, uint32_t *h_ids, uint64_t pre,
                                  uint64_t *n_results, hipStream_t st) {

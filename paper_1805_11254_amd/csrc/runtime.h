@@ -241,4 +241,11 @@ hoph_status cached_scan_tab(hoph_index *idx, const hoph_query_params &qp, bool g
 // fallback.  h_ids holds the plan's max_results ids; pre <= max_results.
 hoph_status plan_results_to_host(hoph_plan *p, uint64_t *h_offsets, uint32_t *h_ids, uint64_t pre,
                                  uint64_t *n_results, hipStream_t st);
+// Survivor records a plan holds: the index capacity (at least 2^20) per 1,024
+// queries of its batch capacity.
+uint64_t plan_survivor_capacity(uint64_t index_capacity, uint32_t max_queries);
+// Takes the tile shapes another plan tuned (from may be null: keep the
+// defaults) and captures this plan's graph now (if it uses one), so that its
+// first batch starts without tuning or capture.
+hoph_status plan_adopt_and_capture(hoph_plan *p, const hoph_plan *from);
 }  // namespace hoph

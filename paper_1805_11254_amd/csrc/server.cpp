@@ -83,8 +83,10 @@ struct hoph_server {
     // memory (which would wait for every batch in flight)
     std::mutex insert_mu;
     hipStream_t insert_stream = nullptr;
-    uint32_t *ins_ids = nullptr;
-    uint64_t *ins_offs = nullptr;
+    // insert staging, allocated at creation (device and pinned host): inserts
+    // larger than it go through in pieces, so no insert allocates
+    uint32_t *ins_ids = nullptr, *h_ins_ids = nullptr;
+    uint64_t *ins_offs = nullptr, *h_ins_offs = nullptr;
     uint64_t ins_ids_cap = 0, ins_sets_cap = 0;
 };
 
@@ -161,7 +163,7 @@ void worker_loop(hoph_server *srv, Slot *sl) {
 
 uint64_t plan_bytes(const hoph_index *idx, const hoph_server_config &c) {
     const uint64_t Q = c.max_batch_queries, k = idx->lay.k, L = idx->lay.L;
-    const uint64_t surv = std::max<uint64_t>(idx->capacity, 1u << 20);
+    const uint64_t surv = plan_survivor_capacity(idx->capacity, c.max_batch_queries);
     const uint64_t keys = sort_capacity(std::max<uint64_t>(c.max_batch_results, 1));
     return 4 * c.max_batch_ids + 8 * 4 * (Q + 1) + 4 * Q * k + 8 * Q * L + 4 * (Q + 1) * idx->cg * code_rec_words(idx->lay.kp) +
            16 * surv + 8 * keys + 4 * c.max_batch_results + 4 * (Q + 1) + 4 * c.max_batch_ids + 8 * (Q + 1);
@@ -185,6 +187,39 @@ hoph_status fetch(hoph_server *srv, const std::shared_ptr<Request> &r, uint32_t 
     if (r->result.size() > cap) return fail(HOPH_E_CAPACITY, "output capacity too small");
     if (h_out && !r->result.empty()) std::memcpy(h_out, r->result.data(), r->result.size() * sizeof(uint32_t));
     srv->table.erase(r->ticket);
+    return HOPH_OK;
+}
+
+hoph_status prime_slots(hoph_server *srv) {
+    Slot &s0 = *srv->slots[0];
+    if (srv->cfg.tune) {
+        const uint32_t n_q = (uint32_t)std::min<uint64_t>(64, srv->cfg.max_batch_queries);
+        const uint64_t per = std::max<uint64_t>(1, std::min<uint64_t>(800, srv->cfg.max_batch_ids / n_q));
+        const uint64_t universe = std::max<uint64_t>(1, srv->params.universe);
+        uint64_t x = 0x9E3779B97F4A7C15ull;
+        for (uint32_t q = 0; q <= n_q; ++q) s0.h_offs[q] = (uint64_t)q * per;
+        for (uint64_t i = 0; i < (uint64_t)n_q * per; ++i) {
+            x = x * 6364136223846793005ull + 1442695040888963407ull;      // 64-bit LCG (Knuth's MMIX constants)
+            s0.h_ids[i] = (uint32_t)((x >> 32) % universe);
+        }
+        HOPH_HIP(hipMemcpyAsync(s0.d_ids, s0.h_ids, (uint64_t)n_q * per * 4, hipMemcpyHostToDevice, s0.stream),
+                 "prime ids");
+        HOPH_HIP(hipMemcpyAsync(s0.d_offs, s0.h_offs, ((uint64_t)n_q + 1) * 8, hipMemcpyHostToDevice, s0.stream),
+                 "prime offsets");
+        hoph_status st = hoph_plan_run(s0.plan, s0.d_ids, s0.d_offs, n_q, (uint64_t)n_q * per, s0.stream);
+        if (st) return st;
+        uint64_t n_res = 0;
+        st = plan_results_to_host(s0.plan, s0.h_res_offs, s0.h_res_ids, 0, &n_res, s0.stream);
+        if (st && st != HOPH_E_CAPACITY) return st;          // the synthetic answers themselves are not needed
+    } else {
+        hoph_status st = plan_adopt_and_capture(s0.plan, nullptr);
+        if (st) return st;
+    }
+    for (size_t i = 1; i < srv->slots.size(); ++i) {
+        hoph_status st = plan_adopt_and_capture(srv->slots[i]->plan, srv->cfg.tune ? s0.plan : nullptr);
+        if (st) return st;
+    }
+    clear_error();
     return HOPH_OK;
 }
 
@@ -241,6 +276,35 @@ hoph_status hoph_server_create(hoph_index *idx, const hoph_sketch_params *params
     if (hipStreamCreateWithFlags(&srv->insert_stream, hipStreamNonBlocking) != hipSuccess) {
         for (auto &s : srv->slots) free_slot(*s);
         return fail(HOPH_E_DEVICE, "hipStreamCreate");
+    }
+    // insert staging: one slot's ids (at least 2^20) and 65,536 sets per piece
+    srv->ins_ids_cap = std::max<uint64_t>(cfg->max_batch_ids, 1u << 20);
+    srv->ins_sets_cap = 65536;
+    if (hipMalloc(&srv->ins_ids, srv->ins_ids_cap * 4) != hipSuccess ||
+        hipMalloc(&srv->ins_offs, (srv->ins_sets_cap + 1) * 8) != hipSuccess ||
+        hipHostMalloc(&srv->h_ins_ids, srv->ins_ids_cap * 4, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&srv->h_ins_offs, (srv->ins_sets_cap + 1) * 8, hipHostMallocDefault) != hipSuccess) {
+        for (auto &s : srv->slots) free_slot(*s);
+        (void)hipStreamDestroy(srv->insert_stream);
+        if (srv->ins_ids) (void)hipFree(srv->ins_ids);
+        if (srv->ins_offs) (void)hipFree(srv->ins_offs);
+        if (srv->h_ins_ids) (void)hipHostFree(srv->h_ins_ids);
+        if (srv->h_ins_offs) (void)hipHostFree(srv->h_ins_offs);
+        return fail(HOPH_E_NOMEM, "insert staging");
+    }
+    // Every slot ready before the first request: with tuning, one synthetic batch
+    // (up to 64 query sets of up to 800 pseudo-random ids) through the first slot
+    // times the tile shapes; every other slot takes them and captures its graph
+    // now, so no request waits for a slot's tuning or graph capture.
+    hoph_status pst = prime_slots(srv.get());
+    if (pst) {
+        for (auto &s : srv->slots) free_slot(*s);
+        (void)hipStreamDestroy(srv->insert_stream);
+        (void)hipFree(srv->ins_ids);
+        (void)hipFree(srv->ins_offs);
+        (void)hipHostFree(srv->h_ins_ids);
+        (void)hipHostFree(srv->h_ins_offs);
+        return pst;
     }
     hoph_server *raw = srv.get();
     for (auto &s : srv->slots) s->worker = std::thread(worker_loop, raw, s.get());
@@ -311,57 +375,51 @@ hoph_status hoph_server_insert(hoph_server *srv, const uint32_t *h_ids, const ui
         if (idx->n + n_sets > idx->max_sets) return fail(HOPH_E_CAPACITY, "index capacity exceeded");
     }
     // the offsets are on the host: a decreasing pair would make the device read
-    // a range that wraps past the staged ids
-    for (uint64_t i = 0; i < n_sets; ++i)
+    // a range that wraps past the staged ids; a set larger than the staging
+    // cannot be sketched in one piece
+    for (uint64_t i = 0; i < n_sets; ++i) {
         if (h_offsets[i + 1] < h_offsets[i]) return fail(HOPH_E_INVAL, "insert offsets decrease");
-    const uint64_t nnz = h_offsets[n_sets] - h_offsets[0];
-    std::vector<uint64_t> offs(h_offsets, h_offsets + n_sets + 1);
-    for (auto &o : offs) o -= h_offsets[0];
-    if (nnz > srv->ins_ids_cap) {
-        // growth frees the old buffer; previous inserts were synchronised already
-        if (srv->ins_ids) (void)hipFree(srv->ins_ids);
-        srv->ins_ids = nullptr;
-        srv->ins_ids_cap = 0;
-        const uint64_t cap = std::max<uint64_t>(nnz + nnz / 2, 1 << 20);
-        if (hipMalloc(&srv->ins_ids, cap * 4) != hipSuccess) return fail(HOPH_E_NOMEM, "insert staging");
-        srv->ins_ids_cap = cap;
+        if (h_offsets[i + 1] - h_offsets[i] > srv->ins_ids_cap)
+            return fail(HOPH_E_CAPACITY, "an inserted set has more ids than the insert staging holds (" +
+                                             std::to_string(srv->ins_ids_cap) + ")");
     }
-    if (n_sets > srv->ins_sets_cap) {
-        if (srv->ins_offs) (void)hipFree(srv->ins_offs);
-        srv->ins_offs = nullptr;
-        srv->ins_sets_cap = 0;
-        const uint64_t cap = std::max<uint64_t>(n_sets + n_sets / 2, 4096);
-        if (hipMalloc(&srv->ins_offs, (cap + 1) * 8) != hipSuccess) return fail(HOPH_E_NOMEM, "insert staging");
-        srv->ins_sets_cap = cap;
-    }
-    uint32_t *d_ids = srv->ins_ids;
-    uint64_t *d_offs = srv->ins_offs;
     uint32_t *errw = nullptr;
     hoph_status es = device_err_word(&errw);
     if (es) return es;
     hipStream_t st = srv->insert_stream;
-    hoph_status s = HOPH_OK;
-    if (hipMemcpyAsync(d_ids, h_ids + h_offsets[0], nnz * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(d_offs, offs.data(), (n_sets + 1) * 8, hipMemcpyHostToDevice, st) != hipSuccess)
-        s = fail(HOPH_E_DEVICE, "insert copy");
-    uint64_t first = 0;
-    if (!s) {
-        std::lock_guard<std::mutex> lk(idx->mu);
-        first = idx->n;
+    // pieces of at most ins_sets_cap sets and ins_ids_cap ids, each sketched into
+    // rows [first, first + m) and then made visible
+    for (uint64_t a = 0; a < n_sets;) {
+        uint64_t b = a;
+        while (b < n_sets && b - a < srv->ins_sets_cap && h_offsets[b + 1] - h_offsets[a] <= srv->ins_ids_cap) ++b;
+        const uint64_t m = b - a, nnz = h_offsets[b] - h_offsets[a];
+        std::memcpy(srv->h_ins_ids, h_ids + h_offsets[a], nnz * 4);
+        for (uint64_t i = 0; i <= m; ++i) srv->h_ins_offs[i] = h_offsets[a + i] - h_offsets[a];
+        hoph_status s = HOPH_OK;
+        if (hipMemcpyAsync(srv->ins_ids, srv->h_ins_ids, nnz * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(srv->ins_offs, srv->h_ins_offs, (m + 1) * 8, hipMemcpyHostToDevice, st) != hipSuccess)
+            s = fail(HOPH_E_DEVICE, "insert copy");
+        uint64_t first = 0;
+        if (!s) {
+            std::lock_guard<std::mutex> lk(idx->mu);
+            first = idx->n;
+        }
+        // batches dispatched meanwhile read only rows below idx->n
+        if (!s && append_sets_async(idx, srv->ins_ids, srv->ins_offs, m, first, errw, st, false) != hipSuccess)
+            s = fail(HOPH_E_DEVICE, "sketch-into-index launch");
+        if (!s && hipStreamSynchronize(st) != hipSuccess) s = fail(HOPH_E_DEVICE, "hipStreamSynchronize");
+        if (s) return s;
+        {
+            // visible to batches dispatched from now on; batches in flight keep their snapshot
+            std::lock_guard<std::mutex> lk(idx->mu);
+            idx->n = first + m;
+        }
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            srv->inserted += m;
+        }
+        a = b;
     }
-    // sketched straight into rows [first, first + n_sets): batches dispatched
-    // meanwhile read only rows below idx->n
-    if (!s && append_sets_async(idx, d_ids, d_offs, n_sets, first, errw, st, false) != hipSuccess)
-        s = fail(HOPH_E_DEVICE, "sketch-into-index launch");
-    if (!s && hipStreamSynchronize(st) != hipSuccess) s = fail(HOPH_E_DEVICE, "hipStreamSynchronize");
-    if (s) return s;
-    {
-        // visible to batches dispatched from now on; batches in flight keep their snapshot
-        std::lock_guard<std::mutex> lk(idx->mu);
-        idx->n = first + n_sets;
-    }
-    std::lock_guard<std::mutex> lk(srv->mu);
-    srv->inserted += n_sets;
     return HOPH_OK;
 }
 
@@ -469,6 +527,8 @@ void hoph_server_destroy(hoph_server *srv) {
         if (srv->insert_stream) (void)hipStreamDestroy(srv->insert_stream);
         if (srv->ins_ids) (void)hipFree(srv->ins_ids);
         if (srv->ins_offs) (void)hipFree(srv->ins_offs);
+        if (srv->h_ins_ids) (void)hipHostFree(srv->h_ins_ids);
+        if (srv->h_ins_offs) (void)hipHostFree(srv->h_ins_offs);
     }
     delete srv;
 }
