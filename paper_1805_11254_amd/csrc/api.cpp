@@ -897,9 +897,18 @@ hoph_status hoph_selftest_bins(const hoph_sketch_params *params, const uint32_t 
             if (be != b || se != start) return fail(HOPH_E_UNSUPPORTED, "bin estimate and region lookup disagree");
         }
         if (narrow) {
-            // the narrow lookups the device uses: the bin of the clamped value and the
-            // offset of the value itself in 32-bit arithmetic
-            const uint32_t v32 = narrow_value(v);
+            // the narrow lookups the device uses: the bin of the value's 32-bit view
+            // and the offset of the value itself in 32-bit arithmetic
+            uint32_t v32 = narrow_value(v);
+            if (p.hash == HOPH_HASH_MODP32P15 && (p.hash_a >> 32) == 0 && (p.hash_b >> 32) == 0) {
+                // the 32-bit form of the hash the device takes for such coefficients
+                uint32_t view, low;
+                psi_p32_narrow((uint32_t)x, (uint32_t)p.hash_a, (uint32_t)p.hash_b, view, low);
+                const bool view_ok = v <= 0xFFFFFFFFull ? view == v32 : (view >= kNarrowLow && view <= kNarrowTop);
+                if (low != (uint32_t)v || !view_ok)
+                    return fail(HOPH_E_UNSUPPORTED, "32-bit and 64-bit forms of the hash disagree");
+                v32 = view;
+            }
             uint32_t bn, sn;
             locate_narrow(v32, lut.data(), lay.lut_shift, rs.data(), lay.reg_mag32.data(), lay.n_regions,
                           lay.nb, s32.data(), bn, sn);

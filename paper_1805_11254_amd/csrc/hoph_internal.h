@@ -236,6 +236,37 @@ __host__ __device__ inline uint32_t narrow_value(uint64_t v) { return v > kNarro
 __host__ __device__ inline uint32_t narrow_start(uint64_t s) { return s > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)s; }
 // R - 1 of the narrow view: the value the log-domain cells count down from.
 __host__ __device__ inline uint32_t narrow_r1(uint64_t R) { return (uint32_t)(R - 1 > kNarrowTop ? kNarrowTop : R - 1); }
+// Smallest 32-bit view psi_p32_narrow may give a value at or above 2^32; the
+// narrow view needs the last bin to start at or below it.
+constexpr uint32_t kNarrowLow = 0xFFFFFFF1u;
+
+// The narrow view of (a x + b) mod p, p = 2^32 + 15, in 32-bit steps, for
+// coefficients a, b < 2^32 (a uniform draw from [0, p) is one but for a 15 / p
+// chance).  w = a x + b < 2^64 = h 2^32 + l = l - 15 h (mod p).  With
+// X = h (2^32 - 15) + l = h 2^32 + (l - 15 h) (one 32 x 32 -> 64 multiply-add,
+// in [0, 2^64)) and X = X1 2^32 + X0: l - 15 h = X0 - c 2^32 with c = h - X1 in
+// [0, 15], so w = e (mod p) for e = X0 + 15 c < 2^32 + 240, and at most one p
+// comes off.  With e0 = e mod 2^32 and g the carry out of that sum,
+// t = e0 - 15 g (mod 2^32):
+//   g = 0: the value is e0 = t;
+//   g = 1, e0 >= 15: the value is e - p = e0 - 15 = t;
+//   g = 1, e0 < 15: the value is 2^32 + e0 (low bits e0), and t wraps to
+//   2^32 - 15 + e0, above e0.
+// So low = min(t, e0) holds the value's low 32 bits, and view = min(t,
+// kNarrowTop) its narrow view, except that the values 2^32 .. p - 1 view as
+// some t in [kNarrowLow, kNarrowTop] instead of kNarrowTop: the same (last) bin
+// when that bin starts at or below kNarrowLow, which the host checks.
+__host__ __device__ inline void psi_p32_narrow(uint32_t x, uint32_t a, uint32_t b, uint32_t &view, uint32_t &low) {
+    const uint64_t w = (uint64_t)a * x + b;
+    const uint32_t h = (uint32_t)(w >> 32);
+    const uint64_t X = (uint64_t)h * 0xFFFFFFF1u + (uint32_t)w;
+    const uint32_t c = h - (uint32_t)(X >> 32);
+    const uint32_t m = mul_u24(c, 15u);
+    const uint32_t e0 = (uint32_t)X + m;
+    const uint32_t t = e0 - (e0 < m ? 15u : 0u);
+    low = t < e0 ? t : e0;
+    view = t < kNarrowTop ? t : kNarrowTop;
+}
 
 // One region of the permuted range: its first value and the reciprocal
 // M = floor(2^64 nb / z) of its size z (nb bins per region).

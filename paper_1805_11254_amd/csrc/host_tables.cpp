@@ -26,15 +26,16 @@ static uint64_t range_of(const hoph_sketch_params &p) {
 void choose_estimate(LayoutInfo &lay);
 void choose_pow2(LayoutInfo &lay);
 
-// Whether the 32-bit narrow view of the permuted range (narrow_value) is exact
-// for this layout: the range ends at or below 2^32 - 1, or (2^32 + 15) every
-// region and the last bin start below kNarrowTop, so every value it clamps lies
-// in the last bin.
+// Whether the 32-bit narrow view of the permuted range (narrow_value,
+// psi_p32_narrow) is exact for this layout: the range ends at or below 2^32 - 1,
+// or (2^32 + 15) every region starts below kNarrowTop and the last bin at or
+// below kNarrowLow, so every value the view moves lies in the last bin.
 bool narrow_view_ok(const LayoutInfo &L) {
     if (L.R <= 0xFFFFFFFFull) return true;
     std::vector<uint64_t> starts;
     host_starts(L, starts);
-    if (starts.size() < 2 || starts[L.k - 1] > kNarrowTop) return false;
+    // the last bin holds every value psi_p32_narrow views at kNarrowLow or above
+    if (starts.size() < 2 || starts[L.k - 1] > kNarrowLow) return false;
     for (uint32_t r = 0; r < L.n_regions; ++r)
         if (L.reg_start[r] >= kNarrowTop) return false;
     return true;
@@ -123,7 +124,7 @@ hoph_status build_layout(const hoph_sketch_params &p, LayoutInfo &out, std::stri
     }
     choose_pow2(L);
     if (p.hash == HOPH_HASH_MODP32P15 && !narrow_view_ok(L)) {
-        // the sketch looks bins up in 32 bits, which needs the last bin to start below 2^32 - 2
+        // the sketch looks bins up in 32 bits, which needs the last bin to start at or below 2^32 - 15
         err = "a bin at the top of the range is narrower than the 32-bit lookup needs (layout too deep)";
         return HOPH_E_UNSUPPORTED;
     }

@@ -16,6 +16,13 @@
 // An index append with no vector-load code-plane row kernel (odd k' or k) also
 // writes the new rows' code planes from the LDS signature.
 //
+// Hash: the shared permutation is computed in 32-bit steps where it can be:
+// (a x + b) mod (2^31 - 1) folds the high part once; (a x + b) mod (2^32 + 15)
+// with a, b < 2^32 takes two 32 x 32 -> 64 multiply-adds and a carry
+// (psi_p32_narrow), and only coefficients at or above 2^32 take the 64-bit
+// reduction.  Every lookup reads the value's 32-bit view; the offset is the
+// value's low 32 bits minus the bin start.
+//
 // Bin lookup: where regions and bins fall on powers of two (the 1:1 hierarchy
 // and power-of-two k over R = 2^31 - 1) one read of a 32-entry table indexed
 // by a leading-zero count gives the region, and a shift and a mask give the
@@ -36,17 +43,6 @@ namespace {
 
 constexpr int kUnroll = 4;
 
-template <uint32_t HASH>
-__device__ __forceinline__ uint64_t permute(uint64_t x, const SketchDesc &d) {
-    if constexpr (HASH == HOPH_HASH_TABLE) {
-        return d.perm[x];
-    } else if constexpr (HASH == HOPH_HASH_MODP31) {
-        return psi_p31(x, d.ha, d.hb);
-    } else {
-        return psi_p32(x, d.ha, d.hb);
-    }
-}
-
 constexpr int LOC_EST = 0, LOC_REGION = 1, LOC_LOG = 2, LOC_POW2 = 3;
 
 // The (a x + b) mod (2^31 - 1) and (a x + b) mod (2^32 + 15) hashes look bins
@@ -54,6 +50,27 @@ constexpr int LOC_EST = 0, LOC_REGION = 1, LOC_LOG = 2, LOC_POW2 = 3;
 // narrow_value); the table hash keeps 64-bit values and starts.
 template <uint32_t HASH>
 constexpr bool kNarrow = HASH != HOPH_HASH_TABLE;
+
+// The (a x + b) mod (2^32 + 15) hash with a, b < 2^32, in 32-bit steps
+// (psi_p32_narrow): a template value of its own, which the host picks.
+constexpr uint32_t kHashP32Small = 0x100u | HOPH_HASH_MODP32P15;
+
+// The permuted value of id x as the narrow lookups read it: its 32-bit view
+// and its low 32 bits.  (a x + b) mod (2^31 - 1) is reduced for x < P only, so
+// its ids are clamped to the universe; the 2^32 + 15 forms take any 32-bit x.
+template <uint32_t HASH>
+__device__ __forceinline__ void permute_narrow(uint32_t x, uint32_t umax, const SketchDesc &d, uint32_t &view,
+                                               uint32_t &low) {
+    if constexpr (HASH == HOPH_HASH_MODP31) {
+        view = low = (uint32_t)psi_p31(min(x, umax), d.ha, d.hb);     // below 2^31 - 1
+    } else if constexpr (HASH == kHashP32Small) {
+        psi_p32_narrow(x, (uint32_t)d.ha, (uint32_t)d.hb, view, low);
+    } else {
+        const uint64_t v = psi_p32(x, d.ha, d.hb);
+        view = narrow_value(v);
+        low = (uint32_t)v;
+    }
+}
 template <uint32_t HASH>
 using StartT = typename std::conditional<kNarrow<HASH>, uint32_t, uint64_t>::type;
 
@@ -161,39 +178,44 @@ __device__ Tables<HASH> build_tables(const SketchDesc &d, unsigned char *smem, c
     return t;
 }
 
-// Bin of the permuted value v and its offset from the bin start.
+// Bin of a narrow permuted value (view, low; see permute_narrow) and its
+// offset from the bin start.
 template <uint32_t HASH, int LOC>
-__device__ __forceinline__ void bin_of(uint64_t v, const SketchDesc &d, const Tables<HASH> &t, uint32_t &b,
-                                       uint32_t &off) {
-    if constexpr (kNarrow<HASH> && LOC == LOC_POW2) {
-        const uint32_t v32 = (uint32_t)v;              // the power-of-two lookup needs R <= 2^32 - 1
-        uint32_t u = (uint32_t)(d.R - 1) - v32;
+__device__ __forceinline__ void bin_of_narrow(uint32_t view, uint32_t low, const SketchDesc &d,
+                                              const Tables<HASH> &t, uint32_t &b, uint32_t &off) {
+    if constexpr (LOC == LOC_POW2) {
+        // the power-of-two lookup needs R <= 2^32 - 1 (view = low)
+        uint32_t u = (uint32_t)(d.R - 1) - view;
         u = u > 1u ? u : 1u;
         const uint4 e = t.pow2[clz32(u)];          // few distinct entries: mostly broadcast reads
-        const uint32_t dl = v32 - e.x;
+        const uint32_t dl = view - e.x;
         b = e.z + (dl >> e.y);
         off = dl & e.w;
-    } else if constexpr (kNarrow<HASH>) {
-        const uint32_t v32 = narrow_value(v);
+    } else {
         uint32_t start;
         if constexpr (LOC == LOC_EST) {
-            const uint32_t e = bin_estimate(v32, d.est_mul, d.est_shift);
+            const uint32_t e = bin_estimate(view, d.est_mul, d.est_shift);
             const uint32_t s0 = t.start[e], s1 = t.start[e + 1];
-            const bool up = v32 >= s1;
+            const bool up = view >= s1;
             b = e + (up ? 1u : 0u);
             start = up ? s1 : s0;
         } else if constexpr (LOC == LOC_LOG) {
-            locate_log(v32, narrow_r1(d.R), t.cells, t.regs, d.nb, t.start, b, start);
+            locate_log(view, narrow_r1(d.R), t.cells, t.regs, d.nb, t.start, b, start);
         } else {
-            locate_narrow(v32, t.lut, d.lut_shift, t.rstart, t.rmag, d.n_regions, d.nb, t.start, b, start);
+            locate_narrow(view, t.lut, d.lut_shift, t.rstart, t.rmag, d.n_regions, d.nb, t.start, b, start);
         }
-        off = (uint32_t)v - start;                     // below 2^32 (the bin's width)
-    } else {
-        uint64_t start;
-        if constexpr (LOC == LOC_EST) locate_est(v, d.est_mul, d.est_shift, t.start, b, start);
-        else locate(v, t.lut, d.lut_shift, t.reg, d.n_regions, d.nb, t.start, b, start);
-        off = (uint32_t)(v - start);
+        off = low - start;                             // below 2^32 (the bin's width)
     }
+}
+
+// Bin of a table value v (64-bit starts) and its offset from the bin start.
+template <int LOC>
+__device__ __forceinline__ void bin_of_wide(uint64_t v, const SketchDesc &d, const Tables<HOPH_HASH_TABLE> &t,
+                                            uint32_t &b, uint32_t &off) {
+    uint64_t start;
+    if constexpr (LOC == LOC_EST) locate_est(v, d.est_mul, d.est_shift, t.start, b, start);
+    else locate(v, t.lut, d.lut_shift, t.reg, d.n_regions, d.nb, t.start, b, start);
+    off = (uint32_t)(v - start);
 }
 
 // Hash, bin and fold into the LDS signature the elements base + lane + 64 u,
@@ -210,25 +232,38 @@ template <uint32_t HASH, int LOC, bool FULL>
 __device__ __forceinline__ void add_elements(const SketchDesc &d, const Tables<HASH> &t, uint32_t *sig,
                                              const uint32_t (&x)[kUnroll], uint64_t base, uint64_t hi,
                                              uint32_t lane, uint32_t umax, uint32_t &xmax, uint64_t &vmax) {
-    uint64_t v[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-        if (!FULL && base + 64u * u >= hi) break;
-        xmax = max(xmax, x[u]);
-        v[u] = permute<HASH>(min(x[u], umax), d);
-        if constexpr (HASH == HOPH_HASH_TABLE) {
-            vmax = max(vmax, v[u]);
-            v[u] = min(v[u], d.R - 1);
-        }
-    }
     // every bin lookup before the first LDS minimum: the tables and the
     // signature share the workgroup's LDS, so a lookup written after a minimum
     // would wait for it
     uint32_t b[kUnroll], off[kUnroll];
+    if constexpr (kNarrow<HASH>) {
+        uint32_t view[kUnroll], low[kUnroll];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-        if (!FULL && base + 64u * u >= hi) break;
-        bin_of<HASH, LOC>(v[u], d, t, b[u], off[u]);
+        for (int u = 0; u < kUnroll; ++u) {
+            if (!FULL && base + 64u * u >= hi) break;
+            xmax = max(xmax, x[u]);
+            permute_narrow<HASH>(x[u], umax, d, view[u], low[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (!FULL && base + 64u * u >= hi) break;
+            bin_of_narrow<HASH, LOC>(view[u], low[u], d, t, b[u], off[u]);
+        }
+    } else {
+        uint64_t v[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (!FULL && base + 64u * u >= hi) break;
+            xmax = max(xmax, x[u]);
+            v[u] = d.perm[min(x[u], umax)];
+            vmax = max(vmax, v[u]);
+            v[u] = min(v[u], d.R - 1);
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (!FULL && base + 64u * u >= hi) break;
+            bin_of_wide<LOC>(v[u], d, t, b[u], off[u]);
+        }
     }
     if constexpr (FULL) {
 #pragma unroll
@@ -584,6 +619,9 @@ hipError_t launch_chunked_t(const SketchDesc &d, const uint32_t *ids, const uint
     return hipGetLastError();
 }
 
+// Whether the (a x + b) mod (2^32 + 15) coefficients fit psi_p32_narrow.
+bool p32_small(const SketchDesc &d) { return (d.ha >> 32) == 0 && (d.hb >> 32) == 0; }
+
 }  // namespace
 
 hipError_t launch_sketch_chunked(const SketchDesc &d, const uint32_t *ids, const uint64_t *offsets,
@@ -606,6 +644,10 @@ hipError_t launch_sketch_chunked(const SketchDesc &d, const uint32_t *ids, const
                : d.log_ok ? HOPH_SKC(HOPH_HASH_MODP31, LOC_LOG)
                           : HOPH_SKC(HOPH_HASH_MODP31, LOC_REGION);
     default:
+        if (p32_small(d))
+            return est        ? HOPH_SKC(kHashP32Small, LOC_EST)
+                   : d.log_ok ? HOPH_SKC(kHashP32Small, LOC_LOG)
+                              : HOPH_SKC(kHashP32Small, LOC_REGION);
         return est        ? HOPH_SKC(HOPH_HASH_MODP32P15, LOC_EST)
                : d.log_ok ? HOPH_SKC(HOPH_HASH_MODP32P15, LOC_LOG)
                           : HOPH_SKC(HOPH_HASH_MODP32P15, LOC_REGION);
@@ -628,6 +670,10 @@ hipError_t launch_sketch(const SketchDesc &d, const uint32_t *ids, const uint64_
                : d.log_ok ? HOPH_SK(HOPH_HASH_MODP31, LOC_LOG)
                           : HOPH_SK(HOPH_HASH_MODP31, LOC_REGION);
     default:
+        if (p32_small(d))
+            return est        ? HOPH_SK(kHashP32Small, LOC_EST)
+                   : d.log_ok ? HOPH_SK(kHashP32Small, LOC_LOG)
+                              : HOPH_SK(kHashP32Small, LOC_REGION);
         return est        ? HOPH_SK(HOPH_HASH_MODP32P15, LOC_EST)
                : d.log_ok ? HOPH_SK(HOPH_HASH_MODP32P15, LOC_LOG)
                           : HOPH_SK(HOPH_HASH_MODP32P15, LOC_REGION);
