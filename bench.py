@@ -777,6 +777,25 @@ def _code_units(k, kp, goph):
     return pk, cu, cu * pk
 
 
+def _plane_split(dthr, kp, Wp):
+    """Phase-1 planes of the first-group pass, as the library picks them: the
+    least expected lane-ops per pair, W p + 3 for phase 1 plus W (8 - p) + 2
+    when any of the wavefront's lanes (64 per tile; 8 tiles for p = 2, else 4,
+    2 for W = 2) keeps a background pair, whose bins agree on p planes with
+    probability 2^-p each; 0 (one phase, 8 W + 3) when none is cheaper."""
+    need = kp - dthr + 1
+    best, pick = 8.0 * Wp + 3.0, 0
+    for p in range(2, 7):
+        f = 2.0 ** -p
+        tail = 1.0 if need <= 0 else sum(math.comb(kp, j) * f ** j * (1 - f) ** (kp - j)
+                                         for j in range(max(need, 0), kp + 1))
+        tiles = (8 if p == 2 else 4) if Wp == 1 else 2
+        cost = Wp * p + 3.0 + (1.0 - (1.0 - min(tail, 1.0)) ** (64 * tiles)) * (Wp * (8 - p) + 2.0)
+        if cost < best:
+            best, pick = cost, p
+    return pick
+
+
 def _coarse_model(H, p, T, eps, goph=False):
     """How the library runs the coarse pass for these parameters (JOINT, a
     query path), and the algorithmic work of one launch per (query, set) pair.
@@ -785,9 +804,8 @@ def _coarse_model(H, p, T, eps, goph=False):
     (no empty bins); else one group past the first step with a reject cutoff,
     in whole code units.  Kernel and minimum work per pair:
     - one group: the first-group pass compares P1 planes of every pair first
-      (P1 W plane operations, W masks, W popcounts, one compare; P1 = 2 when the
-      threshold on differing bins is at most half the bins, 4 when at most three
-      quarters), else all 8 planes (10 W + 1);
+      (P1 W plane operations, W masks, W popcounts, one compare; P1 from 2 to 6
+      by the expected cost of _plane_split), else all 8 planes (10 W + 1);
     - two to four groups of 17-32 bins: the linear-bound pass compares P1 planes
       of groups 1..R+1 (R+1 the first step with a reject cutoff; P1 the smallest
       of 2, 3, 4 planes whose chance match rate is at most a third of that
@@ -806,8 +824,7 @@ def _coarse_model(H, p, T, eps, goph=False):
     Wp = 1 if kp <= 32 else 2
     if m_rej0 >= 0 and 8 * m_rej0 >= kp:
         depth = 1
-        dthr = kp - m_rej0
-        split = 2 if 2 * dthr <= kp else (4 if 4 * dthr <= 3 * kp else 0)
+        split = _plane_split(kp - m_rej0, kp, Wp)
         ops = Wp * (split + 2) + 1 if split else 10 * Wp + 1
         kernel = "scan_codes_fast_kernel"
     else:

@@ -40,14 +40,34 @@ constexpr int kFineAhead = 4;          // most loads per step in the fine pass (
 // tiles), else four (two with two plane words).
 constexpr int fast_tiles(int W, int P1) { return W == 1 ? (P1 == 2 ? 8 : 4) : 2; }
 
-// Planes compared first in the first-group code pass: a non-matching bin
-// differs in the first p planes with probability 1 - 2^-p under uniform codes,
-// so a pair far from the threshold (most of them) is settled by 2 planes when
-// the threshold on differing bins is at most half the bins, by 4 when at most
-// three quarters; 0: all 8 planes in one phase.
+// Planes compared first in the first-group code pass.  A background pair
+// (independent, uniform codes) agrees on a query-non-empty bin's first p
+// planes with probability 2^-p, so phase 1 keeps one of its lanes when at
+// least kp - thr + 1 of the kp bins agree there (a binomial tail), and a
+// wavefront goes on to phase 2 for all of its tiles when any of its 64 TPW
+// lanes is kept.  Per pair, phase 1 costs about W p + 3 lane-ops and phase 2
+// another W (8 - p) + 2, one phase over all 8 planes 8 W + 3; the split of 2
+// to 6 planes (or 0: one phase) with the least expected cost is taken.
 int plane_split(const ScanTab &tab, uint32_t kp) {
-    const int32_t thr = tab.dthr0[0], k = (int32_t)kp;
-    return 2 * thr <= k ? 2 : (4 * thr <= 3 * k ? 4 : 0);
+    const int32_t k = (int32_t)kp, need = k - tab.dthr0[0] + 1;   // agreeing bins that keep a lane
+    const int W = (int)code_plane_words(kp);
+    double best = 8.0 * W + 3.0;
+    int pick = 0;
+    for (int p = 2; p <= 6; ++p) {
+        const double f = std::ldexp(1.0, -p);
+        double tail = need <= 0 ? 1.0 : 0.0, term = std::pow(1.0 - f, k);   // P(j = 0)
+        for (int j = 0; j <= k && need > 0; ++j) {
+            if (j >= need) tail += term;
+            term *= (double)(k - j) / (double)(j + 1) * f / (1.0 - f);
+        }
+        const double open = 1.0 - std::pow(1.0 - std::min(tail, 1.0), 64.0 * fast_tiles(W, p));
+        const double cost = W * p + 3.0 + open * (W * (8 - p) + 2.0);
+        if (cost < best) {
+            best = cost;
+            pick = p;
+        }
+    }
+    return pick;
 }
 
 struct CoarseArgs {
@@ -1301,13 +1321,23 @@ void codes_launch(const ScanLaunch &l, const CoarseArgs &a, const ScanTab &tab, 
     hipLaunchKernelGGL((scan_codes_fast_kernel<W, fast_tiles(W, P1), P1, TRI>), dim3(blocks), dim3(kThreads), 0, st, \
                        l.codes, l.qcodes, l.surv, cnt, l.desc, a)
         if (l.tri) {
-            if (split == 2) HOPH_FAST(2, true);
-            else if (split == 4) HOPH_FAST(4, true);
-            else HOPH_FAST(0, true);
+            switch (split) {
+            case 2: HOPH_FAST(2, true); break;
+            case 3: HOPH_FAST(3, true); break;
+            case 4: HOPH_FAST(4, true); break;
+            case 5: HOPH_FAST(5, true); break;
+            case 6: HOPH_FAST(6, true); break;
+            default: HOPH_FAST(0, true); break;
+            }
         } else {
-            if (split == 2) HOPH_FAST(2, false);
-            else if (split == 4) HOPH_FAST(4, false);
-            else HOPH_FAST(0, false);
+            switch (split) {
+            case 2: HOPH_FAST(2, false); break;
+            case 3: HOPH_FAST(3, false); break;
+            case 4: HOPH_FAST(4, false); break;
+            case 5: HOPH_FAST(5, false); break;
+            case 6: HOPH_FAST(6, false); break;
+            default: HOPH_FAST(0, false); break;
+            }
         }
 #undef HOPH_FAST
         return;

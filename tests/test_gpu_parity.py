@@ -157,6 +157,33 @@ def test_multi_group_code_pass_matches_oracle(ra, rb):
         idx.free()
 
 
+@pytest.mark.parametrize("ra,rb,Ts", [(1, 2, [(67, 100), (70, 100), (73, 100), (79, 100), (85, 100)]),
+                                      (2, 1, [(30, 100), (32, 100), (52, 100)]),
+                                      (1, 1, [(49, 100), (46, 100)])])
+def test_first_group_plane_splits_match_oracle(ra, rb, Ts):
+    """The first-group code pass at thresholds whose reject cutoff on differing
+    bins takes each first-phase plane count (2 to 6 planes before the rest of
+    the chain), for JOINT and LITERAL, on large shingle sets with planted
+    near-duplicates: results equal to the oracle's."""
+    _print_case(f"first-group plane splits {ra}:{rb}")
+    w = W.hoph_shingles(n=6_007, n_q=24, seed=41 + ra + 3 * rb, ra=ra, rb=rb)
+    p = params_of(w)
+    sig = gpu_sketch(w, w.collection, p)
+    qsig = gpu_sketch(w, w.queries, p)
+    idx = H.Index(p, sig)
+    sh, qh = to_u32(sig), to_u32(qsig)
+    found = 0
+    for T in Ts:
+        for policy in (H.EMPTY_JOINT, H.EMPTY_LITERAL):
+            oo, oi = oracle_query(w, sh, qh, T, (1, 10_000), policy)
+            found += len(oi)
+            go, gi = gpu_query("hoph", idx, qsig, T, (1, 10_000), policy)
+            assert go.tolist() == oo.tolist(), (T, policy)
+            assert gi.tolist() == oi.tolist(), (T, policy)
+    assert found > 0
+    idx.free()
+
+
 def test_modp32_top_of_range_signatures():
     """Sets whose ids hash to the top of the (a x + b) mod (2^32 + 15) range
     (2^32 - 3 .. 2^32 + 14, the values the sketch's 32-bit view clamps): every
