@@ -643,9 +643,8 @@ def _code_pass_shape(H, p, T, eps, goph=False):
     depth, split = None, 0
     if m_rej0 >= 0 and 8 * m_rej0 >= kp:
         depth = 1
-        dthr = kp - m_rej0
-        split = 2 if 2 * dthr <= kp else (4 if 4 * dthr <= 3 * kp else 0)
-    ops = W_planes * (split + 2) + 1 if split else 10 * W_planes + 1
+        split = _plane_split(kp - m_rej0, kp, W_planes)
+    ops = W_planes * (split + 1) + 1 if split else 9 * W_planes + 1
     rec_bytes = (8 * W_planes + 4) * 4
     return depth, W_planes, split, ops, rec_bytes
 
@@ -804,8 +803,9 @@ def _coarse_model(H, p, T, eps, goph=False):
     (no empty bins); else one group past the first step with a reject cutoff,
     in whole code units.  Kernel and minimum work per pair:
     - one group: the first-group pass compares P1 planes of every pair first
-      (P1 W plane operations, W masks, W popcounts, one compare; P1 from 2 to 6
-      by the expected cost of _plane_split), else all 8 planes (10 W + 1);
+      (P1 W plane operations, the first of them masked by the query's
+      non-empty bins, W popcounts, one compare; P1 from 2 to 6 by the expected
+      cost of _plane_split), else all 8 planes (9 W + 1);
     - two to four groups of 17-32 bins: the linear-bound pass compares P1 planes
       of groups 1..R+1 (R+1 the first step with a reject cutoff; P1 the smallest
       of 2, 3, 4 planes whose chance match rate is at most a third of that
@@ -825,7 +825,7 @@ def _coarse_model(H, p, T, eps, goph=False):
     if m_rej0 >= 0 and 8 * m_rej0 >= kp:
         depth = 1
         split = _plane_split(kp - m_rej0, kp, Wp)
-        ops = Wp * (split + 2) + 1 if split else 10 * Wp + 1
+        ops = Wp * (split + 1) + 1 if split else 9 * Wp + 1
         kernel = "scan_codes_fast_kernel"
     else:
         g1 = next((l + 1 for l, r in enumerate(tabs["rej"]) if r >= 0), None)

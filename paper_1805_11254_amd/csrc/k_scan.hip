@@ -183,8 +183,10 @@ __device__ __forceinline__ int64_t group_rho(uint32_t eq, uint32_t ej, uint32_t 
 // EMPTY; for the first cg groups also the query's code record: the planes of
 // the group's code unit (same word order as the index's: plane p of the unit's
 // bins [32 w, 32 w + 32) at p * W + w; every group of a unit holds the same
-// planes), the group's non-empty mask (bits from 0), the first group's reject
-// threshold and the group's empty count.
+// planes), the group's non-empty mask (bits from 0), the first group's keep
+// threshold on codes (a pair is kept when more than this many of the query's
+// non-empty bins have equal codes: (k' - e) - ScanTab::dthr0[e], negative when
+// the first group rejects nothing) and the group's empty count e.
 __global__ __launch_bounds__(kThreads) void query_masks_kernel(const uint32_t *__restrict__ qsigs, uint32_t n_q_arg,
                                                               const uint64_t *__restrict__ desc, uint32_t k,
                                                               uint32_t kp, uint32_t L, uint64_t *__restrict__ out,
@@ -226,7 +228,7 @@ __global__ __launch_bounds__(kThreads) void query_masks_kernel(const uint32_t *_
             const uint32_t e = (uint32_t)__popcll(m);
             dst[PW + 0] = (uint32_t)nqm;
             dst[PW + 1] = (uint32_t)(nqm >> 32);
-            dst[PW + 2] = (uint32_t)thr.dthr[e];
+            dst[PW + 2] = (uint32_t)((int32_t)(kp - e) - thr.dthr[e]);   // keep iff more agreeing bins
             dst[PW + 3] = e;
             uint32_t lc = 0, lz = 0xFFFFFFFFu, ly = 0xFFFFFFFFu;
             if (g < lin.steps) {
@@ -274,6 +276,22 @@ __device__ __forceinline__ uint32_t code_diff(const uint32_t *P, const uint32_t 
 #pragma unroll
     for (int p = 1; p < (int)kCodeBits; ++p) d = __builtin_amdgcn_bitop3_b32(d, P[p * W + w], Q[p * W + w], 0xF6);
     return d;
+}
+
+// The agreeing-bin mask of the query's non-empty bins over planes [P0, P1),
+// continuing the chain from a; at P0 = 0 the chain starts from the query's
+// non-empty mask m instead.  A bin's bit stays set while each plane so far
+// agrees, so the popcount over all planes counts the query-non-empty bins
+// with equal codes.  One three-input bit operation per plane: 0x82 =
+// m & ~(P ^ Q) for plane 0, 0x90 = a & ~(P ^ Q) after it.
+template <int W, int P0, int P1>
+__device__ __forceinline__ uint32_t code_agree_part(uint32_t a, uint32_t m, const uint32_t *P,
+                                                    const uint32_t *__restrict__ Q, int w) {
+#pragma unroll
+    for (int p = P0; p < P1; ++p)
+        a = p == 0 ? __builtin_amdgcn_bitop3_b32(P[w], Q[w], m, 0x82)
+                   : __builtin_amdgcn_bitop3_b32(a, P[p * W + w], Q[p * W + w], 0x90);
+    return a;
 }
 
 // The differing-bin mask over planes [P0, P1) only, continuing the chain from d
@@ -574,13 +592,15 @@ __global__ __launch_bounds__(64) void scan_codes_deep_kernel(const uint32_t *__r
 // First-group code pass (depth 1, JOINT or LITERAL), TPW tiles of 64 indexed
 // sets per wavefront: each query's record (read with scalar loads, one query
 // ahead) is compared with TPW tiles, so the scalar work of a query is shared
-// by 64 TPW sets.  A pair is kept when its count of differing query-non-empty
-// bins is below the query's threshold (see ScanTab::dthr0).  With P1 > 0 the
-// first P1 planes are compared first, for all TPW tiles: bins that differ
-// there differ in the full code too, so when no lane's partial count is below
-// the threshold the query is done with these tiles (the usual case for pairs
-// far from the threshold), and otherwise the remaining planes continue each
-// tile's chain.  TRI: the self-join's upper-triangle filter.  Lane sets are
+// by 64 TPW sets.  A pair is kept when more of the query's non-empty bins
+// have equal codes than the query's keep threshold (the record's; the same
+// test as a count of differing bins below ScanTab::dthr0), counted as the
+// popcount of a chain of agreeing-bin masks that starts from the query's
+// non-empty mask.  With P1 > 0 the first P1 planes are compared first, for all
+// TPW tiles: bins that differ there differ in the full code too, so when no
+// lane's partial count exceeds the threshold the query is done with these
+// tiles (the usual case for pairs far from the threshold), and otherwise the
+// remaining planes continue each tile's chain.  TRI: the self-join's upper-triangle filter.  Lane sets are
 // combined as 64-bit wave masks (one ballot per tile and test).
 template <int W, int TPW, int P1, bool TRI>
 __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_t *__restrict__ codes,
@@ -646,31 +666,31 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_
             uint64_t lanes[TPW];                                                                   \
             _Pragma("unroll") for (int t = 0; t < TPW; ++t)                                        \
                 lanes[t] = TRI ? vmask[t] & __builtin_amdgcn_ballot_w64(sid[t] > (qq)) : vmask[t]; \
-            uint32_t dd[TPW][W];                                                                   \
+            uint32_t aa[TPW][W];                                                                   \
             bool open = true;                                                                      \
             if constexpr (P1 > 0) {                                                                \
                 uint64_t keep = 0;                                                                 \
                 _Pragma("unroll") for (int t = 0; t < TPW; ++t) {                                  \
-                    uint32_t dn = 0;                                                               \
+                    uint32_t ag = 0;                                                               \
                     _Pragma("unroll") for (int w = 0; w < W; ++w) {                                \
-                        dd[t][w] = code_diff_part<W, 0, P1>(0u, P[t], r, w);                       \
-                        dn += __popc(dd[t][w] & r[PW + w]);                                        \
+                        aa[t][w] = code_agree_part<W, 0, P1>(0u, r[PW + w], P[t], r, w);           \
+                        ag += __popc(aa[t][w]);                                                    \
                     }                                                                              \
-                    keep |= __builtin_amdgcn_ballot_w64((int32_t)dn < (int32_t)r[PW + 2]) & lanes[t];  \
+                    keep |= __builtin_amdgcn_ballot_w64((int32_t)ag > (int32_t)r[PW + 2]) & lanes[t];  \
                 }                                                                                  \
                 open = keep != 0;                                                                  \
             }                                                                                      \
             if (open) {                                                                            \
                 _Pragma("unroll") for (int t = 0; t < TPW; ++t) {                                  \
-                    uint32_t dn = 0;                                                               \
+                    uint32_t ag = 0;                                                               \
                     _Pragma("unroll") for (int w = 0; w < W; ++w) {                                \
-                        const uint32_t d = P1 > 0                                                  \
-                            ? code_diff_part<W, P1, (int)kCodeBits>(dd[t][w], P[t], r, w)          \
-                            : code_diff<W>(P[t], r, w);                                            \
-                        dn += __popc(d & r[PW + w]);                                               \
+                        const uint32_t x = P1 > 0                                                  \
+                            ? code_agree_part<W, P1, (int)kCodeBits>(aa[t][w], 0u, P[t], r, w)     \
+                            : code_agree_part<W, 0, (int)kCodeBits>(0u, r[PW + w], P[t], r, w);    \
+                        ag += __popc(x);                                                           \
                     }                                                                              \
                     const uint64_t bal =                                                           \
-                        __builtin_amdgcn_ballot_w64((int32_t)dn < (int32_t)r[PW + 2]) & lanes[t];   \
+                        __builtin_amdgcn_ballot_w64((int32_t)ag > (int32_t)r[PW + 2]) & lanes[t];   \
                     sb.push(bal, (qq), sid[t], surv, a.surv_cap, counters + 0, lane);              \
                 }                                                                                  \
             }                                                                                      \
