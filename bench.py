@@ -809,9 +809,9 @@ def _coarse_model(H, p, T, eps, goph=False):
     - two to four groups of 17-32 bins: the linear-bound pass compares P1 planes
       of groups 1..R+1 (R+1 the first step with a reject cutoff; P1 the smallest
       of 2, 3, 4 planes whose chance match rate is at most a third of that
-      step's reject fraction) with a plane chain, a mask, a popcount and a
-      24-bit multiply-add per group and two compares, else all 8 planes of
-      every group (11 per group and two compares);
+      step's reject fraction) with a plane chain started from the query's
+      non-empty mask, a popcount and a 24-bit multiply-add per group and two
+      compares, else all 8 planes of every group (10 per group and two compares);
     - otherwise at least the first code unit of every pair (10 W + 1) and its
       weighted state update (an int64 multiply-add and two compares, 6 more).
     Bytes: each set's planes of the units the kernel loads (32 W per unit) per launch."""
@@ -836,7 +836,7 @@ def _coarse_model(H, p, T, eps, goph=False):
             full = sum(tabs["W"][g] * tabs["dmul"][0] * kp for g in range(R + 1))
             tau = tabs["rej"][R] / full
             split = next((s for s in (2, 3, 4) if 3.0 * 2.0 ** -s <= tau), 0)
-            ops = (R + 1) * (split + 3) + 2 if split else depth * 11 + 2
+            ops = (R + 1) * (split + 2) + 2 if split else depth * 10 + 2
         else:
             split = 0
             ops = 10 * Wp + 1 + 6

@@ -154,10 +154,14 @@ __host__ __device__ inline uint32_t code_rec_words(uint32_t kp) { return code_wo
 // A step's test on the exact state then becomes a test on sum_g C_g dn_g,
 // linear in the counts: reject when it reaches Z_s = sum_g C_g (k' - e_g) -
 // rej_s, keep ("maybe": an accept cutoff may be reached) when it is at most
-// Y_s = sum_g C_g (k' - e_g) - acc_s.  Per query the record of group g holds
-// c_g = floor(C_g / 2^shift), z_g = ceil(Z_g / 2^shift) (UINT32_MAX: no reject
-// cutoff) and y_g = floor(Y_g / 2^shift) (-1: no accept cutoff reachable); the
-// rounding keeps both tests on the safe side (fewer rejects, more keeps).
+// Y_s = sum_g C_g (k' - e_g) - acc_s.  With c_g = floor(C_g / 2^shift),
+// z_s = ceil(Z_s / 2^shift) and y_s = floor(Y_s / 2^shift) the tests on
+// st_s = sum_{g <= s} c_g dn_g (st_s >= z_s rejects, st_s <= y_s keeps) stay
+// on the safe side (fewer rejects, more keeps).  The kernels count agreeing
+// bins, st'_s = sum_{g <= s} c_g ((k' - e_g) - dn_g) = S_s - st_s with
+// S_s = sum_{g <= s} c_g (k' - e_g) < 2^31, so per query the record of group g
+// holds c_g, z'_g = S_g - z_g (-1: never rejects) and y'_g = S_g - y_g
+// (INT32_MAX: no accept cutoff reachable): st' <= z' rejects, st' >= y' keeps.
 constexpr uint32_t kLinMaxSteps = 4;
 struct LinTab {
     int64_t W[kLinMaxSteps], acc[kLinMaxSteps], rej[kLinMaxSteps];

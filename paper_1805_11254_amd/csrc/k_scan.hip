@@ -230,10 +230,10 @@ __global__ __launch_bounds__(kThreads) void query_masks_kernel(const uint32_t *_
             dst[PW + 1] = (uint32_t)(nqm >> 32);
             dst[PW + 2] = (uint32_t)((int32_t)(kp - e) - thr.dthr[e]);   // keep iff more agreeing bins
             dst[PW + 3] = e;
-            uint32_t lc = 0, lz = 0xFFFFFFFFu, ly = 0xFFFFFFFFu;
+            uint32_t lc = 0, lz = 0xFFFFFFFFu, ly = 0x7FFFFFFFu;
             if (g < lin.steps) {
                 // linear bound of step g (see LinTab): sums over this query's groups 0..g
-                int64_t sum_ck = 0, cg_here = 0;
+                int64_t sum_ck = 0, sum_cn = 0;
                 for (uint32_t h = 0; h <= g; ++h) {
                     uint32_t eh = 0;
                     const uint32_t *wh = qsigs + q * k + h * kp;
@@ -247,17 +247,20 @@ __global__ __launch_bounds__(kThreads) void query_masks_kernel(const uint32_t *_
                         ck = lin.W[h] * lin.lambda;
                     }
                     sum_ck += ck;
-                    if (h == g) cg_here = c;
+                    const int64_t ch = c >> lin.shift;
+                    sum_cn += ch * (int64_t)(kp - eh);
+                    if (h == g) lc = (uint32_t)ch;
                 }
+                // the tests on st = sum c_h dn_h, restated on the agreeing counts
+                // st' = sum c_h (k' - e_h - dn_h) = sum_cn - st (below 2^31)
                 const int64_t one = (int64_t)1 << lin.shift;
-                lc = (uint32_t)(cg_here >> lin.shift);
                 if (lin.rej[g] >= 0) {
                     const int64_t Z = sum_ck - lin.rej[g];
-                    const int64_t zc = Z <= 0 ? 0 : (Z + one - 1) >> lin.shift;
-                    lz = zc >= (int64_t)0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)zc;
+                    const int64_t zc = Z <= 0 ? 0 : (Z + one - 1) >> lin.shift;   // reject: st >= zc
+                    lz = zc <= sum_cn ? (uint32_t)(sum_cn - zc) : 0xFFFFFFFFu;
                 }
                 const int64_t Y = sum_ck - lin.acc[g];
-                if (Y >= 0) ly = (uint32_t)min<int64_t>(Y >> lin.shift, 0x7FFFFFFFll);
+                if (Y >= 0) ly = (uint32_t)(int32_t)(sum_cn - min<int64_t>(Y >> lin.shift, sum_cn + 0x7FFFFFFFll));
             }
             dst[PW + 4] = lc;
             dst[PW + 5] = lz;
@@ -598,9 +601,11 @@ __global__ __launch_bounds__(64) void scan_codes_deep_kernel(const uint32_t *__r
 // popcount of a chain of agreeing-bin masks that starts from the query's
 // non-empty mask.  With P1 > 0 the first P1 planes are compared first, for all
 // TPW tiles: bins that differ there differ in the full code too, so when no
-// lane's partial count exceeds the threshold the query is done with these
-// tiles (the usual case for pairs far from the threshold), and otherwise the
-// remaining planes continue each tile's chain.  TRI: the self-join's upper-triangle filter.  Lane sets are
+// lane's largest partial count over the tiles exceeds the threshold the query
+// is done with these tiles (the usual case for pairs far from the threshold),
+// and otherwise the remaining planes continue each tile's chain and the pairs
+// are tested one by one (lanes past the last set or, in the self-join, below
+// the diagonal only cost a second phase that keeps none of them).  TRI: the self-join's upper-triangle filter.  Lane sets are
 // combined as 64-bit wave masks (one ballot per tile and test).
 template <int W, int TPW, int P1, bool TRI>
 __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_t *__restrict__ codes,
@@ -663,24 +668,24 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_
 // loads stay scalar)
 #define HOPH_CODE_QUERY_T(r, qq)                                                                   \
         {                                                                                          \
-            uint64_t lanes[TPW];                                                                   \
-            _Pragma("unroll") for (int t = 0; t < TPW; ++t)                                        \
-                lanes[t] = TRI ? vmask[t] & __builtin_amdgcn_ballot_w64(sid[t] > (qq)) : vmask[t]; \
             uint32_t aa[TPW][W];                                                                   \
             bool open = true;                                                                      \
             if constexpr (P1 > 0) {                                                                \
-                uint64_t keep = 0;                                                                 \
+                int32_t best = 0;                                                                  \
                 _Pragma("unroll") for (int t = 0; t < TPW; ++t) {                                  \
                     uint32_t ag = 0;                                                               \
                     _Pragma("unroll") for (int w = 0; w < W; ++w) {                                \
                         aa[t][w] = code_agree_part<W, 0, P1>(0u, r[PW + w], P[t], r, w);           \
                         ag += __popc(aa[t][w]);                                                    \
                     }                                                                              \
-                    keep |= __builtin_amdgcn_ballot_w64((int32_t)ag > (int32_t)r[PW + 2]) & lanes[t];  \
+                    best = max(best, (int32_t)ag);                                                 \
                 }                                                                                  \
-                open = keep != 0;                                                                  \
+                open = __builtin_amdgcn_ballot_w64(best > (int32_t)r[PW + 2]) != 0;                \
             }                                                                                      \
             if (open) {                                                                            \
+                uint64_t lanes[TPW];                                                               \
+                _Pragma("unroll") for (int t = 0; t < TPW; ++t)                                    \
+                    lanes[t] = TRI ? vmask[t] & __builtin_amdgcn_ballot_w64(sid[t] > (qq)) : vmask[t]; \
                 _Pragma("unroll") for (int t = 0; t < TPW; ++t) {                                  \
                     uint32_t ag = 0;                                                               \
                     _Pragma("unroll") for (int w = 0; w < W; ++w) {                                \
@@ -712,13 +717,19 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_
 // Multi-group code pass with the linear bound of LinTab: D groups (one per
 // code unit, k' <= 32 bins, one plane word), TPW tiles of 64 indexed sets per
 // wavefront sharing each query's scalar work (its record: planes, non-empty
-// mask and the words c, z, y of every group), one set per lane.  The state of a
-// pair after step s is st_s = sum_{g <= s} c_g dn_g, dn_g the query-non-empty
-// bins of group g whose codes differ; st_s <= y_s keeps the pair ("maybe": an
-// accept cutoff may be reached), else st_s >= z_s rejects it.
+// mask and the words c, z', y' of every group), one set per lane.  The state
+// of a pair after step s is st_s = sum_{g <= s} c_g dn_g, dn_g the
+// query-non-empty bins of group g whose codes differ; st_s <= y_s keeps the
+// pair ("maybe": an accept cutoff may be reached), else st_s >= z_s rejects
+// it.  The kernel counts agreeing bins instead (ag_g = (k' - e_g) - dn_g, the
+// popcount of an agreeing-bin chain started from the query's non-empty mask,
+// see code_agree_part) and tests st'_s = sum_{g <= s} c_g ag_g against the
+// record's z'_s and y'_s: st' <= z' rejects (z' < 0: never), st' >= y' keeps
+// (y' = INT32_MAX: never), the same tests as on st.
 // Phase 1 (P1 > 0) compares the first P1 planes of groups 0..R, R the first
 // step with a reject cutoff: a bin that differs there differs in the full
-// code, so the partial state never exceeds the full one.  A lane whose partial
+// code, so the partial state never exceeds the full one (the partial agreeing
+// counts never fall below the full ones).  A lane whose partial
 // state is rejected at step R and kept at no step up to R is rejected by the
 // full test too (the steps before R cannot reject), so when no lane of the
 // wavefront is kept the query is done with these tiles.  Phase 2 continues the
@@ -781,17 +792,17 @@ __global__ __launch_bounds__(kThreads) void scan_codes_lin_kernel(const uint32_t
         }
         for (uint32_t q = qa; q < qb; ++q) {
             const uint32_t *rec = qcodes + (uint64_t)q * rstride;
-            uint32_t nq[D], c[D], z[D];
-            int32_t y[D];
+            uint32_t nq[D], c[D];
+            int32_t z[D], y[D];
 #pragma unroll
             for (int g = 0; g < D; ++g) {
                 nq[g] = rec[g * RS + PW];
                 c[g] = rec[g * RS + PW + 4];
-                z[g] = rec[g * RS + PW + 5];
+                z[g] = (int32_t)rec[g * RS + PW + 5];
                 y[g] = (int32_t)rec[g * RS + PW + 6];
             }
-            const uint32_t zR = rec[R * RS + PW + 5];        // the reject cutoff of step R
-            uint32_t dd[TPW][D];
+            const int32_t zR = (int32_t)rec[R * RS + PW + 5];   // the reject cutoff of step R
+            uint32_t aa[TPW][D];
             bool open = true;
             if constexpr (P1 > 0) {
                 uint64_t keep = 0;
@@ -802,12 +813,12 @@ __global__ __launch_bounds__(kThreads) void scan_codes_lin_kernel(const uint32_t
 #pragma unroll
                     for (int g = 0; g < D; ++g) {
                         if ((uint32_t)g <= R) {
-                            dd[t][g] = code_diff_part<1, 0, P1>(0u, P[t][g], rec + g * RS, 0);
-                            st += __umul24(c[g], (uint32_t)__popc(dd[t][g] & nq[g]));
-                            mb = mb || (int32_t)st <= y[g];
+                            aa[t][g] = code_agree_part<1, 0, P1>(0u, nq[g], P[t][g], rec + g * RS, 0);
+                            st = __umul24(c[g], (uint32_t)__popc(aa[t][g])) + st;
+                            mb = mb || (int32_t)st >= y[g];
                         }
                     }
-                    keep |= __builtin_amdgcn_ballot_w64(mb || st < zR) & vmask[t];
+                    keep |= __builtin_amdgcn_ballot_w64(mb || (int32_t)st > zR) & vmask[t];
                 }
                 open = keep != 0;
             }
@@ -819,15 +830,16 @@ __global__ __launch_bounds__(kThreads) void scan_codes_lin_kernel(const uint32_t
 #pragma unroll
                     for (int g = 0; g < D; ++g) {
                         if ((uint32_t)g > R && !__any(und)) break;
-                        const uint32_t d = (P1 > 0 && (uint32_t)g <= R)
-                                               ? code_diff_part<1, P1, (int)kCodeBits>(dd[t][g], P[t][g], rec + g * RS, 0)
-                                               : code_diff<1>(P[t][g], rec + g * RS, 0);
-                        st += __umul24(c[g], (uint32_t)__popc(d & nq[g]));
+                        const uint32_t x =
+                            (P1 > 0 && (uint32_t)g <= R)
+                                ? code_agree_part<1, P1, (int)kCodeBits>(aa[t][g], 0u, P[t][g], rec + g * RS, 0)
+                                : code_agree_part<1, 0, (int)kCodeBits>(0u, nq[g], P[t][g], rec + g * RS, 0);
+                        st = __umul24(c[g], (uint32_t)__popc(x)) + st;
                         if (und) {
-                            if ((int32_t)st <= y[g]) {
+                            if ((int32_t)st >= y[g]) {
                                 mb = true;
                                 und = false;
-                            } else if (st >= z[g]) {
+                            } else if ((int32_t)st <= z[g]) {
                                 und = false;
                             }
                         }
@@ -908,10 +920,10 @@ __global__ __launch_bounds__(kThreads) void scan_codes_lin1_kernel(const uint32_
                 c[g] = rec[g * RS + PW + 4];
                 y[g] = (int32_t)rec[g * RS + PW + 6];
             }
-            // keep at step R when st < zk: below the reject cutoff, or at or below
-            // the maybe cutoff (y_R + 1 > z_R only when rounding meets them)
-            const uint32_t zR = rec[R * RS + PW + 5];
-            const uint32_t zk = (y[R] >= 0 && (uint32_t)y[R] + 1u > zR) ? (uint32_t)y[R] + 1u : zR;
+            // keep at step R when st' > zk: above the reject cutoff, or at or above
+            // the maybe cutoff (y'_R - 1 < z'_R only when rounding meets them)
+            const int32_t zR = (int32_t)rec[R * RS + PW + 5];
+            const int32_t zk = y[R] - 1 < zR ? y[R] - 1 : zR;
             uint32_t tiles_kept = 0;         // bit t: a lane of tile t is kept
 #pragma unroll
             for (int t = 0; t < TPW; ++t) {
@@ -919,21 +931,21 @@ __global__ __launch_bounds__(kThreads) void scan_codes_lin1_kernel(const uint32_
                 bool mb = false;
 #pragma unroll
                 for (int g = 0; g < G1; ++g) {
-                    const uint32_t d = code_diff_part<1, 0, P1>(0u, P[t][g], rec + g * RS, 0);
-                    st += __umul24(c[g], (uint32_t)__popc(d & nq[g]));
-                    if (g < R) mb = mb || (int32_t)st <= y[g];
+                    const uint32_t x = code_agree_part<1, 0, P1>(0u, nq[g], P[t][g], rec + g * RS, 0);
+                    st = __umul24(c[g], (uint32_t)__popc(x)) + st;
+                    if (g < R) mb = mb || (int32_t)st >= y[g];
                 }
-                tiles_kept |= (__builtin_amdgcn_ballot_w64(mb || st < zk) & vmask[t]) ? (1u << t) : 0u;
+                tiles_kept |= (__builtin_amdgcn_ballot_w64(mb || (int32_t)st > zk) & vmask[t]) ? (1u << t) : 0u;
             }
             if (tiles_kept == 0) continue;
             // phase 2 (rare): full planes of every group, steps in order
-            uint32_t nqf[D], cf[D], zf[D];
-            int32_t yf[D];
+            uint32_t nqf[D], cf[D];
+            int32_t zf[D], yf[D];
 #pragma unroll
             for (int g = 0; g < D; ++g) {
                 nqf[g] = rec[g * RS + PW];
                 cf[g] = rec[g * RS + PW + 4];
-                zf[g] = rec[g * RS + PW + 5];
+                zf[g] = (int32_t)rec[g * RS + PW + 5];
                 yf[g] = (int32_t)rec[g * RS + PW + 6];
             }
             // one tile at a time (not unrolled: the full planes of one tile are live at once)
@@ -951,13 +963,13 @@ __global__ __launch_bounds__(kThreads) void scan_codes_lin1_kernel(const uint32_
                         reinterpret_cast<const uint4 *>(codes + (((uint64_t)g * ctiles + tile) * 64 + lane) * PW);
                     const uint4 v0 = src[0], v1 = src[1];
                     const uint32_t Pf[PW] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-                    const uint32_t d = code_diff<1>(Pf, rec + g * RS, 0);
-                    st += __umul24(cf[g], (uint32_t)__popc(d & nqf[g]));
+                    const uint32_t x = code_agree_part<1, 0, (int)kCodeBits>(0u, nqf[g], Pf, rec + g * RS, 0);
+                    st = __umul24(cf[g], (uint32_t)__popc(x)) + st;
                     if (und) {
-                        if ((int32_t)st <= yf[g]) {
+                        if ((int32_t)st >= yf[g]) {
                             mb = true;
                             und = false;
-                        } else if (st >= zf[g]) {
+                        } else if ((int32_t)st <= zf[g]) {
                             und = false;
                         }
                     }
