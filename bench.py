@@ -983,6 +983,7 @@ def run_c3(args, H, W, np, torch):
                 outs[(r, T)] = H.query_hoph(idx[r], qsig[r], T=T, eps=w.eps, capacity=cap.get((r, T)))
                 if rec is not None:
                     rec[(r, T)] = idx[r].last_query_ms()
+                    rec[(r, T, "n")] = idx[r].last_query_counts()
                 if e: e[3 + ti].record(stream)
             if rec is not None:
                 rec[(r, "append")] = idx[r].last_append_ms()
@@ -1039,7 +1040,9 @@ def run_c3(args, H, W, np, torch):
                 m, ms=co, bound="alu", achieved=ops / (co * 1e-3) / 1e12, peak=ALU_PEAK_OPS / 1e12,
                 unit="Tops/s (32-bit VALU lane-ops)", algorithmic_ops=ops, hbm_gbs=byts / (co * 1e-3) / 1e9,
                 pairs_per_s=Q * N / (co * 1e-3))
-            kernels[f"scan_fine[{tg},T={_ttag(T)}]"] = {"kernel": "scan_fine_kernel", "ms": fi}
+            kernels[f"scan_fine[{tg},T={_ttag(T)}]"] = {"kernel": "scan_fine_kernel", "ms": fi,
+                                                          "survivors": rec_mean((r, T, "n"), 0),
+                                                          "accepted": rec_mean((r, T, "n"), 1)}
             kernels[f"sort_and_csr[{tg},T={_ttag(T)}]"] = {"ms": so}
             phase[f"query[{tg},T={_ttag(T)}]"] = ev_ms(ri, 2 + ti, 3 + ti)
     for v in kernels.values():
@@ -1051,7 +1054,8 @@ def run_c3(args, H, W, np, torch):
     longest_unmodelled = max((v["ms"], n) for n, v in kernels.items() if "achieved" not in v)
     roofline = {"kernel": dom_name, "bound": dom["bound"], "achieved": dom["achieved"], "peak": dom["peak"],
                 "unit": dom["unit"], "frac": dom["frac"], "traffic": None,
-                "ms": dom["ms"], "longest_other_kernel": {"name": longest_unmodelled[1], "ms": longest_unmodelled[0]}}
+                "ms": dom["ms"],
+                "longest_unmodelled_kernel": {"name": longest_unmodelled[1], "ms": longest_unmodelled[0]}}
     if dom["bound"] == "hbm":
         roofline["algorithmic_bytes"] = dom["algorithmic_bytes"]
     else:

@@ -184,6 +184,13 @@ hoph_status hoph_index_reset(hoph_index *index);
    (query_oph_full reports its scan in ms[0].) */
 hoph_status hoph_query_timing(const hoph_index *index, float ms[3]);
 
+/* hoph_query_counts -- pair counts of the last query_goph / query_hoph call on
+   this index (host array): counts[0] the pairs the coarse pass kept for the
+   per-survivor pass (all of them, when the batch was redone in parts),
+   counts[1] the accepted pairs (Alg. 1 / Alg. 2 outcomes).  Zeros before any
+   query and after a query with no queries or no sets. */
+hoph_status hoph_query_counts(const hoph_index *index, uint64_t counts[2]);
+
 /* hoph_scan_timing -- a measurement hook: the coarse pass of query_goph /
    query_hoph (by the index layout; Alg. 1 / Alg. 2 up to the coarse depth) for
    the n_q query signatures d_qsigs, timed alone.  The per-query records are

@@ -95,6 +95,7 @@ SIGNATURES = {
     "hoph_index_reset": (C.c_int, [vp]),
     "hoph_index_code_planes": (C.c_int, [vp, vp, u64, C.POINTER(u64), vp]),
     "hoph_query_timing": (C.c_int, [vp, C.POINTER(C.c_float)]),
+    "hoph_query_counts": (C.c_int, [vp, C.POINTER(C.c_uint64)]),
     "hoph_scan_timing": (C.c_int, [vp, vp, u32, C.POINTER(QueryParamsC), u32, vp, u64, C.POINTER(C.c_float), vp]),
     "hoph_index_free": (None, [vp]),
     "query_goph": (C.c_int, [vp, vp, u32, C.POINTER(QueryParamsC), C.POINTER(ResultsC), vp]),
@@ -317,6 +318,12 @@ class Index:
         ms = (C.c_float * 3)()
         _check(lib().hoph_query_timing(self._h, ms))
         return tuple(ms)
+
+    def last_query_counts(self):
+        """(coarse-pass survivors, accepted pairs) of the last query."""
+        c = (C.c_uint64 * 2)()
+        _check(lib().hoph_query_counts(self._h, c))
+        return c[0], c[1]
 
     def free(self):
         if self._h:

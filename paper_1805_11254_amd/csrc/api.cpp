@@ -325,6 +325,8 @@ hoph_status run_query_impl(const hoph_index *cidx, Workspace *ws_in, const uint3
         const uint64_t surv = ws.h_counters[0], acc = ws.h_counters[1], flags = ws.h_counters[3];
         if (surv <= ws.surv_cap && acc <= ws.keys_cap && acc <= res->capacity && (flags & 3ull) == 0) {
             res->needed = acc;
+            ws.last_counts[0] = surv;
+            ws.last_counts[1] = acc;
             record_timing();
             return HOPH_OK;
         }
@@ -333,7 +335,7 @@ hoph_status run_query_impl(const hoph_index *cidx, Workspace *ws_in, const uint3
         if (surv > ws.surv_cap && qp->coarse_depth == 0 && a.depth < maxd) a.depth = maxd;
     }
 
-    uint64_t accepted = 0;
+    uint64_t accepted = 0, survivors = 0;
     float pass_ms[2] = {0, 0};
     for (int attempt = 0; attempt < 2; ++attempt) {
         a.surv = ws.surv;
@@ -352,6 +354,7 @@ hoph_status run_query_impl(const hoph_index *cidx, Workspace *ws_in, const uint3
                 (void)hipEventElapsedTime(&pass_ms[0], ws.ev[0], ws.ev[1]);
                 (void)hipEventElapsedTime(&pass_ms[1], ws.ev[1], ws.ev[2]);
             }
+            survivors = ws.h_counters[0];
             if (ws.h_counters[0] > ws.surv_cap) {
                 const uint64_t seen = ws.h_counters[0];
                 HOPH_HIP(launch_fill_u64(ws.counters, 2, 0, s), "fill counters");
@@ -399,6 +402,8 @@ hoph_status run_query_impl(const hoph_index *cidx, Workspace *ws_in, const uint3
     if (st) return st;
     if (timed && timed_ev) HOPH_HIP(hipEventRecord(ws.ev[3], s), "hipEventRecord");
     HOPH_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    ws.last_counts[0] = survivors;
+    ws.last_counts[1] = accepted;
     ws.last_ms[0] = ws.last_ms[1] = ws.last_ms[2] = 0.f;
     if (timed && timed_ev) {
         ws.last_ms[0] = pass_ms[0];
@@ -617,6 +622,16 @@ hoph_status hoph_query_timing(const hoph_index *idx, float ms[3]) {
     hoph_index *m = const_cast<hoph_index *>(idx);
     std::lock_guard<std::mutex> lk(m->mu);
     for (int i = 0; i < 3; ++i) ms[i] = m->ws.last_ms[i];
+    return HOPH_OK;
+}
+
+hoph_status hoph_query_counts(const hoph_index *idx, uint64_t counts[2]) {
+    g_last_error.clear();
+    if (!idx || !counts) return fail(HOPH_E_INVAL, "NULL argument");
+    hoph_index *m = const_cast<hoph_index *>(idx);
+    std::lock_guard<std::mutex> lk(m->mu);
+    counts[0] = m->ws.last_counts[0];
+    counts[1] = m->ws.last_counts[1];
     return HOPH_OK;
 }
 

@@ -924,6 +924,26 @@ __global__ __launch_bounds__(kThreads) void scan_codes_lin1_kernel(const uint32_
             // the maybe cutoff (y'_R - 1 < z'_R only when rounding meets them)
             const int32_t zR = (int32_t)rec[R * RS + PW + 5];
             const int32_t zk = y[R] - 1 < zR ? y[R] - 1 : zR;
+            // phase 1: the largest partial state of each step over the tiles (the
+            // keep tests are thresholds on them), then one test per query
+            int32_t top[G1];
+#pragma unroll
+            for (int g = 0; g < G1; ++g) top[g] = 0;
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                uint32_t st = 0;
+#pragma unroll
+                for (int g = 0; g < G1; ++g) {
+                    const uint32_t x = code_agree_part<1, 0, P1>(0u, nq[g], P[t][g], rec + g * RS, 0);
+                    st = __umul24(c[g], (uint32_t)__popc(x)) + st;
+                    top[g] = max(top[g], (int32_t)st);
+                }
+            }
+            bool any = top[R] > zk;
+#pragma unroll
+            for (int g = 0; g < R; ++g) any = any || top[g] >= y[g];
+            if (!__builtin_amdgcn_ballot_w64(any)) continue;
+            // some lane is kept (rare): which tiles
             uint32_t tiles_kept = 0;         // bit t: a lane of tile t is kept
 #pragma unroll
             for (int t = 0; t < TPW; ++t) {
@@ -1106,6 +1126,13 @@ __global__ __launch_bounds__(kThreads) void scan_coarse_kernel(const uint32_t *_
     }
 }
 
+// Per-survivor pass (Alg. 1 / Alg. 2 from the group the coarse pass stopped
+// at): one wavefront per surviving pair, P = 64 / k' groups side by side across
+// the lanes of one load and R loads in flight, the exact weighted state
+// updated group by group until an accept or reject cutoff (or the last group).
+// Accepted keys wait in the wavefront's LDS buffer and are written in batches:
+// a slot reservation per pair on the one accepted-pairs counter would queue
+// every wavefront at that counter.
 __global__ __launch_bounds__(kThreads) void scan_fine_kernel(const uint32_t *__restrict__ slab,
                                                             const uint32_t *__restrict__ qsigs,
                                                             const Survivor *__restrict__ surv,
@@ -1113,12 +1140,16 @@ __global__ __launch_bounds__(kThreads) void scan_fine_kernel(const uint32_t *__r
                                                             unsigned long long *__restrict__ counters,
                                                             const CoarseArgs a, const ScanTab tab) {
     __shared__ int64_t s_dmul[HOPH_MAX_KGROUP + 1];
+    __shared__ uint64_t s_keys[kWaves][64];      // accepted keys of each wavefront, not yet written
+    __shared__ uint32_t s_nk[kWaves];
+    __shared__ unsigned long long s_base;
     for (uint32_t i = threadIdx.x; i <= tab.kp; i += kThreads) s_dmul[i] = tab.dmul[i];
     __syncthreads();
-    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t lane = threadIdx.x & 63, wib = wave_id_in_block();
     const uint64_t nw = (uint64_t)gridDim.x * kWaves;
     const uint64_t n = min((uint64_t)counters[0], a.surv_cap);
     const uint32_t kp = a.kp;
+    uint32_t nk = 0;                              // keys in s_keys[wib] (wave-uniform)
     // P groups side by side across the lanes of one load (lane = c k' + bin),
     // R loads per step: P R groups are read at once (independent loads in
     // flight), then decided in order; reads past the deciding group are discarded
@@ -1167,11 +1198,35 @@ __global__ __launch_bounds__(kThreads) void scan_fine_kernel(const uint32_t *__r
                 }
             }
         }
-        if (accept && lane == 0) {
-            const uint64_t slot = atomicAdd(counters + 1, 1ull);
-            if (slot < a.keys_cap) keys[slot] = ((uint64_t)sv.q << 32) | s;
+        if (accept) {                             // wave-uniform
+            if (nk == 64) {                       // a full buffer: one reservation for 64 keys
+                wave_lds_fence();
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(counters + 1, 64ull);
+                base = __shfl(base, 0);
+                if (base + lane < a.keys_cap) keys[base + lane] = s_keys[wib][lane];
+                wave_lds_fence();
+                nk = 0;
+            }
+            if (lane == 0) s_keys[wib][nk] = ((uint64_t)sv.q << 32) | s;
+            ++nk;
         }
     }
+    // the rest: one reservation per workgroup (a counter that every accepted
+    // pair of the pass bumps by one serialises at its memory channel)
+    wave_lds_fence();
+    if (lane == 0) s_nk[wib] = nk;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long total = 0;
+        for (uint32_t v = 0; v < kWaves; ++v) total += s_nk[v];
+        s_base = total ? atomicAdd(counters + 1, total) : 0ull;
+    }
+    __syncthreads();
+    unsigned long long off = s_base;
+    for (uint32_t v = 0; v < wib; ++v) off += s_nk[v];
+    for (uint32_t j = lane; j < nk; j += 64)
+        if (off + j < a.keys_cap) keys[off + j] = s_keys[wib][j];
 }
 
 // Full-signature estimate of pairs (query row q, set id s), one wavefront per

@@ -67,6 +67,7 @@ struct Workspace {
     hipEvent_t aev[3] = {nullptr, nullptr, nullptr};   // around the last append of sets
     bool aev_recorded = false;
     float last_ms[3] = {0, 0, 0};
+    uint64_t last_counts[2] = {0, 0};   // survivors of the coarse pass, accepted pairs
     void release() {
         if (fixed) return;                 // a view: nothing of its own to free
         for (auto &e : ev)

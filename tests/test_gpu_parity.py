@@ -180,6 +180,8 @@ def test_first_group_plane_splits_match_oracle(ra, rb, Ts):
             go, gi = gpu_query("hoph", idx, qsig, T, (1, 10_000), policy)
             assert go.tolist() == oo.tolist(), (T, policy)
             assert gi.tolist() == oi.tolist(), (T, policy)
+            surv, acc = idx.last_query_counts()
+            assert acc == len(oi) and surv >= acc, (T, policy, surv, acc)
     assert found > 0
     idx.free()
 
