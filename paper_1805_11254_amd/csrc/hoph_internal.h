@@ -324,12 +324,14 @@ __host__ __device__ inline void locate_narrow(uint32_t v, const uint8_t *lut, ui
 }
 
 // Log-domain cells of a narrow permuted range, for regions that shrink
-// geometrically towards the top (a:b HOPH): with u = max(R - 1 - v, 1), a cell
-// is the position e of the leading one of u and the four bits after it,
-// cell = 16 e + m (at most 512 cells, non-increasing in v).  When no cell holds two
-// region boundaries, a cell's first region and its one inner boundary give the
-// region of v with one comparison.
-constexpr uint32_t kLogCells = 512;     // every u < 2^32
+// geometrically towards the top (a:b HOPH): with u = max((R - 1 - v) >> 8, 1),
+// a cell is the position e of the leading one of u and the four bits after it,
+// cell = 16 e + m (at most 384 cells, non-increasing in v; every v within 511
+// of the top shares cell 0).  When no cell holds two region boundaries, a
+// cell's first region and its one inner boundary give the region of v with
+// one comparison.  On the device the cell is read off the bits of u converted
+// to f32 (exponent and the four leading mantissa bits; exact, u < 2^24).
+constexpr uint32_t kLogCells = 384;
 
 __host__ __device__ inline uint32_t clz32(uint32_t u) {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -340,10 +342,14 @@ __host__ __device__ inline uint32_t clz32(uint32_t u) {
 }
 
 __host__ __device__ inline uint32_t log_cell(uint32_t v, uint32_t R1) {
-    uint32_t u = R1 - v;
+    uint32_t u = (R1 - v) >> 8;
     u = u > 1u ? u : 1u;
+#if defined(__HIP_DEVICE_COMPILE__)
+    return (__float_as_uint((float)u) >> 19) - 127u * 16u;
+#else
     const uint32_t lz = clz32(u);
     return (31u - lz) * 16u + ((u << lz) >> 27 & 15u);
+#endif
 }
 
 // Cell table entry c: {first region of the cell, start of the next region if

@@ -108,6 +108,7 @@ struct Tables {
     const uint32_t *rstart, *rmag;           // narrow: region starts (n_regions + 1), 32-bit reciprocals
     const uint8_t *lut;
     const uint32_t (*cells)[2];              // log cells: {first region, inner boundary}
+    const unsigned char *cells_f;            // the same table, 8 (127 * 16) bytes early (see cell_entry)
     const uint32_t (*regs)[2];               // log cells: {region start, 32-bit reciprocal}
     const uint4 *pow2;                       // power-of-two regions, by leading-zero count
 };
@@ -150,6 +151,7 @@ __device__ Tables<HASH> build_tables(const SketchDesc &d, unsigned char *smem, c
             log_cell_entry(c, narrow_r1(d.R) + 1u, d.reg_start, nr, cl[c][0], cl[c][1]);
         t.regs = rg;
         t.cells = cl;
+        t.cells_f = reinterpret_cast<const unsigned char *>(cl) - 8u * 127u * 16u;
     }
     if constexpr (LOC == LOC_REGION) {
         if constexpr (kNarrow<HASH>) {
@@ -178,6 +180,30 @@ __device__ Tables<HASH> build_tables(const SketchDesc &d, unsigned char *smem, c
     return t;
 }
 
+// The cell table entry of v (log_cell): the f32 bits of u = max((R1 - v) >> 8, 1)
+// hold 16 (e + 127) + m above bit 19, so the entry's byte offset is bits 16 and
+// up, less 8 (127 * 16), which cells_f has taken off already.
+template <uint32_t HASH>
+__device__ __forceinline__ uint2 cell_entry(uint32_t v, uint32_t R1, const Tables<HASH> &t) {
+    uint32_t u = (R1 - v) >> 8;
+    u = u > 1u ? u : 1u;
+    return *reinterpret_cast<const uint2 *>(t.cells_f + ((__float_as_uint((float)u) >> 16) & ~7u));
+}
+
+// locate_log with the cell entry read as above.
+template <uint32_t HASH>
+__device__ __forceinline__ void locate_log_f(uint32_t v, uint32_t R1, const Tables<HASH> &t, uint32_t nb,
+                                             uint32_t &bin, uint32_t &start) {
+    const uint2 e = cell_entry<HASH>(v, R1, t);
+    const uint32_t r = e.x + (v >= e.y ? 1u : 0u);
+    const uint32_t y = v - t.regs[r][0];
+    const uint32_t b = mul_u24(r, nb) + (uint32_t)(((uint64_t)y * t.regs[r][1]) >> 32);   // r < 64, nb <= 4096
+    const uint32_t s0 = t.start[b], s1 = t.start[b + 1];
+    const bool up = v >= s1;
+    bin = b + (up ? 1u : 0u);
+    start = up ? s1 : s0;
+}
+
 // Bin of a narrow permuted value (view, low; see permute_narrow) and its
 // offset from the bin start.
 template <uint32_t HASH, int LOC>
@@ -200,7 +226,7 @@ __device__ __forceinline__ void bin_of_narrow(uint32_t view, uint32_t low, const
             b = e + (up ? 1u : 0u);
             start = up ? s1 : s0;
         } else if constexpr (LOC == LOC_LOG) {
-            locate_log(view, narrow_r1(d.R), t.cells, t.regs, d.nb, t.start, b, start);
+            locate_log_f(view, narrow_r1(d.R), t, d.nb, b, start);
         } else {
             locate_narrow(view, t.lut, d.lut_shift, t.rstart, t.rmag, d.n_regions, d.nb, t.start, b, start);
         }
