@@ -643,7 +643,7 @@ def _code_pass_shape(H, p, T, eps, goph=False):
     depth, split = None, 0
     if m_rej0 >= 0 and 8 * m_rej0 >= kp:
         depth = 1
-        split = _plane_split(kp - m_rej0, kp, W_planes)
+        split = _plane_split(kp - m_rej0, kp, W_planes)[0]
     ops = W_planes * (split + 1) + 1 if split else 9 * W_planes + 1
     rec_bytes = (8 * W_planes + 4) * 4
     return depth, W_planes, split, ops, rec_bytes
@@ -776,22 +776,32 @@ def _code_units(k, kp, goph):
     return pk, cu, cu * pk
 
 
-def _plane_split(dthr, kp, Wp):
-    """Phase-1 planes of the first-group pass, as the library picks them: the
-    least expected lane-ops per pair, W p + 3 for phase 1 plus W (8 - p) + 2
-    when any of the wavefront's lanes (64 per tile; 8 tiles for p = 2, else 4,
-    2 for W = 2) keeps a background pair, whose bins agree on p planes with
-    probability 2^-p each; 0 (one phase, 8 W + 3) when none is cheaper."""
+def _plane_split(dthr, kp, Wp, tri=False):
+    """(phase-1 planes, whether scan_codes_fast1_kernel runs) of the first-group
+    pass, as the library picks them: the least expected lane-ops per pair.
+    A background pair's bin agrees on p planes with probability 2^-p, so a lane
+    survives phase 1 with a binomial tail probability and a wavefront opens
+    phase 2 when any of its 64 x tiles lanes does.  scan_codes_fast_kernel:
+    W p + 2 (+ 2.4 with 8 tiles), plus W (8 - p) + 2 in phase 2 (tiles: 8 for
+    p = 2, else 4; 2 for W = 2); scan_codes_fast1_kernel (W = 1, no
+    self-join): p + 1.6, plus p + 10 in phase 2 (tiles: 16 for p <= 3, else
+    8); one phase: 8 W + 3."""
     need = kp - dthr + 1
-    best, pick = 8.0 * Wp + 3.0, 0
+    best, pick = 8.0 * Wp + 3.0, (0, False)
     for p in range(2, 7):
         f = 2.0 ** -p
         tail = 1.0 if need <= 0 else sum(math.comb(kp, j) * f ** j * (1 - f) ** (kp - j)
                                          for j in range(max(need, 0), kp + 1))
+        keep = 1.0 - min(tail, 1.0)
         tiles = (8 if p == 2 else 4) if Wp == 1 else 2
-        cost = Wp * p + 3.0 + (1.0 - (1.0 - min(tail, 1.0)) ** (64 * tiles)) * (Wp * (8 - p) + 2.0)
+        cost = Wp * p + (2.4 if tiles == 8 else 2.0) + (1.0 - keep ** (64 * tiles)) * (Wp * (8 - p) + 2.0)
         if cost < best:
-            best, pick = cost, p
+            best, pick = cost, (p, False)
+        if Wp == 1 and not tri:
+            t1 = 16 if p <= 3 else 8
+            cost1 = p + 1.6 + (1.0 - keep ** (64 * t1)) * (p + 10.0)
+            if cost1 < best:
+                best, pick = cost1, (p, True)
     return pick
 
 
@@ -824,9 +834,9 @@ def _coarse_model(H, p, T, eps, goph=False):
     Wp = 1 if kp <= 32 else 2
     if m_rej0 >= 0 and 8 * m_rej0 >= kp:
         depth = 1
-        split = _plane_split(kp - m_rej0, kp, Wp)
+        split, fast1 = _plane_split(kp - m_rej0, kp, Wp)
         ops = Wp * (split + 1) + 1 if split else 9 * Wp + 1
-        kernel = "scan_codes_fast_kernel"
+        kernel = "scan_codes_fast1_kernel" if fast1 else "scan_codes_fast_kernel"
     else:
         g1 = next((l + 1 for l, r in enumerate(tabs["rej"]) if r >= 0), None)
         depth = cg if g1 is None else min(cg, -(-(g1 + 1) // pk) * pk)

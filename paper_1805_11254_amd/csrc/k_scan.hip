@@ -39,20 +39,35 @@ constexpr int kFineAhead = 4;          // most loads per step in the fine pass (
 // two-plane first phase over one plane word (its registers hold 8 planes of 8
 // tiles), else four (two with two plane words).
 constexpr int fast_tiles(int W, int P1) { return W == 1 ? (P1 == 2 ? 8 : 4) : 2; }
+// Tiles per wavefront of the first-group pass that keeps only its first-phase
+// planes in VGPRs (one plane word, no self-join filter): 16 for up to three
+// planes, else 8.
+constexpr int fast1_tiles(int P1) { return P1 <= 3 ? 16 : 8; }
+// The first-group pass's shape: planes of phase 1 (0: one phase), whether it
+// runs in scan_codes_fast1_kernel, and its tiles per wavefront.
+struct FirstGroupPlan {
+    int planes;
+    bool fast1;
+    int tiles;
+};
 
-// Planes compared first in the first-group code pass.  A background pair
-// (independent, uniform codes) agrees on a query-non-empty bin's first p
-// planes with probability 2^-p, so phase 1 keeps one of its lanes when at
-// least kp - thr + 1 of the kp bins agree there (a binomial tail), and a
-// wavefront goes on to phase 2 for all of its tiles when any of its 64 TPW
-// lanes is kept.  Per pair, phase 1 costs about W p + 3 lane-ops and phase 2
-// another W (8 - p) + 2, one phase over all 8 planes 8 W + 3; the split of 2
-// to 6 planes (or 0: one phase) with the least expected cost is taken.
-int plane_split(const ScanTab &tab, uint32_t kp) {
+// Planes compared first in the first-group code pass, and its kernel.  A
+// background pair (independent, uniform codes) agrees on a query-non-empty
+// bin's first p planes with probability 2^-p, so phase 1 keeps one of its
+// lanes when at least kp - thr + 1 of the kp bins agree there (a binomial
+// tail), and a wavefront goes on to phase 2 when any of its 64 TPW lanes is
+// kept.  Expected lane-ops per pair, with constants fitted to the measured
+// rates of both kernels: scan_codes_fast_kernel (every plane in VGPRs)
+// W p + 2 (W p + 2.4 with 8 tiles), plus W (8 - p) + 2 in phase 2, one phase
+// over all 8 planes 8 W + 3; scan_codes_fast1_kernel (one plane word, no
+// self-join filter; only the first p planes in VGPRs, so twice the tiles)
+// p + 1.6, plus about p + 10 in phase 2 (phase 1 again for the tiles, then the
+// kept tiles' planes read again).  The least of these is taken.
+FirstGroupPlan first_group_plan(const ScanTab &tab, uint32_t kp, bool tri) {
     const int32_t k = (int32_t)kp, need = k - tab.dthr0[0] + 1;   // agreeing bins that keep a lane
     const int W = (int)code_plane_words(kp);
-    double best = 8.0 * W + 3.0;
-    int pick = 0;
+    FirstGroupPlan best{0, false, fast_tiles(W, 0)};
+    double best_cost = 8.0 * W + 3.0;
     for (int p = 2; p <= 6; ++p) {
         const double f = std::ldexp(1.0, -p);
         double tail = need <= 0 ? 1.0 : 0.0, term = std::pow(1.0 - f, k);   // P(j = 0)
@@ -60,14 +75,23 @@ int plane_split(const ScanTab &tab, uint32_t kp) {
             if (j >= need) tail += term;
             term *= (double)(k - j) / (double)(j + 1) * f / (1.0 - f);
         }
-        const double open = 1.0 - std::pow(1.0 - std::min(tail, 1.0), 64.0 * fast_tiles(W, p));
-        const double cost = W * p + 3.0 + open * (W * (8 - p) + 2.0);
-        if (cost < best) {
-            best = cost;
-            pick = p;
+        const double keep = 1.0 - std::min(tail, 1.0);
+        const double open = 1.0 - std::pow(keep, 64.0 * fast_tiles(W, p));
+        const double cost = W * p + (fast_tiles(W, p) == 8 ? 2.4 : 2.0) + open * (W * (8 - p) + 2.0);
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = FirstGroupPlan{p, false, fast_tiles(W, p)};
+        }
+        if (W == 1 && !tri) {
+            const double open1 = 1.0 - std::pow(keep, 64.0 * fast1_tiles(p));
+            const double cost1 = p + 1.6 + open1 * (p + 10.0);
+            if (cost1 < best_cost) {
+                best_cost = cost1;
+                best = FirstGroupPlan{p, true, fast1_tiles(p)};
+            }
         }
     }
-    return pick;
+    return best;
 }
 
 struct CoarseArgs {
@@ -710,6 +734,108 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_
             HOPH_CODE_QUERY_T(rb, q + 1)
         }
 #undef HOPH_CODE_QUERY_T
+    }
+    sb.flush(surv, a.surv_cap, counters + 0, lane);
+}
+
+// The first-group pass with only the first P1 planes of its tiles in VGPRs
+// (one plane word, no self-join filter), so that TPW tiles share each query's
+// scalar work: phase 1 as in scan_codes_fast_kernel (the largest partial
+// agreeing count over the tiles, one test per query); when some lane is kept
+// the tiles that hold one are worked out from the registers, and each of them
+// reads its 8 planes again (from L2 or HBM) and tests its pairs on the full
+// codes.  A lane that phase 1 does not keep has too few agreeing bins on the
+// full codes too, so testing every lane of such a tile gives the same pairs.
+template <int TPW, int P1>
+__global__ __launch_bounds__(kThreads) void scan_codes_fast1_kernel(const uint32_t *__restrict__ codes,
+                                                                   const uint32_t *__restrict__ qcodes,
+                                                                   Survivor *__restrict__ surv,
+                                                                   unsigned long long *__restrict__ counters,
+                                                                   const uint64_t *__restrict__ desc,
+                                                                   const CoarseArgs a) {
+    constexpr int PW = (int)kCodeBits, RW = PW + 4, RS = PW + 8;   // words read per record, record stride
+    static_assert(P1 >= 2 && P1 <= 6, "phase-1 planes");
+    __shared__ Survivor s_surv[kWaves][kSurvBatch];
+    const uint32_t lane = threadIdx.x & 63;
+    SurvBatch<kSurvBatch> sb{s_surv[wave_id_in_block()], 0};
+    const uint64_t n_sets = desc ? desc[1] : a.n_sets;
+    const uint32_t q_lo = desc ? 0u : a.q0, q_hi = desc ? (uint32_t)desc[0] : a.q1;
+    const uint32_t qpw = chunk_queries(a, desc, q_hi - q_lo);
+    const uint64_t ntiles = (n_sets + 63) / 64;
+    const uint64_t ngroups = (ntiles + TPW - 1) / TPW;
+    const uint32_t nchunks = (q_hi - q_lo + qpw - 1) / qpw;
+    const uint64_t n_items = ngroups * nchunks;
+    const uint64_t wstride = (uint64_t)gridDim.x * kWaves;
+    const uint64_t rstride = (uint64_t)a.cg * RS;
+    for (uint64_t item = (uint64_t)blockIdx.x * kWaves + wave_id_in_block(); item < n_items; item += wstride) {
+        const uint64_t tg = item % ngroups;
+        const uint32_t chunk = (uint32_t)(item / ngroups);
+        const uint32_t qa = q_lo + chunk * qpw;
+        const uint32_t qb = min(q_hi, qa + qpw);
+        uint32_t P[TPW][P1];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+            const uint64_t tile = tg * TPW + t;
+            if (tile < ntiles) {             // wave-uniform; tiles below ntiles exist (ntiles <= ctiles)
+                const uint4 *src = reinterpret_cast<const uint4 *>(codes + (tile * 64 + lane) * PW);
+                const uint4 v0 = src[0];
+                uint32_t w[8] = {v0.x, v0.y, v0.z, v0.w, 0u, 0u, 0u, 0u};
+                if constexpr (P1 > 4) {
+                    const uint4 v1 = src[1];
+                    w[4] = v1.x;
+                    w[5] = v1.y;
+                }
+#pragma unroll
+                for (int j = 0; j < P1; ++j) P[t][j] = w[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < P1; ++j) P[t][j] = 0;
+            }
+        }
+        uint32_t ra[RW], rb[RW];
+#pragma unroll
+        for (int j = 0; j < RW; ++j) ra[j] = qcodes[qa * rstride + j];
+// one query against the TPW tiles (written out twice below, on the kernel's
+// own restrict pointers, so that the record loads stay scalar)
+#define HOPH_CODE_QUERY_1(r, qq)                                                                   \
+        {                                                                                          \
+            int32_t best = 0;                                                                      \
+            _Pragma("unroll") for (int t = 0; t < TPW; ++t) {                                      \
+                const uint32_t x = code_agree_part<1, 0, P1>(0u, r[PW], P[t], r, 0);               \
+                best = max(best, (int32_t)__popc(x));                                              \
+            }                                                                                      \
+            if (__builtin_amdgcn_ballot_w64(best > (int32_t)r[PW + 2])) {                          \
+                uint32_t tiles_kept = 0;                                                           \
+                _Pragma("unroll") for (int t = 0; t < TPW; ++t) {                                  \
+                    const uint32_t x = code_agree_part<1, 0, P1>(0u, r[PW], P[t], r, 0);           \
+                    const bool in = (tg * TPW + t) * 64 + lane < n_sets;   /* no tile past the sets */ \
+                    tiles_kept |= __builtin_amdgcn_ballot_w64(in && (int32_t)__popc(x) > (int32_t)r[PW + 2]) \
+                                      ? (1u << t) : 0u;                                            \
+                }                                                                                  \
+                _Pragma("unroll 1") for (int t = 0; t < TPW; ++t) {                                \
+                    if (!((tiles_kept >> t) & 1u)) continue;                                       \
+                    const uint64_t tile = tg * TPW + t;                                            \
+                    const uint64_t sv = tile * 64 + lane;                                          \
+                    const uint4 *src = reinterpret_cast<const uint4 *>(codes + sv * PW);           \
+                    const uint4 v0 = src[0], v1 = src[1];                                          \
+                    const uint32_t Pf[PW] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};      \
+                    const uint32_t x = code_agree_part<1, 0, (int)kCodeBits>(0u, r[PW], Pf, r, 0); \
+                    const uint64_t bal = __builtin_amdgcn_ballot_w64((int32_t)__popc(x) > (int32_t)r[PW + 2]) & \
+                                         __builtin_amdgcn_ballot_w64(sv < n_sets);                  \
+                    sb.push(bal, (qq), (uint32_t)sv, surv, a.surv_cap, counters + 0, lane);        \
+                }                                                                                  \
+            }                                                                                      \
+        }
+        for (uint32_t q = qa; q < qb; q += 2) {
+#pragma unroll
+            for (int j = 0; j < RW; ++j) rb[j] = qcodes[(q + 1) * rstride + j];
+            HOPH_CODE_QUERY_1(ra, q)
+            if (q + 1 >= qb) break;
+#pragma unroll
+            for (int j = 0; j < RW; ++j) ra[j] = qcodes[(q + 2) * rstride + j];
+            HOPH_CODE_QUERY_1(rb, q + 1)
+        }
+#undef HOPH_CODE_QUERY_1
     }
     sb.flush(surv, a.surv_cap, counters + 0, lane);
 }
@@ -1403,7 +1529,8 @@ void codes_launch(const ScanLaunch &l, const CoarseArgs &a, const ScanTab &tab, 
     hipLaunchKernelGGL((scan_codes_kernel<W, G, PACK, UNITW>), dim3(blocks), dim3(kThreads), 0, st, l.codes, \
                        l.qcodes, l.qmasks, l.surv, cnt, l.desc, a, tab)
     if (l.depth == 1 && tab.policy != HOPH_EMPTY_EITHER) {
-        const int split = plane_split(tab, l.kp);
+        const FirstGroupPlan fg = first_group_plan(tab, l.kp, l.tri);
+        const int split = fg.planes;
 #define HOPH_FAST(P1, TRI)                                                                                     \
     hipLaunchKernelGGL((scan_codes_fast_kernel<W, fast_tiles(W, P1), P1, TRI>), dim3(blocks), dim3(kThreads), 0, st, \
                        l.codes, l.qcodes, l.surv, cnt, l.desc, a)
@@ -1416,6 +1543,18 @@ void codes_launch(const ScanLaunch &l, const CoarseArgs &a, const ScanTab &tab, 
             case 6: HOPH_FAST(6, true); break;
             default: HOPH_FAST(0, true); break;
             }
+        } else if (W == 1 && fg.fast1) {
+#define HOPH_FAST1(P1)                                                                                          \
+    hipLaunchKernelGGL((scan_codes_fast1_kernel<fast1_tiles(P1), P1>), dim3(blocks), dim3(kThreads), 0, st, l.codes, \
+                       l.qcodes, l.surv, cnt, l.desc, a)
+            switch (split) {
+            case 2: HOPH_FAST1(2); break;
+            case 3: HOPH_FAST1(3); break;
+            case 4: HOPH_FAST1(4); break;
+            case 5: HOPH_FAST1(5); break;
+            default: HOPH_FAST1(6); break;
+            }
+#undef HOPH_FAST1
         } else {
             switch (split) {
             case 2: HOPH_FAST(2, false); break;
@@ -1566,7 +1705,7 @@ uint32_t coarse_tiles_per_wave(const ScanLaunch &l, const ScanTab &tab) {
         return (uint32_t)(lin_plane_split(tab, l.kp, R) > 0 ? lin1_tiles((int)R + 1) : lin_tiles((int)l.depth));
     }
     if (!(l.codes && l.depth == 1 && policy != HOPH_EMPTY_EITHER)) return 1u;
-    return (uint32_t)fast_tiles((int)code_plane_words(l.kp), plane_split(tab, l.kp));
+    return (uint32_t)first_group_plan(tab, l.kp, l.tri).tiles;
 }
 
 uint32_t max_depth_for_kpad(uint32_t kpad) {
