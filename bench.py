@@ -643,8 +643,10 @@ def _code_pass_shape(H, p, T, eps, goph=False):
     depth, split = None, 0
     if m_rej0 >= 0 and 8 * m_rej0 >= kp:
         depth = 1
-        split = _plane_split(kp - m_rej0, kp, W_planes)[0]
-    ops = W_planes * (split + 1) + 1 if split else 9 * W_planes + 1
+        split, fast1 = _plane_split(kp - m_rej0, kp, W_planes)
+        ops = _first_group_ops(split, fast1, W_planes)
+    else:
+        ops = _first_group_ops(0, False, W_planes)
     rec_bytes = (8 * W_planes + 4) * 4
     return depth, W_planes, split, ops, rec_bytes
 
@@ -805,6 +807,18 @@ def _plane_split(dthr, kp, Wp, tri=False):
     return pick
 
 
+def _first_group_ops(split, fast1, Wp):
+    """VALU lane-ops per pair of the first-group pass's first phase, as its
+    instruction stream counts them: per tile W p three-input bit operations
+    and W popcounts, a running maximum over the tiles (one two- or three-input
+    maximum per two tiles), and per query one copy of the query's mask and one
+    compare, shared by the wavefront's tiles; one phase: 9 W + 1."""
+    if not split:
+        return 9 * Wp + 1
+    tiles = (16 if split <= 3 else 8) if fast1 else ((8 if split == 2 else 4) if Wp == 1 else 2)
+    return Wp * (split + 1) + math.ceil((tiles - 1) / 2) / tiles + 2 / tiles
+
+
 def _coarse_model(H, p, T, eps, goph=False):
     """How the library runs the coarse pass for these parameters (JOINT, a
     query path), and the algorithmic work of one launch per (query, set) pair.
@@ -814,8 +828,9 @@ def _coarse_model(H, p, T, eps, goph=False):
     in whole code units.  Kernel and minimum work per pair:
     - one group: the first-group pass compares P1 planes of every pair first
       (P1 W plane operations, the first of them masked by the query's
-      non-empty bins, W popcounts, one compare; P1 from 2 to 6 by the expected
-      cost of _plane_split), else all 8 planes (9 W + 1);
+      non-empty bins, W popcounts, a share of the running maximum and of the
+      per-query compare, _first_group_ops; P1 from 2 to 6 and the kernel by the
+      expected cost of _plane_split), else all 8 planes (9 W + 1);
     - two to four groups of 17-32 bins: the linear-bound pass compares P1 planes
       of groups 1..R+1 (R+1 the first step with a reject cutoff; P1 the smallest
       of 2, 3, 4 planes whose chance match rate is at most a third of that
@@ -835,18 +850,22 @@ def _coarse_model(H, p, T, eps, goph=False):
     if m_rej0 >= 0 and 8 * m_rej0 >= kp:
         depth = 1
         split, fast1 = _plane_split(kp - m_rej0, kp, Wp)
-        ops = Wp * (split + 1) + 1 if split else 9 * Wp + 1
+        ops = _first_group_ops(split, fast1, Wp)
         kernel = "scan_codes_fast1_kernel" if fast1 else "scan_codes_fast_kernel"
     else:
         g1 = next((l + 1 for l, r in enumerate(tabs["rej"]) if r >= 0), None)
         depth = cg if g1 is None else min(cg, -(-(g1 + 1) // pk) * pk)
         R = (g1 - 1) if g1 is not None else L
         if kp <= 32 and pk == 1 and 2 <= depth <= 4 and R < depth:
-            kernel = "scan_codes_lin_kernel"
             full = sum(tabs["W"][g] * tabs["dmul"][0] * kp for g in range(R + 1))
             tau = tabs["rej"][R] / full
             split = next((s for s in (2, 3, 4) if 3.0 * 2.0 ** -s <= tau), 0)
-            ops = (R + 1) * (split + 2) + 2 if split else depth * 10 + 2
+            kernel = "scan_codes_lin1_kernel" if split else "scan_codes_lin_kernel"
+            # lin1, per pair: per group of phase 1 a chain of P1 planes, a popcount and
+            # a 24-bit multiply-add; a running maximum per group and tile pair; per
+            # query four copies and compares over its 8 (4 for G1 > 2) tiles
+            tiles = 8 if R + 1 <= 2 else 4
+            ops = (R + 1) * (split + 2) + (R + 1) / 2 + 4 / tiles if split else depth * 10 + 2
         else:
             split = 0
             ops = 10 * Wp + 1 + 6
