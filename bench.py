@@ -631,7 +631,7 @@ def bench_sweeps(args):
     print(json.dumps(out), flush=True)
 
 
-def _code_pass_shape(H, p, T, eps, goph=False):
+def _code_pass_shape(H, p, T, eps, goph=False, nq=None):
     """(depth, plane words W, first-phase planes P1, lane-ops per pair and coded
     group, bytes of one query record) of the coarse pass on codes, as the
     library picks them (see the step's accounting below)."""
@@ -643,7 +643,7 @@ def _code_pass_shape(H, p, T, eps, goph=False):
     depth, split = None, 0
     if m_rej0 >= 0 and 8 * m_rej0 >= kp:
         depth = 1
-        split, fast1 = _plane_split(kp - m_rej0, kp, W_planes)
+        split, fast1 = _plane_split(kp - m_rej0, kp, W_planes, small=nq is not None and nq < 32)
         ops = _first_group_ops(split, fast1, W_planes)
     else:
         ops = _first_group_ops(0, False, W_planes)
@@ -710,9 +710,9 @@ def bench_scansweep(args):
                        torch.from_numpy(qsets.offsets.view(np.int64)).to(dev))
         qsig = H.sketch_oph(p, qids, qoffs)
         H.sync()
-        depth, Wp, split, ops, rec_bytes = _code_pass_shape(H, p, T, eps)
         rows = []
         for Q in qs_list:
+            depth, Wp, split, ops, rec_bytes = _code_pass_shape(H, p, T, eps, nq=Q)
             q = qsig[:Q].contiguous()
             reps = max(5, min(200, int(2e9 // (N * 32 + 1) // max(1, Q // 16 + 1))))
             warm_ms = min(H.scan_timing(idx, q, T=T, eps=eps, reps=reps) for _ in range(3))
@@ -778,7 +778,7 @@ def _code_units(k, kp, goph):
     return pk, cu, cu * pk
 
 
-def _plane_split(dthr, kp, Wp, tri=False):
+def _plane_split(dthr, kp, Wp, tri=False, small=False):
     """(phase-1 planes, whether scan_codes_fast1_kernel runs) of the first-group
     pass, as the library picks them: the least expected lane-ops per pair.
     A background pair's bin agrees on p planes with probability 2^-p, so a lane
@@ -787,7 +787,8 @@ def _plane_split(dthr, kp, Wp, tri=False):
     W p + 2 (+ 2.4 with 8 tiles), plus W (8 - p) + 2 in phase 2 (tiles: 8 for
     p = 2, else 4; 2 for W = 2); scan_codes_fast1_kernel (W = 1, no
     self-join): p + 1.6, plus p + 10 in phase 2 (tiles: 16 for p <= 3, else
-    8); one phase: 8 W + 3."""
+    8); one phase: 8 W + 3.  small: a host batch of fewer than 32 queries,
+    which keeps scan_codes_fast_kernel (more wavefronts read the planes)."""
     need = kp - dthr + 1
     best, pick = 8.0 * Wp + 3.0, (0, False)
     for p in range(2, 7):
@@ -799,7 +800,7 @@ def _plane_split(dthr, kp, Wp, tri=False):
         cost = Wp * p + (2.4 if tiles == 8 else 2.0) + (1.0 - keep ** (64 * tiles)) * (Wp * (8 - p) + 2.0)
         if cost < best:
             best, pick = cost, (p, False)
-        if Wp == 1 and not tri:
+        if Wp == 1 and not tri and not small:
             t1 = 16 if p <= 3 else 8
             cost1 = p + 1.6 + (1.0 - keep ** (64 * t1)) * (p + 10.0)
             if cost1 < best:
@@ -819,7 +820,7 @@ def _first_group_ops(split, fast1, Wp):
     return Wp * (split + 1) + math.ceil((tiles - 1) / 2) / tiles + 2 / tiles
 
 
-def _coarse_model(H, p, T, eps, goph=False):
+def _coarse_model(H, p, T, eps, goph=False, nq=None):
     """How the library runs the coarse pass for these parameters (JOINT, a
     query path), and the algorithmic work of one launch per (query, set) pair.
 
@@ -849,7 +850,7 @@ def _coarse_model(H, p, T, eps, goph=False):
     Wp = 1 if kp <= 32 else 2
     if m_rej0 >= 0 and 8 * m_rej0 >= kp:
         depth = 1
-        split, fast1 = _plane_split(kp - m_rej0, kp, Wp)
+        split, fast1 = _plane_split(kp - m_rej0, kp, Wp, small=nq is not None and nq < 32)
         ops = _first_group_ops(split, fast1, Wp)
         kernel = "scan_codes_fast1_kernel" if fast1 else "scan_codes_fast_kernel"
     else:
@@ -1435,16 +1436,17 @@ def run_c5(args, H, W, np, torch):
         q = qsig[:Q].contiguous()
         cold = min(H.scan_timing(idx, q, T=T, eps=eps, reps=20, flush=flush) for _ in range(3))
         warm = min(H.scan_timing(idx, q, T=T, eps=eps, reps=50) for _ in range(3))
+        mq = _coarse_model(H, p, T, eps, nq=Q)
         byts = N * m["plane_bytes_per_set"] + Q * m["record_bytes_per_query"]
-        rows.append({"Q": Q, "cold_ms": cold, "warm_ms": warm, "algorithmic_bytes": byts,
+        rows.append({"Q": Q, "kernel": mq["kernel"], "cold_ms": cold, "warm_ms": warm, "algorithmic_bytes": byts,
                      "cold_gbs": byts / (cold * 1e-3) / 1e9, "cold_frac": byts / (cold * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "warm_gbs": byts / (warm * 1e-3) / 1e9,
-                     "valu_frac": Q * N * m["ops_per_pair"] / (cold * 1e-3) / ALU_PEAK_OPS})
+                     "valu_frac": Q * N * mq["ops_per_pair"] / (cold * 1e-3) / ALU_PEAK_OPS})
         log(f"serving index: coarse pass Q={Q}: cold {cold * 1e3:.1f} us ({rows[-1]['cold_frac']:.2f} of HBM), "
             f"warm {warm * 1e3:.1f} us")
     del flush
     one = rows[0]
-    small = {"kernel": m["kernel"], "index_sets": N, "k": 256, "k_group": 32, "T": "4/5", "Q": 1,
+    small = {"kernel": rows[0]["kernel"], "index_sets": N, "k": 256, "k_group": 32, "T": "4/5", "Q": 1,
              "bound": "hbm", "achieved": one["cold_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
              "frac": one["cold_frac"], "ms": one["cold_ms"], "algorithmic_bytes": one["algorithmic_bytes"],
              "bytes_per_set": m["plane_bytes_per_set"], "rows": rows,

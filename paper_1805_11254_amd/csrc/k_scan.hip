@@ -62,8 +62,12 @@ struct FirstGroupPlan {
 // over all 8 planes 8 W + 3; scan_codes_fast1_kernel (one plane word, no
 // self-join filter; only the first p planes in VGPRs, so twice the tiles)
 // p + 1.6, plus about p + 10 in phase 2 (phase 1 again for the tiles, then the
-// kept tiles' planes read again).  The least of these is taken.
-FirstGroupPlan first_group_plan(const ScanTab &tab, uint32_t kp, bool tri) {
+// kept tiles' planes read again).  The least of these is taken.  A batch of
+// fewer than kFast1MinQueries queries (known on the host) keeps the kernel
+// with more wavefronts: there the pass is bound by reading the planes, and
+// twice the tiles per wavefront halve the wavefronts that read them.
+constexpr uint32_t kFast1MinQueries = 32;
+FirstGroupPlan first_group_plan(const ScanTab &tab, uint32_t kp, bool tri, bool small_batch) {
     const int32_t k = (int32_t)kp, need = k - tab.dthr0[0] + 1;   // agreeing bins that keep a lane
     const int W = (int)code_plane_words(kp);
     FirstGroupPlan best{0, false, fast_tiles(W, 0)};
@@ -82,7 +86,7 @@ FirstGroupPlan first_group_plan(const ScanTab &tab, uint32_t kp, bool tri) {
             best_cost = cost;
             best = FirstGroupPlan{p, false, fast_tiles(W, p)};
         }
-        if (W == 1 && !tri) {
+        if (W == 1 && !tri && !small_batch) {
             const double open1 = 1.0 - std::pow(keep, 64.0 * fast1_tiles(p));
             const double cost1 = p + 1.6 + open1 * (p + 10.0);
             if (cost1 < best_cost) {
@@ -1529,7 +1533,7 @@ void codes_launch(const ScanLaunch &l, const CoarseArgs &a, const ScanTab &tab, 
     hipLaunchKernelGGL((scan_codes_kernel<W, G, PACK, UNITW>), dim3(blocks), dim3(kThreads), 0, st, l.codes, \
                        l.qcodes, l.qmasks, l.surv, cnt, l.desc, a, tab)
     if (l.depth == 1 && tab.policy != HOPH_EMPTY_EITHER) {
-        const FirstGroupPlan fg = first_group_plan(tab, l.kp, l.tri);
+        const FirstGroupPlan fg = first_group_plan(tab, l.kp, l.tri, !l.desc && l.q1 - l.q0 < kFast1MinQueries);
         const int split = fg.planes;
 #define HOPH_FAST(P1, TRI)                                                                                     \
     hipLaunchKernelGGL((scan_codes_fast_kernel<W, fast_tiles(W, P1), P1, TRI>), dim3(blocks), dim3(kThreads), 0, st, \
@@ -1705,7 +1709,7 @@ uint32_t coarse_tiles_per_wave(const ScanLaunch &l, const ScanTab &tab) {
         return (uint32_t)(lin_plane_split(tab, l.kp, R) > 0 ? lin1_tiles((int)R + 1) : lin_tiles((int)l.depth));
     }
     if (!(l.codes && l.depth == 1 && policy != HOPH_EMPTY_EITHER)) return 1u;
-    return (uint32_t)first_group_plan(tab, l.kp, l.tri).tiles;
+    return (uint32_t)first_group_plan(tab, l.kp, l.tri, !l.desc && l.q1 - l.q0 < kFast1MinQueries).tiles;
 }
 
 uint32_t max_depth_for_kpad(uint32_t kpad) {
