@@ -499,11 +499,21 @@ def bench_selfjoin(args):
         sample = pr[:: max(1, len(pr) // 20000)]
         prec = sum(_exact_j(coll.set(a), coll.set(b)) >= T for (a, b) in sample) / max(1, len(sample))
         coarse_ms, fine_ms, sort_ms = (float(np.median([x[i] for x in passes])) for i in range(3))
+        depth, kernel, planes, tiles = idx.last_coarse_plan()
         out[name] = {"seconds": wall, "pairs_per_s": N * (N - 1) / 2 / wall, "coarse_ms": coarse_ms,
                      "fine_ms": fine_ms, "sort_ms": sort_ms, "accepted": len(got),
                      "recall": len(truth & got) / max(1, len(truth)), "precision": prec,
-                     "precision_sample": len(sample)}
-        log(f"self-join {name}: {wall * 1e3:.1f} ms, {len(got)} pairs")
+                     "precision_sample": len(sample),
+                     "coarse_plan": {"depth": depth, "kernel": kernel, "first_phase_planes": planes,
+                                     "tiles_per_wavefront": tiles}}
+        if kernel in ("first_group", "first_group_light"):
+            # the first phase's lane-ops per pair (the second phase's, where a lane
+            # is kept, on top), over the N(N-1)/2 pairs against the VALU peak
+            ops = _first_group_ops(planes, kernel == "first_group_light", 1 if w.kp <= 32 else 2)
+            out[name]["coarse_lane_ops_per_pair"] = ops
+            out[name]["coarse_valu_frac"] = N * (N - 1) / 2 * ops / (coarse_ms * 1e-3) / ALU_PEAK_OPS
+        log(f"self-join {name}: {wall * 1e3:.1f} ms, {len(got)} pairs, coarse {coarse_ms:.1f} ms "
+            f"({kernel}, {planes} planes, {tiles} tiles)")
     out["value"] = out["codes"]["pairs_per_s"]
     out["ms_per_step"] = out["codes"]["seconds"] * 1e3
     idx.free()
@@ -778,16 +788,15 @@ def _code_units(k, kp, goph):
     return pk, cu, cu * pk
 
 
-def _plane_split(dthr, kp, Wp, tri=False, small=False):
+def _plane_split(dthr, kp, Wp, small=False):
     """(phase-1 planes, whether scan_codes_fast1_kernel runs) of the first-group
     pass, as the library picks them: the least expected lane-ops per pair.
     A background pair's bin agrees on p planes with probability 2^-p, so a lane
     survives phase 1 with a binomial tail probability and a wavefront opens
     phase 2 when any of its 64 x tiles lanes does.  scan_codes_fast_kernel:
     W p + 2 (+ 2.4 with 8 tiles), plus W (8 - p) + 2 in phase 2 (tiles: 8 for
-    p = 2, else 4; 2 for W = 2); scan_codes_fast1_kernel (W = 1, no
-    self-join): p + 1.6, plus p + 10 in phase 2 (tiles: 16 for p <= 3, else
-    8); one phase: 8 W + 3.  small: a host batch of fewer than 32 queries,
+    p = 2, else 4; 2 for W = 2); scan_codes_fast1_kernel (W = 1): p + 1.6,
+    plus p + 10 in phase 2 (tiles: 16 for p <= 3, else 8); one phase: 8 W + 3.  small: a host batch of fewer than 32 queries,
     which keeps scan_codes_fast_kernel (more wavefronts read the planes)."""
     need = kp - dthr + 1
     best, pick = 8.0 * Wp + 3.0, (0, False)
@@ -800,7 +809,7 @@ def _plane_split(dthr, kp, Wp, tri=False, small=False):
         cost = Wp * p + (2.4 if tiles == 8 else 2.0) + (1.0 - keep ** (64 * tiles)) * (Wp * (8 - p) + 2.0)
         if cost < best:
             best, pick = cost, (p, False)
-        if Wp == 1 and not tri and not small:
+        if Wp == 1 and not small:
             t1 = 16 if p <= 3 else 8
             cost1 = p + 1.6 + (1.0 - keep ** (64 * t1)) * (p + 10.0)
             if cost1 < best:
@@ -1138,7 +1147,9 @@ def c3_comparators(args, H, W, np, torch, st):
     the timed step: plain OPH over all 256 bins (Eq. 6, no early stop) and
     MinWise with k = 512 independent hashes mod 2^32 + 15, each one query per
     launch and batched, with recall and precision on the first 256 queries;
-    HOPH (1:2) and (2:1) one query per launch beside them."""
+    HOPH (1:2) and (2:1) one query per launch beside them, and HOPH (1:1) on the
+    same sets: its index build, the batched scan of all queries at each
+    threshold (device time) with recall and precision, one query per launch."""
     w, ids, offs, qids, qoffs, exact = st["w"], st["ids"], st["offs"], st["qids"], st["qoffs"], st["exact"]
     dev = torch.device("cuda")
     N, Q, k = w.collection.n, w.queries.n, w.k
@@ -1161,6 +1172,27 @@ def c3_comparators(args, H, W, np, torch, st):
         t = one_per_launch(lambda i: H.query_hoph(ix, qs[i:i + 1].contiguous(), T=(7, 10), eps=w.eps))
         out[f"hoph{r[0]}{r[1]}_one_query_per_launch"] = {"ms_per_query": t * 1e3, "pairs_per_s": N / t}
         del qs
+    p11 = H.SketchParams(W.LAYOUT_HIER, k, w.kp, w.hash_kind, w.universe, 1, 1, w.ha, w.hb)
+    ix11 = H.Index(p11, torch.empty((0, k), dtype=torch.int32, device=dev), capacity=N)
+    ix11.append_sets(ids, offs)
+    ix11.reset()
+    ix11.append_sets(ids, offs)
+    sk11, cd11 = ix11.last_append_ms()
+    q11 = H.sketch_oph(p11, qids, qoffs)
+    ent = {"index_build_ms": sk11 + cd11, "sets_sketched_per_s": N / (sk11 * 1e-3), "batched": {}}
+    for T in C3_T:
+        H.query_hoph(ix11, q11, T=T, eps=w.eps)
+        o, i_ = H.query_hoph(ix11, q11, T=T, eps=w.eps)
+        co, fi, so = ix11.last_query_ms()
+        ms = co + fi + so
+        ent["batched"][_ttag(T)] = dict(ms=ms, pairs_per_s=Q * N / (ms * 1e-3),
+                                        **_accuracy(o.cpu().numpy(), i_.cpu().numpy().view(np.uint32), w.planted,
+                                                    exact, T, n_acc))
+    t = one_per_launch(lambda i: H.query_hoph(ix11, q11[i:i + 1].contiguous(), T=(7, 10), eps=w.eps))
+    ent["one_query_per_launch"] = {"ms_per_query": t * 1e3, "pairs_per_s": N / t}
+    out["hoph11"] = ent
+    ix11.free()
+    del q11
     po = H.SketchParams(W.LAYOUT_OPH, k, w.kp, w.hash_kind, w.universe, 1, 1, w.ha, w.hb)
     ox = H.Index(po, torch.empty((0, k), dtype=torch.int32, device=dev), capacity=N)
     ox.append_sets(ids, offs)

@@ -191,6 +191,27 @@ hoph_status hoph_query_timing(const hoph_index *index, float ms[3]);
    query and after a query with no queries or no sets. */
 hoph_status hoph_query_counts(const hoph_index *index, uint64_t counts[2]);
 
+/* Coarse-pass kernels, as hoph_coarse_plan reports them. */
+enum {
+    HOPH_PLAN_NONE = 0,               /* no query yet, or nothing to compare                          */
+    HOPH_PLAN_WORDS = 1,              /* the 32-bit words of the first groups (HOPH_COARSE_WORDS)      */
+    HOPH_PLAN_CODES = 2,              /* the codes of one or more groups, the general form            */
+    HOPH_PLAN_FIRST_GROUP = 3,        /* the first group's codes, every plane held in registers       */
+    HOPH_PLAN_FIRST_GROUP_LIGHT = 4,  /* the first group's codes, only the first-phase planes held     */
+    HOPH_PLAN_LINEAR = 5,             /* two to four groups' codes under the linear bound              */
+    HOPH_PLAN_LINEAR_LIGHT = 6,       /* the same, only the first-phase planes held                    */
+    HOPH_PLAN_OPH_FULL = 7            /* the plain OPH comparator's full-signature pass                */
+};
+
+/* hoph_coarse_plan -- how the last query_* or self_join call on this index ran
+   its coarse pass (host array; a report, the results do not depend on it):
+   plan[0] the groups it walked (its depth; 0 for HOPH_PLAN_OPH_FULL),
+   plan[1] the kernel (HOPH_PLAN_*), plan[2] the code planes compared before
+   the rest (0: one phase), plan[3] tiles of 64 indexed sets per wavefront.
+   The first-group kernels and their plane count follow an expected-cost model
+   (a self-join also measures keep rates on sampled row pairs). */
+hoph_status hoph_coarse_plan(const hoph_index *index, uint32_t plan[4]);
+
 /* hoph_scan_timing -- a measurement hook: the coarse pass of query_goph /
    query_hoph (by the index layout; Alg. 1 / Alg. 2 up to the coarse depth) for
    the n_q query signatures d_qsigs, timed alone.  The per-query records are

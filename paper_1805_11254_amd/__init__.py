@@ -23,6 +23,9 @@ HASH_TABLE, HASH_MODP31, HASH_MODP32P15 = 0, 1, 2
 LAYOUT_OPH, LAYOUT_HIER = 0, 1
 EMPTY_JOINT, EMPTY_LITERAL, EMPTY_EITHER = 0, 1, 2
 COARSE_CODES, COARSE_WORDS = 0, 1
+# coarse-pass kernels as hoph_coarse_plan reports them (HOPH_PLAN_*)
+PLAN_NAMES = {0: "none", 1: "words", 2: "codes", 3: "first_group", 4: "first_group_light", 5: "linear",
+              6: "linear_light", 7: "oph_full"}
 EMPTY = 0xFFFFFFFF
 
 u32, u64, i32, i64, vp = C.c_uint32, C.c_uint64, C.c_int32, C.c_int64, C.c_void_p
@@ -96,6 +99,7 @@ SIGNATURES = {
     "hoph_index_code_planes": (C.c_int, [vp, vp, u64, C.POINTER(u64), vp]),
     "hoph_query_timing": (C.c_int, [vp, C.POINTER(C.c_float)]),
     "hoph_query_counts": (C.c_int, [vp, C.POINTER(C.c_uint64)]),
+    "hoph_coarse_plan": (C.c_int, [vp, C.POINTER(C.c_uint32)]),
     "hoph_scan_timing": (C.c_int, [vp, vp, u32, C.POINTER(QueryParamsC), u32, vp, u64, C.POINTER(C.c_float), vp]),
     "hoph_index_free": (None, [vp]),
     "query_goph": (C.c_int, [vp, vp, u32, C.POINTER(QueryParamsC), C.POINTER(ResultsC), vp]),
@@ -324,6 +328,13 @@ class Index:
         c = (C.c_uint64 * 2)()
         _check(lib().hoph_query_counts(self._h, c))
         return c[0], c[1]
+
+    def last_coarse_plan(self):
+        """(depth, kernel, first-phase planes, tiles per wavefront) of the last
+        query's coarse pass; kernel is one of the PLAN_* names."""
+        c = (C.c_uint32 * 4)()
+        _check(lib().hoph_coarse_plan(self._h, c))
+        return c[0], PLAN_NAMES.get(c[1], str(c[1])), c[2], c[3]
 
     def free(self):
         if self._h:

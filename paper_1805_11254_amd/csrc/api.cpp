@@ -65,10 +65,14 @@ hoph_status check_results(const hoph_results *r, uint32_t n_q) {
 // the device (about 32 per CU) without splitting the query batch further, and
 // into at most one chunk per kChunkQueries queries (each chunk reads the
 // index's planes again).
-uint32_t pick_q_per_wave(uint64_t n_sets, uint32_t n_q, uint32_t tiles_per_wave) {
+uint32_t pick_q_per_wave(uint64_t n_sets, uint32_t n_q, uint32_t tiles_per_wave, bool tri) {
     const uint64_t per_wave = 64ull * std::max<uint32_t>(1, tiles_per_wave);
     const uint64_t ntiles = std::max<uint64_t>(1, (n_sets + per_wave - 1) / per_wave);
-    uint64_t want_chunks = (4 * 8192ull + ntiles - 1) / ntiles;   // about four rounds of items
+    // about four rounds of items; the self-join keeps about half of its items
+    // (the upper triangle) and takes about eight rounds of those, so that the
+    // last round's stragglers cost little
+    const uint64_t rounds = tri ? 16 : 4;
+    uint64_t want_chunks = (rounds * 8192ull + ntiles - 1) / ntiles;
     want_chunks = std::min<uint64_t>(want_chunks, std::max<uint64_t>(1, n_q / kChunkQueries));
     if (want_chunks == 0) want_chunks = 1;
     return (uint32_t)((n_q + want_chunks - 1) / want_chunks);
@@ -241,12 +245,30 @@ hoph_status run_query_impl(const hoph_index *cidx, Workspace *ws_in, const uint3
     }
     a.qmasks = ws.qmasks;
     a.qcodes = ws.qcodes;
+    // A self-join's first-group pass picks its kernel and plane count from keep
+    // rates measured on sampled row pairs (the rows are the queries, and the
+    // pass is long enough that one read-back of a few records costs little).
+    double keep_rate[8];
+    if (self_join && use_codes && depth == 1 && tab.policy != HOPH_EMPTY_EITHER && code_plane_words(lay.kp) == 1 &&
+        n_q >= 2 && n_sets) {
+        HOPH_HIP(sample_keep_rates(ws.qcodes, n_q, idx->cg, lay.kp, keep_rate, s), "sample_keep_rates");
+        a.keep_rate = keep_rate;
+    }
 
     // one pass over queries [q0, q1) (coarse, then per-survivor), events ev[0..2]
+    uint32_t plan[4] = {0, HOPH_PLAN_NONE, 0, 0};
     auto pass = [&](uint32_t q0, uint32_t q1) -> hoph_status {
         a.q0 = q0;
         a.q1 = q1;
-        a.q_per_wave = pick_q_per_wave(n_sets, q1 - q0, coarse_tiles_per_wave(a, tab));
+        a.q_per_wave = pick_q_per_wave(n_sets, q1 - q0, coarse_tiles_per_wave(a, tab), a.tri);
+        if (kind == QueryKind::OPH_FULL) {
+            plan[0] = 0;
+            plan[1] = HOPH_PLAN_OPH_FULL;
+            plan[2] = 0;
+            plan[3] = 1;
+        } else {
+            describe_coarse(a, tab, plan);
+        }
         if (timed_ev) HOPH_HIP(hipEventRecord(ws.ev[0], s), "hipEventRecord");
         if (kind == QueryKind::OPH_FULL) {
             HOPH_HIP(launch_oph_full(a, qp->T, qp->empty_policy, s), "oph_full launch");
@@ -269,7 +291,7 @@ hoph_status run_query_impl(const hoph_index *cidx, Workspace *ws_in, const uint3
         a.keys_cap = ws.keys_cap;
         a.q0 = 0;
         a.q1 = n_q;
-        a.q_per_wave = pick_q_per_wave(n_sets, n_q, coarse_tiles_per_wave(a, tab));
+        a.q_per_wave = pick_q_per_wave(n_sets, n_q, coarse_tiles_per_wave(a, tab), a.tri);
         HOPH_HIP(launch_fill_u64(ws.counters, 4, 0, s), "fill counters");
         HOPH_HIP(launch_scan_coarse(a, tab, s), "coarse scan launch");    // warm: code object, caches
         if (flush_bytes) HOPH_HIP(launch_read_sweep(flush, flush_bytes, flush, s), "flush read");   // warm it
@@ -327,6 +349,7 @@ hoph_status run_query_impl(const hoph_index *cidx, Workspace *ws_in, const uint3
             res->needed = acc;
             ws.last_counts[0] = surv;
             ws.last_counts[1] = acc;
+            std::memcpy(ws.last_plan, plan, sizeof(plan));
             record_timing();
             return HOPH_OK;
         }
@@ -404,6 +427,7 @@ hoph_status run_query_impl(const hoph_index *cidx, Workspace *ws_in, const uint3
     HOPH_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
     ws.last_counts[0] = survivors;
     ws.last_counts[1] = accepted;
+    std::memcpy(ws.last_plan, plan, sizeof(plan));
     ws.last_ms[0] = ws.last_ms[1] = ws.last_ms[2] = 0.f;
     if (timed && timed_ev) {
         ws.last_ms[0] = pass_ms[0];
@@ -632,6 +656,15 @@ hoph_status hoph_query_counts(const hoph_index *idx, uint64_t counts[2]) {
     std::lock_guard<std::mutex> lk(m->mu);
     counts[0] = m->ws.last_counts[0];
     counts[1] = m->ws.last_counts[1];
+    return HOPH_OK;
+}
+
+hoph_status hoph_coarse_plan(const hoph_index *idx, uint32_t plan[4]) {
+    g_last_error.clear();
+    if (!idx || !plan) return fail(HOPH_E_INVAL, "NULL argument");
+    hoph_index *m = const_cast<hoph_index *>(idx);
+    std::lock_guard<std::mutex> lk(m->mu);
+    std::memcpy(plan, m->ws.last_plan, sizeof(m->ws.last_plan));
     return HOPH_OK;
 }
 

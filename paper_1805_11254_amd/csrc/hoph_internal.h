@@ -514,6 +514,7 @@ struct ScanLaunch {
     uint64_t *counters;         // [0] survivors, [1] accepted
     const uint64_t *desc;       // nullable: desc[0] = n_q, desc[1] = n_sets, read on the device
     uint32_t waves_per_cu;      // persistent grid size with desc (0 = default)
+    const double *keep_rate;    // nullable: sample_keep_rates of these records, for the first-group plan
 };
 // Empty-bin masks of every (query, group) and, when qcodes is not null, the code
 // records (code_rec_words each) of each query's first cg groups; thr is then required.
@@ -527,8 +528,16 @@ hipError_t launch_query_masks(const uint32_t *qsigs, uint32_t n_q, const uint64_
 // kp, L and cg set.
 bool lin_records(const ScanLaunch &a, const ScanTab &tab, LinTab *lin);
 hipError_t launch_scan_coarse(const ScanLaunch &a, const ScanTab &tab, hipStream_t st);
+// Phase-1 lane keep rates of the first-group code pass (one plane word) on the
+// data, rate[p] for p = 2 .. 6, from sampled pairs of the n_q query records in
+// qcodes (each with cg groups); synchronises st.
+hipError_t sample_keep_rates(const uint32_t *qcodes, uint32_t n_q, uint32_t cg, uint32_t kp, double rate[8],
+                             hipStream_t st);
 // Tiles of 64 sets one wavefront of the coarse pass holds for this launch.
 uint32_t coarse_tiles_per_wave(const ScanLaunch &a, const ScanTab &tab);
+// The coarse pass launch_scan_coarse runs for a: depth, HOPH_PLAN_* kernel,
+// first-phase planes, tiles per wavefront (hoph_coarse_plan).
+void describe_coarse(const ScanLaunch &a, const ScanTab &tab, uint32_t out[4]);
 hipError_t launch_scan_fine(const ScanLaunch &a, const ScanTab &tab, hipStream_t st);
 hipError_t launch_oph_full(const ScanLaunch &a, hoph_ratio T, uint32_t policy, hipStream_t st);
 hipError_t launch_pair_estimates(const uint32_t *slab, uint64_t n_sets, uint32_t k, uint32_t kp, uint32_t L,

@@ -23,8 +23,10 @@
 // across the lanes of a load (one lane per bin) and two to four loads per
 // step; counts come from ballots and popcounts, the decision is wave-uniform,
 // and the wavefront leaves at the first deciding group.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "hoph_internal.h"
 
@@ -40,8 +42,7 @@ constexpr int kFineAhead = 4;          // most loads per step in the fine pass (
 // tiles), else four (two with two plane words).
 constexpr int fast_tiles(int W, int P1) { return W == 1 ? (P1 == 2 ? 8 : 4) : 2; }
 // Tiles per wavefront of the first-group pass that keeps only its first-phase
-// planes in VGPRs (one plane word, no self-join filter): 16 for up to three
-// planes, else 8.
+// planes in VGPRs (one plane word): 16 for up to three planes, else 8.
 constexpr int fast1_tiles(int P1) { return P1 <= 3 ? 16 : 8; }
 // The first-group pass's shape: planes of phase 1 (0: one phase), whether it
 // runs in scan_codes_fast1_kernel, and its tiles per wavefront.
@@ -59,19 +60,38 @@ struct FirstGroupPlan {
 // kept.  Expected lane-ops per pair, with constants fitted to the measured
 // rates of both kernels: scan_codes_fast_kernel (every plane in VGPRs)
 // W p + 2 (W p + 2.4 with 8 tiles), plus W (8 - p) + 2 in phase 2, one phase
-// over all 8 planes 8 W + 3; scan_codes_fast1_kernel (one plane word, no
-// self-join filter; only the first p planes in VGPRs, so twice the tiles)
-// p + 1.6, plus about p + 10 in phase 2 (phase 1 again for the tiles, then the
-// kept tiles' planes read again).  The least of these is taken.  A batch of
-// fewer than kFast1MinQueries queries (known on the host) keeps the kernel
-// with more wavefronts: there the pass is bound by reading the planes, and
-// twice the tiles per wavefront halve the wavefronts that read them.
+// over all 8 planes 8 W + 3; scan_codes_fast1_kernel (one plane word; only
+// the first p planes in VGPRs, so twice the tiles) p + 1.6, plus about p + 10
+// in phase 2 (phase 1 again for the tiles, then the kept tiles' planes read
+// again).  The least of these is taken.  A batch of fewer than
+// kFast1MinQueries queries (known on the host) keeps the kernel with more
+// wavefronts: there the pass is bound by reading the planes, and twice the
+// tiles per wavefront halve the wavefronts that read them.
+//
+// keep_rate (nullable): the lane keep rate of each p measured on sampled pairs
+// of the data (sample_keep_rates), taken where it exceeds the binomial tail:
+// sets that share common elements agree on more bins than independent codes.
+// With it, each tile of scan_codes_fast1_kernel that keeps a lane also costs
+// the wait for its planes read again, about kRereadCost lane-ops per pair of
+// that tile (fitted to a self-join of 10^6 rows where 1.6% of the tiles kept
+// a lane at p = 2: 2.5 times the time at p = 3).  A self-join (tri) with one
+// plane word runs scan_codes_fast1_kernel unless even its best plane count
+// costs more than one phase over all planes: the rows' records stream from
+// memory through the scalar unit, and that kernel shares each record over
+// twice the tiles (measured 1.5 to 1.7 times faster than
+// scan_codes_fast_kernel at 2, 3 and 4 planes on that self-join).
 constexpr uint32_t kFast1MinQueries = 32;
-FirstGroupPlan first_group_plan(const ScanTab &tab, uint32_t kp, bool tri, bool small_batch) {
+constexpr double kRereadCost = 520.0;
+FirstGroupPlan first_group_plan(const ScanTab &tab, uint32_t kp, bool tri, bool small_batch,
+                                const double *keep_rate) {
     const int32_t k = (int32_t)kp, need = k - tab.dthr0[0] + 1;   // agreeing bins that keep a lane
     const int W = (int)code_plane_words(kp);
+    const bool light = W == 1 && !small_batch;                     // scan_codes_fast1_kernel may run
+    const bool light_only = light && tri;
     FirstGroupPlan best{0, false, fast_tiles(W, 0)};
     double best_cost = 8.0 * W + 3.0;
+    FirstGroupPlan best1{0, false, 0};
+    double best1_cost = HUGE_VAL;
     for (int p = 2; p <= 6; ++p) {
         const double f = std::ldexp(1.0, -p);
         double tail = need <= 0 ? 1.0 : 0.0, term = std::pow(1.0 - f, k);   // P(j = 0)
@@ -79,24 +99,30 @@ FirstGroupPlan first_group_plan(const ScanTab &tab, uint32_t kp, bool tri, bool 
             if (j >= need) tail += term;
             term *= (double)(k - j) / (double)(j + 1) * f / (1.0 - f);
         }
-        const double keep = 1.0 - std::min(tail, 1.0);
-        const double open = 1.0 - std::pow(keep, 64.0 * fast_tiles(W, p));
-        const double cost = W * p + (fast_tiles(W, p) == 8 ? 2.4 : 2.0) + open * (W * (8 - p) + 2.0);
-        if (cost < best_cost) {
-            best_cost = cost;
-            best = FirstGroupPlan{p, false, fast_tiles(W, p)};
+        const double lane = keep_rate ? std::max(tail, keep_rate[p]) : tail;
+        const double keep = 1.0 - std::min(lane, 1.0);
+        if (!light_only) {
+            const double open = 1.0 - std::pow(keep, 64.0 * fast_tiles(W, p));
+            const double cost = W * p + (fast_tiles(W, p) == 8 ? 2.4 : 2.0) + open * (W * (8 - p) + 2.0);
+            if (cost < best_cost) {
+                best_cost = cost;
+                best = FirstGroupPlan{p, false, fast_tiles(W, p)};
+            }
         }
-        if (W == 1 && !tri && !small_batch) {
+        if (light) {
             const double open1 = 1.0 - std::pow(keep, 64.0 * fast1_tiles(p));
-            const double cost1 = p + 1.6 + open1 * (p + 10.0);
-            if (cost1 < best_cost) {
-                best_cost = cost1;
-                best = FirstGroupPlan{p, true, fast1_tiles(p)};
+            double cost1 = p + 1.6 + open1 * (p + 10.0);
+            if (keep_rate) cost1 += (1.0 - std::pow(keep, 64.0)) * kRereadCost;
+            if (cost1 < best1_cost) {
+                best1_cost = cost1;
+                best1 = FirstGroupPlan{p, true, fast1_tiles(p)};
             }
         }
     }
+    if (best1.fast1 && (light_only || best1_cost < best_cost)) return best1;
     return best;
 }
+
 
 struct CoarseArgs {
     uint64_t capacity, n_sets, surv_cap, keys_cap;
@@ -620,6 +646,24 @@ __global__ __launch_bounds__(64) void scan_codes_deep_kernel(const uint32_t *__r
     sb.flush(surv, a.surv_cap, counters + 0, lane);
 }
 
+// The self-join's (tile group, query chunk) items that hold a set id above the
+// chunk's first query row: the tile groups of chunk c start at first(c), and
+// the items are numbered chunk by chunk, so that a persistent grid spreads the
+// upper triangle's work evenly instead of stepping over the items below it.
+struct TriItems {
+    uint64_t ngroups, span;         // tile groups, sets per tile group
+    uint32_t q_lo, qpw, nchunks;
+    __device__ __forceinline__ uint64_t first(uint32_t c) const {
+        const uint64_t qa = q_lo + (uint64_t)c * qpw;
+        return min(ngroups, (qa + 1) / span);
+    }
+    __device__ __forceinline__ uint64_t total() const {
+        uint64_t t = 0;
+        for (uint32_t c = 0; c < nchunks; ++c) t += ngroups - first(c);
+        return t;
+    }
+};
+
 // First-group code pass (depth 1, JOINT or LITERAL), TPW tiles of 64 indexed
 // sets per wavefront: each query's record (read with scalar loads, one query
 // ahead) is compared with TPW tiles, so the scalar work of a query is shared
@@ -652,17 +696,30 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_
     const uint64_t ntiles = (n_sets + 63) / 64;
     const uint64_t ngroups = (ntiles + TPW - 1) / TPW;
     const uint32_t nchunks = (q_hi - q_lo + qpw - 1) / qpw;
-    const uint64_t n_items = ngroups * nchunks;
+    const TriItems tri{ngroups, (uint64_t)TPW * 64, q_lo, qpw, nchunks};
+    const uint64_t n_items = TRI ? tri.total() : ngroups * nchunks;
     const uint64_t wstride = (uint64_t)gridDim.x * kWaves;
     const uint64_t ctiles = a.capacity / 64;
     const uint64_t rstride = (uint64_t)a.cg * RS;
+    uint32_t tri_c = 0;                  // self-join: chunk of the cursor, and its first item
+    uint64_t tri_base = 0;
     for (uint64_t item = (uint64_t)blockIdx.x * kWaves + wave_id_in_block(); item < n_items; item += wstride) {
-        const uint64_t tg = item % ngroups;
-        const uint32_t chunk = (uint32_t)(item / ngroups);
+        uint64_t tg;
+        uint32_t chunk;
+        if constexpr (TRI) {
+            // items come in increasing order, so the cursor only moves forward
+            while (item >= tri_base + (ngroups - tri.first(tri_c))) {
+                tri_base += ngroups - tri.first(tri_c);
+                ++tri_c;
+            }
+            chunk = tri_c;
+            tg = tri.first(tri_c) + (item - tri_base);
+        } else {
+            tg = item % ngroups;
+            chunk = (uint32_t)(item / ngroups);
+        }
         const uint32_t qa = q_lo + chunk * qpw;
         const uint32_t qb = min(q_hi, qa + qpw);
-        // self-join: skip (before any load) an item with no set id above its first query row
-        if (TRI && (tg + 1) * TPW * 64 <= (uint64_t)qa + 1) continue;
         uint32_t P[TPW][PW];
         uint64_t vmask[TPW];                 // lanes holding an indexed set, per tile
         uint32_t sid[TPW];
@@ -743,14 +800,14 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast_kernel(const uint32_
 }
 
 // The first-group pass with only the first P1 planes of its tiles in VGPRs
-// (one plane word, no self-join filter), so that TPW tiles share each query's
+// (one plane word; TRI: the self-join's filter), so that TPW tiles share each query's
 // scalar work: phase 1 as in scan_codes_fast_kernel (the largest partial
 // agreeing count over the tiles, one test per query); when some lane is kept
 // the tiles that hold one are worked out from the registers, and each of them
 // reads its 8 planes again (from L2 or HBM) and tests its pairs on the full
 // codes.  A lane that phase 1 does not keep has too few agreeing bins on the
 // full codes too, so testing every lane of such a tile gives the same pairs.
-template <int TPW, int P1>
+template <int TPW, int P1, bool TRI>
 __global__ __launch_bounds__(kThreads) void scan_codes_fast1_kernel(const uint32_t *__restrict__ codes,
                                                                    const uint32_t *__restrict__ qcodes,
                                                                    Survivor *__restrict__ surv,
@@ -768,12 +825,26 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast1_kernel(const uint32
     const uint64_t ntiles = (n_sets + 63) / 64;
     const uint64_t ngroups = (ntiles + TPW - 1) / TPW;
     const uint32_t nchunks = (q_hi - q_lo + qpw - 1) / qpw;
-    const uint64_t n_items = ngroups * nchunks;
+    const TriItems tri{ngroups, (uint64_t)TPW * 64, q_lo, qpw, nchunks};
+    const uint64_t n_items = TRI ? tri.total() : ngroups * nchunks;
     const uint64_t wstride = (uint64_t)gridDim.x * kWaves;
     const uint64_t rstride = (uint64_t)a.cg * RS;
+    uint32_t tri_c = 0;                  // self-join: chunk of the cursor, and its first item
+    uint64_t tri_base = 0;
     for (uint64_t item = (uint64_t)blockIdx.x * kWaves + wave_id_in_block(); item < n_items; item += wstride) {
-        const uint64_t tg = item % ngroups;
-        const uint32_t chunk = (uint32_t)(item / ngroups);
+        uint64_t tg;
+        uint32_t chunk;
+        if constexpr (TRI) {
+            while (item >= tri_base + (ngroups - tri.first(tri_c))) {
+                tri_base += ngroups - tri.first(tri_c);
+                ++tri_c;
+            }
+            chunk = tri_c;
+            tg = tri.first(tri_c) + (item - tri_base);
+        } else {
+            tg = item % ngroups;
+            chunk = (uint32_t)(item / ngroups);
+        }
         const uint32_t qa = q_lo + chunk * qpw;
         const uint32_t qb = min(q_hi, qa + qpw);
         uint32_t P[TPW][P1];
@@ -812,7 +883,8 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast1_kernel(const uint32
                 uint32_t tiles_kept = 0;                                                           \
                 _Pragma("unroll") for (int t = 0; t < TPW; ++t) {                                  \
                     const uint32_t x = code_agree_part<1, 0, P1>(0u, r[PW], P[t], r, 0);           \
-                    const bool in = (tg * TPW + t) * 64 + lane < n_sets;   /* no tile past the sets */ \
+                    const uint64_t sv = (tg * TPW + t) * 64 + lane;                                \
+                    const bool in = sv < n_sets && (!TRI || sv > (qq));   /* pairs the pass may emit */ \
                     tiles_kept |= __builtin_amdgcn_ballot_w64(in && (int32_t)__popc(x) > (int32_t)r[PW + 2]) \
                                       ? (1u << t) : 0u;                                            \
                 }                                                                                  \
@@ -825,7 +897,7 @@ __global__ __launch_bounds__(kThreads) void scan_codes_fast1_kernel(const uint32
                     const uint32_t Pf[PW] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};      \
                     const uint32_t x = code_agree_part<1, 0, (int)kCodeBits>(0u, r[PW], Pf, r, 0); \
                     const uint64_t bal = __builtin_amdgcn_ballot_w64((int32_t)__popc(x) > (int32_t)r[PW + 2]) & \
-                                         __builtin_amdgcn_ballot_w64(sv < n_sets);                  \
+                                         __builtin_amdgcn_ballot_w64(sv < n_sets && (!TRI || sv > (qq))); \
                     sb.push(bal, (qq), (uint32_t)sv, surv, a.surv_cap, counters + 0, lane);        \
                 }                                                                                  \
             }                                                                                      \
@@ -1533,12 +1605,24 @@ void codes_launch(const ScanLaunch &l, const CoarseArgs &a, const ScanTab &tab, 
     hipLaunchKernelGGL((scan_codes_kernel<W, G, PACK, UNITW>), dim3(blocks), dim3(kThreads), 0, st, l.codes, \
                        l.qcodes, l.qmasks, l.surv, cnt, l.desc, a, tab)
     if (l.depth == 1 && tab.policy != HOPH_EMPTY_EITHER) {
-        const FirstGroupPlan fg = first_group_plan(tab, l.kp, l.tri, !l.desc && l.q1 - l.q0 < kFast1MinQueries);
+        const FirstGroupPlan fg = first_group_plan(tab, l.kp, l.tri, !l.desc && l.q1 - l.q0 < kFast1MinQueries, l.keep_rate);
         const int split = fg.planes;
 #define HOPH_FAST(P1, TRI)                                                                                     \
     hipLaunchKernelGGL((scan_codes_fast_kernel<W, fast_tiles(W, P1), P1, TRI>), dim3(blocks), dim3(kThreads), 0, st, \
                        l.codes, l.qcodes, l.surv, cnt, l.desc, a)
-        if (l.tri) {
+        if (l.tri && W == 1 && fg.fast1) {
+#define HOPH_FAST1T(P1)                                                                                          \
+    hipLaunchKernelGGL((scan_codes_fast1_kernel<fast1_tiles(P1), P1, true>), dim3(blocks), dim3(kThreads), 0, st, \
+                       l.codes, l.qcodes, l.surv, cnt, l.desc, a)
+            switch (split) {
+            case 2: HOPH_FAST1T(2); break;
+            case 3: HOPH_FAST1T(3); break;
+            case 4: HOPH_FAST1T(4); break;
+            case 5: HOPH_FAST1T(5); break;
+            default: HOPH_FAST1T(6); break;
+            }
+#undef HOPH_FAST1T
+        } else if (l.tri) {
             switch (split) {
             case 2: HOPH_FAST(2, true); break;
             case 3: HOPH_FAST(3, true); break;
@@ -1549,7 +1633,7 @@ void codes_launch(const ScanLaunch &l, const CoarseArgs &a, const ScanTab &tab, 
             }
         } else if (W == 1 && fg.fast1) {
 #define HOPH_FAST1(P1)                                                                                          \
-    hipLaunchKernelGGL((scan_codes_fast1_kernel<fast1_tiles(P1), P1>), dim3(blocks), dim3(kThreads), 0, st, l.codes, \
+    hipLaunchKernelGGL((scan_codes_fast1_kernel<fast1_tiles(P1), P1, false>), dim3(blocks), dim3(kThreads), 0, st, l.codes, \
                        l.qcodes, l.surv, cnt, l.desc, a)
             switch (split) {
             case 2: HOPH_FAST1(2); break;
@@ -1635,6 +1719,47 @@ void oph_kp(const ScanLaunch &l, const CoarseArgs &a, hoph_ratio T, hipStream_t 
 
 }  // namespace
 
+// Phase-1 lane keep rates of the first-group pass measured on the data: up to
+// kKeepSample rows spaced evenly over [0, n_q), each row's first-group record
+// as the query against every other sampled row's planes as the set; rate[p]
+// (p = 2 .. 6) is the fraction of those ordered pairs with more agreeing bins
+// on the first p planes than the query's keep threshold, as the kernels test
+// it.  One strided copy of the records (one plane word) and a count on the
+// host, on st (synchronised).  rate[] is all 0 when fewer than two rows.
+constexpr uint32_t kKeepSample = 512;
+hipError_t sample_keep_rates(const uint32_t *qcodes, uint32_t n_q, uint32_t cg, uint32_t kp, double rate[8],
+                             hipStream_t st) {
+    for (int p = 0; p < 8; ++p) rate[p] = 0.0;
+    if (code_plane_words(kp) != 1 || n_q < 2 || cg == 0) return hipErrorInvalidValue;
+    const uint32_t S = std::min(n_q, kKeepSample), step = n_q / S;
+    constexpr uint32_t PW = kCodeBits, take = PW + 3;     // planes, non-empty mask, (high word), threshold
+    const size_t rec = (size_t)cg * code_rec_words(kp);  // words per query
+    std::vector<uint32_t> h((size_t)S * take);
+    hipError_t e = hipMemcpy2DAsync(h.data(), take * sizeof(uint32_t), qcodes, (size_t)step * rec * sizeof(uint32_t),
+                                    take * sizeof(uint32_t), S, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    uint64_t kept[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t i = 0; i < S; ++i) {
+        const uint32_t *q = &h[(size_t)i * take];
+        const int32_t thr = (int32_t)q[PW + 2];
+        for (uint32_t j = 0; j < S; ++j) {
+            if (j == i) continue;
+            const uint32_t *c = &h[(size_t)j * take];
+            uint32_t a = q[PW];
+            for (int p = 0; p < 6; ++p) {
+                a &= ~(q[p] ^ c[p]);
+                if ((int32_t)__builtin_popcount(a) <= thr) break;    // the chain only loses bins
+                if (p >= 1) ++kept[p + 1];
+            }
+        }
+    }
+    const double pairs = (double)S * (double)(S - 1);
+    for (int p = 2; p <= 6; ++p) rate[p] = (double)kept[p] / pairs;
+    return hipSuccess;
+}
+
 // Whether the index and query parameters allow linear-bound records (see
 // LinTab): code planes, one plane word (k' <= 32), one group per code unit,
 // JOINT or LITERAL, not the self-join; then lin (if not null) gets the table
@@ -1709,7 +1834,25 @@ uint32_t coarse_tiles_per_wave(const ScanLaunch &l, const ScanTab &tab) {
         return (uint32_t)(lin_plane_split(tab, l.kp, R) > 0 ? lin1_tiles((int)R + 1) : lin_tiles((int)l.depth));
     }
     if (!(l.codes && l.depth == 1 && policy != HOPH_EMPTY_EITHER)) return 1u;
-    return (uint32_t)first_group_plan(tab, l.kp, l.tri, !l.desc && l.q1 - l.q0 < kFast1MinQueries).tiles;
+    return (uint32_t)first_group_plan(tab, l.kp, l.tri, !l.desc && l.q1 - l.q0 < kFast1MinQueries, l.keep_rate).tiles;
+}
+
+void describe_coarse(const ScanLaunch &l, const ScanTab &tab, uint32_t out[4]) {
+    out[0] = l.depth;
+    out[1] = l.codes ? HOPH_PLAN_CODES : HOPH_PLAN_WORDS;
+    out[2] = 0;
+    out[3] = coarse_tiles_per_wave(l, tab);
+    if (!l.codes) return;
+    if (lin_code_pass(l, tab, nullptr)) {
+        const int p1 = lin_plane_split(tab, l.kp, first_reject_step(tab));
+        out[1] = p1 > 0 ? HOPH_PLAN_LINEAR_LIGHT : HOPH_PLAN_LINEAR;
+        out[2] = (uint32_t)p1;
+    } else if (l.depth == 1 && tab.policy != HOPH_EMPTY_EITHER) {
+        const FirstGroupPlan fg =
+            first_group_plan(tab, l.kp, l.tri, !l.desc && l.q1 - l.q0 < kFast1MinQueries, l.keep_rate);
+        out[1] = fg.fast1 ? HOPH_PLAN_FIRST_GROUP_LIGHT : HOPH_PLAN_FIRST_GROUP;
+        out[2] = (uint32_t)fg.planes;
+    }
 }
 
 uint32_t max_depth_for_kpad(uint32_t kpad) {

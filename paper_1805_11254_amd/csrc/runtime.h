@@ -68,6 +68,7 @@ struct Workspace {
     bool aev_recorded = false;
     float last_ms[3] = {0, 0, 0};
     uint64_t last_counts[2] = {0, 0};   // survivors of the coarse pass, accepted pairs
+    uint32_t last_plan[4] = {0, 0, 0, 0};   // the coarse pass's shape (hoph_coarse_plan)
     void release() {
         if (fixed) return;                 // a view: nothing of its own to free
         for (auto &e : ev)
@@ -180,7 +181,7 @@ enum class QueryKind { GOPH, HOPH, OPH_FULL };
 
 // Queries per wavefront so that a pass has enough (tile group, query chunk) items
 // to fill the device; tiles_per_wave as coarse_tiles_per_wave reports.
-uint32_t pick_q_per_wave(uint64_t n_sets, uint32_t n_q, uint32_t tiles_per_wave);
+uint32_t pick_q_per_wave(uint64_t n_sets, uint32_t n_q, uint32_t tiles_per_wave, bool tri = false);
 hoph_status copy_counters(Workspace &ws, hipStream_t st);
 hoph_status write_output(Workspace &ws, uint64_t accepted, uint32_t n_q, hoph_results *res, hipStream_t s);
 

@@ -167,13 +167,13 @@ def test_first_group_plane_splits_match_oracle(ra, rb, Ts):
     two-group pass, for JOINT and LITERAL, on large shingle sets with planted
     near-duplicates: results equal to the oracle's."""
     _print_case(f"first-group plane splits {ra}:{rb}")
-    w = W.hoph_shingles(n=6_007, n_q=24, seed=41 + ra + 3 * rb, ra=ra, rb=rb)
+    w = W.hoph_shingles(n=6_007, n_q=40, seed=41 + ra + 3 * rb, ra=ra, rb=rb)   # >= 32: both kernels
     p = params_of(w)
     sig = gpu_sketch(w, w.collection, p)
     qsig = gpu_sketch(w, w.queries, p)
     idx = H.Index(p, sig)
     sh, qh = to_u32(sig), to_u32(qsig)
-    found = 0
+    found, shapes = 0, set()
     for T in Ts:
         for policy in (H.EMPTY_JOINT, H.EMPTY_LITERAL):
             oo, oi = oracle_query(w, sh, qh, T, (1, 10_000), policy)
@@ -183,6 +183,9 @@ def test_first_group_plane_splits_match_oracle(ra, rb, Ts):
             assert gi.tolist() == oi.tolist(), (T, policy)
             surv, acc = idx.last_query_counts()
             assert acc == len(oi) and surv >= acc, (T, policy, surv, acc)
+            depth, kernel, planes, _ = idx.last_coarse_plan()
+            shapes.add((depth, kernel, planes))
+    assert len(shapes) >= 2, shapes      # the thresholds take different pass shapes
     assert found > 0
     idx.free()
 
@@ -686,6 +689,43 @@ def test_self_join_matches_oracle(name):
                 go, gi = H.self_join(idx, T=T, eps=eps, policy=policy, coarse=coarse)
                 got = csr_lists(go.cpu().numpy(), to_u32(gi))
                 assert len(got) == n and got == want, (T, eps, policy, coarse)
+    idx.free()
+
+
+@pytest.mark.parametrize("ra,rb,Ts", [(1, 2, [(63, 100), (71, 100), (81, 100), (87, 100)]),
+                                      (2, 1, [(30, 100), (45, 100), (60, 100)]),
+                                      (1, 1, [(4, 5), (51, 100)])])
+def test_self_join_plane_splits_match_oracle(ra, rb, Ts):
+    """The self-join's first-group pass at thresholds that take different
+    first-phase plane counts and both first-group kernels (the upper-triangle
+    item walk and the i < j filter of each), for JOINT and LITERAL, on shingle
+    sets with planted near-duplicates: every accepted pair i < j equal to the
+    oracle's."""
+    _print_case(f"self-join plane splits {ra}:{rb}")
+    w = W.hoph_shingles(n=1_777, n_q=24, seed=61 + ra + 3 * rb, ra=ra, rb=rb)
+    coll = _with_queries_inside(w)
+    p = params_of(w)
+    sig = gpu_sketch(w, coll, p)
+    sh = to_u32(sig)
+    idx = H.Index(p, sig)
+    found = 0
+    for T in Ts:
+        for policy in (H.EMPTY_JOINT, H.EMPTY_LITERAL):
+            oo, oi = oracle_query(w, sh, sh, T, (1, 10_000), policy)
+            want = [[j for j in row if j > i] for i, row in enumerate(csr_lists(oo, oi))]
+            found += sum(len(r) for r in want)
+            go, gi = H.self_join(idx, T=T, eps=(1, 10_000), policy=policy)
+            got = csr_lists(go.cpu().numpy(), to_u32(gi))
+            assert got == want, (T, policy)
+            surv, acc = idx.last_query_counts()
+            assert acc == sum(len(r) for r in want) and surv >= acc, (T, policy, surv, acc)
+            depth, kernel, planes, tiles = idx.last_coarse_plan()
+            if depth == 1:      # one plane word: the light kernel, else one phase over all planes
+                assert kernel == "first_group_light" or (kernel == "first_group" and planes == 0), \
+                    (T, policy, kernel, planes)
+                if kernel == "first_group_light":
+                    assert tiles == (16 if planes <= 3 else 8), (T, policy, planes, tiles)
+    assert found > 0
     idx.free()
 
 
