@@ -727,6 +727,10 @@ def bench_scansweep(args):
             reps = max(5, min(200, int(2e9 // (N * 32 + 1) // max(1, Q // 16 + 1))))
             warm_ms = min(H.scan_timing(idx, q, T=T, eps=eps, reps=reps) for _ in range(3))
             kms = min(H.scan_timing(idx, q, T=T, eps=eps, reps=min(reps, 40), flush=flush) for _ in range(3))
+            pd, pkern, pplanes, _ = idx.last_coarse_plan()
+            if pkern in ("first_group", "first_group_light"):
+                split = pplanes
+                ops = _first_group_ops(pplanes, pkern == "first_group_light", Wp)
             H.query_hoph(idx, q, T=T, eps=eps)        # warm (tables cached, buffers grown)
             walls, phases = [], []
             for _ in range(max(5, args.steps)):
@@ -738,7 +742,8 @@ def bench_scansweep(args):
             byts = N * 32 * Wp * depth + Q * rec_bytes * depth
             gbs = byts / (kms * 1e-3) / 1e9
             valu = Q * N * depth * ops / (kms * 1e-3)
-            rows.append({"Q": Q, "coarse_kernel_ms": kms, "coarse_kernel_ms_warm": warm_ms,
+            rows.append({"Q": Q, "coarse_plan": [pd, pkern, pplanes], "ops_per_pair": ops,
+                         "coarse_kernel_ms": kms, "coarse_kernel_ms_warm": warm_ms,
                          "hbm_gbs_warm": byts / (warm_ms * 1e-3) / 1e9, "launches_timed": reps,
                          "algorithmic_bytes": byts,
                          "hbm_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS, "valu_ops_per_s": valu,
@@ -886,6 +891,25 @@ def _coarse_model(H, p, T, eps, goph=False, nq=None):
             "record_bytes_per_query": (8 * Wp + 8) * 4 * units}
 
 
+def _apply_plan(m, plan, Wp):
+    """The model's record with the coarse kernel the library reports it ran
+    (Index.last_coarse_plan): the first-group kernel and its plane count follow
+    keep rates the library samples from the index, which the model above does
+    not see; the other kernels are checked against the model."""
+    depth, kernel, planes, tiles = plan
+    m = dict(m, library_plan={"depth": depth, "kernel": kernel, "first_phase_planes": planes,
+                              "tiles_per_wavefront": tiles})
+    if kernel in ("first_group", "first_group_light"):
+        light = kernel == "first_group_light"
+        m.update(kernel="scan_codes_fast1_kernel" if light else "scan_codes_fast_kernel", depth=depth,
+                 first_phase_planes=planes, ops_per_pair=_first_group_ops(planes, light, Wp))
+    elif kernel in ("linear", "linear_light"):
+        want = "scan_codes_lin1_kernel" if kernel == "linear_light" else "scan_codes_lin_kernel"
+        if m["kernel"] != want or m["depth"] != depth:
+            log(f"warning: coarse model says {m['kernel']} at depth {m['depth']}, the library ran {want} at {depth}")
+    return m
+
+
 def _jaccard_cache(qcoll, coll):
     cache = {}
 
@@ -1023,6 +1047,7 @@ def run_c3(args, H, W, np, torch):
                 if rec is not None:
                     rec[(r, T)] = idx[r].last_query_ms()
                     rec[(r, T, "n")] = idx[r].last_query_counts()
+                    rec[(r, T, "plan")] = idx[r].last_coarse_plan()
                 if e: e[3 + ti].record(stream)
             if rec is not None:
                 rec[(r, "append")] = idx[r].last_append_ms()
@@ -1071,7 +1096,7 @@ def run_c3(args, H, W, np, torch):
         phase[f"index_build[{tg}]"] = ev_ms(ri, 0, 1)
         phase[f"query_sketch[{tg}]"] = ev_ms(ri, 1, 2)
         for ti, T in enumerate(C3_T):
-            m = _coarse_model(H, params[r], T, w.eps)
+            m = _apply_plan(_coarse_model(H, params[r], T, w.eps), recs[-1][(r, T, "plan")], 1 if kp <= 32 else 2)
             co, fi, so = rec_mean((r, T), 0), rec_mean((r, T), 1), rec_mean((r, T), 2)
             ops = Q * N * m["ops_per_pair"]
             byts = N * m["plane_bytes_per_set"] + Q * m["record_bytes_per_query"]
@@ -1285,7 +1310,7 @@ def run_c2(args, H, W, np, torch):
     codes_ms = sum(a[1] for a in ams) / len(ams)
     coarse_ms = sum(q[0] for q in qms) / len(qms)
     sketch_bytes = nnz * 4 + (N + 1) * 8 + N * k * 4
-    m = _coarse_model(H, p, w.T, w.eps)
+    m = _apply_plan(_coarse_model(H, p, w.T, w.eps), idx.last_coarse_plan(), 1 if kp <= 32 else 2)
     ops = Q * N * m["ops_per_pair"]
     # the HBM rate a plain device copy reaches here (2 GiB)
     cbuf = torch.empty(1 << 29, dtype=torch.int32, device=dev)
@@ -1468,7 +1493,7 @@ def run_c5(args, H, W, np, torch):
         q = qsig[:Q].contiguous()
         cold = min(H.scan_timing(idx, q, T=T, eps=eps, reps=20, flush=flush) for _ in range(3))
         warm = min(H.scan_timing(idx, q, T=T, eps=eps, reps=50) for _ in range(3))
-        mq = _coarse_model(H, p, T, eps, nq=Q)
+        mq = _apply_plan(_coarse_model(H, p, T, eps, nq=Q), idx.last_coarse_plan(), 1)
         byts = N * m["plane_bytes_per_set"] + Q * m["record_bytes_per_query"]
         rows.append({"Q": Q, "kernel": mq["kernel"], "cold_ms": cold, "warm_ms": warm, "algorithmic_bytes": byts,
                      "cold_gbs": byts / (cold * 1e-3) / 1e9, "cold_frac": byts / (cold * 1e-3) / 1e9 / HBM_PEAK_GBS,

@@ -203,13 +203,16 @@ enum {
     HOPH_PLAN_OPH_FULL = 7            /* the plain OPH comparator's full-signature pass                */
 };
 
-/* hoph_coarse_plan -- how the last query_* or self_join call on this index ran
-   its coarse pass (host array; a report, the results do not depend on it):
+/* hoph_coarse_plan -- how the last query_*, self_join or hoph_scan_timing call
+   on this index ran its coarse pass (host array; a report, the results do not
+   depend on it):
    plan[0] the groups it walked (its depth; 0 for HOPH_PLAN_OPH_FULL),
    plan[1] the kernel (HOPH_PLAN_*), plan[2] the code planes compared before
    the rest (0: one phase), plan[3] tiles of 64 indexed sets per wavefront.
-   The first-group kernels and their plane count follow an expected-cost model
-   (a self-join also measures keep rates on sampled row pairs). */
+   The first-group kernels and their plane count follow an expected-cost model;
+   a self-join feeds it keep rates measured on sampled pairs of index rows
+   (taken on the first self-join with given parameters, and again when the
+   index size has changed twofold; kept across hoph_index_reset). */
 hoph_status hoph_coarse_plan(const hoph_index *index, uint32_t plan[4]);
 
 /* hoph_scan_timing -- a measurement hook: the coarse pass of query_goph /

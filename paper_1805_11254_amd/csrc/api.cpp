@@ -134,11 +134,13 @@ hipError_t append_sets_async(hoph_index *idx, const uint32_t *d_ids, const uint6
     return hipSuccess;
 }
 
-hoph_status cached_scan_tab(hoph_index *idx, const hoph_query_params &qp, bool goph, ScanTab &out) {
-    for (const TabEntry &e : idx->tabs) {
+hoph_status cached_scan_tab(hoph_index *idx, const hoph_query_params &qp, bool goph, ScanTab &out,
+                            TabEntry **entry) {
+    for (TabEntry &e : idx->tabs) {
         if (e.T.num == qp.T.num && e.T.den == qp.T.den && e.eps.num == qp.eps.num && e.eps.den == qp.eps.den &&
             e.policy == qp.empty_policy && e.goph == (goph ? 1u : 0u)) {
             out = e.tab;
+            if (entry) *entry = &e;
             return HOPH_OK;
         }
     }
@@ -153,12 +155,35 @@ hoph_status cached_scan_tab(hoph_index *idx, const hoph_query_params &qp, bool g
     e.goph = goph ? 1u : 0u;
     to_scan_tab(t, e.tab);
     out = e.tab;
+    TabEntry *slot;
     if (idx->tabs.size() < kTabCache) {
         idx->tabs.push_back(e);                  // within the capacity reserved at build
+        slot = &idx->tabs.back();
     } else {
-        idx->tabs[idx->tab_next] = e;
+        slot = &idx->tabs[idx->tab_next];
+        *slot = e;
         idx->tab_next = (idx->tab_next + 1) % kTabCache;
     }
+    if (entry) *entry = slot;
+    return HOPH_OK;
+}
+
+// The first-group pass's keep rates for these tables (ent), sampled from the
+// first n_sets index rows when none were taken yet or the index has since
+// grown or shrunk more than twofold, and when sampling is allowed (it reads a
+// few rows back to the host and synchronises s); false when there are none.
+hoph_status index_keep_rates(hoph_index *idx, TabEntry &ent, uint64_t n_sets, hipStream_t s, bool may_sample,
+                             double rate[8], bool &have) {
+    have = false;
+    const bool stale = ent.keep_n == 0 || n_sets > 2 * ent.keep_n || 2 * n_sets < ent.keep_n;
+    if (stale && may_sample && n_sets >= 2) {
+        HOPH_HIP(sample_keep_rates(idx->codes, n_sets, idx->lay.kp, ent.tab.dthr0, ent.keep_rate, s),
+                 "sample_keep_rates");
+        ent.keep_n = n_sets;
+    }
+    if (ent.keep_n == 0) return HOPH_OK;
+    std::memcpy(rate, ent.keep_rate, sizeof(ent.keep_rate));
+    have = true;
     return HOPH_OK;
 }
 
@@ -204,10 +229,11 @@ hoph_status run_query_impl(const hoph_index *cidx, Workspace *ws_in, const uint3
     const bool timed_ev = ws.ev[0] != nullptr;       // a fixed workspace has no events
 
     ScanTab tab{};
+    TabEntry *tab_entry = nullptr;
     uint32_t depth = 0, maxd = 0;
     const bool use_codes = kind != QueryKind::OPH_FULL && qp->coarse_filter == HOPH_COARSE_CODES && idx->codes;
     if (kind != QueryKind::OPH_FULL) {
-        st = cached_scan_tab(idx, *qp, kind == QueryKind::GOPH, tab);
+        st = cached_scan_tab(idx, *qp, kind == QueryKind::GOPH, tab, &tab_entry);
         if (st) return st;
         maxd = use_codes ? idx->cg : std::min(max_depth_for_kpad(idx->kpad), lay.L);
         depth = default_coarse_depth(tab, qp->coarse_depth, maxd, use_codes ? code_pack(lay.kp, lay.L) : 1u);
@@ -245,14 +271,19 @@ hoph_status run_query_impl(const hoph_index *cidx, Workspace *ws_in, const uint3
     }
     a.qmasks = ws.qmasks;
     a.qcodes = ws.qcodes;
-    // A self-join's first-group pass picks its kernel and plane count from keep
-    // rates measured on sampled row pairs (the rows are the queries, and the
-    // pass is long enough that one read-back of a few records costs little).
+    // A self-join's first-group pass picks its kernel and plane count with keep
+    // rates measured on sampled pairs of index rows, taken once per index size
+    // and parameters.  (Query batches keep the binomial rates: on bag-of-words
+    // sets, where background pairs agree on more bins, 1,024 queries over 10^6
+    // sets still ran fastest at the plane count those give, 0.139 ms at 2
+    // planes against 0.175 ms at the 3 the sampled rates pick.)
     double keep_rate[8];
-    if (self_join && use_codes && depth == 1 && tab.policy != HOPH_EMPTY_EITHER && code_plane_words(lay.kp) == 1 &&
-        n_q >= 2 && n_sets) {
-        HOPH_HIP(sample_keep_rates(ws.qcodes, n_q, idx->cg, lay.kp, keep_rate, s), "sample_keep_rates");
-        a.keep_rate = keep_rate;
+    if (self_join && use_codes && tab_entry && depth == 1 && tab.policy != HOPH_EMPTY_EITHER &&
+        code_plane_words(lay.kp) == 1 && n_q && n_sets >= 2) {
+        bool have = false;
+        st = index_keep_rates(idx, *tab_entry, n_sets, s, ws_in == nullptr, keep_rate, have);
+        if (st) return st;
+        if (have) a.keep_rate = keep_rate;
     }
 
     // one pass over queries [q0, q1) (coarse, then per-survivor), events ev[0..2]
@@ -309,6 +340,7 @@ hoph_status run_query_impl(const hoph_index *cidx, Workspace *ws_in, const uint3
             HOPH_HIP(hipEventRecord(ws.ev[3], s), "hipEventRecord");
         }
         HOPH_HIP(hipEventSynchronize(flush_bytes ? ws.ev[3] : ws.ev[1]), "hipEventSynchronize");
+        describe_coarse(a, tab, ws.last_plan);
         float ms = 0.f, flush_ms = 0.f;
         HOPH_HIP(hipEventElapsedTime(&ms, ws.ev[0], ws.ev[1]), "hipEventElapsedTime");
         if (flush_bytes) HOPH_HIP(hipEventElapsedTime(&flush_ms, ws.ev[2], ws.ev[3]), "hipEventElapsedTime");
@@ -532,7 +564,6 @@ hoph_status build_index(const hoph_sketch_params *params, const uint32_t *d_sigs
     const uint64_t code_words_total = idx->capacity * cu * code_words(idx->lay.kp);
     auto release = [&] {
         if (idx->slab) (void)hipFree(idx->slab);
-        if (idx->codes) (void)hipFree(idx->codes);
         if (idx->codes) (void)hipFree(idx->codes);
         idx->slab = nullptr;
         idx->codes = nullptr;

@@ -529,10 +529,11 @@ hipError_t launch_query_masks(const uint32_t *qsigs, uint32_t n_q, const uint64_
 bool lin_records(const ScanLaunch &a, const ScanTab &tab, LinTab *lin);
 hipError_t launch_scan_coarse(const ScanLaunch &a, const ScanTab &tab, hipStream_t st);
 // Phase-1 lane keep rates of the first-group code pass (one plane word) on the
-// data, rate[p] for p = 2 .. 6, from sampled pairs of the n_q query records in
-// qcodes (each with cg groups); synchronises st.
-hipError_t sample_keep_rates(const uint32_t *qcodes, uint32_t n_q, uint32_t cg, uint32_t kp, double rate[8],
-                             hipStream_t st);
+// data, rate[p] for p = 2 .. 6, from sampled pairs of the first n_sets index
+// rows' code planes and the reject thresholds dthr0 (ScanTab::dthr0);
+// synchronises st.
+hipError_t sample_keep_rates(const uint32_t *codes, uint64_t n_sets, uint32_t kp, const int32_t *dthr0,
+                             double rate[8], hipStream_t st);
 // Tiles of 64 sets one wavefront of the coarse pass holds for this launch.
 uint32_t coarse_tiles_per_wave(const ScanLaunch &a, const ScanTab &tab);
 // The coarse pass launch_scan_coarse runs for a: depth, HOPH_PLAN_* kernel,

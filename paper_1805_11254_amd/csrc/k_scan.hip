@@ -71,10 +71,14 @@ struct FirstGroupPlan {
 // keep_rate (nullable): the lane keep rate of each p measured on sampled pairs
 // of the data (sample_keep_rates), taken where it exceeds the binomial tail:
 // sets that share common elements agree on more bins than independent codes.
-// With it, each tile of scan_codes_fast1_kernel that keeps a lane also costs
-// the wait for its planes read again, about kRereadCost lane-ops per pair of
-// that tile (fitted to a self-join of 10^6 rows where 1.6% of the tiles kept
-// a lane at p = 2: 2.5 times the time at p = 3).  A self-join (tri) with one
+// In a self-join each tile of scan_codes_fast1_kernel kept beyond the
+// binomial rate (which the fitted constants cover) also costs the wait for
+// its planes read again, about kRereadCost lane-ops per pair of that tile
+// (fitted to a self-join of 10^6 rows where 1.6% of the tiles kept a lane at
+// p = 2: 2.5 times the time at p = 3; a wavefront there works through
+// thousands of queries per item, and its tiles' planes have left the caches
+// when they are read again; with a query batch the same kept-tile rate cost
+// less than the phase-2 term above).  A self-join (tri) with one
 // plane word runs scan_codes_fast1_kernel unless even its best plane count
 // costs more than one phase over all planes: the rows' records stream from
 // memory through the scalar unit, and that kernel shares each record over
@@ -99,6 +103,7 @@ FirstGroupPlan first_group_plan(const ScanTab &tab, uint32_t kp, bool tri, bool 
             if (j >= need) tail += term;
             term *= (double)(k - j) / (double)(j + 1) * f / (1.0 - f);
         }
+        const double keep0 = 1.0 - std::min(tail, 1.0);
         const double lane = keep_rate ? std::max(tail, keep_rate[p]) : tail;
         const double keep = 1.0 - std::min(lane, 1.0);
         if (!light_only) {
@@ -112,7 +117,7 @@ FirstGroupPlan first_group_plan(const ScanTab &tab, uint32_t kp, bool tri, bool 
         if (light) {
             const double open1 = 1.0 - std::pow(keep, 64.0 * fast1_tiles(p));
             double cost1 = p + 1.6 + open1 * (p + 10.0);
-            if (keep_rate) cost1 += (1.0 - std::pow(keep, 64.0)) * kRereadCost;
+            if (tri) cost1 += (std::pow(keep0, 64.0) - std::pow(keep, 64.0)) * kRereadCost;
             if (cost1 < best1_cost) {
                 best1_cost = cost1;
                 best1 = FirstGroupPlan{p, true, fast1_tiles(p)};
@@ -1720,37 +1725,48 @@ void oph_kp(const ScanLaunch &l, const CoarseArgs &a, hoph_ratio T, hipStream_t 
 }  // namespace
 
 // Phase-1 lane keep rates of the first-group pass measured on the data: up to
-// kKeepSample rows spaced evenly over [0, n_q), each row's first-group record
-// as the query against every other sampled row's planes as the set; rate[p]
-// (p = 2 .. 6) is the fraction of those ordered pairs with more agreeing bins
-// on the first p planes than the query's keep threshold, as the kernels test
-// it.  One strided copy of the records (one plane word) and a count on the
-// host, on st (synchronised).  rate[] is all 0 when fewer than two rows.
+// kKeepSample index rows spaced evenly over [0, n_sets), each as the query
+// (its non-empty bins and keep threshold worked out from its planes as the
+// query records hold them: a bin is empty where its code is 255, every plane
+// set) against every other sampled row as the set; rate[p] (p = 2 .. 6) is
+// the fraction of those ordered pairs with more agreeing bins on the first p
+// planes than the query's threshold, as the kernels test it.  One strided copy
+// of the first code unit's planes (one plane word) and a count on the host,
+// on st (synchronised).  rate[] is all 0 when fewer than two rows.
 constexpr uint32_t kKeepSample = 512;
-hipError_t sample_keep_rates(const uint32_t *qcodes, uint32_t n_q, uint32_t cg, uint32_t kp, double rate[8],
-                             hipStream_t st) {
+hipError_t sample_keep_rates(const uint32_t *codes, uint64_t n_sets, uint32_t kp, const int32_t *dthr0,
+                             double rate[8], hipStream_t st) {
     for (int p = 0; p < 8; ++p) rate[p] = 0.0;
-    if (code_plane_words(kp) != 1 || n_q < 2 || cg == 0) return hipErrorInvalidValue;
-    const uint32_t S = std::min(n_q, kKeepSample), step = n_q / S;
-    constexpr uint32_t PW = kCodeBits, take = PW + 3;     // planes, non-empty mask, (high word), threshold
-    const size_t rec = (size_t)cg * code_rec_words(kp);  // words per query
-    std::vector<uint32_t> h((size_t)S * take);
-    hipError_t e = hipMemcpy2DAsync(h.data(), take * sizeof(uint32_t), qcodes, (size_t)step * rec * sizeof(uint32_t),
-                                    take * sizeof(uint32_t), S, hipMemcpyDeviceToHost, st);
+    if (code_plane_words(kp) != 1 || n_sets < 2) return hipSuccess;
+    constexpr uint32_t PW = kCodeBits;
+    const uint32_t S = (uint32_t)std::min<uint64_t>(n_sets, kKeepSample);
+    const uint64_t step = n_sets / S;
+    uint32_t h[kKeepSample * PW];                        // row i's planes at h[i * PW]
+    hipError_t e = hipMemcpy2DAsync(h, PW * sizeof(uint32_t), codes, step * PW * sizeof(uint32_t),
+                                    PW * sizeof(uint32_t), S, hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return e;
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return e;
+    const uint32_t kpmask = kp >= 32 ? 0xFFFFFFFFu : ((1u << kp) - 1u);
+    uint32_t mask[kKeepSample];
+    int32_t thr[kKeepSample];
+    for (uint32_t i = 0; i < S; ++i) {
+        uint32_t em = kpmask;
+        for (uint32_t p = 0; p < PW; ++p) em &= h[i * PW + p];
+        const uint32_t ne = (uint32_t)__builtin_popcount(em);
+        mask[i] = ~em & kpmask;
+        thr[i] = (int32_t)(kp - ne) - dthr0[ne];
+    }
     uint64_t kept[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (uint32_t i = 0; i < S; ++i) {
-        const uint32_t *q = &h[(size_t)i * take];
-        const int32_t thr = (int32_t)q[PW + 2];
+        const uint32_t *q = &h[i * PW];
         for (uint32_t j = 0; j < S; ++j) {
             if (j == i) continue;
-            const uint32_t *c = &h[(size_t)j * take];
-            uint32_t a = q[PW];
+            const uint32_t *c = &h[j * PW];
+            uint32_t a = mask[i];
             for (int p = 0; p < 6; ++p) {
                 a &= ~(q[p] ^ c[p]);
-                if ((int32_t)__builtin_popcount(a) <= thr) break;    // the chain only loses bins
+                if ((int32_t)__builtin_popcount(a) <= thr[i]) break;   // the chain only loses bins
                 if (p >= 1) ++kept[p + 1];
             }
         }

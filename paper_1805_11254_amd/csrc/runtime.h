@@ -193,6 +193,10 @@ struct TabEntry {
     hoph_ratio T{}, eps{};
     uint32_t policy = 0, goph = 0;
     ScanTab tab{};
+    // phase-1 keep rates of the first-group pass sampled from the index rows
+    // (sample_keep_rates), and the index size they were sampled at (0: none)
+    double keep_rate[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint64_t keep_n = 0;
 };
 constexpr size_t kTabCache = 16;
 }  // namespace hoph
@@ -235,7 +239,8 @@ hoph_status run_query_in(const hoph_index *cidx, Workspace &ws, const uint32_t *
 hoph_status scan_timing(const hoph_index *cidx, const uint32_t *d_qsigs, uint32_t n_q, const hoph_query_params *qp,
                         uint32_t reps, void *d_flush, uint64_t flush_bytes, float *ms, void *stream);
 // The scan tables for qp on idx's layout, from the index's cache (caller holds idx->mu).
-hoph_status cached_scan_tab(hoph_index *idx, const hoph_query_params &qp, bool goph, ScanTab &out);
+hoph_status cached_scan_tab(hoph_index *idx, const hoph_query_params &qp, bool goph, ScanTab &out,
+                            TabEntry **entry = nullptr);
 // The results of a plan's last batch copied to host buffers with one stream
 // synchronisation in the usual case: the counters, the CSR offsets (n_q + 1)
 // and the first `pre` ids are read together; more ids are read only when the
