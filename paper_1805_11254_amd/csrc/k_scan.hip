@@ -238,6 +238,56 @@ __device__ __forceinline__ int64_t group_rho(uint32_t eq, uint32_t ej, uint32_t 
     return (int64_t)m * dmul[e];
 }
 
+// Bits of the EMPTY words among w[0 .. n), n <= 64; with vec (n a multiple of
+// 4, w 16-byte aligned) read as 16-byte words, four loads issued together.
+__device__ __forceinline__ uint64_t empty_bits(const uint32_t *__restrict__ w, uint32_t n, bool vec) {
+    uint64_t m = 0;
+    if (vec) {
+        const uint4 *w4 = reinterpret_cast<const uint4 *>(w);
+#pragma unroll 4
+        for (uint32_t j = 0; j < n / 4; ++j) {
+            const uint4 v = w4[j];
+            const uint32_t b = (uint32_t)(v.x == HOPH_EMPTY) | (uint32_t)(v.y == HOPH_EMPTY) << 1 |
+                               (uint32_t)(v.z == HOPH_EMPTY) << 2 | (uint32_t)(v.w == HOPH_EMPTY) << 3;
+            m |= (uint64_t)b << (4 * j);
+        }
+    } else {
+        for (uint32_t i = 0; i < n; ++i) m |= (uint64_t)(w[i] == HOPH_EMPTY) << i;
+    }
+    return m;
+}
+
+// Code planes of the ub <= 64 bins at w: bit b & 31 of lo[p] (b < 32) or hi[p]
+// (b >= 32) is bit p of bin b's code; 16-byte reads with vec as above.
+__device__ __forceinline__ void code_planes_of(const uint32_t *__restrict__ w, uint32_t ub, bool vec,
+                                               uint32_t (&lo)[kCodeBits], uint32_t (&hi)[kCodeBits]) {
+#pragma unroll
+    for (int p = 0; p < (int)kCodeBits; ++p) lo[p] = hi[p] = 0;
+    auto put = [&](uint32_t v, uint32_t b) {
+        const uint32_t c = bin_code(v), bit = b & 31;
+        if (b < 32) {
+#pragma unroll
+            for (int p = 0; p < (int)kCodeBits; ++p) lo[p] |= ((c >> p) & 1u) << bit;
+        } else {
+#pragma unroll
+            for (int p = 0; p < (int)kCodeBits; ++p) hi[p] |= ((c >> p) & 1u) << bit;
+        }
+    };
+    if (vec) {
+        const uint4 *w4 = reinterpret_cast<const uint4 *>(w);
+#pragma unroll 4
+        for (uint32_t j = 0; j < ub / 4; ++j) {
+            const uint4 v = w4[j];
+            put(v.x, 4 * j);
+            put(v.y, 4 * j + 1);
+            put(v.z, 4 * j + 2);
+            put(v.w, 4 * j + 3);
+        }
+    } else {
+        for (uint32_t b = 0; b < ub; ++b) put(w[b], b);
+    }
+}
+
 // Empty-bin mask of every (query, group): bit i set when bin i of the group is
 // EMPTY; for the first cg groups also the query's code record: the planes of
 // the group's code unit (same word order as the index's: plane p of the unit's
@@ -245,7 +295,10 @@ __device__ __forceinline__ int64_t group_rho(uint32_t eq, uint32_t ej, uint32_t 
 // planes), the group's non-empty mask (bits from 0), the first group's keep
 // threshold on codes (a pair is kept when more than this many of the query's
 // non-empty bins have equal codes: (k' - e) - ScanTab::dthr0[e], negative when
-// the first group rejects nothing) and the group's empty count e.
+// the first group rejects nothing) and the group's empty count e.  A group
+// with a record takes its empty mask from the planes (code 255, every plane
+// set, is EMPTY and nothing else); rows are read as 16-byte words when k and
+// k' are multiples of 4, and each record is written as 16-byte words.
 __global__ __launch_bounds__(kThreads) void query_masks_kernel(const uint32_t *__restrict__ qsigs, uint32_t n_q_arg,
                                                               const uint64_t *__restrict__ desc, uint32_t k,
                                                               uint32_t kp, uint32_t L, uint64_t *__restrict__ out,
@@ -256,75 +309,77 @@ __global__ __launch_bounds__(kThreads) void query_masks_kernel(const uint32_t *_
     const uint32_t W = code_plane_words(kp), PW = code_words(kp), RW = code_rec_words(kp);
     const uint32_t pk = code_pack(kp, L), ub = pk * kp;
     const uint64_t kpmask = kp >= 64 ? ~0ull : ((1ull << kp) - 1ull);
+    const bool vec = (k % 4 == 0) && (kp % 4 == 0) && ((reinterpret_cast<uintptr_t>(qsigs) & 15) == 0);
     for (uint64_t t = blockIdx.x * (uint64_t)kThreads + threadIdx.x; t < n; t += (uint64_t)gridDim.x * kThreads) {
         const uint64_t q = t / L, g = t % L;
-        const uint32_t *w = qsigs + q * k + g * kp;
-        uint64_t m = 0;
-        for (uint32_t i = 0; i < kp; ++i) m |= (uint64_t)(w[i] == HOPH_EMPTY) << i;
+        const uint32_t *row = qsigs + q * k;
+        if (!(qcodes && g < cg)) {
+            out[t] = empty_bits(row + g * kp, kp, vec);
+            continue;
+        }
+        uint32_t lo[kCodeBits], hi[kCodeBits];
+        code_planes_of(row + (g / pk) * ub, ub, vec, lo, hi);  // the group's code unit (cg <= L / pk * pk)
+        uint32_t elo = lo[0], ehi = hi[0];
+#pragma unroll
+        for (int p = 1; p < (int)kCodeBits; ++p) {
+            elo &= lo[p];
+            ehi &= hi[p];
+        }
+        const uint64_t m = ((((uint64_t)ehi << 32) | elo) >> ((g % pk) * kp)) & kpmask;
         out[t] = m;
-        if (qcodes && g < cg) {
-            const uint32_t *wu = qsigs + q * k + (g / pk) * ub;      // the group's code unit (cg <= L / pk * pk)
-            uint32_t lo[kCodeBits], hi[kCodeBits];
+        uint32_t rec[2 * kCodeBits + 8];         // code_rec_words for two plane words
 #pragma unroll
-            for (int p = 0; p < (int)kCodeBits; ++p) lo[p] = hi[p] = 0;
-            for (uint32_t b = 0; b < ub; ++b) {
-                const uint32_t c = bin_code(wu[b]), bit = b & 31;
-                if (b < 32) {
-#pragma unroll
-                    for (int p = 0; p < (int)kCodeBits; ++p) lo[p] |= ((c >> p) & 1u) << bit;
-                } else {
-#pragma unroll
-                    for (int p = 0; p < (int)kCodeBits; ++p) hi[p] |= ((c >> p) & 1u) << bit;
+        for (int p = 0; p < (int)kCodeBits; ++p) {
+            rec[p * W] = lo[p];
+            if (W == 2) rec[p * W + 1] = hi[p];
+        }
+        const uint64_t nqm = ~m & kpmask;
+        const uint32_t e = (uint32_t)__popcll(m);
+        rec[PW + 0] = (uint32_t)nqm;
+        rec[PW + 1] = (uint32_t)(nqm >> 32);
+        rec[PW + 2] = (uint32_t)((int32_t)(kp - e) - thr.dthr[e]);   // keep iff more agreeing bins
+        rec[PW + 3] = e;
+        uint32_t lc = 0, lz = 0xFFFFFFFFu, ly = 0x7FFFFFFFu;
+        if (g < lin.steps) {
+            // linear bound of step g (see LinTab): sums over this query's groups 0..g
+            int64_t sum_ck = 0, sum_cn = 0;
+            for (uint32_t h = 0; h <= g; ++h) {
+                const uint32_t eh = h == g ? e : (uint32_t)__popcll(empty_bits(row + h * kp, kp, vec));
+                int64_t c, ck;
+                if (lin.policy == HOPH_EMPTY_LITERAL) {
+                    c = eh < kp ? lin.W[h] : 0;
+                    ck = lin.W[h] * (int64_t)(kp - eh);
+                } else {                      // JOINT: C (k' - e) = W lambda
+                    c = eh < kp ? lin.W[h] * lin.dmul[eh] : 0;
+                    ck = lin.W[h] * lin.lambda;
                 }
+                sum_ck += ck;
+                const int64_t ch = c >> lin.shift;
+                sum_cn += ch * (int64_t)(kp - eh);
+                if (h == g) lc = (uint32_t)ch;
             }
-            uint32_t *dst = qcodes + (q * cg + g) * RW;
+            // the tests on st = sum c_h dn_h, restated on the agreeing counts
+            // st' = sum c_h (k' - e_h - dn_h) = sum_cn - st (below 2^31)
+            const int64_t one = (int64_t)1 << lin.shift;
+            if (lin.rej[g] >= 0) {
+                const int64_t Z = sum_ck - lin.rej[g];
+                const int64_t zc = Z <= 0 ? 0 : (Z + one - 1) >> lin.shift;   // reject: st >= zc
+                lz = zc <= sum_cn ? (uint32_t)(sum_cn - zc) : 0xFFFFFFFFu;
+            }
+            const int64_t Y = sum_ck - lin.acc[g];
+            if (Y >= 0) ly = (uint32_t)(int32_t)(sum_cn - min<int64_t>(Y >> lin.shift, sum_cn + 0x7FFFFFFFll));
+        }
+        rec[PW + 4] = lc;
+        rec[PW + 5] = lz;
+        rec[PW + 6] = ly;
+        rec[PW + 7] = 0;
+        uint4 *dst = reinterpret_cast<uint4 *>(qcodes + (q * cg + g) * RW);   // RW is a multiple of 4
+        if (W == 1) {
 #pragma unroll
-            for (int p = 0; p < (int)kCodeBits; ++p) {
-                dst[p * W] = lo[p];
-                if (W == 2) dst[p * W + 1] = hi[p];
-            }
-            const uint64_t nqm = ~m & kpmask;
-            const uint32_t e = (uint32_t)__popcll(m);
-            dst[PW + 0] = (uint32_t)nqm;
-            dst[PW + 1] = (uint32_t)(nqm >> 32);
-            dst[PW + 2] = (uint32_t)((int32_t)(kp - e) - thr.dthr[e]);   // keep iff more agreeing bins
-            dst[PW + 3] = e;
-            uint32_t lc = 0, lz = 0xFFFFFFFFu, ly = 0x7FFFFFFFu;
-            if (g < lin.steps) {
-                // linear bound of step g (see LinTab): sums over this query's groups 0..g
-                int64_t sum_ck = 0, sum_cn = 0;
-                for (uint32_t h = 0; h <= g; ++h) {
-                    uint32_t eh = 0;
-                    const uint32_t *wh = qsigs + q * k + h * kp;
-                    for (uint32_t i = 0; i < kp; ++i) eh += wh[i] == HOPH_EMPTY ? 1u : 0u;
-                    int64_t c, ck;
-                    if (lin.policy == HOPH_EMPTY_LITERAL) {
-                        c = eh < kp ? lin.W[h] : 0;
-                        ck = lin.W[h] * (int64_t)(kp - eh);
-                    } else {                      // JOINT: C (k' - e) = W lambda
-                        c = eh < kp ? lin.W[h] * lin.dmul[eh] : 0;
-                        ck = lin.W[h] * lin.lambda;
-                    }
-                    sum_ck += ck;
-                    const int64_t ch = c >> lin.shift;
-                    sum_cn += ch * (int64_t)(kp - eh);
-                    if (h == g) lc = (uint32_t)ch;
-                }
-                // the tests on st = sum c_h dn_h, restated on the agreeing counts
-                // st' = sum c_h (k' - e_h - dn_h) = sum_cn - st (below 2^31)
-                const int64_t one = (int64_t)1 << lin.shift;
-                if (lin.rej[g] >= 0) {
-                    const int64_t Z = sum_ck - lin.rej[g];
-                    const int64_t zc = Z <= 0 ? 0 : (Z + one - 1) >> lin.shift;   // reject: st >= zc
-                    lz = zc <= sum_cn ? (uint32_t)(sum_cn - zc) : 0xFFFFFFFFu;
-                }
-                const int64_t Y = sum_ck - lin.acc[g];
-                if (Y >= 0) ly = (uint32_t)(int32_t)(sum_cn - min<int64_t>(Y >> lin.shift, sum_cn + 0x7FFFFFFFll));
-            }
-            dst[PW + 4] = lc;
-            dst[PW + 5] = lz;
-            dst[PW + 6] = ly;
-            dst[PW + 7] = 0;
+            for (int j = 0; j < 4; ++j) dst[j] = make_uint4(rec[4 * j], rec[4 * j + 1], rec[4 * j + 2], rec[4 * j + 3]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 6; ++j) dst[j] = make_uint4(rec[4 * j], rec[4 * j + 1], rec[4 * j + 2], rec[4 * j + 3]);
         }
     }
 }
@@ -1888,7 +1943,7 @@ hipError_t launch_query_masks(const uint32_t *qsigs, uint32_t n_q, const uint64_
     const uint64_t n = (uint64_t)n_q * L;         // n_q: the batch size, or its upper bound with desc
     if (n == 0) return hipSuccess;
     uint64_t blocks = (n + kThreads - 1) / kThreads;
-    if (blocks > 4096) blocks = 4096;
+    if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(query_masks_kernel, dim3((uint32_t)blocks), dim3(kThreads), 0, st, qsigs, n_q, desc, k, kp, L,
                        out, qcodes, cg, t, lt);
     return hipGetLastError();

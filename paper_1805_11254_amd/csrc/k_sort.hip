@@ -150,44 +150,72 @@ __global__ __launch_bounds__(kThreads) void seg_count_kernel(const uint64_t *__r
 
 // One workgroup: exclusive scan of qcount[0..n_q) into offsets[0..n_q] and
 // cursor[0..n_q); flags bit 0: a query has more than seg_max ids; bit 1: the
-// total exceeds out_cap.  counters[2] receives the total.
+// total exceeds out_cap.  counters[2] receives the total.  Chunks of
+// 4 kScanThreads counts: each thread reads four consecutive counts (one 16-byte
+// load where the chunk is whole), a wavefront scans its threads' sums with
+// shuffles, and the wavefront totals are combined through LDS (two barriers
+// per chunk).
 __global__ __launch_bounds__(kScanThreads) void seg_scan_kernel(const uint32_t *__restrict__ qcount,
                                                                const uint64_t *__restrict__ desc, uint32_t n_q_arg,
                                                                uint64_t *__restrict__ offsets,
                                                                uint64_t *__restrict__ cursor, uint64_t out_cap,
                                                                uint64_t *__restrict__ counters, uint32_t seg_max) {
-    __shared__ uint64_t s_part[kScanThreads];
-    __shared__ uint64_t s_carry;
+    constexpr uint32_t kW = kScanThreads / 64;
+    __shared__ uint64_t s_w[kW];
     __shared__ uint32_t s_big;
     const uint32_t n_q = nq_of(desc, n_q_arg);
-    const uint32_t t = threadIdx.x;
-    if (t == 0) { s_carry = 0; s_big = 0; }
-    __syncthreads();
-    for (uint32_t base = 0; base < n_q; base += kScanThreads) {
-        const uint32_t q = base + t;
-        const uint64_t v = q < n_q ? qcount[q] : 0;
-        if (v > seg_max) atomicOr(&s_big, 1u);
-        s_part[t] = v;
-        __syncthreads();
-        for (uint32_t d = 1; d < kScanThreads; d <<= 1) {     // inclusive Hillis-Steele scan
-            const uint64_t add = t >= d ? s_part[t - d] : 0;
-            __syncthreads();
-            s_part[t] += add;
-            __syncthreads();
+    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (t == 0) s_big = 0;
+    uint64_t carry = 0;
+    uint32_t big = 0;
+    for (uint64_t base = 0; base < n_q; base += 4ull * kScanThreads) {
+        const uint64_t q0 = base + 4ull * t;
+        uint32_t a[4] = {0, 0, 0, 0};
+        if (q0 + 4 <= n_q) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(qcount + q0);   // qcount is 16-byte aligned
+            a[0] = v.x;
+            a[1] = v.y;
+            a[2] = v.z;
+            a[3] = v.w;
+        } else {
+            for (uint32_t i = 0; i < 4; ++i)
+                if (q0 + i < n_q) a[i] = qcount[q0 + i];
         }
-        const uint64_t excl = s_carry + s_part[t] - v;
-        if (q < n_q) {
-            offsets[q] = excl;
-            cursor[q] = excl;
+        uint64_t tsum = 0;
+        for (uint32_t i = 0; i < 4; ++i) {
+            big |= a[i] > seg_max ? 1u : 0u;
+            tsum += a[i];
         }
+        uint64_t inc = tsum;                                  // inclusive scan over the wavefront
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint64_t o = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += o;
+        }
+        if (lane == 63) s_w[wv] = inc;
         __syncthreads();
-        if (t == kScanThreads - 1) s_carry += s_part[t];
-        __syncthreads();
+        uint64_t before = 0, chunk = 0;
+        for (uint32_t w = 0; w < kW; ++w) {
+            const uint64_t x = s_w[w];
+            before += w < wv ? x : 0;
+            chunk += x;
+        }
+        uint64_t run = carry + before + inc - tsum;
+        for (uint32_t i = 0; i < 4; ++i) {
+            if (q0 + i < n_q) {
+                offsets[q0 + i] = run;
+                cursor[q0 + i] = run;
+            }
+            run += a[i];
+        }
+        carry += chunk;
+        __syncthreads();                                      // s_w is rewritten by the next chunk
     }
+    if (big) atomicOr(&s_big, 1u);
+    __syncthreads();
     if (t == 0) {
-        offsets[n_q] = s_carry;
-        counters[2] = s_carry;
-        counters[3] = (s_big ? 1ull : 0ull) | (s_carry > out_cap ? 2ull : 0ull);
+        offsets[n_q] = carry;
+        counters[2] = carry;
+        counters[3] = (s_big ? 1ull : 0ull) | (carry > out_cap ? 2ull : 0ull);
     }
 }
 
