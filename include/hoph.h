@@ -300,7 +300,9 @@ hoph_status query_hoph(const hoph_index *index, const uint32_t *d_qsigs, uint32_
    is set) and about 3.1 million first-pass survivors for any one query.  Calls
    on one device are serialised by the library (each finishes, stream
    synchronised, before the next starts); calls on different devices run
-   independently.  Synchronises hip_stream. */
+   independently.  Its pair counts and coarse-pass shape are not reported
+   through hoph_query_counts or hoph_coarse_plan (they describe the index's own
+   calls).  Synchronises hip_stream. */
 hoph_status query_hoph_noalloc(const hoph_index *index, const uint32_t *d_qsigs, uint32_t n_q,
                                const hoph_query_params *qp, hoph_results *results, void *hip_stream);
 
