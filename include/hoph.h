@@ -537,7 +537,10 @@ hoph_status hoph_selftest_bins(const hoph_sketch_params *params, const uint32_t 
  * Alg. 2) comparison accepts, as CSR over the rows: for row i, the ascending j > i
  * in d_set_ids[d_offsets[i] .. d_offsets[i+1]); d_offsets has size + 1 entries.
  * The decision is symmetric, so the pair (j, i) is not repeated.  Errors and
- * capacity reporting as for query_hoph.  Synchronises the stream.
+ * capacity reporting as for query_hoph.  Synchronises the stream (on the first
+ * call with given parameters, and after the index size changes twofold, also
+ * once to read 512 rows' first code planes back, whose pair agreement picks the
+ * coarse kernel; hoph_coarse_plan reports the choice).
  */
 hoph_status hoph_self_join(const hoph_index *index, const hoph_query_params *qp,
                            hoph_results *results, void *hip_stream);
