@@ -708,8 +708,9 @@ __global__ __launch_bounds__(64) void scan_codes_deep_kernel(const uint32_t *__r
 
 // The self-join's (tile group, query chunk) items that hold a set id above the
 // chunk's first query row: the tile groups of chunk c start at first(c), and
-// the items are numbered chunk by chunk, so that a persistent grid spreads the
-// upper triangle's work evenly instead of stepping over the items below it.
+// the items are numbered chunk by chunk, so that consecutive wavefronts take
+// consecutive items of the upper triangle (wavefronts past the item count exit
+// at once) instead of half of them landing on items below the diagonal.
 struct TriItems {
     uint64_t ngroups, span;         // tile groups, sets per tile group
     uint32_t q_lo, qpw, nchunks;
