@@ -293,3 +293,33 @@ def test_server_admission_by_memory(bovw):
                    max_batch_results=4096, device_mem_budget=2 * st["slot_bytes"] + 1)
     assert two.stats()["slots"] == 2
     two.close()
+
+
+def test_coarse_plan_report():
+    """hoph_coarse_plan follows the last call on the index: nothing before any
+    query and after an empty batch, the first-group code kernels for a
+    first-group pass (the light one for a self-join with one plane word), the
+    word pass with COARSE_WORDS, the plain OPH comparator's pass, and the
+    same shape from hoph_scan_timing as from the query it times."""
+    w = W.hoph_bovw(n=3_000, n_q=40, seed=71, planted_frac=0.05)
+    p = params_of(w)
+    ids, offs = dev_csr(w.collection)
+    qids, qoffs = dev_csr(w.queries)
+    idx = H.Index(p, H.sketch_oph(p, ids, offs))
+    qsig = H.sketch_oph(p, qids, qoffs)
+    assert idx.last_coarse_plan() == (0, "none", 0, 0)
+    H.query_hoph(idx, qsig, T=w.T, eps=w.eps)
+    depth, kernel, planes, tiles = idx.last_coarse_plan()
+    assert depth == 1 and kernel in ("first_group", "first_group_light") and tiles >= 1, (depth, kernel)
+    assert H.scan_timing(idx, qsig, T=w.T, eps=w.eps, reps=2) > 0
+    assert idx.last_coarse_plan() == (depth, kernel, planes, tiles)
+    H.query_hoph(idx, qsig, T=w.T, eps=w.eps, coarse=H.COARSE_WORDS)
+    assert idx.last_coarse_plan()[1] == "words"
+    H.query_oph_full(idx, qsig, T=w.T)
+    assert idx.last_coarse_plan()[:2] == (0, "oph_full")
+    H.self_join(idx, T=w.T, eps=w.eps)
+    depth, kernel, planes, tiles = idx.last_coarse_plan()
+    assert depth == 1 and (kernel == "first_group_light" or (kernel == "first_group" and planes == 0)), kernel
+    H.query_hoph(idx, qsig[:0], T=w.T, eps=w.eps)
+    assert idx.last_coarse_plan() == (0, "none", 0, 0)
+    idx.free()
