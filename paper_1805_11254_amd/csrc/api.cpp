@@ -368,16 +368,37 @@ hoph_status run_query_impl(const hoph_index *cidx, Workspace *ws_in, const uint3
         HOPH_HIP(launch_fill_u64(ws.counters, 4, 0, s), "fill counters");
         st = pass(0, n_q);
         if (st) return st;
-        HOPH_HIP(launch_segmented_output(ws.keys, ws.counters, ws.keys_cap, ws.qcount, nullptr, n_q, res->d_offsets,
-                                         ws.cursor, res->d_set_ids, res->capacity, ws.counters, n_q, ws.keys_cap,
-                                         kSegMaxPlan, s),
-                 "output launch");
+        // a batch of up to kSmallOutQueries queries tries the one-workgroup output
+        // stage first (one launch instead of five); it leaves counters[3] = 4 when
+        // more keys were accepted than it sorts, and the general stage follows
+        auto general_output = [&]() {
+            return launch_segmented_output(ws.keys, ws.counters, ws.keys_cap, ws.qcount, nullptr, n_q,
+                                           res->d_offsets, ws.cursor, res->d_set_ids, res->capacity, ws.counters,
+                                           n_q, ws.keys_cap, kSegMaxPlan, s);
+        };
+        if (n_q <= kSmallOutQueries) {
+            HOPH_HIP(launch_small_output(ws.keys, ws.counters, ws.keys_cap, n_q, res->d_offsets, res->d_set_ids,
+                                         res->capacity, s),
+                     "output launch");
+        } else {
+            HOPH_HIP(general_output(), "output launch");
+        }
         if (timed_ev) HOPH_HIP(hipEventRecord(ws.ev[3], s), "hipEventRecord");
         HOPH_HIP(hipMemcpyAsync(ws.h_counters, ws.counters, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, s),
                  "hipMemcpyAsync(counters)");
         HOPH_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
-        const uint64_t surv = ws.h_counters[0], acc = ws.h_counters[1], flags = ws.h_counters[3];
-        if (surv <= ws.surv_cap && acc <= ws.keys_cap && acc <= res->capacity && (flags & 3ull) == 0) {
+        const uint64_t surv = ws.h_counters[0], acc = ws.h_counters[1];
+        const bool fits = surv <= ws.surv_cap && acc <= ws.keys_cap && acc <= res->capacity;
+        if (fits && (ws.h_counters[3] & 4ull)) {
+            HOPH_HIP(general_output(), "output launch");
+            if (timed_ev) HOPH_HIP(hipEventRecord(ws.ev[3], s), "hipEventRecord");
+            HOPH_HIP(hipMemcpyAsync(ws.h_counters + 2, ws.counters + 2, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                                    s),
+                     "hipMemcpyAsync(flags)");
+            HOPH_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+        }
+        const uint64_t flags = ws.h_counters[3];
+        if (fits && (flags & 7ull) == 0) {
             res->needed = acc;
             ws.last_counts[0] = surv;
             ws.last_counts[1] = acc;

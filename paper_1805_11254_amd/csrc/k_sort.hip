@@ -265,7 +265,67 @@ __global__ __launch_bounds__(kThreads) void seg_sort_kernel(const uint64_t *__re
     }
 }
 
+// One workgroup: the whole output stage of a batch with at most kSmallOutKeys
+// accepted keys (query row << 32 | set id): the keys sorted in LDS (bitonic),
+// which orders them by row and then by set id, each row's offset found by a
+// binary search for its first key, the ids written in that order, and
+// counters[2] = the total, counters[3] = 2 when it exceeds out_cap.  More
+// keys (or more than keys_cap) write nothing but counters[3] = 4, and the
+// caller runs the general stage.
+__global__ __launch_bounds__(kScanThreads) void seg_small_kernel(const uint64_t *__restrict__ keys,
+                                                                uint64_t *__restrict__ counters, uint64_t keys_cap,
+                                                                uint32_t n_q, uint64_t *__restrict__ offsets,
+                                                                uint32_t *__restrict__ ids, uint64_t out_cap) {
+    __shared__ uint64_t s[kSmallOutKeys];
+    const uint32_t t = threadIdx.x;
+    const uint64_t acc = counters[1];
+    if (acc > kSmallOutKeys || acc > keys_cap) {         // uniform: every thread reads the same count
+        if (t == 0) counters[3] = 4;
+        return;
+    }
+    const uint32_t A = (uint32_t)acc;
+    uint32_t N = 2;
+    while (N < A) N <<= 1;
+    for (uint32_t i = t; i < N; i += kScanThreads) s[i] = i < A ? keys[i] : ~0ull;
+    __syncthreads();
+    for (uint32_t k = 2; k <= N; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t u = t; u < N / 2; u += kScanThreads) {
+                const uint32_t i = 2 * u - (u & (j - 1));
+                const uint64_t x = s[i], y = s[i + j];
+                if ((x > y) == ((i & k) == 0)) {
+                    s[i] = y;
+                    s[i + j] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t q = t; q <= n_q; q += kScanThreads) {
+        const uint64_t first = (uint64_t)q << 32;          // row q's first key is the first >= this
+        uint32_t lo = 0, hi = A;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s[mid] < first) lo = mid + 1;
+            else hi = mid;
+        }
+        offsets[q] = lo;
+    }
+    for (uint32_t i = t; i < A && i < out_cap; i += kScanThreads) ids[i] = (uint32_t)(s[i] & 0xFFFFFFFFull);
+    if (t == 0) {
+        counters[2] = A;
+        counters[3] = A > out_cap ? 2ull : 0ull;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_small_output(const uint64_t *keys, uint64_t *counters, uint64_t keys_cap, uint32_t n_q,
+                               uint64_t *offsets, uint32_t *ids, uint64_t out_cap, hipStream_t st) {
+    hipLaunchKernelGGL(seg_small_kernel, dim3(1), dim3(kScanThreads), 0, st, keys, counters, keys_cap, n_q, offsets,
+                       ids, out_cap);
+    return hipGetLastError();
+}
 
 hipError_t launch_segmented_output(const uint64_t *keys, const uint64_t *counters_ro, uint64_t keys_cap,
                                    uint32_t *qcount, const uint64_t *desc, uint32_t n_q, uint64_t *offsets,

@@ -190,6 +190,43 @@ def test_first_group_plane_splits_match_oracle(ra, rb, Ts):
     idx.free()
 
 
+@pytest.mark.parametrize("copies", [2_047, 2_048, 2_049, 4_100])
+def test_output_stage_around_its_one_workgroup_limit(copies):
+    """Batches whose accepted pairs fall just below, at and above the 2,048 keys
+    the one-workgroup output stage sorts (above it the general stage runs):
+    collections holding `copies` copies of two query sets among other sets, one
+    and two queries per batch, CSR lists equal to the oracle's; with too small
+    a result capacity the call reports the count it needs."""
+    _print_case(f"output stage, {copies} copies")
+    rng = np.random.default_rng(copies)
+    qa = np.sort(rng.choice(1 << 20, size=60, replace=False)).astype(np.uint32)
+    qb = np.sort(rng.choice(1 << 20, size=90, replace=False)).astype(np.uint32)
+    sets = []
+    for i in range(copies):
+        sets.append(qa if i % 2 == 0 else qb)
+        if i % 3 == 0:
+            sets.append(np.sort(rng.choice(1 << 20, size=int(rng.integers(20, 200)), replace=False)).astype(np.uint32))
+    coll = W.csr_from_lists(sets)
+    a, b = W.hash_coeffs(W.P31, 1, 77)
+    for qsets in ([qa], [qa, qb]):
+        qs = W.csr_from_lists(qsets)
+        w = W.Workload("copies", coll, qs, 1 << 20, W.HASH_MODP31, W.LAYOUT_HIER, 256, 32, ha=int(a[0]), hb=int(b[0]))
+        p = params_of(w)
+        sig = gpu_sketch(w, coll, p)
+        qsig = gpu_sketch(w, qs, p)
+        idx = H.Index(p, sig)
+        oo, oi = oracle_query(w, oracle_sketch(w, coll), oracle_sketch(w, qs), w.T, w.eps, H.EMPTY_JOINT)
+        go, gi = gpu_query("hoph", idx, qsig, w.T, w.eps, H.EMPTY_JOINT)
+        assert go.tolist() == oo.tolist() and gi.tolist() == oi.tolist(), (copies, len(qsets))
+        assert len(oi) >= copies // 2
+        with pytest.raises(H.HophError) as e:
+            H.query_hoph(idx, qsig, T=w.T, eps=w.eps, capacity=len(oi) - 1)
+        assert e.value.status == H.HOPH_E_CAPACITY and e.value.needed == len(oi)
+        _, exact = H.query_hoph(idx, qsig, T=w.T, eps=w.eps, capacity=len(oi))
+        assert exact.tolist() == oi.tolist()
+        idx.free()
+
+
 def test_modp32_top_of_range_signatures():
     """Sets whose ids hash to the top of the (a x + b) mod (2^32 + 15) range
     (2^32 - 3 .. 2^32 + 14, the values the sketch's 32-bit view clamps): every
