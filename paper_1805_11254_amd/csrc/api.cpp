@@ -376,7 +376,10 @@ hoph_status run_query_impl(const hoph_index *cidx, Workspace *ws_in, const uint3
                                            res->d_offsets, ws.cursor, res->d_set_ids, res->capacity, ws.counters,
                                            n_q, ws.keys_cap, kSegMaxPlan, s);
         };
-        if (n_q <= kSmallOutQueries) {
+        // (skipped when the workspace's last batch, scaled to this one, accepted
+        // more pairs than it sorts: that saves a second read-back)
+        const uint64_t expect = ws.last_nq ? ws.last_counts[1] * n_q / ws.last_nq : 0;
+        if (n_q <= kSmallOutQueries && expect <= kSmallOutKeys) {
             HOPH_HIP(launch_small_output(ws.keys, ws.counters, ws.keys_cap, n_q, res->d_offsets, res->d_set_ids,
                                          res->capacity, s),
                      "output launch");
@@ -402,6 +405,7 @@ hoph_status run_query_impl(const hoph_index *cidx, Workspace *ws_in, const uint3
             res->needed = acc;
             ws.last_counts[0] = surv;
             ws.last_counts[1] = acc;
+            ws.last_nq = n_q;
             std::memcpy(ws.last_plan, plan, sizeof(plan));
             record_timing();
             return HOPH_OK;
@@ -480,6 +484,7 @@ hoph_status run_query_impl(const hoph_index *cidx, Workspace *ws_in, const uint3
     HOPH_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
     ws.last_counts[0] = survivors;
     ws.last_counts[1] = accepted;
+    ws.last_nq = n_q;
     std::memcpy(ws.last_plan, plan, sizeof(plan));
     ws.last_ms[0] = ws.last_ms[1] = ws.last_ms[2] = 0.f;
     if (timed && timed_ev) {

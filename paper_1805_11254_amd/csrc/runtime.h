@@ -68,6 +68,7 @@ struct Workspace {
     bool aev_recorded = false;
     float last_ms[3] = {0, 0, 0};
     uint64_t last_counts[2] = {0, 0};   // survivors of the coarse pass, accepted pairs
+    uint32_t last_nq = 0;                // queries of that batch
     uint32_t last_plan[4] = {0, 0, 0, 0};   // the coarse pass's shape (hoph_coarse_plan)
     void release() {
         if (fixed) return;                 // a view: nothing of its own to free
