@@ -279,7 +279,10 @@ void hoph_index_free(hoph_index *index);
  * group.  Requires an index built with HOPH_LAYOUT_OPH.
  * Returns HOPH_E_CAPACITY (with results->needed) if capacity is too small;
  * HOPH_E_UNSUPPORTED if the exact state does not fit 64 bits.
- * Synchronises hip_stream once; the CSR output is complete on return.
+ * Synchronises hip_stream (once in the usual case; again when the batch
+ * accepted more pairs than the one-workgroup output stage sorts, or when a
+ * buffer overflowed and the batch is redone); the CSR output is complete on
+ * return.
  */
 hoph_status query_goph(const hoph_index *index, const uint32_t *d_qsigs, uint32_t n_q,
                        const hoph_query_params *qp, hoph_results *results, void *hip_stream);
