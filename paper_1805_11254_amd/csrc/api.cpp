@@ -380,8 +380,8 @@ hoph_status run_query_impl(const hoph_index *cidx, Workspace *ws_in, const uint3
         // more pairs than it sorts: that saves a second read-back)
         const uint64_t expect = ws.last_nq ? ws.last_counts[1] * n_q / ws.last_nq : 0;
         if (n_q <= kSmallOutQueries && expect <= kSmallOutKeys) {
-            HOPH_HIP(launch_small_output(ws.keys, ws.counters, ws.keys_cap, n_q, res->d_offsets, res->d_set_ids,
-                                         res->capacity, s),
+            HOPH_HIP(launch_small_output(ws.keys, ws.counters, ws.keys_cap, nullptr, n_q, res->d_offsets,
+                                         res->d_set_ids, res->capacity, s),
                      "output launch");
         } else {
             HOPH_HIP(general_output(), "output launch");

@@ -557,11 +557,12 @@ hipError_t launch_segmented_output(const uint64_t *keys, const uint64_t *counter
 // The output stage in one workgroup for a batch of up to kSmallOutKeys
 // accepted keys (counters[1], read on the device): the same CSR, counters[2]
 // and counters[3] bit 1 as launch_segmented_output; with more keys it writes
-// nothing but counters[3] = 4 (run launch_segmented_output then).
+// nothing but counters[3] = 4 (run launch_segmented_output then).  desc
+// (nullable): desc[0] = n_q, read on the device.
 constexpr uint32_t kSmallOutKeys = 2048;
 constexpr uint32_t kSmallOutQueries = 4096;
-hipError_t launch_small_output(const uint64_t *keys, uint64_t *counters, uint64_t keys_cap, uint32_t n_q,
-                               uint64_t *offsets, uint32_t *ids, uint64_t out_cap, hipStream_t st);
+hipError_t launch_small_output(const uint64_t *keys, uint64_t *counters, uint64_t keys_cap, const uint64_t *desc,
+                               uint32_t n_q, uint64_t *offsets, uint32_t *ids, uint64_t out_cap, hipStream_t st);
 hipError_t launch_results(const uint64_t *keys, uint64_t n, uint32_t n_q, uint64_t *offsets,
                           uint32_t *set_ids, hipStream_t st);
 hipError_t launch_minwise_sketch(uint32_t k, uint32_t hash, uint64_t universe, const uint64_t *ha,

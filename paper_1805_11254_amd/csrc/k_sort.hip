@@ -274,10 +274,12 @@ __global__ __launch_bounds__(kThreads) void seg_sort_kernel(const uint64_t *__re
 // caller runs the general stage.
 __global__ __launch_bounds__(kScanThreads) void seg_small_kernel(const uint64_t *__restrict__ keys,
                                                                 uint64_t *__restrict__ counters, uint64_t keys_cap,
-                                                                uint32_t n_q, uint64_t *__restrict__ offsets,
+                                                                const uint64_t *__restrict__ desc, uint32_t n_q_arg,
+                                                                uint64_t *__restrict__ offsets,
                                                                 uint32_t *__restrict__ ids, uint64_t out_cap) {
     __shared__ uint64_t s[kSmallOutKeys];
     const uint32_t t = threadIdx.x;
+    const uint32_t n_q = nq_of(desc, n_q_arg);
     const uint64_t acc = counters[1];
     if (acc > kSmallOutKeys || acc > keys_cap) {         // uniform: every thread reads the same count
         if (t == 0) counters[3] = 4;
@@ -320,10 +322,10 @@ __global__ __launch_bounds__(kScanThreads) void seg_small_kernel(const uint64_t 
 
 }  // namespace
 
-hipError_t launch_small_output(const uint64_t *keys, uint64_t *counters, uint64_t keys_cap, uint32_t n_q,
-                               uint64_t *offsets, uint32_t *ids, uint64_t out_cap, hipStream_t st) {
-    hipLaunchKernelGGL(seg_small_kernel, dim3(1), dim3(kScanThreads), 0, st, keys, counters, keys_cap, n_q, offsets,
-                       ids, out_cap);
+hipError_t launch_small_output(const uint64_t *keys, uint64_t *counters, uint64_t keys_cap, const uint64_t *desc,
+                               uint32_t n_q, uint64_t *offsets, uint32_t *ids, uint64_t out_cap, hipStream_t st) {
+    hipLaunchKernelGGL(seg_small_kernel, dim3(1), dim3(kScanThreads), 0, st, keys, counters, keys_cap, desc, n_q,
+                       offsets, ids, out_cap);
     return hipGetLastError();
 }
 

@@ -190,11 +190,40 @@ hoph_status enqueue_scan(hoph_plan *p, const PlanShape &s, hipStream_t st, bool 
     return HOPH_OK;
 }
 
-hoph_status enqueue_output(hoph_plan *p, hipStream_t st) {
+// The general output stage (counts, scan, scatter, per-query sort).
+hoph_status enqueue_general_output(hoph_plan *p, hipStream_t st) {
     HOPH_HIP(launch_segmented_output(p->keys, p->counters, p->keys_cap, p->qcount, p->desc, p->cfg.max_queries,
                                      p->out_offsets, p->cursor, p->out_ids, p->cfg.max_results, p->counters,
                                      p->cfg.max_queries, p->keys_cap, kSegMaxPlan, st),
              "output launch");
+    return HOPH_OK;
+}
+
+// Plans of up to kSmallOutQueries queries end with the one-workgroup output
+// stage; a batch that accepted more pairs than it sorts leaves counters[3] = 4
+// and gets the general stage when its results are read (finish_output).
+hoph_status enqueue_output(hoph_plan *p, hipStream_t st) {
+    if (p->cfg.max_queries > kSmallOutQueries) return enqueue_general_output(p, st);
+    HOPH_HIP(launch_small_output(p->keys, p->counters, p->keys_cap, p->desc, p->cfg.max_queries, p->out_offsets,
+                                 p->out_ids, p->cfg.max_results, st),
+             "output launch");
+    return HOPH_OK;
+}
+
+// After the counters of a batch were read into h_counters: when the
+// one-workgroup stage left the output to the general stage and nothing
+// overflowed, run it and read counters[2..3] again (synchronises st); true
+// when it ran.
+hoph_status finish_output(hoph_plan *p, hipStream_t st, bool &ran) {
+    ran = false;
+    const uint64_t surv = p->h_counters[0], acc = p->h_counters[1];
+    if (!(p->h_counters[3] & 4ull) || surv > p->surv_cap || acc > p->keys_cap) return HOPH_OK;
+    hoph_status r = enqueue_general_output(p, st);
+    if (r) return r;
+    HOPH_HIP(hipMemcpyAsync(p->h_counters + 2, p->counters + 2, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, st),
+             "read counters");
+    HOPH_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    ran = true;
     return HOPH_OK;
 }
 
@@ -424,9 +453,12 @@ hoph_status hoph_plan_results(hoph_plan *p, const uint64_t **d_offsets, const ui
     HOPH_HIP(hipMemcpyAsync(p->h_counters, p->counters, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, st),
              "read counters");
     HOPH_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    bool general = false;
+    hoph_status fo = finish_output(p, st, general);
+    if (fo) return fo;
     const uint64_t surv = p->h_counters[0], acc = p->h_counters[1], total = p->h_counters[2], flags = p->h_counters[3];
     *n_results = total;
-    const bool exact = surv <= p->surv_cap && acc <= p->keys_cap && (flags & 3ull) == 0;
+    const bool exact = surv <= p->surv_cap && acc <= p->keys_cap && (flags & 7ull) == 0;
     if (!exact) {
         // redo on the host-synchronised path with the batch's signatures
         p->note_fallback(surv, acc, flags);
@@ -513,9 +545,15 @@ hoph_status plan_results_to_host(hoph_plan *p, uint64_t *h_offsets, uint32_t *h_
              "read result offsets");
     if (pre) HOPH_HIP(hipMemcpyAsync(h_ids, p->out_ids, pre * 4, hipMemcpyDeviceToHost, st), "read result ids");
     HOPH_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    bool general = false;
+    hoph_status fo = finish_output(p, st, general);
+    if (fo) return fo;
     const uint64_t surv = p->h_counters[0], acc = p->h_counters[1], total = p->h_counters[2], flags = p->h_counters[3];
-    uint64_t n = total, have = pre;
-    if (!(surv <= p->surv_cap && acc <= p->keys_cap && (flags & 3ull) == 0)) {
+    uint64_t n = total, have = general ? 0 : pre;     // ids read early are stale once the general stage ran
+    if (general)
+        HOPH_HIP(hipMemcpyAsync(h_offsets, p->out_offsets, ((uint64_t)n_q + 1) * 8, hipMemcpyDeviceToHost, st),
+                 "read result offsets");
+    if (!(surv <= p->surv_cap && acc <= p->keys_cap && (flags & 7ull) == 0)) {
         // redo on the host-synchronised path with the batch's signatures
         p->note_fallback(surv, acc, flags);
         hoph_results r{p->out_offsets, p->out_ids, p->cfg.max_results, 0};

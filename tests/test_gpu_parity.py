@@ -195,8 +195,9 @@ def test_output_stage_around_its_one_workgroup_limit(copies):
     """Batches whose accepted pairs fall just below, at and above the 2,048 keys
     the one-workgroup output stage sorts (above it the general stage runs):
     collections holding `copies` copies of two query sets among other sets, one
-    and two queries per batch, CSR lists equal to the oracle's; with too small
-    a result capacity the call reports the count it needs."""
+    and two queries per batch, CSR lists equal to the oracle's, through
+    query_hoph and through a batched plan (eager and graph-captured); with too
+    small a result capacity the call reports the count it needs."""
     _print_case(f"output stage, {copies} copies")
     rng = np.random.default_rng(copies)
     qa = np.sort(rng.choice(1 << 20, size=60, replace=False)).astype(np.uint32)
@@ -224,6 +225,18 @@ def test_output_stage_around_its_one_workgroup_limit(copies):
         assert e.value.status == H.HOPH_E_CAPACITY and e.value.needed == len(oi)
         _, exact = H.query_hoph(idx, qsig, T=w.T, eps=w.eps, capacity=len(oi))
         assert exact.tolist() == oi.tolist()
+        # a batched plan (eager and graph-captured): the same lists, and no batch
+        # redone on the host path (the general stage follows within the plan)
+        qi, qo = dev_csr(qs)
+        for graph in (False, True):
+            plan = H.Plan(idx, p, T=w.T, eps=w.eps, max_queries=4, max_query_ids=1_000, max_results=1 << 13,
+                          use_graph=graph)
+            for _ in range(2):
+                plan.run(qi, qo)
+                po, pi = plan.results()
+                assert po.cpu().numpy().tolist() == oo.tolist() and to_u32(pi).tolist() == oi.tolist(), graph
+            assert plan.info()["fallbacks"] == 0
+            plan.free()
         idx.free()
 
 
