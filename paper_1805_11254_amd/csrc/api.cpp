@@ -253,6 +253,7 @@ hoph_status run_query_impl(const hoph_index *cidx, Workspace *ws_in, const uint3
     a.counters = ws.counters;
     a.codes = use_codes ? idx->codes : nullptr;
     a.cg = idx->cg;
+    bool counters_zeroed = false;                    // by the query-record launch (no fill launch needed)
     if (kind != QueryKind::OPH_FULL && n_q && n_sets) {
         st = ws.grow_qmasks((uint64_t)n_q * lay.L);
         if (st) return st;
@@ -266,8 +267,10 @@ hoph_status run_query_impl(const hoph_index *cidx, Workspace *ws_in, const uint3
             with_lin = lin_records(a, tab, &lin);
         }
         HOPH_HIP(launch_query_masks(d_qsigs, n_q, nullptr, lay.k, lay.kp, lay.L, ws.qmasks,
-                                    use_codes ? ws.qcodes : nullptr, idx->cg, &thr, s, with_lin ? &lin : nullptr),
+                                    use_codes ? ws.qcodes : nullptr, idx->cg, &thr, s, with_lin ? &lin : nullptr,
+                                    ws.counters, 4),
                  "query mask launch");
+        counters_zeroed = true;
     }
     a.qmasks = ws.qmasks;
     a.qcodes = ws.qcodes;
@@ -365,7 +368,7 @@ hoph_status run_query_impl(const hoph_index *cidx, Workspace *ws_in, const uint3
         a.surv_cap = ws.surv_cap;
         a.keys = ws.keys;
         a.keys_cap = ws.keys_cap;
-        HOPH_HIP(launch_fill_u64(ws.counters, 4, 0, s), "fill counters");
+        if (!counters_zeroed) HOPH_HIP(launch_fill_u64(ws.counters, 4, 0, s), "fill counters");
         st = pass(0, n_q);
         if (st) return st;
         // a batch of up to kSmallOutQueries queries tries the one-workgroup output

@@ -519,9 +519,12 @@ struct ScanLaunch {
 // Empty-bin masks of every (query, group) and, when qcodes is not null, the code
 // records (code_rec_words each) of each query's first cg groups; thr is then required.
 // lin (nullable): the linear-bound words of the first lin->steps groups.
+// zero (nullable): n_zero <= 256 words set to 0 by the same launch (the pass
+// counters, so that no fill launch precedes the pass).
 hipError_t launch_query_masks(const uint32_t *qsigs, uint32_t n_q, const uint64_t *desc, uint32_t k, uint32_t kp,
                               uint32_t L, uint64_t *out, uint32_t *qcodes, uint32_t cg, const CodeThr *thr,
-                              hipStream_t st, const LinTab *lin = nullptr);
+                              hipStream_t st, const LinTab *lin = nullptr, uint64_t *zero = nullptr,
+                              uint32_t n_zero = 0);
 // Whether query records for this index and these parameters carry the words of
 // the linear bound (the multi-group code pass may run at some depth); if so
 // and lin is not null, its LinTab for launch_query_masks.  a needs codes, tri,

@@ -303,7 +303,9 @@ __global__ __launch_bounds__(kThreads) void query_masks_kernel(const uint32_t *_
                                                               const uint64_t *__restrict__ desc, uint32_t k,
                                                               uint32_t kp, uint32_t L, uint64_t *__restrict__ out,
                                                               uint32_t *__restrict__ qcodes, uint32_t cg,
-                                                              const CodeThr thr, const LinTab lin) {
+                                                              const CodeThr thr, const LinTab lin,
+                                                              uint64_t *__restrict__ zero, uint32_t n_zero) {
+    if (zero && blockIdx.x == 0 && threadIdx.x < n_zero) zero[threadIdx.x] = 0;   // the pass counters
     const uint32_t n_q = desc ? (uint32_t)desc[0] : n_q_arg;
     const uint64_t n = (uint64_t)n_q * L;
     const uint32_t W = code_plane_words(kp), PW = code_words(kp), RW = code_rec_words(kp);
@@ -1934,19 +1936,20 @@ uint32_t max_depth_for_kpad(uint32_t kpad) {
 
 hipError_t launch_query_masks(const uint32_t *qsigs, uint32_t n_q, const uint64_t *desc, uint32_t k, uint32_t kp,
                               uint32_t L, uint64_t *out, uint32_t *qcodes, uint32_t cg, const CodeThr *thr,
-                              hipStream_t st, const LinTab *lin) {
+                              hipStream_t st, const LinTab *lin, uint64_t *zero, uint32_t n_zero) {
     if (qcodes && !thr) return hipErrorInvalidValue;
+    if (n_zero > kThreads) return hipErrorInvalidValue;
     CodeThr t{};
     if (thr) t = *thr;
     LinTab lt;
     std::memset(&lt, 0, sizeof(lt));
     if (lin && qcodes) lt = *lin;
     const uint64_t n = (uint64_t)n_q * L;         // n_q: the batch size, or its upper bound with desc
-    if (n == 0) return hipSuccess;
+    if (n == 0) return zero && n_zero ? launch_fill_u64(zero, n_zero, 0, st) : hipSuccess;
     uint64_t blocks = (n + kThreads - 1) / kThreads;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(query_masks_kernel, dim3((uint32_t)blocks), dim3(kThreads), 0, st, qsigs, n_q, desc, k, kp, L,
-                       out, qcodes, cg, t, lt);
+                       out, qcodes, cg, t, lt, zero, n_zero);
     return hipGetLastError();
 }
 

@@ -177,13 +177,16 @@ hoph_status enqueue_sketch(hoph_plan *p, const PlanShape &s, hipStream_t st) {
     LinTab lin;
     const bool with_lin = p->codes && lin_records(scan_launch(p, s), p->tab, &lin);
     HOPH_HIP(launch_query_masks(p->q_sigs, p->cfg.max_queries, p->desc, lay.k, lay.kp, lay.L, p->q_masks,
-                                p->codes ? p->q_codes : nullptr, p->idx->cg, &thr, st, with_lin ? &lin : nullptr),
+                                p->codes ? p->q_codes : nullptr, p->idx->cg, &thr, st, with_lin ? &lin : nullptr,
+                                p->counters, 4),
              "query mask launch");
     return HOPH_OK;
 }
 
-hoph_status enqueue_scan(hoph_plan *p, const PlanShape &s, hipStream_t st, bool with_fine) {
-    HOPH_HIP(launch_fill_u64(p->counters, 4, 0, st), "fill counters");
+// fill: zero the counters first (the sketch stage's record launch already
+// zeroes them in the pipeline; the tuner runs passes on their own)
+hoph_status enqueue_scan(hoph_plan *p, const PlanShape &s, hipStream_t st, bool with_fine, bool fill) {
+    if (fill) HOPH_HIP(launch_fill_u64(p->counters, 4, 0, st), "fill counters");
     const ScanLaunch l = scan_launch(p, s);
     HOPH_HIP(launch_scan_coarse(l, p->tab, st), "coarse scan launch");
     if (with_fine) HOPH_HIP(launch_scan_fine(l, p->tab, st), "fine scan launch");
@@ -230,7 +233,7 @@ hoph_status finish_output(hoph_plan *p, hipStream_t st, bool &ran) {
 hoph_status enqueue_pipeline(hoph_plan *p, const PlanShape &s, hipStream_t st) {
     hoph_status r = enqueue_sketch(p, s, st);
     if (r) return r;
-    r = enqueue_scan(p, s, st, true);
+    r = enqueue_scan(p, s, st, true, false);
     if (r) return r;
     return enqueue_output(p, st);
 }
@@ -285,7 +288,7 @@ hoph_status tune(hoph_plan *p, hipStream_t st, uint64_t n_sets, uint32_t n_q) {
             PlanShape s = best;
             s.q_per_wave = qpw;
             s.coarse_wpc = wpc;
-            const float ms = time_it([&] { return enqueue_scan(p, s, st, false); });
+            const float ms = time_it([&] { return enqueue_scan(p, s, st, false, true); });
             if (ms < sc_best) {
                 sc_best = ms;
                 best.q_per_wave = qpw;
