@@ -524,6 +524,20 @@ hoph_status hoph_build_decision_tables(const hoph_sketch_params *params,
                                        const hoph_query_params *qp, uint32_t goph,
                                        hoph_decision_tables *out);
 
+/* hoph_first_group_plan -- the shape the first-group code pass takes for an
+   index layout (params) and a query (qp, JOINT or LITERAL; goph as for
+   hoph_build_decision_tables), without a GPU: tri = 1 for a self-join,
+   small_batch = 1 for a host batch of fewer than 32 queries, keep_rate (host,
+   nullable; entries 2..6 read) the fraction of row pairs phase 1 keeps at 2..6
+   planes as measured on the data (a self-join samples it).  out (host):
+   out[0] the planes compared first (0: one phase over all 8), out[1] 1 when
+   the kernel holds only those planes in registers (HOPH_PLAN_FIRST_GROUP_LIGHT),
+   out[2] tiles of 64 sets per wavefront.  A test hook for the expected-cost
+   choice; a query uses it when its coarse pass stops after the first group. */
+hoph_status hoph_first_group_plan(const hoph_sketch_params *params, const hoph_query_params *qp,
+                                  uint32_t goph, uint32_t tri, uint32_t small_batch,
+                                  const double *keep_rate, uint32_t out[3]);
+
 /* hoph_selftest_bins -- runs the library's own hash-and-bin arithmetic (the code
    the sketch kernel inlines) on the host for n ids: out_bin[i], out_off[i].  Both
    bin lookups are run where the layout admits the uniform estimate, and a

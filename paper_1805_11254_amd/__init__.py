@@ -100,6 +100,8 @@ SIGNATURES = {
     "hoph_query_timing": (C.c_int, [vp, C.POINTER(C.c_float)]),
     "hoph_query_counts": (C.c_int, [vp, C.POINTER(C.c_uint64)]),
     "hoph_coarse_plan": (C.c_int, [vp, C.POINTER(C.c_uint32)]),
+    "hoph_first_group_plan": (C.c_int, [C.POINTER(SketchParamsC), C.POINTER(QueryParamsC), u32, u32, u32,
+                                        C.POINTER(C.c_double), C.POINTER(C.c_uint32)]),
     "hoph_scan_timing": (C.c_int, [vp, vp, u32, C.POINTER(QueryParamsC), u32, vp, u64, C.POINTER(C.c_float), vp]),
     "hoph_index_free": (None, [vp]),
     "query_goph": (C.c_int, [vp, vp, u32, C.POINTER(QueryParamsC), C.POINTER(ResultsC), vp]),
@@ -726,6 +728,24 @@ def tail_integers(n: int, T, eps) -> Tuple[int, int]:
     lo, hi = i32(), i32()
     _check(lib().hoph_tail_integers(n, _ratio(T), _ratio(eps), C.byref(lo), C.byref(hi)))
     return lo.value, hi.value
+
+
+def first_group_plan(params: SketchParams, T, eps, policy=EMPTY_JOINT, goph: Optional[bool] = None, tri=False,
+                     small_batch=False, keep_rate=None):
+    """(first-phase planes, light kernel, tiles per wavefront) of the first-group
+    code pass for these parameters (host only); keep_rate: {planes: measured
+    phase-1 keep rate} for planes 2..6, or None for independent codes."""
+    if goph is None:
+        goph = params.layout == LAYOUT_OPH
+    pc = params.c()
+    qp = QueryParamsC(_ratio(T), _ratio(eps), policy, 0, 0, 0)
+    rates = None
+    if keep_rate is not None:
+        rates = (C.c_double * 8)(*[float(keep_rate.get(i, 0.0)) for i in range(8)])
+    out = (C.c_uint32 * 3)()
+    _check(lib().hoph_first_group_plan(C.byref(pc), C.byref(qp), 1 if goph else 0, 1 if tri else 0,
+                                       1 if small_batch else 0, rates, out))
+    return out[0], bool(out[1]), out[2]
 
 
 def decision_tables(params: SketchParams, T, eps, policy=EMPTY_JOINT, goph: Optional[bool] = None) -> dict:

@@ -951,6 +951,28 @@ hoph_status hoph_build_decision_tables(const hoph_sketch_params *params, const h
     return HOPH_OK;
 }
 
+hoph_status hoph_first_group_plan(const hoph_sketch_params *params, const hoph_query_params *qp, uint32_t goph,
+                                  uint32_t tri, uint32_t small_batch, const double *keep_rate, uint32_t out[3]) {
+    g_last_error.clear();
+    if (!params || !qp || !out) return fail(HOPH_E_INVAL, "NULL argument");
+    if (!valid_ratio_T(qp->T)) return fail(HOPH_E_INVAL, "T must be an exact ratio in (0, 1]");
+    if (!valid_ratio_eps(qp->eps)) return fail(HOPH_E_INVAL, "eps must be in [0, 1)");
+    if (qp->empty_policy == HOPH_EMPTY_EITHER) return fail(HOPH_E_INVAL, "the first-group code pass runs under JOINT or LITERAL");
+    hoph_sketch_params p = *params;
+    if (p.hash == HOPH_HASH_TABLE && !p.d_perm) p.d_perm = reinterpret_cast<const uint32_t *>(1);  // not read here
+    LayoutInfo lay;
+    std::string err;
+    hoph_status st = build_layout(p, lay, err);
+    if (st) return fail(st, err);
+    hoph_decision_tables t;
+    st = build_tables(lay, *qp, goph != 0, t, err);
+    if (st) return fail(st, err);
+    ScanTab tab{};
+    to_scan_tab(t, tab);
+    first_group_shape(tab, lay.kp, tri != 0, small_batch != 0, keep_rate, out);
+    return HOPH_OK;
+}
+
 hoph_status hoph_selftest_bins(const hoph_sketch_params *params, const uint32_t *h_perm, const uint32_t *h_ids,
                                uint64_t n, uint32_t *out_bin, uint32_t *out_off) {
     g_last_error.clear();

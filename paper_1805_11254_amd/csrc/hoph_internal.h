@@ -531,6 +531,11 @@ hipError_t launch_query_masks(const uint32_t *qsigs, uint32_t n_q, const uint64_
 // kp, L and cg set.
 bool lin_records(const ScanLaunch &a, const ScanTab &tab, LinTab *lin);
 hipError_t launch_scan_coarse(const ScanLaunch &a, const ScanTab &tab, hipStream_t st);
+// The first-group code pass's shape for these tables (first_group_plan):
+// out[0] first-phase planes, out[1] 1 for scan_codes_fast1_kernel, out[2]
+// tiles per wavefront (hoph_first_group_plan).
+void first_group_shape(const ScanTab &tab, uint32_t kp, bool tri, bool small_batch, const double *keep_rate,
+                       uint32_t out[3]);
 // Phase-1 lane keep rates of the first-group code pass (one plane word) on the
 // data, rate[p] for p = 2 .. 6, from sampled pairs of the first n_sets index
 // rows' code planes and the reject thresholds dthr0 (ScanTab::dthr0);

@@ -124,7 +124,8 @@ FirstGroupPlan first_group_plan(const ScanTab &tab, uint32_t kp, bool tri, bool 
             }
         }
     }
-    if (best1.fast1 && (light_only || best1_cost < best_cost)) return best1;
+    // (with light_only, best is still the one-phase pass and best_cost its cost)
+    if (best1.fast1 && best1_cost < best_cost) return best1;
     return best;
 }
 
@@ -1781,6 +1782,14 @@ void oph_kp(const ScanLaunch &l, const CoarseArgs &a, hoph_ratio T, hipStream_t 
     }
 
 }  // namespace
+
+void first_group_shape(const ScanTab &tab, uint32_t kp, bool tri, bool small_batch, const double *keep_rate,
+                       uint32_t out[3]) {
+    const FirstGroupPlan f = first_group_plan(tab, kp, tri, small_batch, keep_rate);
+    out[0] = (uint32_t)f.planes;
+    out[1] = f.fast1 ? 1u : 0u;
+    out[2] = (uint32_t)f.tiles;
+}
 
 // Phase-1 lane keep rates of the first-group pass measured on the data: up to
 // kKeepSample index rows spaced evenly over [0, n_sets), each as the query

@@ -393,3 +393,40 @@ def test_abi_struct_layouts_match_binding(tmp_path):
         assert got[(cname, "size")] == H.C.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_first_group_plan_choices():
+    """The first-group code pass's expected-cost choice, on the host (HOPH 1:1,
+    k = 256, k' = 32, every threshold T = n/100 whose first group can reject):
+    for independent codes two planes up to 14 differing bins, three up to 21,
+    four up to 24, five up to 27, six up to 29, else one phase; a host batch of
+    fewer than 32 queries never takes the light kernel; a self-join takes the
+    light kernel unless one phase costs less, which it does past 28 differing
+    bins; with the keep rates measured on the bag-of-words rows at T = 4/5 it
+    takes three planes over 16 tiles, and with rates that keep half the lanes
+    at every plane count one phase."""
+    p = H.SketchParams(H.LAYOUT_HIER, 256, 32, H.HASH_MODP31, 1 << 20, 1, 1, 48271, 11)
+    want = lambda d: 2 if d <= 14 else 3 if d <= 21 else 4 if d <= 24 else 5 if d <= 27 else 6 if d <= 29 else 0
+    seen = set()
+    for num in range(30, 100):
+        T, eps = (num, 100), (1, 10_000)
+        tabs = H.decision_tables(p, T, eps)
+        if tabs["rej"][0] < 0:
+            continue
+        d = 32 - tabs["rej"][0] // (tabs["W"][0] * tabs["dmul"][0])   # differing bins that still keep a pair
+        seen.add(d)
+        planes, light, tiles = H.first_group_plan(p, T, eps)
+        assert planes == want(d), (num, d, planes)
+        assert tiles == ((16 if planes <= 3 else 8) if light else (8 if planes == 2 else 4)), (num, planes, tiles)
+        s_planes, s_light, _ = H.first_group_plan(p, T, eps, small_batch=True)
+        assert not s_light, num
+        t_planes, t_light, _ = H.first_group_plan(p, T, eps, tri=True)
+        assert t_light == (d <= 28) and (t_light or t_planes == 0), (num, d, t_planes, t_light)
+    assert {14, 21, 24, 27, 29, 30} <= seen
+    bovw = {2: 2.45e-4, 3: 1.0e-5, 4: 5e-6, 5: 5e-6, 6: 5e-6}
+    assert H.first_group_plan(p, (4, 5), (1, 10_000), tri=True, keep_rate=bovw) == (3, True, 16)
+    assert H.first_group_plan(p, (4, 5), (1, 10_000), tri=True) == (2, True, 16)
+    half = {i: 0.5 for i in range(2, 7)}
+    assert H.first_group_plan(p, (4, 5), (1, 10_000), tri=True, keep_rate=half) == (0, False, 4)
+    with pytest.raises(H.HophError):
+        H.first_group_plan(p, (4, 5), (1, 10_000), policy=H.EMPTY_EITHER)
