@@ -430,3 +430,9 @@ def test_first_group_plan_choices():
     assert H.first_group_plan(p, (4, 5), (1, 10_000), tri=True, keep_rate=half) == (0, False, 4)
     with pytest.raises(H.HophError):
         H.first_group_plan(p, (4, 5), (1, 10_000), policy=H.EMPTY_EITHER)
+    # two plane words (k' = 64): the kernel with every plane in registers, two tiles per wavefront
+    p64 = H.SketchParams(H.LAYOUT_HIER, 512, 64, H.HASH_MODP31, 1 << 20, 1, 1, 48271, 11)
+    for num in range(30, 100, 7):
+        for tri in (False, True):
+            planes, light, tiles = H.first_group_plan(p64, (num, 100), (1, 10_000), policy=H.EMPTY_LITERAL, tri=tri)
+            assert not light and tiles == 2, (num, tri, planes, tiles)
