@@ -653,7 +653,7 @@ def _code_pass_shape(H, p, T, eps, goph=False, nq=None):
     depth, split = None, 0
     if m_rej0 >= 0 and 8 * m_rej0 >= kp:
         depth = 1
-        split, fast1 = _plane_split(kp - m_rej0, kp, W_planes, small=nq is not None and nq < 32)
+        split, fast1, _ = H.first_group_plan(p, T, eps, goph=goph, small_batch=nq is not None and nq < 32)
         ops = _first_group_ops(split, fast1, W_planes)
     else:
         ops = _first_group_ops(0, False, W_planes)
@@ -793,35 +793,6 @@ def _code_units(k, kp, goph):
     return pk, cu, cu * pk
 
 
-def _plane_split(dthr, kp, Wp, small=False):
-    """(phase-1 planes, whether scan_codes_fast1_kernel runs) of the first-group
-    pass, as the library picks them: the least expected lane-ops per pair.
-    A background pair's bin agrees on p planes with probability 2^-p, so a lane
-    survives phase 1 with a binomial tail probability and a wavefront opens
-    phase 2 when any of its 64 x tiles lanes does.  scan_codes_fast_kernel:
-    W p + 2 (+ 2.4 with 8 tiles), plus W (8 - p) + 2 in phase 2 (tiles: 8 for
-    p = 2, else 4; 2 for W = 2); scan_codes_fast1_kernel (W = 1): p + 1.6,
-    plus p + 10 in phase 2 (tiles: 16 for p <= 3, else 8); one phase: 8 W + 3.  small: a host batch of fewer than 32 queries,
-    which keeps scan_codes_fast_kernel (more wavefronts read the planes)."""
-    need = kp - dthr + 1
-    best, pick = 8.0 * Wp + 3.0, (0, False)
-    for p in range(2, 7):
-        f = 2.0 ** -p
-        tail = 1.0 if need <= 0 else sum(math.comb(kp, j) * f ** j * (1 - f) ** (kp - j)
-                                         for j in range(max(need, 0), kp + 1))
-        keep = 1.0 - min(tail, 1.0)
-        tiles = (8 if p == 2 else 4) if Wp == 1 else 2
-        cost = Wp * p + (2.4 if tiles == 8 else 2.0) + (1.0 - keep ** (64 * tiles)) * (Wp * (8 - p) + 2.0)
-        if cost < best:
-            best, pick = cost, (p, False)
-        if Wp == 1 and not small:
-            t1 = 16 if p <= 3 else 8
-            cost1 = p + 1.6 + (1.0 - keep ** (64 * t1)) * (p + 10.0)
-            if cost1 < best:
-                best, pick = cost1, (p, True)
-    return pick
-
-
 def _first_group_ops(split, fast1, Wp):
     """VALU lane-ops per pair of the first-group pass's first phase, as its
     instruction stream counts them: per tile W p three-input bit operations
@@ -845,7 +816,8 @@ def _coarse_model(H, p, T, eps, goph=False, nq=None):
       (P1 W plane operations, the first of them masked by the query's
       non-empty bins, W popcounts, a share of the running maximum and of the
       per-query compare, _first_group_ops; P1 from 2 to 6 and the kernel by the
-      expected cost of _plane_split), else all 8 planes (9 W + 1);
+      library's expected-cost choice, hoph_first_group_plan), else all 8 planes
+      (9 W + 1);
     - two to four groups of 17-32 bins: the linear-bound pass compares P1 planes
       of groups 1..R+1 (R+1 the first step with a reject cutoff; P1 the smallest
       of 2, 3, 4 planes whose chance match rate is at most a third of that
@@ -864,7 +836,7 @@ def _coarse_model(H, p, T, eps, goph=False, nq=None):
     Wp = 1 if kp <= 32 else 2
     if m_rej0 >= 0 and 8 * m_rej0 >= kp:
         depth = 1
-        split, fast1 = _plane_split(kp - m_rej0, kp, Wp, small=nq is not None and nq < 32)
+        split, fast1, _ = H.first_group_plan(p, T, eps, goph=goph, small_batch=nq is not None and nq < 32)
         ops = _first_group_ops(split, fast1, Wp)
         kernel = "scan_codes_fast1_kernel" if fast1 else "scan_codes_fast_kernel"
     else:
